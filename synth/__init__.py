@@ -1,0 +1,155 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module only draws random numbers and shapes them into workloads; it holds
+none of the set's arithmetic (no sorting network, codec, search or reduction of
+the method).  Every stream is the counter-based splitmix64 generator
+(Steele, Lea, Flood, "Fast splittable pseudorandom number generators",
+OOPSLA 2014): value i of stream `seed` is mix64(seed + (i + 1) * golden_gamma).
+
+Workload recipes follow the paper's experiments:
+  * uniform 40-bit keys (Section "Evaluation on microbenchmarks", setup);
+  * Zipf-distributed range lengths (skewed batch of queries);
+  * R-MAT edges with a=0.5, b=c=0.1, d=0.3 (graph batch-insert setup).
+"""
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+SEED_BASE = 0x230505055
+
+MASK40 = (1 << 40) - 1
+
+
+def splitmix64(seed, n, offset=0):
+    """n consecutive outputs of the splitmix64 stream `seed`, starting at index offset."""
+    with np.errstate(over="ignore"):
+        i = np.arange(offset + 1, offset + n + 1, dtype=np.uint64)
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + i * GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform_keys(n, seed, bits=40, offset=0):
+    """n uniform keys of `bits` bits (duplicates possible)."""
+    z = splitmix64(seed, n, offset)
+    if bits < 64:
+        z &= np.uint64((1 << bits) - 1)
+    return z
+
+
+def unique_uniform_keys(n, seed, bits=40):
+    """Exactly n distinct uniform keys of `bits` bits, returned in generation order.
+
+    Draws n keys, drops repeats (keeping first occurrences) and tops up from the
+    continuation of the same stream until n distinct keys exist.
+    """
+    keys = uniform_keys(n, seed, bits)
+    _, first = np.unique(keys, return_index=True)
+    if len(first) == n:
+        return keys
+    keep = keys[np.sort(first)]
+    offset = n
+    while len(keep) < n:
+        need = n - len(keep)
+        extra = uniform_keys(2 * need + 16, seed, bits, offset)
+        offset += len(extra)
+        cand = np.concatenate([keep, extra])
+        _, first = np.unique(cand, return_index=True)
+        keep = cand[np.sort(first)][:n]
+    return keep
+
+
+def sample_indices(n, k, seed):
+    """k distinct indices in [0, n), uniformly at random (k <= n)."""
+    if k > n:
+        raise ValueError("k > n")
+    if k == 0:
+        return np.empty(0, dtype=np.int64)
+    if 2 * k >= n:
+        r = splitmix64(seed, n)
+        return np.argsort(r, kind="stable")[:k].astype(np.int64)
+    idx = np.empty(0, dtype=np.int64)
+    offset = 0
+    while len(idx) < k:
+        r = splitmix64(seed, 2 * (k - len(idx)) + 16, offset)
+        offset += len(r)
+        cand = (r % np.uint64(n)).astype(np.int64)
+        cat = np.concatenate([idx, cand])
+        _, first = np.unique(cat, return_index=True)
+        idx = cat[np.sort(first)]
+    return idx[:k]
+
+
+def uniform_float(n, seed, offset=0):
+    """n doubles in [0, 1) from the top 53 bits of the stream."""
+    z = splitmix64(seed, n, offset) >> np.uint64(11)
+    return z.astype(np.float64) * (1.0 / (1 << 53))
+
+
+def zipf_lengths(n, seed, alpha=1.2, lmax=10**6):
+    """n lengths in {1..lmax} with P(l) proportional to l^-alpha (inverse-CDF table)."""
+    ranks = np.arange(1, lmax + 1, dtype=np.float64)
+    w = ranks ** (-alpha)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    u = uniform_float(n, seed)
+    return (np.searchsorted(cdf, u, side="right") + 1).clip(1, lmax).astype(np.int64)
+
+
+def range_queries_width(n, seed, width, bits=40):
+    """Queries [lo, lo + width) with lo uniform over the key space."""
+    lo = uniform_keys(n, seed, bits)
+    hi = lo + np.uint64(width)
+    return lo, hi
+
+
+def range_queries_by_count(keys_sorted, lengths, seed):
+    """Queries that cover exactly lengths[i] keys of the sorted key array.
+
+    lo = keys[s], hi = keys[s + l] (or keys[-1] + 1 at the end), s uniform in
+    [0, n - l].  Counting keys here is workload shaping on the harness side.
+    """
+    n = len(keys_sorted)
+    lengths = np.minimum(np.asarray(lengths, dtype=np.int64), n)
+    u = uniform_float(len(lengths), seed)
+    start = np.floor(u * (n - lengths + 1)).astype(np.int64)
+    start = np.minimum(start, n - lengths)
+    lo = keys_sorted[start]
+    end = start + lengths
+    top = np.uint64(keys_sorted[-1]) + np.uint64(1)
+    hi = np.where(end < n, keys_sorted[np.minimum(end, n - 1)], top).astype(np.uint64)
+    return lo.astype(np.uint64), hi
+
+
+def rmat_edges(m, seed, scale=24, a=0.5, b=0.1, c=0.1):
+    """m directed R-MAT edges (src, dst) on 2^scale vertices, `scale` quadrant draws each.
+
+    No noise and no vertex permutation, so vertex 0 is the hub.
+    """
+    src = np.zeros(m, dtype=np.uint64)
+    dst = np.zeros(m, dtype=np.uint64)
+    ab, abc = a + b, a + b + c
+    for lvl in range(scale):
+        u = uniform_float(m, seed + 7919 * (lvl + 1))
+        bit = np.uint64(1 << (scale - 1 - lvl))
+        right = ((u >= a) & (u < ab)) | (u >= abc)   # quadrants b and d: dst bit set
+        down = u >= ab                                # quadrants c and d: src bit set
+        dst |= np.where(right, bit, np.uint64(0))
+        src |= np.where(down, bit, np.uint64(0))
+    return src, dst
+
+
+def edge_keys(src, dst, symmetric=True, drop_self_loops=True):
+    """Edge keys src<<32|dst (unsorted, possibly with repeats)."""
+    src = np.asarray(src, dtype=np.uint64)
+    dst = np.asarray(dst, dtype=np.uint64)
+    if drop_self_loops:
+        keep = src != dst
+        src, dst = src[keep], dst[keep]
+    k = (src << np.uint64(32)) | dst
+    if symmetric:
+        k = np.concatenate([k, (dst << np.uint64(32)) | src])
+    return k

@@ -1,0 +1,281 @@
+"""Pins for the CPU oracle: each check ties it to something other than itself.
+
+* set algebra vs. Python's own set type on random small inputs (brute force);
+* range sums vs. closed forms (arithmetic series, full range = total, empty
+  ranges) and vs. a predicate scan;
+* the byte codec vs. published LEB128 byte patterns (tests/golden);
+* the structure checker vs. a hand-built image (tests/golden) and planted
+  mistakes in it;
+* PageRank / BFS vs. graph special cases with known answers.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+M64 = (1 << 64) - 1
+
+
+# --------------------------------------------------------------------------- sets
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("n,k", [(0, 0), (0, 7), (1, 1), (50, 20), (700, 300), (2000, 2000)])
+def test_set_ops_match_python_sets(orc, seed, n, k):
+    rng = np.random.default_rng(seed)
+    space = max(8, 3 * (n + k))
+    base = rng.integers(0, space, size=n, dtype=np.uint64)
+    batch = rng.integers(0, space, size=k, dtype=np.uint64)
+    S = orc.build_set(base)
+    assert S.tolist() == sorted(set(base.tolist()))
+    ins, added = orc.insert(S, batch)
+    ref = set(S.tolist()) | set(batch.tolist())
+    assert ins.tolist() == sorted(ref)
+    assert added == len(set(batch.tolist()) - set(S.tolist()))
+    dele, removed = orc.delete(ins, batch[: k // 2])
+    ref2 = ref - set(batch[: k // 2].tolist())
+    assert dele.tolist() == sorted(ref2)
+    assert removed == len(set(batch[: k // 2].tolist()) & ref)
+    q = rng.integers(0, space, size=64, dtype=np.uint64)
+    assert orc.contains(ins, q).tolist() == [int(x in ref) for x in q.tolist()]
+
+
+def test_insert_then_delete_restores_set(orc):
+    S = orc.build_set(synth.uniform_keys(5000, 11))
+    B = synth.uniform_keys(3000, 12)
+    ins, added = orc.insert(S, B)
+    assert len(ins) == len(S) + added
+    fresh = np.setdiff1d(B, S)
+    back, removed = orc.delete(ins, fresh)
+    assert removed == added
+    assert np.array_equal(back, S)
+
+
+# ------------------------------------------------------------------------ ranges
+def test_range_closed_form_arithmetic_series(orc):
+    S = np.arange(1000, 3001, dtype=np.uint64)  # keys a..b
+    lo = np.array([1000, 0, 1500, 1500, 2000, 5000, 3001], dtype=np.uint64)
+    hi = np.array([3001, 10 ** 6, 1501, 1500, 1000, 6000, 4000], dtype=np.uint64)
+    s, c = orc.range_map(S, lo, hi)
+    for i in range(len(lo)):
+        a = max(1000, int(lo[i]))
+        b = min(3000, int(hi[i]) - 1)
+        if int(lo[i]) >= int(hi[i]) or a > b:
+            assert (s[i], c[i]) == (0, 0)
+        else:
+            assert int(c[i]) == b - a + 1
+            assert int(s[i]) == ((a + b) * (b - a + 1) // 2) % (1 << 64)
+
+
+def test_range_full_equals_total_and_wraps(orc):
+    top = M64 - 5
+    S = orc.build_set(np.array([top - 3 * i for i in range(50)], dtype=np.uint64))
+    s, c = orc.range_map(S, np.array([0], dtype=np.uint64), np.array([M64], dtype=np.uint64))
+    assert int(c[0]) == 50
+    assert int(s[0]) == sum(int(x) for x in S) % (1 << 64)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_range_matches_predicate_scan(orc, seed):
+    S = orc.build_set(synth.uniform_keys(800, 100 + seed, bits=16))
+    lo = synth.uniform_keys(300, 200 + seed, bits=16)
+    w = synth.uniform_keys(300, 300 + seed, bits=12)
+    hi = lo + w
+    hi[:10] = lo[:10]                      # empty
+    hi[10:20] = lo[10:20] - np.uint64(1)   # lo > hi
+    s1, c1 = orc.range_map(S, lo, hi)
+    s2, c2 = orc.range_map(S, lo, hi, brute=True)
+    assert np.array_equal(s1, s2) and np.array_equal(c1, c2)
+    assert (c1[:20] == 0).all() and (s1[:20] == 0).all()
+
+
+# ------------------------------------------------------------------------- codec
+def _golden_leb():
+    rows = []
+    with open(os.path.join(GOLDEN, "leb128_examples.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            parts = line.split()
+            rows.append((int(parts[0]), bytes(int(x, 16) for x in parts[1:])))
+    return rows
+
+
+def test_codec_published_patterns(orc):
+    rows = _golden_leb()
+    assert len(rows) >= 7
+    for v, b in rows:
+        assert orc.varint_encode(v) == b
+        assert orc.varint_decode(b) == (v, len(b))
+
+
+def test_codec_length_boundaries_and_roundtrip(orc):
+    vals = [1, M64, M64 - 1]
+    for j in range(1, 10):
+        vals += [(1 << (7 * j)) - 1, 1 << (7 * j)]
+    for v in vals:
+        b = orc.varint_encode(v)
+        assert len(b) == -(-v.bit_length() // 7)          # ceil(bitlen / 7)
+        assert all(x & 0x80 for x in b[:-1]) and not (b[-1] & 0x80)
+        assert b[-1] != 0                                  # terminator never 0x00
+        assert orc.varint_decode(b) == (v, len(b))
+        assert orc.varint_decode(b[:-1])[1] == -1          # truncated code rejected
+    assert orc.varint_encode(M64) == bytes([0xFF] * 9 + [0x01])
+
+
+# ------------------------------------------------------------------------ bounds
+def test_bounds_interpolate_between_leaf_and_root(orc):
+    for H in (0, 1, 5, 19):
+        ups = [orc.bound_q(0, h, H) for h in range(H + 1)]
+        los = [orc.bound_q(1, h, H) for h in range(H + 1)]
+        assert ups[0] == round(0.9 * 65536) and los[0] == round(0.1 * 65536)
+        if H > 0:
+            assert ups[-1] == round(0.7 * 65536) and los[-1] == round(0.3 * 65536)
+        assert all(a >= b for a, b in zip(ups, ups[1:]))
+        assert all(a <= b for a, b in zip(los, los[1:]))
+    assert [orc.tree_height(L) for L in (1, 2, 3, 4, 5, 1024, 1025)] == [0, 1, 2, 2, 3, 10, 11]
+
+
+# ----------------------------------------------------------------------- checker
+def _golden_image():
+    S = None
+    params = None
+    keys = []
+    leaves = []
+    with open(os.path.join(GOLDEN, "leaf_image_s64.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            tag, *rest = line.split()
+            if tag == "S":
+                S = int(rest[0])
+            elif tag == "params":
+                params = tuple(float(x) for x in rest)
+            elif tag == "keys":
+                keys = [int(x) for x in rest]
+            elif tag == "leaf":
+                leaves.append(bytes(int(x, 16) for x in rest))
+    L = len(leaves)
+    img = np.zeros(L * S, dtype=np.uint8)
+    used = np.zeros(L, dtype=np.uint32)
+    head = np.zeros(L, dtype=np.uint64)
+    for i, lf in enumerate(leaves):
+        img[i * S:i * S + len(lf)] = np.frombuffer(lf, dtype=np.uint8)
+        used[i] = len(lf)
+        head[i] = int.from_bytes(lf[:8], "little")
+    return S, params, np.array(keys, dtype=np.uint64), img, used, head
+
+
+def test_checker_accepts_golden_image(orc):
+    S, params, keys, img, used, head = _golden_image()
+    code, msg = orc.check_image(img, used, head, S, keys, params)
+    assert code == 0, msg
+    assert orc.decode_image(img, used, S, 100).tolist() == keys.tolist()
+
+
+def test_checker_rejects_planted_mistakes(orc):
+    S, params, keys, img, used, head = _golden_image()
+
+    def bad(mut):
+        i2, u2, h2, k2 = img.copy(), used.copy(), head.copy(), keys.copy()
+        mut(i2, u2, h2, k2)
+        code, _ = orc.check_image(i2, u2, h2, S, k2, params)
+        return code
+
+    assert bad(lambda i, u, h, k: i.__setitem__(9, 0x82)) != 0          # continue bit flipped on
+    assert bad(lambda i, u, h, k: i.__setitem__(8, 0x2c)) != 0          # continue bit flipped off
+    assert bad(lambda i, u, h, k: i.__setitem__(40, 0x01)) != 0         # garbage past used
+    assert bad(lambda i, u, h, k: h.__setitem__(1, 4999)) != 0          # head index stale
+    assert bad(lambda i, u, h, k: u.__setitem__(0, 12)) != 0            # used too short
+    assert bad(lambda i, u, h, k: k.__setitem__(2, 1302)) != 0          # content differs
+    # leaf 1 starting below leaf 0's last key breaks global order
+    assert bad(lambda i, u, h, k: (i.__setitem__(slice(64, 72), np.frombuffer(
+        (1200).to_bytes(8, "little"), dtype=np.uint8)), h.__setitem__(1, 1200))) != 0
+    # density: default bounds (root lower 0.30) reject the 23/128 root
+    code, msg = orc.check_image(img, used, head, S, keys)
+    assert code != 0 and "lower" in msg
+    # a leaf above 0.9 * 64 bytes violates the leaf upper bound
+    big = np.zeros(64, dtype=np.uint8)
+    big[:8] = np.frombuffer((7).to_bytes(8, "little"), dtype=np.uint8)
+    big[8:60] = 1                                                       # 52 deltas of 1
+    ks = np.arange(7, 7 + 53, dtype=np.uint64)
+    code, msg = orc.check_image(big, np.array([60], np.uint32), np.array([7], np.uint64), 64, ks)
+    assert code != 0 and "upper" in msg
+    big[8:57] = 1
+    big[57:60] = 0
+    ks = np.arange(7, 7 + 50, dtype=np.uint64)
+    code, msg = orc.check_image(big, np.array([57], np.uint32), np.array([7], np.uint64), 64, ks)
+    assert code == 0, msg                                                # 57 <= 57.6
+
+
+# ------------------------------------------------------------------------- graph
+def _sym(pairs):
+    ks = set()
+    for u, v in pairs:
+        if u != v:
+            ks.add((u << 32) | v)
+            ks.add((v << 32) | u)
+    return np.array(sorted(ks), dtype=np.uint64)
+
+
+def test_pagerank_regular_graphs_stay_uniform(orc):
+    n = 64
+    cycle = _sym([(i, (i + 1) % n) for i in range(n)])
+    clique = _sym([(i, j) for i in range(12) for j in range(i + 1, 12)])
+    for e, nv in ((cycle, n), (clique, 12)):
+        p = orc.pagerank(e, nv, iters=10)
+        assert np.allclose(p, 1.0 / nv, rtol=1e-14, atol=0)
+
+
+def test_pagerank_star_one_step_closed_form(orc):
+    nv, d = 9, 0.85
+    e = _sym([(0, i) for i in range(1, nv)])
+    p = orc.pagerank(e, nv, iters=1, damping=d)
+    center = (1 - d) / nv + d * (nv - 1) * (1.0 / nv)
+    leaf = (1 - d) / nv + d * (1.0 / nv) / (nv - 1)
+    assert abs(p[0] - center) < 1e-15 and np.allclose(p[1:], leaf, rtol=1e-14)
+
+
+def test_pagerank_mass_identity(orc):
+    nv, d = 300, 0.85
+    src, dst = synth.rmat_edges(2000, 5, scale=8)
+    e = np.unique(synth.edge_keys(src, dst))
+    e = e[(e >> np.uint64(32)) < nv]
+    e = e[(e & np.uint64(0xffffffff)) < nv]
+    p0 = orc.pagerank(e, nv, iters=3, damping=d)
+    p1 = orc.pagerank(e, nv, iters=4, damping=d)
+    deg = np.bincount((e >> np.uint64(32)).astype(np.int64), minlength=nv)
+    expect = (1 - d) + d * p0[deg > 0].sum()
+    assert abs(p1.sum() - expect) < 1e-12
+
+
+def test_bfs_special_graphs(orc):
+    path = _sym([(i, i + 1) for i in range(19)])
+    assert orc.bfs(path, 20).tolist() == list(range(20))
+    star = _sym([(0, i) for i in range(1, 10)])
+    lv = orc.bfs(star, 12)
+    assert lv.tolist()[:10] == [0] + [1] * 9 and lv[10] == lv[11] == 0xFFFFFFFF
+
+
+def test_bfs_matches_python_bfs(orc):
+    src, dst = synth.rmat_edges(3000, 9, scale=10)
+    e = np.unique(synth.edge_keys(src, dst))
+    nv = 1024
+    adj = {}
+    for x in e.tolist():
+        adj.setdefault(x >> 32, []).append(x & 0xffffffff)
+    ref = [0xFFFFFFFF] * nv
+    ref[0] = 0
+    frontier = [0]
+    while frontier:
+        nxt = []
+        for u in frontier:
+            for v in adj.get(u, []):
+                if ref[v] == 0xFFFFFFFF:
+                    ref[v] = ref[u] + 1
+                    nxt.append(v)
+        frontier = nxt
+    assert orc.bfs(e, nv).tolist() == ref
