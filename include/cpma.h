@@ -1,0 +1,171 @@
+/*
+ * cpma.h -- C ABI of the MI355X (gfx950) compressed packed memory array.
+ *
+ * A CPMA is a pointer-free sorted set of 64-bit keys (Wheatman, Burns, Bulu\c{c},
+ * Xu, "CPMA: An Efficient Batch-Parallel Compressed Set Without Pointers",
+ * PPoPP'24).  Keys live in fixed-size leaves of an implicit binary tree; a leaf
+ * stores its first key (the head) uncompressed and the following keys as
+ * delta-encoded byte codes packed to the left (Section "Compressed Packed
+ * Memory Array", "CPMA structure").  Every node of the implicit tree keeps its
+ * byte density between height-dependent bounds (Section "Packed Memory
+ * Array", "Design and operations"); batch updates merge into leaves, count
+ * densities level by level and redistribute the violating regions (Section
+ * "Parallel Batch Updates in a PMA").
+ *
+ * All state lives in device memory of the GPU that is current when the set is
+ * built.  Every call takes a HIP stream (hipStream_t passed as void*, NULL =
+ * the null stream) and enqueues its work there.
+ *
+ * Conventions shared by every entry point:
+ *   - Key domain: [0, 2^64 - 2].  UINT64_MAX is reserved and a key equal to it
+ *     is rejected with CPMA_ERR_RESERVED_KEY before anything is modified.
+ *   - Memory spaces: `mem` says whether the key / query / output pointers of a
+ *     call are host memory (CPMA_MEM_HOST) or device memory of the set's GPU
+ *     (CPMA_MEM_DEVICE).  Inputs are only read during the call.  Outputs
+ *     written to host memory, and the host out-parameters n_added / n_removed,
+ *     are complete when the call returns (the call synchronises the stream);
+ *     outputs written to device memory are complete when the stream reaches
+ *     the point after the call.
+ *   - Ownership: the handle owns all device memory it allocates (leaves,
+ *     heads, used counts, scratch); cpma_destroy frees it.  Caller buffers are
+ *     never retained.
+ *   - Concurrency: one writer per handle (the paper phases updates and queries,
+ *     Section "Evaluation on graph workloads", F-Graph description).  Queries
+ *     may run concurrently with each other on one stream, never with an
+ *     update.
+ *   - Errors: argument errors (CPMA_ERR_INVALID, CPMA_ERR_RESERVED_KEY) are
+ *     detected before any mutation and leave the set unchanged.  A device or
+ *     allocation failure in the middle of an update (CPMA_ERR_DEVICE,
+ *     CPMA_ERR_NOMEM) leaves the handle unusable except for cpma_destroy.
+ */
+#ifndef CPMA_H
+#define CPMA_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cpma cpma; /* opaque handle */
+
+typedef enum {
+  CPMA_OK = 0,
+  CPMA_ERR_INVALID = 1,      /* bad argument (NULL pointer, bad config, ...) */
+  CPMA_ERR_NOMEM = 2,        /* device allocation failed */
+  CPMA_ERR_DEVICE = 3,       /* HIP runtime error or internal limit reached */
+  CPMA_ERR_RESERVED_KEY = 4  /* a key equal to UINT64_MAX was passed */
+} cpma_status;
+
+typedef enum { CPMA_MEM_HOST = 0, CPMA_MEM_DEVICE = 1 } cpma_mem;
+
+/*
+ * Structure parameters.  A zero field takes the default.
+ *   leaf_bytes     bytes per leaf S: a power of two in [64, 4096]; default 1024.
+ *                  The paper sizes leaves Theta(log N) cells (Section "Packed
+ *                  Memory Array"); here S is fixed per set.
+ *   grow           growing factor when the root exceeds its upper bound;
+ *                  default 1.2 (the factor the paper uses, appendix "Data
+ *                  tables" and Section "Growing factor sensitivity").
+ *   up_leaf, up_root, lo_leaf, lo_root
+ *                  byte-density bounds at the leaves and at the root; bounds at
+ *                  height h interpolate linearly in h/H.  Defaults 0.90, 0.70,
+ *                  0.10, 0.30 (the paper's examples use 0.9 at the leaves,
+ *                  Figures "pma-insert" and "cpma-update"; it gives no other
+ *                  constants).  Must satisfy 0 < lo_leaf <= lo_root <
+ *                  up_root <= up_leaf < 1 and lo_root * grow < up_root.
+ *   build_density  target root density after a build or resize; default
+ *                  up_root / grow.
+ */
+typedef struct {
+  uint32_t leaf_bytes;
+  double grow;
+  double up_leaf, up_root, lo_leaf, lo_root;
+  double build_density;
+} cpma_config;
+
+/* Fills *cfg with the defaults above.  Returns CPMA_ERR_INVALID if cfg is NULL. */
+cpma_status cpma_config_default(cpma_config* cfg);
+
+/*
+ * Builds a set from n keys (any order, duplicates allowed): the CPMA(start, end)
+ * constructor of the paper's API (appendix "PMA/CPMA API").  keys may be NULL
+ * when n == 0.  *out receives the handle (NULL on error).  cfg NULL = defaults.
+ * Synchronises `stream`.
+ */
+cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem,
+                       const cpma_config* cfg, void* stream, cpma** out);
+
+/*
+ * insert_batch (Section "Parallel Batch Updates in a PMA"; API: returns the
+ * number of keys added, not counting keys already present).  keys[0..k) in
+ * any order with duplicates unless `sorted` != 0, which promises
+ * non-decreasing order (checked; an unsorted batch is sorted anyway).  k == 0
+ * is a no-op.  *n_added (host pointer, may be NULL) receives the count.
+ * Synchronises `stream`.
+ */
+cpma_status cpma_insert_batch(cpma* set, const uint64_t* keys, uint64_t k,
+                              cpma_mem mem, int sorted, void* stream,
+                              uint64_t* n_added);
+
+/*
+ * remove_batch (deletes are symmetric to inserts, Section "Parallel Batch
+ * Updates in a PMA"; API: returns the number of keys removed, not counting
+ * absent keys).  Same argument rules as cpma_insert_batch.
+ */
+cpma_status cpma_delete_batch(cpma* set, const uint64_t* keys, uint64_t k,
+                              cpma_mem mem, int sorted, void* stream,
+                              uint64_t* n_removed);
+
+/*
+ * has(e) for a batch of q keys (point query: search on the leaf heads, then a
+ * pass through one leaf; Section "Compressed Packed Memory Array", "Point
+ * queries").  out[i] = 1 if keys[i] is in the set, else 0.  keys and out are
+ * both in memory space `mem`.
+ */
+cpma_status cpma_contains(const cpma* set, const uint64_t* keys, uint64_t q,
+                          cpma_mem mem, uint8_t* out, void* stream);
+
+/*
+ * range_map(start, end, f) for a batch of q half-open ranges [lo[i], hi[i])
+ * (Section "Packed Memory Array", "Design and operations": search for the first
+ * element, then scan) with f = (sum, count): sum[i] is the sum mod 2^64 of the
+ * keys in the range and count[i] their number.  lo >= hi gives (0, 0).  Every
+ * key of every range is decoded; no per-leaf aggregate is cached.  lo, hi, sum
+ * and count are all in memory space `mem`.
+ */
+cpma_status cpma_range_map(const cpma* set, const uint64_t* lo, const uint64_t* hi,
+                           uint64_t q, cpma_mem mem, uint64_t* sum,
+                           uint64_t* count, void* stream);
+
+/* size(): number of keys.  0 for a NULL handle. */
+uint64_t cpma_size(const cpma* set);
+
+/*
+ * get_size(): bytes of device memory held by the structure itself -- leaves
+ * (num_leaves * leaf_bytes), leaf heads (8 B each) and used counts (4 B each).
+ * Scratch buffers kept for later batches are not counted.
+ */
+uint64_t cpma_bytes(const cpma* set);
+
+/* Number of leaves and leaf size in bytes of the current layout. */
+cpma_status cpma_geometry(const cpma* set, uint64_t* num_leaves, uint32_t* leaf_bytes);
+
+/*
+ * Copies the structure to host memory for inspection: bytes[num_leaves *
+ * leaf_bytes], used[num_leaves], head[num_leaves] (any pointer may be NULL to
+ * skip it).  Synchronises `stream`.
+ */
+cpma_status cpma_export(const cpma* set, uint8_t* bytes, uint32_t* used,
+                        uint64_t* head, void* stream);
+
+/* Frees the handle and all its device memory.  NULL is a no-op. */
+void cpma_destroy(cpma* set);
+
+/* Static description of a status code. */
+const char* cpma_status_str(cpma_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPMA_H */

@@ -1,0 +1,211 @@
+"""Python binding of the MI355X CPMA (C ABI in include/cpma.h).
+
+Argument marshalling only: every step of build / insert_batch / delete_batch /
+contains / range_map runs in the HIP kernels of libcpma.so.  Host inputs are
+numpy arrays (uint64); device inputs are torch tensors on the GPU (int64 or
+uint64 storage, the bit pattern is the key), passed with the current torch
+stream.  There is no CPU fallback: without the built library every call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcpma.so")
+
+MEM_HOST = 0
+MEM_DEVICE = 1
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "device allocation failed", 3: "device error",
+          4: "reserved key (UINT64_MAX)"}
+
+
+class CpmaError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {STATUS.get(code, code)}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("leaf_bytes", ctypes.c_uint32), ("grow", ctypes.c_double),
+                ("up_leaf", ctypes.c_double), ("up_root", ctypes.c_double),
+                ("lo_leaf", ctypes.c_double), ("lo_root", ctypes.c_double),
+                ("build_density", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libcpma.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libcpma.so is not built: run __graft_entry__.build() "
+                               "(or python -m paper_2305_05055_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        u64 = ctypes.c_uint64
+        L.cpma_config_default.argtypes = [ctypes.POINTER(Config)]
+        L.cpma_build.argtypes = [vp, u64, ctypes.c_int, ctypes.POINTER(Config), vp,
+                                 ctypes.POINTER(vp)]
+        L.cpma_insert_batch.argtypes = [vp, vp, u64, ctypes.c_int, ctypes.c_int, vp,
+                                        ctypes.POINTER(u64)]
+        L.cpma_delete_batch.argtypes = L.cpma_insert_batch.argtypes
+        L.cpma_contains.argtypes = [vp, vp, u64, ctypes.c_int, vp, vp]
+        L.cpma_range_map.argtypes = [vp, vp, vp, u64, ctypes.c_int, vp, vp, vp]
+        L.cpma_size.argtypes = [vp]
+        L.cpma_size.restype = u64
+        L.cpma_bytes.argtypes = [vp]
+        L.cpma_bytes.restype = u64
+        L.cpma_geometry.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_uint32)]
+        L.cpma_export.argtypes = [vp, vp, vp, vp, vp]
+        L.cpma_destroy.argtypes = [vp]
+        L.cpma_destroy.restype = None
+        L.cpma_status_str.argtypes = [ctypes.c_int]
+        L.cpma_status_str.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(code, what):
+    if code != 0:
+        raise CpmaError(code, what)
+
+
+def _is_torch_cuda(x):
+    return hasattr(x, "is_cuda") and x.is_cuda
+
+
+def _stream(stream, device_args):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    if device_args:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(0)
+
+
+def _keys(x):
+    """(pointer, length, memspace, keepalive) for a key array."""
+    if _is_torch_cuda(x):
+        import torch
+        if x.dtype not in (torch.int64, torch.uint64):
+            raise TypeError("device keys must be int64/uint64 tensors")
+        x = x.contiguous()
+        return ctypes.c_void_p(x.data_ptr()), x.numel(), MEM_DEVICE, x
+    a = np.ascontiguousarray(x, dtype=np.uint64)
+    return ctypes.c_void_p(a.ctypes.data), len(a), MEM_HOST, a
+
+
+def default_config():
+    c = Config()
+    lib().cpma_config_default(ctypes.byref(c))
+    return c
+
+
+class CPMA:
+    """A device-resident compressed packed memory array of uint64 keys."""
+
+    def __init__(self, keys=(), leaf_bytes=0, grow=0.0, bounds=None, build_density=0.0,
+                 stream=None):
+        cfg = Config()
+        cfg.leaf_bytes = leaf_bytes
+        cfg.grow = grow
+        if bounds is not None:
+            cfg.up_leaf, cfg.up_root, cfg.lo_leaf, cfg.lo_root = bounds
+        cfg.build_density = build_density
+        p, n, mem, keep = _keys(keys)
+        h = ctypes.c_void_p()
+        _check(lib().cpma_build(p if n else None, n, mem, ctypes.byref(cfg),
+                                _stream(stream, mem == MEM_DEVICE), ctypes.byref(h)), "cpma_build")
+        self._h = h
+        self._keep = keep
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cpma_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _update(self, fn, keys, sorted, stream, what):
+        p, k, mem, keep = _keys(keys)
+        out = ctypes.c_uint64(0)
+        _check(fn(self._h, p if k else None, k, mem, 1 if sorted else 0,
+                  _stream(stream, mem == MEM_DEVICE), ctypes.byref(out)), what)
+        return int(out.value)
+
+    def insert_batch(self, keys, sorted=False, stream=None):
+        """Inserts keys; returns how many were not present before."""
+        return self._update(lib().cpma_insert_batch, keys, sorted, stream, "cpma_insert_batch")
+
+    def delete_batch(self, keys, sorted=False, stream=None):
+        """Deletes keys; returns how many were present."""
+        return self._update(lib().cpma_delete_batch, keys, sorted, stream, "cpma_delete_batch")
+
+    def contains(self, keys, stream=None):
+        p, q, mem, keep = _keys(keys)
+        if mem == MEM_DEVICE:
+            import torch
+            out = torch.empty(q, dtype=torch.uint8, device=keys.device)
+            optr = ctypes.c_void_p(out.data_ptr())
+        else:
+            out = np.empty(q, dtype=np.uint8)
+            optr = ctypes.c_void_p(out.ctypes.data)
+        _check(lib().cpma_contains(self._h, p, q, mem, optr, _stream(stream, mem == MEM_DEVICE)),
+               "cpma_contains")
+        return out
+
+    def range_map(self, lo, hi, stream=None):
+        """(sum mod 2^64, count) of the keys in each [lo[i], hi[i])."""
+        plo, q, mem, klo = _keys(lo)
+        phi, q2, mem2, khi = _keys(hi)
+        if q != q2 or mem != mem2:
+            raise ValueError("lo and hi must have the same length and memory space")
+        if mem == MEM_DEVICE:
+            import torch
+            s = torch.empty(q, dtype=torch.int64, device=lo.device)
+            c = torch.empty(q, dtype=torch.int64, device=lo.device)
+            ps, pc = ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(c.data_ptr())
+        else:
+            s = np.empty(q, dtype=np.uint64)
+            c = np.empty(q, dtype=np.uint64)
+            ps, pc = ctypes.c_void_p(s.ctypes.data), ctypes.c_void_p(c.ctypes.data)
+        _check(lib().cpma_range_map(self._h, plo, phi, q, mem, ps, pc,
+                                    _stream(stream, mem == MEM_DEVICE)), "cpma_range_map")
+        return s, c
+
+    def __len__(self):
+        return int(lib().cpma_size(self._h))
+
+    def size(self):
+        return int(lib().cpma_size(self._h))
+
+    def bytes(self):
+        return int(lib().cpma_bytes(self._h))
+
+    def geometry(self):
+        L = ctypes.c_uint64(0)
+        S = ctypes.c_uint32(0)
+        _check(lib().cpma_geometry(self._h, ctypes.byref(L), ctypes.byref(S)), "cpma_geometry")
+        return int(L.value), int(S.value)
+
+    def export(self, stream=None):
+        """Host copies (bytes[L*S] u8, used[L] u32, head[L] u64) of the layout."""
+        L, S = self.geometry()
+        b = np.empty(L * S, dtype=np.uint8)
+        u = np.empty(L, dtype=np.uint32)
+        h = np.empty(L, dtype=np.uint64)
+        _check(lib().cpma_export(self._h, ctypes.c_void_p(b.ctypes.data), ctypes.c_void_p(u.ctypes.data),
+                                 ctypes.c_void_p(h.ctypes.data), _stream(stream, False)), "cpma_export")
+        return b, u, h

@@ -1,0 +1,126 @@
+// Device-side building blocks shared by every CPMA kernel on gfx950 (wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cpma_dev {
+
+constexpr int kWave = 64;
+constexpr uint64_t kNoKey = ~0ull;   // reserved key: head of an empty single-leaf set
+constexpr int64_t kQ = 65536;        // fixed-point unit of the density bounds
+constexpr int kMaxLevels = 48;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// ---- wave-level scans / reductions (64 lanes) -----------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T t = __shfl_up(v, d, kWave);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_or(uint64_t v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v |= __shfl_xor(v, d, kWave);
+  return v;
+}
+
+// ---- byte codes ------------------------------------------------------------------
+// A delta d >= 1 takes ceil(bitlen(d) / 7) bytes: 7 payload bits per byte, least
+// significant group first, high bit set while more bytes follow.
+__host__ __device__ __forceinline__ uint32_t vlen(uint64_t d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  uint32_t bits = 64u - (uint32_t)__clzll((long long)(d | 1));
+#else
+  uint32_t bits = 64u - (uint32_t)__builtin_clzll(d | 1);
+#endif
+  return (bits + 6u) / 7u;
+}
+
+// Writes the code of d at dst (dst may be LDS or global); returns its length.
+__device__ __forceinline__ uint32_t vput(uint8_t* dst, uint64_t d) {
+  uint32_t n = 0;
+  while (d >= 0x80) {
+    dst[n++] = (uint8_t)(d | 0x80);
+    d >>= 7;
+  }
+  dst[n++] = (uint8_t)d;
+  return n;
+}
+
+__device__ __forceinline__ void put_le64(uint8_t* dst, uint64_t x) {
+#pragma unroll
+  for (int i = 0; i < 8; i++) dst[i] = (uint8_t)(x >> (8 * i));
+}
+
+// ---- density bounds ----------------------------------------------------------------
+// Upper / lower byte-density bound at height h of a tree of height H, fixed point
+// 1/65536, interpolated linearly between the leaf and the root values.
+struct Bounds {
+  int64_t up_leaf, up_root, lo_leaf, lo_root;
+  int H;          // ceil(log2 L)
+  uint64_t L;     // leaves
+  uint32_t S;     // leaf bytes
+};
+
+__host__ __device__ __forceinline__ int64_t bound_up(const Bounds& b, int h) {
+  return b.H == 0 ? b.up_leaf : b.up_leaf - ((b.up_leaf - b.up_root) * h) / b.H;
+}
+__host__ __device__ __forceinline__ int64_t bound_lo(const Bounds& b, int h) {
+  return b.H == 0 ? b.lo_leaf : b.lo_leaf + ((b.lo_root - b.lo_leaf) * h) / b.H;
+}
+
+// Violation of node (h, i) holding `sum` filled bytes over `nleaves` leaves:
+// bit 0 = above its upper bound, bit 1 = below its lower bound.  The root of a
+// single-leaf structure has no lower bound.
+__host__ __device__ __forceinline__ uint32_t violation(const Bounds& b, int h, uint64_t sum,
+                                                       uint64_t nleaves) {
+  const uint64_t cap = nleaves * (uint64_t)b.S;
+  const uint64_t lhs = sum * (uint64_t)kQ;
+  uint32_t v = 0;
+  if (lhs > (uint64_t)bound_up(b, h) * cap) v |= 1u;
+  const bool exempt = (h == b.H) && (b.L == 1);
+  if (!exempt && lhs < (uint64_t)bound_lo(b, h) * cap) v |= 2u;
+  return v;
+}
+
+// Implicit-tree level table: level h (1..H) of a tree over L leaves has
+// ceil(L / 2^h) nodes stored at base + off[h]; level 0 is the used[] array.
+struct Pyramid {
+  uint64_t* base;
+  uint64_t off[kMaxLevels];
+  uint64_t cnt[kMaxLevels];
+  int H;
+};
+
+__device__ __forceinline__ uint64_t node_sum(const Pyramid& p, const uint32_t* used, int h,
+                                             uint64_t i) {
+  return h == 0 ? (uint64_t)used[i] : p.base[p.off[h] + i];
+}
+__device__ __forceinline__ uint64_t node_leaves(uint64_t L, int h, uint64_t i) {
+  uint64_t first = i << h;
+  uint64_t last = first + (1ull << h);
+  return (last > L ? L : last) - first;
+}
+
+// Plain fill kernel (used instead of memset nodes so the work can be graph-captured).
+template <typename T>
+__global__ void k_fill(T* p, uint64_t n, T v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+}  // namespace cpma_dev

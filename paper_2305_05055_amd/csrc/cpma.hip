@@ -1,0 +1,929 @@
+// Host orchestration and C ABI of the MI355X CPMA (declarations: include/cpma.h).
+//
+// One handle owns a device-resident CPMA: leaves (L * S bytes), leaf heads and
+// used byte counts, plus scratch kept across calls.  A batch update runs the
+// paper's three phases (Section "Parallel Batch Updates in a PMA") as device
+// kernels: merge into leaves (with out-of-place overflow), counting of node
+// densities up the implicit tree, and redistribution of the violating regions;
+// the host only reads a few counters at the sync points between phases.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "cpma.h"
+#include "query.hpp"
+#include "sort.hpp"
+#include "update.hpp"
+
+using namespace cpma_dev;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  template <typename T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+struct Fail {
+  cpma_status st;
+};
+
+#define HIPCHK(expr)                                   \
+  do {                                                 \
+    hipError_t _e = (expr);                            \
+    if (_e != hipSuccess) throw Fail{CPMA_ERR_DEVICE}; \
+  } while (0)
+
+void ensure(DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (b.cap >= bytes) return;
+  if (b.p) {
+    hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t want = bytes + bytes / 4 + 256;
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    hipGetLastError();
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+      hipGetLastError();
+      b.p = nullptr;
+      throw Fail{CPMA_ERR_NOMEM};
+    }
+    want = bytes;
+  }
+  b.cap = want;
+}
+
+void release(DevBuf& b) {
+  if (b.p) hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+uint32_t grid_for(uint64_t n, uint32_t block, uint32_t cap = 65535u * 4) {
+  uint64_t g = (n + block - 1) / block;
+  if (g == 0) g = 1;
+  return (uint32_t)std::min<uint64_t>(g, cap);
+}
+
+int tree_height(uint64_t L) {
+  int H = 0;
+  while ((1ull << H) < L) H++;
+  return H;
+}
+
+}  // namespace
+
+struct cpma {
+  int device = 0;
+  int num_cus = 256;
+  cpma_config cfg{};
+  uint32_t S = 1024;
+  uint64_t L = 0, n = 0;
+  int64_t q_up_leaf = 0, q_up_root = 0, q_lo_leaf = 0, q_lo_root = 0;
+  DevBuf bytes, used, head;
+  // scratch
+  DevBuf kin, kb0, kb1, kdedup, leafid, segpos, seg_leaf, seg_begin, heavy, scan_tmp, ovf, arena,
+      stage, pyr, win, wargs, cnt, koff, win_id, welem, P, ncost, lstart, planU, plan_used,
+      win_of_leaf, fail, qa, qb, qfirst, qnvis, qvoff, qsum, qcount, qout;
+  Counters* dctr = nullptr;
+  Counters* hctr = nullptr;
+  BatchInfo* dinfo = nullptr;
+  BatchInfo* hinfo = nullptr;
+  void* hpin = nullptr;  // pinned host staging for small uploads
+  size_t hpin_cap = 0;
+  uint64_t wol_L = 0;    // leaves covered by win_of_leaf's -1 initialisation
+  bool broken = false;
+
+  Bounds bounds(uint64_t Lx) const {
+    Bounds b;
+    b.up_leaf = q_up_leaf;
+    b.up_root = q_up_root;
+    b.lo_leaf = q_lo_leaf;
+    b.lo_root = q_lo_root;
+    b.H = tree_height(Lx);
+    b.L = Lx;
+    b.S = S;
+    return b;
+  }
+};
+
+namespace {
+
+Pyramid make_pyramid(cpma* s, uint64_t L) {
+  Pyramid P;
+  memset(&P, 0, sizeof(P));
+  P.H = tree_height(L);
+  uint64_t off = 0;
+  P.cnt[0] = L;
+  for (int h = 1; h <= P.H; h++) {
+    P.cnt[h] = (L + (1ull << h) - 1) >> h;
+    P.off[h] = off;
+    off += P.cnt[h];
+  }
+  ensure(s->pyr, (off + 1) * sizeof(uint64_t));
+  P.base = s->pyr.as<uint64_t>();
+  return P;
+}
+
+void build_pyramid(cpma* s, const Pyramid& P, const uint32_t* used, uint64_t L, hipStream_t st) {
+  if (P.H == 0) return;
+  const int top = std::min(P.H, kPyrLowLevels);
+  const uint64_t blocks = (P.cnt[1] + kPyrThreads - 1) / kPyrThreads;
+  hipLaunchKernelGGL(k_pyr_low, dim3((uint32_t)blocks), dim3(kPyrThreads), 0, st, used, L, P, top);
+  if (P.H > top) hipLaunchKernelGGL(k_pyr_high, dim3(1), dim3(1024), 0, st, P, top);
+  HIPCHK(hipGetLastError());
+}
+
+void* host_pin(cpma* s, size_t bytes) {
+  if (s->hpin_cap < bytes) {
+    if (s->hpin) {
+      HIPCHK(hipDeviceSynchronize());  // no copy may still read the old buffer
+      hipHostFree(s->hpin);
+    }
+    s->hpin = nullptr;
+    size_t want = std::max<size_t>(bytes, 1 << 16);
+    HIPCHK(hipHostMalloc(&s->hpin, want, hipHostMallocDefault));
+    s->hpin_cap = want;
+  }
+  return s->hpin;
+}
+
+void zero_counters(cpma* s, hipStream_t st) {
+  hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(s->dctr),
+                     (uint64_t)(sizeof(Counters) / 4), 0u);
+  HIPCHK(hipGetLastError());
+}
+
+void read_counters(cpma* s, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(s->hctr, s->dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (s->hctr->error) throw Fail{CPMA_ERR_DEVICE};
+}
+
+template <typename T, typename F>
+void scan(cpma* s, T* out, uint64_t n, hipStream_t st, F fn) {
+  ensure(s->scan_tmp, scan_scratch_elems(n) * sizeof(T));
+  HIPCHK(scan_exclusive<T>(fn, n, out, s->scan_tmp.as<T>(), st));
+}
+
+// ---------------------------------------------------------------------------
+// Batch prep: device copy, validation, radix sort, removal of repeats.
+// Returns the device pointer of the sorted repeat-free batch; its length is in
+// dctr->kprime (device).  Throws CPMA_ERR_RESERVED_KEY before any mutation.
+// ---------------------------------------------------------------------------
+const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem mem, hipStream_t st) {
+  if (k >= (1ull << 32)) throw Fail{CPMA_ERR_INVALID};
+  const uint64_t* src = keys;
+  if (mem == CPMA_MEM_HOST) {
+    ensure(s->kin, k * sizeof(uint64_t));
+    HIPCHK(hipMemcpyAsync(s->kin.p, keys, k * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    src = s->kin.as<uint64_t>();
+  }
+  hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(s->dinfo),
+                     (uint64_t)(sizeof(BatchInfo) / 4), 0u);
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(k, 256, 4096)), dim3(256), 0, st, src, k, s->dinfo);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(s->hinfo, s->dinfo, sizeof(BatchInfo), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (s->hinfo->has_reserved) throw Fail{CPMA_ERR_RESERVED_KEY};
+
+  const uint64_t* sorted = src;
+  if (s->hinfo->unsorted) {
+    const uint64_t orv = s->hinfo->or_all;
+    int bits = 64 - __builtin_clzll(orv | 1);
+    int passes = (bits + 7) / 8;
+    ensure(s->kb0, k * sizeof(uint64_t));
+    ensure(s->kb1, k * sizeof(uint64_t));
+    const uint32_t nblk = (uint32_t)((k + kSortTile - 1) / kSortTile);
+    ensure(s->cnt, ((uint64_t)nblk * 256 + 1) * sizeof(uint32_t));
+    ensure(s->koff, ((uint64_t)nblk * 256 + 1) * sizeof(uint32_t));
+    const uint64_t* in = src;
+    for (int p = 0; p < passes; p++) {
+      uint64_t* out = (p & 1) ? s->kb1.as<uint64_t>() : s->kb0.as<uint64_t>();
+      hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, st, in, (uint32_t)k, 8 * p,
+                         s->cnt.as<uint32_t>());
+      HIPCHK(hipGetLastError());
+      scan<uint32_t>(s, s->koff.as<uint32_t>(), (uint64_t)nblk * 256, st,
+                     LoadFn<uint32_t>{s->cnt.as<uint32_t>()});
+      hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kSortThreads), 0, st, in, out, (uint32_t)k,
+                         8 * p, (const uint32_t*)s->koff.as<uint32_t>());
+      HIPCHK(hipGetLastError());
+      in = out;
+    }
+    sorted = in;
+  }
+  ensure(s->segpos, (k + 1) * sizeof(uint32_t));
+  ensure(s->kdedup, k * sizeof(uint64_t));
+  scan<uint32_t>(s, s->segpos.as<uint32_t>(), k, st, FirstFlag{sorted});
+  hipLaunchKernelGGL(k_compact_unique, dim3(grid_for(k, 256)), dim3(256), 0, st, sorted, k,
+                     (const uint32_t*)s->segpos.as<uint32_t>(), s->kdedup.as<uint64_t>(), &s->dctr->kprime);
+  HIPCHK(hipGetLastError());
+  return s->kdedup.as<uint64_t>();
+}
+
+size_t merge_smem(uint32_t S) {
+  const uint32_t maxA = S - 7;
+  return 8ull * (maxA + 1) + 8ull * (maxA + kSliceCap + 1) + 4ull * ((maxA + 4) & ~3u) + S;
+}
+size_t heavy_smem(uint32_t S) {
+  const uint32_t maxA = S - 7;
+  return 8ull * (maxA + 1) + 4ull * ((maxA + 4) & ~3u) + S;
+}
+
+// ---------------------------------------------------------------------------
+// Redistribution of a set of windows (level, index) in place.  Returns false if
+// some window had to escalate past the root (caller resizes).
+// ---------------------------------------------------------------------------
+struct Win {
+  int h;
+  uint64_t i;
+};
+
+void normalize(std::vector<Win>& w) {
+  std::sort(w.begin(), w.end(), [](const Win& a, const Win& b) {
+    uint64_t fa = a.i << a.h, fb = b.i << b.h;
+    if (fa != fb) return fa < fb;
+    return a.h > b.h;
+  });
+  std::vector<Win> out;
+  uint64_t cover_end = 0;
+  bool have = false;
+  for (const Win& x : w) {
+    uint64_t f = x.i << x.h, e = (x.i + 1) << x.h;
+    if (have && f < cover_end) continue;  // nested in the previous kept window
+    out.push_back(x);
+    cover_end = e;
+    have = true;
+  }
+  w.swap(out);
+}
+
+// Uploads the window description; returns device WinArgs.
+WinArgs upload_windows(cpma* s, const std::vector<uint64_t>& src_begin, const std::vector<uint64_t>& src_n,
+                       const std::vector<uint64_t>& dst_begin, const std::vector<uint64_t>& dst_n,
+                       const std::vector<uint32_t>& level, hipStream_t st, uint64_t& nsrc, uint64_t& ndst) {
+  const uint32_t W = (uint32_t)src_begin.size();
+  const size_t n64 = 6ull * (W + 1);
+  const size_t bytes = n64 * 8 + (W + 1) * 4ull;
+  uint64_t* h = reinterpret_cast<uint64_t*>(host_pin(s, bytes));
+  uint64_t* sb = h;
+  uint64_t* sf = sb + (W + 1);
+  uint64_t* db = sf + (W + 1);
+  uint64_t* dn = db + (W + 1);
+  uint64_t* df = dn + (W + 1);
+  uint32_t* lv = reinterpret_cast<uint32_t*>(df + (W + 1) + (W + 1));
+  nsrc = ndst = 0;
+  for (uint32_t w = 0; w < W; w++) {
+    sb[w] = src_begin[w];
+    sf[w] = nsrc;
+    nsrc += src_n[w];
+    db[w] = dst_begin[w];
+    dn[w] = dst_n[w];
+    df[w] = ndst;
+    ndst += dst_n[w];
+    lv[w] = level[w];
+  }
+  sb[W] = 0;
+  sf[W] = nsrc;
+  db[W] = 0;
+  dn[W] = 0;
+  df[W] = ndst;
+  lv[W] = 0;
+  ensure(s->wargs, bytes);
+  HIPCHK(hipMemcpyAsync(s->wargs.p, h, bytes, hipMemcpyHostToDevice, st));
+  uint64_t* d = s->wargs.as<uint64_t>();
+  WinArgs wa;
+  wa.W = W;
+  wa.src_begin = d;
+  wa.src_flat = d + (W + 1);
+  wa.dst_begin = d + 2 * (W + 1);
+  wa.dst_n = d + 3 * (W + 1);
+  wa.dst_flat = d + 4 * (W + 1);
+  wa.level = reinterpret_cast<const uint32_t*>(d + 6 * (W + 1));
+  return wa;
+}
+
+SrcLeaves src_leaves(cpma* s) {
+  SrcLeaves sl;
+  sl.bytes = s->bytes.as<uint8_t>();
+  sl.used = s->used.as<uint32_t>();
+  sl.ovf = s->ovf.as<uint64_t>();
+  sl.arena = s->arena.as<uint8_t>();
+  sl.S = s->S;
+  return sl;
+}
+
+// Pack (copy 1): decode the source leaves of every window into the staging
+// buffer.  Returns the number of staged keys K.
+uint64_t pack_windows(cpma* s, const WinArgs& wa, uint64_t nsrc, hipStream_t st) {
+  ensure(s->cnt, nsrc * sizeof(uint64_t));
+  ensure(s->koff, (nsrc + 1) * sizeof(uint64_t));
+  const SrcLeaves sl = src_leaves(s);
+  hipLaunchKernelGGL(k_win_count, dim3(grid_for(nsrc, 1, 1u << 20)), dim3(kWave), 0, st, wa, sl, nsrc,
+                     s->cnt.as<uint64_t>());
+  HIPCHK(hipGetLastError());
+  scan<uint64_t>(s, s->koff.as<uint64_t>(), nsrc, st, LoadFn<uint64_t>{s->cnt.as<uint64_t>()});
+  uint64_t K = 0;
+  HIPCHK(hipMemcpyAsync(&s->hctr->root_sum, s->koff.as<uint64_t>() + nsrc, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  K = s->hctr->root_sum;
+  ensure(s->stage, std::max<uint64_t>(K, 1) * sizeof(uint64_t));
+  ensure(s->win_id, std::max<uint64_t>(K, 1) * sizeof(uint32_t));
+  hipLaunchKernelGGL(k_win_pack, dim3(grid_for(nsrc, 1, 1u << 20)), dim3(kWave), 0, st, wa, sl, nsrc,
+                     (const uint64_t*)s->koff.as<uint64_t>(), s->stage.as<uint64_t>(), s->win_id.as<uint32_t>());
+  HIPCHK(hipGetLastError());
+  return K;
+}
+
+// Plans the even spread of the staged keys into the destination leaves and checks
+// it.  Returns per-window failure bits in `fails`.
+void plan_spread(cpma* s, const WinArgs& wa, uint64_t K, uint64_t ndst, const Bounds& dstb,
+                 uint32_t* plan_used, uint64_t Ldst, bool fresh, hipStream_t st, std::vector<uint32_t>& fails) {
+  const uint32_t W = wa.W;
+  ensure(s->welem, (W + 1) * sizeof(uint64_t));
+  ensure(s->fail, std::max<uint32_t>(W, 1) * sizeof(uint32_t));
+  ensure(s->P, (K + 1) * sizeof(uint64_t));
+  ensure(s->ncost, std::max<uint64_t>(K, 1));
+  ensure(s->lstart, (ndst + 1) * sizeof(uint64_t));
+  ensure(s->planU, (ndst + 1) * sizeof(uint32_t));
+  hipLaunchKernelGGL(k_win_elems, dim3(grid_for(W + 1, 256)), dim3(256), 0, st, wa,
+                     (const uint64_t*)s->koff.as<uint64_t>(), s->welem.as<uint64_t>(), s->fail.as<uint32_t>());
+  HIPCHK(hipGetLastError());
+  scan<uint64_t>(s, s->P.as<uint64_t>(), K, st,
+                 CostFn{s->stage.as<uint64_t>(), s->win_id.as<uint32_t>(), s->welem.as<uint64_t>()});
+  hipLaunchKernelGGL((k_fill<uint64_t>), dim3(grid_for(ndst + 1, 256, 4096)), dim3(256), 0, st,
+                     s->lstart.as<uint64_t>(), ndst + 1, ~0ull);
+  hipLaunchKernelGGL(k_assign, dim3(grid_for(K, 256, 1u << 16)), dim3(256), 0, st, wa, K,
+                     (const uint64_t*)s->stage.as<uint64_t>(), (const uint32_t*)s->win_id.as<uint32_t>(),
+                     (const uint64_t*)s->welem.as<uint64_t>(), (const uint64_t*)s->P.as<uint64_t>(),
+                     s->ncost.as<uint8_t>(), s->lstart.as<uint64_t>(), s->fail.as<uint32_t>());
+  HIPCHK(hipGetLastError());
+  int32_t* wol = fresh ? nullptr : s->win_of_leaf.as<int32_t>();
+  hipLaunchKernelGGL(k_leaf_bytes, dim3(grid_for(ndst, 1, 1u << 20)), dim3(kWave), 0, st, wa, dstb, ndst,
+                     (const uint64_t*)s->welem.as<uint64_t>(), (const uint64_t*)s->lstart.as<uint64_t>(),
+                     (const uint8_t*)s->ncost.as<uint8_t>(), s->planU.as<uint32_t>(), plan_used, wol,
+                     s->fail.as<uint32_t>());
+  HIPCHK(hipGetLastError());
+  Pyramid P = make_pyramid(s, Ldst);
+  build_pyramid(s, P, plan_used, Ldst, st);
+  const uint64_t nodes = (P.H == 0) ? 1 : P.off[P.H] + P.cnt[P.H];
+  hipLaunchKernelGGL(k_check_plan, dim3(grid_for(nodes, 256, 1u << 16)), dim3(256), 0, st, dstb, P,
+                     (const uint32_t*)plan_used, (const int32_t*)wol, wa.level, fresh ? 1 : 0,
+                     s->fail.as<uint32_t>());
+  HIPCHK(hipGetLastError());
+  if (!fresh)
+    hipLaunchKernelGGL(k_clear_win_map, dim3(grid_for(ndst, 256, 1u << 16)), dim3(256), 0, st, wa, ndst,
+                       s->win_of_leaf.as<int32_t>());
+  HIPCHK(hipGetLastError());
+  fails.resize(W);
+  uint32_t* hf = reinterpret_cast<uint32_t*>(host_pin(s, W * 4ull + 16));
+  HIPCHK(hipMemcpyAsync(hf, s->fail.p, W * 4ull, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::copy(hf, hf + W, fails.begin());
+}
+
+void encode_spread(cpma* s, const WinArgs& wa, uint64_t ndst, uint8_t* dbytes, uint32_t* dused, uint64_t* dhead,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_leaf_encode, dim3(grid_for(ndst, 1, 1u << 20)), dim3(kWave), s->S, st, wa, ndst, s->S,
+                     (const uint64_t*)s->welem.as<uint64_t>(), (const uint64_t*)s->lstart.as<uint64_t>(),
+                     (const uint64_t*)s->stage.as<uint64_t>(), (const uint32_t*)s->planU.as<uint32_t>(), dbytes,
+                     dused, dhead);
+  HIPCHK(hipGetLastError());
+}
+
+void ensure_win_map(cpma* s) {
+  if (s->wol_L >= s->L && s->win_of_leaf.cap >= s->L * 4) return;
+  ensure(s->win_of_leaf, s->L * sizeof(int32_t));
+  hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid_for(s->win_of_leaf.cap / 4, 256, 4096)), dim3(256), 0, 0,
+                     s->win_of_leaf.as<int32_t>(), (uint64_t)(s->win_of_leaf.cap / 4), -1);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipDeviceSynchronize());
+  s->wol_L = s->win_of_leaf.cap / 4;
+}
+
+// Returns true when done, false when a window escalated past the root.
+bool redistribute(cpma* s, std::vector<Win> wins, hipStream_t st) {
+  const int H = tree_height(s->L);
+  ensure_win_map(s);
+  for (int attempt = 0; attempt < 4 * (H + 2); attempt++) {
+    normalize(wins);
+    std::vector<uint64_t> sb, sn;
+    std::vector<uint32_t> lv;
+    for (const Win& w : wins) {
+      uint64_t f = w.i << w.h;
+      uint64_t e = std::min<uint64_t>(s->L, (w.i + 1) << w.h);
+      sb.push_back(f);
+      sn.push_back(e - f);
+      lv.push_back((uint32_t)w.h);
+    }
+    uint64_t nsrc, ndst;
+    WinArgs wa = upload_windows(s, sb, sn, sb, sn, lv, st, nsrc, ndst);
+    const uint64_t K = pack_windows(s, wa, nsrc, st);
+    ensure(s->plan_used, s->L * sizeof(uint32_t));
+    HIPCHK(hipMemcpyAsync(s->plan_used.p, s->used.p, s->L * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+    std::vector<uint32_t> fails;
+    plan_spread(s, wa, K, ndst, s->bounds(s->L), s->plan_used.as<uint32_t>(), s->L, false, st, fails);
+    bool any = false;
+    for (uint32_t f : fails) any |= (f != 0);
+    if (!any) {
+      encode_spread(s, wa, ndst, s->bytes.as<uint8_t>(), s->used.as<uint32_t>(), s->head.as<uint64_t>(), st);
+      return true;
+    }
+    for (size_t w = 0; w < wins.size(); w++) {
+      if (!fails[w]) continue;
+      wins[w].h += 1;
+      wins[w].i >>= 1;
+      if (wins[w].h > H) return false;
+    }
+  }
+  throw Fail{CPMA_ERR_DEVICE};
+}
+
+// Spreads the K staged keys (sorted, window 0 = all) evenly over a fresh array of
+// Lt leaves; adjusts Lt by the growing factor until every node is within bounds,
+// then replaces the structure.
+void spread_fresh(cpma* s, uint64_t K, uint64_t Lt, hipStream_t st) {
+  if (K == 0) {
+    DevBuf nb, nu, nh;
+    ensure(nb, s->S);
+    ensure(nu, 4);
+    ensure(nh, 8);
+    HIPCHK(hipMemsetAsync(nb.p, 0, s->S, st));
+    HIPCHK(hipMemsetAsync(nu.p, 0, 4, st));
+    HIPCHK(hipMemsetAsync(nh.p, 0xff, 8, st));
+    HIPCHK(hipStreamSynchronize(st));
+    release(s->bytes);
+    release(s->used);
+    release(s->head);
+    s->bytes = nb;
+    s->used = nu;
+    s->head = nh;
+    s->L = 1;
+    return;
+  }
+  const double g = s->cfg.grow;
+  ensure(s->win_id, K * sizeof(uint32_t));
+  hipLaunchKernelGGL((k_fill<uint32_t>), dim3(grid_for(K, 256, 4096)), dim3(256), 0, st, s->win_id.as<uint32_t>(),
+                     K, 0u);
+  // One window over all staged keys: its source is one flat entry, so the
+  // window's key range comes from koff = {0, K}.
+  ensure(s->koff, 2 * sizeof(uint64_t));
+  uint64_t* hk = reinterpret_cast<uint64_t*>(host_pin(s, 16));
+  hk[0] = 0;
+  hk[1] = K;
+  HIPCHK(hipMemcpyAsync(s->koff.p, hk, 16, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int last_dir = 0;
+  for (int attempt = 0; attempt < 64; attempt++) {
+    uint64_t nsrc, ndst;
+    std::vector<uint64_t> sb{0}, sn{1}, db{0}, dn{Lt};
+    std::vector<uint32_t> lv{(uint32_t)(tree_height(Lt) + 1)};
+    WinArgs wa = upload_windows(s, sb, sn, db, dn, lv, st, nsrc, ndst);
+    DevBuf nb, nu, nh;
+    ensure(nu, Lt * sizeof(uint32_t));
+    std::vector<uint32_t> fails;
+    plan_spread(s, wa, K, ndst, s->bounds(Lt), nu.as<uint32_t>(), Lt, true, st, fails);
+    if (fails[0] == 0) {
+      ensure(nb, Lt * (uint64_t)s->S);
+      ensure(nh, Lt * sizeof(uint64_t));
+      encode_spread(s, wa, ndst, nb.as<uint8_t>(), nu.as<uint32_t>(), nh.as<uint64_t>(), st);
+      HIPCHK(hipStreamSynchronize(st));
+      release(s->bytes);
+      release(s->used);
+      release(s->head);
+      s->bytes = nb;
+      s->used = nu;
+      s->head = nh;
+      s->L = Lt;
+      release(s->ovf);
+      return;
+    }
+    release(nu);
+    int dir = (fails[0] & 1u) ? +1 : -1;
+    if (dir == -1 && Lt == 1) throw Fail{CPMA_ERR_DEVICE};
+    if (last_dir != 0 && dir != last_dir) {
+      // Bounds pull both ways: settle on the larger layout's neighbour.
+      Lt = Lt + 1;
+    } else if (dir > 0) {
+      Lt = std::max<uint64_t>(Lt + 1, (uint64_t)std::ceil(g * (double)Lt));
+    } else {
+      Lt = std::max<uint64_t>(1, (uint64_t)std::floor((double)Lt / g));
+    }
+    last_dir = dir;
+  }
+  throw Fail{CPMA_ERR_DEVICE};
+}
+
+// Root out of bounds: copy everything to an array grown (or shrunk) by the growing
+// factor and spread evenly (Section "Packed Memory Array", "Resizing a PMA").
+void resize(cpma* s, uint64_t total, uint32_t viol, hipStream_t st) {
+  const double g = s->cfg.grow;
+  const int64_t Q = kQ;
+  uint64_t Lt = s->L;
+  if (viol & 1u) {
+    do {
+      Lt = std::max<uint64_t>(Lt + 1, (uint64_t)std::ceil(g * (double)Lt));
+    } while ((__int128)(total + 8 * Lt) * Q > (__int128)s->q_up_root * Lt * s->S);
+  } else {
+    while (Lt > 1 && (__int128)total * Q < (__int128)s->q_lo_root * Lt * s->S)
+      Lt = std::max<uint64_t>(1, (uint64_t)std::floor((double)Lt / g));
+  }
+  uint64_t nsrc, ndst;
+  std::vector<uint64_t> sb{0}, sn{s->L};
+  std::vector<uint32_t> lv{(uint32_t)(tree_height(s->L) + 1)};
+  WinArgs wa = upload_windows(s, sb, sn, sb, sn, lv, st, nsrc, ndst);
+  const uint64_t K = pack_windows(s, wa, nsrc, st);
+  if (K != s->n) throw Fail{CPMA_ERR_DEVICE};
+  spread_fresh(s, K, Lt, st);
+}
+
+// Counting + redistribution until every node of the implicit tree is within its
+// bounds.
+void rebalance(cpma* s, hipStream_t st) {
+  for (int round = 0; round < 256; round++) {
+    Pyramid P = make_pyramid(s, s->L);
+    build_pyramid(s, P, s->used.as<uint32_t>(), s->L, st);
+    ensure(s->win, std::max<uint64_t>(s->L, 1) * sizeof(uint64_t));
+    zero_counters(s, st);
+    const uint64_t nodes = (P.H == 0) ? 1 : P.off[P.H] + P.cnt[P.H];
+    hipLaunchKernelGGL(k_select, dim3(grid_for(nodes, 256, 1u << 16)), dim3(256), 0, st, s->bounds(s->L), P,
+                       (const uint32_t*)s->used.as<uint32_t>(), s->win.as<uint64_t>(), s->dctr);
+    HIPCHK(hipGetLastError());
+    read_counters(s, st);
+    const Counters c = *s->hctr;
+    if (c.root_viol) {
+      resize(s, c.root_sum, c.root_viol, st);
+      continue;
+    }
+    if (c.nwin == 0) return;
+    uint64_t* hw = reinterpret_cast<uint64_t*>(host_pin(s, c.nwin * 8ull));
+    HIPCHK(hipMemcpyAsync(hw, s->win.p, c.nwin * 8ull, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<Win> wins(c.nwin);
+    for (uint32_t w = 0; w < c.nwin; w++) wins[w] = Win{(int)(hw[w] >> 48), hw[w] & ((1ull << 48) - 1)};
+    if (!redistribute(s, wins, st)) {
+      // Escalation past the root: grow if the structure is dense, else shrink.
+      const uint64_t total = c.root_sum;
+      const bool dense = (__int128)total * kQ * 2 >
+                         (__int128)(s->q_up_root + s->q_lo_root) * s->L * s->S;
+      resize(s, total, dense ? 1u : 2u, st);
+    }
+  }
+  throw Fail{CPMA_ERR_DEVICE};
+}
+
+uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, hipStream_t st) {
+  ensure(s->leafid, kbound * sizeof(uint32_t));
+  ensure(s->seg_leaf, kbound * sizeof(uint32_t));
+  ensure(s->seg_begin, (kbound + 1) * sizeof(uint32_t));
+  ensure(s->heavy, kbound * sizeof(uint32_t));
+  ensure(s->ovf, std::max<uint64_t>(s->L, 1) * sizeof(uint64_t));
+  const uint64_t arena_cap = insert ? std::min<uint64_t>(s->L, kbound) * (uint64_t)(s->S + 16) + 10 * kbound + 256 : 256;
+  ensure(s->arena, arena_cap);
+  const uint64_t stage_cap = insert ? s->n + kbound + 64 : 64;
+  ensure(s->stage, stage_cap * sizeof(uint64_t));
+  hipLaunchKernelGGL(k_locate, dim3(grid_for(kbound, 256, 1u << 16)), dim3(256), 0, st, B,
+                     (const unsigned long long*)&s->dctr->kprime, (const uint64_t*)s->head.as<uint64_t>(), s->L,
+                     s->leafid.as<uint32_t>());
+  HIPCHK(hipGetLastError());
+  scan<uint32_t>(s, s->segpos.as<uint32_t>(), kbound, st,
+                 SegFlag{s->leafid.as<uint32_t>(), (const unsigned long long*)&s->dctr->kprime});
+  hipLaunchKernelGGL(k_segments, dim3(grid_for(kbound, 256, 1u << 16)), dim3(256), 0, st,
+                     (const uint32_t*)s->leafid.as<uint32_t>(), (const unsigned long long*)&s->dctr->kprime,
+                     (const uint32_t*)s->segpos.as<uint32_t>(), kbound, s->seg_leaf.as<uint32_t>(),
+                     s->seg_begin.as<uint32_t>(), s->dctr);
+  HIPCHK(hipGetLastError());
+  MergeArgs a;
+  a.bytes = s->bytes.as<uint8_t>();
+  a.used = s->used.as<uint32_t>();
+  a.head = s->head.as<uint64_t>();
+  a.ovf = s->ovf.as<uint64_t>();
+  a.arena = s->arena.as<uint8_t>();
+  a.arena_cap = s->arena.cap;
+  a.stage = s->stage.as<uint64_t>();
+  a.stage_cap = s->stage.cap / sizeof(uint64_t);
+  a.B = B;
+  a.seg_leaf = s->seg_leaf.as<uint32_t>();
+  a.seg_begin = s->seg_begin.as<uint32_t>();
+  a.heavy_list = s->heavy.as<uint32_t>();
+  a.ctr = s->dctr;
+  a.S = s->S;
+  a.is_insert = insert ? 1 : 0;
+  const uint32_t mgrid = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(kbound, s->L), (uint64_t)s->num_cus * 16);
+  hipLaunchKernelGGL(k_merge, dim3(std::max(1u, mgrid)), dim3(kWave), merge_smem(s->S), st, a);
+  HIPCHK(hipGetLastError());
+  if (insert) {
+    hipLaunchKernelGGL(k_merge_heavy, dim3(std::max(1u, std::min(mgrid, 1024u))), dim3(kWave), heavy_smem(s->S),
+                       st, a);
+    HIPCHK(hipGetLastError());
+  }
+  read_counters(s, st);
+  const uint64_t delta = s->hctr->delta;
+  if (insert)
+    s->n += delta;
+  else
+    s->n -= delta;
+  rebalance(s, st);
+  return delta;
+}
+
+cpma_status check_config(const cpma_config& c) {
+  if (c.leaf_bytes < 64 || c.leaf_bytes > 2048 || (c.leaf_bytes & (c.leaf_bytes - 1))) return CPMA_ERR_INVALID;
+  if (!(c.grow > 1.0 && c.grow <= 4.0)) return CPMA_ERR_INVALID;
+  if (!(c.lo_leaf > 0 && c.lo_leaf <= c.lo_root && c.lo_root < c.up_root && c.up_root <= c.up_leaf &&
+        c.up_leaf < 1.0))
+    return CPMA_ERR_INVALID;
+  if (!(c.lo_root * c.grow < c.up_root)) return CPMA_ERR_INVALID;
+  if (!(c.build_density > c.lo_root && c.build_density < c.up_root)) return CPMA_ERR_INVALID;
+  return CPMA_OK;
+}
+
+template <class F>
+cpma_status guarded(cpma* s, F&& f) {
+  try {
+    f();
+    return CPMA_OK;
+  } catch (const Fail& e) {
+    if (s && (e.st == CPMA_ERR_DEVICE || e.st == CPMA_ERR_NOMEM)) s->broken = true;
+    return e.st;
+  }
+}
+
+}  // namespace
+
+// =============================================================================
+// C ABI
+// =============================================================================
+extern "C" {
+
+cpma_status cpma_config_default(cpma_config* cfg) {
+  if (!cfg) return CPMA_ERR_INVALID;
+  cfg->leaf_bytes = 1024;
+  cfg->grow = 1.2;
+  cfg->up_leaf = 0.90;
+  cfg->up_root = 0.70;
+  cfg->lo_leaf = 0.10;
+  cfg->lo_root = 0.30;
+  cfg->build_density = cfg->up_root / cfg->grow;
+  return CPMA_OK;
+}
+
+const char* cpma_status_str(cpma_status s) {
+  switch (s) {
+    case CPMA_OK: return "ok";
+    case CPMA_ERR_INVALID: return "invalid argument";
+    case CPMA_ERR_NOMEM: return "device allocation failed";
+    case CPMA_ERR_DEVICE: return "device error";
+    case CPMA_ERR_RESERVED_KEY: return "reserved key (UINT64_MAX)";
+  }
+  return "unknown status";
+}
+
+cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpma_config* cfg_in, void* stream,
+                       cpma** out) {
+  if (!out) return CPMA_ERR_INVALID;
+  *out = nullptr;
+  if (n > 0 && !keys) return CPMA_ERR_INVALID;
+  cpma_config cfg;
+  cpma_config_default(&cfg);
+  if (cfg_in) {
+    if (cfg_in->leaf_bytes) cfg.leaf_bytes = cfg_in->leaf_bytes;
+    if (cfg_in->grow > 0) cfg.grow = cfg_in->grow;
+    if (cfg_in->up_leaf > 0) cfg.up_leaf = cfg_in->up_leaf;
+    if (cfg_in->up_root > 0) cfg.up_root = cfg_in->up_root;
+    if (cfg_in->lo_leaf > 0) cfg.lo_leaf = cfg_in->lo_leaf;
+    if (cfg_in->lo_root > 0) cfg.lo_root = cfg_in->lo_root;
+    cfg.build_density = cfg_in->build_density > 0 ? cfg_in->build_density : cfg.up_root / cfg.grow;
+  }
+  cpma_status cs = check_config(cfg);
+  if (cs != CPMA_OK) return cs;
+  cpma* s = new cpma();
+  s->cfg = cfg;
+  s->S = cfg.leaf_bytes;
+  s->q_up_leaf = llround(cfg.up_leaf * (double)kQ);
+  s->q_up_root = llround(cfg.up_root * (double)kQ);
+  s->q_lo_leaf = llround(cfg.lo_leaf * (double)kQ);
+  s->q_lo_root = llround(cfg.lo_root * (double)kQ);
+  hipStream_t st = (hipStream_t)stream;
+  cpma_status r = guarded(s, [&] {
+    HIPCHK(hipGetDevice(&s->device));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, s->device));
+    s->num_cus = prop.multiProcessorCount;
+    HIPCHK(hipMalloc(&s->dctr, sizeof(Counters)));
+    HIPCHK(hipHostMalloc(&s->hctr, sizeof(Counters), hipHostMallocDefault));
+    HIPCHK(hipMalloc(&s->dinfo, sizeof(BatchInfo)));
+    HIPCHK(hipHostMalloc(&s->hinfo, sizeof(BatchInfo), hipHostMallocDefault));
+    zero_counters(s, st);
+    uint64_t K = 0;
+    if (n > 0) {
+      const uint64_t* B = prepare_batch(s, keys, n, mem, st);
+      read_counters(s, st);
+      K = s->hctr->kprime;
+      ensure(s->stage, std::max<uint64_t>(K, 1) * sizeof(uint64_t));
+      HIPCHK(hipMemcpyAsync(s->stage.p, B, K * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    }
+    s->n = K;
+    uint64_t Lt = 1;
+    if (K > 0) {
+      // Total bytes of the keys as one delta chain: the head plus every delta code.
+      ensure(s->win_id, K * sizeof(uint32_t));
+      hipLaunchKernelGGL((k_fill<uint32_t>), dim3(grid_for(K, 256, 4096)), dim3(256), 0, st,
+                         s->win_id.as<uint32_t>(), K, 0u);
+      ensure(s->welem, 2 * sizeof(uint64_t));
+      uint64_t* kk = reinterpret_cast<uint64_t*>(host_pin(s, 16));
+      kk[0] = 0;
+      kk[1] = K;
+      HIPCHK(hipMemcpyAsync(s->welem.p, kk, 16, hipMemcpyHostToDevice, st));
+      ensure(s->P, (K + 1) * sizeof(uint64_t));
+      scan<uint64_t>(s, s->P.as<uint64_t>(), K, st,
+                     CostFn{s->stage.as<uint64_t>(), s->win_id.as<uint32_t>(), s->welem.as<uint64_t>()});
+      uint64_t tot = 0;
+      HIPCHK(hipMemcpyAsync(&s->hctr->root_sum, s->P.as<uint64_t>() + K, 8, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      tot = s->hctr->root_sum;
+      Lt = std::max<uint64_t>(1, (uint64_t)std::ceil((double)tot / (cfg.build_density * (double)s->S)));
+    }
+    spread_fresh(s, K, Lt, st);
+    rebalance(s, st);
+  });
+  if (r != CPMA_OK) {
+    cpma_destroy(s);
+    return r;
+  }
+  *out = s;
+  return CPMA_OK;
+}
+
+static cpma_status update(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem mem, int sorted, void* stream,
+                          uint64_t* delta_out, bool insert) {
+  (void)sorted;  // sortedness is checked on the device either way
+  if (delta_out) *delta_out = 0;
+  if (!s) return CPMA_ERR_INVALID;
+  if (s->broken) return CPMA_ERR_DEVICE;
+  if (k == 0) return CPMA_OK;
+  if (!keys) return CPMA_ERR_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  uint64_t delta = 0;
+  cpma_status r = guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    zero_counters(s, st);
+    const uint64_t* B = prepare_batch(s, keys, k, mem, st);
+    delta = apply_batch(s, B, k, insert, st);
+  });
+  if (r == CPMA_OK && delta_out) *delta_out = delta;
+  return r;
+}
+
+cpma_status cpma_insert_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem mem, int sorted, void* stream,
+                              uint64_t* n_added) {
+  return update(s, keys, k, mem, sorted, stream, n_added, true);
+}
+
+cpma_status cpma_delete_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem mem, int sorted, void* stream,
+                              uint64_t* n_removed) {
+  return update(s, keys, k, mem, sorted, stream, n_removed, false);
+}
+
+static QueryArgs query_args(const cpma* s) {
+  QueryArgs a;
+  a.head = (const uint64_t*)s->head.p;
+  a.bytes = (const uint8_t*)s->bytes.p;
+  a.used = (const uint32_t*)s->used.p;
+  a.L = s->L;
+  a.S = s->S;
+  return a;
+}
+
+cpma_status cpma_range_map(const cpma* cs, const uint64_t* lo, const uint64_t* hi, uint64_t q, cpma_mem mem,
+                           uint64_t* sum, uint64_t* count, void* stream) {
+  cpma* s = const_cast<cpma*>(cs);
+  if (!s) return CPMA_ERR_INVALID;
+  if (s->broken) return CPMA_ERR_DEVICE;
+  if (q == 0) return CPMA_OK;
+  if (!lo || !hi || !sum || !count) return CPMA_ERR_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  return guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    QueryArgs a = query_args(s);
+    a.q = q;
+    unsigned long long* dsum = (unsigned long long*)sum;
+    unsigned long long* dcount = (unsigned long long*)count;
+    if (mem == CPMA_MEM_HOST) {
+      ensure(s->qa, q * 8);
+      ensure(s->qb, q * 8);
+      HIPCHK(hipMemcpyAsync(s->qa.p, lo, q * 8, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(s->qb.p, hi, q * 8, hipMemcpyHostToDevice, st));
+      a.lo = s->qa.as<uint64_t>();
+      a.hi = s->qb.as<uint64_t>();
+      ensure(s->qsum, q * 8);
+      ensure(s->qcount, q * 8);
+      dsum = s->qsum.as<unsigned long long>();
+      dcount = s->qcount.as<unsigned long long>();
+    } else {
+      a.lo = lo;
+      a.hi = hi;
+    }
+    ensure(s->qfirst, q * 8);
+    ensure(s->qnvis, q * 8);
+    ensure(s->qvoff, (q + 1) * 8);
+    hipLaunchKernelGGL(k_rm_locate, dim3(grid_for(q, 256, 1u << 16)), dim3(256), 0, st, a,
+                       s->qfirst.as<uint64_t>(), s->qnvis.as<uint64_t>(), dsum, dcount);
+    HIPCHK(hipGetLastError());
+    scan<uint64_t>(s, s->qvoff.as<uint64_t>(), q, st, LoadFn<uint64_t>{s->qnvis.as<uint64_t>()});
+    const uint32_t blocks = (uint32_t)s->num_cus * 8;
+    hipLaunchKernelGGL(k_rm_scan, dim3(blocks), dim3(256), 0, st, a, (const uint64_t*)s->qvoff.as<uint64_t>(),
+                       (const uint64_t*)s->qfirst.as<uint64_t>(), 4u, dsum, dcount);
+    HIPCHK(hipGetLastError());
+    if (mem == CPMA_MEM_HOST) {
+      HIPCHK(hipMemcpyAsync(sum, dsum, q * 8, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(count, dcount, q * 8, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+  });
+}
+
+cpma_status cpma_contains(const cpma* cs, const uint64_t* keys, uint64_t q, cpma_mem mem, uint8_t* out,
+                          void* stream) {
+  cpma* s = const_cast<cpma*>(cs);
+  if (!s) return CPMA_ERR_INVALID;
+  if (s->broken) return CPMA_ERR_DEVICE;
+  if (q == 0) return CPMA_OK;
+  if (!keys || !out) return CPMA_ERR_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  return guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    QueryArgs a = query_args(s);
+    a.q = q;
+    const uint64_t* dk = keys;
+    uint8_t* dout = out;
+    if (mem == CPMA_MEM_HOST) {
+      ensure(s->qa, q * 8);
+      ensure(s->qout, q);
+      HIPCHK(hipMemcpyAsync(s->qa.p, keys, q * 8, hipMemcpyHostToDevice, st));
+      dk = s->qa.as<uint64_t>();
+      dout = s->qout.as<uint8_t>();
+    }
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((q + 3) / 4, (uint64_t)s->num_cus * 8);
+    hipLaunchKernelGGL(k_contains, dim3(std::max(1u, blocks)), dim3(256), 0, st, a, dk, dout);
+    HIPCHK(hipGetLastError());
+    if (mem == CPMA_MEM_HOST) {
+      HIPCHK(hipMemcpyAsync(out, dout, q, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+  });
+}
+
+uint64_t cpma_size(const cpma* s) { return s ? s->n : 0; }
+
+uint64_t cpma_bytes(const cpma* s) { return s ? s->L * ((uint64_t)s->S + 8 + 4) : 0; }
+
+cpma_status cpma_geometry(const cpma* s, uint64_t* num_leaves, uint32_t* leaf_bytes) {
+  if (!s) return CPMA_ERR_INVALID;
+  if (num_leaves) *num_leaves = s->L;
+  if (leaf_bytes) *leaf_bytes = s->S;
+  return CPMA_OK;
+}
+
+cpma_status cpma_export(const cpma* cs, uint8_t* bytes, uint32_t* used, uint64_t* head, void* stream) {
+  cpma* s = const_cast<cpma*>(cs);
+  if (!s) return CPMA_ERR_INVALID;
+  if (s->broken) return CPMA_ERR_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  return guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    if (bytes) HIPCHK(hipMemcpyAsync(bytes, s->bytes.p, s->L * (uint64_t)s->S, hipMemcpyDeviceToHost, st));
+    if (used) HIPCHK(hipMemcpyAsync(used, s->used.p, s->L * 4, hipMemcpyDeviceToHost, st));
+    if (head) HIPCHK(hipMemcpyAsync(head, s->head.p, s->L * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
+void cpma_destroy(cpma* s) {
+  if (!s) return;
+  hipDeviceSynchronize();
+  DevBuf* bufs[] = {&s->bytes,  &s->used,     &s->head,      &s->kin,       &s->kb0,   &s->kb1,    &s->kdedup,
+                    &s->leafid, &s->segpos,   &s->seg_leaf,  &s->seg_begin, &s->heavy, &s->scan_tmp,
+                    &s->ovf,    &s->arena,    &s->stage,     &s->pyr,       &s->win,   &s->wargs,  &s->cnt,
+                    &s->koff,   &s->win_id,   &s->welem,     &s->P,         &s->ncost, &s->lstart, &s->planU,
+                    &s->plan_used, &s->win_of_leaf, &s->fail, &s->qa,        &s->qb,    &s->qfirst, &s->qnvis,
+                    &s->qvoff,  &s->qsum,     &s->qcount,    &s->qout};
+  for (DevBuf* b : bufs) release(*b);
+  if (s->dctr) hipFree(s->dctr);
+  if (s->dinfo) hipFree(s->dinfo);
+  if (s->hctr) hipHostFree(s->hctr);
+  if (s->hinfo) hipHostFree(s->hinfo);
+  if (s->hpin) hipHostFree(s->hpin);
+  delete s;
+}
+
+}  // extern "C"

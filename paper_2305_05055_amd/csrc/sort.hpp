@@ -1,0 +1,127 @@
+// Batch prep: stable LSD radix sort of 64-bit keys (8-bit digits, only as many
+// passes as the OR of the keys needs) followed by removal of repeated keys.
+// The paper sorts an unsorted batch in O(k log k) before merging it (Section
+// "Parallel Batch Updates in a PMA"); on the GPU a radix sort does it in O(k)
+// passes over HBM.
+#pragma once
+#include "scan.hpp"
+
+namespace cpma_dev {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr uint32_t kSortTile = kSortThreads * kSortItems;  // keys per block
+
+// Validation pass over a batch: OR of all keys (radix pass count), whether a
+// reserved key occurs, and whether the batch is already non-decreasing.
+struct BatchInfo {
+  unsigned long long or_all;
+  unsigned int has_reserved;
+  unsigned int unsorted;
+};
+
+__global__ void __launch_bounds__(256) k_validate(const uint64_t* __restrict__ keys, uint64_t k,
+                                                  BatchInfo* info) {
+  uint64_t orv = 0;
+  uint32_t res = 0, uns = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t x = keys[i];
+    orv |= x;
+    res |= (x == kNoKey);
+    if (i + 1 < k && keys[i + 1] < x) uns = 1;
+  }
+  orv = wave_or(orv);
+  uint64_t flags = wave_or((uint64_t)(res | (uns << 1)));
+  if (lane_id() == 0) {
+    if (orv) atomicOr(&info->or_all, (unsigned long long)orv);
+    if (flags & 1) atomicOr(&info->has_reserved, 1u);
+    if (flags & 2) atomicOr(&info->unsorted, 1u);
+  }
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t* __restrict__ in,
+                                                             uint32_t n, int shift,
+                                                             uint32_t* __restrict__ ghist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t base = blockIdx.x * kSortTile;
+#pragma unroll 4
+  for (int r = 0; r < kSortItems; r++) {
+    uint32_t i = base + r * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(in[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  ghist[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// Scatter with stable in-block ranks.  Keys are visited round by round (round r
+// holds tile positions r*256 .. r*256+255); inside a round a lane's rank among
+// equal digits comes from eight ballots, across waves from per-wave digit counts,
+// across rounds from a running per-digit count.
+__global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint64_t* __restrict__ in,
+                                                                uint64_t* __restrict__ out,
+                                                                uint32_t n, int shift,
+                                                                const uint32_t* __restrict__ goff) {
+  constexpr int kW = kSortThreads / kWave;
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[kW][256];
+  __shared__ uint32_t base_ofs[256];
+  const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+  run[tid] = 0;
+#pragma unroll
+  for (int w = 0; w < kW; w++) wcnt[w][tid] = 0;
+  base_ofs[tid] = goff[(uint64_t)tid * gridDim.x + blockIdx.x];
+  __syncthreads();
+  const uint32_t base = blockIdx.x * kSortTile;
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  for (int r = 0; r < kSortItems; r++) {
+    const uint32_t i = base + r * kSortThreads + tid;
+    const bool valid = i < n;
+    const uint64_t x = valid ? in[i] : 0;
+    const uint32_t d = (uint32_t)(x >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+    if (valid && rank == 0) wcnt[wid][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = base_ofs[d] + run[d] + rank;
+      for (int w = 0; w < wid; w++) pos += wcnt[w][d];
+      out[pos] = x;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kW; w++) {
+      add += wcnt[w][tid];
+      wcnt[w][tid] = 0;
+    }
+    run[tid] += add;
+    __syncthreads();
+  }
+}
+
+// Flags of first occurrences in a sorted array.
+struct FirstFlag {
+  const uint64_t* a;
+  __device__ uint32_t operator()(uint64_t i) const { return (i == 0 || a[i] != a[i - 1]) ? 1u : 0u; }
+};
+
+__global__ void k_compact_unique(const uint64_t* __restrict__ a, uint64_t n,
+                                 const uint32_t* __restrict__ pos, uint64_t* __restrict__ out,
+                                 unsigned long long* __restrict__ n_out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    if (i == 0 || a[i] != a[i - 1]) out[pos[i]] = a[i];
+    if (i == 0) *n_out = pos[n];
+  }
+}
+
+}  // namespace cpma_dev

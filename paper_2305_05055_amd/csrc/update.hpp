@@ -1,0 +1,605 @@
+// Batch-update kernels: leaf location, per-leaf merge, density counting up the
+// implicit tree and window redistribution (Section "Parallel Batch Updates in a
+// PMA": batch-merge phase, counting phase, redistribution phase).
+#pragma once
+#include "leaf.hpp"
+#include "scan.hpp"
+
+namespace cpma_dev {
+
+constexpr uint32_t kSliceCap = 1024;  // batch keys merged per leaf in LDS; more -> heavy path
+
+// Device-side counters of one update, read back by the host at its sync points.
+struct Counters {
+  unsigned long long delta;         // keys added (insert) or removed (delete)
+  unsigned long long arena_cursor;  // bytes used in the overflow arena
+  unsigned long long stage_cursor;  // keys used in the staging buffer by heavy merges
+  unsigned long long kprime;        // batch size after removing repeats
+  unsigned long long T;             // touched leaves (segments)
+  unsigned long long root_sum;      // filled bytes of the whole structure
+  unsigned int heavy;               // segments routed to the heavy merge
+  unsigned int nwin;                // windows selected for redistribution
+  unsigned int root_viol;           // violation bits of the root
+  unsigned int error;               // internal capacity overflow (bug guard)
+};
+
+__device__ __forceinline__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t x) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint64_t mid = (lo + hi) >> 1;
+    if (a[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+__device__ __forceinline__ uint64_t upper_bound_u64(const uint64_t* a, uint64_t n, uint64_t x) {
+  uint64_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint64_t mid = (lo + hi) >> 1;
+    if (a[mid] <= x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Leaf that holds (or would hold) key x: the last leaf whose head is <= x, leaf 0
+// for keys below every head (Section "Compressed Packed Memory Array", "Point
+// queries": binary search on the uncompressed leaf heads).
+__device__ __forceinline__ uint64_t locate_leaf(const uint64_t* head, uint64_t L, uint64_t x) {
+  uint64_t ub = upper_bound_u64(head, L, x);
+  return ub ? ub - 1 : 0;
+}
+
+__global__ void k_locate(const uint64_t* __restrict__ B, const unsigned long long* kprime,
+                         const uint64_t* __restrict__ head, uint64_t L, uint32_t* __restrict__ leafid) {
+  const uint64_t k = *kprime;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    leafid[i] = (uint32_t)locate_leaf(head, L, B[i]);
+}
+
+struct SegFlag {
+  const uint32_t* leafid;
+  const unsigned long long* kprime;
+  __device__ uint32_t operator()(uint64_t i) const {
+    return (i < *kprime && (i == 0 || leafid[i] != leafid[i - 1])) ? 1u : 0u;
+  }
+};
+
+// Touched leaves: one segment per run of equal leaf ids (the batch slice bound
+// for each leaf, which the paper finds with two exponential searches).
+__global__ void k_segments(const uint32_t* __restrict__ leafid, const unsigned long long* kprime,
+                           const uint32_t* __restrict__ segpos, uint64_t kbound,
+                           uint32_t* __restrict__ seg_leaf, uint32_t* __restrict__ seg_begin,
+                           Counters* ctr) {
+  const uint64_t k = *kprime;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    if (i == 0 || leafid[i] != leafid[i - 1]) {
+      seg_leaf[segpos[i]] = leafid[i];
+      seg_begin[segpos[i]] = (uint32_t)i;
+    }
+    if (i == 0) {
+      uint32_t T = segpos[kbound];
+      seg_begin[T] = (uint32_t)k;
+      ctr->T = T;
+    }
+  }
+}
+
+// ---- per-leaf merge -------------------------------------------------------------
+struct MergeArgs {
+  uint8_t* bytes;
+  uint32_t* used;
+  uint64_t* head;
+  uint64_t* ovf;          // arena offset of an overflowing leaf
+  uint8_t* arena;
+  uint64_t arena_cap;
+  uint64_t* stage;        // heavy-merge output keys
+  uint64_t stage_cap;
+  const uint64_t* B;      // sorted, repeat-free batch
+  const uint32_t* seg_leaf;
+  const uint32_t* seg_begin;
+  uint32_t* heavy_list;
+  Counters* ctr;
+  uint32_t S;
+  int is_insert;
+};
+
+__device__ __forceinline__ uint64_t lds_lower_bound(const uint64_t* A, uint32_t n, uint64_t x) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (A[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Exclusive prefix sum in place over F[0..n) (one wave).
+__device__ __forceinline__ void wave_scan_inplace(uint32_t* F, uint32_t n) {
+  uint32_t run = 0;
+  for (uint32_t base = 0; base < n; base += kWave) {
+    const uint32_t i = base + lane_id();
+    const uint32_t v = i < n ? F[i] : 0u;
+    const uint32_t incl = wave_incl_scan(v);
+    if (i < n) F[i] = run + incl - v;
+    run += __shfl(incl, kWave - 1, kWave);
+  }
+}
+
+// Writes keys get(0..m) into leaf `leaf`: in place if they fit, else into the
+// overflow arena (the paper's out-of-place memory for an overflowing leaf,
+// cleaned up by the redistribution).  Updates used / head / ovf.
+template <class Get>
+__device__ void wave_store_leaf(const MergeArgs& a, uint64_t leaf, Get&& get, uint32_t m,
+                                uint8_t* buf) {
+  const int lane = lane_id();
+  uint8_t* dst = a.bytes + leaf * (uint64_t)a.S;
+  if (m == 0) {
+    wave_zero(dst, a.S);
+    if (lane == 0) {
+      a.used[leaf] = 0;
+      a.head[leaf] = kNoKey;
+    }
+    return;
+  }
+  const uint64_t T = wave_encoded_size(get, m);
+  if (T <= a.S) {
+    wave_zero(buf, a.S);
+    __syncthreads();
+    wave_encode_bytes(get, m, buf);
+    __syncthreads();
+    wave_copy16(dst, buf, a.S);
+  } else {
+    const uint64_t need = (T + 15) & ~15ull;
+    uint64_t off = 0;
+    if (lane == 0) off = atomicAdd(&a.ctr->arena_cursor, (unsigned long long)need);
+    off = __shfl(off, 0, kWave);
+    if (off + need > a.arena_cap) {
+      if (lane == 0) atomicOr(&a.ctr->error, 1u);
+      return;
+    }
+    wave_encode_bytes(get, m, a.arena + off);
+    if (lane == 0) a.ovf[leaf] = off;
+  }
+  if (lane == 0) {
+    a.used[leaf] = (uint32_t)T;
+    a.head[leaf] = get(0);
+  }
+}
+
+// One wave (block of 64) per touched leaf: decode the leaf into LDS, merge its
+// batch slice (union for inserts, difference for deletes), re-encode.
+__global__ void __launch_bounds__(kWave) k_merge(MergeArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const uint32_t S = a.S;
+  const uint32_t maxA = S - 7;
+  uint64_t* A = reinterpret_cast<uint64_t*>(smem);
+  uint64_t* C = A + maxA + 1;
+  uint32_t* F = reinterpret_cast<uint32_t*>(C + maxA + kSliceCap + 1);
+  uint8_t* buf = reinterpret_cast<uint8_t*>(F + ((maxA + 4) & ~3u));
+  const int lane = lane_id();
+  const uint64_t T = a.ctr->T;
+  unsigned long long delta = 0;
+  for (uint64_t s = blockIdx.x; s < T; s += gridDim.x) {
+    const uint64_t leaf = a.seg_leaf[s];
+    const uint32_t b = a.seg_begin[s], e = a.seg_begin[s + 1];
+    const uint32_t nb = e - b;
+    const uint64_t* Bs = a.B + b;
+    if (a.is_insert && nb > kSliceCap) {
+      if (lane == 0) a.heavy_list[atomicAdd(&a.ctr->heavy, 1u)] = (uint32_t)s;
+      continue;
+    }
+    const uint8_t* src = a.bytes + leaf * (uint64_t)S;
+    const uint32_t nA = wave_decode_leaf(src, a.used[leaf], [&](uint32_t i, uint64_t x) { A[i] = x; });
+    __syncthreads();
+    uint32_t nC;
+    if (a.is_insert) {
+      for (uint32_t i = lane; i <= nA; i += kWave) F[i] = 0;
+      __syncthreads();
+      for (uint32_t j = lane; j < nb; j += kWave) {
+        const uint64_t x = Bs[j];
+        const uint32_t r = (uint32_t)lds_lower_bound(A, nA, x);
+        if (r < nA && A[r] == x) F[r] = 1;
+      }
+      __syncthreads();
+      wave_scan_inplace(F, nA + 1);
+      __syncthreads();
+      const uint32_t present = F[nA];
+      for (uint32_t j = lane; j < nb; j += kWave) {
+        const uint64_t x = Bs[j];
+        const uint32_t r = (uint32_t)lds_lower_bound(A, nA, x);
+        if (!(r < nA && A[r] == x)) C[r + j - F[r]] = x;
+      }
+      for (uint32_t i = lane; i < nA; i += kWave) {
+        const uint32_t lb = (uint32_t)lower_bound_u64(Bs, nb, A[i]);
+        C[i + lb - F[i]] = A[i];
+      }
+      nC = nA + nb - present;
+      delta += nb - present;
+    } else {
+      for (uint32_t i = lane; i < nA; i += kWave) {
+        const uint64_t x = A[i];
+        const uint64_t r = lower_bound_u64(Bs, nb, x);
+        F[i] = (r < nb && Bs[r] == x) ? 0u : 1u;
+      }
+      if (lane == 0) F[nA] = 0;
+      __syncthreads();
+      wave_scan_inplace(F, nA + 1);
+      __syncthreads();
+      for (uint32_t i = lane; i < nA; i += kWave) {
+        const bool keep = F[i + 1] != F[i];
+        if (keep) C[F[i]] = A[i];
+      }
+      nC = F[nA];
+      delta += nA - nC;
+    }
+    __syncthreads();
+    wave_store_leaf(a, leaf, [&](uint32_t i) { return C[i]; }, nC, buf);
+    __syncthreads();
+  }
+  if (lane == 0 && delta) atomicAdd(&a.ctr->delta, delta);
+}
+
+// Heavy inserts: a slice larger than kSliceCap.  The merged keys go to the
+// staging buffer in HBM (each output position from two binary searches), then
+// are encoded in place or into the arena.
+__global__ void __launch_bounds__(kWave) k_merge_heavy(MergeArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const uint32_t S = a.S;
+  const uint32_t maxA = S - 7;
+  uint64_t* A = reinterpret_cast<uint64_t*>(smem);
+  uint32_t* F = reinterpret_cast<uint32_t*>(A + maxA + 1);
+  uint8_t* buf = reinterpret_cast<uint8_t*>(F + ((maxA + 4) & ~3u));
+  const int lane = lane_id();
+  const uint32_t nheavy = a.ctr->heavy;
+  unsigned long long delta = 0;
+  for (uint32_t h = blockIdx.x; h < nheavy; h += gridDim.x) {
+    const uint32_t s = a.heavy_list[h];
+    const uint64_t leaf = a.seg_leaf[s];
+    const uint32_t b = a.seg_begin[s], e = a.seg_begin[s + 1];
+    const uint32_t nb = e - b;
+    const uint64_t* Bs = a.B + b;
+    const uint8_t* src = a.bytes + leaf * (uint64_t)S;
+    const uint32_t nA = wave_decode_leaf(src, a.used[leaf], [&](uint32_t i, uint64_t x) { A[i] = x; });
+    for (uint32_t i = lane; i <= nA; i += kWave) F[i] = 0;
+    __syncthreads();
+    for (uint32_t j = lane; j < nb; j += kWave) {
+      const uint64_t x = Bs[j];
+      const uint32_t r = (uint32_t)lds_lower_bound(A, nA, x);
+      if (r < nA && A[r] == x) F[r] = 1;
+    }
+    __syncthreads();
+    wave_scan_inplace(F, nA + 1);
+    __syncthreads();
+    const uint32_t present = F[nA];
+    const uint32_t nC = nA + nb - present;
+    uint64_t off = 0;
+    if (lane == 0) off = atomicAdd(&a.ctr->stage_cursor, (unsigned long long)nC);
+    off = __shfl(off, 0, kWave);
+    if (off + nC > a.stage_cap) {
+      if (lane == 0) atomicOr(&a.ctr->error, 2u);
+      continue;
+    }
+    uint64_t* C = a.stage + off;
+    for (uint32_t j = lane; j < nb; j += kWave) {
+      const uint64_t x = Bs[j];
+      const uint32_t r = (uint32_t)lds_lower_bound(A, nA, x);
+      if (!(r < nA && A[r] == x)) C[r + j - F[r]] = x;
+    }
+    for (uint32_t i = lane; i < nA; i += kWave) {
+      const uint32_t lb = (uint32_t)lower_bound_u64(Bs, nb, A[i]);
+      C[i + lb - F[i]] = A[i];
+    }
+    delta += nb - present;
+    __threadfence_block();
+    __syncthreads();
+    wave_store_leaf(a, leaf, [&](uint32_t i) { return C[i]; }, nC, buf);
+    __syncthreads();
+  }
+  if (lane == 0 && delta) atomicAdd(&a.ctr->delta, delta);
+}
+
+// ---- counting phase: byte sums of every node of the implicit tree ----------------
+constexpr int kPyrThreads = 256;
+constexpr int kPyrLowLevels = 9;  // levels 1..9 per block of 512 leaves
+
+__global__ void __launch_bounds__(kPyrThreads) k_pyr_low(const uint32_t* __restrict__ used, uint64_t L,
+                                                         Pyramid P, int top) {
+  __shared__ uint64_t s[kPyrThreads];
+  const int t = threadIdx.x;
+  const uint64_t n1 = (uint64_t)blockIdx.x * kPyrThreads + t;  // level-1 node
+  uint64_t v = 0;
+  if (2 * n1 < L) v += used[2 * n1];
+  if (2 * n1 + 1 < L) v += used[2 * n1 + 1];
+  s[t] = v;
+  if (n1 < P.cnt[1]) P.base[P.off[1] + n1] = v;
+  __syncthreads();
+  for (int h = 2; h <= top; h++) {
+    const int active = kPyrThreads >> (h - 1);
+    uint64_t x = 0;
+    if (t < active) x = s[2 * t] + s[2 * t + 1];
+    __syncthreads();
+    if (t < active) {
+      s[t] = x;
+      const uint64_t node = (uint64_t)blockIdx.x * active + t;
+      if (node < P.cnt[h]) P.base[P.off[h] + node] = x;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_pyr_high(Pyramid P, int from) {
+  for (int h = from + 1; h <= P.H; h++) {
+    const uint64_t* lower = P.base + P.off[h - 1];
+    const uint64_t nlow = P.cnt[h - 1];
+    for (uint64_t i = threadIdx.x; i < P.cnt[h]; i += blockDim.x) {
+      uint64_t v = lower[2 * i];
+      if (2 * i + 1 < nlow) v += lower[2 * i + 1];
+      P.base[P.off[h] + i] = v;
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ uint32_t node_viol(const Bounds& bd, const Pyramid& P, const uint32_t* used,
+                                              int h, uint64_t i) {
+  return violation(bd, h, node_sum(P, used, h, i), node_leaves(bd.L, h, i));
+}
+
+// A node is redistributed when it is within its bounds but a child is not (the
+// walk up from a violating node stops at the first ancestor within bounds).
+__device__ __forceinline__ bool node_redist(const Bounds& bd, const Pyramid& P, const uint32_t* used,
+                                            int h, uint64_t i) {
+  if (h == 0 || node_viol(bd, P, used, h, i)) return false;
+  const uint64_t c0 = 2 * i, c1 = 2 * i + 1;
+  const uint64_t nchild = (h - 1 == 0) ? bd.L : P.cnt[h - 1];
+  if (node_viol(bd, P, used, h - 1, c0)) return true;
+  return c1 < nchild && node_viol(bd, P, used, h - 1, c1) != 0;
+}
+
+// Window selection: every node that must be redistributed and has no ancestor
+// that is itself redistributed (maximal windows).  Root violation -> resize.
+__global__ void k_select(Bounds bd, Pyramid P, const uint32_t* __restrict__ used,
+                         uint64_t* __restrict__ win, Counters* ctr) {
+  const uint64_t total = (bd.H == 0) ? 1 : P.off[bd.H] + P.cnt[bd.H] - P.off[1];
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (uint64_t)gridDim.x * blockDim.x) {
+    if (bd.H == 0) {
+      ctr->root_sum = used[0];
+      ctr->root_viol = violation(bd, 0, used[0], 1);
+      return;
+    }
+    int h = 1;
+    uint64_t g = t + P.off[1];
+    while (!(g >= P.off[h] && g < P.off[h] + P.cnt[h])) h++;
+    const uint64_t i = g - P.off[h];
+    if (h == bd.H) {
+      ctr->root_sum = P.base[P.off[h]];
+      ctr->root_viol = node_viol(bd, P, used, h, 0);
+    }
+    if (!node_redist(bd, P, used, h, i)) continue;
+    bool covered = false;
+    for (int h2 = h + 1; h2 <= bd.H && !covered; h2++)
+      covered = node_redist(bd, P, used, h2, i >> (h2 - h));
+    if (covered) continue;
+    const uint32_t slot = atomicAdd(&ctr->nwin, 1u);
+    win[slot] = ((uint64_t)h << 48) | i;
+  }
+}
+
+// ---- redistribution: pack (copy 1) then spread evenly (copy 2) -------------------
+// Windows are described by flat index ranges: window w owns source leaves
+// src_begin[w] .. +src_n[w] (flat ids src_flat[w] ..) and destination leaves
+// dst_begin[w] .. +dst_n[w] (flat ids dst_flat[w] ..).
+struct WinArgs {
+  uint32_t W;
+  const uint64_t* src_begin;
+  const uint64_t* src_flat;  // W + 1
+  const uint64_t* dst_begin;
+  const uint64_t* dst_n;
+  const uint64_t* dst_flat;  // W + 1
+  const uint32_t* level;     // window height (subtree check bound)
+};
+
+__device__ __forceinline__ uint32_t find_window(const uint64_t* flat, uint32_t W, uint64_t f) {
+  return (uint32_t)(upper_bound_u64(flat, (uint64_t)W + 1, f) - 1);
+}
+
+struct SrcLeaves {
+  const uint8_t* bytes;
+  const uint32_t* used;
+  const uint64_t* ovf;
+  const uint8_t* arena;
+  uint32_t S;
+  __device__ const uint8_t* ptr(uint64_t leaf, uint32_t u) const {
+    return u > S ? arena + ovf[leaf] : bytes + leaf * (uint64_t)S;
+  }
+};
+
+__global__ void __launch_bounds__(kWave) k_win_count(WinArgs wa, SrcLeaves src, uint64_t nflat,
+                                                     uint64_t* __restrict__ cnt) {
+  for (uint64_t f = blockIdx.x; f < nflat; f += gridDim.x) {
+    const uint32_t w = find_window(wa.src_flat, wa.W, f);
+    const uint64_t leaf = wa.src_begin[w] + (f - wa.src_flat[w]);
+    const uint32_t u = src.used[leaf];
+    const uint32_t c = wave_count_keys(src.ptr(leaf, u), u);
+    if (lane_id() == 0) cnt[f] = c;
+  }
+}
+
+__global__ void __launch_bounds__(kWave) k_win_pack(WinArgs wa, SrcLeaves src, uint64_t nflat,
+                                                    const uint64_t* __restrict__ koff,
+                                                    uint64_t* __restrict__ stage,
+                                                    uint32_t* __restrict__ win_id) {
+  for (uint64_t f = blockIdx.x; f < nflat; f += gridDim.x) {
+    const uint32_t w = find_window(wa.src_flat, wa.W, f);
+    const uint64_t leaf = wa.src_begin[w] + (f - wa.src_flat[w]);
+    const uint32_t u = src.used[leaf];
+    uint64_t* out = stage + koff[f];
+    uint32_t* wid = win_id + koff[f];
+    wave_decode_leaf(src.ptr(leaf, u), u, [&](uint32_t i, uint64_t x) {
+      out[i] = x;
+      wid[i] = w;
+    });
+  }
+}
+
+// welem[w] = first staged key of window w (W + 1 entries).
+__global__ void k_win_elems(WinArgs wa, const uint64_t* __restrict__ koff, uint64_t* __restrict__ welem,
+                            uint32_t* __restrict__ fail) {
+  for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w <= wa.W; w += gridDim.x * blockDim.x) {
+    welem[w] = koff[wa.src_flat[w]];
+    if (w < wa.W) fail[w] = 0;
+  }
+}
+
+// Byte cost of key e within its window: 8 for the window's first key, else the
+// length of its delta code.
+struct CostFn {
+  const uint64_t* x;
+  const uint32_t* win_id;
+  const uint64_t* welem;
+  __device__ uint64_t operator()(uint64_t e) const {
+    return e == welem[win_id[e]] ? 8ull : (uint64_t)vlen(x[e] - x[e - 1]);
+  }
+};
+
+// Even split by bytes: key e goes to destination leaf j = floor(P_e * n / total),
+// where P_e is the window's byte prefix before e.  A key that starts a leaf becomes
+// its head (8 bytes).  Gaps (empty leaves) fail the window.
+__global__ void k_assign(WinArgs wa, uint64_t K, const uint64_t* __restrict__ x,
+                         const uint32_t* __restrict__ win_id, const uint64_t* __restrict__ welem,
+                         const uint64_t* __restrict__ P, uint8_t* __restrict__ ncost,
+                         uint64_t* __restrict__ lstart, uint32_t* __restrict__ fail) {
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < K;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t w = win_id[e];
+    const uint64_t first = welem[w], end = welem[w + 1];
+    const uint64_t n = wa.dst_n[w];
+    const uint64_t tot = P[end] - P[first];
+    const uint64_t j = ((P[e] - P[first]) * n) / tot;
+    bool head = (e == first);
+    if (!head) {
+      const uint64_t jp = ((P[e - 1] - P[first]) * n) / tot;
+      head = j != jp;
+      if (j > jp + 1) atomicOr(&fail[w], 2u);
+    }
+    if (e + 1 == end && j != n - 1) atomicOr(&fail[w], 2u);
+    ncost[e] = head ? 8 : (uint8_t)vlen(x[e] - x[e - 1]);
+    if (head) lstart[wa.dst_flat[w] + j] = e;
+  }
+}
+
+__device__ __forceinline__ bool leaf_range(const WinArgs& wa, const uint64_t* welem, const uint64_t* lstart,
+                                           uint64_t fd, uint32_t& w, uint64_t& d, uint64_t& s,
+                                           uint64_t& e) {
+  w = find_window(wa.dst_flat, wa.W, fd);
+  const uint64_t j = fd - wa.dst_flat[w];
+  d = wa.dst_begin[w] + j;
+  s = lstart[fd];
+  e = (j + 1 == wa.dst_n[w]) ? welem[w + 1] : lstart[fd + 1];
+  return s != ~0ull && e != ~0ull && s < e && s >= welem[w] && e <= welem[w + 1];
+}
+
+// Planned byte count of every destination leaf, checked against the leaf bounds.
+__global__ void __launch_bounds__(kWave) k_leaf_bytes(WinArgs wa, Bounds dstb, uint64_t nflat,
+                                                      const uint64_t* __restrict__ welem,
+                                                      const uint64_t* __restrict__ lstart,
+                                                      const uint8_t* __restrict__ ncost,
+                                                      uint32_t* __restrict__ planU,
+                                                      uint32_t* __restrict__ plan_used,
+                                                      int32_t* __restrict__ win_of_leaf,
+                                                      uint32_t* __restrict__ fail) {
+  for (uint64_t fd = blockIdx.x; fd < nflat; fd += gridDim.x) {
+    uint32_t w;
+    uint64_t d, s, e;
+    const bool ok = leaf_range(wa, welem, lstart, fd, w, d, s, e);
+    uint64_t U = 0;
+    if (ok)
+      for (uint64_t i = s + lane_id(); i < e; i += kWave) U += ncost[i];
+    U = wave_sum(U);
+    if (lane_id() == 0) {
+      uint32_t v = ok ? violation(dstb, 0, U, 1) : 2u;
+      if (U > dstb.S) v |= 1u;
+      if (v) atomicOr(&fail[w], v);
+      planU[fd] = (uint32_t)(U > 0xffffffffull ? 0xffffffffull : U);
+      plan_used[d] = planU[fd];
+      if (win_of_leaf) win_of_leaf[d] = (int32_t)w;
+    }
+  }
+}
+
+// Subtree check of the planned layout: a node strictly inside a window (lower than
+// the window's own height) must satisfy its bounds, else the window escalates.
+// check_all: every node of the destination tree counts (fresh layouts).
+__global__ void k_check_plan(Bounds bd, Pyramid P, const uint32_t* __restrict__ plan_used,
+                             const int32_t* __restrict__ win_of_leaf, const uint32_t* __restrict__ level,
+                             int check_all, uint32_t* __restrict__ fail) {
+  const uint64_t total = (bd.H == 0) ? 1 : P.off[bd.H] + P.cnt[bd.H] - P.off[1];
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (uint64_t)gridDim.x * blockDim.x) {
+    int h = 0;
+    uint64_t i = 0;
+    if (bd.H > 0) {
+      h = 1;
+      const uint64_t g = t + P.off[1];
+      while (!(g >= P.off[h] && g < P.off[h] + P.cnt[h])) h++;
+      i = g - P.off[h];
+    }
+    const uint32_t v = violation(bd, h, node_sum(P, plan_used, h, i), node_leaves(bd.L, h, i));
+    if (!v) continue;
+    if (check_all) {
+      atomicOr(&fail[0], v);
+    } else {
+      const int32_t w = win_of_leaf[i << h];
+      if (w >= 0 && (uint32_t)h < level[w]) atomicOr(&fail[w], v);
+    }
+  }
+}
+
+__global__ void k_clear_win_map(WinArgs wa, uint64_t nflat, int32_t* __restrict__ win_of_leaf) {
+  for (uint64_t fd = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; fd < nflat;
+       fd += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t w = find_window(wa.dst_flat, wa.W, fd);
+    win_of_leaf[wa.dst_begin[w] + (fd - wa.dst_flat[w])] = -1;
+  }
+}
+
+// Spread: encode every destination leaf from the staged keys (copy 2).
+__global__ void __launch_bounds__(kWave) k_leaf_encode(WinArgs wa, uint64_t nflat, uint32_t S,
+                                                       const uint64_t* __restrict__ welem,
+                                                       const uint64_t* __restrict__ lstart,
+                                                       const uint64_t* __restrict__ x,
+                                                       const uint32_t* __restrict__ planU,
+                                                       uint8_t* __restrict__ dst_bytes,
+                                                       uint32_t* __restrict__ dst_used,
+                                                       uint64_t* __restrict__ dst_head) {
+  extern __shared__ __align__(16) uint8_t buf[];
+  for (uint64_t fd = blockIdx.x; fd < nflat; fd += gridDim.x) {
+    uint32_t w;
+    uint64_t d, s, e;
+    leaf_range(wa, welem, lstart, fd, w, d, s, e);
+    wave_zero(buf, S);
+    __syncthreads();
+    const uint64_t* xs = x + s;
+    wave_encode_bytes([&](uint32_t i) { return xs[i]; }, (uint32_t)(e - s), buf);
+    __syncthreads();
+    wave_copy16(dst_bytes + d * (uint64_t)S, buf, S);
+    if (lane_id() == 0) {
+      dst_used[d] = planU[fd];
+      dst_head[d] = xs[0];
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace cpma_dev

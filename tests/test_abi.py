@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every entry point include/cpma.h declares
+(no compute call: this container has no GPU)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cpma.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cpma_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("cpma_build", "cpma_insert_batch", "cpma_delete_batch", "cpma_contains",
+                 "cpma_range_map", "cpma_size", "cpma_bytes", "cpma_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2305_05055_amd as p
+    if not os.path.exists(p.LIB_PATH):
+        pytest.skip("libcpma.so not built")
+    L = p.lib()
+    missing = [n for n in declared() if not hasattr(L, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", p.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r" T (cpma_[a-z_]+)$", out, flags=re.M))
+    assert set(declared()) <= exported
+
+
+def test_host_only_calls_without_gpu():
+    """Calls that never touch the device behave as documented."""
+    import ctypes
+    import paper_2305_05055_amd as p
+    if not os.path.exists(p.LIB_PATH):
+        pytest.skip("libcpma.so not built")
+    L = p.lib()
+    c = p.default_config()
+    assert c.leaf_bytes == 1024 and abs(c.grow - 1.2) < 1e-12
+    assert abs(c.build_density - 0.7 / 1.2) < 1e-12
+    assert L.cpma_size(None) == 0 and L.cpma_bytes(None) == 0
+    assert L.cpma_config_default(None) == 1
+    assert L.cpma_status_str(4) == b"reserved key (UINT64_MAX)"
+    h = ctypes.c_void_p()
+    assert L.cpma_build(None, 5, 0, None, None, ctypes.byref(h)) == 1   # keys NULL with n > 0
+    bad = p.Config()
+    bad.leaf_bytes = 100                                                 # not a power of two
+    assert L.cpma_build(None, 0, 0, ctypes.byref(bad), None, ctypes.byref(h)) == 1
+    assert L.cpma_insert_batch(None, None, 1, 0, 0, None, None) == 1
+    L.cpma_destroy(None)
+
+
+def test_package_fails_loudly_without_library(monkeypatch):
+    import paper_2305_05055_amd as p
+    monkeypatch.setattr(p, "LIB_PATH", "/nonexistent/libcpma.so")
+    monkeypatch.setattr(p, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        p.lib()
+
+
+def test_package_does_not_import_oracle():
+    src = open(os.path.join(ROOT, "paper_2305_05055_amd", "__init__.py")).read()
+    assert "oracle" not in src.replace("no CPU fallback", "")
+    for f in os.listdir(os.path.join(ROOT, "paper_2305_05055_amd", "csrc")):
+        assert "oracle" not in open(os.path.join(ROOT, "paper_2305_05055_amd", "csrc", f)).read()

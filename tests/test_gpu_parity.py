@@ -1,0 +1,230 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element by
+element, with the structure checker run on the exported layout after every batch.
+
+Integer results are bit-exact: set contents, n_added / n_removed, range sums
+(mod 2^64) and counts, membership.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+M64 = (1 << 64) - 1
+
+
+@pytest.fixture(scope="module")
+def cp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2305_05055_amd as p
+    p.lib()
+    return p
+
+
+def check(c, expect, orc, params=None):
+    b, u, h = c.export()
+    L, S = c.geometry()
+    code, msg = orc.check_image(b, u, h, S, expect, params or orc.DEFAULT_PARAMS)
+    assert code == 0, msg
+    assert c.size() == len(expect)
+    assert c.bytes() == L * (S + 12)
+
+
+def full_range(c, S_oracle):
+    s, n = c.range_map(np.array([0], np.uint64), np.array([M64], np.uint64))
+    return int(s[0]), int(n[0])
+
+
+@pytest.mark.parametrize("S", [64, 256, 1024])
+@pytest.mark.parametrize("n", [0, 1, 2, 17, 1000, 20000])
+def test_build(cp, orc, S, n):
+    keys = synth.uniform_keys(n, 1000 + n, bits=40)
+    if n > 4:
+        keys[: n // 4] = keys[n // 4: 2 * (n // 4)]  # repeated keys in the input
+    expect = orc.build_set(keys)
+    c = cp.CPMA(keys, leaf_bytes=S)
+    check(c, expect, orc)
+    s, cnt = full_range(c, expect)
+    assert cnt == len(expect) and s == int(expect.sum(dtype=np.uint64))
+
+
+@pytest.mark.parametrize("S", [64, 128, 1024])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_insert_delete_sequence(cp, orc, S, seed):
+    base = synth.uniform_keys(3000, seed, bits=24)
+    expect = orc.build_set(base)
+    c = cp.CPMA(base, leaf_bytes=S)
+    check(c, expect, orc)
+    for step in range(10):
+        k = [1, 7, 100, 900, 2500, 50, 4000, 3, 1200, 640][step]
+        if step % 3 == 2:
+            # delete: half present keys, half random (mostly absent)
+            present = expect[synth.sample_indices(len(expect), min(k // 2, len(expect)), seed * 100 + step)]
+            batch = np.concatenate([present, synth.uniform_keys(k - len(present), seed * 77 + step, bits=24)])
+            new, removed = orc.delete(expect, batch)
+            got = c.delete_batch(batch)
+            assert got == removed
+        else:
+            batch = synth.uniform_keys(k, seed * 1000 + step, bits=24)
+            if len(expect) and k > 4:
+                batch[: k // 4] = expect[synth.sample_indices(len(expect), k // 4, step)]
+            new, added = orc.insert(expect, batch)
+            got = c.insert_batch(batch)
+            assert got == added
+        expect = new
+        check(c, expect, orc)
+    lo = synth.uniform_keys(500, seed + 5, bits=24)
+    hi = lo + synth.uniform_keys(500, seed + 6, bits=16)
+    s, n = c.range_map(lo, hi)
+    es, en = orc.range_map(expect, lo, hi)
+    assert np.array_equal(s, es) and np.array_equal(n, en)
+
+
+@pytest.mark.parametrize("S", [64, 1024])
+def test_range_map_edges(cp, orc, S):
+    keys = np.concatenate([np.array([0, 1, 2, M64 - 1, M64 - 2, 1 << 63], np.uint64),
+                           synth.uniform_keys(5000, 9, bits=64)])
+    keys = keys[keys != np.uint64(M64)]
+    expect = orc.build_set(keys)
+    c = cp.CPMA(keys, leaf_bytes=S)
+    check(c, expect, orc)
+    rnd_lo = synth.uniform_keys(2000, 10, bits=64)
+    rnd_hi = rnd_lo + synth.uniform_keys(2000, 11, bits=58)
+    lo = np.concatenate([np.array([0, 0, 5, 5, M64 - 1, 0, 1 << 63, 3], np.uint64), expect[:50], rnd_lo])
+    hi = np.concatenate([np.array([M64, 1, 5, 4, M64, M64 - 1, M64, 2], np.uint64),
+                         expect[:50] + np.uint64(1), rnd_hi])
+    s, n = c.range_map(lo, hi)
+    es, en = orc.range_map(expect, lo, hi)
+    assert np.array_equal(n, en)
+    assert np.array_equal(s, es)
+
+
+@pytest.mark.parametrize("S", [64, 1024])
+def test_contains(cp, orc, S):
+    keys = synth.uniform_keys(30000, 21, bits=32)
+    expect = orc.build_set(keys)
+    c = cp.CPMA(keys, leaf_bytes=S)
+    q = np.concatenate([expect[::7], synth.uniform_keys(3000, 22, bits=32),
+                        np.array([0, M64 - 1], np.uint64)])
+    assert np.array_equal(c.contains(q), orc.contains(expect, q))
+
+
+def test_plain_cpma_config(cp, orc):
+    """1e6 uniform 40-bit keys, 10 inserts of 1e4, a delete of 1e4 present keys,
+    1e4 range sums over [lo, lo + 2^24): everything bit-exact."""
+    seed = synth.SEED_BASE + 1
+    keys = synth.unique_uniform_keys(10 ** 6, seed)
+    expect = orc.build_set(keys)
+    c = cp.CPMA(keys)
+    check(c, expect, orc)
+    for b in range(10):
+        batch = synth.uniform_keys(10 ** 4, seed + 100 + b)
+        expect, added = orc.insert(expect, batch)
+        assert c.insert_batch(batch) == added
+    idx = synth.sample_indices(len(expect), 10 ** 4, seed + 200)
+    dbatch = expect[idx]
+    expect, removed = orc.delete(expect, dbatch)
+    assert removed == 10 ** 4
+    assert c.delete_batch(dbatch) == removed
+    check(c, expect, orc)
+    lo, hi = synth.range_queries_width(10 ** 4, seed + 300, 1 << 24)
+    s, n = c.range_map(lo, hi)
+    es, en = orc.range_map(expect, lo, hi)
+    assert np.array_equal(n, en) and np.array_equal(s, es)
+
+
+def test_heavy_slice_sequential_batch(cp, orc):
+    """A batch whose keys all land in one leaf (more than the in-LDS slice)."""
+    base = synth.uniform_keys(20000, 31, bits=40)
+    expect = orc.build_set(base)
+    c = cp.CPMA(base)
+    x0 = int(expect[5000]) + 1
+    batch = np.arange(x0, x0 + 6000, dtype=np.uint64)
+    expect, added = orc.insert(expect, batch)
+    assert c.insert_batch(batch) == added
+    check(c, expect, orc)
+    batch2 = np.arange(0, 3000, dtype=np.uint64) * np.uint64(3)  # below every key
+    expect, added = orc.insert(expect, batch2)
+    assert c.insert_batch(batch2, sorted=True) == added
+    check(c, expect, orc)
+
+
+def test_delete_all_then_reinsert(cp, orc):
+    keys = synth.uniform_keys(5000, 41, bits=40)
+    expect = orc.build_set(keys)
+    c = cp.CPMA(keys, leaf_bytes=128)
+    assert c.delete_batch(expect[::-1].copy()) == len(expect)
+    check(c, np.empty(0, np.uint64), orc)
+    assert c.range_map(np.array([0], np.uint64), np.array([M64], np.uint64))[1][0] == 0
+    assert c.insert_batch(keys) == len(expect)
+    check(c, expect, orc)
+
+
+def test_repeats_present_keys_and_empty_batches(cp, orc):
+    keys = synth.uniform_keys(4000, 51, bits=20)
+    expect = orc.build_set(keys)
+    c = cp.CPMA(keys, leaf_bytes=256)
+    assert c.insert_batch(np.empty(0, np.uint64)) == 0
+    assert c.delete_batch(np.empty(0, np.uint64)) == 0
+    assert c.insert_batch(np.repeat(expect[:100], 3)) == 0       # all present, repeated
+    absent = np.setdiff1d(synth.uniform_keys(500, 52, bits=20), expect)
+    assert c.delete_batch(absent) == 0
+    check(c, expect, orc)
+
+
+def test_reserved_key_rejected_and_set_unchanged(cp, orc):
+    keys = synth.uniform_keys(1000, 61, bits=40)
+    expect = orc.build_set(keys)
+    c = cp.CPMA(keys)
+    bad = np.array([5, M64, 7], dtype=np.uint64)
+    with pytest.raises(cp.CpmaError) as e:
+        c.insert_batch(bad)
+    assert e.value.code == 4
+    with pytest.raises(cp.CpmaError):
+        c.delete_batch(bad)
+    check(c, expect, orc)
+    with pytest.raises(cp.CpmaError):
+        cp.CPMA(bad)
+
+
+def test_growth_and_shrink_tiny_leaves(cp, orc):
+    """64-byte leaves: many resizes up, then deletes shrink the array again."""
+    c = cp.CPMA(np.empty(0, np.uint64), leaf_bytes=64)
+    expect = np.empty(0, np.uint64)
+    for b in range(12):
+        batch = synth.uniform_keys(300 * (b + 1), 70 + b, bits=40)
+        expect, added = orc.insert(expect, batch)
+        assert c.insert_batch(batch) == added
+        check(c, expect, orc)
+    L_big = c.geometry()[0]
+    for b in range(6):
+        idx = synth.sample_indices(len(expect), len(expect) // 2, 90 + b)
+        dbatch = expect[idx]
+        expect, removed = orc.delete(expect, dbatch)
+        assert c.delete_batch(dbatch) == removed
+        check(c, expect, orc)
+    assert c.geometry()[0] < L_big
+
+
+def test_device_tensors(cp, orc):
+    import torch
+    keys = synth.uniform_keys(50000, 81, bits=40)
+    expect = orc.build_set(keys)
+    dev = torch.from_numpy(keys.view(np.int64)).cuda()
+    c = cp.CPMA(dev)
+    check(c, expect, orc)
+    batch = synth.uniform_keys(20000, 82, bits=40)
+    expect, added = orc.insert(expect, batch)
+    assert c.insert_batch(torch.from_numpy(batch.view(np.int64)).cuda()) == added
+    lo, hi = synth.range_queries_width(3000, 83, 1 << 30)
+    s, n = c.range_map(torch.from_numpy(lo.view(np.int64)).cuda(), torch.from_numpy(hi.view(np.int64)).cuda())
+    torch.cuda.synchronize()
+    es, en = orc.range_map(expect, lo, hi)
+    assert np.array_equal(s.cpu().numpy().view(np.uint64), es)
+    assert np.array_equal(n.cpu().numpy().view(np.uint64), en)
+    q = torch.from_numpy(np.concatenate([expect[:1000], batch[:1000] + np.uint64(1)]).view(np.int64)).cuda()
+    got = c.contains(q).cpu().numpy()
+    assert np.array_equal(got, orc.contains(expect, q.cpu().numpy().view(np.uint64)))
+    check(c, expect, orc)
