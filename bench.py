@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""CPMA benchmark on one MI355X.
+
+Headline (printed as one JSON line): batch-insert throughput of uniform 40-bit
+keys into a CPMA that starts with 1e8 keys, batches of 1e7 -- the paper's
+microbenchmark (Section "Evaluation on microbenchmarks": 100 M start, 100 M
+inserted in batches).  A step is one insert batch (sort, locate, merge, density
+count, redistribute, grow) over keys already resident in HBM.
+
+Beside it: per-batch-size insert / delete throughput and p50 / p99 latency
+(1e1 .. 1e6, each insert followed by a delete of present keys), a batched
+range_map of Zipf(1.2) lengths against one launch per query, bytes per key,
+per-phase device time from HIP events recorded inside the library, the roofline
+of the dominant kernel, and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+METRIC = "insert keys/s at batch 1e3–1e7; range_map keys/s (%HBM peak); p99 latency"
+PAPER_CPMA_INSERT_1E7 = 2.4e8   # paper, CPMA batch insert, uniform, batch 1e7 (64 cores)
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=9)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=float, default=1e8)
+    ap.add_argument("--batch", type=float, default=1e7)
+    ap.add_argument("--sweep", default="1e1,1e2,1e3,1e4,1e5,1e6")
+    ap.add_argument("--queries", type=float, default=1e6)
+    ap.add_argument("--leaf-bytes", type=int, default=0)
+    ap.add_argument("--cpu-batches", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-steps", action="store_true", help="skip sweep and range_map")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the CPMA hot path here runs on a single "
+              "MI355X (multi-GPU sharding by key range is a design note, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2305_05055_amd as cp
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    torch.cuda.set_device(0)
+    n0 = int(args.n)
+    k = int(args.batch)
+    seed = synth.SEED_BASE + 2
+
+    # ---- base set: exactly n0 distinct uniform 40-bit keys -----------------------
+    t = time.time()
+    base = synth.uniform_keys(n0, seed)
+    c = cp.CPMA(to_dev(base), leaf_bytes=args.leaf_bytes)
+    extra = []
+    off = n0
+    while c.size() < n0:
+        need = n0 - c.size()
+        more = synth.uniform_keys(need, seed, offset=off)
+        off += need
+        c.insert_batch(to_dev(more))
+        extra.append(more)
+    base_all = np.concatenate([base] + extra) if extra else base
+    torch.cuda.synchronize()
+    L, S = c.geometry()
+    log(f"built n={c.size()} L={L} S={S} bytes/key={c.bytes() / c.size():.3f} in {time.time() - t:.1f}s")
+    result_extra = {"bytes_per_key_at_n0": c.bytes() / c.size(), "leaves_at_n0": L, "leaf_bytes": S}
+
+    # ---- batched range_map (Zipf(1.2) lengths 1..1e6) vs one launch per query -----
+    if not args.only_steps and args.queries > 0:
+        q = int(args.queries)
+        lens = synth.zipf_lengths(q, seed + 10, alpha=1.2, lmax=10 ** 6)
+        width = np.uint64((1 << 40) // n0)
+        lo = synth.uniform_keys(q, seed + 11)
+        hi = lo + lens.astype(np.uint64) * width
+        dlo, dhi = to_dev(lo), to_dev(hi)
+        c.range_map(dlo, dhi)
+        torch.cuda.synchronize()
+        c.stats_enable(True)
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            s_, n_ = c.range_map(dlo, dhi)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        st = c.stats()
+        c.stats_enable(False)
+        total_keys = int(n_.sum().item())
+        sc_launch, sc_ms, sc_bytes = st["range_scan"]
+        rm = {
+            "queries": q, "keys_per_pass": total_keys, "keys_per_s": total_keys / dt,
+            "ms_per_pass": dt * 1e3,
+            "scan_kernel_ms": sc_ms / max(1, sc_launch),
+            "scan_alg_bytes": sc_bytes / max(1, sc_launch),
+            "scan_alg_GBps": (sc_bytes / max(1, sc_launch)) / (sc_ms / max(1, sc_launch) * 1e-3) / 1e9,
+        }
+        rm["frac_hbm_alg"] = rm["scan_alg_GBps"] / HBM_PEAK_GBS
+        # one launch per query on a prefix of the same queries
+        m = min(2000, q)
+        t0 = time.perf_counter()
+        for i in range(m):
+            c.range_map(dlo[i:i + 1], dhi[i:i + 1])
+        torch.cuda.synchronize()
+        per_q = (time.perf_counter() - t0) / m
+        t0 = time.perf_counter()
+        c.range_map(dlo[:m], dhi[:m])
+        torch.cuda.synchronize()
+        batched_m = time.perf_counter() - t0
+        rm["one_launch_per_query_s_per_query"] = per_q
+        rm["batched_speedup_on_prefix"] = (per_q * m) / batched_m
+        rm["batched_speedup_extrapolated"] = (per_q * q) / dt
+        result_extra["range_map"] = rm
+        log(f"range_map: {total_keys / dt:.3e} keys/s, scan {rm['scan_alg_GBps']:.0f} GB/s alg")
+        del dlo, dhi
+
+    # ---- batch-size sweep: insert k fresh keys, then delete k present keys --------
+    per_batch = {}
+    if not args.only_steps:
+        sizes = [int(float(x)) for x in args.sweep.split(",") if x]
+        reps = {10: 30, 100: 30, 1000: 20, 10000: 10, 100000: 5, 1000000: 3}
+        total_del = sum(s * reps.get(s, 3) for s in sizes)
+        del_idx = synth.sample_indices(len(base_all), total_del, seed + 20)
+        dpos = 0
+        gen_off = 10 ** 11
+        for s in sizes:
+            r = reps.get(s, 3)
+            ins_b = [to_dev(synth.uniform_keys(s, seed + 30, offset=gen_off + i * s)) for i in range(r)]
+            gen_off += r * s
+            del_b = [to_dev(base_all[del_idx[dpos + i * s: dpos + (i + 1) * s]]) for i in range(r)]
+            dpos += r * s
+            torch.cuda.synchronize()
+            ti, td = [], []
+            for i in range(r):
+                t0 = time.perf_counter()
+                c.insert_batch(ins_b[i])
+                ti.append(time.perf_counter() - t0)
+                t0 = time.perf_counter()
+                c.delete_batch(del_b[i])
+                td.append(time.perf_counter() - t0)
+            ti, td = np.array(ti), np.array(td)
+            per_batch[f"{s:.0e}"] = {
+                "insert_keys_s": s / ti.mean(), "delete_keys_s": s / td.mean(),
+                "insert_p50_ms": float(np.percentile(ti, 50) * 1e3),
+                "insert_p99_ms": float(np.percentile(ti, 99) * 1e3),
+                "delete_p50_ms": float(np.percentile(td, 50) * 1e3),
+                "delete_p99_ms": float(np.percentile(td, 99) * 1e3), "reps": r}
+            log(f"k={s:.0e}: insert {s / ti.mean():.3e}/s delete {s / td.mean():.3e}/s "
+                f"p99 {np.percentile(ti, 99) * 1e3:.2f} ms")
+        result_extra["per_batch"] = per_batch
+
+    # ---- headline: W warm-up + K timed insert batches of k keys ------------------
+    nb = args.warmup + args.steps
+    batches = [to_dev(synth.uniform_keys(k, seed + 40, offset=i * k)) for i in range(nb)]
+    torch.cuda.synchronize()
+    for i in range(args.warmup):
+        c.insert_batch(batches[i])
+    torch.cuda.synchronize()
+    c.stats_enable(True)
+    lat = []
+    t0 = time.perf_counter()
+    for i in range(args.warmup, nb):
+        ts = time.perf_counter()
+        c.insert_batch(batches[i])
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = c.stats()
+    c.stats_enable(False)
+    dt = t1 - t0
+    value = args.steps * k / dt
+    log(f"headline: {value:.3e} inserts/s, {dt / args.steps * 1e3:.2f} ms/step, n={c.size()}")
+    phases = {name: {"launches": v[0], "ms": v[1], "alg_bytes": v[2]} for name, v in st.items()}
+
+    # roofline of the dominant single kernel of the step (the merge, or the sort's passes)
+    mg_l, mg_ms, mg_b = st["merge"]
+    dominant = max(("merge", "sort", "locate", "count", "redist"), key=lambda p: st[p][1])
+    roof = None
+    if mg_l > 0 and mg_ms > 0:
+        ach = (mg_b / mg_l) / ((mg_ms / mg_l) * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": "k_merge", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "alg_bytes_per_launch": mg_b / mg_l, "avg_launch_ms": mg_ms / mg_l,
+                "dominant_phase": dominant}
+
+    # delete throughput at the headline batch size (present keys from the base set)
+    dsel = synth.sample_indices(len(base_all), 2 * k, seed + 50)
+    dels = [to_dev(base_all[dsel[i * k:(i + 1) * k]]) for i in range(2)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d in dels:
+        c.delete_batch(d)
+    torch.cuda.synchronize()
+    result_extra["delete_keys_s_at_batch"] = 2 * k / (time.perf_counter() - t0)
+    result_extra["bytes_per_key_final"] = c.bytes() / c.size()
+    del batches, dels
+
+    # ---- CPU baseline: the oracle inserting the same kind of batches ------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("cpu baseline: oracle set of n0 keys ...")
+        S_host = oracle.build_set(base_all)
+        nbat = args.cpu_batches
+        t0 = time.perf_counter()
+        for i in range(nbat):
+            S_host, _ = oracle.insert(S_host, synth.uniform_keys(k, seed + 40, offset=i * k))
+        tc = time.perf_counter() - t0
+        cpu = {"value": nbat * k / tc, "unit": "keys/s", "cores": 1, "kind": "oracle",
+               "sample": f"{nbat} insert batches of {k:.0e} uniform 40-bit keys into the {n0:.0e}-key "
+                         f"set (sorted-vector set_union, single thread), {tc:.1f} s"}
+        log(f"cpu baseline {cpu['value']:.3e} keys/s")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "keys/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": value / PAPER_CPMA_INSERT_1E7, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "plain CPMA at scale: 1e8 uniform 40-bit keys, insert batches of 1e7",
+                   "n0": n0, "batch": k, "leaf_bytes": S, "key_bits": 40},
+        "roofline": roof, "cpu_baseline": cpu,
+        "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
+        "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
+        "phases": phases,
+    }
+    out.update(result_extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

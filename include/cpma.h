@@ -61,7 +61,7 @@ typedef enum { CPMA_MEM_HOST = 0, CPMA_MEM_DEVICE = 1 } cpma_mem;
 
 /*
  * Structure parameters.  A zero field takes the default.
- *   leaf_bytes     bytes per leaf S: a power of two in [64, 4096]; default 1024.
+ *   leaf_bytes     bytes per leaf S: a power of two in [64, 2048]; default 1024.
  *                  The paper sizes leaves Theta(log N) cells (Section "Packed
  *                  Memory Array"); here S is fixed per set.
  *   grow           growing factor when the root exceeds its upper bound;
@@ -158,6 +158,46 @@ cpma_status cpma_geometry(const cpma* set, uint64_t* num_leaves, uint32_t* leaf_
  */
 cpma_status cpma_export(const cpma* set, uint8_t* bytes, uint32_t* used,
                         uint64_t* head, void* stream);
+
+/*
+ * Phase statistics (instrumentation, not part of the paper's API).  While
+ * enabled, every call records HIP events around its phases on the call's stream
+ * and accumulates, per phase, the number of timed launches, their total device
+ * time, and the algorithmic HBM bytes the phase had to move:
+ *   CPMA_PHASE_SORT        radix passes + repeat removal of a batch
+ *   CPMA_PHASE_LOCATE      leaf location + touched-leaf segments
+ *   CPMA_PHASE_MERGE       the per-leaf merge kernel; bytes = leaf bytes read and
+ *                          rewritten + 8 per batch key + 20 per touched leaf
+ *   CPMA_PHASE_HEAVY       the merge of batch slices too large for one leaf's LDS
+ *   CPMA_PHASE_COUNT       density counting up the implicit tree
+ *   CPMA_PHASE_REDIST      window redistribution and resizing
+ *   CPMA_PHASE_RANGE_SCAN  the range_map scan kernel; bytes = used bytes of every
+ *                          visited leaf + 32 per query
+ *   CPMA_PHASE_QUERY       a whole range_map or contains call
+ * cpma_stats_enable(set, 1) zeroes the statistics and starts timing; 0 stops.
+ * cpma_stats_get copies min(n, CPMA_PHASE_NUM) entries and synchronises the
+ * device.
+ */
+typedef enum {
+  CPMA_PHASE_SORT = 0,
+  CPMA_PHASE_LOCATE = 1,
+  CPMA_PHASE_MERGE = 2,
+  CPMA_PHASE_HEAVY = 3,
+  CPMA_PHASE_COUNT = 4,
+  CPMA_PHASE_REDIST = 5,
+  CPMA_PHASE_RANGE_SCAN = 6,
+  CPMA_PHASE_QUERY = 7,
+  CPMA_PHASE_NUM = 8
+} cpma_phase;
+
+typedef struct {
+  uint64_t launches;
+  double ms;
+  uint64_t alg_bytes;
+} cpma_phase_stat;
+
+cpma_status cpma_stats_enable(cpma* set, int on);
+cpma_status cpma_stats_get(const cpma* set, cpma_phase_stat* out, int n);
 
 /* Frees the handle and all its device memory.  NULL is a no-op. */
 void cpma_destroy(cpma* set);

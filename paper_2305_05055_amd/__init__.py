@@ -34,6 +34,12 @@ class Config(ctypes.Structure):
                 ("build_density", ctypes.c_double)]
 
 
+class PhaseStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("ms", ctypes.c_double), ("alg_bytes", ctypes.c_uint64)]
+
+
+PHASES = ("sort", "locate", "merge", "heavy", "count", "redist", "range_scan", "query")
+
 _lib = None
 
 
@@ -63,6 +69,8 @@ def lib():
         L.cpma_export.argtypes = [vp, vp, vp, vp, vp]
         L.cpma_destroy.argtypes = [vp]
         L.cpma_destroy.restype = None
+        L.cpma_stats_enable.argtypes = [vp, ctypes.c_int]
+        L.cpma_stats_get.argtypes = [vp, ctypes.POINTER(PhaseStat), ctypes.c_int]
         L.cpma_status_str.argtypes = [ctypes.c_int]
         L.cpma_status_str.restype = ctypes.c_char_p
         _lib = L
@@ -199,6 +207,17 @@ class CPMA:
         S = ctypes.c_uint32(0)
         _check(lib().cpma_geometry(self._h, ctypes.byref(L), ctypes.byref(S)), "cpma_geometry")
         return int(L.value), int(S.value)
+
+    def stats_enable(self, on=True):
+        """Starts (zeroing) or stops per-phase HIP-event timing inside the library."""
+        _check(lib().cpma_stats_enable(self._h, 1 if on else 0), "cpma_stats_enable")
+
+    def stats(self):
+        """{phase: (launches, ms, algorithmic bytes)} accumulated since stats_enable."""
+        arr = (PhaseStat * len(PHASES))()
+        _check(lib().cpma_stats_get(self._h, arr, len(PHASES)), "cpma_stats_get")
+        return {name: (int(arr[i].launches), float(arr[i].ms), int(arr[i].alg_bytes))
+                for i, name in enumerate(PHASES)}
 
     def export(self, stream=None):
         """Host copies (bytes[L*S] u8, used[L] u32, head[L] u64) of the layout."""

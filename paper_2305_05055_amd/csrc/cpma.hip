@@ -17,6 +17,7 @@
 #include "query.hpp"
 #include "sort.hpp"
 #include "update.hpp"
+#include "merge_lane.hpp"
 
 using namespace cpma_dev;
 
@@ -102,6 +103,16 @@ struct cpma {
   size_t hpin_cap = 0;
   uint64_t wol_L = 0;    // leaves covered by win_of_leaf's -1 initialisation
   bool broken = false;
+  // phase statistics (cpma_stats_*)
+  bool stats_on = false;
+  cpma_phase_stat stats[CPMA_PHASE_NUM];
+  struct Pending {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> evpool;
+  unsigned long long* dqalg = nullptr;  // range-scan byte counter
 
   Bounds bounds(uint64_t Lx) const {
     Bounds b;
@@ -163,9 +174,56 @@ void zero_counters(cpma* s, hipStream_t st) {
   HIPCHK(hipGetLastError());
 }
 
+// ---- phase timing with HIP events (only while statistics are enabled) ----------
+struct PhaseMark {
+  int phase;
+  hipEvent_t a;
+};
+
+hipEvent_t get_event(cpma* s) {
+  if (!s->evpool.empty()) {
+    hipEvent_t e = s->evpool.back();
+    s->evpool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+
+PhaseMark phase_begin(cpma* s, int phase, hipStream_t st) {
+  if (!s->stats_on) return PhaseMark{-1, nullptr};
+  hipEvent_t e = get_event(s);
+  HIPCHK(hipEventRecord(e, st));
+  return PhaseMark{phase, e};
+}
+
+void phase_end(cpma* s, const PhaseMark& m, hipStream_t st, uint64_t alg_bytes = 0) {
+  if (m.phase < 0) return;
+  hipEvent_t e = get_event(s);
+  HIPCHK(hipEventRecord(e, st));
+  s->pending.push_back({m.phase, m.a, e});
+  s->stats[m.phase].alg_bytes += alg_bytes;
+}
+
+// Folds completed event pairs into the statistics (call after a synchronisation).
+void resolve_phases(cpma* s) {
+  for (const auto& p : s->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      s->stats[p.phase].ms += ms;
+      s->stats[p.phase].launches += 1;
+    }
+    s->evpool.push_back(p.a);
+    s->evpool.push_back(p.b);
+  }
+  s->pending.clear();
+}
+
 void read_counters(cpma* s, hipStream_t st) {
   HIPCHK(hipMemcpyAsync(s->hctr, s->dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  resolve_phases(s);
   if (s->hctr->error) throw Fail{CPMA_ERR_DEVICE};
 }
 
@@ -197,6 +255,8 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
   if (s->hinfo->has_reserved) throw Fail{CPMA_ERR_RESERVED_KEY};
 
   const uint64_t* sorted = src;
+  int passes_done = 0;
+  PhaseMark pm = phase_begin(s, CPMA_PHASE_SORT, st);
   if (s->hinfo->unsorted) {
     const uint64_t orv = s->hinfo->or_all;
     int bits = 64 - __builtin_clzll(orv | 1);
@@ -220,6 +280,7 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
       in = out;
     }
     sorted = in;
+    passes_done = passes;
   }
   ensure(s->segpos, (k + 1) * sizeof(uint32_t));
   ensure(s->kdedup, k * sizeof(uint64_t));
@@ -227,13 +288,10 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
   hipLaunchKernelGGL(k_compact_unique, dim3(grid_for(k, 256)), dim3(256), 0, st, sorted, k,
                      (const uint32_t*)s->segpos.as<uint32_t>(), s->kdedup.as<uint64_t>(), &s->dctr->kprime);
   HIPCHK(hipGetLastError());
+  phase_end(s, pm, st, 24ull * k * (uint64_t)(passes_done + 1));
   return s->kdedup.as<uint64_t>();
 }
 
-size_t merge_smem(uint32_t S) {
-  const uint32_t maxA = S - 7;
-  return 8ull * (maxA + 1) + 8ull * (maxA + kSliceCap + 1) + 4ull * ((maxA + 4) & ~3u) + S;
-}
 size_t heavy_smem(uint32_t S) {
   const uint32_t maxA = S - 7;
   return 8ull * (maxA + 1) + 4ull * ((maxA + 4) & ~3u) + S;
@@ -550,6 +608,7 @@ void resize(cpma* s, uint64_t total, uint32_t viol, hipStream_t st) {
 // bounds.
 void rebalance(cpma* s, hipStream_t st) {
   for (int round = 0; round < 256; round++) {
+    PhaseMark pc = phase_begin(s, CPMA_PHASE_COUNT, st);
     Pyramid P = make_pyramid(s, s->L);
     build_pyramid(s, P, s->used.as<uint32_t>(), s->L, st);
     ensure(s->win, std::max<uint64_t>(s->L, 1) * sizeof(uint64_t));
@@ -558,10 +617,13 @@ void rebalance(cpma* s, hipStream_t st) {
     hipLaunchKernelGGL(k_select, dim3(grid_for(nodes, 256, 1u << 16)), dim3(256), 0, st, s->bounds(s->L), P,
                        (const uint32_t*)s->used.as<uint32_t>(), s->win.as<uint64_t>(), s->dctr);
     HIPCHK(hipGetLastError());
+    phase_end(s, pc, st, 4ull * s->L + 16ull * nodes);
     read_counters(s, st);
     const Counters c = *s->hctr;
     if (c.root_viol) {
+      PhaseMark pr = phase_begin(s, CPMA_PHASE_REDIST, st);
       resize(s, c.root_sum, c.root_viol, st);
+      phase_end(s, pr, st);
       continue;
     }
     if (c.nwin == 0) return;
@@ -570,7 +632,10 @@ void rebalance(cpma* s, hipStream_t st) {
     HIPCHK(hipStreamSynchronize(st));
     std::vector<Win> wins(c.nwin);
     for (uint32_t w = 0; w < c.nwin; w++) wins[w] = Win{(int)(hw[w] >> 48), hw[w] & ((1ull << 48) - 1)};
-    if (!redistribute(s, wins, st)) {
+    PhaseMark pr = phase_begin(s, CPMA_PHASE_REDIST, st);
+    const bool done = redistribute(s, wins, st);
+    phase_end(s, pr, st);
+    if (!done) {
       // Escalation past the root: grow if the structure is dense, else shrink.
       const uint64_t total = c.root_sum;
       const bool dense = (__int128)total * kQ * 2 >
@@ -591,6 +656,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   ensure(s->arena, arena_cap);
   const uint64_t stage_cap = insert ? s->n + kbound + 64 : 64;
   ensure(s->stage, stage_cap * sizeof(uint64_t));
+  PhaseMark pl = phase_begin(s, CPMA_PHASE_LOCATE, st);
   hipLaunchKernelGGL(k_locate, dim3(grid_for(kbound, 256, 1u << 16)), dim3(256), 0, st, B,
                      (const unsigned long long*)&s->dctr->kprime, (const uint64_t*)s->head.as<uint64_t>(), s->L,
                      s->leafid.as<uint32_t>());
@@ -602,6 +668,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
                      (const uint32_t*)s->segpos.as<uint32_t>(), kbound, s->seg_leaf.as<uint32_t>(),
                      s->seg_begin.as<uint32_t>(), s->dctr);
   HIPCHK(hipGetLastError());
+  phase_end(s, pl, st, 24ull * kbound);
   MergeArgs a;
   a.bytes = s->bytes.as<uint8_t>();
   a.used = s->used.as<uint32_t>();
@@ -618,15 +685,21 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   a.ctr = s->dctr;
   a.S = s->S;
   a.is_insert = insert ? 1 : 0;
-  const uint32_t mgrid = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(kbound, s->L), (uint64_t)s->num_cus * 16);
-  hipLaunchKernelGGL(k_merge, dim3(std::max(1u, mgrid)), dim3(kWave), merge_smem(s->S), st, a);
+  const uint64_t segs = std::min<uint64_t>(kbound, s->L);
+  const uint32_t lgrid = (uint32_t)std::min<uint64_t>((segs + 255) / 256, (uint64_t)s->num_cus * 16);
+  PhaseMark pmg = phase_begin(s, CPMA_PHASE_MERGE, st);
+  hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a);
   HIPCHK(hipGetLastError());
+  phase_end(s, pmg, st);
   if (insert) {
-    hipLaunchKernelGGL(k_merge_heavy, dim3(std::max(1u, std::min(mgrid, 1024u))), dim3(kWave), heavy_smem(s->S),
-                       st, a);
+    const uint32_t hgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, kbound / kLaneHeavy), 1024);
+    PhaseMark ph = phase_begin(s, CPMA_PHASE_HEAVY, st);
+    hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid), dim3(kWave), heavy_smem(s->S), st, a);
     HIPCHK(hipGetLastError());
+    phase_end(s, ph, st);
   }
   read_counters(s, st);
+  if (s->stats_on) s->stats[CPMA_PHASE_MERGE].alg_bytes += s->hctr->alg_bytes;
   const uint64_t delta = s->hctr->delta;
   if (insert)
     s->n += delta;
@@ -779,6 +852,7 @@ static cpma_status update(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem me
     zero_counters(s, st);
     const uint64_t* B = prepare_batch(s, keys, k, mem, st);
     delta = apply_batch(s, B, k, insert, st);
+    resolve_phases(s);
   });
   if (r == CPMA_OK && delta_out) *delta_out = delta;
   return r;
@@ -836,18 +910,24 @@ cpma_status cpma_range_map(const cpma* cs, const uint64_t* lo, const uint64_t* h
     ensure(s->qfirst, q * 8);
     ensure(s->qnvis, q * 8);
     ensure(s->qvoff, (q + 1) * 8);
+    PhaseMark pq = phase_begin(s, CPMA_PHASE_QUERY, st);
     hipLaunchKernelGGL(k_rm_locate, dim3(grid_for(q, 256, 1u << 16)), dim3(256), 0, st, a,
                        s->qfirst.as<uint64_t>(), s->qnvis.as<uint64_t>(), dsum, dcount);
     HIPCHK(hipGetLastError());
     scan<uint64_t>(s, s->qvoff.as<uint64_t>(), q, st, LoadFn<uint64_t>{s->qnvis.as<uint64_t>()});
     const uint32_t blocks = (uint32_t)s->num_cus * 8;
+    PhaseMark ps = phase_begin(s, CPMA_PHASE_RANGE_SCAN, st);
     hipLaunchKernelGGL(k_rm_scan, dim3(blocks), dim3(256), 0, st, a, (const uint64_t*)s->qvoff.as<uint64_t>(),
-                       (const uint64_t*)s->qfirst.as<uint64_t>(), 4u, dsum, dcount);
+                       (const uint64_t*)s->qfirst.as<uint64_t>(), 4u, dsum, dcount,
+                       s->stats_on ? s->dqalg : (unsigned long long*)nullptr);
     HIPCHK(hipGetLastError());
+    phase_end(s, ps, st, 32ull * q);
+    phase_end(s, pq, st);
     if (mem == CPMA_MEM_HOST) {
       HIPCHK(hipMemcpyAsync(sum, dsum, q * 8, hipMemcpyDeviceToHost, st));
       HIPCHK(hipMemcpyAsync(count, dcount, q * 8, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
+      resolve_phases(s);
     }
   });
 }
@@ -874,8 +954,10 @@ cpma_status cpma_contains(const cpma* cs, const uint64_t* keys, uint64_t q, cpma
       dout = s->qout.as<uint8_t>();
     }
     const uint32_t blocks = (uint32_t)std::min<uint64_t>((q + 3) / 4, (uint64_t)s->num_cus * 8);
+    PhaseMark pq = phase_begin(s, CPMA_PHASE_QUERY, st);
     hipLaunchKernelGGL(k_contains, dim3(std::max(1u, blocks)), dim3(256), 0, st, a, dk, dout);
     HIPCHK(hipGetLastError());
+    phase_end(s, pq, st);
     if (mem == CPMA_MEM_HOST) {
       HIPCHK(hipMemcpyAsync(out, dout, q, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -908,9 +990,49 @@ cpma_status cpma_export(const cpma* cs, uint8_t* bytes, uint32_t* used, uint64_t
   });
 }
 
+cpma_status cpma_stats_enable(cpma* s, int on) {
+  if (!s) return CPMA_ERR_INVALID;
+  return guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    HIPCHK(hipDeviceSynchronize());
+    resolve_phases(s);
+    if (on) {
+      if (!s->dqalg) HIPCHK(hipMalloc(&s->dqalg, sizeof(unsigned long long)));
+      HIPCHK(hipMemset(s->dqalg, 0, sizeof(unsigned long long)));
+      HIPCHK(hipDeviceSynchronize());
+      memset(s->stats, 0, sizeof(s->stats));
+    }
+    s->stats_on = on != 0;
+  });
+}
+
+cpma_status cpma_stats_get(const cpma* cs, cpma_phase_stat* out, int n) {
+  cpma* s = const_cast<cpma*>(cs);
+  if (!s || !out || n < 0) return CPMA_ERR_INVALID;
+  return guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    HIPCHK(hipDeviceSynchronize());
+    resolve_phases(s);
+    cpma_phase_stat tmp[CPMA_PHASE_NUM];
+    memcpy(tmp, s->stats, sizeof(tmp));
+    if (s->dqalg) {
+      unsigned long long q = 0;
+      HIPCHK(hipMemcpy(&q, s->dqalg, sizeof(q), hipMemcpyDeviceToHost));
+      tmp[CPMA_PHASE_RANGE_SCAN].alg_bytes += q;
+    }
+    for (int i = 0; i < n && i < CPMA_PHASE_NUM; i++) out[i] = tmp[i];
+  });
+}
+
 void cpma_destroy(cpma* s) {
   if (!s) return;
   hipDeviceSynchronize();
+  for (const auto& p : s->pending) {
+    hipEventDestroy(p.a);
+    hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : s->evpool) hipEventDestroy(e);
+  if (s->dqalg) hipFree(s->dqalg);
   DevBuf* bufs[] = {&s->bytes,  &s->used,     &s->head,      &s->kin,       &s->kb0,   &s->kb1,    &s->kdedup,
                     &s->leafid, &s->segpos,   &s->seg_leaf,  &s->seg_begin, &s->heavy, &s->scan_tmp,
                     &s->ovf,    &s->arena,    &s->stage,     &s->pyr,       &s->win,   &s->wargs,  &s->cnt,

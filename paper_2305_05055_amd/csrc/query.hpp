@@ -47,8 +47,10 @@ __global__ void k_rm_locate(QueryArgs a, uint64_t* __restrict__ first_leaf, uint
 __global__ void __launch_bounds__(256) k_rm_scan(QueryArgs a, const uint64_t* __restrict__ voff,
                                                  const uint64_t* __restrict__ first_leaf, uint32_t chunk,
                                                  unsigned long long* __restrict__ sum,
-                                                 unsigned long long* __restrict__ count) {
+                                                 unsigned long long* __restrict__ count,
+                                                 unsigned long long* __restrict__ alg) {
   const int lane = lane_id();
+  uint64_t visited = 0;  // used bytes decoded by this wave (statistics)
   const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
   const uint64_t wid = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const uint64_t V = voff[a.q];
@@ -77,6 +79,7 @@ __global__ void __launch_bounds__(256) k_rm_scan(QueryArgs a, const uint64_t* __
       }
       const uint64_t leaf = first_leaf[qi] + (v - voff[qi]);
       const uint32_t u = a.used[leaf];
+      visited += u;
       wave_decode_leaf(a.bytes + leaf * (uint64_t)a.S, u, [&](uint32_t, uint64_t x) {
         const bool in = (x >= qlo) & (x < qhi);
         acc_s += in ? x : 0ull;
@@ -89,6 +92,7 @@ __global__ void __launch_bounds__(256) k_rm_scan(QueryArgs a, const uint64_t* __
       atomicAdd(&count[qi], (unsigned long long)n);
     }
   }
+  if (alg && lane == 0 && visited) atomicAdd(alg, (unsigned long long)visited);
 }
 
 // Membership: one wave per key -- locate the leaf, decode it, compare.

@@ -7,7 +7,6 @@
 
 namespace cpma_dev {
 
-constexpr uint32_t kSliceCap = 1024;  // batch keys merged per leaf in LDS; more -> heavy path
 
 // Device-side counters of one update, read back by the host at its sync points.
 struct Counters {
@@ -21,6 +20,8 @@ struct Counters {
   unsigned int nwin;                // windows selected for redistribution
   unsigned int root_viol;           // violation bits of the root
   unsigned int error;               // internal capacity overflow (bug guard)
+  unsigned long long alg_bytes;     // algorithmic HBM bytes of the merge (statistics)
+  unsigned long long alg_bytes_q;   // algorithmic HBM bytes of range scans (statistics)
 };
 
 __device__ __forceinline__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t x) {
@@ -136,27 +137,32 @@ __device__ __forceinline__ void wave_scan_inplace(uint32_t* F, uint32_t n) {
 
 // Writes keys get(0..m) into leaf `leaf`: in place if they fit, else into the
 // overflow arena (the paper's out-of-place memory for an overflowing leaf,
-// cleaned up by the redistribution).  Updates used / head / ovf.
+// cleaned up by the redistribution).  Only the first max(old_used, new size)
+// bytes are rewritten: the rest of the leaf is already zero.  Updates used /
+// head / ovf and returns the bytes written.
 template <class Get>
-__device__ void wave_store_leaf(const MergeArgs& a, uint64_t leaf, Get&& get, uint32_t m,
-                                uint8_t* buf) {
+__device__ uint64_t wave_store_leaf(const MergeArgs& a, uint64_t leaf, Get&& get, uint32_t m,
+                                    uint8_t* buf, uint32_t old_used) {
   const int lane = lane_id();
   uint8_t* dst = a.bytes + leaf * (uint64_t)a.S;
   if (m == 0) {
-    wave_zero(dst, a.S);
+    wave_zero(dst, (old_used + 15u) & ~15u);
     if (lane == 0) {
       a.used[leaf] = 0;
       a.head[leaf] = kNoKey;
     }
-    return;
+    return old_used;
   }
   const uint64_t T = wave_encoded_size(get, m);
+  uint64_t written;
   if (T <= a.S) {
-    wave_zero(buf, a.S);
+    const uint32_t len = ((uint32_t)max((uint64_t)old_used, T) + 15u) & ~15u;
+    wave_zero(buf, len);
     __syncthreads();
     wave_encode_bytes(get, m, buf);
     __syncthreads();
-    wave_copy16(dst, buf, a.S);
+    wave_copy16(dst, buf, len);
+    written = len;
   } else {
     const uint64_t need = (T + 15) & ~15ull;
     uint64_t off = 0;
@@ -164,91 +170,20 @@ __device__ void wave_store_leaf(const MergeArgs& a, uint64_t leaf, Get&& get, ui
     off = __shfl(off, 0, kWave);
     if (off + need > a.arena_cap) {
       if (lane == 0) atomicOr(&a.ctr->error, 1u);
-      return;
+      return 0;
     }
     wave_encode_bytes(get, m, a.arena + off);
     if (lane == 0) a.ovf[leaf] = off;
+    written = T;
   }
   if (lane == 0) {
     a.used[leaf] = (uint32_t)T;
     a.head[leaf] = get(0);
   }
+  return written;
 }
 
-// One wave (block of 64) per touched leaf: decode the leaf into LDS, merge its
-// batch slice (union for inserts, difference for deletes), re-encode.
-__global__ void __launch_bounds__(kWave) k_merge(MergeArgs a) {
-  extern __shared__ __align__(16) uint8_t smem[];
-  const uint32_t S = a.S;
-  const uint32_t maxA = S - 7;
-  uint64_t* A = reinterpret_cast<uint64_t*>(smem);
-  uint64_t* C = A + maxA + 1;
-  uint32_t* F = reinterpret_cast<uint32_t*>(C + maxA + kSliceCap + 1);
-  uint8_t* buf = reinterpret_cast<uint8_t*>(F + ((maxA + 4) & ~3u));
-  const int lane = lane_id();
-  const uint64_t T = a.ctr->T;
-  unsigned long long delta = 0;
-  for (uint64_t s = blockIdx.x; s < T; s += gridDim.x) {
-    const uint64_t leaf = a.seg_leaf[s];
-    const uint32_t b = a.seg_begin[s], e = a.seg_begin[s + 1];
-    const uint32_t nb = e - b;
-    const uint64_t* Bs = a.B + b;
-    if (a.is_insert && nb > kSliceCap) {
-      if (lane == 0) a.heavy_list[atomicAdd(&a.ctr->heavy, 1u)] = (uint32_t)s;
-      continue;
-    }
-    const uint8_t* src = a.bytes + leaf * (uint64_t)S;
-    const uint32_t nA = wave_decode_leaf(src, a.used[leaf], [&](uint32_t i, uint64_t x) { A[i] = x; });
-    __syncthreads();
-    uint32_t nC;
-    if (a.is_insert) {
-      for (uint32_t i = lane; i <= nA; i += kWave) F[i] = 0;
-      __syncthreads();
-      for (uint32_t j = lane; j < nb; j += kWave) {
-        const uint64_t x = Bs[j];
-        const uint32_t r = (uint32_t)lds_lower_bound(A, nA, x);
-        if (r < nA && A[r] == x) F[r] = 1;
-      }
-      __syncthreads();
-      wave_scan_inplace(F, nA + 1);
-      __syncthreads();
-      const uint32_t present = F[nA];
-      for (uint32_t j = lane; j < nb; j += kWave) {
-        const uint64_t x = Bs[j];
-        const uint32_t r = (uint32_t)lds_lower_bound(A, nA, x);
-        if (!(r < nA && A[r] == x)) C[r + j - F[r]] = x;
-      }
-      for (uint32_t i = lane; i < nA; i += kWave) {
-        const uint32_t lb = (uint32_t)lower_bound_u64(Bs, nb, A[i]);
-        C[i + lb - F[i]] = A[i];
-      }
-      nC = nA + nb - present;
-      delta += nb - present;
-    } else {
-      for (uint32_t i = lane; i < nA; i += kWave) {
-        const uint64_t x = A[i];
-        const uint64_t r = lower_bound_u64(Bs, nb, x);
-        F[i] = (r < nb && Bs[r] == x) ? 0u : 1u;
-      }
-      if (lane == 0) F[nA] = 0;
-      __syncthreads();
-      wave_scan_inplace(F, nA + 1);
-      __syncthreads();
-      for (uint32_t i = lane; i < nA; i += kWave) {
-        const bool keep = F[i + 1] != F[i];
-        if (keep) C[F[i]] = A[i];
-      }
-      nC = F[nA];
-      delta += nA - nC;
-    }
-    __syncthreads();
-    wave_store_leaf(a, leaf, [&](uint32_t i) { return C[i]; }, nC, buf);
-    __syncthreads();
-  }
-  if (lane == 0 && delta) atomicAdd(&a.ctr->delta, delta);
-}
-
-// Heavy inserts: a slice larger than kSliceCap.  The merged keys go to the
+// Heavy inserts: a slice too long for one lane.  The merged keys go to the
 // staging buffer in HBM (each output position from two binary searches), then
 // are encoded in place or into the arena.
 __global__ void __launch_bounds__(kWave) k_merge_heavy(MergeArgs a) {
@@ -268,7 +203,8 @@ __global__ void __launch_bounds__(kWave) k_merge_heavy(MergeArgs a) {
     const uint32_t nb = e - b;
     const uint64_t* Bs = a.B + b;
     const uint8_t* src = a.bytes + leaf * (uint64_t)S;
-    const uint32_t nA = wave_decode_leaf(src, a.used[leaf], [&](uint32_t i, uint64_t x) { A[i] = x; });
+    const uint32_t used0 = a.used[leaf];
+    const uint32_t nA = wave_decode_leaf(src, used0, [&](uint32_t i, uint64_t x) { A[i] = x; });
     for (uint32_t i = lane; i <= nA; i += kWave) F[i] = 0;
     __syncthreads();
     for (uint32_t j = lane; j < nb; j += kWave) {
@@ -301,7 +237,7 @@ __global__ void __launch_bounds__(kWave) k_merge_heavy(MergeArgs a) {
     delta += nb - present;
     __threadfence_block();
     __syncthreads();
-    wave_store_leaf(a, leaf, [&](uint32_t i) { return C[i]; }, nC, buf);
+    wave_store_leaf(a, leaf, [&](uint32_t i) { return C[i]; }, nC, buf, used0);
     __syncthreads();
   }
   if (lane == 0 && delta) atomicAdd(&a.ctr->delta, delta);
