@@ -12,23 +12,84 @@ constexpr int kMaxLevels = 48;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
-// ---- wave-level scans / reductions (64 lanes) -----------------------------------
+// ---- DPP wave primitives (GFX9 row shifts, row broadcasts, wave shifts) -------------
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf, bool BOUND_ZERO = true>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, BANK_MASK, BOUND_ZERO);
+}
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf, bool BOUND_ZERO = true>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  const uint32_t lo = dpp32<CTRL, ROW_MASK, BANK_MASK, BOUND_ZERO>((uint32_t)v);
+  const uint32_t hi = dpp32<CTRL, ROW_MASK, BANK_MASK, BOUND_ZERO>((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive prefix sum over the 64 lanes: in-row Hillis-Steele steps of 1, 2, 4, 8
+// lanes, then the row broadcasts of lanes 15 and 31.
 template <typename T>
-__device__ __forceinline__ T wave_incl_scan(T v) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    T t = __shfl_up(v, d, kWave);
-    if (lane >= d) v += t;
-  }
+__device__ __forceinline__ T dpp_incl_scan(T v);
+template <>
+__device__ __forceinline__ uint32_t dpp_incl_scan<uint32_t>(uint32_t v) {
+  v += dpp32<0x111>(v);
+  v += dpp32<0x112>(v);
+  v += dpp32<0x114>(v);
+  v += dpp32<0x118>(v);
+  v += dpp32<0x142, 0xa, 0xf, false>(v);
+  v += dpp32<0x143, 0xc, 0xf, false>(v);
+  return v;
+}
+template <>
+__device__ __forceinline__ uint64_t dpp_incl_scan<uint64_t>(uint64_t v) {
+  v += dpp64<0x111>(v);
+  v += dpp64<0x112>(v);
+  v += dpp64<0x114>(v);
+  v += dpp64<0x118>(v);
+  v += dpp64<0x142, 0xa, 0xf, false>(v);
+  v += dpp64<0x143, 0xc, 0xf, false>(v);
   return v;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+// Inclusive prefix maximum over the 64 lanes (same step pattern).
+__device__ __forceinline__ uint32_t dpp_incl_max(uint32_t v) {
+  v = max(v, dpp32<0x111>(v));
+  v = max(v, dpp32<0x112>(v));
+  v = max(v, dpp32<0x114>(v));
+  v = max(v, dpp32<0x118>(v));
+  v = max(v, dpp32<0x142, 0xa, 0xf, false>(v));
+  v = max(v, dpp32<0x143, 0xc, 0xf, false>(v));
   return v;
+}
+
+// Value of lane l-1 (0 for lane 0) and of lane l+1 (0 for lane 63).
+__device__ __forceinline__ uint32_t dpp_prev32(uint32_t v) { return dpp32<0x138>(v); }
+__device__ __forceinline__ uint64_t dpp_prev64(uint64_t v) { return dpp64<0x138>(v); }
+__device__ __forceinline__ uint32_t dpp_next32(uint32_t v) { return dpp32<0x130>(v); }
+__device__ __forceinline__ uint64_t dpp_next64(uint64_t v) { return dpp64<0x130>(v); }
+
+__device__ __forceinline__ uint32_t lane63_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ uint64_t lane63_u64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// ---- wave-level scans / reductions (64 lanes, DPP) ---------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  return dpp_incl_scan<T>(v);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v);
+template <>
+__device__ __forceinline__ uint32_t wave_sum<uint32_t>(uint32_t v) {
+  return lane63_u32(dpp_incl_scan<uint32_t>(v));
+}
+template <>
+__device__ __forceinline__ uint64_t wave_sum<uint64_t>(uint64_t v) {
+  return lane63_u64(dpp_incl_scan<uint64_t>(v));
 }
 
 __device__ __forceinline__ uint64_t wave_or(uint64_t v) {

@@ -18,6 +18,7 @@
 #include "sort.hpp"
 #include "update.hpp"
 #include "merge_lane.hpp"
+#include "merge_wave.hpp"
 
 using namespace cpma_dev;
 
@@ -92,7 +93,7 @@ struct cpma {
   int64_t q_up_leaf = 0, q_up_root = 0, q_lo_leaf = 0, q_lo_root = 0;
   DevBuf bytes, used, head;
   // scratch
-  DevBuf kin, kb0, kb1, kdedup, leafid, segpos, seg_leaf, seg_begin, heavy, scan_tmp, ovf, arena,
+  DevBuf kin, kb0, kb1, kdedup, leafid, segpos, seg_leaf, seg_begin, heavy, spill, scan_tmp, ovf, arena,
       stage, pyr, win, wargs, cnt, koff, win_id, welem, P, ncost, lstart, planU, plan_used,
       win_of_leaf, fail, qa, qb, qfirst, qnvis, qvoff, qsum, qcount, qout;
   Counters* dctr = nullptr;
@@ -651,6 +652,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   ensure(s->seg_leaf, kbound * sizeof(uint32_t));
   ensure(s->seg_begin, (kbound + 1) * sizeof(uint32_t));
   ensure(s->heavy, kbound * sizeof(uint32_t));
+  ensure(s->spill, kbound * sizeof(uint32_t));
   ensure(s->ovf, std::max<uint64_t>(s->L, 1) * sizeof(uint64_t));
   const uint64_t arena_cap = insert ? std::min<uint64_t>(s->L, kbound) * (uint64_t)(s->S + 16) + 10 * kbound + 256 : 256;
   ensure(s->arena, arena_cap);
@@ -682,13 +684,22 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   a.seg_leaf = s->seg_leaf.as<uint32_t>();
   a.seg_begin = s->seg_begin.as<uint32_t>();
   a.heavy_list = s->heavy.as<uint32_t>();
+  a.spill_list = s->spill.as<uint32_t>();
   a.ctr = s->dctr;
   a.S = s->S;
   a.is_insert = insert ? 1 : 0;
   const uint64_t segs = std::min<uint64_t>(kbound, s->L);
   const uint32_t lgrid = (uint32_t)std::min<uint64_t>((segs + 255) / 256, (uint64_t)s->num_cus * 16);
   PhaseMark pmg = phase_begin(s, CPMA_PHASE_MERGE, st);
-  hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a);
+  if (s->S <= kWaveMaxS) {
+    // one wave per touched leaf; long insert slices spill to the lane merge
+    const uint32_t wgrid = (uint32_t)std::min<uint64_t>(segs, (uint64_t)s->num_cus * 40);
+    hipLaunchKernelGGL(k_merge_wave, dim3(std::max(1u, wgrid)), dim3(kWave), 0, st, a);
+    HIPCHK(hipGetLastError());
+    if (insert) hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 1);
+  } else {
+    hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 0);
+  }
   HIPCHK(hipGetLastError());
   phase_end(s, pmg, st);
   if (insert) {
@@ -911,15 +922,15 @@ cpma_status cpma_range_map(const cpma* cs, const uint64_t* lo, const uint64_t* h
     ensure(s->qnvis, q * 8);
     ensure(s->qvoff, (q + 1) * 8);
     PhaseMark pq = phase_begin(s, CPMA_PHASE_QUERY, st);
-    hipLaunchKernelGGL(k_rm_locate, dim3(grid_for(q, 256, 1u << 16)), dim3(256), 0, st, a,
-                       s->qfirst.as<uint64_t>(), s->qnvis.as<uint64_t>(), dsum, dcount);
+    unsigned long long* qalg = s->stats_on ? s->dqalg : (unsigned long long*)nullptr;
+    hipLaunchKernelGGL(k_rm_ends, dim3(grid_for(q, 256, (uint32_t)s->num_cus * 16)), dim3(256), 0, st, a,
+                       s->qfirst.as<uint64_t>(), s->qnvis.as<uint64_t>(), dsum, dcount, qalg);
     HIPCHK(hipGetLastError());
     scan<uint64_t>(s, s->qvoff.as<uint64_t>(), q, st, LoadFn<uint64_t>{s->qnvis.as<uint64_t>()});
     const uint32_t blocks = (uint32_t)s->num_cus * 8;
     PhaseMark ps = phase_begin(s, CPMA_PHASE_RANGE_SCAN, st);
-    hipLaunchKernelGGL(k_rm_scan, dim3(blocks), dim3(256), 0, st, a, (const uint64_t*)s->qvoff.as<uint64_t>(),
-                       (const uint64_t*)s->qfirst.as<uint64_t>(), 4u, dsum, dcount,
-                       s->stats_on ? s->dqalg : (unsigned long long*)nullptr);
+    hipLaunchKernelGGL(k_rm_interior, dim3(blocks), dim3(256), 0, st, a, (const uint64_t*)s->qvoff.as<uint64_t>(),
+                       (const uint64_t*)s->qfirst.as<uint64_t>(), 8u, dsum, dcount, qalg);
     HIPCHK(hipGetLastError());
     phase_end(s, ps, st, 32ull * q);
     phase_end(s, pq, st);
@@ -953,9 +964,9 @@ cpma_status cpma_contains(const cpma* cs, const uint64_t* keys, uint64_t q, cpma
       dk = s->qa.as<uint64_t>();
       dout = s->qout.as<uint8_t>();
     }
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>((q + 3) / 4, (uint64_t)s->num_cus * 8);
     PhaseMark pq = phase_begin(s, CPMA_PHASE_QUERY, st);
-    hipLaunchKernelGGL(k_contains, dim3(std::max(1u, blocks)), dim3(256), 0, st, a, dk, dout);
+    hipLaunchKernelGGL(k_contains, dim3(grid_for(q, 256, (uint32_t)s->num_cus * 16)), dim3(256), 0, st, a, dk,
+                       dout);
     HIPCHK(hipGetLastError());
     phase_end(s, pq, st);
     if (mem == CPMA_MEM_HOST) {
@@ -1034,7 +1045,7 @@ void cpma_destroy(cpma* s) {
   for (hipEvent_t e : s->evpool) hipEventDestroy(e);
   if (s->dqalg) hipFree(s->dqalg);
   DevBuf* bufs[] = {&s->bytes,  &s->used,     &s->head,      &s->kin,       &s->kb0,   &s->kb1,    &s->kdedup,
-                    &s->leafid, &s->segpos,   &s->seg_leaf,  &s->seg_begin, &s->heavy, &s->scan_tmp,
+                    &s->leafid, &s->segpos,   &s->seg_leaf,  &s->seg_begin, &s->heavy, &s->spill, &s->scan_tmp,
                     &s->ovf,    &s->arena,    &s->stage,     &s->pyr,       &s->win,   &s->wargs,  &s->cnt,
                     &s->koff,   &s->win_id,   &s->welem,     &s->P,         &s->ncost, &s->lstart, &s->planU,
                     &s->plan_used, &s->win_of_leaf, &s->fail, &s->qa,        &s->qb,    &s->qfirst, &s->qnvis,

@@ -76,8 +76,8 @@ __device__ __forceinline__ uint32_t wave_decode_leaf(const uint8_t* __restrict__
     if (pos0 < used) w = *reinterpret_cast<const uint4*>(src + pos0);
     LaneCodes c;
     lane_parse(w, pos0, used, c);
-    uint64_t cin_acc = __shfl_up(c.tail_acc, 1, kWave);
-    uint32_t cin_sh = __shfl_up(c.tail_sh, 1, kWave);
+    uint64_t cin_acc = dpp_prev64(c.tail_acc);
+    uint32_t cin_sh = dpp_prev32(c.tail_sh);
     if (lane == 0) {
       cin_acc = carry_acc;
       cin_sh = carry_sh;
@@ -103,10 +103,10 @@ __device__ __forceinline__ uint32_t wave_decode_leaf(const uint8_t* __restrict__
         idx++;
       }
     }
-    run_key += __shfl(incl_sum, kWave - 1, kWave);
-    run_cnt += __shfl(incl_cnt, kWave - 1, kWave);
-    carry_acc = __shfl(c.tail_acc, kWave - 1, kWave);
-    carry_sh = __shfl(c.tail_sh, kWave - 1, kWave);
+    run_key += lane63_u64(incl_sum);
+    run_cnt += lane63_u32(incl_cnt);
+    carry_acc = lane63_u64(c.tail_acc);
+    carry_sh = lane63_u32(c.tail_sh);
   }
   return run_cnt;
 }
@@ -169,7 +169,7 @@ __device__ __forceinline__ void wave_encode_bytes(Get&& get, uint32_t m, uint8_t
       else
         vput(p, x - prev);
     }
-    off0 += __shfl(incl, kWave - 1, kWave);
+    off0 += lane63_u64(incl);
   }
 }
 

@@ -189,12 +189,14 @@ struct BwdWriter {
 
 constexpr uint32_t kLaneHeavy = 4096;  // inserts with longer slices take the wave path
 
-__global__ void __launch_bounds__(256) k_merge_lane(MergeArgs a) {
-  const uint64_t T = a.ctr->T;
+// from_list: process the segments listed by the wave merge instead of all of them.
+__global__ void __launch_bounds__(256) k_merge_lane(MergeArgs a, int from_list) {
+  const uint64_t T = from_list ? (uint64_t)a.ctr->nspill : a.ctr->T;
   const uint64_t lanes = (uint64_t)gridDim.x * blockDim.x;
   unsigned long long delta = 0, alg = 0;
   const uint32_t S = a.S;
-  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < T; s += lanes) {
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < T; t += lanes) {
+    const uint64_t s = from_list ? (uint64_t)a.spill_list[t] : t;
     const uint64_t leaf = a.seg_leaf[s];
     const uint32_t b = a.seg_begin[s], e = a.seg_begin[s + 1];
     const uint32_t nb = e - b;

@@ -5,9 +5,12 @@
 // runs on the uncompressed leaf heads and the scan decodes every leaf it passes
 // (Section "Compressed Packed Memory Array", "Point queries").  A batch of
 // queries becomes a flat list of leaf visits (query q visits leaves
-// leaf(lo_q) .. leaf(hi_q - 1)); persistent waves take fixed-size chunks of
-// visits, so long and short ranges balance across the GPU.
+// leaf(lo_q) .. leaf(hi_q - 1)).  The two end leaves of each query are scanned
+// with comparisons by one lane per query; the interior leaves are flattened over
+// all queries and split into fixed-size chunks, so long and short ranges balance
+// across the GPU in one launch.
 #pragma once
+#include "scan_lane.hpp"
 #include "update.hpp"
 
 namespace cpma_dev {
@@ -23,91 +26,110 @@ struct QueryArgs {
   uint32_t S;
 };
 
-// First leaf of every query and its number of leaf visits; zeroes the outputs.
-__global__ void k_rm_locate(QueryArgs a, uint64_t* __restrict__ first_leaf, uint64_t* __restrict__ nvis,
-                            unsigned long long* __restrict__ sum, unsigned long long* __restrict__ count) {
+// End leaves of every query (the leaf of lo and the leaf of hi - 1), scanned with
+// comparisons by one lane per query; the result initialises sum / count.  The
+// leaves strictly between them are the query's interior visits.
+__global__ void __launch_bounds__(256) k_rm_ends(QueryArgs a, uint64_t* __restrict__ first_int,
+                                                 uint64_t* __restrict__ nint,
+                                                 unsigned long long* __restrict__ sum,
+                                                 unsigned long long* __restrict__ count,
+                                                 unsigned long long* __restrict__ alg) {
+  uint64_t visited = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.q;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t lo = a.lo[i], hi = a.hi[i];
     uint64_t f = 0, n = 0;
+    LeafSum r{0, 0};
     if (lo < hi) {
       f = locate_leaf(a.head, a.L, lo);
-      n = locate_leaf(a.head, a.L, hi - 1) - f + 1;
+      const uint64_t l = locate_leaf(a.head, a.L, hi - 1);
+      const uint32_t uf = a.used[f];
+      r = leaf_sum_range(a.bytes + f * (uint64_t)a.S, uf, lo, hi);
+      visited += uf;
+      if (l != f) {
+        const uint32_t ul = a.used[l];
+        const LeafSum r2 = leaf_sum_range(a.bytes + l * (uint64_t)a.S, ul, lo, hi);
+        r.sum += r2.sum;
+        r.count += r2.count;
+        visited += ul;
+      }
+      n = (l > f + 1) ? l - f - 1 : 0;
     }
-    first_leaf[i] = f;
-    nvis[i] = n;
-    sum[i] = 0;
-    count[i] = 0;
+    first_int[i] = f + 1;
+    nint[i] = n;
+    sum[i] = r.sum;
+    count[i] = r.count;
+  }
+  if (alg) {
+    const uint64_t t = wave_sum(visited);
+    if (lane_id() == 0 && t) atomicAdd(alg, (unsigned long long)t);
   }
 }
 
-// Persistent scan: each wave owns chunks of `chunk` consecutive visits.  Per-lane
-// partial sums stay in registers while the query is unchanged and are flushed
-// with one wave reduction and two 64-bit atomics (exact: integer adds commute).
-__global__ void __launch_bounds__(256) k_rm_scan(QueryArgs a, const uint64_t* __restrict__ voff,
-                                                 const uint64_t* __restrict__ first_leaf, uint32_t chunk,
-                                                 unsigned long long* __restrict__ sum,
-                                                 unsigned long long* __restrict__ count,
-                                                 unsigned long long* __restrict__ alg) {
-  const int lane = lane_id();
-  uint64_t visited = 0;  // used bytes decoded by this wave (statistics)
-  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
-  const uint64_t wid = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const uint64_t V = voff[a.q];
+// Interior visits, flattened over all queries: each lane takes `chunk`
+// consecutive visits (consecutive leaves of one query, or the tail of one query
+// and the head of the next), keeps running sums in registers while the query is
+// unchanged and flushes them with 64-bit atomics (exact: integer adds commute).
+__global__ void __launch_bounds__(256) k_rm_interior(QueryArgs a, const uint64_t* __restrict__ ioff,
+                                                     const uint64_t* __restrict__ first_int, uint32_t chunk,
+                                                     unsigned long long* __restrict__ sum,
+                                                     unsigned long long* __restrict__ count,
+                                                     unsigned long long* __restrict__ alg) {
+  const uint64_t lanes = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t V = ioff[a.q];
   const uint64_t nchunks = (V + chunk - 1) / chunk;
-  for (uint64_t c = wid; c < nchunks; c += waves) {
+  uint64_t visited = 0;
+  for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nchunks; c += lanes) {
     const uint64_t v0 = c * chunk;
     const uint64_t v1 = min(v0 + chunk, V);
-    uint64_t qi = upper_bound_u64(voff, a.q + 1, v0) - 1;
-    uint64_t acc_s = 0, acc_c = 0;
-    uint64_t qend = voff[qi + 1];
-    uint64_t qlo = a.lo[qi], qhi = a.hi[qi];
+    uint64_t qi = upper_bound_u64(ioff, a.q + 1, v0) - 1;
+    uint64_t qbeg = ioff[qi], qend = ioff[qi + 1];
+    uint64_t fl = first_int[qi];
+    uint64_t s = 0, n = 0;
     for (uint64_t v = v0; v < v1; v++) {
       if (v >= qend) {
-        const uint64_t s = wave_sum(acc_s), n = wave_sum(acc_c);
-        if (lane == 0 && n) {
+        if (n) {
           atomicAdd(&sum[qi], (unsigned long long)s);
           atomicAdd(&count[qi], (unsigned long long)n);
         }
-        acc_s = acc_c = 0;
+        s = n = 0;
         do {
           qi++;
-          qend = voff[qi + 1];
+          qbeg = ioff[qi];
+          qend = ioff[qi + 1];
         } while (v >= qend);
-        qlo = a.lo[qi];
-        qhi = a.hi[qi];
+        fl = first_int[qi];
       }
-      const uint64_t leaf = first_leaf[qi] + (v - voff[qi]);
+      const uint64_t leaf = fl + (v - qbeg);
       const uint32_t u = a.used[leaf];
+      const uint64_t h = a.head[leaf];
+      const uint64_t span = a.head[leaf + 1] - h;  // interior leaves always have a successor
+      const uint8_t* lp = a.bytes + leaf * (uint64_t)a.S;
+      const LeafSum r = span < (1ull << 28) ? leaf_sum_fast(lp, u, h) : leaf_sum_range(lp, u, 0, kNoKey);
+      s += r.sum;
+      n += r.count;
       visited += u;
-      wave_decode_leaf(a.bytes + leaf * (uint64_t)a.S, u, [&](uint32_t, uint64_t x) {
-        const bool in = (x >= qlo) & (x < qhi);
-        acc_s += in ? x : 0ull;
-        acc_c += in ? 1u : 0u;
-      });
     }
-    const uint64_t s = wave_sum(acc_s), n = wave_sum(acc_c);
-    if (lane == 0 && n) {
+    if (n) {
       atomicAdd(&sum[qi], (unsigned long long)s);
       atomicAdd(&count[qi], (unsigned long long)n);
     }
   }
-  if (alg && lane == 0 && visited) atomicAdd(alg, (unsigned long long)visited);
+  if (alg) {
+    const uint64_t t = wave_sum(visited);
+    if (lane_id() == 0 && t) atomicAdd(alg, (unsigned long long)t);
+  }
 }
 
-// Membership: one wave per key -- locate the leaf, decode it, compare.
+// Membership: one lane per key -- locate the leaf, scan it for [x, x + 1).
 __global__ void __launch_bounds__(256) k_contains(QueryArgs a, const uint64_t* __restrict__ keys,
                                                   uint8_t* __restrict__ out) {
-  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
-  const uint64_t wid = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  for (uint64_t i = wid; i < a.q; i += waves) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.q;
+       i += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t x = keys[i];
     const uint64_t leaf = locate_leaf(a.head, a.L, x);
-    uint32_t found = 0;
-    wave_decode_leaf(a.bytes + leaf * (uint64_t)a.S, a.used[leaf],
-                     [&](uint32_t, uint64_t y) { found |= (y == x); });
-    const uint64_t any = __ballot(found != 0);
-    if (lane_id() == 0) out[i] = any ? 1 : 0;
+    const LeafSum r = leaf_sum_range(a.bytes + leaf * (uint64_t)a.S, a.used[leaf], x, x + 1);
+    out[i] = r.count ? 1 : 0;
   }
 }
 

@@ -1,0 +1,108 @@
+// Lane-per-leaf decoders for range_map and contains.
+//
+// A range query is a search followed by a scan (Section "Packed Memory Array",
+// "Design and operations").  Leaves strictly inside a query's leaf span hold only
+// keys of the range, so they need a sum and a count but no comparisons; the two
+// end leaves (and a point query's single leaf) compare every key.
+//
+// Each lane decodes a whole leaf on its own.  All lanes of a wave walk their
+// leaves one byte per step from offset 0, so their 16-byte chunk loads happen
+// in the same step (coalesced in time, no divergent stalls), and no cross-lane
+// operation is needed.
+#pragma once
+#include "common.hpp"
+
+namespace cpma_dev {
+
+struct LeafSum {
+  uint64_t sum;    // wrapping sum of keys
+  uint64_t count;  // number of keys
+};
+
+__device__ __forceinline__ uint4 load16(const uint8_t* p) { return *reinterpret_cast<const uint4*>(p); }
+
+// Interior fast path: sum and count of every key of a leaf whose key span is
+// below 2^28 (so every delta code is at most 4 bytes and fits 32-bit shifts).
+//
+// Per byte: p = payload bits, the running chunk-relative delta Dc grows by
+// p << sh; at a terminator byte Dc equals (key - key at chunk start), so the
+// chunk's keys sum to cnt * base + sum of Dc at terminators.
+__device__ __forceinline__ LeafSum leaf_sum_fast(const uint8_t* __restrict__ leaf, uint32_t used,
+                                                 uint64_t head) {
+  LeafSum r{head, 1};
+  uint64_t base = head;  // key value at the start of the current chunk's running delta
+  uint32_t Dc = 0, sh = 0;
+  uint4 cur = load16(leaf);
+  for (uint32_t c = 0; c < used; c += 16) {
+    uint4 nxt = make_uint4(0, 0, 0, 0);
+    if (c + 16 < used) nxt = load16(leaf + c + 16);
+    const uint32_t words[4] = {cur.x, cur.y, cur.z, cur.w};
+    const uint32_t nvalid = min(16u, used - c);
+    uint32_t Sc = 0, cnt = 0;
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      const uint32_t w = words[i >> 2];
+      const int o = 8 * (i & 3);
+      const bool valid = (uint32_t)i < nvalid && !(c == 0 && i < 8);
+      const uint32_t p = valid ? ((w >> o) & 0x7fu) : 0u;
+      const bool term = valid && !((w >> (o + 7)) & 1u);
+      Dc += p << sh;
+      sh = term ? 0u : (valid ? sh + 7u : sh);
+      Sc += term ? Dc : 0u;
+      cnt += term ? 1u : 0u;
+    }
+    // keys of this chunk: cnt of them, each = base + (its Dc)
+    r.sum += (uint64_t)cnt * base + Sc;
+    r.count += cnt;
+    base += Dc;
+    Dc = 0;
+    cur = nxt;
+  }
+  return r;
+}
+
+// General path: 64-bit decode; counts and sums keys in [lo, hi).  Stops early
+// once a key reaches hi.
+__device__ __forceinline__ LeafSum leaf_sum_range(const uint8_t* __restrict__ leaf, uint32_t used,
+                                                  uint64_t lo, uint64_t hi) {
+  LeafSum r{0, 0};
+  if (used < 8) return r;
+  uint4 cur = load16(leaf);
+  uint64_t key = ((uint64_t)cur.y << 32) | cur.x;
+  if (key >= hi) return r;
+  if (key >= lo) {
+    r.sum += key;
+    r.count++;
+  }
+  uint64_t acc = 0;
+  uint32_t sh = 0;
+  bool done = false;
+  for (uint32_t c = 0; c < used && !done; c += 16) {
+    if (c) cur = load16(leaf + c);
+    const uint32_t words[4] = {cur.x, cur.y, cur.z, cur.w};
+    const uint32_t nvalid = min(16u, used - c);
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      const uint32_t b = (words[i >> 2] >> (8 * (i & 3))) & 0xffu;
+      const bool valid = (uint32_t)i < nvalid && !(c == 0 && i < 8) && !done;
+      if (valid) {
+        if (sh < 64) acc |= (uint64_t)(b & 0x7fu) << sh;
+        sh += 7;
+        if (!(b & 0x80u)) {
+          key += acc;
+          acc = 0;
+          sh = 0;
+          if (key >= hi) {
+            done = true;
+          } else if (key >= lo) {
+            r.sum += key;
+            r.count++;
+          }
+        }
+      }
+    }
+  }
+  return r;
+}
+
+}  // namespace cpma_dev

@@ -20,6 +20,8 @@ struct Counters {
   unsigned int nwin;                // windows selected for redistribution
   unsigned int root_viol;           // violation bits of the root
   unsigned int error;               // internal capacity overflow (bug guard)
+  unsigned int nspill;              // segments the wave merge hands to the lane merge
+  unsigned int pad0;
   unsigned long long alg_bytes;     // algorithmic HBM bytes of the merge (statistics)
   unsigned long long alg_bytes_q;   // algorithmic HBM bytes of range scans (statistics)
 };
@@ -106,6 +108,7 @@ struct MergeArgs {
   const uint32_t* seg_leaf;
   const uint32_t* seg_begin;
   uint32_t* heavy_list;
+  uint32_t* spill_list;   // segments routed from the wave merge to the lane merge
   Counters* ctr;
   uint32_t S;
   int is_insert;
@@ -131,7 +134,7 @@ __device__ __forceinline__ void wave_scan_inplace(uint32_t* F, uint32_t n) {
     const uint32_t v = i < n ? F[i] : 0u;
     const uint32_t incl = wave_incl_scan(v);
     if (i < n) F[i] = run + incl - v;
-    run += __shfl(incl, kWave - 1, kWave);
+    run += lane63_u32(incl);
   }
 }
 
