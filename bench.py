@@ -199,7 +199,7 @@ def main():
     roof = None
     if mg_l > 0 and mg_ms > 0:
         ach = (mg_b / mg_l) / ((mg_ms / mg_l) * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": "k_merge", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        roof = {"bound": "hbm", "kernel": "k_merge_wave" if S <= 1024 else "k_merge_lane", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": None,
                 "alg_bytes_per_launch": mg_b / mg_l, "avg_launch_ms": mg_ms / mg_l,
                 "dominant_phase": dominant}

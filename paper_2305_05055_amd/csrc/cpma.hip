@@ -93,8 +93,9 @@ struct cpma {
   int64_t q_up_leaf = 0, q_up_root = 0, q_lo_leaf = 0, q_lo_root = 0;
   DevBuf bytes, used, head;
   // scratch
-  DevBuf kin, kb0, kb1, kdedup, leafid, segpos, seg_leaf, seg_begin, heavy, spill, scan_tmp, ovf, arena,
-      stage, pyr, win, wargs, cnt, koff, win_id, welem, P, ncost, lstart, planU, plan_used,
+  DevBuf kin, kb0, kb1, kdedup, leafid, segpos, seg_leaf, seg_begin, seg_desc, heavy, spill, scan_tmp, ovf, arena,
+      stage, pyr, win, wargs, cnt, koff, win_id, welem, P, ccost, ncost, lstart, planU, plan_used,
+      spare_bytes, spare_used, spare_head,
       win_of_leaf, fail, qa, qb, qfirst, qnvis, qvoff, qsum, qcount, qout;
   Counters* dctr = nullptr;
   Counters* hctr = nullptr;
@@ -397,15 +398,19 @@ uint64_t pack_windows(cpma* s, const WinArgs& wa, uint64_t nsrc, hipStream_t st)
   K = s->hctr->root_sum;
   ensure(s->stage, std::max<uint64_t>(K, 1) * sizeof(uint64_t));
   ensure(s->win_id, std::max<uint64_t>(K, 1) * sizeof(uint32_t));
+  ensure(s->ccost, std::max<uint64_t>(K, 1));
   hipLaunchKernelGGL(k_win_pack, dim3(grid_for(nsrc, 1, 1u << 20)), dim3(kWave), 0, st, wa, sl, nsrc,
-                     (const uint64_t*)s->koff.as<uint64_t>(), s->stage.as<uint64_t>(), s->win_id.as<uint32_t>());
+                     (const uint64_t*)s->koff.as<uint64_t>(), s->stage.as<uint64_t>(), s->win_id.as<uint32_t>(),
+                     s->ccost.as<uint8_t>());
   HIPCHK(hipGetLastError());
   return K;
 }
 
 // Plans the even spread of the staged keys into the destination leaves and checks
 // it.  Returns per-window failure bits in `fails`.
-void plan_spread(cpma* s, const WinArgs& wa, uint64_t K, uint64_t ndst, const Bounds& dstb,
+// nsrc > 0: the staged keys come from pack_windows (fix the heads' chain costs);
+// nsrc == 0: the caller prepared the chain costs.
+void plan_spread(cpma* s, const WinArgs& wa, uint64_t nsrc, uint64_t K, uint64_t ndst, const Bounds& dstb,
                  uint32_t* plan_used, uint64_t Ldst, bool fresh, hipStream_t st, std::vector<uint32_t>& fails) {
   const uint32_t W = wa.W;
   ensure(s->welem, (W + 1) * sizeof(uint64_t));
@@ -417,12 +422,15 @@ void plan_spread(cpma* s, const WinArgs& wa, uint64_t K, uint64_t ndst, const Bo
   hipLaunchKernelGGL(k_win_elems, dim3(grid_for(W + 1, 256)), dim3(256), 0, st, wa,
                      (const uint64_t*)s->koff.as<uint64_t>(), s->welem.as<uint64_t>(), s->fail.as<uint32_t>());
   HIPCHK(hipGetLastError());
-  scan<uint64_t>(s, s->P.as<uint64_t>(), K, st,
-                 CostFn{s->stage.as<uint64_t>(), s->win_id.as<uint32_t>(), s->welem.as<uint64_t>()});
+  if (nsrc > 0)
+    hipLaunchKernelGGL(k_head_costs, dim3(grid_for(nsrc, 256, 1u << 16)), dim3(256), 0, st, wa, nsrc,
+                       (const uint64_t*)s->koff.as<uint64_t>(), (const uint64_t*)s->welem.as<uint64_t>(),
+                       (const uint64_t*)s->stage.as<uint64_t>(), s->ccost.as<uint8_t>());
+  scan<uint64_t>(s, s->P.as<uint64_t>(), K, st, U8Fn{s->ccost.as<uint8_t>()});
   hipLaunchKernelGGL((k_fill<uint64_t>), dim3(grid_for(ndst + 1, 256, 4096)), dim3(256), 0, st,
                      s->lstart.as<uint64_t>(), ndst + 1, ~0ull);
   hipLaunchKernelGGL(k_assign, dim3(grid_for(K, 256, 1u << 16)), dim3(256), 0, st, wa, K,
-                     (const uint64_t*)s->stage.as<uint64_t>(), (const uint32_t*)s->win_id.as<uint32_t>(),
+                     (const uint8_t*)s->ccost.as<uint8_t>(), (const uint32_t*)s->win_id.as<uint32_t>(),
                      (const uint64_t*)s->welem.as<uint64_t>(), (const uint64_t*)s->P.as<uint64_t>(),
                      s->ncost.as<uint8_t>(), s->lstart.as<uint64_t>(), s->fail.as<uint32_t>());
   HIPCHK(hipGetLastError());
@@ -490,7 +498,7 @@ bool redistribute(cpma* s, std::vector<Win> wins, hipStream_t st) {
     ensure(s->plan_used, s->L * sizeof(uint32_t));
     HIPCHK(hipMemcpyAsync(s->plan_used.p, s->used.p, s->L * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
     std::vector<uint32_t> fails;
-    plan_spread(s, wa, K, ndst, s->bounds(s->L), s->plan_used.as<uint32_t>(), s->L, false, st, fails);
+    plan_spread(s, wa, nsrc, K, ndst, s->bounds(s->L), s->plan_used.as<uint32_t>(), s->L, false, st, fails);
     bool any = false;
     for (uint32_t f : fails) any |= (f != 0);
     if (!any) {
@@ -507,32 +515,44 @@ bool redistribute(cpma* s, std::vector<Win> wins, hipStream_t st) {
   throw Fail{CPMA_ERR_DEVICE};
 }
 
-// Spreads the K staged keys (sorted, window 0 = all) evenly over a fresh array of
-// Lt leaves; adjusts Lt by the growing factor until every node is within bounds,
-// then replaces the structure.
-void spread_fresh(cpma* s, uint64_t K, uint64_t Lt, hipStream_t st) {
+// The spare leaf arrays become the structure (the old ones become the spares,
+// so repeated resizes reuse memory instead of freeing and allocating it).
+void swap_in_spare(cpma* s, uint64_t Lt) {
+  std::swap(s->bytes, s->spare_bytes);
+  std::swap(s->used, s->spare_used);
+  std::swap(s->head, s->spare_head);
+  s->L = Lt;
+}
+
+// Spreads the K staged keys (sorted, one window) evenly over a fresh array of Lt
+// leaves; adjusts Lt by the growing factor until every node is within bounds,
+// then replaces the structure.  costs_ready: s->ccost already holds the chain
+// costs of the staged keys.
+void spread_fresh(cpma* s, uint64_t K, uint64_t Lt, hipStream_t st, bool costs_ready = false) {
   if (K == 0) {
-    DevBuf nb, nu, nh;
-    ensure(nb, s->S);
-    ensure(nu, 4);
-    ensure(nh, 8);
-    HIPCHK(hipMemsetAsync(nb.p, 0, s->S, st));
-    HIPCHK(hipMemsetAsync(nu.p, 0, 4, st));
-    HIPCHK(hipMemsetAsync(nh.p, 0xff, 8, st));
+    ensure(s->spare_bytes, s->S);
+    ensure(s->spare_used, 4);
+    ensure(s->spare_head, 8);
+    hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(256), 0, st, s->spare_bytes.as<uint32_t>(),
+                       (uint64_t)(s->S / 4), 0u);
+    hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, s->spare_used.as<uint32_t>(), (uint64_t)1, 0u);
+    hipLaunchKernelGGL((k_fill<uint64_t>), dim3(1), dim3(64), 0, st, s->spare_head.as<uint64_t>(), (uint64_t)1,
+                       kNoKey);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
-    release(s->bytes);
-    release(s->used);
-    release(s->head);
-    s->bytes = nb;
-    s->used = nu;
-    s->head = nh;
-    s->L = 1;
+    swap_in_spare(s, 1);
     return;
   }
   const double g = s->cfg.grow;
   ensure(s->win_id, K * sizeof(uint32_t));
   hipLaunchKernelGGL((k_fill<uint32_t>), dim3(grid_for(K, 256, 4096)), dim3(256), 0, st, s->win_id.as<uint32_t>(),
                      K, 0u);
+  if (!costs_ready) {
+    ensure(s->ccost, K);
+    hipLaunchKernelGGL(k_chain_costs, dim3(grid_for(K, 256, 1u << 16)), dim3(256), 0, st,
+                       (const uint64_t*)s->stage.as<uint64_t>(), K, s->ccost.as<uint8_t>());
+    HIPCHK(hipGetLastError());
+  }
   // One window over all staged keys: its source is one flat entry, so the
   // window's key range comes from koff = {0, K}.
   ensure(s->koff, 2 * sizeof(uint64_t));
@@ -547,26 +567,18 @@ void spread_fresh(cpma* s, uint64_t K, uint64_t Lt, hipStream_t st) {
     std::vector<uint64_t> sb{0}, sn{1}, db{0}, dn{Lt};
     std::vector<uint32_t> lv{(uint32_t)(tree_height(Lt) + 1)};
     WinArgs wa = upload_windows(s, sb, sn, db, dn, lv, st, nsrc, ndst);
-    DevBuf nb, nu, nh;
-    ensure(nu, Lt * sizeof(uint32_t));
+    ensure(s->spare_used, Lt * sizeof(uint32_t));
     std::vector<uint32_t> fails;
-    plan_spread(s, wa, K, ndst, s->bounds(Lt), nu.as<uint32_t>(), Lt, true, st, fails);
+    plan_spread(s, wa, 0, K, ndst, s->bounds(Lt), s->spare_used.as<uint32_t>(), Lt, true, st, fails);
     if (fails[0] == 0) {
-      ensure(nb, Lt * (uint64_t)s->S);
-      ensure(nh, Lt * sizeof(uint64_t));
-      encode_spread(s, wa, ndst, nb.as<uint8_t>(), nu.as<uint32_t>(), nh.as<uint64_t>(), st);
+      ensure(s->spare_bytes, Lt * (uint64_t)s->S);
+      ensure(s->spare_head, Lt * sizeof(uint64_t));
+      encode_spread(s, wa, ndst, s->spare_bytes.as<uint8_t>(), s->spare_used.as<uint32_t>(),
+                    s->spare_head.as<uint64_t>(), st);
       HIPCHK(hipStreamSynchronize(st));
-      release(s->bytes);
-      release(s->used);
-      release(s->head);
-      s->bytes = nb;
-      s->used = nu;
-      s->head = nh;
-      s->L = Lt;
-      release(s->ovf);
+      swap_in_spare(s, Lt);
       return;
     }
-    release(nu);
     int dir = (fails[0] & 1u) ? +1 : -1;
     if (dir == -1 && Lt == 1) throw Fail{CPMA_ERR_DEVICE};
     if (last_dir != 0 && dir != last_dir) {
@@ -651,6 +663,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   ensure(s->leafid, kbound * sizeof(uint32_t));
   ensure(s->seg_leaf, kbound * sizeof(uint32_t));
   ensure(s->seg_begin, (kbound + 1) * sizeof(uint32_t));
+  ensure(s->seg_desc, (kbound + 1) * sizeof(uint4));
   ensure(s->heavy, kbound * sizeof(uint32_t));
   ensure(s->spill, kbound * sizeof(uint32_t));
   ensure(s->ovf, std::max<uint64_t>(s->L, 1) * sizeof(uint64_t));
@@ -668,7 +681,8 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   hipLaunchKernelGGL(k_segments, dim3(grid_for(kbound, 256, 1u << 16)), dim3(256), 0, st,
                      (const uint32_t*)s->leafid.as<uint32_t>(), (const unsigned long long*)&s->dctr->kprime,
                      (const uint32_t*)s->segpos.as<uint32_t>(), kbound, s->seg_leaf.as<uint32_t>(),
-                     s->seg_begin.as<uint32_t>(), s->dctr);
+                     s->seg_begin.as<uint32_t>(), s->seg_desc.as<uint4>(), (const uint32_t*)s->used.as<uint32_t>(),
+                     s->dctr);
   HIPCHK(hipGetLastError());
   phase_end(s, pl, st, 24ull * kbound);
   MergeArgs a;
@@ -683,6 +697,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   a.B = B;
   a.seg_leaf = s->seg_leaf.as<uint32_t>();
   a.seg_begin = s->seg_begin.as<uint32_t>();
+  a.seg_desc = s->seg_desc.as<uint4>();
   a.heavy_list = s->heavy.as<uint32_t>();
   a.spill_list = s->spill.as<uint32_t>();
   a.ctr = s->dctr;
@@ -820,24 +835,18 @@ cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpm
     uint64_t Lt = 1;
     if (K > 0) {
       // Total bytes of the keys as one delta chain: the head plus every delta code.
-      ensure(s->win_id, K * sizeof(uint32_t));
-      hipLaunchKernelGGL((k_fill<uint32_t>), dim3(grid_for(K, 256, 4096)), dim3(256), 0, st,
-                         s->win_id.as<uint32_t>(), K, 0u);
-      ensure(s->welem, 2 * sizeof(uint64_t));
-      uint64_t* kk = reinterpret_cast<uint64_t*>(host_pin(s, 16));
-      kk[0] = 0;
-      kk[1] = K;
-      HIPCHK(hipMemcpyAsync(s->welem.p, kk, 16, hipMemcpyHostToDevice, st));
+      ensure(s->ccost, K);
+      hipLaunchKernelGGL(k_chain_costs, dim3(grid_for(K, 256, 1u << 16)), dim3(256), 0, st,
+                         (const uint64_t*)s->stage.as<uint64_t>(), K, s->ccost.as<uint8_t>());
+      HIPCHK(hipGetLastError());
       ensure(s->P, (K + 1) * sizeof(uint64_t));
-      scan<uint64_t>(s, s->P.as<uint64_t>(), K, st,
-                     CostFn{s->stage.as<uint64_t>(), s->win_id.as<uint32_t>(), s->welem.as<uint64_t>()});
-      uint64_t tot = 0;
+      scan<uint64_t>(s, s->P.as<uint64_t>(), K, st, U8Fn{s->ccost.as<uint8_t>()});
       HIPCHK(hipMemcpyAsync(&s->hctr->root_sum, s->P.as<uint64_t>() + K, 8, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
-      tot = s->hctr->root_sum;
+      const uint64_t tot = s->hctr->root_sum;
       Lt = std::max<uint64_t>(1, (uint64_t)std::ceil((double)tot / (cfg.build_density * (double)s->S)));
     }
-    spread_fresh(s, K, Lt, st);
+    spread_fresh(s, K, Lt, st, K > 0);
     rebalance(s, st);
   });
   if (r != CPMA_OK) {
@@ -1045,9 +1054,9 @@ void cpma_destroy(cpma* s) {
   for (hipEvent_t e : s->evpool) hipEventDestroy(e);
   if (s->dqalg) hipFree(s->dqalg);
   DevBuf* bufs[] = {&s->bytes,  &s->used,     &s->head,      &s->kin,       &s->kb0,   &s->kb1,    &s->kdedup,
-                    &s->leafid, &s->segpos,   &s->seg_leaf,  &s->seg_begin, &s->heavy, &s->spill, &s->scan_tmp,
+                    &s->leafid, &s->segpos,   &s->seg_leaf,  &s->seg_begin, &s->seg_desc, &s->heavy, &s->spill, &s->scan_tmp,
                     &s->ovf,    &s->arena,    &s->stage,     &s->pyr,       &s->win,   &s->wargs,  &s->cnt,
-                    &s->koff,   &s->win_id,   &s->welem,     &s->P,         &s->ncost, &s->lstart, &s->planU,
+                    &s->koff,   &s->win_id,   &s->welem,     &s->P,         &s->ccost, &s->ncost, &s->spare_bytes, &s->spare_used, &s->spare_head, &s->lstart, &s->planU,
                     &s->plan_used, &s->win_of_leaf, &s->fail, &s->qa,        &s->qb,    &s->qfirst, &s->qnvis,
                     &s->qvoff,  &s->qsum,     &s->qcount,    &s->qout};
   for (DevBuf* b : bufs) release(*b);

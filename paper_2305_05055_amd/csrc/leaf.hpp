@@ -63,7 +63,8 @@ __device__ __forceinline__ void lane_parse(const uint4 w, uint32_t pos0, uint32_
 }
 
 // Decodes the leaf at src (16-byte aligned, `used` valid bytes) with one wave and
-// calls emit(index, key) for every key in order.  Returns the key count (uniform).
+// calls emit(index, key, delta) for every key in order (the head's delta is the
+// head itself).  Returns the key count (uniform).
 template <class Emit>
 __device__ __forceinline__ uint32_t wave_decode_leaf(const uint8_t* __restrict__ src, uint32_t used,
                                                      Emit&& emit) {
@@ -93,13 +94,16 @@ __device__ __forceinline__ uint32_t wave_decode_leaf(const uint8_t* __restrict__
     const uint32_t lcnt = (uint32_t)__popc(c.tmask);
     const uint64_t incl_sum = wave_incl_scan(lsum);
     const uint32_t incl_cnt = wave_incl_scan(lcnt);
-    uint64_t key = run_key + (incl_sum - lsum) + corr;
+    uint64_t key = run_key + (incl_sum - lsum);
+    uint64_t pend = corr;  // the carry fix belongs to the lane's first code
     uint32_t idx = run_cnt + (incl_cnt - lcnt);
 #pragma unroll
     for (int i = 0; i < 16; i++) {
       if (c.tmask & (1u << i)) {
-        key += c.v[i];
-        emit(idx, key);
+        const uint64_t d = c.v[i] + pend;
+        pend = 0;
+        key += d;
+        emit(idx, key, d);
         idx++;
       }
     }
@@ -109,6 +113,43 @@ __device__ __forceinline__ uint32_t wave_decode_leaf(const uint8_t* __restrict__
     carry_sh = lane63_u32(c.tail_sh);
   }
   return run_cnt;
+}
+
+// Single-chunk variant (leaf size <= 1024): the caller has already loaded the
+// lane's 16 bytes w (zeros past `used`).
+template <class Emit>
+__device__ __forceinline__ uint32_t wave_decode_regs(const uint4 w, uint32_t used, Emit&& emit) {
+  const int lane = lane_id();
+  const uint32_t pos0 = 16u * lane;
+  LaneCodes c;
+  lane_parse(w, pos0, used, c);
+  uint64_t cin_acc = dpp_prev64(c.tail_acc);
+  uint32_t cin_sh = dpp_prev32(c.tail_sh);
+  uint64_t corr = 0;
+  if (c.tmask != 0 && pos0 != 0) {
+    const uint64_t fixed = cin_acc | (cin_sh < 64 ? (c.first_raw << cin_sh) : 0ull);
+    corr = fixed - c.first_raw;
+  }
+  uint64_t lsum = corr;
+#pragma unroll
+  for (int i = 0; i < 16; i++) lsum += c.v[i];
+  const uint32_t lcnt = (uint32_t)__popc(c.tmask);
+  const uint64_t incl_sum = wave_incl_scan(lsum);
+  const uint32_t incl_cnt = wave_incl_scan(lcnt);
+  uint64_t key = incl_sum - lsum;
+  uint64_t pend = corr;
+  uint32_t idx = incl_cnt - lcnt;
+#pragma unroll
+  for (int i = 0; i < 16; i++) {
+    if (c.tmask & (1u << i)) {
+      const uint64_t d = c.v[i] + pend;
+      pend = 0;
+      key += d;
+      emit(idx, key, d);
+      idx++;
+    }
+  }
+  return lane63_u32(incl_cnt);
 }
 
 // Number of keys in a leaf image: the head plus one per byte with a clear high bit.

@@ -35,19 +35,49 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
   const int lane = lane_id();
   const uint32_t S = a.S;
   const uint64_t T = a.ctr->T;
+  const uint32_t pos0 = 16u * lane;
   unsigned long long delta = 0, alg = 0;
-  for (uint64_t s = blockIdx.x; s < T; s += gridDim.x) {
-    const uint64_t leaf = a.seg_leaf[s];
-    const uint32_t b = a.seg_begin[s], e = a.seg_begin[s + 1];
+  // Software pipeline: the next segment's descriptor, leaf bytes and batch keys
+  // are loaded while the current one is merged.
+  uint4 d_cur = make_uint4(0, 0, 0, 0), d_nxt = d_cur;
+  uint32_t e_cur = 0, e_nxt = 0;
+  uint4 w_cur = make_uint4(0, 0, 0, 0), w_nxt = w_cur;
+  uint64_t b_cur = 0, b_nxt = 0;
+  uint64_t s = blockIdx.x;
+  if (s < T) {
+    d_cur = a.seg_desc[s];
+    e_cur = a.seg_begin[s + 1];
+    if (pos0 < d_cur.z) w_cur = *reinterpret_cast<const uint4*>(a.bytes + (uint64_t)d_cur.x * S + pos0);
+    if ((uint32_t)lane < e_cur - d_cur.y) b_cur = a.B[d_cur.y + lane];
+  }
+  for (; s < T; s += gridDim.x) {
+    const uint64_t sn = s + gridDim.x;
+    if (sn < T) {
+      d_nxt = a.seg_desc[sn];
+      e_nxt = a.seg_begin[sn + 1];
+    }
+    const uint64_t leaf = d_cur.x;
+    const uint32_t b = d_cur.y, e = e_cur;
     const uint32_t nb = e - b;
+    const uint32_t used0 = d_cur.z;
+    const uint4 w = w_cur;
+    const uint64_t bj0 = b_cur;
+    if (sn < T) {
+      w_nxt = make_uint4(0, 0, 0, 0);
+      if (pos0 < d_nxt.z) w_nxt = *reinterpret_cast<const uint4*>(a.bytes + (uint64_t)d_nxt.x * S + pos0);
+      b_nxt = ((uint32_t)lane < e_nxt - d_nxt.y) ? a.B[d_nxt.y + lane] : 0;
+    }
+    d_cur = d_nxt;
+    e_cur = e_nxt;
+    w_cur = w_nxt;
+    b_cur = b_nxt;
     if (a.is_insert && nb > kWaveSlice) {
       if (lane == 0) a.spill_list[atomicAdd(&a.ctr->nspill, 1u)] = (uint32_t)s;
       continue;
     }
     const uint64_t* Bg = a.B + b;
     uint8_t* lp = a.bytes + leaf * (uint64_t)S;
-    const uint32_t used0 = a.used[leaf];
-    const uint32_t nA = wave_decode_leaf(lp, used0, [&](uint32_t i, uint64_t x) { K[i] = x; });
+    const uint32_t nA = wave_decode_regs(w, used0, [&](uint32_t i, uint64_t x, uint64_t) { K[i] = x; });
     wave_zero(out, S);
     // lane-contiguous block of old-key indices [i0, i1) over [0, nA] (index nA: trailing group)
     const uint32_t m = (nA + 1 + kWave - 1) / kWave;
@@ -59,7 +89,7 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
     bool to_arena = false;
     if (a.is_insert) {
       const bool has_b = (uint32_t)lane < nb;
-      const uint64_t bj = has_b ? Bg[lane] : 0;
+      const uint64_t bj = has_b ? bj0 : 0;
       if (has_b) Bs[lane] = bj;
       for (uint32_t i = lane; i <= nA; i += kWave) G[i] = 0xffu;
       __syncthreads();

@@ -26,37 +26,54 @@ __device__ __forceinline__ uint4 load16(const uint8_t* p) { return *reinterpret_
 //
 // Per byte: p = payload bits, the running chunk-relative delta Dc grows by
 // p << sh; at a terminator byte Dc equals (key - key at chunk start), so the
-// chunk's keys sum to cnt * base + sum of Dc at terminators.
+// chunk's keys sum to cnt * base + sum of Dc at terminators.  The leaf streams
+// in 64-byte rounds with the next round's four loads in flight.
+__device__ __forceinline__ void fast_chunk(const uint4 q, uint32_t c, uint32_t used, uint64_t& base, uint32_t& sh,
+                                           LeafSum& r) {
+  const uint32_t words[4] = {q.x, q.y, q.z, q.w};
+  const uint32_t nvalid = c < used ? min(16u, used - c) : 0u;
+  uint32_t Dc = 0, Sc = 0, cnt = 0;
+#pragma unroll
+  for (int i = 0; i < 16; i++) {
+    const uint32_t w = words[i >> 2];
+    const int o = 8 * (i & 3);
+    const bool valid = (uint32_t)i < nvalid && !(c == 0 && i < 8);
+    const uint32_t p = valid ? ((w >> o) & 0x7fu) : 0u;
+    const bool term = valid && !((w >> (o + 7)) & 1u);
+    Dc += p << sh;
+    sh = term ? 0u : (valid ? sh + 7u : sh);
+    Sc += term ? Dc : 0u;
+    cnt += term ? 1u : 0u;
+  }
+  r.sum += (uint64_t)cnt * base + Sc;
+  r.count += cnt;
+  base += Dc;
+}
+
 __device__ __forceinline__ LeafSum leaf_sum_fast(const uint8_t* __restrict__ leaf, uint32_t used,
                                                  uint64_t head) {
   LeafSum r{head, 1};
-  uint64_t base = head;  // key value at the start of the current chunk's running delta
-  uint32_t Dc = 0, sh = 0;
-  uint4 cur = load16(leaf);
-  for (uint32_t c = 0; c < used; c += 16) {
-    uint4 nxt = make_uint4(0, 0, 0, 0);
-    if (c + 16 < used) nxt = load16(leaf + c + 16);
-    const uint32_t words[4] = {cur.x, cur.y, cur.z, cur.w};
-    const uint32_t nvalid = min(16u, used - c);
-    uint32_t Sc = 0, cnt = 0;
-#pragma unroll
-    for (int i = 0; i < 16; i++) {
-      const uint32_t w = words[i >> 2];
-      const int o = 8 * (i & 3);
-      const bool valid = (uint32_t)i < nvalid && !(c == 0 && i < 8);
-      const uint32_t p = valid ? ((w >> o) & 0x7fu) : 0u;
-      const bool term = valid && !((w >> (o + 7)) & 1u);
-      Dc += p << sh;
-      sh = term ? 0u : (valid ? sh + 7u : sh);
-      Sc += term ? Dc : 0u;
-      cnt += term ? 1u : 0u;
-    }
-    // keys of this chunk: cnt of them, each = base + (its Dc)
-    r.sum += (uint64_t)cnt * base + Sc;
-    r.count += cnt;
-    base += Dc;
-    Dc = 0;
-    cur = nxt;
+  uint64_t base = head;  // key value reached by the running delta so far
+  uint32_t sh = 0;
+  const uint4 z = make_uint4(0, 0, 0, 0);
+  uint4 a0 = load16(leaf);
+  uint4 a1 = 16 < used ? load16(leaf + 16) : z;
+  uint4 a2 = 32 < used ? load16(leaf + 32) : z;
+  uint4 a3 = 48 < used ? load16(leaf + 48) : z;
+  for (uint32_t c = 0; c < used; c += 64) {
+    uint4 b0 = z, b1 = z, b2 = z, b3 = z;
+    if (c + 64 < used) b0 = load16(leaf + c + 64);
+    if (c + 80 < used) b1 = load16(leaf + c + 80);
+    if (c + 96 < used) b2 = load16(leaf + c + 96);
+    if (c + 112 < used) b3 = load16(leaf + c + 112);
+    fast_chunk(a0, c, used, base, sh, r);
+    fast_chunk(a1, c + 16, used, base, sh, r);
+    fast_chunk(a2, c + 32, used, base, sh, r);
+    fast_chunk(a3, c + 48, used, base, sh, r);
+    a0 = b0;
+    a1 = b1;
+    a2 = b2;
+    a3 = b3;
   }
   return r;
 }

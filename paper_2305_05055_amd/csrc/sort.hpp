@@ -22,6 +22,7 @@ struct BatchInfo {
 
 __global__ void __launch_bounds__(256) k_validate(const uint64_t* __restrict__ keys, uint64_t k,
                                                   BatchInfo* info) {
+  __shared__ uint64_t red[4];
   uint64_t orv = 0;
   uint32_t res = 0, uns = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
@@ -32,11 +33,18 @@ __global__ void __launch_bounds__(256) k_validate(const uint64_t* __restrict__ k
     if (i + 1 < k && keys[i + 1] < x) uns = 1;
   }
   orv = wave_or(orv);
-  uint64_t flags = wave_or((uint64_t)(res | (uns << 1)));
-  if (lane_id() == 0) {
-    if (orv) atomicOr(&info->or_all, (unsigned long long)orv);
-    if (flags & 1) atomicOr(&info->has_reserved, 1u);
-    if (flags & 2) atomicOr(&info->unsorted, 1u);
+  const uint64_t flags = wave_or((uint64_t)(res | (uns << 1)));
+  const int wid = threadIdx.x / kWave;
+  if (lane_id() == 0) red[wid] = orv;
+  __shared__ uint32_t fl[4];
+  if (lane_id() == 0) fl[wid] = (uint32_t)flags;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint64_t o = red[0] | red[1] | red[2] | red[3];
+    const uint32_t f = fl[0] | fl[1] | fl[2] | fl[3];
+    if (o) atomicOr(&info->or_all, (unsigned long long)o);
+    if (f & 1) atomicOr(&info->has_reserved, 1u);
+    if (f & 2) atomicOr(&info->unsorted, 1u);
   }
 }
 

@@ -78,13 +78,16 @@ struct SegFlag {
 __global__ void k_segments(const uint32_t* __restrict__ leafid, const unsigned long long* kprime,
                            const uint32_t* __restrict__ segpos, uint64_t kbound,
                            uint32_t* __restrict__ seg_leaf, uint32_t* __restrict__ seg_begin,
+                           uint4* __restrict__ seg_desc, const uint32_t* __restrict__ used,
                            Counters* ctr) {
   const uint64_t k = *kprime;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
        i += (uint64_t)gridDim.x * blockDim.x) {
     if (i == 0 || leafid[i] != leafid[i - 1]) {
-      seg_leaf[segpos[i]] = leafid[i];
+      const uint32_t lf = leafid[i];
+      seg_leaf[segpos[i]] = lf;
       seg_begin[segpos[i]] = (uint32_t)i;
+      seg_desc[segpos[i]] = make_uint4(lf, (uint32_t)i, used[lf], 0u);
     }
     if (i == 0) {
       uint32_t T = segpos[kbound];
@@ -107,6 +110,7 @@ struct MergeArgs {
   const uint64_t* B;      // sorted, repeat-free batch
   const uint32_t* seg_leaf;
   const uint32_t* seg_begin;
+  const uint4* seg_desc;  // {leaf, slice begin, used before the merge, 0}
   uint32_t* heavy_list;
   uint32_t* spill_list;   // segments routed from the wave merge to the lane merge
   Counters* ctr;
@@ -207,7 +211,7 @@ __global__ void __launch_bounds__(kWave) k_merge_heavy(MergeArgs a) {
     const uint64_t* Bs = a.B + b;
     const uint8_t* src = a.bytes + leaf * (uint64_t)S;
     const uint32_t used0 = a.used[leaf];
-    const uint32_t nA = wave_decode_leaf(src, used0, [&](uint32_t i, uint64_t x) { A[i] = x; });
+    const uint32_t nA = wave_decode_leaf(src, used0, [&](uint32_t i, uint64_t x, uint64_t) { A[i] = x; });
     for (uint32_t i = lane; i <= nA; i += kWave) F[i] = 0;
     __syncthreads();
     for (uint32_t j = lane; j < nb; j += kWave) {
@@ -375,22 +379,54 @@ __global__ void __launch_bounds__(kWave) k_win_count(WinArgs wa, SrcLeaves src, 
   }
 }
 
+// Also records every staged key's byte cost in the old delta chain: its code
+// length, 8 for a leaf head (fixed up by k_head_costs when the head is not the
+// first key of its window).
 __global__ void __launch_bounds__(kWave) k_win_pack(WinArgs wa, SrcLeaves src, uint64_t nflat,
                                                     const uint64_t* __restrict__ koff,
                                                     uint64_t* __restrict__ stage,
-                                                    uint32_t* __restrict__ win_id) {
+                                                    uint32_t* __restrict__ win_id,
+                                                    uint8_t* __restrict__ ccost) {
   for (uint64_t f = blockIdx.x; f < nflat; f += gridDim.x) {
     const uint32_t w = find_window(wa.src_flat, wa.W, f);
     const uint64_t leaf = wa.src_begin[w] + (f - wa.src_flat[w]);
     const uint32_t u = src.used[leaf];
     uint64_t* out = stage + koff[f];
     uint32_t* wid = win_id + koff[f];
-    wave_decode_leaf(src.ptr(leaf, u), u, [&](uint32_t i, uint64_t x) {
+    uint8_t* cc = ccost + koff[f];
+    wave_decode_leaf(src.ptr(leaf, u), u, [&](uint32_t i, uint64_t x, uint64_t d) {
       out[i] = x;
       wid[i] = w;
+      cc[i] = i == 0 ? (uint8_t)8 : (uint8_t)vlen(d);
     });
   }
 }
+
+// Head of a non-first source leaf: its chain cost is the code of its distance
+// to the previous staged key.
+__global__ void k_head_costs(WinArgs wa, uint64_t nflat, const uint64_t* __restrict__ koff,
+                             const uint64_t* __restrict__ welem, const uint64_t* __restrict__ x,
+                             uint8_t* __restrict__ ccost) {
+  for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nflat;
+       f += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t e = koff[f];
+    if (koff[f + 1] == e) continue;
+    const uint32_t w = find_window(wa.src_flat, wa.W, f);
+    if (e != welem[w]) ccost[e] = (uint8_t)vlen(x[e] - x[e - 1]);
+  }
+}
+
+// Chain costs of a sorted key array that forms a single window.
+__global__ void k_chain_costs(const uint64_t* __restrict__ x, uint64_t K, uint8_t* __restrict__ ccost) {
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < K;
+       e += (uint64_t)gridDim.x * blockDim.x)
+    ccost[e] = e == 0 ? (uint8_t)8 : (uint8_t)vlen(x[e] - x[e - 1]);
+}
+
+struct U8Fn {
+  const uint8_t* p;
+  __device__ uint64_t operator()(uint64_t i) const { return p[i]; }
+};
 
 // welem[w] = first staged key of window w (W + 1 entries).
 __global__ void k_win_elems(WinArgs wa, const uint64_t* __restrict__ koff, uint64_t* __restrict__ welem,
@@ -401,21 +437,11 @@ __global__ void k_win_elems(WinArgs wa, const uint64_t* __restrict__ koff, uint6
   }
 }
 
-// Byte cost of key e within its window: 8 for the window's first key, else the
-// length of its delta code.
-struct CostFn {
-  const uint64_t* x;
-  const uint32_t* win_id;
-  const uint64_t* welem;
-  __device__ uint64_t operator()(uint64_t e) const {
-    return e == welem[win_id[e]] ? 8ull : (uint64_t)vlen(x[e] - x[e - 1]);
-  }
-};
-
 // Even split by bytes: key e goes to destination leaf j = floor(P_e * n / total),
-// where P_e is the window's byte prefix before e.  A key that starts a leaf becomes
-// its head (8 bytes).  Gaps (empty leaves) fail the window.
-__global__ void k_assign(WinArgs wa, uint64_t K, const uint64_t* __restrict__ x,
+// where P_e is the window's byte prefix before e (chain costs).  A key that
+// starts a leaf becomes its head (8 bytes); the others keep their code.  Gaps
+// (empty leaves) fail the window.
+__global__ void k_assign(WinArgs wa, uint64_t K, const uint8_t* __restrict__ ccost,
                          const uint32_t* __restrict__ win_id, const uint64_t* __restrict__ welem,
                          const uint64_t* __restrict__ P, uint8_t* __restrict__ ncost,
                          uint64_t* __restrict__ lstart, uint32_t* __restrict__ fail) {
@@ -424,16 +450,18 @@ __global__ void k_assign(WinArgs wa, uint64_t K, const uint64_t* __restrict__ x,
     const uint32_t w = win_id[e];
     const uint64_t first = welem[w], end = welem[w + 1];
     const uint64_t n = wa.dst_n[w];
-    const uint64_t tot = P[end] - P[first];
-    const uint64_t j = ((P[e] - P[first]) * n) / tot;
+    const uint64_t p0 = P[first];
+    const uint64_t tot = P[end] - p0;
+    const uint64_t pe = P[e] - p0;
+    const uint64_t j = (pe * n) / tot;
     bool head = (e == first);
     if (!head) {
-      const uint64_t jp = ((P[e - 1] - P[first]) * n) / tot;
+      const uint64_t jp = ((pe - ccost[e - 1]) * n) / tot;
       head = j != jp;
       if (j > jp + 1) atomicOr(&fail[w], 2u);
     }
     if (e + 1 == end && j != n - 1) atomicOr(&fail[w], 2u);
-    ncost[e] = head ? 8 : (uint8_t)vlen(x[e] - x[e - 1]);
+    ncost[e] = head ? (uint8_t)8 : ccost[e];
     if (head) lstart[wa.dst_flat[w] + j] = e;
   }
 }
