@@ -160,6 +160,28 @@ cpma_status cpma_export(const cpma* set, uint8_t* bytes, uint32_t* used,
                         uint64_t* head, void* stream);
 
 /*
+ * F-Graph (Section "Evaluation on graph workloads"): the set holds a graph's
+ * edges as keys u<<32 | v.  Vertex ids must be < nv; edge keys with a larger
+ * source or destination are ignored.  Both calls need leaf_bytes <= 1024
+ * (CPMA_ERR_INVALID otherwise) and synchronise `stream`.
+ *
+ * cpma_fgraph_bfs: level[v] = hop distance from `source` (UINT32_MAX when
+ * unreachable), following edges u -> v.  level is nv entries in memory space
+ * `mem`.  The result is unique; the traversal is level-synchronous.
+ *
+ * cpma_fgraph_pagerank: `iters` rounds (the paper runs 10) of
+ *   p'(v) = (1 - damping) / nv + damping * sum over edges (v, u) of p(u) / deg(u)
+ * from p = 1/nv, with deg(u) the number of edges leaving u and FP32 arithmetic
+ * and accumulation.  The edge set must be symmetric (an undirected graph, as
+ * in the paper's F-Graph); then this equals pushing p(u)/deg(u) along every
+ * edge u -> v.  p is nv floats in memory space `mem`.
+ */
+cpma_status cpma_fgraph_bfs(const cpma* set, uint32_t nv, uint32_t source, cpma_mem mem,
+                            uint32_t* level, void* stream);
+cpma_status cpma_fgraph_pagerank(const cpma* set, uint32_t nv, int iters, double damping,
+                                 cpma_mem mem, float* p, void* stream);
+
+/*
  * Phase statistics (instrumentation, not part of the paper's API).  While
  * enabled, every call records HIP events around its phases on the call's stream
  * and accumulates, per phase, the number of timed launches, their total device

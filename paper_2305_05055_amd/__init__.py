@@ -69,6 +69,9 @@ def lib():
         L.cpma_export.argtypes = [vp, vp, vp, vp, vp]
         L.cpma_destroy.argtypes = [vp]
         L.cpma_destroy.restype = None
+        L.cpma_fgraph_bfs.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, vp, vp]
+        L.cpma_fgraph_pagerank.argtypes = [vp, ctypes.c_uint32, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_int, vp, vp]
         L.cpma_stats_enable.argtypes = [vp, ctypes.c_int]
         L.cpma_stats_get.argtypes = [vp, ctypes.POINTER(PhaseStat), ctypes.c_int]
         L.cpma_status_str.argtypes = [ctypes.c_int]
@@ -207,6 +210,33 @@ class CPMA:
         S = ctypes.c_uint32(0)
         _check(lib().cpma_geometry(self._h, ctypes.byref(L), ctypes.byref(S)), "cpma_geometry")
         return int(L.value), int(S.value)
+
+    # ---- F-Graph: edge keys u<<32 | v --------------------------------------------
+    def bfs(self, nv, source=0, device=False, stream=None):
+        """Hop distance of every vertex from `source` (0xFFFFFFFF if unreachable)."""
+        if device:
+            import torch
+            out = torch.empty(nv, dtype=torch.int32, device="cuda")
+            ptr, mem = ctypes.c_void_p(out.data_ptr()), MEM_DEVICE
+        else:
+            out = np.empty(nv, dtype=np.uint32)
+            ptr, mem = ctypes.c_void_p(out.ctypes.data), MEM_HOST
+        _check(lib().cpma_fgraph_bfs(self._h, nv, source, mem, ptr, _stream(stream, device)),
+               "cpma_fgraph_bfs")
+        return out
+
+    def pagerank(self, nv, iters=10, damping=0.85, device=False, stream=None):
+        """FP32 PageRank after `iters` rounds from the uniform vector."""
+        if device:
+            import torch
+            out = torch.empty(nv, dtype=torch.float32, device="cuda")
+            ptr, mem = ctypes.c_void_p(out.data_ptr()), MEM_DEVICE
+        else:
+            out = np.empty(nv, dtype=np.float32)
+            ptr, mem = ctypes.c_void_p(out.ctypes.data), MEM_HOST
+        _check(lib().cpma_fgraph_pagerank(self._h, nv, iters, damping, mem, ptr,
+                                          _stream(stream, device)), "cpma_fgraph_pagerank")
+        return out
 
     def stats_enable(self, on=True):
         """Starts (zeroing) or stops per-phase HIP-event timing inside the library."""

@@ -19,6 +19,7 @@
 #include "update.hpp"
 #include "merge_lane.hpp"
 #include "merge_wave.hpp"
+#include "fgraph.hpp"
 
 using namespace cpma_dev;
 
@@ -95,7 +96,7 @@ struct cpma {
   // scratch
   DevBuf kin, kb0, kb1, kdedup, leafid, segpos, seg_leaf, seg_begin, seg_desc, heavy, spill, scan_tmp, ovf, arena,
       stage, pyr, win, wargs, cnt, koff, win_id, welem, P, ccost, ncost, lstart, planU, plan_used,
-      spare_bytes, spare_used, spare_head,
+      spare_bytes, spare_used, spare_head, fg_level, fg_deg, fg_p, fg_c, fg_acc,
       win_of_leaf, fail, qa, qb, qfirst, qnvis, qvoff, qsum, qcount, qout;
   Counters* dctr = nullptr;
   Counters* hctr = nullptr;
@@ -985,6 +986,93 @@ cpma_status cpma_contains(const cpma* cs, const uint64_t* keys, uint64_t q, cpma
   });
 }
 
+static FgArgs fg_args(const cpma* s, uint32_t nv) {
+  FgArgs g;
+  g.bytes = (const uint8_t*)s->bytes.p;
+  g.used = (const uint32_t*)s->used.p;
+  g.L = s->L;
+  g.S = s->S;
+  g.nv = nv;
+  return g;
+}
+
+static uint32_t fg_grid(const cpma* s) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((s->L + 3) / 4, (uint64_t)s->num_cus * 16));
+}
+
+cpma_status cpma_fgraph_bfs(const cpma* cs, uint32_t nv, uint32_t source, cpma_mem mem, uint32_t* level,
+                            void* stream) {
+  cpma* s = const_cast<cpma*>(cs);
+  if (!s || !level || nv == 0 || source >= nv) return CPMA_ERR_INVALID;
+  if (s->S > kWaveMaxS) return CPMA_ERR_INVALID;
+  if (s->broken) return CPMA_ERR_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  return guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    uint32_t* lv = level;
+    if (mem == CPMA_MEM_HOST) {
+      ensure(s->fg_level, (uint64_t)nv * 4);
+      lv = s->fg_level.as<uint32_t>();
+    }
+    hipLaunchKernelGGL((k_fill<uint32_t>), dim3(grid_for(nv, 256, 4096)), dim3(256), 0, st, lv, (uint64_t)nv,
+                       0xffffffffu);
+    hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, lv + source, (uint64_t)1, 0u);
+    HIPCHK(hipGetLastError());
+    const FgArgs g = fg_args(s, nv);
+    for (uint32_t cur = 0; cur < nv; cur++) {
+      zero_counters(s, st);
+      hipLaunchKernelGGL(k_fg_bfs_step, dim3(fg_grid(s)), dim3(256), 0, st, g, lv, cur, &s->dctr->found);
+      HIPCHK(hipGetLastError());
+      read_counters(s, st);
+      if (s->hctr->found == 0) break;
+    }
+    if (mem == CPMA_MEM_HOST) {
+      HIPCHK(hipMemcpyAsync(level, lv, (uint64_t)nv * 4, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
+cpma_status cpma_fgraph_pagerank(const cpma* cs, uint32_t nv, int iters, double damping, cpma_mem mem, float* p,
+                                 void* stream) {
+  cpma* s = const_cast<cpma*>(cs);
+  if (!s || !p || nv == 0 || iters < 0 || !(damping >= 0.0 && damping <= 1.0)) return CPMA_ERR_INVALID;
+  if (s->S > kWaveMaxS) return CPMA_ERR_INVALID;
+  if (s->broken) return CPMA_ERR_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  return guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    float* pv = p;
+    if (mem == CPMA_MEM_HOST) {
+      ensure(s->fg_p, (uint64_t)nv * 4);
+      pv = s->fg_p.as<float>();
+    }
+    ensure(s->fg_deg, (uint64_t)nv * 4);
+    ensure(s->fg_c, (uint64_t)nv * 4);
+    ensure(s->fg_acc, (uint64_t)nv * 4);
+    const uint32_t vg = grid_for(nv, 256, 8192);
+    hipLaunchKernelGGL((k_fill<uint32_t>), dim3(vg), dim3(256), 0, st, s->fg_deg.as<uint32_t>(), (uint64_t)nv, 0u);
+    hipLaunchKernelGGL((k_fill<float>), dim3(vg), dim3(256), 0, st, pv, (uint64_t)nv, 1.0f / (float)nv);
+    const FgArgs g = fg_args(s, nv);
+    PhaseMark pq = phase_begin(s, CPMA_PHASE_QUERY, st);
+    hipLaunchKernelGGL(k_fg_degree, dim3(fg_grid(s)), dim3(256), 0, st, g, s->fg_deg.as<uint32_t>());
+    const float base = (float)((1.0 - damping) / (double)nv);
+    for (int it = 0; it < iters; it++) {
+      hipLaunchKernelGGL(k_pr_contrib, dim3(vg), dim3(256), 0, st, (const float*)pv,
+                         (const uint32_t*)s->fg_deg.as<uint32_t>(), nv, s->fg_c.as<float>(), s->fg_acc.as<float>());
+      hipLaunchKernelGGL(k_fg_pull, dim3(fg_grid(s)), dim3(256), 0, st, g, (const float*)s->fg_c.as<float>(),
+                         s->fg_acc.as<float>());
+      hipLaunchKernelGGL(k_pr_update, dim3(vg), dim3(256), 0, st, (const float*)s->fg_acc.as<float>(), nv, base,
+                         (float)damping, pv);
+    }
+    HIPCHK(hipGetLastError());
+    phase_end(s, pq, st);
+    if (mem == CPMA_MEM_HOST) HIPCHK(hipMemcpyAsync(p, pv, (uint64_t)nv * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    resolve_phases(s);
+  });
+}
+
 uint64_t cpma_size(const cpma* s) { return s ? s->n : 0; }
 
 uint64_t cpma_bytes(const cpma* s) { return s ? s->L * ((uint64_t)s->S + 8 + 4) : 0; }
@@ -1056,7 +1144,8 @@ void cpma_destroy(cpma* s) {
   DevBuf* bufs[] = {&s->bytes,  &s->used,     &s->head,      &s->kin,       &s->kb0,   &s->kb1,    &s->kdedup,
                     &s->leafid, &s->segpos,   &s->seg_leaf,  &s->seg_begin, &s->seg_desc, &s->heavy, &s->spill, &s->scan_tmp,
                     &s->ovf,    &s->arena,    &s->stage,     &s->pyr,       &s->win,   &s->wargs,  &s->cnt,
-                    &s->koff,   &s->win_id,   &s->welem,     &s->P,         &s->ccost, &s->ncost, &s->spare_bytes, &s->spare_used, &s->spare_head, &s->lstart, &s->planU,
+                    &s->koff,   &s->win_id,   &s->welem,     &s->P,         &s->ccost, &s->ncost, &s->spare_bytes, &s->spare_used, &s->spare_head,
+                    &s->fg_level, &s->fg_deg, &s->fg_p, &s->fg_c, &s->fg_acc, &s->lstart, &s->planU,
                     &s->plan_used, &s->win_of_leaf, &s->fail, &s->qa,        &s->qb,    &s->qfirst, &s->qnvis,
                     &s->qvoff,  &s->qsum,     &s->qcount,    &s->qout};
   for (DevBuf* b : bufs) release(*b);

@@ -21,7 +21,7 @@ struct Counters {
   unsigned int root_viol;           // violation bits of the root
   unsigned int error;               // internal capacity overflow (bug guard)
   unsigned int nspill;              // segments the wave merge hands to the lane merge
-  unsigned int pad0;
+  unsigned int found;               // vertices claimed by a BFS step
   unsigned long long alg_bytes;     // algorithmic HBM bytes of the merge (statistics)
   unsigned long long alg_bytes_q;   // algorithmic HBM bytes of range scans (statistics)
 };

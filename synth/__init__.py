@@ -153,3 +153,56 @@ def edge_keys(src, dst, symmetric=True, drop_self_loops=True):
     if symmetric:
         k = np.concatenate([k, (dst << np.uint64(32)) | src])
     return k
+
+
+# ---- the same streams drawn with torch (on any device), bit-identical to numpy ----
+def _t_splitmix64(seed, n, offset, device):
+    import torch
+    g = -0x61C8864680B583EB            # 0x9E3779B97F4A7C15 as int64
+    m1 = -0x40A7B892E31B1A47           # 0xBF58476D1CE4E5B9 as int64
+    m2 = -0x6B2FB644ECCEEE15           # 0x94D049BB133111EB as int64
+    s = seed & 0xFFFFFFFFFFFFFFFF
+    if s >= 1 << 63:
+        s -= 1 << 64
+    i = torch.arange(offset + 1, offset + n + 1, dtype=torch.int64, device=device)
+    z = s + i * g
+
+    def lsr(x, k):
+        return (x >> k) & ((1 << (64 - k)) - 1)
+
+    z = (z ^ lsr(z, 30)) * m1
+    z = (z ^ lsr(z, 27)) * m2
+    return z ^ lsr(z, 31)
+
+
+def uniform_float_torch(n, seed, device, offset=0):
+    import torch
+    z = _t_splitmix64(seed, n, offset, device)
+    return ((z >> 11) & ((1 << 53) - 1)).to(torch.float64) * (1.0 / (1 << 53))
+
+
+def rmat_edges_torch(m, seed, scale=24, a=0.5, b=0.1, c=0.1, device="cpu"):
+    """rmat_edges drawn with torch: same values, int64 tensors on `device`."""
+    import torch
+    src = torch.zeros(m, dtype=torch.int64, device=device)
+    dst = torch.zeros(m, dtype=torch.int64, device=device)
+    ab, abc = a + b, a + b + c
+    for lvl in range(scale):
+        u = uniform_float_torch(m, seed + 7919 * (lvl + 1), device)
+        bit = 1 << (scale - 1 - lvl)
+        right = ((u >= a) & (u < ab)) | (u >= abc)
+        down = u >= ab
+        dst |= right.to(torch.int64) * bit
+        src |= down.to(torch.int64) * bit
+    return src, dst
+
+
+def edge_keys_torch(src, dst, symmetric=True, drop_self_loops=True):
+    import torch
+    if drop_self_loops:
+        keep = src != dst
+        src, dst = src[keep], dst[keep]
+    k = (src << 32) | dst
+    if symmetric:
+        k = torch.cat([k, (dst << 32) | src])
+    return k

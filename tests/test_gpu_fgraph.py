@@ -1,0 +1,94 @@
+"""F-Graph on the GPU CPMA against the CPU oracle: BFS levels bit-exact,
+FP32 PageRank within 1e-5 relative of the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cp():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2305_05055_amd as p
+    p.lib()
+    return p
+
+
+def graph(scale, samples, seed):
+    s, d = synth.rmat_edges(samples, seed, scale=scale)
+    return synth.edge_keys(s, d)
+
+
+def check_graph(c, keys_sorted, nv, orc, src=0, pagerank=True):
+    lv = c.bfs(nv, src)
+    assert np.array_equal(lv, orc.bfs(keys_sorted, nv, src))
+    if not pagerank:
+        return
+    p32 = c.pagerank(nv, iters=10).astype(np.float64)
+    p64 = orc.pagerank(keys_sorted, nv, iters=10)
+    rel = np.abs(p32 - p64) / p64
+    assert rel.max() <= 1e-5, rel.max()
+
+
+@pytest.mark.parametrize("S", [128, 1024])
+def test_bfs_pagerank_small_rmat(cp, orc, S):
+    scale = 12
+    keys = graph(scale, 30000, 101)
+    ks = orc.build_set(keys)
+    c = cp.CPMA(keys, leaf_bytes=S)
+    check_graph(c, ks, 1 << scale, orc)
+    check_graph(c, ks, 1 << scale, orc, src=17)
+
+
+def test_edge_batches_then_algorithms(cp, orc):
+    scale = 14
+    keys = graph(scale, 100000, 202)
+    ks = orc.build_set(keys)
+    c = cp.CPMA(keys)
+    for b in range(3):
+        batch = graph(scale, 20000, 300 + b)
+        ks, added = orc.insert(ks, batch)
+        assert c.insert_batch(batch) == added
+    check_graph(c, ks, 1 << scale, orc)
+    fwd = ks[::5]
+    rev = ((fwd & np.uint64(0xffffffff)) << np.uint64(32)) | (fwd >> np.uint64(32))
+    dels = np.concatenate([fwd, rev])                    # keep the edge set symmetric
+    ks, removed = orc.delete(ks, dels)
+    assert c.delete_batch(dels) == removed
+    check_graph(c, ks, 1 << scale, orc)
+
+
+def test_disconnected_and_isolated_vertices(cp, orc):
+    # two components plus isolated vertices; ids near the top of the range
+    nv = 1000
+    pairs = [(i, i + 1) for i in range(10)] + [(900, 950), (950, 999)]
+    ks = np.array(sorted({(a << 32) | b for a, b in pairs} | {(b << 32) | a for a, b in pairs}),
+                  dtype=np.uint64)
+    c = cp.CPMA(ks, leaf_bytes=64)
+    check_graph(c, ks, nv, orc)
+    check_graph(c, ks, nv, orc, src=950)
+
+
+def test_bfs_directed_edges(cp, orc):
+    """BFS follows u -> v on an asymmetric edge set too."""
+    nv = 4096
+    s, d = synth.rmat_edges(20000, 505, scale=12)
+    ks = orc.build_set(synth.edge_keys(s, d, symmetric=False))
+    c = cp.CPMA(ks, leaf_bytes=256)
+    check_graph(c, ks, nv, orc, pagerank=False)
+    check_graph(c, ks, nv, orc, src=1, pagerank=False)
+
+
+def test_rmat_scale20(cp, orc):
+    """A larger R-MAT graph drawn on the GPU (same values as the numpy generator)."""
+    import torch
+    scale = 20
+    s, d = synth.rmat_edges_torch(1 << 23, 404, scale=scale, device="cuda")
+    dk = synth.edge_keys_torch(s, d)
+    c = cp.CPMA(dk)
+    ks = orc.build_set(dk.cpu().numpy().view(np.uint64))
+    assert c.size() == len(ks)
+    check_graph(c, ks, 1 << scale, orc)

@@ -1,0 +1,34 @@
+"""Input generators: shapes and reproducibility (no method arithmetic here)."""
+import numpy as np
+
+import synth
+
+
+def test_unique_uniform_keys_exact_count_and_range():
+    k = synth.unique_uniform_keys(200000, 5, bits=20)   # forces many repeats, then top-up
+    assert len(k) == 200000 and len(np.unique(k)) == 200000
+    assert int(k.max()) < (1 << 20)
+
+
+def test_sample_indices_distinct():
+    for n, k in ((10, 10), (1000, 3), (10 ** 6, 5000)):
+        idx = synth.sample_indices(n, k, 9)
+        assert len(idx) == k and len(np.unique(idx)) == k and idx.min() >= 0 and idx.max() < n
+
+
+def test_zipf_lengths_range_and_skew():
+    l = synth.zipf_lengths(100000, 3, alpha=1.2, lmax=10 ** 6)
+    assert l.min() >= 1 and l.max() <= 10 ** 6
+    assert 0.15 < np.mean(l == 1) < 0.25          # P(1) = 1/zeta_N(1.2) ~ 0.19
+
+
+def test_rmat_torch_matches_numpy():
+    s1, d1 = synth.rmat_edges(4000, 11, scale=14)
+    s2, d2 = synth.rmat_edges_torch(4000, 11, scale=14)
+    assert np.array_equal(s1.astype(np.int64), s2.numpy())
+    assert np.array_equal(d1.astype(np.int64), d2.numpy())
+    assert int(s1.max()) < (1 << 14) and int(d1.max()) < (1 << 14)
+    # vertex 0 is the hub of the (a=.5, b=c=.1, d=.3) recursion
+    s3, d3 = synth.rmat_edges(200000, 12, scale=10)
+    deg = np.bincount(np.concatenate([s3, d3]).astype(np.int64))
+    assert deg.argmax() == 0
