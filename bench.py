@@ -40,6 +40,103 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
 
 
+def fgraph_section(cp, torch, scale, seed):
+    """F-Graph: symmetric R-MAT graph with 2^scale vertices from 2^(scale+3) samples."""
+    nv = 1 << scale
+    src, dst = synth.rmat_edges_torch(1 << (scale + 3), seed, scale=scale, device="cuda")
+    keys = synth.edge_keys_torch(src, dst)
+    del src, dst
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = cp.CPMA(keys)
+    torch.cuda.synchronize()
+    out = {"scale": scale, "vertices": nv, "edges": g.size(), "build_s": time.perf_counter() - t0,
+           "bytes_per_edge": g.bytes() / g.size()}
+    del keys
+    g.bfs(nv, 0)
+    t0 = time.perf_counter()
+    lv = g.bfs(nv, 0)
+    out["bfs_ms"] = (time.perf_counter() - t0) * 1e3
+    reach = lv[lv != 0xFFFFFFFF]
+    out["bfs_levels"] = int(reach.max()) + 1
+    out["bfs_reached"] = int(len(reach))
+    g.pagerank(nv, iters=1)
+    t0 = time.perf_counter()
+    g.pagerank(nv, iters=10)
+    out["pagerank_10_iters_ms"] = (time.perf_counter() - t0) * 1e3
+    ins = {}
+    for k in (10 ** 5, 10 ** 6, 10 ** 7):
+        s2, d2 = synth.rmat_edges_torch(k // 2, seed + k, scale=scale, device="cuda")
+        b = synth.edge_keys_torch(s2, d2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.insert_batch(b)
+        ins[f"{k:.0e}"] = len(b) / (time.perf_counter() - t0)
+    out["edge_insert_keys_s"] = ins
+    log(f"fgraph: {out}")
+    g.close()
+    return out
+
+
+def serving_section(cp, torch, n0, nreq, seed):
+    """Open-loop Poisson stream of mixed requests against a resident set."""
+    base_d = synth.uniform_keys_torch(n0, seed, "cuda")
+    base = base_d.cpu().numpy().view(np.uint64)
+    width = (1 << 40) // n0
+
+    def requests(count, s0):
+        kinds = synth.uniform_float(count, s0)
+        lens = synth.zipf_lengths(count, s0 + 1, alpha=1.2, lmax=10 ** 5)
+        sizes = synth.log_uniform_sizes(count, s0 + 2)
+        los = synth.uniform_keys(count, s0 + 3)
+        out = []
+        for i in range(count):
+            if kinds[i] < 0.70:
+                lo = los[i:i + 1]
+                out.append(cp.ServedRequest(cp.REQ_RANGE, lo, lo + np.uint64(int(lens[i]) * width)))
+            elif kinds[i] < 0.95:
+                out.append(cp.ServedRequest(cp.REQ_INSERT, synth.uniform_keys(int(sizes[i]), s0 + 4, offset=10 ** 7 * i)))
+            else:
+                idx = synth.sample_indices(len(base), int(sizes[i]), s0 + 5 + i)
+                out.append(cp.ServedRequest(cp.REQ_DELETE, base[idx]))
+        return out
+
+    def run(reqs, slots, rate=None):
+        srv = cp.Server(c, max_slots=slots)
+        t0 = cp.clock_ns()
+        if rate is None:
+            for r in reqs:
+                srv.submit(r)
+        else:
+            gaps = -np.log(1.0 - synth.uniform_float(len(reqs), seed + 77)) / rate
+            arrive = t0 + np.cumsum(gaps) * 1e9
+            for r, ta in zip(reqs, arrive):
+                while cp.clock_ns() < ta:
+                    pass
+                srv.submit(r)
+        steps = srv.stop()
+        t1 = max(r.req.t_done_ns for r in reqs)
+        lat = np.array([(r.req.t_done_ns - r.t_submit_ns) * 1e-6 for r in reqs])
+        return {"ops_s": len(reqs) / ((t1 - t0) * 1e-9), "steps": steps,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
+
+    c = cp.CPMA(base_d)
+    del base_d
+    torch.cuda.synchronize()
+    out = {"n0": c.size(), "requests": nreq, "mix": "70% range (Zipf(1.2) 1..1e5), 25% insert, 5% delete "
+           "(log-uniform 10..1e6 keys)"}
+    sat = run(requests(nreq, seed + 100), 4096)
+    fifo = run(requests(nreq // 4, seed + 200), 1)
+    out["saturation_batched"] = sat
+    out["saturation_one_request_per_step"] = fifo
+    for frac in (0.5, 0.8):
+        out[f"poisson_{frac}"] = run(requests(nreq // 2, seed + int(300 + 100 * frac)), 4096,
+                                     rate=frac * sat["ops_s"])
+    log(f"serving: {out}")
+    c.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,7 +149,10 @@ def main():
     ap.add_argument("--leaf-bytes", type=int, default=0)
     ap.add_argument("--cpu-batches", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only-steps", action="store_true", help="skip sweep and range_map")
+    ap.add_argument("--only-steps", action="store_true", help="skip every side measurement")
+    ap.add_argument("--fg-scale", type=int, default=24, help="R-MAT scale of the F-Graph section (0: skip)")
+    ap.add_argument("--serve-n", type=float, default=1e8, help="keys of the served set (0: skip serving)")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -215,6 +315,14 @@ def main():
     result_extra["delete_keys_s_at_batch"] = 2 * k / (time.perf_counter() - t0)
     result_extra["bytes_per_key_final"] = c.bytes() / c.size()
     del batches, dels
+
+    c.close()
+    torch.cuda.empty_cache()
+    if not args.only_steps and args.fg_scale > 0:
+        result_extra["fgraph"] = fgraph_section(cp, torch, args.fg_scale, seed + 60)
+        torch.cuda.empty_cache()
+    if not args.only_steps and args.serve_n > 0:
+        result_extra["serving"] = serving_section(cp, torch, int(args.serve_n), args.serve_requests, seed + 70)
 
     # ---- CPU baseline: the oracle inserting the same kind of batches ------------
     cpu = None

@@ -182,6 +182,57 @@ cpma_status cpma_fgraph_pagerank(const cpma* set, uint32_t nv, int iters, double
                                  cpma_mem mem, float* p, void* stream);
 
 /*
+ * Serving: a request queue in front of one set, served by a worker thread.
+ *
+ * Requests are admitted in arrival order while the in-flight HBM footprint
+ * stays under `hbm_budget` bytes and at most `max_slots` requests are in
+ * flight; the admitted requests form one step.  A step runs every range
+ * request it holds as one batched cpma_range_map launch against the state left
+ * by the previous steps, then applies its insert / delete requests in arrival
+ * order (the paper phases updates and queries with a single writer, Section
+ * "Evaluation on graph workloads").  Each request's result therefore equals
+ * replaying all requests in (step, queries first, updates in arrival order)
+ * order one call each.
+ *
+ * All request buffers are host memory and must stay valid until the request
+ * is done.  `done` becomes nonzero (release store) when the outputs are
+ * written; `t_done_ns` is the completion time on the steady clock that
+ * cpma_clock_ns reads, `step` the step that served it.
+ */
+typedef enum { CPMA_REQ_RANGE = 0, CPMA_REQ_INSERT = 1, CPMA_REQ_DELETE = 2 } cpma_req_kind;
+
+typedef struct {
+  int32_t kind;          /* cpma_req_kind */
+  uint32_t pad;
+  uint64_t n;            /* number of ranges, or of keys */
+  const uint64_t* keys;  /* insert / delete keys, or the ranges' lo */
+  const uint64_t* hi;    /* ranges' hi (range requests only) */
+  uint64_t* sum;         /* range outputs, n entries each */
+  uint64_t* count;
+  uint64_t result;       /* keys added / removed (insert / delete) */
+  int32_t status;        /* cpma_status of the request */
+  volatile int32_t done;
+  uint64_t t_done_ns;
+  uint64_t step;
+} cpma_request;
+
+typedef struct {
+  uint64_t hbm_budget;   /* bytes of in-flight request data; 0 = 16 GiB */
+  uint32_t max_slots;    /* requests in flight; 0 = 4096 */
+} cpma_server_config;
+
+typedef struct cpma_server cpma_server;
+
+/* Starts a worker thread serving `set` (which it must be the only writer of). */
+cpma_status cpma_server_start(cpma* set, const cpma_server_config* cfg, cpma_server** out);
+/* Queues a request (stamped with its arrival); thread safe. */
+cpma_status cpma_server_submit(cpma_server* srv, cpma_request* req);
+/* Serves everything queued, stops the worker and frees the server. */
+cpma_status cpma_server_stop(cpma_server* srv, uint64_t* steps_run);
+/* Steady-clock nanoseconds (the clock of t_done_ns). */
+uint64_t cpma_clock_ns(void);
+
+/*
  * Phase statistics (instrumentation, not part of the paper's API).  While
  * enabled, every call records HIP events around its phases on the call's stream
  * and accumulates, per phase, the number of timed launches, their total device

@@ -34,6 +34,21 @@ class Config(ctypes.Structure):
                 ("build_density", ctypes.c_double)]
 
 
+class Request(ctypes.Structure):
+    """cpma_request: one range batch, insert batch or delete batch for the server."""
+    _fields_ = [("kind", ctypes.c_int32), ("pad", ctypes.c_uint32), ("n", ctypes.c_uint64),
+                ("keys", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("sum", ctypes.c_void_p),
+                ("count", ctypes.c_void_p), ("result", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("done", ctypes.c_int32), ("t_done_ns", ctypes.c_uint64), ("step", ctypes.c_uint64)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_slots", ctypes.c_uint32)]
+
+
+REQ_RANGE, REQ_INSERT, REQ_DELETE = 0, 1, 2
+
+
 class PhaseStat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("ms", ctypes.c_double), ("alg_bytes", ctypes.c_uint64)]
 
@@ -72,6 +87,11 @@ def lib():
         L.cpma_fgraph_bfs.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, vp, vp]
         L.cpma_fgraph_pagerank.argtypes = [vp, ctypes.c_uint32, ctypes.c_int, ctypes.c_double,
                                            ctypes.c_int, vp, vp]
+        L.cpma_server_start.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+        L.cpma_server_submit.argtypes = [vp, ctypes.POINTER(Request)]
+        L.cpma_server_stop.argtypes = [vp, ctypes.POINTER(u64)]
+        L.cpma_clock_ns.argtypes = []
+        L.cpma_clock_ns.restype = u64
         L.cpma_stats_enable.argtypes = [vp, ctypes.c_int]
         L.cpma_stats_get.argtypes = [vp, ctypes.POINTER(PhaseStat), ctypes.c_int]
         L.cpma_status_str.argtypes = [ctypes.c_int]
@@ -258,3 +278,55 @@ class CPMA:
         _check(lib().cpma_export(self._h, ctypes.c_void_p(b.ctypes.data), ctypes.c_void_p(u.ctypes.data),
                                  ctypes.c_void_p(h.ctypes.data), _stream(stream, False)), "cpma_export")
         return b, u, h
+
+
+def clock_ns():
+    """Steady-clock nanoseconds (the clock of a request's t_done_ns)."""
+    return int(lib().cpma_clock_ns())
+
+
+class ServedRequest:
+    """A request plus the host arrays it points to (kept alive until done)."""
+
+    def __init__(self, kind, keys, hi=None):
+        self.kind = kind
+        self.keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        self.hi = None if hi is None else np.ascontiguousarray(hi, dtype=np.uint64)
+        n = len(self.keys)
+        self.sum = np.zeros(n, dtype=np.uint64) if kind == REQ_RANGE else None
+        self.count = np.zeros(n, dtype=np.uint64) if kind == REQ_RANGE else None
+        self.req = Request()
+        self.req.kind = kind
+        self.req.n = n
+        self.req.keys = self.keys.ctypes.data if n else None
+        self.req.hi = self.hi.ctypes.data if self.hi is not None and n else None
+        self.req.sum = self.sum.ctypes.data if self.sum is not None and n else None
+        self.req.count = self.count.ctypes.data if self.count is not None and n else None
+        self.t_submit_ns = 0
+
+    @property
+    def done(self):
+        return self.req.done != 0
+
+
+class Server:
+    """Serving loop over one CPMA (native worker thread; see cpma_server_* in cpma.h)."""
+
+    def __init__(self, cpma_obj, hbm_budget=0, max_slots=0):
+        cfg = ServerConfig(hbm_budget, max_slots)
+        h = ctypes.c_void_p()
+        _check(lib().cpma_server_start(cpma_obj.handle, ctypes.byref(cfg), ctypes.byref(h)),
+               "cpma_server_start")
+        self._h = h
+        self._set = cpma_obj
+
+    def submit(self, sr):
+        sr.t_submit_ns = clock_ns()
+        _check(lib().cpma_server_submit(self._h, ctypes.byref(sr.req)), "cpma_server_submit")
+
+    def stop(self):
+        steps = ctypes.c_uint64(0)
+        if self._h:
+            _check(lib().cpma_server_stop(self._h, ctypes.byref(steps)), "cpma_server_stop")
+            self._h = None
+        return int(steps.value)

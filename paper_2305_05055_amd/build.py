@@ -23,9 +23,9 @@ FLAGS = [
 
 
 def build(verbose=False):
-    src = os.path.join(CSRC, "cpma.hip")
+    srcs = [os.path.join(CSRC, "cpma.hip"), os.path.join(CSRC, "serve.cpp")]
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp, src]
+    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-pthread", "-o", tmp] + srcs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -206,3 +206,17 @@ def edge_keys_torch(src, dst, symmetric=True, drop_self_loops=True):
     if symmetric:
         k = torch.cat([k, (dst << 32) | src])
     return k
+
+
+def uniform_keys_torch(n, seed, device, bits=40, offset=0):
+    """uniform_keys drawn with torch (int64 tensor on `device`, same values)."""
+    z = _t_splitmix64(seed, n, offset, device)
+    if bits < 64:
+        z = z & ((1 << bits) - 1)
+    return z
+
+
+def log_uniform_sizes(n, seed, lo_exp=1.0, hi_exp=6.0):
+    """n sizes floor(10^(lo_exp + (hi_exp - lo_exp) u)), u uniform in [0, 1)."""
+    u = uniform_float(n, seed)
+    return np.floor(10.0 ** (lo_exp + (hi_exp - lo_exp) * u)).astype(np.int64)

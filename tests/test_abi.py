@@ -71,3 +71,18 @@ def test_package_does_not_import_oracle():
     assert "oracle" not in src.replace("no CPU fallback", "")
     for f in os.listdir(os.path.join(ROOT, "paper_2305_05055_amd", "csrc")):
         assert "oracle" not in open(os.path.join(ROOT, "paper_2305_05055_amd", "csrc", f)).read()
+
+
+def test_server_argument_checks_without_gpu():
+    import ctypes
+    import paper_2305_05055_amd as p
+    if not os.path.exists(p.LIB_PATH):
+        pytest.skip("libcpma.so not built")
+    L = p.lib()
+    h = ctypes.c_void_p()
+    assert L.cpma_server_start(None, None, ctypes.byref(h)) == 1
+    assert L.cpma_server_submit(None, None) == 1
+    assert L.cpma_server_stop(None, None) == 1
+    t0 = p.clock_ns()
+    assert p.clock_ns() >= t0 > 0
+    assert ctypes.sizeof(p.Request) == 80
