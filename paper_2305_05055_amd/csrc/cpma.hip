@@ -20,6 +20,7 @@
 #include "merge_lane.hpp"
 #include "merge_wave.hpp"
 #include "fgraph.hpp"
+#include "resize.hpp"
 
 using namespace cpma_dev;
 
@@ -97,7 +98,8 @@ struct cpma {
   DevBuf kin, kb0, kb1, kdedup, leafid, segpos, seg_leaf, seg_begin, seg_desc, heavy, spill, scan_tmp, ovf, arena,
       stage, pyr, win, wargs, cnt, koff, win_id, welem, P, ccost, ncost, lstart, planU, plan_used,
       spare_bytes, spare_used, spare_head, fg_level, fg_deg, fg_p, fg_c, fg_acc,
-      win_of_leaf, fail, qa, qb, qfirst, qnvis, qvoff, qsum, qcount, qout;
+      win_of_leaf, fail, qa, qb, qfirst, qnvis, qvoff, qsum, qcount, qout, lastk, ne_rank, ne_list, chain_pfx,
+      srec;
   Counters* dctr = nullptr;
   Counters* hctr = nullptr;
   BatchInfo* dinfo = nullptr;
@@ -595,9 +597,90 @@ void spread_fresh(cpma* s, uint64_t K, uint64_t Lt, hipStream_t st, bool costs_r
   throw Fail{CPMA_ERR_DEVICE};
 }
 
-// Root out of bounds: copy everything to an array grown (or shrunk) by the growing
-// factor and spread evenly (Section "Packed Memory Array", "Resizing a PMA").
-void resize(cpma* s, uint64_t total, uint32_t viol, hipStream_t st) {
+// Grows or shrinks to Lt leaves (Lt then moves by the growing factor until every
+// node of the new tree is within its bounds) by a direct split of the old leaf
+// images into the spare arrays.  Returns the algorithmic bytes moved.
+uint64_t split_resize(cpma* s, uint64_t Lt, hipStream_t st) {
+  const uint64_t L = s->L;
+  ensure(s->lastk, L * sizeof(uint64_t));
+  ensure(s->ne_rank, (L + 1) * sizeof(uint32_t));
+  ensure(s->ne_list, (L + 1) * sizeof(uint32_t));
+  ensure(s->chain_pfx, (L + 1) * sizeof(uint64_t));
+  const SrcLeaves sl = src_leaves(s);
+  hipLaunchKernelGGL(k_leaf_last, dim3(grid_for(L, 1, 1u << 20)), dim3(kWave), 0, st, sl, L,
+                     s->lastk.as<uint64_t>());
+  HIPCHK(hipGetLastError());
+  scan<uint32_t>(s, s->ne_rank.as<uint32_t>(), L, st, NonEmptyFn{sl.used});
+  hipLaunchKernelGGL(k_ne_compact, dim3(grid_for(L + 1, 256, 1u << 16)), dim3(256), 0, st, sl.used,
+                     (const uint32_t*)s->ne_rank.as<uint32_t>(), L, s->ne_list.as<uint32_t>());
+  HIPCHK(hipGetLastError());
+  SplitArgs a;
+  a.src = sl;
+  a.head = s->head.as<uint64_t>();
+  a.lastk = s->lastk.as<uint64_t>();
+  a.rank = s->ne_rank.as<uint32_t>();
+  a.ne = s->ne_list.as<uint32_t>();
+  a.CP = s->chain_pfx.as<uint64_t>();
+  a.L = L;
+  scan<uint64_t>(s, s->chain_pfx.as<uint64_t>(), L, st, ChainFn{sl.used, a.head, a.lastk, a.rank, a.ne});
+  const double g = s->cfg.grow;
+  int last_dir = 0;
+  for (int attempt = 0; attempt < 64; attempt++) {
+    a.Lt = Lt;
+    ensure(s->srec, (Lt + 1) * sizeof(SplitRec));
+    ensure(s->spare_used, Lt * sizeof(uint32_t));
+    ensure(s->fail, 16);
+    hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, s->fail.as<uint32_t>(), (uint64_t)1, 0u);
+    hipLaunchKernelGGL(k_split_locate, dim3(grid_for(Lt + 1, 1, 1u << 20)), dim3(kWave), 0, st, a,
+                       s->srec.as<SplitRec>());
+    HIPCHK(hipGetLastError());
+    const Bounds db = s->bounds(Lt);
+    hipLaunchKernelGGL(k_split_plan, dim3(grid_for(Lt, 256, 1u << 16)), dim3(256), 0, st, db, Lt,
+                       (const SplitRec*)s->srec.as<SplitRec>(), s->spare_used.as<uint32_t>(),
+                       s->fail.as<uint32_t>());
+    HIPCHK(hipGetLastError());
+    Pyramid P = make_pyramid(s, Lt);
+    build_pyramid(s, P, s->spare_used.as<uint32_t>(), Lt, st);
+    const uint64_t nodes = (P.H == 0) ? 1 : P.off[P.H] + P.cnt[P.H];
+    hipLaunchKernelGGL(k_check_plan, dim3(grid_for(nodes, 256, 1u << 16)), dim3(256), 0, st, db, P,
+                       (const uint32_t*)s->spare_used.as<uint32_t>(), (const int32_t*)nullptr,
+                       (const uint32_t*)nullptr, 1, s->fail.as<uint32_t>());
+    HIPCHK(hipGetLastError());
+    uint32_t* hf = reinterpret_cast<uint32_t*>(host_pin(s, 16));
+    HIPCHK(hipMemcpyAsync(hf, s->fail.p, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const uint32_t fail = hf[0];
+    if (fail == 0) {
+      ensure(s->spare_bytes, Lt * (uint64_t)s->S);
+      ensure(s->spare_head, Lt * sizeof(uint64_t));
+      zero_counters(s, st);
+      hipLaunchKernelGGL(k_split_write, dim3(grid_for(Lt, 1, 1u << 20)), dim3(kWave), s->S, st, a, s->S,
+                         (const SplitRec*)s->srec.as<SplitRec>(), s->spare_bytes.as<uint8_t>(),
+                         s->spare_used.as<uint32_t>(), s->spare_head.as<uint64_t>(), s->dctr);
+      HIPCHK(hipGetLastError());
+      read_counters(s, st);
+      swap_in_spare(s, Lt);
+      return Lt * ((uint64_t)s->S + 12);
+    }
+    const int dir = (fail & 1u) ? +1 : -1;
+    if (dir == -1 && Lt == 1) throw Fail{CPMA_ERR_DEVICE};
+    if (last_dir != 0 && dir != last_dir) {
+      Lt = Lt + 1;  // bounds pull both ways: settle on the larger layout's neighbour
+    } else if (dir > 0) {
+      Lt = std::max<uint64_t>(Lt + 1, (uint64_t)std::ceil(g * (double)Lt));
+    } else {
+      Lt = std::max<uint64_t>(1, (uint64_t)std::floor((double)Lt / g));
+    }
+    last_dir = dir;
+  }
+  throw Fail{CPMA_ERR_DEVICE};
+}
+
+// Root out of bounds: move everything to an array grown (or shrunk) by the
+// growing factor, spread evenly (Section "Packed Memory Array", "Resizing a
+// PMA").  Returns the algorithmic bytes moved (old used bytes read, new array
+// written).
+uint64_t resize(cpma* s, uint64_t total, uint32_t viol, hipStream_t st) {
   const double g = s->cfg.grow;
   const int64_t Q = kQ;
   uint64_t Lt = s->L;
@@ -609,13 +692,11 @@ void resize(cpma* s, uint64_t total, uint32_t viol, hipStream_t st) {
     while (Lt > 1 && (__int128)total * Q < (__int128)s->q_lo_root * Lt * s->S)
       Lt = std::max<uint64_t>(1, (uint64_t)std::floor((double)Lt / g));
   }
-  uint64_t nsrc, ndst;
-  std::vector<uint64_t> sb{0}, sn{s->L};
-  std::vector<uint32_t> lv{(uint32_t)(tree_height(s->L) + 1)};
-  WinArgs wa = upload_windows(s, sb, sn, sb, sn, lv, st, nsrc, ndst);
-  const uint64_t K = pack_windows(s, wa, nsrc, st);
-  if (K != s->n) throw Fail{CPMA_ERR_DEVICE};
-  spread_fresh(s, K, Lt, st);
+  if (s->n == 0) {
+    spread_fresh(s, 0, 1, st);
+    return 0;
+  }
+  return total + split_resize(s, Lt, st);
 }
 
 // Counting + redistribution until every node of the implicit tree is within its
@@ -636,8 +717,8 @@ void rebalance(cpma* s, hipStream_t st) {
     const Counters c = *s->hctr;
     if (c.root_viol) {
       PhaseMark pr = phase_begin(s, CPMA_PHASE_REDIST, st);
-      resize(s, c.root_sum, c.root_viol, st);
-      phase_end(s, pr, st);
+      const uint64_t moved = resize(s, c.root_sum, c.root_viol, st);
+      phase_end(s, pr, st, moved);
       continue;
     }
     if (c.nwin == 0) return;
@@ -1147,7 +1228,8 @@ void cpma_destroy(cpma* s) {
                     &s->koff,   &s->win_id,   &s->welem,     &s->P,         &s->ccost, &s->ncost, &s->spare_bytes, &s->spare_used, &s->spare_head,
                     &s->fg_level, &s->fg_deg, &s->fg_p, &s->fg_c, &s->fg_acc, &s->lstart, &s->planU,
                     &s->plan_used, &s->win_of_leaf, &s->fail, &s->qa,        &s->qb,    &s->qfirst, &s->qnvis,
-                    &s->qvoff,  &s->qsum,     &s->qcount,    &s->qout};
+                    &s->qvoff,  &s->qsum,     &s->qcount,    &s->qout,  &s->lastk, &s->ne_rank, &s->ne_list,
+                    &s->chain_pfx, &s->srec};
   for (DevBuf* b : bufs) release(*b);
   if (s->dctr) hipFree(s->dctr);
   if (s->dinfo) hipFree(s->dinfo);

@@ -12,6 +12,8 @@
 // (at most one lane back, since a code is at most 10 bytes long).  Keys then come
 // from a wave prefix sum of the per-lane delta totals.
 #pragma once
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace cpma_dev {
@@ -64,7 +66,8 @@ __device__ __forceinline__ void lane_parse(const uint4 w, uint32_t pos0, uint32_
 
 // Decodes the leaf at src (16-byte aligned, `used` valid bytes) with one wave and
 // calls emit(index, key, delta) for every key in order (the head's delta is the
-// head itself).  Returns the key count (uniform).
+// head itself); an emit taking a fourth argument also gets the byte where the
+// key's code ends.  Returns the key count (uniform).
 template <class Emit>
 __device__ __forceinline__ uint32_t wave_decode_leaf(const uint8_t* __restrict__ src, uint32_t used,
                                                      Emit&& emit) {
@@ -103,7 +106,10 @@ __device__ __forceinline__ uint32_t wave_decode_leaf(const uint8_t* __restrict__
         const uint64_t d = c.v[i] + pend;
         pend = 0;
         key += d;
-        emit(idx, key, d);
+        if constexpr (std::is_invocable<Emit&, uint32_t, uint64_t, uint64_t, uint32_t>::value)
+          emit(idx, key, d, pos0 + (uint32_t)i);
+        else
+          emit(idx, key, d);
         idx++;
       }
     }
