@@ -45,7 +45,8 @@ struct Fail {
     if (_e != hipSuccess) throw Fail{CPMA_ERR_DEVICE}; \
   } while (0)
 
-void ensure(DevBuf& b, size_t bytes) {
+// Grows b to at least `bytes` (contents are not kept), with `slack` extra room.
+void ensure(DevBuf& b, size_t bytes, double slack = 0.5) {
   if (bytes == 0) bytes = 16;
   if (b.cap >= bytes) return;
   if (b.p) {
@@ -53,7 +54,7 @@ void ensure(DevBuf& b, size_t bytes) {
     b.p = nullptr;
     b.cap = 0;
   }
-  size_t want = bytes + bytes / 4 + 256;
+  size_t want = bytes + (size_t)((double)bytes * slack) + 256;
   if (hipMalloc(&b.p, want) != hipSuccess) {
     hipGetLastError();
     if (hipMalloc(&b.p, bytes) != hipSuccess) {
@@ -99,7 +100,7 @@ struct cpma {
       stage, pyr, win, wargs, cnt, koff, win_id, welem, P, ccost, ncost, lstart, planU, plan_used,
       spare_bytes, spare_used, spare_head, fg_level, fg_deg, fg_p, fg_c, fg_acc,
       win_of_leaf, fail, qa, qb, qfirst, qnvis, qvoff, qsum, qcount, qout, lastk, ne_rank, ne_list, chain_pfx,
-      srec;
+      srec, wide;
   Counters* dctr = nullptr;
   Counters* hctr = nullptr;
   BatchInfo* dinfo = nullptr;
@@ -600,15 +601,20 @@ void spread_fresh(cpma* s, uint64_t K, uint64_t Lt, hipStream_t st, bool costs_r
 // Grows or shrinks to Lt leaves (Lt then moves by the growing factor until every
 // node of the new tree is within its bounds) by a direct split of the old leaf
 // images into the spare arrays.  Returns the algorithmic bytes moved.
-uint64_t split_resize(cpma* s, uint64_t Lt, hipStream_t st) {
+// total_used: sum of the old used bytes (bounds the chain total from above).
+// Returns false, with nothing changed, when thresholds would overflow 64 bits.
+bool split_resize(cpma* s, uint64_t Lt, uint64_t total_used, hipStream_t st, uint64_t* moved) {
   const uint64_t L = s->L;
+  // a head's chain cost can exceed its 8 bytes by 2 (64-bit distances)
+  auto fits = [&](uint64_t lt) { return (__int128)(total_used + 2 * L + 16) * (lt + 1) < ((__int128)1 << 62); };
+  if (!fits(Lt)) return false;
   ensure(s->lastk, L * sizeof(uint64_t));
   ensure(s->ne_rank, (L + 1) * sizeof(uint32_t));
   ensure(s->ne_list, (L + 1) * sizeof(uint32_t));
   ensure(s->chain_pfx, (L + 1) * sizeof(uint64_t));
   const SrcLeaves sl = src_leaves(s);
-  hipLaunchKernelGGL(k_leaf_last, dim3(grid_for(L, 1, 1u << 20)), dim3(kWave), 0, st, sl, L,
-                     s->lastk.as<uint64_t>());
+  hipLaunchKernelGGL(k_leaf_last, dim3(grid_for(L, 256, 1u << 16)), dim3(256), 0, st, sl,
+                     (const uint64_t*)s->head.as<uint64_t>(), L, s->lastk.as<uint64_t>());
   HIPCHK(hipGetLastError());
   scan<uint32_t>(s, s->ne_rank.as<uint32_t>(), L, st, NonEmptyFn{sl.used});
   hipLaunchKernelGGL(k_ne_compact, dim3(grid_for(L + 1, 256, 1u << 16)), dim3(256), 0, st, sl.used,
@@ -626,12 +632,13 @@ uint64_t split_resize(cpma* s, uint64_t Lt, hipStream_t st) {
   const double g = s->cfg.grow;
   int last_dir = 0;
   for (int attempt = 0; attempt < 64; attempt++) {
+    if (!fits(Lt)) throw Fail{CPMA_ERR_DEVICE};
     a.Lt = Lt;
     ensure(s->srec, (Lt + 1) * sizeof(SplitRec));
-    ensure(s->spare_used, Lt * sizeof(uint32_t));
+    ensure(s->spare_used, Lt * sizeof(uint32_t), std::max(0.25, s->cfg.grow * s->cfg.grow - 1.0 + 0.05));
     ensure(s->fail, 16);
     hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, s->fail.as<uint32_t>(), (uint64_t)1, 0u);
-    hipLaunchKernelGGL(k_split_locate, dim3(grid_for(Lt + 1, 1, 1u << 20)), dim3(kWave), 0, st, a,
+    hipLaunchKernelGGL(k_split_locate, dim3(grid_for(L, 256, 1u << 16)), dim3(256), 0, st, a,
                        s->srec.as<SplitRec>());
     HIPCHK(hipGetLastError());
     const Bounds db = s->bounds(Lt);
@@ -651,8 +658,10 @@ uint64_t split_resize(cpma* s, uint64_t Lt, hipStream_t st) {
     HIPCHK(hipStreamSynchronize(st));
     const uint32_t fail = hf[0];
     if (fail == 0) {
-      ensure(s->spare_bytes, Lt * (uint64_t)s->S);
-      ensure(s->spare_head, Lt * sizeof(uint64_t));
+      // room for the next growth too, so that alternating arrays stop reallocating
+      const double room = std::max(0.25, s->cfg.grow * s->cfg.grow - 1.0 + 0.05);
+      ensure(s->spare_bytes, Lt * (uint64_t)s->S, room);
+      ensure(s->spare_head, Lt * sizeof(uint64_t), room);
       zero_counters(s, st);
       hipLaunchKernelGGL(k_split_write, dim3(grid_for(Lt, 1, 1u << 20)), dim3(kWave), s->S, st, a, s->S,
                          (const SplitRec*)s->srec.as<SplitRec>(), s->spare_bytes.as<uint8_t>(),
@@ -660,7 +669,8 @@ uint64_t split_resize(cpma* s, uint64_t Lt, hipStream_t st) {
       HIPCHK(hipGetLastError());
       read_counters(s, st);
       swap_in_spare(s, Lt);
-      return Lt * ((uint64_t)s->S + 12);
+      *moved = Lt * ((uint64_t)s->S + 12);
+      return true;
     }
     const int dir = (fail & 1u) ? +1 : -1;
     if (dir == -1 && Lt == 1) throw Fail{CPMA_ERR_DEVICE};
@@ -696,7 +706,17 @@ uint64_t resize(cpma* s, uint64_t total, uint32_t viol, hipStream_t st) {
     spread_fresh(s, 0, 1, st);
     return 0;
   }
-  return total + split_resize(s, Lt, st);
+  uint64_t moved = 0;
+  if (split_resize(s, Lt, total, st, &moved)) return total + moved;
+  // staged fallback for structures whose split thresholds exceed 64 bits
+  uint64_t nsrc, ndst;
+  std::vector<uint64_t> sb{0}, sn{s->L};
+  std::vector<uint32_t> lv{(uint32_t)(tree_height(s->L) + 1)};
+  WinArgs wa = upload_windows(s, sb, sn, sb, sn, lv, st, nsrc, ndst);
+  const uint64_t K = pack_windows(s, wa, nsrc, st);
+  if (K != s->n) throw Fail{CPMA_ERR_DEVICE};
+  spread_fresh(s, K, Lt, st);
+  return total + Lt * ((uint64_t)s->S + 12);
 }
 
 // Counting + redistribution until every node of the implicit tree is within its
@@ -748,10 +768,14 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   ensure(s->seg_desc, (kbound + 1) * sizeof(uint4));
   ensure(s->heavy, kbound * sizeof(uint32_t));
   ensure(s->spill, kbound * sizeof(uint32_t));
+  ensure(s->wide, kbound * sizeof(uint32_t));
   ensure(s->ovf, std::max<uint64_t>(s->L, 1) * sizeof(uint64_t));
+  // overflow arena: every leaf that outgrows S holds at most S + 10 bytes per new key
   const uint64_t arena_cap = insert ? std::min<uint64_t>(s->L, kbound) * (uint64_t)(s->S + 16) + 10 * kbound + 256 : 256;
-  ensure(s->arena, arena_cap);
-  const uint64_t stage_cap = insert ? s->n + kbound + 64 : 64;
+  ensure(s->arena, arena_cap, 1.0);
+  // heavy-merge staging: each heavy slice (more than kLaneHeavy keys) stages at
+  // most its own keys plus one leaf's keys
+  const uint64_t stage_cap = insert ? kbound + (kbound / kLaneHeavy + 1) * (uint64_t)s->S + 64 : 64;
   ensure(s->stage, stage_cap * sizeof(uint64_t));
   PhaseMark pl = phase_begin(s, CPMA_PHASE_LOCATE, st);
   hipLaunchKernelGGL(k_locate, dim3(grid_for(kbound, 256, 1u << 16)), dim3(256), 0, st, B,
@@ -764,7 +788,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
                      (const uint32_t*)s->leafid.as<uint32_t>(), (const unsigned long long*)&s->dctr->kprime,
                      (const uint32_t*)s->segpos.as<uint32_t>(), kbound, s->seg_leaf.as<uint32_t>(),
                      s->seg_begin.as<uint32_t>(), s->seg_desc.as<uint4>(), (const uint32_t*)s->used.as<uint32_t>(),
-                     s->dctr);
+                     (const uint64_t*)s->head.as<uint64_t>(), s->L, B, s->dctr);
   HIPCHK(hipGetLastError());
   phase_end(s, pl, st, 24ull * kbound);
   MergeArgs a;
@@ -782,6 +806,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   a.seg_desc = s->seg_desc.as<uint4>();
   a.heavy_list = s->heavy.as<uint32_t>();
   a.spill_list = s->spill.as<uint32_t>();
+  a.wide_list = s->wide.as<uint32_t>();
   a.ctr = s->dctr;
   a.S = s->S;
   a.is_insert = insert ? 1 : 0;
@@ -791,7 +816,8 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   if (s->S <= kWaveMaxS) {
     // one wave per touched leaf; long insert slices spill to the lane merge
     const uint32_t wgrid = (uint32_t)std::min<uint64_t>(segs, (uint64_t)s->num_cus * 40);
-    hipLaunchKernelGGL(k_merge_wave, dim3(std::max(1u, wgrid)), dim3(kWave), 0, st, a);
+    hipLaunchKernelGGL(k_merge_wave<uint32_t>, dim3(std::max(1u, wgrid)), dim3(kWave), 0, st, a);
+    hipLaunchKernelGGL(k_merge_wave<uint64_t>, dim3(std::max(1u, wgrid)), dim3(kWave), 0, st, a);
     HIPCHK(hipGetLastError());
     if (insert) hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 1);
   } else {
@@ -1229,7 +1255,7 @@ void cpma_destroy(cpma* s) {
                     &s->fg_level, &s->fg_deg, &s->fg_p, &s->fg_c, &s->fg_acc, &s->lstart, &s->planU,
                     &s->plan_used, &s->win_of_leaf, &s->fail, &s->qa,        &s->qb,    &s->qfirst, &s->qnvis,
                     &s->qvoff,  &s->qsum,     &s->qcount,    &s->qout,  &s->lastk, &s->ne_rank, &s->ne_list,
-                    &s->chain_pfx, &s->srec};
+                    &s->chain_pfx, &s->srec, &s->wide};
   for (DevBuf* b : bufs) release(*b);
   if (s->dctr) hipFree(s->dctr);
   if (s->dinfo) hipFree(s->dinfo);

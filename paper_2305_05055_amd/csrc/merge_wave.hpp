@@ -7,9 +7,12 @@
 // Insert (slice of at most 64 keys, one per lane): new keys with the same rank r
 // (the number of old keys below them) form the group inserted before old key r.
 // Each old key's code is recomputed against its new predecessor (the last key of
-// its group, else the previous old key); group bytes and offsets come from LDS
-// atomics and prefix sums.  Delete (any slice length): present keys are flagged
-// by rank, and each kept key's code is recomputed against the previous kept key.
+// its group, else the previous old key).  Groups are runs of lanes, so their
+// ranks, byte totals and last keys go to 64-entry tables from DPP scans, and a
+// lane walking its block of old keys meets them in rank order.  Delete (any
+// slice length): present keys are flagged by rank in a bit mask, and each kept
+// key's code is recomputed against the previous kept key.  LDS per wave stays
+// near 10 KB (the decoded keys dominate), which keeps several waves per SIMD.
 #pragma once
 #include "leaf.hpp"
 #include "update.hpp"
@@ -26,47 +29,66 @@ __device__ __forceinline__ void put_key_bytes(uint8_t* dst, bool head, uint64_t 
     vput(dst, x - pred);
 }
 
+// KT = uint32_t: keys are stored in LDS as offsets from the segment's smallest
+// possible key (segments flagged wide are handed to the 64-bit instance), which
+// halves the dominant LDS array.  KT = uint64_t: processes the handed-over list.
+template <typename KT>
 __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
-  __shared__ uint64_t K[kWaveMaxS];
-  __shared__ uint64_t Bs[kWaveSlice];
-  __shared__ uint32_t G[kWaveMaxS + 1];
-  __shared__ uint16_t OFF[kWaveMaxS + 1];
+  constexpr bool kNarrow = sizeof(KT) == 4;
+  __shared__ KT K[kWaveMaxS];
+  __shared__ uint64_t GK[kWaveSlice];      // group g: its last key (new predecessor of old key GR[g])
+  __shared__ uint32_t GR[kWaveSlice + 1];  // group g: rank; GR[ng] closes the table
+  __shared__ uint32_t GB[kWaveSlice];      // group g: bytes of its codes
+  __shared__ uint32_t GS[kWaveSlice];      // group g: output offset
+  __shared__ uint32_t DF[kWaveMaxS / 32];  // delete flags by old index
   __shared__ __align__(16) uint8_t out[kWaveMaxS];
   const int lane = lane_id();
   const uint32_t S = a.S;
-  const uint64_t T = a.ctr->T;
+  const uint64_t T = kNarrow ? (uint64_t)a.ctr->T : (uint64_t)a.ctr->nwide;
   const uint32_t pos0 = 16u * lane;
   unsigned long long delta = 0, alg = 0;
+  auto seg_of = [&](uint64_t t) -> uint64_t { return kNarrow ? t : (uint64_t)a.wide_list[t]; };
   // Software pipeline: the next segment's descriptor, leaf bytes and batch keys
   // are loaded while the current one is merged.
   uint4 d_cur = make_uint4(0, 0, 0, 0), d_nxt = d_cur;
   uint32_t e_cur = 0, e_nxt = 0;
+  uint64_t s_cur = 0, s_nxt = 0;
   uint4 w_cur = make_uint4(0, 0, 0, 0), w_nxt = w_cur;
   uint64_t b_cur = 0, b_nxt = 0;
-  uint64_t s = blockIdx.x;
-  if (s < T) {
-    d_cur = a.seg_desc[s];
-    e_cur = a.seg_begin[s + 1];
-    if (pos0 < d_cur.z) w_cur = *reinterpret_cast<const uint4*>(a.bytes + (uint64_t)d_cur.x * S + pos0);
-    if ((uint32_t)lane < e_cur - d_cur.y) b_cur = a.B[d_cur.y + lane];
-  }
-  for (; s < T; s += gridDim.x) {
-    const uint64_t sn = s + gridDim.x;
-    if (sn < T) {
-      d_nxt = a.seg_desc[sn];
-      e_nxt = a.seg_begin[sn + 1];
+  uint64_t t = blockIdx.x;
+  if (t < T) {
+    s_cur = seg_of(t);
+    d_cur = a.seg_desc[s_cur];
+    e_cur = a.seg_begin[s_cur + 1];
+    if (!(kNarrow && d_cur.w)) {
+      if (pos0 < d_cur.z) w_cur = *reinterpret_cast<const uint4*>(a.bytes + (uint64_t)d_cur.x * S + pos0);
+      if ((uint32_t)lane < e_cur - d_cur.y) b_cur = a.B[d_cur.y + lane];
     }
+  }
+  for (; t < T; t += gridDim.x) {
+    const uint64_t tn = t + gridDim.x;
+    if (tn < T) {
+      s_nxt = seg_of(tn);
+      d_nxt = a.seg_desc[s_nxt];
+      e_nxt = a.seg_begin[s_nxt + 1];
+    }
+    const uint64_t s = s_cur;
     const uint64_t leaf = d_cur.x;
     const uint32_t b = d_cur.y, e = e_cur;
     const uint32_t nb = e - b;
     const uint32_t used0 = d_cur.z;
+    const bool wide = kNarrow && d_cur.w;
     const uint4 w = w_cur;
     const uint64_t bj0 = b_cur;
-    if (sn < T) {
+    if (tn < T) {
       w_nxt = make_uint4(0, 0, 0, 0);
-      if (pos0 < d_nxt.z) w_nxt = *reinterpret_cast<const uint4*>(a.bytes + (uint64_t)d_nxt.x * S + pos0);
-      b_nxt = ((uint32_t)lane < e_nxt - d_nxt.y) ? a.B[d_nxt.y + lane] : 0;
+      b_nxt = 0;
+      if (!(kNarrow && d_nxt.w)) {
+        if (pos0 < d_nxt.z) w_nxt = *reinterpret_cast<const uint4*>(a.bytes + (uint64_t)d_nxt.x * S + pos0);
+        if ((uint32_t)lane < e_nxt - d_nxt.y) b_nxt = a.B[d_nxt.y + lane];
+      }
     }
+    s_cur = s_nxt;
     d_cur = d_nxt;
     e_cur = e_nxt;
     w_cur = w_nxt;
@@ -75,9 +97,23 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
       if (lane == 0) a.spill_list[atomicAdd(&a.ctr->nspill, 1u)] = (uint32_t)s;
       continue;
     }
+    if (wide) {
+      if (lane == 0) a.wide_list[atomicAdd(&a.ctr->nwide, 1u)] = (uint32_t)s;
+      continue;
+    }
+    // smallest possible key of the segment: the old head or the first slice key
+    uint64_t base = 0;
+    if (kNarrow) {
+      const uint64_t hd = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)w.y, 0) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)w.x, 0);
+      const uint64_t b0 = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bj0 >> 32), 0) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bj0, 0);
+      base = used0 ? min(hd, b0) : b0;
+    }
+    auto key = [&](uint32_t i) -> uint64_t { return base + (uint64_t)K[i]; };
     const uint64_t* Bg = a.B + b;
     uint8_t* lp = a.bytes + leaf * (uint64_t)S;
-    const uint32_t nA = wave_decode_regs(w, used0, [&](uint32_t i, uint64_t x, uint64_t) { K[i] = x; });
+    const uint32_t nA = wave_decode_regs(w, used0, [&](uint32_t i, uint64_t x, uint64_t) { K[i] = (KT)(x - base); });
     wave_zero(out, S);
     // lane-contiguous block of old-key indices [i0, i1) over [0, nA] (index nA: trailing group)
     const uint32_t m = (nA + 1 + kWave - 1) / kWave;
@@ -90,14 +126,12 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
     if (a.is_insert) {
       const bool has_b = (uint32_t)lane < nb;
       const uint64_t bj = has_b ? bj0 : 0;
-      if (has_b) Bs[lane] = bj;
-      for (uint32_t i = lane; i <= nA; i += kWave) G[i] = 0xffu;
-      __syncthreads();
       uint32_t r = 0xffffffffu;
       bool isnew = false;
       if (has_b) {
-        r = (uint32_t)lds_lower_bound(K, nA, bj);
-        isnew = !(r < nA && K[r] == bj);
+        const KT xb = (KT)(bj - base);
+        r = lds_lower_bound<KT>(K, nA, xb);
+        isnew = !(r < nA && K[r] == xb);
       }
       const uint64_t b_prev = dpp_prev64(bj);
       const uint32_t r_prev = dpp_prev32(r);
@@ -113,33 +147,52 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
           pred = b_prev;
           has_pred = true;
         } else if (r > 0) {
-          pred = K[r - 1];
+          pred = key(r - 1);
           has_pred = true;
         }
       }
       const uint32_t cost = isnew ? (has_pred ? vlen(bj - pred) : 8u) : 0u;
       const uint32_t incl = dpp_incl_scan<uint32_t>(cost);
       const uint32_t ex = incl - cost;
-      if (isnew) {
-        atomicAdd(&G[r], cost << 8);
-        if (!same_next) atomicAnd(&G[r], 0xffffff00u | (uint32_t)lane);
-        if (!same_prev) atomicOr(&G[r], ex << 20);
+      const bool gstart = isnew && !same_prev;
+      const uint64_t smask = __ballot(gstart);
+      const uint32_t ng = (uint32_t)__popcll(smask);
+      const uint32_t gid = (uint32_t)__popcll(smask & ((2ull << lane) - 1ull)) - 1u;
+      const uint32_t exfirst = dpp_incl_max(gstart ? ex : 0u);  // ex of the group's first lane
+      if (gstart) GR[gid] = r;
+      if (isnew && !same_next) {
+        GB[gid] = incl - exfirst;
+        GK[gid] = bj;
       }
+      if (lane == 0) GR[ng] = 0xffffffffu;
       const uint64_t newmask = __ballot(isnew);
       const uint32_t nnew = (uint32_t)__popcll(newmask);
       __syncthreads();
+      // first group at or after this lane's block
+      uint32_t p0 = 0;
+      {
+        uint32_t hi = ng;
+        while (p0 < hi) {
+          const uint32_t mid = (p0 + hi) >> 1;
+          if (GR[mid] < i0)
+            p0 = mid + 1;
+          else
+            hi = mid;
+        }
+      }
       // sweep 1: bytes per index (group before old key i, then old key i)
       uint32_t lt = 0;
+      uint32_t p = p0;
       for (uint32_t i = i0; i < i1; i++) {
-        const uint32_t g = G[i];
-        uint32_t t = (g >> 8) & 0xfffu;
+        const bool gh = GR[p] == i;
+        uint32_t t = gh ? GB[p] : 0u;
         if (i < nA) {
-          const uint32_t lj = g & 0xffu;
-          const bool hp = lj != 0xffu || i > 0;
-          const uint64_t np = lj != 0xffu ? Bs[lj] : (i > 0 ? K[i - 1] : 0);
-          t += hp ? vlen(K[i] - np) : 8u;
+          const bool hp = gh || i > 0;
+          const uint64_t np = gh ? GK[p] : (i > 0 ? key(i - 1) : 0);
+          t += hp ? vlen(key(i) - np) : 8u;
         }
         lt += t;
+        p += gh ? 1u : 0u;
       }
       const uint32_t lincl = dpp_incl_scan<uint32_t>(lt);
       U = lane63_u32(lincl);
@@ -158,55 +211,59 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
       }
       // sweep 2: write old keys, record group starts
       uint32_t run = lincl - lt;
+      p = p0;
       for (uint32_t i = i0; i < i1; i++) {
-        const uint32_t g = G[i];
-        const uint32_t gb = (g >> 8) & 0xfffu;
-        OFF[i] = (uint16_t)min(run, 0xffffu);
+        const bool gh = GR[p] == i;
+        const uint32_t gb = gh ? GB[p] : 0u;
+        if (gh) GS[p] = run;
         if (i < nA) {
-          const uint32_t lj = g & 0xffu;
-          const bool hp = lj != 0xffu || i > 0;
-          const uint64_t np = lj != 0xffu ? Bs[lj] : (i > 0 ? K[i - 1] : 0);
-          const uint64_t x = K[i];
+          const bool hp = gh || i > 0;
+          const uint64_t np = gh ? GK[p] : (i > 0 ? key(i - 1) : 0);
+          const uint64_t x = key(i);
           const uint32_t c = hp ? vlen(x - np) : 8u;
           put_key_bytes(dst + run + gb, !hp, x, np);
           run += gb + c;
         } else {
           run += gb;
         }
+        p += gh ? 1u : 0u;
       }
       __syncthreads();
       // new keys: group start + offset inside the group
-      if (isnew) {
-        const uint32_t gstart = OFF[r];
-        const uint32_t exfirst = G[r] >> 20;
-        put_key_bytes(dst + gstart + (ex - exfirst), !has_pred, bj, pred);
+      if (isnew) put_key_bytes(dst + GS[gid] + (ex - exfirst), !has_pred, bj, pred);
+      uint64_t firstnew = kNoKey;
+      if (nnew) {
+        const int fl = __ffsll((unsigned long long)newmask) - 1;
+        firstnew = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bj >> 32), fl) << 32) |
+                   (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bj, fl);
       }
-      const uint64_t firstnew = nnew ? Bs[__ffsll((unsigned long long)newmask) - 1] : kNoKey;
-      first_key = nA ? min(K[0], firstnew) : firstnew;
+      first_key = nA ? min(key(0), firstnew) : firstnew;
       delta += nnew;
     } else {
-      for (uint32_t i = lane; i < nA; i += kWave) G[i] = 0;
+      for (uint32_t i = lane; i < kWaveMaxS / 32; i += kWave) DF[i] = 0;
       __syncthreads();
       for (uint32_t c0 = 0; c0 < nb; c0 += kWave) {
         const uint32_t j = c0 + lane;
         if (j < nb) {
           const uint64_t x = Bg[j];
-          const uint32_t r = (uint32_t)lds_lower_bound(K, nA, x);
-          if (r < nA && K[r] == x) G[r] = 1;
+          const KT xr = (KT)(x - base);
+          const uint32_t r = lds_lower_bound<KT>(K, nA, xr);
+          if (r < nA && K[r] == xr) atomicOr(&DF[r >> 5], 1u << (r & 31));
         }
       }
       __syncthreads();
+      auto gone = [&](uint32_t i) { return (DF[i >> 5] >> (i & 31)) & 1u; };
       // last kept index (+1) inside this lane's block, then across lanes
       uint32_t lastk = 0, lt = 0, nrem = 0;
       for (uint32_t i = i0; i < min(i1, nA); i++) {
-        if (!G[i]) lastk = i + 1;
+        if (!gone(i)) lastk = i + 1;
         else nrem++;
       }
       const uint32_t pk_in = dpp_prev32(dpp_incl_max(lastk));  // 0 = none before this block
       uint32_t pk = pk_in;
       for (uint32_t i = i0; i < min(i1, nA); i++) {
-        if (G[i]) continue;
-        lt += pk ? vlen(K[i] - K[pk - 1]) : 8u;
+        if (gone(i)) continue;
+        lt += pk ? vlen(key(i) - key(pk - 1)) : 8u;
         pk = i + 1;
       }
       const uint32_t lincl = dpp_incl_scan<uint32_t>(lt);
@@ -214,9 +271,9 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
       uint32_t run = lincl - lt;
       pk = pk_in;
       for (uint32_t i = i0; i < min(i1, nA); i++) {
-        if (G[i]) continue;
-        const uint64_t x = K[i];
-        const uint64_t np = pk ? K[pk - 1] : 0;
+        if (gone(i)) continue;
+        const uint64_t x = key(i);
+        const uint64_t np = pk ? key(pk - 1) : 0;
         put_key_bytes(out + run, pk == 0, x, np);
         run += pk ? vlen(x - np) : 8u;
         pk = i + 1;
@@ -224,13 +281,13 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
       // smallest kept key: the key at the first index whose flag is clear
       uint32_t fk = 0xffffffffu;
       for (uint32_t i = i0; i < min(i1, nA); i++)
-        if (!G[i]) {
+        if (!gone(i)) {
           fk = i;
           break;
         }
       uint32_t fkmin = fk;
       for (int d = 32; d > 0; d >>= 1) fkmin = min(fkmin, (uint32_t)__shfl_xor((int)fkmin, d, kWave));
-      first_key = (fkmin != 0xffffffffu) ? K[fkmin] : kNoKey;
+      first_key = (fkmin != 0xffffffffu) ? key(fkmin) : kNoKey;
       delta += wave_sum(nrem);
     }
     __syncthreads();

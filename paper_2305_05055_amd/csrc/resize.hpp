@@ -19,6 +19,7 @@
 // copy, the same layout as the staged spread produces.
 #pragma once
 #include "leaf.hpp"
+#include "scan_lane.hpp"
 #include "update.hpp"
 
 namespace cpma_dev {
@@ -32,21 +33,70 @@ struct SplitRec {
   uint32_t cost;  // its chain cost
 };
 
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+// Last key of a leaf: the head plus every delta, one lane per leaf streaming
+// the leaf in 16-byte chunks.  A code's value is the sum of its payload groups
+// shifted by 7 bits per byte, so the running total needs no per-key step.
+// Narrow form: every delta is below 2^28 (32-bit shifts).
+__device__ __forceinline__ uint64_t leaf_last_narrow(const uint8_t* __restrict__ leaf, uint32_t used,
+                                                     uint64_t head) {
+  uint64_t last = head;
+  uint32_t sh = 0;
+  uint4 cur = load16(leaf);
+  for (uint32_t c = 0; c < used; c += 16) {
+    uint4 nxt = make_uint4(0, 0, 0, 0);
+    if (c + 16 < used) nxt = load16(leaf + c + 16);
+    const uint32_t words[4] = {cur.x, cur.y, cur.z, cur.w};
+    const uint32_t nvalid = min(16u, used - c);
+    uint32_t Dc = 0;
 #pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, d, kWave));
-  return v;
+    for (int i = 0; i < 16; i++) {
+      const uint32_t w = words[i >> 2];
+      const int o = 8 * (i & 3);
+      const bool valid = (uint32_t)i < nvalid && !(c == 0 && i < 8);
+      const uint32_t pb = valid ? ((w >> o) & 0x7fu) : 0u;
+      const bool term = !((w >> (o + 7)) & 1u);
+      Dc += pb << sh;
+      sh = !valid ? sh : (term ? 0u : sh + 7u);
+    }
+    last += Dc;
+    cur = nxt;
+  }
+  return last;
 }
 
-// lastk[f] = last key of every non-empty old leaf (the sum of all its deltas).
-__global__ void __launch_bounds__(kWave) k_leaf_last(SrcLeaves src, uint64_t L, uint64_t* __restrict__ lastk) {
-  for (uint64_t f = blockIdx.x; f < L; f += gridDim.x) {
+__device__ __forceinline__ uint64_t leaf_last_wide(const uint8_t* __restrict__ leaf, uint32_t used, uint64_t head) {
+  uint64_t last = head;
+  uint32_t sh = 0;
+  for (uint32_t c = 0; c < used; c += 16) {
+    const uint4 cur = load16(leaf + c);
+    const uint32_t words[4] = {cur.x, cur.y, cur.z, cur.w};
+    const uint32_t nvalid = min(16u, used - c);
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      const uint32_t b = (words[i >> 2] >> (8 * (i & 3))) & 0xffu;
+      const bool valid = (uint32_t)i < nvalid && !(c == 0 && i < 8);
+      if (valid) {
+        if (sh < 64) last += (uint64_t)(b & 0x7fu) << sh;
+        sh = (b & 0x80u) ? sh + 7u : 0u;
+      }
+    }
+  }
+  return last;
+}
+
+// lastk[f] = last key of every non-empty old leaf.  head[f + 1] bounds the keys
+// of leaf f from above (an empty leaf keeps a head above every earlier key), so
+// a span below 2^28 selects the narrow decoder.
+__global__ void __launch_bounds__(256) k_leaf_last(SrcLeaves src, const uint64_t* __restrict__ head, uint64_t L,
+                                                   uint64_t* __restrict__ lastk) {
+  for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < L;
+       f += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t u = src.used[f];
     if (u == 0) continue;
-    uint64_t sum = 0;
-    wave_decode_leaf(src.ptr(f, u), u, [&](uint32_t, uint64_t, uint64_t d) { sum += d; });
-    sum = wave_sum(sum);
-    if (lane_id() == 0) lastk[f] = sum;
+    const uint64_t h = head[f];
+    const uint64_t nx = f + 1 < L ? head[f + 1] : ~0ull;
+    const uint8_t* p = src.ptr(f, u);
+    lastk[f] = (nx > h && nx - h < (1ull << 28)) ? leaf_last_narrow(p, u, h) : leaf_last_wide(p, u, h);
   }
 }
 
@@ -94,66 +144,93 @@ struct SplitArgs {
   uint64_t Lt;            // destination leaves
 };
 
+// ceil(j * total / Lt); the caller guarantees total * Lt < 2^63.
+__device__ __forceinline__ uint64_t split_threshold(uint64_t j, uint64_t total, uint64_t Lt) {
+  return (j * total + Lt - 1) / Lt;
+}
+
+__device__ __forceinline__ void put_rec(SplitRec* rec, uint64_t j, uint64_t leaf, uint64_t x, uint64_t P, uint32_t p,
+                                        uint32_t cost) {
+  SplitRec R;
+  R.leaf = leaf;
+  R.x = x;
+  R.P = P;
+  R.p = p;
+  R.cost = cost;
+  rec[j] = R;
+}
+
 // rec[j] for j in [0, Lt]: the first key of destination leaf j (rec[Lt] = end).
-__global__ void __launch_bounds__(kWave) k_split_locate(SplitArgs a, SplitRec* __restrict__ rec) {
+// One lane per old leaf f writes the records of the thresholds in
+// [CP[f], CP[f + 1]): j from floor((CP[f] - 1) Lt / total) + 1 (0 when
+// CP[f] = 0) up to, excluding, the same bound for CP[f + 1].  Thresholds past
+// the last code of f fall on the head of the next non-empty leaf.
+__global__ void __launch_bounds__(256) k_split_locate(SplitArgs a, SplitRec* __restrict__ rec) {
   const uint64_t total = a.CP[a.L];
-  const uint64_t q = total / a.Lt, rem = total % a.Lt;
-  for (uint64_t j = blockIdx.x; j <= a.Lt; j += gridDim.x) {
-    SplitRec R;
-    R.leaf = a.L;
-    R.x = 0;
-    R.P = total;
-    R.p = 0;
-    R.cost = 0;
-    bool mine = lane_id() == 0;
-    // T = ceil(j * total / Lt) without a 128-bit product (j * rem < Lt^2)
-    const uint64_t T = (j == a.Lt) ? total : j * q + (j * rem + a.Lt - 1) / a.Lt;
-    if (T < total) {
-      // CP[f] <= T < CP[f + 1]: leaf f is not empty
-      const uint64_t f = upper_bound_u64(a.CP, a.L + 1, T) - 1;
-      const uint32_t u = a.src.used[f];
-      const uint64_t hc = a.CP[f + 1] - a.CP[f] - (u - 8u);
-      uint64_t hf = f;  // leaf whose head is the key, if it is a head
-      if (a.CP[f] != T) {
-        hf = a.L;
-        // first code that starts at byte >= b
-        const uint64_t over = T - a.CP[f];
-        const uint32_t b = over <= hc ? 8u : (uint32_t)(over - hc + 8u);
-        uint32_t best = 0xffffffffu, bc = 0;
-        uint64_t bx = 0;
-        wave_decode_leaf(a.src.ptr(f, u), u, [&](uint32_t idx, uint64_t key, uint64_t d, uint32_t end) {
-          if (idx == 0) return;
-          const uint32_t len = vlen(d);
-          const uint32_t start = end + 1u - len;
-          if (start >= b && start < best) {
-            best = start;
-            bx = key;
-            bc = len;
+  const uint64_t Lt = a.Lt;
+  for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < a.L;
+       f += (uint64_t)gridDim.x * blockDim.x) {
+    if (f == 0) {
+      // thresholds at or past the total: the end record
+      for (uint64_t j = (total - 1) * Lt / total + 1; j <= Lt; j++) put_rec(rec, j, a.L, 0, total, 0, 0);
+    }
+    const uint32_t u = a.src.used[f];
+    if (u == 0) continue;
+    const uint64_t c0 = a.CP[f], c1 = a.CP[f + 1];
+    uint64_t j = c0 == 0 ? 0 : (c0 - 1) * Lt / total + 1;
+    const uint64_t jend = (c1 - 1) * Lt / total + 1;
+    if (j >= jend) continue;
+    const uint32_t hc = (uint32_t)(c1 - c0 - (u - 8u));
+    const uint64_t h = a.head[f];
+    uint64_t T = split_threshold(j, total, Lt);
+    if (T == c0) {
+      put_rec(rec, j, f, h, c0, 0, hc);
+      j++;
+      T = split_threshold(j, total, Lt);
+    }
+    if (j >= jend) continue;
+    // walk the codes of f: the code starting at byte s has chain prefix c0 + hc + s - 8
+    const uint8_t* leaf = a.src.ptr(f, u);
+    uint64_t key = h, acc = 0;
+    uint32_t sh = 0, start = 8;
+    for (uint32_t c = 0; c < u && j < jend; c += 16) {
+      const uint4 cur = load16(leaf + c);
+      const uint32_t words[4] = {cur.x, cur.y, cur.z, cur.w};
+      const uint32_t nvalid = min(16u, u - c);
+#pragma unroll
+      for (int i = 0; i < 16; i++) {
+        const uint32_t b = (words[i >> 2] >> (8 * (i & 3))) & 0xffu;
+        const bool valid = (uint32_t)i < nvalid && !(c == 0 && i < 8);
+        if (valid && j < jend) {
+          if (sh < 64) acc |= (uint64_t)(b & 0x7fu) << sh;
+          sh += 7;
+          if (!(b & 0x80u)) {
+            key += acc;
+            const uint64_t P = c0 + hc + start - 8u;
+            const uint32_t end = c + (uint32_t)i;
+            while (j < jend && P >= T) {
+              put_rec(rec, j, f, key, P, start, end + 1u - start);
+              j++;
+              T = split_threshold(j, total, Lt);
+            }
+            acc = 0;
+            sh = 0;
+            start = end + 1u;
           }
-        });
-        const uint32_t bmin = wave_min_u32(best);
-        if (bmin != 0xffffffffu) {
-          mine = best == bmin;
-          R.leaf = f;
-          R.x = bx;
-          R.P = a.CP[f] + hc + bmin - 8u;
-          R.p = bmin;
-          R.cost = bc;
-        } else if (a.CP[f + 1] < total) {
-          // no code of leaf f qualifies: the head of the next non-empty leaf
-          hf = a.ne[a.rank[f] + 1];
         }
       }
+    }
+    if (j < jend) {
+      const uint64_t hf = a.ne[a.rank[f] + 1];
       if (hf < a.L) {
         const uint32_t uf = a.src.used[hf];
-        R.leaf = hf;
-        R.x = a.head[hf];
-        R.P = a.CP[hf];
-        R.p = 0;
-        R.cost = (uint32_t)(a.CP[hf + 1] - a.CP[hf] - (uf - 8u));
+        const uint64_t cf = a.CP[hf];
+        const uint32_t hcf = (uint32_t)(a.CP[hf + 1] - cf - (uf - 8u));
+        for (; j < jend; j++) put_rec(rec, j, hf, a.head[hf], cf, 0, hcf);
+      } else {
+        for (; j < jend; j++) put_rec(rec, j, a.L, 0, total, 0, 0);
       }
     }
-    if (mine) rec[j] = R;
   }
 }
 

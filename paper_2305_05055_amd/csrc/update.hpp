@@ -22,6 +22,7 @@ struct Counters {
   unsigned int error;               // internal capacity overflow (bug guard)
   unsigned int nspill;              // segments the wave merge hands to the lane merge
   unsigned int found;               // vertices claimed by a BFS step
+  unsigned int nwide;               // segments whose key span needs 64-bit merge keys
   unsigned long long alg_bytes;     // algorithmic HBM bytes of the merge (statistics)
   unsigned long long alg_bytes_q;   // algorithmic HBM bytes of range scans (statistics)
 };
@@ -75,19 +76,26 @@ struct SegFlag {
 
 // Touched leaves: one segment per run of equal leaf ids (the batch slice bound
 // for each leaf, which the paper finds with two exponential searches).
+// A segment is wide when its old keys and slice keys can span more than 2^32:
+// they lie in [min(head, first slice key), head of the next leaf).
 __global__ void k_segments(const uint32_t* __restrict__ leafid, const unsigned long long* kprime,
                            const uint32_t* __restrict__ segpos, uint64_t kbound,
                            uint32_t* __restrict__ seg_leaf, uint32_t* __restrict__ seg_begin,
                            uint4* __restrict__ seg_desc, const uint32_t* __restrict__ used,
+                           const uint64_t* __restrict__ head, uint64_t L, const uint64_t* __restrict__ B,
                            Counters* ctr) {
   const uint64_t k = *kprime;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
        i += (uint64_t)gridDim.x * blockDim.x) {
     if (i == 0 || leafid[i] != leafid[i - 1]) {
       const uint32_t lf = leafid[i];
+      const uint32_t u = used[lf];
+      const uint64_t lo = u ? min(head[lf], B[i]) : B[i];
+      const uint64_t hi = lf + 1 < L ? head[lf + 1] : ~0ull;
+      const uint32_t wide = (hi - lo > (1ull << 32)) ? 1u : 0u;
       seg_leaf[segpos[i]] = lf;
       seg_begin[segpos[i]] = (uint32_t)i;
-      seg_desc[segpos[i]] = make_uint4(lf, (uint32_t)i, used[lf], 0u);
+      seg_desc[segpos[i]] = make_uint4(lf, (uint32_t)i, u, wide);
     }
     if (i == 0) {
       uint32_t T = segpos[kbound];
@@ -110,15 +118,17 @@ struct MergeArgs {
   const uint64_t* B;      // sorted, repeat-free batch
   const uint32_t* seg_leaf;
   const uint32_t* seg_begin;
-  const uint4* seg_desc;  // {leaf, slice begin, used before the merge, 0}
+  const uint4* seg_desc;  // {leaf, slice begin, used before the merge, wide span}
   uint32_t* heavy_list;
   uint32_t* spill_list;   // segments routed from the wave merge to the lane merge
+  uint32_t* wide_list;    // segments whose keys span more than 2^32
   Counters* ctr;
   uint32_t S;
   int is_insert;
 };
 
-__device__ __forceinline__ uint64_t lds_lower_bound(const uint64_t* A, uint32_t n, uint64_t x) {
+template <typename KT>
+__device__ __forceinline__ uint32_t lds_lower_bound(const KT* A, uint32_t n, KT x) {
   uint32_t lo = 0, hi = n;
   while (lo < hi) {
     uint32_t mid = (lo + hi) >> 1;
