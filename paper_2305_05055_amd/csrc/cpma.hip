@@ -778,17 +778,35 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   const uint64_t stage_cap = insert ? kbound + (kbound / kLaneHeavy + 1) * (uint64_t)s->S + 64 : 64;
   ensure(s->stage, stage_cap * sizeof(uint64_t));
   PhaseMark pl = phase_begin(s, CPMA_PHASE_LOCATE, st);
-  hipLaunchKernelGGL(k_locate, dim3(grid_for(kbound, 256, 1u << 16)), dim3(256), 0, st, B,
-                     (const unsigned long long*)&s->dctr->kprime, (const uint64_t*)s->head.as<uint64_t>(), s->L,
-                     s->leafid.as<uint32_t>());
-  HIPCHK(hipGetLastError());
-  scan<uint32_t>(s, s->segpos.as<uint32_t>(), kbound, st,
-                 SegFlag{s->leafid.as<uint32_t>(), (const unsigned long long*)&s->dctr->kprime});
-  hipLaunchKernelGGL(k_segments, dim3(grid_for(kbound, 256, 1u << 16)), dim3(256), 0, st,
-                     (const uint32_t*)s->leafid.as<uint32_t>(), (const unsigned long long*)&s->dctr->kprime,
-                     (const uint32_t*)s->segpos.as<uint32_t>(), kbound, s->seg_leaf.as<uint32_t>(),
-                     s->seg_begin.as<uint32_t>(), s->seg_desc.as<uint4>(), (const uint32_t*)s->used.as<uint32_t>(),
-                     (const uint64_t*)s->head.as<uint64_t>(), s->L, B, s->dctr);
+  const uint64_t L = s->L;
+  if (kbound >= L) {
+    // per leaf: one search of head[f] in the batch
+    ensure(s->leafid, (L + 1) * sizeof(uint32_t));
+    ensure(s->segpos, (std::max(kbound, L) + 1) * sizeof(uint32_t));
+    hipLaunchKernelGGL(k_leaf_slices, dim3(grid_for(L + 1, 256, 1u << 16)), dim3(256), 0, st, B,
+                       (const unsigned long long*)&s->dctr->kprime, (const uint64_t*)s->head.as<uint64_t>(), L,
+                       s->leafid.as<uint32_t>());
+    HIPCHK(hipGetLastError());
+    scan<uint32_t>(s, s->segpos.as<uint32_t>(), L, st, SliceFlag{s->leafid.as<uint32_t>()});
+    hipLaunchKernelGGL(k_segments_by_leaf, dim3(grid_for(L + 1, 256, 1u << 16)), dim3(256), 0, st,
+                       (const uint32_t*)s->leafid.as<uint32_t>(), (const unsigned long long*)&s->dctr->kprime,
+                       (const uint32_t*)s->segpos.as<uint32_t>(), L, s->seg_leaf.as<uint32_t>(),
+                       s->seg_begin.as<uint32_t>(), s->seg_desc.as<uint4>(), (const uint32_t*)s->used.as<uint32_t>(),
+                       (const uint64_t*)s->head.as<uint64_t>(), B, s->dctr);
+  } else {
+    // per key: one search of the key in the heads
+    hipLaunchKernelGGL(k_locate, dim3(grid_for(kbound, 256, 1u << 16)), dim3(256), 0, st, B,
+                       (const unsigned long long*)&s->dctr->kprime, (const uint64_t*)s->head.as<uint64_t>(), L,
+                       s->leafid.as<uint32_t>());
+    HIPCHK(hipGetLastError());
+    scan<uint32_t>(s, s->segpos.as<uint32_t>(), kbound, st,
+                   SegFlag{s->leafid.as<uint32_t>(), (const unsigned long long*)&s->dctr->kprime});
+    hipLaunchKernelGGL(k_segments, dim3(grid_for(kbound, 256, 1u << 16)), dim3(256), 0, st,
+                       (const uint32_t*)s->leafid.as<uint32_t>(), (const unsigned long long*)&s->dctr->kprime,
+                       (const uint32_t*)s->segpos.as<uint32_t>(), kbound, s->seg_leaf.as<uint32_t>(),
+                       s->seg_begin.as<uint32_t>(), s->seg_desc.as<uint4>(), (const uint32_t*)s->used.as<uint32_t>(),
+                       (const uint64_t*)s->head.as<uint64_t>(), L, B, s->dctr);
+  }
   HIPCHK(hipGetLastError());
   phase_end(s, pl, st, 24ull * kbound);
   MergeArgs a;

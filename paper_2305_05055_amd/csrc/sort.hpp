@@ -40,11 +40,16 @@ __global__ void __launch_bounds__(256) k_validate(const uint64_t* __restrict__ k
   if (lane_id() == 0) fl[wid] = (uint32_t)flags;
   __syncthreads();
   if (threadIdx.x == 0) {
+    // one atomic per block and field, and only while it still adds bits (a
+    // stale read only costs a redundant atomic)
     const uint64_t o = red[0] | red[1] | red[2] | red[3];
     const uint32_t f = fl[0] | fl[1] | fl[2] | fl[3];
-    if (o) atomicOr(&info->or_all, (unsigned long long)o);
-    if (f & 1) atomicOr(&info->has_reserved, 1u);
-    if (f & 2) atomicOr(&info->unsorted, 1u);
+    if (o & ~__hip_atomic_load(&info->or_all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicOr(&info->or_all, (unsigned long long)o);
+    if ((f & 1) && !__hip_atomic_load(&info->has_reserved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicOr(&info->has_reserved, 1u);
+    if ((f & 2) && !__hip_atomic_load(&info->unsorted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicOr(&info->unsorted, 1u);
   }
 }
 
@@ -64,31 +69,43 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t* __r
   ghist[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// Scatter with stable in-block ranks.  Keys are visited round by round (round r
-// holds tile positions r*256 .. r*256+255); inside a round a lane's rank among
-// equal digits comes from eight ballots, across waves from per-wave digit counts,
-// across rounds from a running per-digit count.
+// Scatter of one tile (kSortTile keys) with stable ranks, written out in digit
+// order.  Wave w ranks its own contiguous quarter of the tile (round r, lane l
+// holds key w * 1024 + 64 r + l): a lane's rank among equal digits in a round
+// comes from eight ballots, and wave-private digit counters in LDS carry it
+// across rounds, so no barrier is needed while ranking.  The tile is then
+// placed in LDS in digit order and written with consecutive threads on
+// consecutive output positions inside each digit's run.
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint64_t* __restrict__ in,
                                                                 uint64_t* __restrict__ out,
                                                                 uint32_t n, int shift,
                                                                 const uint32_t* __restrict__ goff) {
   constexpr int kW = kSortThreads / kWave;
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t wcnt[kW][256];
-  __shared__ uint32_t base_ofs[256];
+  constexpr int kRounds = kSortTile / kSortThreads;  // rounds per wave (16)
+  __shared__ uint64_t tile[kSortTile];
+  __shared__ uint32_t cnt[kW][256];
+  __shared__ uint32_t toff[256];
+  __shared__ uint32_t gbase[256];
+  __shared__ uint32_t wsum[kW];
   const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
-  run[tid] = 0;
 #pragma unroll
-  for (int w = 0; w < kW; w++) wcnt[w][tid] = 0;
-  base_ofs[tid] = goff[(uint64_t)tid * gridDim.x + blockIdx.x];
+  for (int w = 0; w < kW; w++) cnt[w][tid] = 0;
+  gbase[tid] = goff[(uint64_t)tid * gridDim.x + blockIdx.x];
   __syncthreads();
   const uint32_t base = blockIdx.x * kSortTile;
+  const uint32_t wbase = base + (uint32_t)wid * (kRounds * kWave);
   const uint64_t lt_mask = (1ull << lane) - 1ull;
-  for (int r = 0; r < kSortItems; r++) {
-    const uint32_t i = base + r * kSortThreads + tid;
-    const bool valid = i < n;
-    const uint64_t x = valid ? in[i] : 0;
-    const uint32_t d = (uint32_t)(x >> shift) & 255u;
+  uint64_t x[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; r++) {
+    const uint32_t i = wbase + (uint32_t)r * kWave + lane;
+    x[r] = i < n ? in[i] : 0;
+  }
+  uint32_t rk[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; r++) {
+    const bool valid = wbase + (uint32_t)r * kWave + lane < n;
+    const uint32_t d = (uint32_t)(x[r] >> shift) & 255u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; b++) {
@@ -96,23 +113,48 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint64_t* 
       const uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
     }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-    if (valid && rank == 0) wcnt[wid][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = base_ofs[d] + run[d] + rank;
-      for (int w = 0; w < wid; w++) pos += wcnt[w][d];
-      out[pos] = x;
-    }
-    __syncthreads();
-    uint32_t add = 0;
+    const uint32_t below = (uint32_t)__popcll(peers & lt_mask);
+    uint32_t pre = 0;
+    if (valid) pre = cnt[wid][d];
+    rk[r] = pre + below;
+    if (valid && below == 0) cnt[wid][d] = pre + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // tile offsets of every digit (exclusive scan over 256 digits) and of every
+  // wave's share of it
+  uint32_t tot = 0;
 #pragma unroll
-    for (int w = 0; w < kW; w++) {
-      add += wcnt[w][tid];
-      wcnt[w][tid] = 0;
+  for (int w = 0; w < kW; w++) tot += cnt[w][tid];
+  const uint32_t incl = wave_incl_scan(tot);
+  if (lane == kWave - 1) wsum[wid] = incl;
+  __syncthreads();
+  uint32_t wofs = 0;
+#pragma unroll
+  for (int w = 0; w < kW; w++)
+    if (w < wid) wofs += wsum[w];
+  const uint32_t ex = wofs + incl - tot;
+  toff[tid] = ex;
+  uint32_t run = ex;
+#pragma unroll
+  for (int w = 0; w < kW; w++) {
+    const uint32_t c = cnt[w][tid];
+    cnt[w][tid] = run;  // becomes the wave's first slot for digit tid
+    run += c;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRounds; r++) {
+    if (wbase + (uint32_t)r * kWave + lane < n) {
+      const uint32_t d = (uint32_t)(x[r] >> shift) & 255u;
+      tile[cnt[wid][d] + rk[r]] = x[r];
     }
-    run[tid] += add;
-    __syncthreads();
+  }
+  __syncthreads();
+  const uint32_t m = min(kSortTile, n - base);
+  for (uint32_t i = tid; i < m; i += kSortThreads) {
+    const uint64_t v = tile[i];
+    const uint32_t d = (uint32_t)(v >> shift) & 255u;
+    out[gbase[d] + (i - toff[d])] = v;
   }
 }
 

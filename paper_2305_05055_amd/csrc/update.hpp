@@ -78,6 +78,13 @@ struct SegFlag {
 // for each leaf, which the paper finds with two exponential searches).
 // A segment is wide when its old keys and slice keys can span more than 2^32:
 // they lie in [min(head, first slice key), head of the next leaf).
+__device__ __forceinline__ uint32_t seg_wide(const uint32_t* used, const uint64_t* head, uint64_t L, uint32_t lf,
+                                             uint64_t bfirst) {
+  const uint64_t lo = used[lf] ? min(head[lf], bfirst) : bfirst;
+  const uint64_t hi = lf + 1 < L ? head[lf + 1] : ~0ull;
+  return (hi - lo > (1ull << 32)) ? 1u : 0u;
+}
+
 __global__ void k_segments(const uint32_t* __restrict__ leafid, const unsigned long long* kprime,
                            const uint32_t* __restrict__ segpos, uint64_t kbound,
                            uint32_t* __restrict__ seg_leaf, uint32_t* __restrict__ seg_begin,
@@ -89,18 +96,52 @@ __global__ void k_segments(const uint32_t* __restrict__ leafid, const unsigned l
        i += (uint64_t)gridDim.x * blockDim.x) {
     if (i == 0 || leafid[i] != leafid[i - 1]) {
       const uint32_t lf = leafid[i];
-      const uint32_t u = used[lf];
-      const uint64_t lo = u ? min(head[lf], B[i]) : B[i];
-      const uint64_t hi = lf + 1 < L ? head[lf + 1] : ~0ull;
-      const uint32_t wide = (hi - lo > (1ull << 32)) ? 1u : 0u;
       seg_leaf[segpos[i]] = lf;
       seg_begin[segpos[i]] = (uint32_t)i;
-      seg_desc[segpos[i]] = make_uint4(lf, (uint32_t)i, u, wide);
+      seg_desc[segpos[i]] = make_uint4(lf, (uint32_t)i, used[lf], seg_wide(used, head, L, lf, B[i]));
     }
     if (i == 0) {
       uint32_t T = segpos[kbound];
       seg_begin[T] = (uint32_t)k;
       ctr->T = T;
+    }
+  }
+}
+
+// Large batches: the same segments found per leaf instead of per key.  Leaf f
+// owns the batch keys in [head[f], head[f + 1]) (leaf 0 also those below every
+// head, the last leaf those above), so its slice starts at the first batch key
+// >= head[f]: L searches in the batch instead of k' searches in the heads.
+__global__ void k_leaf_slices(const uint64_t* __restrict__ B, const unsigned long long* kprime,
+                              const uint64_t* __restrict__ head, uint64_t L, uint32_t* __restrict__ sbeg) {
+  const uint64_t k = *kprime;
+  for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f <= L;
+       f += (uint64_t)gridDim.x * blockDim.x)
+    sbeg[f] = (uint32_t)(f == 0 ? 0 : (f == L ? k : lower_bound_u64(B, k, head[f])));
+}
+
+struct SliceFlag {
+  const uint32_t* sbeg;
+  __device__ uint32_t operator()(uint64_t f) const { return sbeg[f + 1] > sbeg[f] ? 1u : 0u; }
+};
+
+__global__ void k_segments_by_leaf(const uint32_t* __restrict__ sbeg, const unsigned long long* kprime,
+                                   const uint32_t* __restrict__ segpos, uint64_t L,
+                                   uint32_t* __restrict__ seg_leaf, uint32_t* __restrict__ seg_begin,
+                                   uint4* __restrict__ seg_desc, const uint32_t* __restrict__ used,
+                                   const uint64_t* __restrict__ head, const uint64_t* __restrict__ B,
+                                   Counters* ctr) {
+  for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f <= L;
+       f += (uint64_t)gridDim.x * blockDim.x) {
+    if (f == L) {
+      const uint32_t T = segpos[L];
+      seg_begin[T] = (uint32_t)*kprime;
+      ctr->T = T;
+    } else if (sbeg[f + 1] > sbeg[f]) {
+      const uint32_t b = sbeg[f], p = segpos[f];
+      seg_leaf[p] = (uint32_t)f;
+      seg_begin[p] = b;
+      seg_desc[p] = make_uint4((uint32_t)f, b, used[f], seg_wide(used, head, L, (uint32_t)f, B[b]));
     }
   }
 }
