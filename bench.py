@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--fg-scale", type=int, default=24, help="R-MAT scale of the F-Graph section (0: skip)")
     ap.add_argument("--serve-n", type=float, default=1e8, help="keys of the served set (0: skip serving)")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device to device (reference dispatch for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -166,6 +168,14 @@ def main():
 
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {src.numel() * 8} bytes read and written")
+        del src, dst
     n0 = int(args.n)
     k = int(args.batch)
     seed = synth.SEED_BASE + 2
@@ -299,7 +309,8 @@ def main():
     roof = None
     if mg_l > 0 and mg_ms > 0:
         ach = (mg_b / mg_l) / ((mg_ms / mg_l) * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": "k_merge_wave" if S <= 1024 else "k_merge_lane", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        roof = {"bound": "hbm", "kernel": "k_merge_wave<unsigned int>" if S <= 1024 else "k_merge_lane",
+                "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": None,
                 "alg_bytes_per_launch": mg_b / mg_l, "avg_launch_ms": mg_ms / mg_l,
                 "dominant_phase": dominant}

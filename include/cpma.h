@@ -239,9 +239,12 @@ uint64_t cpma_clock_ns(void);
  * time, and the algorithmic HBM bytes the phase had to move:
  *   CPMA_PHASE_SORT        radix passes + repeat removal of a batch
  *   CPMA_PHASE_LOCATE      leaf location + touched-leaf segments
- *   CPMA_PHASE_MERGE       the per-leaf merge kernel; bytes = leaf bytes read and
- *                          rewritten + 8 per batch key + 20 per touched leaf
- *   CPMA_PHASE_HEAVY       the merge of batch slices too large for one leaf's LDS
+ *   CPMA_PHASE_MERGE       the main per-leaf merge kernel (one wave per leaf of
+ *                          narrow key span; one lane per leaf above 1024-byte
+ *                          leaves); bytes = leaf bytes read and rewritten + 8 per
+ *                          batch key + 20 per touched leaf
+ *   CPMA_PHASE_HEAVY       the follow-up merges: leaves of wide key span, slices
+ *                          longer than a wave takes, heavy slices (same bytes)
  *   CPMA_PHASE_COUNT       density counting up the implicit tree
  *   CPMA_PHASE_REDIST      window redistribution and resizing
  *   CPMA_PHASE_RANGE_SCAN  the range_map scan kernel; bytes = used bytes of every

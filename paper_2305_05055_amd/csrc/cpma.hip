@@ -830,28 +830,40 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   a.is_insert = insert ? 1 : 0;
   const uint64_t segs = std::min<uint64_t>(kbound, s->L);
   const uint32_t lgrid = (uint32_t)std::min<uint64_t>((segs + 255) / 256, (uint64_t)s->num_cus * 16);
+  // MERGE times exactly the main merge kernel; HEAVY the follow-up kernels for
+  // wide, long and heavy slices
   PhaseMark pmg = phase_begin(s, CPMA_PHASE_MERGE, st);
   if (s->S <= kWaveMaxS) {
-    // one wave per touched leaf; long insert slices spill to the lane merge
     const uint32_t wgrid = (uint32_t)std::min<uint64_t>(segs, (uint64_t)s->num_cus * 40);
     hipLaunchKernelGGL(k_merge_wave<uint32_t>, dim3(std::max(1u, wgrid)), dim3(kWave), 0, st, a);
-    hipLaunchKernelGGL(k_merge_wave<uint64_t>, dim3(std::max(1u, wgrid)), dim3(kWave), 0, st, a);
     HIPCHK(hipGetLastError());
-    if (insert) hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 1);
-  } else {
-    hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 0);
-  }
-  HIPCHK(hipGetLastError());
-  phase_end(s, pmg, st);
-  if (insert) {
-    const uint32_t hgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, kbound / kLaneHeavy), 1024);
+    phase_end(s, pmg, st);
     PhaseMark ph = phase_begin(s, CPMA_PHASE_HEAVY, st);
-    hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid), dim3(kWave), heavy_smem(s->S), st, a);
+    hipLaunchKernelGGL(k_merge_wave<uint64_t>, dim3(std::max(1u, wgrid)), dim3(kWave), 0, st, a);
+    if (insert) hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 1);
+    if (insert) {
+      const uint32_t hgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, kbound / kLaneHeavy), 1024);
+      hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid), dim3(kWave), heavy_smem(s->S), st, a);
+    }
     HIPCHK(hipGetLastError());
     phase_end(s, ph, st);
+  } else {
+    hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 0);
+    HIPCHK(hipGetLastError());
+    phase_end(s, pmg, st);
+    if (insert) {
+      const uint32_t hgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, kbound / kLaneHeavy), 1024);
+      PhaseMark ph = phase_begin(s, CPMA_PHASE_HEAVY, st);
+      hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid), dim3(kWave), heavy_smem(s->S), st, a);
+      HIPCHK(hipGetLastError());
+      phase_end(s, ph, st);
+    }
   }
   read_counters(s, st);
-  if (s->stats_on) s->stats[CPMA_PHASE_MERGE].alg_bytes += s->hctr->alg_bytes;
+  if (s->stats_on) {
+    s->stats[CPMA_PHASE_MERGE].alg_bytes += s->hctr->alg_bytes;
+    s->stats[CPMA_PHASE_HEAVY].alg_bytes += s->hctr->alg_bytes_h;
+  }
   const uint64_t delta = s->hctr->delta;
   if (insert)
     s->n += delta;

@@ -158,6 +158,63 @@ __device__ __forceinline__ uint32_t wave_decode_regs(const uint4 w, uint32_t use
   return lane63_u32(incl_cnt);
 }
 
+// Narrow single-chunk decode (leaf size <= 1024): every key lies within 2^32 of
+// `base`, so every delta fits 32 bits and a code has at most 5 bytes.  Keys are
+// produced as 32-bit offsets from base (head_rel = head - base).  Branch-free per
+// byte: the shift of a byte inside its code comes from a per-lane mask of
+// continuation bytes, and the shift a code carries in from the previous lane is
+// 7 times that lane's run of trailing continuation bytes, known before parsing.
+// emit(index, key offset) runs for every key in order; returns the key count.
+__device__ __forceinline__ uint32_t msb_nibble(uint32_t x) {
+  x = (x >> 7) & 0x01010101u;
+  return (x | (x >> 7) | (x >> 14) | (x >> 21)) & 0xfu;
+}
+
+template <class Emit>
+__device__ __forceinline__ uint32_t wave_decode_narrow(uint4 w, uint32_t used, uint32_t head_rel, Emit&& emit) {
+  const int lane = lane_id();
+  const uint32_t pos0 = 16u * lane;
+  const uint32_t nvalid = pos0 < used ? min(16u, used - pos0) : 0u;
+  uint32_t vm = nvalid >= 16u ? 0xffffu : ((1u << nvalid) - 1u);
+  const bool hl = lane == 0 && used >= 8u;
+  if (lane == 0) {
+    vm &= 0xff00u;  // the head is not a code
+    w.x = 0;
+    w.y = 0;
+  }
+  const uint32_t msb = msb_nibble(w.x) | (msb_nibble(w.y) << 4) | (msb_nibble(w.z) << 8) | (msb_nibble(w.w) << 12);
+  const uint32_t tm = vm & ~msb;  // code ends
+  const uint32_t cm = vm & msb;   // continuation bytes
+  const uint32_t tc = __clz(~(cm << 16));
+  uint32_t sh = 7u * dpp_prev32(tc);
+  const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+  uint32_t acc = 0, run = 0;
+  uint32_t kv[16];
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    const uint32_t pb = (words[j >> 2] >> (8 * (j & 3))) & 0x7fu;
+    acc |= pb << sh;
+    const uint32_t tmask = 0u - ((tm >> j) & 1u);
+    run += acc & tmask;
+    kv[j] = run;
+    acc &= ~tmask;
+    sh = (sh + 7u) & (0u - ((cm >> j) & 1u));
+  }
+  const uint32_t cin = dpp_prev32(acc);  // low bits of the code continuing into this lane
+  const uint32_t lead = (hl ? head_rel : 0u) + (tm ? cin : 0u);
+  const uint32_t tot = run + lead;
+  const uint32_t lcnt = (uint32_t)__popc(tm) + (hl ? 1u : 0u);
+  const uint32_t ex = wave_incl_scan(tot) - tot;
+  const uint32_t icl = wave_incl_scan(lcnt);
+  uint32_t idx = icl - lcnt;
+  if (hl) emit(idx++, head_rel);
+  const uint32_t off = ex + lead;
+#pragma unroll
+  for (int j = 0; j < 16; j++)
+    if ((tm >> j) & 1u) emit(idx++, off + kv[j]);
+  return lane63_u32(icl);
+}
+
 // Number of keys in a leaf image: the head plus one per byte with a clear high bit.
 __device__ __forceinline__ uint32_t wave_count_keys(const uint8_t* __restrict__ src, uint32_t used) {
   const int lane = lane_id();

@@ -329,7 +329,7 @@ __global__ void __launch_bounds__(256) k_merge_lane(MergeArgs a, int from_list) 
   alg = wave_sum((uint64_t)alg);
   if (lane_id() == 0) {
     if (delta) atomicAdd(&a.ctr->delta, delta);
-    if (alg) atomicAdd(&a.ctr->alg_bytes, alg);
+    if (alg) atomicAdd(from_list ? &a.ctr->alg_bytes_h : &a.ctr->alg_bytes, alg);
   }
 }
 

@@ -113,7 +113,14 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
     auto key = [&](uint32_t i) -> uint64_t { return base + (uint64_t)K[i]; };
     const uint64_t* Bg = a.B + b;
     uint8_t* lp = a.bytes + leaf * (uint64_t)S;
-    const uint32_t nA = wave_decode_regs(w, used0, [&](uint32_t i, uint64_t x, uint64_t) { K[i] = (KT)(x - base); });
+    uint32_t nA;
+    if constexpr (kNarrow) {
+      const uint64_t hd = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)w.y, 0) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)w.x, 0);
+      nA = wave_decode_narrow(w, used0, (uint32_t)(hd - base), [&](uint32_t i, uint32_t x) { K[i] = (KT)x; });
+    } else {
+      nA = wave_decode_regs(w, used0, [&](uint32_t i, uint64_t x, uint64_t) { K[i] = (KT)x; });
+    }
     wave_zero(out, S);
     // lane-contiguous block of old-key indices [i0, i1) over [0, nA] (index nA: trailing group)
     const uint32_t m = (nA + 1 + kWave - 1) / kWave;
@@ -307,7 +314,7 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
   }
   if (lane == 0) {
     if (delta) atomicAdd(&a.ctr->delta, delta);
-    if (alg) atomicAdd(&a.ctr->alg_bytes, alg);
+    if (alg) atomicAdd(kNarrow ? &a.ctr->alg_bytes : &a.ctr->alg_bytes_h, alg);
   }
 }
 

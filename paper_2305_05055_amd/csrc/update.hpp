@@ -25,6 +25,7 @@ struct Counters {
   unsigned int nwide;               // segments whose key span needs 64-bit merge keys
   unsigned long long alg_bytes;     // algorithmic HBM bytes of the merge (statistics)
   unsigned long long alg_bytes_q;   // algorithmic HBM bytes of range scans (statistics)
+  unsigned long long alg_bytes_h;   // algorithmic HBM bytes of the follow-up merges (statistics)
 };
 
 __device__ __forceinline__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t x) {
