@@ -22,11 +22,36 @@ namespace cpma_dev {
 constexpr uint32_t kWaveSlice = 64;   // insert slice handled per wave
 constexpr uint32_t kWaveMaxS = 1024;  // leaf size handled per wave (16 bytes per lane)
 
-__device__ __forceinline__ void put_key_bytes(uint8_t* dst, bool head, uint64_t x, uint64_t pred) {
+// Code length and code bytes of a delta held in the key type (32-bit offsets
+// in the narrow instance).
+__device__ __forceinline__ uint32_t vlen_t(uint32_t d) { return (32u - (uint32_t)__clz((int)(d | 1u)) + 6u) / 7u; }
+__device__ __forceinline__ uint32_t vlen_t(uint64_t d) { return vlen(d); }
+template <typename T>
+__device__ __forceinline__ void vput_t(uint8_t* dst, T d) {
+  uint32_t n = 0;
+  while (d >= 0x80) {
+    dst[n++] = (uint8_t)(d | 0x80);
+    d >>= 7;
+  }
+  dst[n] = (uint8_t)d;
+}
+__device__ __forceinline__ uint32_t dpp_prev_t(uint32_t v) { return dpp_prev32(v); }
+__device__ __forceinline__ uint64_t dpp_prev_t(uint64_t v) { return dpp_prev64(v); }
+__device__ __forceinline__ uint32_t readlane_t(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ uint64_t readlane_t(uint64_t v, int l) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+}
+
+// Key x (offset from base) as a leaf head (8 bytes) or as the code of x - pred.
+template <typename KT>
+__device__ __forceinline__ void put_key_bytes(uint8_t* dst, bool head, KT x, KT pred, uint64_t base) {
   if (head)
-    put_le64(dst, x);
+    put_le64(dst, base + (uint64_t)x);
   else
-    vput(dst, x - pred);
+    vput_t<KT>(dst, (KT)(x - pred));
 }
 
 // KT = uint32_t: keys are stored in LDS as offsets from the segment's smallest
@@ -36,7 +61,7 @@ template <typename KT>
 __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
   constexpr bool kNarrow = sizeof(KT) == 4;
   __shared__ KT K[kWaveMaxS];
-  __shared__ uint64_t GK[kWaveSlice];      // group g: its last key (new predecessor of old key GR[g])
+  __shared__ KT GK[kWaveSlice];            // group g: its last key (new predecessor of old key GR[g])
   __shared__ uint32_t GR[kWaveSlice + 1];  // group g: rank; GR[ng] closes the table
   __shared__ uint32_t GB[kWaveSlice];      // group g: bytes of its codes
   __shared__ uint32_t GS[kWaveSlice];      // group g: output offset
@@ -110,7 +135,6 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
                           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bj0, 0);
       base = used0 ? min(hd, b0) : b0;
     }
-    auto key = [&](uint32_t i) -> uint64_t { return base + (uint64_t)K[i]; };
     const uint64_t* Bg = a.B + b;
     uint8_t* lp = a.bytes + leaf * (uint64_t)S;
     uint32_t nA;
@@ -131,16 +155,16 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
     uint64_t arena_off = 0;
     bool to_arena = false;
     if (a.is_insert) {
+      // keys below are offsets from base (the key type of this instance)
       const bool has_b = (uint32_t)lane < nb;
-      const uint64_t bj = has_b ? bj0 : 0;
+      const KT bj = has_b ? (KT)(bj0 - base) : (KT)0;
       uint32_t r = 0xffffffffu;
       bool isnew = false;
       if (has_b) {
-        const KT xb = (KT)(bj - base);
-        r = lds_lower_bound<KT>(K, nA, xb);
-        isnew = !(r < nA && K[r] == xb);
+        r = lds_lower_bound<KT>(K, nA, bj);
+        isnew = !(r < nA && K[r] == bj);
       }
-      const uint64_t b_prev = dpp_prev64(bj);
+      const KT b_prev = dpp_prev_t(bj);
       const uint32_t r_prev = dpp_prev32(r);
       const uint32_t new_prev = dpp_prev32(isnew ? 1u : 0u);
       const uint32_t r_next = dpp_next32(r);
@@ -148,17 +172,17 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
       const bool same_prev = lane > 0 && new_prev && r_prev == r;
       const bool same_next = lane < kWave - 1 && new_next && r_next == r;
       bool has_pred = false;
-      uint64_t pred = 0;
+      KT pred = 0;
       if (isnew) {
         if (same_prev) {
           pred = b_prev;
           has_pred = true;
         } else if (r > 0) {
-          pred = key(r - 1);
+          pred = K[r - 1];
           has_pred = true;
         }
       }
-      const uint32_t cost = isnew ? (has_pred ? vlen(bj - pred) : 8u) : 0u;
+      const uint32_t cost = isnew ? (has_pred ? vlen_t((KT)(bj - pred)) : 8u) : 0u;
       const uint32_t incl = dpp_incl_scan<uint32_t>(cost);
       const uint32_t ex = incl - cost;
       const bool gstart = isnew && !same_prev;
@@ -187,16 +211,20 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
             hi = mid;
         }
       }
+      const KT k_before = (i0 > 0 && i0 <= nA) ? K[i0 - 1] : (KT)0;  // old key before the block
       // sweep 1: bytes per index (group before old key i, then old key i)
       uint32_t lt = 0;
       uint32_t p = p0;
+      KT kp = k_before;
       for (uint32_t i = i0; i < i1; i++) {
         const bool gh = GR[p] == i;
         uint32_t t = gh ? GB[p] : 0u;
         if (i < nA) {
+          const KT x = K[i];
           const bool hp = gh || i > 0;
-          const uint64_t np = gh ? GK[p] : (i > 0 ? key(i - 1) : 0);
-          t += hp ? vlen(key(i) - np) : 8u;
+          const KT np = gh ? GK[p] : kp;
+          t += hp ? vlen_t((KT)(x - np)) : 8u;
+          kp = x;
         }
         lt += t;
         p += gh ? 1u : 0u;
@@ -219,17 +247,19 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
       // sweep 2: write old keys, record group starts
       uint32_t run = lincl - lt;
       p = p0;
+      kp = k_before;
       for (uint32_t i = i0; i < i1; i++) {
         const bool gh = GR[p] == i;
         const uint32_t gb = gh ? GB[p] : 0u;
         if (gh) GS[p] = run;
         if (i < nA) {
+          const KT x = K[i];
           const bool hp = gh || i > 0;
-          const uint64_t np = gh ? GK[p] : (i > 0 ? key(i - 1) : 0);
-          const uint64_t x = key(i);
-          const uint32_t c = hp ? vlen(x - np) : 8u;
-          put_key_bytes(dst + run + gb, !hp, x, np);
+          const KT np = gh ? GK[p] : kp;
+          const uint32_t c = hp ? vlen_t((KT)(x - np)) : 8u;
+          put_key_bytes<KT>(dst + run + gb, !hp, x, np, base);
           run += gb + c;
+          kp = x;
         } else {
           run += gb;
         }
@@ -237,14 +267,10 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
       }
       __syncthreads();
       // new keys: group start + offset inside the group
-      if (isnew) put_key_bytes(dst + GS[gid] + (ex - exfirst), !has_pred, bj, pred);
+      if (isnew) put_key_bytes<KT>(dst + GS[gid] + (ex - exfirst), !has_pred, bj, pred, base);
       uint64_t firstnew = kNoKey;
-      if (nnew) {
-        const int fl = __ffsll((unsigned long long)newmask) - 1;
-        firstnew = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bj >> 32), fl) << 32) |
-                   (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bj, fl);
-      }
-      first_key = nA ? min(key(0), firstnew) : firstnew;
+      if (nnew) firstnew = base + (uint64_t)readlane_t(bj, __ffsll((unsigned long long)newmask) - 1);
+      first_key = nA ? min(base + (uint64_t)K[0], firstnew) : firstnew;
       delta += nnew;
     } else {
       for (uint32_t i = lane; i < kWaveMaxS / 32; i += kWave) DF[i] = 0;
@@ -252,8 +278,7 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
       for (uint32_t c0 = 0; c0 < nb; c0 += kWave) {
         const uint32_t j = c0 + lane;
         if (j < nb) {
-          const uint64_t x = Bg[j];
-          const KT xr = (KT)(x - base);
+          const KT xr = (KT)(Bg[j] - base);
           const uint32_t r = lds_lower_bound<KT>(K, nA, xr);
           if (r < nA && K[r] == xr) atomicOr(&DF[r >> 5], 1u << (r & 31));
         }
@@ -267,23 +292,28 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
         else nrem++;
       }
       const uint32_t pk_in = dpp_prev32(dpp_incl_max(lastk));  // 0 = none before this block
+      const KT kin = pk_in ? K[pk_in - 1] : (KT)0;
       uint32_t pk = pk_in;
+      KT kp = kin;
       for (uint32_t i = i0; i < min(i1, nA); i++) {
         if (gone(i)) continue;
-        lt += pk ? vlen(key(i) - key(pk - 1)) : 8u;
+        const KT x = K[i];
+        lt += pk ? vlen_t((KT)(x - kp)) : 8u;
         pk = i + 1;
+        kp = x;
       }
       const uint32_t lincl = dpp_incl_scan<uint32_t>(lt);
       U = lane63_u32(lincl);
       uint32_t run = lincl - lt;
       pk = pk_in;
+      kp = kin;
       for (uint32_t i = i0; i < min(i1, nA); i++) {
         if (gone(i)) continue;
-        const uint64_t x = key(i);
-        const uint64_t np = pk ? key(pk - 1) : 0;
-        put_key_bytes(out + run, pk == 0, x, np);
-        run += pk ? vlen(x - np) : 8u;
+        const KT x = K[i];
+        put_key_bytes<KT>(out + run, pk == 0, x, kp, base);
+        run += pk ? vlen_t((KT)(x - kp)) : 8u;
         pk = i + 1;
+        kp = x;
       }
       // smallest kept key: the key at the first index whose flag is clear
       uint32_t fk = 0xffffffffu;
@@ -294,7 +324,7 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
         }
       uint32_t fkmin = fk;
       for (int d = 32; d > 0; d >>= 1) fkmin = min(fkmin, (uint32_t)__shfl_xor((int)fkmin, d, kWave));
-      first_key = (fkmin != 0xffffffffu) ? key(fkmin) : kNoKey;
+      first_key = (fkmin != 0xffffffffu) ? base + (uint64_t)K[fkmin] : kNoKey;
       delta += wave_sum(nrem);
     }
     __syncthreads();
