@@ -35,6 +35,83 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+# ---- HBM traffic of the main merge kernel from rocprofv3 counter runs ------------
+MERGE_KERNEL = "k_merge_wave<unsigned int>"
+MERGE_SOURCES = ["common.hpp", "leaf.hpp", "update.hpp", "merge_wave.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_merge_wave_traffic_insert_batch1e7_n1e8.md")
+
+
+def merge_source_hash():
+    """Hash of the sources that define the main merge kernel: traffic measured on
+    another version of it is not reported."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in MERGE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2305_05055_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_rows(path):
+    import csv
+    rows = []
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("cpma_dev::", "")
+            rows.append((int(r["Dispatch_Id"]), name, r["Counter_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    return rows
+
+
+def pmc_summary(fetch_csv, write_csv, steps, cmd_fetch, cmd_write):
+    """Traffic per timed launch of the merge kernel: FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch), each scaled by what the counter reads for the 1 GiB
+    calibration copy (the largest copy dispatch of the run)."""
+    out = {}
+    for tag, path, ctr in (("read", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = [r for r in pmc_rows(path) if r[2] == ctr]
+        copy = max(v for _, n, _, v in rows if n == "__amd_rocclr_copyBuffer")
+        factor = float(1 << 30) / (copy * 1024.0)
+        merge = [v for _, n, _, v in rows if n == MERGE_KERNEL]
+        timed = merge[-(steps + 2):-2]   # the run ends with two delete batches
+        out[tag] = {"copy_kib": copy, "factor": factor,
+                    "kib_per_launch": sum(timed) / len(timed),
+                    "bytes_per_launch": sum(timed) / len(timed) * 1024.0 * factor,
+                    "launches": len(timed)}
+    total = out["read"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
+    lines = [
+        f"# {MERGE_KERNEL}: HBM traffic per launch, insert batches of 1e7 into 1e8 keys", "",
+        "Two counter runs of the headline steps (each from the repository root, after "
+        "`cd /tmp && export TMPDIR=/tmp`):", "", "```", cmd_fetch, cmd_write, "```", "",
+        "The first dispatch of each run is a 1 GiB device-to-device copy "
+        "(`--calibrate-copy`); the counter's reading for it gives the scale factor "
+        "(bytes actually moved / counter bytes).", "",
+        "| counter | copy reads (KiB) | factor | per timed launch (KiB) | per launch (bytes, scaled) |",
+        "|---|---|---|---|---|"]
+    for tag, ctr in (("read", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        o = out[tag]
+        lines.append(f"| {ctr} | {o['copy_kib']:.1f} | {o['factor']:.4f} | {o['kib_per_launch']:.1f} | "
+                     f"{o['bytes_per_launch']:.4e} |")
+    lines += ["", f"Timed launches averaged: {out['read']['launches']}.", "",
+              "Machine-readable (read by bench.py; `source` is the hash of the kernel's sources "
+              "when the counters were taken):", "", "```",
+              f"traffic_bytes_per_launch={total:.6e}", f"source={merge_source_hash()}", "```", ""]
+    return "\n".join(lines)
+
+
+def merge_traffic():
+    """Traffic per launch from the committed counter summary, or None when it is
+    missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(l.strip().split("=", 1) for l in fh if "=" in l and not l.startswith("|"))
+    except OSError:
+        return None
+    if kv.get("source") != merge_source_hash():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def to_dev(a):
     import torch
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
@@ -155,7 +232,19 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device to device (reference dispatch for HBM byte counters)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the merge kernel's traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+
+    if args.pmc_summary:
+        base = "rocprofv3 --pmc {c} --output-format csv -d /root/repo/gpurun_out/pmc_{t} -o run -- " \
+               f"python3 /root/repo/bench.py --only-steps --no-cpu-baseline --calibrate-copy --steps {args.steps}"
+        text = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.steps,
+                           base.format(c="FETCH_SIZE", t="fetch"), base.format(c="WRITE_SIZE", t="write"))
+        with open(TRAFFIC_FILE, "w") as fh:
+            fh.write(text)
+        print(text)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the CPMA hot path here runs on a single "
@@ -311,7 +400,7 @@ def main():
         ach = (mg_b / mg_l) / ((mg_ms / mg_l) * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": "k_merge_wave<unsigned int>" if S <= 1024 else "k_merge_lane",
                 "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "frac": ach / HBM_PEAK_GBS, "traffic": merge_traffic(),
                 "alg_bytes_per_launch": mg_b / mg_l, "avg_launch_ms": mg_ms / mg_l,
                 "dominant_phase": dominant}
 

@@ -61,7 +61,7 @@ typedef enum { CPMA_MEM_HOST = 0, CPMA_MEM_DEVICE = 1 } cpma_mem;
 
 /*
  * Structure parameters.  A zero field takes the default.
- *   leaf_bytes     bytes per leaf S: a power of two in [64, 2048]; default 1024.
+ *   leaf_bytes     bytes per leaf S: a power of two in [64, 4096]; default 1024.
  *                  The paper sizes leaves Theta(log N) cells (Section "Packed
  *                  Memory Array"); here S is fixed per set.
  *   grow           growing factor when the root exceeds its upper bound;
@@ -76,16 +76,69 @@ typedef enum { CPMA_MEM_HOST = 0, CPMA_MEM_DEVICE = 1 } cpma_mem;
  *                  up_root <= up_leaf < 1 and lo_root * grow < up_root.
  *   build_density  target root density after a build or resize; default
  *                  up_root / grow.
+ *   range_chunk    interior leaves one lane of the range_map scan decodes in a
+ *                  row (a range query is a search then a scan, Section "Packed
+ *                  Memory Array", "Design and operations"); a power of two in
+ *                  [1, 64]; default 8.  Layout and results do not depend on it.
  */
 typedef struct {
   uint32_t leaf_bytes;
   double grow;
   double up_leaf, up_root, lo_leaf, lo_root;
   double build_density;
+  uint32_t range_chunk;
 } cpma_config;
 
 /* Fills *cfg with the defaults above.  Returns CPMA_ERR_INVALID if cfg is NULL. */
 cpma_status cpma_config_default(cpma_config* cfg);
+
+/*
+ * Autotuner for the batching parameters: leaf size and range-scan chunk picked
+ * by measurement on this GPU.  The paper sizes leaves by the structure size
+ * (Theta(log N) cells; CPMA leaves grow with n, Section "Compressed Packed
+ * Memory Array"); here the trade-off between bytes moved per small update and
+ * decode work per scanned byte is timed instead.
+ *
+ * A sample of `keys` is taken as the keys below a threshold chosen so that about
+ * hint->sample_keys remain, which keeps the key density (and so the codes) of
+ * the full set.  For each leaf size in {256, 512, 1024, 2048, 4096} the sample
+ * is built, an insert batch of hint->batch * sample / n fresh keys in the
+ * sample's key range is timed, then hint->queries range queries covering about
+ * hint->range_keys sample keys each; the score is
+ * insert_weight * insert_ms + (1 - insert_weight) * range_ms.  At the winning
+ * size, range_chunk in {1, 2, 4, 8, 16, 32} is timed on the same queries.  Each
+ * time is the least of three runs after a warm-up.
+ *
+ * keys: n keys in `mem` (host or device), any order; UINT64_MAX is rejected.
+ * hint: NULL or zero fields take defaults (batch n / 10, range_keys 1000,
+ *       queries 1e5, sample_keys 2^22, insert_weight 0.5 when negative).
+ * base: the other configuration fields (NULL = defaults).
+ * out:  receives base with leaf_bytes and range_chunk set to the winners.
+ * report: NULL or receives every measured time.
+ * Synchronises `stream`; allocates and frees its own trial sets.
+ */
+typedef struct {
+  uint64_t batch;
+  uint64_t range_keys;
+  uint64_t queries;
+  uint64_t sample_keys;
+  double insert_weight;
+} cpma_tune_hint;
+
+typedef struct {
+  uint64_t sample_n;         /* keys in the tuning sample */
+  uint32_t leaf_bytes[5];    /* candidates, in the order timed */
+  double insert_ms[5];       /* insert batch time per candidate */
+  double range_ms[5];        /* range query batch time per candidate */
+  uint32_t chunk[6];
+  double chunk_ms[6];        /* range query batch time per chunk at the winning size */
+  uint32_t best_leaf_bytes;
+  uint32_t best_chunk;
+} cpma_tune_report;
+
+cpma_status cpma_autotune(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpma_tune_hint* hint,
+                          const cpma_config* base, void* stream, cpma_config* out,
+                          cpma_tune_report* report);
 
 /*
  * Builds a set from n keys (any order, duplicates allowed): the CPMA(start, end)

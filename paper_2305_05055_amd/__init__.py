@@ -31,7 +31,19 @@ class Config(ctypes.Structure):
     _fields_ = [("leaf_bytes", ctypes.c_uint32), ("grow", ctypes.c_double),
                 ("up_leaf", ctypes.c_double), ("up_root", ctypes.c_double),
                 ("lo_leaf", ctypes.c_double), ("lo_root", ctypes.c_double),
-                ("build_density", ctypes.c_double)]
+                ("build_density", ctypes.c_double), ("range_chunk", ctypes.c_uint32)]
+
+
+class TuneHint(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_uint64), ("range_keys", ctypes.c_uint64), ("queries", ctypes.c_uint64),
+                ("sample_keys", ctypes.c_uint64), ("insert_weight", ctypes.c_double)]
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("sample_n", ctypes.c_uint64), ("leaf_bytes", ctypes.c_uint32 * 5),
+                ("insert_ms", ctypes.c_double * 5), ("range_ms", ctypes.c_double * 5),
+                ("chunk", ctypes.c_uint32 * 6), ("chunk_ms", ctypes.c_double * 6),
+                ("best_leaf_bytes", ctypes.c_uint32), ("best_chunk", ctypes.c_uint32)]
 
 
 class Request(ctypes.Structure):
@@ -94,6 +106,8 @@ def lib():
         L.cpma_clock_ns.restype = u64
         L.cpma_stats_enable.argtypes = [vp, ctypes.c_int]
         L.cpma_stats_get.argtypes = [vp, ctypes.POINTER(PhaseStat), ctypes.c_int]
+        L.cpma_autotune.argtypes = [vp, u64, ctypes.c_int, ctypes.POINTER(TuneHint), ctypes.POINTER(Config),
+                                    vp, ctypes.POINTER(Config), ctypes.POINTER(TuneReport)]
         L.cpma_status_str.argtypes = [ctypes.c_int]
         L.cpma_status_str.restype = ctypes.c_char_p
         _lib = L
@@ -136,17 +150,39 @@ def default_config():
     return c
 
 
+def autotune(keys, batch=0, range_keys=0, queries=0, sample_keys=0, insert_weight=-1.0, base=None,
+             stream=None):
+    """cpma_autotune: (Config with the chosen leaf_bytes and range_chunk, report dict)."""
+    p, n, mem, keep = _keys(keys)
+    hint = TuneHint(batch, range_keys, queries, sample_keys, insert_weight)
+    out = Config()
+    rep = TuneReport()
+    _check(lib().cpma_autotune(p if n else None, n, mem, ctypes.byref(hint),
+                               ctypes.byref(base) if base is not None else None,
+                               _stream(stream, mem == MEM_DEVICE), ctypes.byref(out), ctypes.byref(rep)),
+           "cpma_autotune")
+    report = {"sample_n": rep.sample_n, "best_leaf_bytes": rep.best_leaf_bytes, "best_chunk": rep.best_chunk,
+              "leaf_bytes": {int(rep.leaf_bytes[i]): {"insert_ms": rep.insert_ms[i], "range_ms": rep.range_ms[i]}
+                             for i in range(5)},
+              "range_chunk_ms": {int(rep.chunk[i]): rep.chunk_ms[i] for i in range(6)}}
+    return out, report
+
+
 class CPMA:
     """A device-resident compressed packed memory array of uint64 keys."""
 
     def __init__(self, keys=(), leaf_bytes=0, grow=0.0, bounds=None, build_density=0.0,
-                 stream=None):
-        cfg = Config()
-        cfg.leaf_bytes = leaf_bytes
-        cfg.grow = grow
-        if bounds is not None:
-            cfg.up_leaf, cfg.up_root, cfg.lo_leaf, cfg.lo_root = bounds
-        cfg.build_density = build_density
+                 stream=None, config=None, range_chunk=0):
+        if config is not None:
+            cfg = Config.from_buffer_copy(config)
+        else:
+            cfg = Config()
+            cfg.leaf_bytes = leaf_bytes
+            cfg.grow = grow
+            if bounds is not None:
+                cfg.up_leaf, cfg.up_root, cfg.lo_leaf, cfg.lo_root = bounds
+            cfg.build_density = build_density
+            cfg.range_chunk = range_chunk
         p, n, mem, keep = _keys(keys)
         h = ctypes.c_void_p()
         _check(lib().cpma_build(p if n else None, n, mem, ctypes.byref(cfg),

@@ -21,6 +21,7 @@
 #include "merge_wave.hpp"
 #include "fgraph.hpp"
 #include "resize.hpp"
+#include "tune.hpp"
 
 using namespace cpma_dev;
 
@@ -874,7 +875,8 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
 }
 
 cpma_status check_config(const cpma_config& c) {
-  if (c.leaf_bytes < 64 || c.leaf_bytes > 2048 || (c.leaf_bytes & (c.leaf_bytes - 1))) return CPMA_ERR_INVALID;
+  if (c.leaf_bytes < 64 || c.leaf_bytes > 4096 || (c.leaf_bytes & (c.leaf_bytes - 1))) return CPMA_ERR_INVALID;
+  if (c.range_chunk < 1 || c.range_chunk > 64 || (c.range_chunk & (c.range_chunk - 1))) return CPMA_ERR_INVALID;
   if (!(c.grow > 1.0 && c.grow <= 4.0)) return CPMA_ERR_INVALID;
   if (!(c.lo_leaf > 0 && c.lo_leaf <= c.lo_root && c.lo_root < c.up_root && c.up_root <= c.up_leaf &&
         c.up_leaf < 1.0))
@@ -911,6 +913,7 @@ cpma_status cpma_config_default(cpma_config* cfg) {
   cfg->lo_leaf = 0.10;
   cfg->lo_root = 0.30;
   cfg->build_density = cfg->up_root / cfg->grow;
+  cfg->range_chunk = 8;
   return CPMA_OK;
 }
 
@@ -940,6 +943,7 @@ cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpm
     if (cfg_in->lo_leaf > 0) cfg.lo_leaf = cfg_in->lo_leaf;
     if (cfg_in->lo_root > 0) cfg.lo_root = cfg_in->lo_root;
     cfg.build_density = cfg_in->build_density > 0 ? cfg_in->build_density : cfg.up_root / cfg.grow;
+    if (cfg_in->range_chunk) cfg.range_chunk = cfg_in->range_chunk;
   }
   cpma_status cs = check_config(cfg);
   if (cs != CPMA_OK) return cs;
@@ -1077,7 +1081,7 @@ cpma_status cpma_range_map(const cpma* cs, const uint64_t* lo, const uint64_t* h
     const uint32_t blocks = (uint32_t)s->num_cus * 8;
     PhaseMark ps = phase_begin(s, CPMA_PHASE_RANGE_SCAN, st);
     hipLaunchKernelGGL(k_rm_interior, dim3(blocks), dim3(256), 0, st, a, (const uint64_t*)s->qvoff.as<uint64_t>(),
-                       (const uint64_t*)s->qfirst.as<uint64_t>(), 8u, dsum, dcount, qalg);
+                       (const uint64_t*)s->qfirst.as<uint64_t>(), s->cfg.range_chunk, dsum, dcount, qalg);
     HIPCHK(hipGetLastError());
     phase_end(s, ps, st, 32ull * q);
     phase_end(s, pq, st);
@@ -1296,3 +1300,204 @@ void cpma_destroy(cpma* s) {
 }
 
 }  // extern "C"
+
+// ---- autotuner ------------------------------------------------------------------
+namespace {
+
+struct DevScratch {
+  std::vector<void*> ptrs;
+  ~DevScratch() {
+    for (void* p : ptrs) hipFree(p);
+  }
+  template <typename T>
+  T* get(size_t count) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(count * sizeof(T), 16)) != hipSuccess) {
+      hipGetLastError();
+      throw Fail{CPMA_ERR_NOMEM};
+    }
+    ptrs.push_back(p);
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+struct Handle {
+  cpma* h = nullptr;
+  ~Handle() { cpma_destroy(h); }
+};
+
+// Least device time of `reps` runs of f() after one warm-up, in ms (events on st).
+template <class F>
+double time_min(hipStream_t st, int reps, F&& f) {
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  double best = 1e30;
+  for (int r = 0; r <= reps; r++) {
+    HIPCHK(hipEventRecord(a, st));
+    f(r);
+    HIPCHK(hipEventRecord(b, st));
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    if (r > 0) best = std::min(best, (double)ms);
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return best;
+}
+
+void st_check(cpma_status r) {
+  if (r != CPMA_OK) throw Fail{r};
+}
+
+}  // namespace
+
+extern "C" cpma_status cpma_autotune(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpma_tune_hint* hint_in,
+                                     const cpma_config* base, void* stream, cpma_config* out,
+                                     cpma_tune_report* report) {
+  if (!out || n == 0 || !keys) return CPMA_ERR_INVALID;
+  cpma_config cfg;
+  cpma_config_default(&cfg);
+  if (base) {
+    if (base->leaf_bytes) cfg.leaf_bytes = base->leaf_bytes;
+    if (base->grow > 0) cfg.grow = base->grow;
+    if (base->up_leaf > 0) cfg.up_leaf = base->up_leaf;
+    if (base->up_root > 0) cfg.up_root = base->up_root;
+    if (base->lo_leaf > 0) cfg.lo_leaf = base->lo_leaf;
+    if (base->lo_root > 0) cfg.lo_root = base->lo_root;
+    cfg.build_density = base->build_density > 0 ? base->build_density : cfg.up_root / cfg.grow;
+    if (base->range_chunk) cfg.range_chunk = base->range_chunk;
+  }
+  cpma_status cs = check_config(cfg);
+  if (cs != CPMA_OK) return cs;
+  cpma_tune_hint hint{};
+  if (hint_in) hint = *hint_in;
+  if (!hint.batch) hint.batch = std::max<uint64_t>(1, n / 10);
+  if (!hint.range_keys) hint.range_keys = 1000;
+  if (!hint.queries) hint.queries = 100000;
+  if (!hint.sample_keys) hint.sample_keys = 1ull << 22;
+  if (hint.insert_weight < 0) hint.insert_weight = 0.5;
+  if (hint.insert_weight > 1) return CPMA_ERR_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  cpma_tune_report rep{};
+  try {
+    DevScratch sc;
+    const uint64_t* dk = keys;
+    if (mem == CPMA_MEM_HOST) {
+      uint64_t* d = sc.get<uint64_t>(n);
+      HIPCHK(hipMemcpyAsync(d, keys, n * 8, hipMemcpyHostToDevice, st));
+      dk = d;
+    }
+    BatchInfo* di = sc.get<BatchInfo>(1);
+    hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(di),
+                       (uint64_t)(sizeof(BatchInfo) / 4), 0u);
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, dk, n, di);
+    HIPCHK(hipGetLastError());
+    BatchInfo bi;
+    HIPCHK(hipMemcpyAsync(&bi, di, sizeof(bi), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (bi.has_reserved) return CPMA_ERR_RESERVED_KEY;
+    const int bits = 64 - __builtin_clzll(bi.or_all | 1);
+    const long double space = std::ldexp(1.0L, bits);  // keys lie in [0, 2^bits)
+    // density-preserving sample: the keys below T
+    const uint64_t* sample = dk;
+    uint64_t ns = n;
+    long double Tl = space;
+    if (n > hint.sample_keys) {
+      const uint64_t cap = std::min<uint64_t>(n, 4 * hint.sample_keys);
+      uint64_t* buf = sc.get<uint64_t>(cap);
+      unsigned long long* cnt = sc.get<unsigned long long>(1);
+      Tl = space * (long double)hint.sample_keys / (long double)n;
+      for (int tries = 0;; tries++) {
+        const uint64_t T = (uint64_t)std::min<long double>(Tl, 18446744073709551615.0L);
+        hipLaunchKernelGGL((k_fill<uint64_t>), dim3(1), dim3(64), 0, st, (uint64_t*)cnt, (uint64_t)1, 0ull);
+        hipLaunchKernelGGL(k_sample_below, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, dk, n, T, buf, cap, cnt);
+        HIPCHK(hipGetLastError());
+        unsigned long long c = 0;
+        HIPCHK(hipMemcpyAsync(&c, cnt, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (c <= cap && (c >= hint.sample_keys / 4 || tries >= 8)) {
+          ns = c;
+          break;
+        }
+        if (tries >= 16) throw Fail{CPMA_ERR_DEVICE};
+        Tl = (c > cap) ? Tl / 2 : Tl * 2;
+      }
+      sample = buf;
+    }
+    if (ns == 0) {
+      ns = std::min<uint64_t>(n, hint.sample_keys);
+      sample = dk;
+      Tl = space;
+    }
+    const uint64_t T = (uint64_t)std::min<long double>(Tl, 18446744073709551615.0L);
+    rep.sample_n = ns;
+    const uint64_t kk = std::max<uint64_t>(
+        1, (uint64_t)((long double)hint.batch * (long double)ns / (long double)n));
+    const uint64_t q = hint.queries;
+    const uint64_t width = std::max<uint64_t>(
+        1, (uint64_t)((long double)hint.range_keys * (long double)T / (long double)ns));
+    uint64_t* ins = sc.get<uint64_t>(kk);
+    uint64_t* qlo = sc.get<uint64_t>(q);
+    uint64_t* qhi = sc.get<uint64_t>(q);
+    uint64_t* qs = sc.get<uint64_t>(q);
+    uint64_t* qc = sc.get<uint64_t>(q);
+    hipLaunchKernelGGL(k_gen_ranges, dim3(grid_for(q, 256, 4096)), dim3(256), 0, st, qlo, qhi, q, T, width,
+                       0x7475ull);
+    HIPCHK(hipGetLastError());
+    const uint32_t sizes[5] = {256, 512, 1024, 2048, 4096};
+    double best_score = 1e300;
+    uint32_t bestS = cfg.leaf_bytes;
+    for (int c = 0; c < 5; c++) {
+      cpma_config tc = cfg;
+      tc.leaf_bytes = sizes[c];
+      Handle h;
+      st_check(cpma_build(sample, ns, CPMA_MEM_DEVICE, &tc, st, &h.h));
+      const double ims = time_min(st, 3, [&](int r) {
+        hipLaunchKernelGGL(k_gen_uniform, dim3(grid_for(kk, 256, 4096)), dim3(256), 0, st, ins, kk, T,
+                           0x1000ull + (uint64_t)r);
+        st_check(cpma_insert_batch(h.h, ins, kk, CPMA_MEM_DEVICE, 0, st, nullptr));
+      });
+      const double rms = time_min(st, 3, [&](int) {
+        st_check(cpma_range_map(h.h, qlo, qhi, q, CPMA_MEM_DEVICE, qs, qc, st));
+      });
+      rep.leaf_bytes[c] = sizes[c];
+      rep.insert_ms[c] = ims;
+      rep.range_ms[c] = rms;
+      const double score = hint.insert_weight * ims + (1.0 - hint.insert_weight) * rms;
+      if (score < best_score) {
+        best_score = score;
+        bestS = sizes[c];
+      }
+    }
+    cfg.leaf_bytes = bestS;
+    const uint32_t chunks[6] = {1, 2, 4, 8, 16, 32};
+    uint32_t bestC = cfg.range_chunk;
+    {
+      Handle h;
+      st_check(cpma_build(sample, ns, CPMA_MEM_DEVICE, &cfg, st, &h.h));
+      double best = 1e300;
+      for (int c = 0; c < 6; c++) {
+        h.h->cfg.range_chunk = chunks[c];
+        const double ms = time_min(st, 3, [&](int) {
+          st_check(cpma_range_map(h.h, qlo, qhi, q, CPMA_MEM_DEVICE, qs, qc, st));
+        });
+        rep.chunk[c] = chunks[c];
+        rep.chunk_ms[c] = ms;
+        if (ms < best) {
+          best = ms;
+          bestC = chunks[c];
+        }
+      }
+    }
+    cfg.range_chunk = bestC;
+    rep.best_leaf_bytes = bestS;
+    rep.best_chunk = bestC;
+  } catch (const Fail& e) {
+    return e.st;
+  }
+  *out = cfg;
+  if (report) *report = rep;
+  return CPMA_OK;
+}

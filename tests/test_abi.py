@@ -86,3 +86,39 @@ def test_server_argument_checks_without_gpu():
     t0 = p.clock_ns()
     assert p.clock_ns() >= t0 > 0
     assert ctypes.sizeof(p.Request) == 80
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """ctypes mirrors of the C structs have the C compiler's sizes and offsets."""
+    import ctypes
+    import paper_2305_05055_amd as p
+    prog = tmp_path / "sizes.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "cpma.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(cpma_config),"
+        " offsetof(cpma_config, range_chunk), sizeof(cpma_tune_hint), sizeof(cpma_tune_report),"
+        " offsetof(cpma_tune_report, best_chunk), sizeof(cpma_request), sizeof(cpma_phase_stat));return 0;}\n")
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    want = [ctypes.sizeof(p.Config), p.Config.range_chunk.offset, ctypes.sizeof(p.TuneHint),
+            ctypes.sizeof(p.TuneReport), p.TuneReport.best_chunk.offset, ctypes.sizeof(p.Request),
+            ctypes.sizeof(p.PhaseStat)]
+    assert got == want
+
+
+def test_config_defaults_and_checks_without_gpu():
+    import ctypes
+    import paper_2305_05055_amd as p
+    if not os.path.exists(p.LIB_PATH):
+        pytest.skip("libcpma.so not built")
+    L = p.lib()
+    c = p.default_config()
+    assert c.range_chunk == 8
+    h = ctypes.c_void_p()
+    for S, chunk in ((8192, 0), (32, 0), (0, 3), (0, 128)):
+        bad = p.Config()
+        bad.leaf_bytes, bad.range_chunk = S, chunk
+        assert L.cpma_build(None, 0, 0, ctypes.byref(bad), None, ctypes.byref(h)) == 1
+    out = p.Config()
+    assert L.cpma_autotune(None, 0, 0, None, None, None, ctypes.byref(out), None) == 1
