@@ -155,10 +155,86 @@ def fgraph_section(cp, torch, scale, seed):
     return out
 
 
-def serving_section(cp, torch, n0, nreq, seed):
-    """Open-loop Poisson stream of mixed requests against a resident set."""
-    base_d = synth.uniform_keys_torch(n0, seed, "cuda")
-    base = base_d.cpu().numpy().view(np.uint64)
+def time_range(torch, c, dlo, dhi, reps=3):
+    """Batched range_map on device queries: wall time per pass and the scan
+    kernel's algorithmic bytes and device time from the library's HIP events."""
+    c.range_map(dlo, dhi)
+    torch.cuda.synchronize()
+    c.stats_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s_, n_ = c.range_map(dlo, dhi)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    st = c.stats()
+    c.stats_enable(False)
+    keys = int(n_.sum().item())
+    sc_launch, sc_ms, sc_bytes = st["range_scan"]
+    out = {"keys_per_pass": keys, "keys_per_s": keys / dt, "ms_per_pass": dt * 1e3,
+           "scan_kernel_ms": sc_ms / max(1, sc_launch), "scan_alg_bytes": sc_bytes / max(1, sc_launch)}
+    out["scan_alg_GBps"] = out["scan_alg_bytes"] / (out["scan_kernel_ms"] * 1e-3) / 1e9
+    out["frac_hbm_alg"] = out["scan_alg_GBps"] / HBM_PEAK_GBS
+    return out
+
+
+def range_section(cp, torch, c, base_dev, q, seed):
+    """Batched range_map on the 1e8-key set: q queries whose lengths (in keys)
+    are Zipf(1.2) on 1..1e6, each covering exactly its length of the sorted set;
+    on the default layout and on the autotuned one; against one launch per query."""
+    keys_sorted = torch.unique(base_dev).cpu().numpy().view(np.uint64)
+    lens = synth.zipf_lengths(q, seed, alpha=1.2, lmax=10 ** 6)
+    lo, hi = synth.range_queries_by_count(keys_sorted, lens, seed + 1)
+    del keys_sorted
+    dlo, dhi = to_dev(lo), to_dev(hi)
+    out = {"queries": q, "lengths": "Zipf(1.2) on 1..1e6 keys, exact counts",
+           "default": time_range(torch, c, dlo, dhi)}
+    cfg, rep = cp.autotune(base_dev, insert_weight=0.0, range_keys=int(lens.mean()), queries=100_000)
+    out["autotune"] = rep
+    tuned = cp.CPMA(base_dev, config=cfg)
+    torch.cuda.synchronize()
+    res = time_range(torch, tuned, dlo, dhi)
+    res["leaf_bytes"], res["range_chunk"] = int(cfg.leaf_bytes), int(cfg.range_chunk)
+    out["autotuned"] = res
+    # one launch per query on a prefix of the same queries
+    m = min(2000, q)
+    t0 = time.perf_counter()
+    for i in range(m):
+        tuned.range_map(dlo[i:i + 1], dhi[i:i + 1])
+    torch.cuda.synchronize()
+    per_q = (time.perf_counter() - t0) / m
+    t0 = time.perf_counter()
+    tuned.range_map(dlo[:m], dhi[:m])
+    torch.cuda.synchronize()
+    out["one_launch_per_query_s_per_query"] = per_q
+    out["batched_speedup_on_prefix"] = (per_q * m) / (time.perf_counter() - t0)
+    out["batched_speedup_extrapolated"] = (per_q * q) / (res["ms_per_pass"] * 1e-3)
+    tuned.close()
+    log(f"range_map: default {out['default']['keys_per_s']:.3e} keys/s, autotuned (S={res['leaf_bytes']}, "
+        f"chunk={res['range_chunk']}) {res['keys_per_s']:.3e} keys/s, scan {res['scan_alg_GBps']:.0f} GB/s alg")
+    return out
+
+
+def gate_section(cp, torch, c, n0, seed):
+    """range_map on cold data: 1e3 queries of about 1e6 keys at random starts
+    (width = 1e6 * floor(2^40 / n0)) plus one query over the whole key space, on
+    a set far larger than the 256 MB last-level cache."""
+    width = np.uint64(10 ** 6 * ((1 << 40) // n0))
+    lo = synth.uniform_keys(1000, seed)
+    hi = lo + width
+    lo = np.concatenate([lo, np.array([0], np.uint64)])
+    hi = np.concatenate([hi, np.array([(1 << 64) - 1], np.uint64)])
+    res = time_range(torch, c, to_dev(lo), to_dev(hi))
+    res["n0"] = c.size()
+    res["queries"] = "1e3 of ~1e6 keys + 1 full range"
+    log(f"range gate: {res['keys_per_s']:.3e} keys/s, scan {res['scan_alg_GBps']:.0f} GB/s "
+        f"({100 * res['frac_hbm_alg']:.1f}% of HBM peak)")
+    return res
+
+
+def serving_section(cp, torch, c, base, nreq, seed):
+    """Open-loop Poisson stream of mixed requests against the resident set c
+    (built from the keys `base`)."""
+    n0 = len(base)
     width = (1 << 40) // n0
 
     def requests(count, s0):
@@ -197,9 +273,6 @@ def serving_section(cp, torch, n0, nreq, seed):
         return {"ops_s": len(reqs) / ((t1 - t0) * 1e-9), "steps": steps,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
 
-    c = cp.CPMA(base_d)
-    del base_d
-    torch.cuda.synchronize()
     out = {"n0": c.size(), "requests": nreq, "mix": "70% range (Zipf(1.2) 1..1e5), 25% insert, 5% delete "
            "(log-uniform 10..1e6 keys)"}
     sat = run(requests(nreq, seed + 100), 4096)
@@ -210,7 +283,6 @@ def serving_section(cp, torch, n0, nreq, seed):
         out[f"poisson_{frac}"] = run(requests(nreq // 2, seed + int(300 + 100 * frac)), 4096,
                                      rate=frac * sat["ops_s"])
     log(f"serving: {out}")
-    c.close()
     return out
 
 
@@ -228,7 +300,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-steps", action="store_true", help="skip every side measurement")
     ap.add_argument("--fg-scale", type=int, default=24, help="R-MAT scale of the F-Graph section (0: skip)")
-    ap.add_argument("--serve-n", type=float, default=1e8, help="keys of the served set (0: skip serving)")
+    ap.add_argument("--serve-n", type=float, default=1e9,
+                    help="keys of the resident set for the cold range gate and serving (0: skip both)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device to device (reference dispatch for HBM byte counters)")
@@ -282,6 +355,7 @@ def main():
         c.insert_batch(to_dev(more))
         extra.append(more)
     base_all = np.concatenate([base] + extra) if extra else base
+    base_dev = to_dev(base_all) if not args.only_steps else None
     torch.cuda.synchronize()
     L, S = c.geometry()
     log(f"built n={c.size()} L={L} S={S} bytes/key={c.bytes() / c.size():.3f} in {time.time() - t:.1f}s")
@@ -289,50 +363,9 @@ def main():
 
     # ---- batched range_map (Zipf(1.2) lengths 1..1e6) vs one launch per query -----
     if not args.only_steps and args.queries > 0:
-        q = int(args.queries)
-        lens = synth.zipf_lengths(q, seed + 10, alpha=1.2, lmax=10 ** 6)
-        width = np.uint64((1 << 40) // n0)
-        lo = synth.uniform_keys(q, seed + 11)
-        hi = lo + lens.astype(np.uint64) * width
-        dlo, dhi = to_dev(lo), to_dev(hi)
-        c.range_map(dlo, dhi)
-        torch.cuda.synchronize()
-        c.stats_enable(True)
-        reps = 3
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            s_, n_ = c.range_map(dlo, dhi)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
-        st = c.stats()
-        c.stats_enable(False)
-        total_keys = int(n_.sum().item())
-        sc_launch, sc_ms, sc_bytes = st["range_scan"]
-        rm = {
-            "queries": q, "keys_per_pass": total_keys, "keys_per_s": total_keys / dt,
-            "ms_per_pass": dt * 1e3,
-            "scan_kernel_ms": sc_ms / max(1, sc_launch),
-            "scan_alg_bytes": sc_bytes / max(1, sc_launch),
-            "scan_alg_GBps": (sc_bytes / max(1, sc_launch)) / (sc_ms / max(1, sc_launch) * 1e-3) / 1e9,
-        }
-        rm["frac_hbm_alg"] = rm["scan_alg_GBps"] / HBM_PEAK_GBS
-        # one launch per query on a prefix of the same queries
-        m = min(2000, q)
-        t0 = time.perf_counter()
-        for i in range(m):
-            c.range_map(dlo[i:i + 1], dhi[i:i + 1])
-        torch.cuda.synchronize()
-        per_q = (time.perf_counter() - t0) / m
-        t0 = time.perf_counter()
-        c.range_map(dlo[:m], dhi[:m])
-        torch.cuda.synchronize()
-        batched_m = time.perf_counter() - t0
-        rm["one_launch_per_query_s_per_query"] = per_q
-        rm["batched_speedup_on_prefix"] = (per_q * m) / batched_m
-        rm["batched_speedup_extrapolated"] = (per_q * q) / dt
-        result_extra["range_map"] = rm
-        log(f"range_map: {total_keys / dt:.3e} keys/s, scan {rm['scan_alg_GBps']:.0f} GB/s alg")
-        del dlo, dhi
+        result_extra["range_map"] = range_section(cp, torch, c, base_dev, int(args.queries), seed + 10)
+    base_dev = None
+    torch.cuda.empty_cache()
 
     # ---- batch-size sweep: insert k fresh keys, then delete k present keys --------
     per_batch = {}
@@ -422,7 +455,21 @@ def main():
         result_extra["fgraph"] = fgraph_section(cp, torch, args.fg_scale, seed + 60)
         torch.cuda.empty_cache()
     if not args.only_steps and args.serve_n > 0:
-        result_extra["serving"] = serving_section(cp, torch, int(args.serve_n), args.serve_requests, seed + 70)
+        # one resident set of serve_n keys: the cold range gate, then the serving loop
+        n_big = int(args.serve_n)
+        big_d = synth.uniform_keys_torch(n_big, seed + 70, "cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        big = cp.CPMA(big_d)
+        torch.cuda.synchronize()
+        log(f"built {big.size()} keys in {time.perf_counter() - t0:.1f}s, {big.bytes() / big.size():.3f} B/key")
+        big_host = big_d.cpu().numpy().view(np.uint64)
+        del big_d
+        torch.cuda.empty_cache()
+        result_extra["range_gate"] = gate_section(cp, torch, big, n_big, seed + 80)
+        result_extra["serving"] = serving_section(cp, torch, big, big_host, args.serve_requests, seed + 90)
+        big.close()
+        del big_host
 
     # ---- CPU baseline: the oracle inserting the same kind of batches ------------
     cpu = None
