@@ -305,6 +305,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device to device (reference dispatch for HBM byte counters)")
+    ap.add_argument("--fg-only", action="store_true", help="run only the F-Graph section (diagnostics)")
+    ap.add_argument("--gate-only", action="store_true", help="run only the cold range gate (diagnostics)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the merge kernel's traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
@@ -341,6 +343,16 @@ def main():
     n0 = int(args.n)
     k = int(args.batch)
     seed = synth.SEED_BASE + 2
+    if args.fg_only:
+        print(json.dumps(fgraph_section(cp, torch, args.fg_scale, seed + 60)), flush=True)
+        return
+    if args.gate_only:
+        big_d = synth.uniform_keys_torch(int(args.serve_n), seed + 70, "cuda")
+        big = cp.CPMA(big_d)
+        del big_d
+        torch.cuda.empty_cache()
+        print(json.dumps(gate_section(cp, torch, big, int(args.serve_n), seed + 80)), flush=True)
+        return
 
     # ---- base set: exactly n0 distinct uniform 40-bit keys -----------------------
     t = time.time()

@@ -809,6 +809,14 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
                        (const uint64_t*)s->head.as<uint64_t>(), L, B, s->dctr);
   }
   HIPCHK(hipGetLastError());
+  if (s->S <= kWaveMaxS) {
+    // route segments: narrow (32-bit wave merge), wide (64-bit), long insert slices (lane merge)
+    const uint64_t nseg = std::min<uint64_t>(kbound, L);
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(nseg, 256, (uint32_t)s->num_cus * 8)), dim3(256), 0, st,
+                       s->seg_desc.as<uint4>(), (const uint32_t*)s->seg_begin.as<uint32_t>(), kWaveSlice,
+                       insert ? 1 : 0, s->wide.as<uint32_t>(), s->spill.as<uint32_t>(), s->dctr, nseg);
+    HIPCHK(hipGetLastError());
+  }
   phase_end(s, pl, st, 24ull * kbound);
   MergeArgs a;
   a.bytes = s->bytes.as<uint8_t>();
@@ -831,6 +839,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   a.is_insert = insert ? 1 : 0;
   const uint64_t segs = std::min<uint64_t>(kbound, s->L);
   const uint32_t lgrid = (uint32_t)std::min<uint64_t>((segs + 255) / 256, (uint64_t)s->num_cus * 16);
+
   // MERGE times exactly the main merge kernel; HEAVY the follow-up kernels for
   // wide, long and heavy slices
   PhaseMark pmg = phase_begin(s, CPMA_PHASE_MERGE, st);

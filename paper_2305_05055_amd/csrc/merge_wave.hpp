@@ -118,14 +118,7 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
     e_cur = e_nxt;
     w_cur = w_nxt;
     b_cur = b_nxt;
-    if (a.is_insert && nb > kWaveSlice) {
-      if (lane == 0) a.spill_list[atomicAdd(&a.ctr->nspill, 1u)] = (uint32_t)s;
-      continue;
-    }
-    if (wide) {
-      if (lane == 0) a.wide_list[atomicAdd(&a.ctr->nwide, 1u)] = (uint32_t)s;
-      continue;
-    }
+    if (wide) continue;  // routed by k_classify to the wide or spill list
     // smallest possible key of the segment: the old head or the first slice key
     uint64_t base = 0;
     if (kNarrow) {

@@ -68,8 +68,13 @@ __global__ void __launch_bounds__(256) k_rm_ends(QueryArgs a, uint64_t* __restri
 
 // Interior visits, flattened over all queries: each lane takes `chunk`
 // consecutive visits (consecutive leaves of one query, or the tail of one query
-// and the head of the next), keeps running sums in registers while the query is
-// unchanged and flushes them with 64-bit atomics (exact: integer adds commute).
+// and the head of the next) and keeps running sums in registers while the query
+// is unchanged.  Partial sums are exact integers, so they may be combined in any
+// order: a lane flushes a finished query with 64-bit atomics, and the partials
+// still open at the end of a chunk are first reduced by query across the wave
+// (lanes hold consecutive chunks, so equal queries sit in runs of lanes), leaving
+// one atomic per run -- a query spanning millions of leaves would otherwise
+// serialise on one address.
 __global__ void __launch_bounds__(256) k_rm_interior(QueryArgs a, const uint64_t* __restrict__ ioff,
                                                      const uint64_t* __restrict__ first_int, uint32_t chunk,
                                                      unsigned long long* __restrict__ sum,
@@ -78,39 +83,56 @@ __global__ void __launch_bounds__(256) k_rm_interior(QueryArgs a, const uint64_t
   const uint64_t lanes = (uint64_t)gridDim.x * blockDim.x;
   const uint64_t V = ioff[a.q];
   const uint64_t nchunks = (V + chunk - 1) / chunk;
+  const uint64_t npad = (nchunks + kWave - 1) / kWave * kWave;  // whole waves iterate together
+  const int lane = lane_id();
   uint64_t visited = 0;
-  for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nchunks; c += lanes) {
-    const uint64_t v0 = c * chunk;
-    const uint64_t v1 = min(v0 + chunk, V);
-    uint64_t qi = upper_bound_u64(ioff, a.q + 1, v0) - 1;
-    uint64_t qbeg = ioff[qi], qend = ioff[qi + 1];
-    uint64_t fl = first_int[qi];
-    uint64_t s = 0, n = 0;
-    for (uint64_t v = v0; v < v1; v++) {
-      if (v >= qend) {
-        if (n) {
-          atomicAdd(&sum[qi], (unsigned long long)s);
-          atomicAdd(&count[qi], (unsigned long long)n);
+  for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < npad; c += lanes) {
+    uint64_t qi = ~0ull, s = 0, n = 0;
+    if (c < nchunks) {
+      const uint64_t v0 = c * chunk;
+      const uint64_t v1 = min(v0 + chunk, V);
+      qi = upper_bound_u64(ioff, a.q + 1, v0) - 1;
+      uint64_t qbeg = ioff[qi], qend = ioff[qi + 1];
+      uint64_t fl = first_int[qi];
+      for (uint64_t v = v0; v < v1; v++) {
+        if (v >= qend) {
+          if (n) {
+            atomicAdd(&sum[qi], (unsigned long long)s);
+            atomicAdd(&count[qi], (unsigned long long)n);
+          }
+          s = n = 0;
+          do {
+            qi++;
+            qbeg = ioff[qi];
+            qend = ioff[qi + 1];
+          } while (v >= qend);
+          fl = first_int[qi];
         }
-        s = n = 0;
-        do {
-          qi++;
-          qbeg = ioff[qi];
-          qend = ioff[qi + 1];
-        } while (v >= qend);
-        fl = first_int[qi];
+        const uint64_t leaf = fl + (v - qbeg);
+        const uint32_t u = a.used[leaf];
+        const uint64_t h = a.head[leaf];
+        const uint64_t span = a.head[leaf + 1] - h;  // interior leaves always have a successor
+        const uint8_t* lp = a.bytes + leaf * (uint64_t)a.S;
+        const LeafSum r = span < (1ull << 28) ? leaf_sum_fast(lp, u, h) : leaf_sum_range(lp, u, 0, kNoKey);
+        s += r.sum;
+        n += r.count;
+        visited += u;
       }
-      const uint64_t leaf = fl + (v - qbeg);
-      const uint32_t u = a.used[leaf];
-      const uint64_t h = a.head[leaf];
-      const uint64_t span = a.head[leaf + 1] - h;  // interior leaves always have a successor
-      const uint8_t* lp = a.bytes + leaf * (uint64_t)a.S;
-      const LeafSum r = span < (1ull << 28) ? leaf_sum_fast(lp, u, h) : leaf_sum_range(lp, u, 0, kNoKey);
-      s += r.sum;
-      n += r.count;
-      visited += u;
     }
-    if (n) {
+    // segmented inclusive scan over runs of equal qi (qi is non-decreasing over lanes)
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint64_t qu = __shfl_up(qi, d, kWave);
+      const uint64_t su = __shfl_up(s, d, kWave);
+      const uint64_t nu = __shfl_up(n, d, kWave);
+      if (lane >= d && qu == qi) {
+        s += su;
+        n += nu;
+      }
+    }
+    const uint64_t qn = __shfl_down(qi, 1, kWave);
+    const bool run_end = lane == kWave - 1 || qn != qi;
+    if (run_end && qi != ~0ull && n) {
       atomicAdd(&sum[qi], (unsigned long long)s);
       atomicAdd(&count[qi], (unsigned long long)n);
     }

@@ -78,6 +78,25 @@ __device__ __forceinline__ LeafSum leaf_sum_fast(const uint8_t* __restrict__ lea
   return r;
 }
 
+// The same in 128-byte rounds: a lane's eight loads of one round cover one whole
+// cache line, so a line is consumed before any other lane's stream can evict it
+// (many lanes stream separate leaves at once, far more lines than L2 holds).
+__device__ __forceinline__ LeafSum leaf_sum_fast_line(const uint8_t* __restrict__ leaf, uint32_t used,
+                                                      uint64_t head) {
+  LeafSum r{head, 1};
+  uint64_t base = head;
+  uint32_t sh = 0;
+  const uint4 z = make_uint4(0, 0, 0, 0);
+  for (uint32_t c = 0; c < used; c += 128) {
+    uint4 q[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) q[k] = (c + 16u * k < used) ? load16(leaf + c + 16u * k) : z;
+#pragma unroll
+    for (int k = 0; k < 8; k++) fast_chunk(q[k], c + 16u * k, used, base, sh, r);
+  }
+  return r;
+}
+
 // General path: 64-bit decode; counts and sums keys in [lo, hi).  Stops early
 // once a key reaches hi.
 __device__ __forceinline__ LeafSum leaf_sum_range(const uint8_t* __restrict__ leaf, uint32_t used,

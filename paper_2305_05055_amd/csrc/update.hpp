@@ -147,6 +147,42 @@ __global__ void k_segments_by_leaf(const uint32_t* __restrict__ sbeg, const unsi
   }
 }
 
+// Appends `value` for every active lane with pred set: one atomic per wave.
+__device__ __forceinline__ void wave_append(uint32_t* __restrict__ list, unsigned int* counter, bool pred,
+                                            uint32_t value) {
+  const uint64_t m = __ballot(pred);
+  if (!m) return;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, (unsigned int)__popcll(m));
+  base = __shfl(base, leader, kWave);
+  if (pred) list[base + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull))] = value;
+}
+
+// Segment routing for the wave merge: inserts with more keys than one wave takes
+// go to the lane merge (spill list), segments of wide key span to the 64-bit
+// instance (wide list); desc.w becomes 0 (narrow instance), 1 (wide) or 2 (spill).
+__global__ void k_classify(uint4* __restrict__ seg_desc, const uint32_t* __restrict__ seg_begin, uint32_t slice,
+                           int is_insert, uint32_t* __restrict__ wide_list, uint32_t* __restrict__ spill_list,
+                           Counters* ctr, uint64_t bound) {
+  const uint64_t T = ctr->T;
+  const uint64_t n = (bound + kWave - 1) / kWave * kWave;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (uint64_t)gridDim.x * blockDim.x) {
+    bool spill = false, wide = false;
+    if (s < T) {
+      uint4 d = seg_desc[s];
+      const uint32_t nb = seg_begin[s + 1] - d.y;
+      spill = is_insert && nb > slice;
+      wide = !spill && d.w != 0;
+      d.w = spill ? 2u : (wide ? 1u : 0u);
+      seg_desc[s] = d;
+    }
+    wave_append(spill_list, &ctr->nspill, spill, (uint32_t)s);
+    wave_append(wide_list, &ctr->nwide, wide, (uint32_t)s);
+  }
+}
+
 // ---- per-leaf merge -------------------------------------------------------------
 struct MergeArgs {
   uint8_t* bytes;
