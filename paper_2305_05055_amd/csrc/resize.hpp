@@ -33,53 +33,12 @@ struct SplitRec {
   uint32_t cost;  // its chain cost
 };
 
-// Last key of a leaf: the head plus every delta, one lane per leaf streaming
-// the leaf in 64-byte rounds with the next round's four loads in flight.  A
-// code's value is the sum of its payload groups shifted by 7 bits per byte, so
-// the running total needs no per-key step.  Narrow form: every delta is below
-// 2^28 (32-bit shifts).
-__device__ __forceinline__ uint32_t last_chunk(const uint4 q, uint32_t c, uint32_t used, uint32_t& sh) {
-  const uint32_t words[4] = {q.x, q.y, q.z, q.w};
-  const uint32_t nvalid = c < used ? min(16u, used - c) : 0u;
-  uint32_t Dc = 0;
-#pragma unroll
-  for (int i = 0; i < 16; i++) {
-    const uint32_t w = words[i >> 2];
-    const int o = 8 * (i & 3);
-    const bool valid = (uint32_t)i < nvalid && !(c == 0 && i < 8);
-    const uint32_t pb = valid ? ((w >> o) & 0x7fu) : 0u;
-    const bool term = !((w >> (o + 7)) & 1u);
-    Dc += pb << sh;
-    sh = !valid ? sh : (term ? 0u : sh + 7u);
-  }
-  return Dc;
-}
-
+// Last key of a leaf: the head plus every delta.  Narrow form (every delta below
+// 2^28): the range scan's lane decoder, which ends on the last key.
 __device__ __forceinline__ uint64_t leaf_last_narrow(const uint8_t* __restrict__ leaf, uint32_t used,
                                                      uint64_t head) {
   uint64_t last = head;
-  uint32_t sh = 0;
-  const uint4 z = make_uint4(0, 0, 0, 0);
-  uint4 a0 = load16(leaf);
-  uint4 a1 = 16 < used ? load16(leaf + 16) : z;
-  uint4 a2 = 32 < used ? load16(leaf + 32) : z;
-  uint4 a3 = 48 < used ? load16(leaf + 48) : z;
-  for (uint32_t c = 0; c < used; c += 64) {
-    uint4 b0 = z, b1 = z, b2 = z, b3 = z;
-    if (c + 64 < used) b0 = load16(leaf + c + 64);
-    if (c + 80 < used) b1 = load16(leaf + c + 80);
-    if (c + 96 < used) b2 = load16(leaf + c + 96);
-    if (c + 112 < used) b3 = load16(leaf + c + 112);
-    uint32_t D = last_chunk(a0, c, used, sh);
-    D += last_chunk(a1, c + 16, used, sh);
-    D += last_chunk(a2, c + 32, used, sh);
-    D += last_chunk(a3, c + 48, used, sh);
-    last += D;
-    a0 = b0;
-    a1 = b1;
-    a2 = b2;
-    a3 = b3;
-  }
+  leaf_sum_fast(leaf, used, head, &last);
   return last;
 }
 

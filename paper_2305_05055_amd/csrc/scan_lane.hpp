@@ -26,33 +26,53 @@ __device__ __forceinline__ uint4 load16(const uint8_t* p) { return *reinterpret_
 //
 // Per byte: p = payload bits, the running chunk-relative delta Dc grows by
 // p << sh; at a terminator byte Dc equals (key - key at chunk start), so the
-// chunk's keys sum to cnt * base + sum of Dc at terminators.  The leaf streams
-// in 64-byte rounds with the next round's four loads in flight.
+// chunk's keys sum to cnt * base + sum of Dc at terminators.  The byte loop has
+// no validity tests: bytes at or past `used` are rewritten to 0x80, continuation
+// bytes without payload (one masked merge per word, in the last chunk only); the head's eight
+// bytes become seven such bytes and a zero terminator, so the head counts as a
+// key at offset 0 from the chunk base (the head itself).  The terminator count
+// is one popcount per word.  The leaf streams in 64-byte rounds with the next
+// round's four loads in flight.
 __device__ __forceinline__ void fast_chunk(const uint4 q, uint32_t c, uint32_t used, uint64_t& base, uint32_t& sh,
                                            LeafSum& r) {
-  const uint32_t words[4] = {q.x, q.y, q.z, q.w};
-  const uint32_t nvalid = c < used ? min(16u, used - c) : 0u;
-  uint32_t Dc = 0, Sc = 0, cnt = 0;
+  uint32_t w[4] = {q.x, q.y, q.z, q.w};
+  if (c == 0) {
+    w[0] = 0x80808080u;
+    w[1] = 0x00808080u;
+  }
+  const int32_t nv = (int32_t)used - (int32_t)c;
+  if (nv < 16) {
+    // bytes at or past `used` (zero fill in place; arbitrary in an overflow
+    // copy) become exactly 0x80
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int32_t v = nv - 4 * k;
+      const uint32_t keep = v >= 4 ? 0xffffffffu : (v <= 0 ? 0u : ((1u << (8 * v)) - 1u));
+      w[k] = (w[k] & keep) | (0x80808080u & ~keep);
+    }
+  }
+  const uint32_t cnt = (uint32_t)(__popc(~w[0] & 0x80808080u) + __popc(~w[1] & 0x80808080u) +
+                                  __popc(~w[2] & 0x80808080u) + __popc(~w[3] & 0x80808080u));
+  uint32_t Dc = 0, Sc = 0;
 #pragma unroll
   for (int i = 0; i < 16; i++) {
-    const uint32_t w = words[i >> 2];
+    const uint32_t x = w[i >> 2];
     const int o = 8 * (i & 3);
-    const bool valid = (uint32_t)i < nvalid && !(c == 0 && i < 8);
-    const uint32_t p = valid ? ((w >> o) & 0x7fu) : 0u;
-    const bool term = valid && !((w >> (o + 7)) & 1u);
-    Dc += p << sh;
-    sh = term ? 0u : (valid ? sh + 7u : sh);
-    Sc += term ? Dc : 0u;
-    cnt += term ? 1u : 0u;
+    const uint32_t p = (x >> o) & 0x7fu;
+    const uint32_t cm = 0u - ((x >> (o + 7)) & 1u);  // all ones on a continuation byte
+    Dc += p << (sh & 31u);
+    Sc += Dc & ~cm;
+    sh = (sh + 7u) & cm;
   }
   r.sum += (uint64_t)cnt * base + Sc;
   r.count += cnt;
   base += Dc;
 }
 
+// Also returns the leaf's last key through *last.
 __device__ __forceinline__ LeafSum leaf_sum_fast(const uint8_t* __restrict__ leaf, uint32_t used,
-                                                 uint64_t head) {
-  LeafSum r{head, 1};
+                                                 uint64_t head, uint64_t* last = nullptr) {
+  LeafSum r{0, 0};
   uint64_t base = head;  // key value reached by the running delta so far
   uint32_t sh = 0;
   const uint4 z = make_uint4(0, 0, 0, 0);
@@ -75,25 +95,7 @@ __device__ __forceinline__ LeafSum leaf_sum_fast(const uint8_t* __restrict__ lea
     a2 = b2;
     a3 = b3;
   }
-  return r;
-}
-
-// The same in 128-byte rounds: a lane's eight loads of one round cover one whole
-// cache line, so a line is consumed before any other lane's stream can evict it
-// (many lanes stream separate leaves at once, far more lines than L2 holds).
-__device__ __forceinline__ LeafSum leaf_sum_fast_line(const uint8_t* __restrict__ leaf, uint32_t used,
-                                                      uint64_t head) {
-  LeafSum r{head, 1};
-  uint64_t base = head;
-  uint32_t sh = 0;
-  const uint4 z = make_uint4(0, 0, 0, 0);
-  for (uint32_t c = 0; c < used; c += 128) {
-    uint4 q[8];
-#pragma unroll
-    for (int k = 0; k < 8; k++) q[k] = (c + 16u * k < used) ? load16(leaf + c + 16u * k) : z;
-#pragma unroll
-    for (int k = 0; k < 8; k++) fast_chunk(q[k], c + 16u * k, used, base, sh, r);
-  }
+  if (last) *last = base;
   return r;
 }
 
