@@ -1083,8 +1083,12 @@ cpma_status cpma_range_map(const cpma* cs, const uint64_t* lo, const uint64_t* h
     ensure(s->qvoff, (q + 1) * 8);
     PhaseMark pq = phase_begin(s, CPMA_PHASE_QUERY, st);
     unsigned long long* qalg = s->stats_on ? s->dqalg : (unsigned long long*)nullptr;
-    hipLaunchKernelGGL(k_rm_ends, dim3(grid_for(q, 256, (uint32_t)s->num_cus * 16)), dim3(256), 0, st, a,
-                       s->qfirst.as<uint64_t>(), s->qnvis.as<uint64_t>(), dsum, dcount, qalg);
+    if (q <= (uint64_t)s->num_cus * 64)  // few queries: a wave per query
+      hipLaunchKernelGGL(k_rm_ends_wave, dim3(grid_for(q, 1, (uint32_t)s->num_cus * 64)), dim3(kWave), 0, st, a,
+                         s->qfirst.as<uint64_t>(), s->qnvis.as<uint64_t>(), dsum, dcount, qalg);
+    else
+      hipLaunchKernelGGL(k_rm_ends, dim3(grid_for(q, 256, (uint32_t)s->num_cus * 16)), dim3(256), 0, st, a,
+                         s->qfirst.as<uint64_t>(), s->qnvis.as<uint64_t>(), dsum, dcount, qalg);
     HIPCHK(hipGetLastError());
     scan<uint64_t>(s, s->qvoff.as<uint64_t>(), q, st, LoadFn<uint64_t>{s->qnvis.as<uint64_t>()});
     const uint32_t blocks = (uint32_t)s->num_cus * 8;

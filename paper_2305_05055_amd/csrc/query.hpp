@@ -66,6 +66,75 @@ __global__ void __launch_bounds__(256) k_rm_ends(QueryArgs a, uint64_t* __restri
   }
 }
 
+// Few queries: one wave per query.  The leaf of a key comes from a 64-ary
+// search of the heads (64 pivots compared per step, so a few steps for millions
+// of leaves), and the two end leaves are decoded by the whole wave.
+__device__ __forceinline__ uint64_t wave_locate_leaf(const uint64_t* __restrict__ head, uint64_t L, uint64_t x) {
+  uint64_t lo = 0, hi = L;  // the first head above x lies in [lo, hi]
+  const uint32_t lane = (uint32_t)lane_id();
+  while (lo < hi) {
+    const uint64_t step = (hi - lo + kWave - 1) / kWave;
+    const uint64_t idx = lo + lane * step;
+    const bool le = idx < hi && head[idx] <= x;
+    const uint32_t t = (uint32_t)__popcll(__ballot(le));  // pivots at or below x form a prefix
+    if (t == 0) {
+      hi = lo;
+    } else {
+      const uint64_t last = lo + (uint64_t)(t - 1) * step;
+      lo = last + 1;
+      hi = min(hi, last + step);
+    }
+  }
+  return lo ? lo - 1 : 0;
+}
+
+__device__ __forceinline__ LeafSum wave_leaf_sum_range(const uint8_t* __restrict__ leaf, uint32_t used, uint64_t lo,
+                                                       uint64_t hi) {
+  uint64_t s = 0, n = 0;
+  wave_decode_leaf(leaf, used, [&](uint32_t, uint64_t k, uint64_t) {
+    if (k >= lo && k < hi) {
+      s += k;
+      n++;
+    }
+  });
+  return LeafSum{wave_sum(s), wave_sum(n)};
+}
+
+__global__ void __launch_bounds__(kWave) k_rm_ends_wave(QueryArgs a, uint64_t* __restrict__ first_int,
+                                                        uint64_t* __restrict__ nint,
+                                                        unsigned long long* __restrict__ sum,
+                                                        unsigned long long* __restrict__ count,
+                                                        unsigned long long* __restrict__ alg) {
+  uint64_t visited = 0;
+  for (uint64_t i = blockIdx.x; i < a.q; i += gridDim.x) {
+    const uint64_t lo = a.lo[i], hi = a.hi[i];
+    uint64_t f = 0, n = 0;
+    LeafSum r{0, 0};
+    if (lo < hi) {
+      f = wave_locate_leaf(a.head, a.L, lo);
+      const uint64_t l = wave_locate_leaf(a.head, a.L, hi - 1);
+      const uint32_t uf = a.used[f];
+      r = wave_leaf_sum_range(a.bytes + f * (uint64_t)a.S, uf, lo, hi);
+      visited += uf;
+      if (l != f) {
+        const uint32_t ul = a.used[l];
+        const LeafSum r2 = wave_leaf_sum_range(a.bytes + l * (uint64_t)a.S, ul, lo, hi);
+        r.sum += r2.sum;
+        r.count += r2.count;
+        visited += ul;
+      }
+      n = (l > f + 1) ? l - f - 1 : 0;
+    }
+    if (lane_id() == 0) {
+      first_int[i] = f + 1;
+      nint[i] = n;
+      sum[i] = r.sum;
+      count[i] = r.count;
+    }
+  }
+  if (alg && lane_id() == 0 && visited) atomicAdd(alg, (unsigned long long)visited);
+}
+
 // Interior visits, flattened over all queries: each lane takes `chunk`
 // consecutive visits (consecutive leaves of one query, or the tail of one query
 // and the head of the next) and keeps running sums in registers while the query
