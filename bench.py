@@ -86,7 +86,7 @@ def pmc_summary(fetch_csv, write_csv, steps, cmd_fetch, cmd_write):
         "The first dispatch of each run is a 1 GiB device-to-device copy "
         "(`--calibrate-copy`); the counter's reading for it gives the scale factor "
         "(bytes actually moved / counter bytes).", "",
-        "| counter | copy reads (KiB) | factor | per timed launch (KiB) | per launch (bytes, scaled) |",
+        "| counter | calibration copy (KiB) | factor | per timed launch (KiB) | per launch (bytes, scaled) |",
         "|---|---|---|---|---|"]
     for tag, ctr in (("read", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
         o = out[tag]
@@ -307,6 +307,7 @@ def main():
                     help="first copy 1 GiB device to device (reference dispatch for HBM byte counters)")
     ap.add_argument("--fg-only", action="store_true", help="run only the F-Graph section (diagnostics)")
     ap.add_argument("--gate-only", action="store_true", help="run only the cold range gate (diagnostics)")
+    ap.add_argument("--range-only", action="store_true", help="run only the batched range_map section (diagnostics)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the merge kernel's traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
@@ -373,6 +374,10 @@ def main():
     log(f"built n={c.size()} L={L} S={S} bytes/key={c.bytes() / c.size():.3f} in {time.time() - t:.1f}s")
     result_extra = {"bytes_per_key_at_n0": c.bytes() / c.size(), "leaves_at_n0": L, "leaf_bytes": S}
 
+    if args.range_only:
+        print(json.dumps(range_section(cp, torch, c, base_dev if base_dev is not None else to_dev(base_all),
+                                       int(args.queries), seed + 10)), flush=True)
+        return
     # ---- batched range_map (Zipf(1.2) lengths 1..1e6) vs one launch per query -----
     if not args.only_steps and args.queries > 0:
         result_extra["range_map"] = range_section(cp, torch, c, base_dev, int(args.queries), seed + 10)

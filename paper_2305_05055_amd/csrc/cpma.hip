@@ -47,7 +47,7 @@ struct Fail {
   } while (0)
 
 // Grows b to at least `bytes` (contents are not kept), with `slack` extra room.
-void ensure(DevBuf& b, size_t bytes, double slack = 0.5) {
+void ensure(DevBuf& b, size_t bytes, double slack = 1.0) {
   if (bytes == 0) bytes = 16;
   if (b.cap >= bytes) return;
   if (b.p) {
@@ -101,7 +101,7 @@ struct cpma {
       stage, pyr, win, wargs, cnt, koff, win_id, welem, P, ccost, ncost, lstart, planU, plan_used,
       spare_bytes, spare_used, spare_head, fg_level, fg_deg, fg_p, fg_c, fg_acc,
       win_of_leaf, fail, qa, qb, qfirst, qnvis, qvoff, qsum, qcount, qout, lastk, ne_rank, ne_list, chain_pfx,
-      srec, wide;
+      srec, wide, srcinfo;
   Counters* dctr = nullptr;
   Counters* hctr = nullptr;
   BatchInfo* dinfo = nullptr;
@@ -630,6 +630,11 @@ bool split_resize(cpma* s, uint64_t Lt, uint64_t total_used, hipStream_t st, uin
   a.CP = s->chain_pfx.as<uint64_t>();
   a.L = L;
   scan<uint64_t>(s, s->chain_pfx.as<uint64_t>(), L, st, ChainFn{sl.used, a.head, a.lastk, a.rank, a.ne});
+  ensure(s->srcinfo, std::max<uint64_t>(L, 1) * sizeof(SrcInfo));
+  hipLaunchKernelGGL(k_src_info, dim3(grid_for(L, 256, 1u << 16)), dim3(256), 0, st, sl.used, a.head, a.lastk,
+                     a.rank, a.ne, L, s->srcinfo.as<SrcInfo>());
+  HIPCHK(hipGetLastError());
+  a.info = s->srcinfo.as<SrcInfo>();
   const double g = s->cfg.grow;
   int last_dir = 0;
   for (int attempt = 0; attempt < 64; attempt++) {
@@ -1302,7 +1307,7 @@ void cpma_destroy(cpma* s) {
                     &s->fg_level, &s->fg_deg, &s->fg_p, &s->fg_c, &s->fg_acc, &s->lstart, &s->planU,
                     &s->plan_used, &s->win_of_leaf, &s->fail, &s->qa,        &s->qb,    &s->qfirst, &s->qnvis,
                     &s->qvoff,  &s->qsum,     &s->qcount,    &s->qout,  &s->lastk, &s->ne_rank, &s->ne_list,
-                    &s->chain_pfx, &s->srec, &s->wide};
+                    &s->chain_pfx, &s->srec, &s->wide, &s->srcinfo};
   for (DevBuf* b : bufs) release(*b);
   if (s->dctr) hipFree(s->dctr);
   if (s->dinfo) hipFree(s->dinfo);

@@ -111,8 +111,36 @@ struct ChainFn {
   }
 };
 
+// Per old leaf, what the writer needs when it walks from one source leaf to the
+// next: one 32-byte load per hop instead of a chain of dependent loads.
+struct SrcInfo {
+  uint64_t head;
+  uint64_t lastk;
+  uint32_t used;
+  uint32_t next;  // next non-empty old leaf (L after the last)
+  uint64_t pad;
+};
+
+__global__ void k_src_info(const uint32_t* __restrict__ used, const uint64_t* __restrict__ head,
+                           const uint64_t* __restrict__ lastk, const uint32_t* __restrict__ rank,
+                           const uint32_t* __restrict__ ne, uint64_t L, SrcInfo* __restrict__ info) {
+  for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < L;
+       f += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t u = used[f];
+    if (u == 0) continue;
+    SrcInfo I;
+    I.head = head[f];
+    I.lastk = lastk[f];
+    I.used = u;
+    I.next = ne[rank[f] + 1];
+    I.pad = 0;
+    info[f] = I;
+  }
+}
+
 struct SplitArgs {
   SrcLeaves src;
+  const SrcInfo* info;
   const uint64_t* head;   // old heads
   const uint64_t* lastk;  // old last keys
   const uint32_t* rank;   // non-empty rank of each old leaf
@@ -167,8 +195,61 @@ __global__ void __launch_bounds__(256) k_split_locate(SplitArgs a, SplitRec* __r
       T = split_threshold(j, total, Lt);
     }
     if (j >= jend) continue;
-    // walk the codes of f: the code starting at byte s has chain prefix c0 + hc + s - 8
     const uint8_t* leaf = a.src.ptr(f, u);
+    const uint64_t nx = f + 1 < a.L ? a.head[f + 1] : ~0ull;
+    if (nx > h && nx - h < (1ull << 28)) {
+      // narrow leaf (every delta below 2^28): 32-bit walk with the next chunk in
+      // flight; bytes past `used` become payload-free continuation bytes and the
+      // head a zero terminator, as in the range scan's decoder.  The code that
+      // starts at byte s (s >= 8) reaches threshold T when s >= T - c0 - hc + 8.
+      auto first_byte = [&](uint64_t t) -> uint32_t {
+        const uint64_t over = t - c0;
+        return over <= hc ? 8u : (uint32_t)min<uint64_t>(over - hc + 8u, 0xffffffffull);
+      };
+      uint32_t bp = first_byte(T);
+      uint32_t key32 = 0, acc = 0, sh = 0, start = 0;
+      uint4 nxt = load16(leaf);
+      for (uint32_t c = 0; c < u && j < jend; c += 16) {
+        const uint4 cur = nxt;
+        if (c + 16 < u) nxt = load16(leaf + c + 16);
+        uint32_t w[4] = {cur.x, cur.y, cur.z, cur.w};
+        if (c == 0) {
+          w[0] = 0x80808080u;
+          w[1] = 0x00808080u;
+        }
+        const int32_t nv = (int32_t)u - (int32_t)c;
+        if (nv < 16) {
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const int32_t v = nv - 4 * k;
+            const uint32_t keep = v >= 4 ? 0xffffffffu : (v <= 0 ? 0u : ((1u << (8 * v)) - 1u));
+            w[k] = (w[k] & keep) | (0x80808080u & ~keep);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+          const uint32_t x = w[i >> 2];
+          const int o = 8 * (i & 3);
+          const uint32_t cm = 0u - ((x >> (o + 7)) & 1u);  // all ones on a continuation byte
+          acc |= ((x >> o) & 0x7fu) << (sh & 31u);
+          key32 += acc & ~cm;
+          if (!cm && start >= 8u && start >= bp && j < jend) {
+            const uint32_t end = c + (uint32_t)i;
+            const uint64_t P = c0 + hc + start - 8u;
+            do {
+              put_rec(rec, j, f, h + key32, P, start, end + 1u - start);
+              j++;
+              T = split_threshold(j, total, Lt);
+              bp = first_byte(T);
+            } while (j < jend && start >= bp);
+          }
+          acc &= cm;
+          start = cm ? start : c + (uint32_t)i + 1u;
+          sh = (sh + 7u) & cm;
+        }
+      }
+    } else {
+    // walk the codes of f: the code starting at byte s has chain prefix c0 + hc + s - 8
     uint64_t key = h, acc = 0;
     uint32_t sh = 0, start = 8;
     for (uint32_t c = 0; c < u && j < jend; c += 16) {
@@ -197,6 +278,7 @@ __global__ void __launch_bounds__(256) k_split_locate(SplitArgs a, SplitRec* __r
           }
         }
       }
+    }
     }
     if (j < jend) {
       const uint64_t hf = a.ne[a.rank[f] + 1];
@@ -252,23 +334,29 @@ __device__ __forceinline__ void wave_copy_bytes(uint8_t* dst, uint32_t dst_cap, 
 
 // Writes destination leaf j from the old images (a planned split: no leaf is
 // empty or above S bytes).  A length that disagrees with the plan sets the
-// error counter.
+// error counter.  The next source leaf's record loads while the current
+// leaf's bytes are copied.
 __global__ void __launch_bounds__(kWave) k_split_write(SplitArgs a, uint32_t S, const SplitRec* __restrict__ rec,
                                                        uint8_t* __restrict__ dbytes, uint32_t* __restrict__ dused,
                                                        uint64_t* __restrict__ dhead, Counters* ctr) {
   extern __shared__ __align__(16) uint8_t buf[];
   for (uint64_t j = blockIdx.x; j < a.Lt; j += gridDim.x) {
     const SplitRec A = rec[j], B = rec[j + 1];
+    bool bad = A.leaf >= a.L;
+    uint64_t f = bad ? 0 : A.leaf;
+    SrcInfo I = a.info[f];
     wave_zero(buf, S);
     __syncthreads();
     if (lane_id() == 0) put_le64(buf, A.x);
     uint32_t pos = 8;
-    uint64_t f = A.leaf;
     uint32_t bs = A.p == 0 ? 8u : A.p + A.cost;
-    bool bad = f >= a.L;
     while (!bad) {
-      const uint32_t u = a.src.used[f];
+      const uint32_t u = I.used;
       const bool last = f == B.leaf;  // the end lies inside leaf f (B.p >= 8)
+      const uint64_t fn = I.next;
+      const bool hop = !last && fn < a.L && !(fn == B.leaf && B.p == 0);
+      SrcInfo In;
+      if (hop) In = a.info[fn];
       const uint32_t be = last ? B.p : u;
       if (be < bs || be > u) {
         bad = true;
@@ -276,14 +364,13 @@ __global__ void __launch_bounds__(kWave) k_split_write(SplitArgs a, uint32_t S, 
       }
       wave_copy_bytes(buf + min(pos, S), S - min(pos, S), a.src.ptr(f, u), bs, be);
       pos += be - bs;
-      if (last) break;
-      const uint64_t fn = a.ne[a.rank[f] + 1];
-      if (fn >= a.L || (fn == B.leaf && B.p == 0)) break;
-      const uint64_t d = a.head[fn] - a.lastk[f];
+      if (!hop) break;
+      const uint64_t d = In.head - I.lastk;
       const uint32_t len = vlen(d);
       if (lane_id() == 0 && pos + len <= S) vput(buf + pos, d);
       pos += len;
       f = fn;
+      I = In;
       bs = 8;
     }
     __syncthreads();
