@@ -22,6 +22,7 @@
 #include "fgraph.hpp"
 #include "resize.hpp"
 #include "tune.hpp"
+#include "small.hpp"
 
 using namespace cpma_dev;
 
@@ -767,7 +768,9 @@ void rebalance(cpma* s, hipStream_t st) {
   throw Fail{CPMA_ERR_DEVICE};
 }
 
-uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, hipStream_t st) {
+// segments_ready: the small-batch kernel already wrote kprime, the segments and T.
+uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, hipStream_t st,
+                     bool segments_ready = false) {
   ensure(s->leafid, kbound * sizeof(uint32_t));
   ensure(s->seg_leaf, kbound * sizeof(uint32_t));
   ensure(s->seg_begin, (kbound + 1) * sizeof(uint32_t));
@@ -785,7 +788,9 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   ensure(s->stage, stage_cap * sizeof(uint64_t));
   PhaseMark pl = phase_begin(s, CPMA_PHASE_LOCATE, st);
   const uint64_t L = s->L;
-  if (kbound >= L) {
+  if (segments_ready) {
+    // nothing to do: the segments come with the batch
+  } else if (kbound >= L) {
     // per leaf: one search of head[f] in the batch
     ensure(s->leafid, (L + 1) * sizeof(uint32_t));
     ensure(s->segpos, (std::max(kbound, L) + 1) * sizeof(uint32_t));
@@ -875,6 +880,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
     }
   }
   read_counters(s, st);
+  if (s->hctr->reserved) throw Fail{CPMA_ERR_RESERVED_KEY};  // small batch: nothing was merged
   if (s->stats_on) {
     s->stats[CPMA_PHASE_MERGE].alg_bytes += s->hctr->alg_bytes;
     s->stats[CPMA_PHASE_HEAVY].alg_bytes += s->hctr->alg_bytes_h;
@@ -1026,8 +1032,30 @@ static cpma_status update(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem me
   cpma_status r = guarded(s, [&] {
     HIPCHK(hipSetDevice(s->device));
     zero_counters(s, st);
-    const uint64_t* B = prepare_batch(s, keys, k, mem, st);
-    delta = apply_batch(s, B, k, insert, st);
+    if (k <= kSmallBatch) {
+      // one launch prepares the whole batch
+      const uint64_t* src = keys;
+      if (mem == CPMA_MEM_HOST) {
+        ensure(s->kin, k * sizeof(uint64_t));
+        HIPCHK(hipMemcpyAsync(s->kin.p, keys, k * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+        src = s->kin.as<uint64_t>();
+      }
+      ensure(s->kdedup, k * sizeof(uint64_t));
+      ensure(s->seg_leaf, k * sizeof(uint32_t));
+      ensure(s->seg_begin, (k + 1) * sizeof(uint32_t));
+      ensure(s->seg_desc, (k + 1) * sizeof(uint4));
+      PhaseMark pm = phase_begin(s, CPMA_PHASE_SORT, st);
+      hipLaunchKernelGGL(k_small_prep, dim3(1), dim3(kSmallThreads), 0, st, src, (uint32_t)k,
+                         (const uint64_t*)s->head.as<uint64_t>(), s->L, (const uint32_t*)s->used.as<uint32_t>(),
+                         s->kdedup.as<uint64_t>(), s->seg_leaf.as<uint32_t>(), s->seg_begin.as<uint32_t>(),
+                         s->seg_desc.as<uint4>(), s->dctr);
+      HIPCHK(hipGetLastError());
+      phase_end(s, pm, st, 16ull * k);
+      delta = apply_batch(s, s->kdedup.as<uint64_t>(), k, insert, st, true);
+    } else {
+      const uint64_t* B = prepare_batch(s, keys, k, mem, st);
+      delta = apply_batch(s, B, k, insert, st);
+    }
     resolve_phases(s);
   });
   if (r == CPMA_OK && delta_out) *delta_out = delta;

@@ -1,0 +1,137 @@
+// Small batches (at most kSmallBatch keys): one workgroup does the whole batch
+// preparation that large batches spread over some thirty launches -- the
+// reserved-key check, a bitonic sort in LDS, removal of repeats, the leaf of
+// every key (binary search on the heads) and the touched-leaf segments -- so a
+// small update is bound by a handful of launches instead of dozens.
+#pragma once
+#include "update.hpp"
+
+namespace cpma_dev {
+
+constexpr uint32_t kSmallBatch = 4096;
+constexpr uint32_t kSmallThreads = 1024;
+
+// Exclusive scan of one value per thread over the workgroup; returns the
+// thread's offset, *total the sum.
+__device__ __forceinline__ uint32_t block_scan_u32(uint32_t v, uint32_t* wsum, uint32_t* total) {
+  const int lane = lane_id(), wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const uint32_t incl = wave_incl_scan(v);
+  if (lane == kWave - 1) wsum[wid] = incl;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+  for (int w = 0; w < nw; w++) {
+    const uint32_t x = wsum[w];
+    before += w < wid ? x : 0u;
+    all += x;
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - v;
+}
+
+__global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __restrict__ in, uint32_t k,
+                                                              const uint64_t* __restrict__ head, uint64_t L,
+                                                              const uint32_t* __restrict__ used,
+                                                              uint64_t* __restrict__ B, uint32_t* __restrict__ seg_leaf,
+                                                              uint32_t* __restrict__ seg_begin,
+                                                              uint4* __restrict__ seg_desc, Counters* ctr) {
+  __shared__ uint64_t A[kSmallBatch];
+  __shared__ uint32_t LF[kSmallBatch];
+  __shared__ uint32_t wsum[kSmallThreads / kWave];
+  __shared__ uint32_t bad;
+  const uint32_t tid = threadIdx.x;
+  constexpr uint32_t kPer = kSmallBatch / kSmallThreads;
+  uint32_t n = 1;
+  while (n < k) n <<= 1;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (uint32_t i = tid; i < n; i += kSmallThreads) {
+    const uint64_t x = i < k ? in[i] : kNoKey;  // padding sorts last
+    if (i < k && x == kNoKey) bad = 1;
+    A[i] = x;
+  }
+  __syncthreads();
+  if (bad) {
+    if (tid == 0) {
+      ctr->reserved = 1;
+      ctr->kprime = 0;
+      ctr->T = 0;
+      seg_begin[0] = 0;
+    }
+    return;
+  }
+  // bitonic sort of n (a power of two) keys
+  for (uint32_t size = 2; size <= n; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t t = tid; t < n / 2; t += kSmallThreads) {
+        const uint32_t i = 2 * t - (t & (stride - 1));
+        const uint32_t j = i + stride;
+        const uint64_t a = A[i], b = A[j];
+        const bool up = (i & size) == 0;
+        if ((a > b) == up) {
+          A[i] = b;
+          A[j] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // drop repeats: each thread owns kPer consecutive positions
+  const uint32_t i0 = tid * kPer;
+  uint32_t mine = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; q++) {
+    const uint32_t i = i0 + q;
+    mine += (i < k && (i == 0 || A[i] != A[i - 1])) ? 1u : 0u;
+  }
+  uint32_t kp;
+  uint32_t pos = block_scan_u32(mine, wsum, &kp);
+  uint64_t mykeys[kPer];
+  uint32_t mypos[kPer];
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; q++) {
+    const uint32_t i = i0 + q;
+    const bool first = i < k && (i == 0 || A[i] != A[i - 1]);
+    mykeys[q] = first ? A[i] : 0;
+    mypos[q] = first ? pos : ~0u;
+    pos += first ? 1u : 0u;
+  }
+  __syncthreads();
+  // unique keys back to A[0, kp) and to B; their leaves to LF
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; q++) {
+    if (mypos[q] != ~0u) {
+      A[mypos[q]] = mykeys[q];
+      B[mypos[q]] = mykeys[q];
+      LF[mypos[q]] = (uint32_t)locate_leaf(head, L, mykeys[q]);
+    }
+  }
+  __syncthreads();
+  // segments: runs of equal leaf ids
+  uint32_t starts = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; q++) {
+    const uint32_t i = i0 + q;
+    starts += (i < kp && (i == 0 || LF[i] != LF[i - 1])) ? 1u : 0u;
+  }
+  uint32_t T;
+  uint32_t sp = block_scan_u32(starts, wsum, &T);
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; q++) {
+    const uint32_t i = i0 + q;
+    if (i < kp && (i == 0 || LF[i] != LF[i - 1])) {
+      const uint32_t lf = LF[i];
+      seg_leaf[sp] = lf;
+      seg_begin[sp] = i;
+      seg_desc[sp] = make_uint4(lf, i, used[lf], seg_wide(used, head, L, lf, A[i]));
+      sp++;
+    }
+  }
+  if (tid == 0) {
+    seg_begin[T] = kp;
+    ctr->kprime = kp;
+    ctr->T = T;
+  }
+}
+
+}  // namespace cpma_dev

@@ -26,6 +26,7 @@ struct Counters {
   unsigned long long alg_bytes;     // algorithmic HBM bytes of the merge (statistics)
   unsigned long long alg_bytes_q;   // algorithmic HBM bytes of range scans (statistics)
   unsigned long long alg_bytes_h;   // algorithmic HBM bytes of the follow-up merges (statistics)
+  unsigned int reserved;            // a small batch held the reserved key (nothing was changed)
 };
 
 __device__ __forceinline__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t x) {
