@@ -308,6 +308,7 @@ def main():
     ap.add_argument("--fg-only", action="store_true", help="run only the F-Graph section (diagnostics)")
     ap.add_argument("--gate-only", action="store_true", help="run only the cold range gate (diagnostics)")
     ap.add_argument("--range-only", action="store_true", help="run only the batched range_map section (diagnostics)")
+    ap.add_argument("--sweep-only", action="store_true", help="run only the batch-size sweep (diagnostics)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the merge kernel's traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
@@ -386,7 +387,7 @@ def main():
 
     # ---- batch-size sweep: insert k fresh keys, then delete k present keys --------
     per_batch = {}
-    if not args.only_steps:
+    if not args.only_steps or args.sweep_only:
         sizes = [int(float(x)) for x in args.sweep.split(",") if x]
         reps = {10: 30, 100: 30, 1000: 20, 10000: 10, 100000: 5, 1000000: 3}
         total_del = sum(s * reps.get(s, 3) for s in sizes)
@@ -418,6 +419,9 @@ def main():
             log(f"k={s:.0e}: insert {s / ti.mean():.3e}/s delete {s / td.mean():.3e}/s "
                 f"p99 {np.percentile(ti, 99) * 1e3:.2f} ms")
         result_extra["per_batch"] = per_batch
+        if args.sweep_only:
+            print(json.dumps(per_batch), flush=True)
+            return
 
     # ---- headline: W warm-up + K timed insert batches of k keys ------------------
     nb = args.warmup + args.steps

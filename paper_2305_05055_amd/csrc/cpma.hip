@@ -728,13 +728,22 @@ uint64_t resize(cpma* s, uint64_t total, uint32_t viol, hipStream_t st) {
 
 // Counting + redistribution until every node of the implicit tree is within its
 // bounds.
-void rebalance(cpma* s, hipStream_t st) {
+// merged: -1 after a build; 0 / 1 right after a delete / insert merge, whose
+// counters are still on the device: the first count only reads the structure,
+// so one read-back serves both (the merge's errors are checked before anything
+// is redistributed).  Returns the merge's delta.
+uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1) {
+  uint64_t delta = 0;
   for (int round = 0; round < 256; round++) {
+    const bool after_merge = round == 0 && merged >= 0;
     PhaseMark pc = phase_begin(s, CPMA_PHASE_COUNT, st);
     Pyramid P = make_pyramid(s, s->L);
     build_pyramid(s, P, s->used.as<uint32_t>(), s->L, st);
     ensure(s->win, std::max<uint64_t>(s->L, 1) * sizeof(uint64_t));
-    zero_counters(s, st);
+    if (after_merge)
+      hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, &s->dctr->nwin, (uint64_t)1, 0u);
+    else
+      zero_counters(s, st);
     const uint64_t nodes = (P.H == 0) ? 1 : P.off[P.H] + P.cnt[P.H];
     hipLaunchKernelGGL(k_select, dim3(grid_for(nodes, 256, 1u << 16)), dim3(256), 0, st, s->bounds(s->L), P,
                        (const uint32_t*)s->used.as<uint32_t>(), s->win.as<uint64_t>(), s->dctr);
@@ -742,13 +751,25 @@ void rebalance(cpma* s, hipStream_t st) {
     phase_end(s, pc, st, 4ull * s->L + 16ull * nodes);
     read_counters(s, st);
     const Counters c = *s->hctr;
+    if (after_merge) {
+      if (c.reserved) throw Fail{CPMA_ERR_RESERVED_KEY};  // small batch: nothing was merged
+      if (s->stats_on) {
+        s->stats[CPMA_PHASE_MERGE].alg_bytes += c.alg_bytes;
+        s->stats[CPMA_PHASE_HEAVY].alg_bytes += c.alg_bytes_h;
+      }
+      delta = c.delta;
+      if (merged)
+        s->n += delta;
+      else
+        s->n -= delta;
+    }
     if (c.root_viol) {
       PhaseMark pr = phase_begin(s, CPMA_PHASE_REDIST, st);
       const uint64_t moved = resize(s, c.root_sum, c.root_viol, st);
       phase_end(s, pr, st, moved);
       continue;
     }
-    if (c.nwin == 0) return;
+    if (c.nwin == 0) return delta;
     uint64_t* hw = reinterpret_cast<uint64_t*>(host_pin(s, c.nwin * 8ull));
     HIPCHK(hipMemcpyAsync(hw, s->win.p, c.nwin * 8ull, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -768,9 +789,9 @@ void rebalance(cpma* s, hipStream_t st) {
   throw Fail{CPMA_ERR_DEVICE};
 }
 
-// segments_ready: the small-batch kernel already wrote kprime, the segments and T.
-uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, hipStream_t st,
-                     bool segments_ready = false) {
+// small: the small-batch kernel already wrote kprime, the segments, their routing and T.
+uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, hipStream_t st, bool small = false) {
+  const bool segments_ready = small;
   ensure(s->leafid, kbound * sizeof(uint32_t));
   ensure(s->seg_leaf, kbound * sizeof(uint32_t));
   ensure(s->seg_begin, (kbound + 1) * sizeof(uint32_t));
@@ -819,7 +840,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
                        (const uint64_t*)s->head.as<uint64_t>(), L, B, s->dctr);
   }
   HIPCHK(hipGetLastError());
-  if (s->S <= kWaveMaxS) {
+  if (s->S <= kWaveMaxS && !small) {
     // route segments: narrow (32-bit wave merge), wide (64-bit), long insert slices (lane merge)
     const uint64_t nseg = std::min<uint64_t>(kbound, L);
     hipLaunchKernelGGL(k_classify, dim3(grid_for(nseg, 256, (uint32_t)s->num_cus * 8)), dim3(256), 0, st,
@@ -853,7 +874,14 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   // MERGE times exactly the main merge kernel; HEAVY the follow-up kernels for
   // wide, long and heavy slices
   PhaseMark pmg = phase_begin(s, CPMA_PHASE_MERGE, st);
-  if (s->S <= kWaveMaxS) {
+  if (small && s->S <= kWaveMaxS) {
+    // every segment in one 64-bit wave pass; long insert slices in the lane merge
+    const uint32_t wgrid = (uint32_t)std::min<uint64_t>(segs, (uint64_t)s->num_cus * 40);
+    hipLaunchKernelGGL(k_merge_wave<uint64_t>, dim3(std::max(1u, wgrid)), dim3(kWave), 0, st, a, 1);
+    if (insert) hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 1);
+    HIPCHK(hipGetLastError());
+    phase_end(s, pmg, st);
+  } else if (s->S <= kWaveMaxS) {
     const uint32_t wgrid = (uint32_t)std::min<uint64_t>(segs, (uint64_t)s->num_cus * 40);
     hipLaunchKernelGGL(k_merge_wave<uint32_t>, dim3(std::max(1u, wgrid)), dim3(kWave), 0, st, a);
     HIPCHK(hipGetLastError());
@@ -879,19 +907,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
       phase_end(s, ph, st);
     }
   }
-  read_counters(s, st);
-  if (s->hctr->reserved) throw Fail{CPMA_ERR_RESERVED_KEY};  // small batch: nothing was merged
-  if (s->stats_on) {
-    s->stats[CPMA_PHASE_MERGE].alg_bytes += s->hctr->alg_bytes;
-    s->stats[CPMA_PHASE_HEAVY].alg_bytes += s->hctr->alg_bytes_h;
-  }
-  const uint64_t delta = s->hctr->delta;
-  if (insert)
-    s->n += delta;
-  else
-    s->n -= delta;
-  rebalance(s, st);
-  return delta;
+  return rebalance(s, st, insert ? 1 : 0);
 }
 
 cpma_status check_config(const cpma_config& c) {
@@ -1045,10 +1061,12 @@ static cpma_status update(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem me
       ensure(s->seg_begin, (k + 1) * sizeof(uint32_t));
       ensure(s->seg_desc, (k + 1) * sizeof(uint4));
       PhaseMark pm = phase_begin(s, CPMA_PHASE_SORT, st);
+      ensure(s->spill, k * sizeof(uint32_t));
       hipLaunchKernelGGL(k_small_prep, dim3(1), dim3(kSmallThreads), 0, st, src, (uint32_t)k,
                          (const uint64_t*)s->head.as<uint64_t>(), s->L, (const uint32_t*)s->used.as<uint32_t>(),
                          s->kdedup.as<uint64_t>(), s->seg_leaf.as<uint32_t>(), s->seg_begin.as<uint32_t>(),
-                         s->seg_desc.as<uint4>(), s->dctr);
+                         s->seg_desc.as<uint4>(), insert ? 1 : 0, s->S <= kWaveMaxS ? kWaveSlice : 0xffffffffu,
+                         s->spill.as<uint32_t>(), s->dctr);
       HIPCHK(hipGetLastError());
       phase_end(s, pm, st, 16ull * k);
       delta = apply_batch(s, s->kdedup.as<uint64_t>(), k, insert, st, true);

@@ -56,9 +56,11 @@ __device__ __forceinline__ void put_key_bytes(uint8_t* dst, bool head, KT x, KT 
 
 // KT = uint32_t: keys are stored in LDS as offsets from the segment's smallest
 // possible key (segments flagged wide are handed to the 64-bit instance), which
-// halves the dominant LDS array.  KT = uint64_t: processes the handed-over list.
+// halves the dominant LDS array.  KT = uint64_t: processes the handed-over list,
+// or with all_segments every segment not routed to the lane merge (small
+// batches: one launch instead of two).
 template <typename KT>
-__global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
+__global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segments = 0) {
   constexpr bool kNarrow = sizeof(KT) == 4;
   __shared__ KT K[kWaveMaxS];
   __shared__ KT GK[kWaveSlice];            // group g: its last key (new predecessor of old key GR[g])
@@ -69,10 +71,12 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
   __shared__ __align__(16) uint8_t out[kWaveMaxS];
   const int lane = lane_id();
   const uint32_t S = a.S;
-  const uint64_t T = kNarrow ? (uint64_t)a.ctr->T : (uint64_t)a.ctr->nwide;
+  const bool listed = !kNarrow && !all_segments;
+  const uint64_t T = listed ? (uint64_t)a.ctr->nwide : (uint64_t)a.ctr->T;
   const uint32_t pos0 = 16u * lane;
   unsigned long long delta = 0, alg = 0;
-  auto seg_of = [&](uint64_t t) -> uint64_t { return kNarrow ? t : (uint64_t)a.wide_list[t]; };
+  auto seg_of = [&](uint64_t t) -> uint64_t { return listed ? (uint64_t)a.wide_list[t] : t; };
+  auto skip = [&](const uint4& d) { return kNarrow ? d.w != 0 : (all_segments && d.w == 2); };
   // Software pipeline: the next segment's descriptor, leaf bytes and batch keys
   // are loaded while the current one is merged.
   uint4 d_cur = make_uint4(0, 0, 0, 0), d_nxt = d_cur;
@@ -85,7 +89,7 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
     s_cur = seg_of(t);
     d_cur = a.seg_desc[s_cur];
     e_cur = a.seg_begin[s_cur + 1];
-    if (!(kNarrow && d_cur.w)) {
+    if (!skip(d_cur)) {
       if (pos0 < d_cur.z) w_cur = *reinterpret_cast<const uint4*>(a.bytes + (uint64_t)d_cur.x * S + pos0);
       if ((uint32_t)lane < e_cur - d_cur.y) b_cur = a.B[d_cur.y + lane];
     }
@@ -102,13 +106,13 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
     const uint32_t b = d_cur.y, e = e_cur;
     const uint32_t nb = e - b;
     const uint32_t used0 = d_cur.z;
-    const bool wide = kNarrow && d_cur.w;
+    const bool wide = skip(d_cur);
     const uint4 w = w_cur;
     const uint64_t bj0 = b_cur;
     if (tn < T) {
       w_nxt = make_uint4(0, 0, 0, 0);
       b_nxt = 0;
-      if (!(kNarrow && d_nxt.w)) {
+      if (!skip(d_nxt)) {
         if (pos0 < d_nxt.z) w_nxt = *reinterpret_cast<const uint4*>(a.bytes + (uint64_t)d_nxt.x * S + pos0);
         if ((uint32_t)lane < e_nxt - d_nxt.y) b_nxt = a.B[d_nxt.y + lane];
       }
@@ -118,7 +122,7 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a) {
     e_cur = e_nxt;
     w_cur = w_nxt;
     b_cur = b_nxt;
-    if (wide) continue;  // routed by k_classify to the wide or spill list
+    if (wide) continue;  // routed to the wide or spill list
     // smallest possible key of the segment: the old head or the first slice key
     uint64_t base = 0;
     if (kNarrow) {

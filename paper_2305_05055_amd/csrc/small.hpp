@@ -1,8 +1,9 @@
 // Small batches (at most kSmallBatch keys): one workgroup does the whole batch
 // preparation that large batches spread over some thirty launches -- the
 // reserved-key check, a bitonic sort in LDS, removal of repeats, the leaf of
-// every key (binary search on the heads) and the touched-leaf segments -- so a
-// small update is bound by a handful of launches instead of dozens.
+// every key (binary search on the heads), the touched-leaf segments and their
+// routing -- so a small update is bound by a handful of launches instead of
+// dozens.
 #pragma once
 #include "update.hpp"
 
@@ -29,14 +30,19 @@ __device__ __forceinline__ uint32_t block_scan_u32(uint32_t v, uint32_t* wsum, u
   return before + incl - v;
 }
 
+// Also routes the segments: an insert slice longer than `slice` keys goes to the
+// lane merge (desc.w = 2, spill list); every other segment is merged by the
+// 64-bit wave instance (desc.w = 0).
 __global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __restrict__ in, uint32_t k,
                                                               const uint64_t* __restrict__ head, uint64_t L,
                                                               const uint32_t* __restrict__ used,
                                                               uint64_t* __restrict__ B, uint32_t* __restrict__ seg_leaf,
                                                               uint32_t* __restrict__ seg_begin,
-                                                              uint4* __restrict__ seg_desc, Counters* ctr) {
+                                                              uint4* __restrict__ seg_desc, int is_insert,
+                                                              uint32_t slice, uint32_t* __restrict__ spill_list,
+                                                              Counters* ctr) {
   __shared__ uint64_t A[kSmallBatch];
-  __shared__ uint32_t LF[kSmallBatch];
+  __shared__ uint32_t LF[kSmallBatch];  // leaf of each key, then segment starts
   __shared__ uint32_t wsum[kSmallThreads / kWave];
   __shared__ uint32_t bad;
   const uint32_t tid = threadIdx.x;
@@ -116,21 +122,46 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __
   }
   uint32_t T;
   uint32_t sp = block_scan_u32(starts, wsum, &T);
+  uint32_t segl[kPer], segi[kPer];
 #pragma unroll
   for (uint32_t q = 0; q < kPer; q++) {
     const uint32_t i = i0 + q;
-    if (i < kp && (i == 0 || LF[i] != LF[i - 1])) {
-      const uint32_t lf = LF[i];
-      seg_leaf[sp] = lf;
-      seg_begin[sp] = i;
-      seg_desc[sp] = make_uint4(lf, i, used[lf], seg_wide(used, head, L, lf, A[i]));
-      sp++;
-    }
+    const bool st = i < kp && (i == 0 || LF[i] != LF[i - 1]);
+    segl[q] = st ? LF[i] : ~0u;
+    segi[q] = st ? sp : ~0u;
+    sp += st ? 1u : 0u;
+  }
+  __syncthreads();
+  // segment starts into LF[0, T]
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; q++)
+    if (segi[q] != ~0u) LF[segi[q]] = i0 + q;
+  if (tid == 0) LF[T] = kp;
+  __syncthreads();
+  uint32_t nsp = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; q++) {
+    if (segi[q] == ~0u) continue;
+    const uint32_t s = segi[q], b = LF[s], lf = segl[q];
+    const bool spill = is_insert && LF[s + 1] - b > slice;
+    seg_leaf[s] = lf;
+    seg_begin[s] = b;
+    seg_desc[s] = make_uint4(lf, b, used[lf], spill ? 2u : 0u);
+    nsp += spill ? 1u : 0u;
+  }
+  uint32_t nspill;
+  uint32_t pos2 = block_scan_u32(nsp, wsum, &nspill);
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; q++) {
+    if (segi[q] == ~0u) continue;
+    const uint32_t s = segi[q];
+    if (is_insert && LF[s + 1] - LF[s] > slice) spill_list[pos2++] = s;
   }
   if (tid == 0) {
     seg_begin[T] = kp;
     ctr->kprime = kp;
     ctr->T = T;
+    ctr->nspill = nspill;
   }
 }
 
