@@ -307,6 +307,7 @@ def main():
                     help="first copy 1 GiB device to device (reference dispatch for HBM byte counters)")
     ap.add_argument("--fg-only", action="store_true", help="run only the F-Graph section (diagnostics)")
     ap.add_argument("--gate-only", action="store_true", help="run only the cold range gate (diagnostics)")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving loop (diagnostics)")
     ap.add_argument("--range-only", action="store_true", help="run only the batched range_map section (diagnostics)")
     ap.add_argument("--sweep-only", action="store_true", help="run only the batch-size sweep (diagnostics)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -354,6 +355,14 @@ def main():
         del big_d
         torch.cuda.empty_cache()
         print(json.dumps(gate_section(cp, torch, big, int(args.serve_n), seed + 80)), flush=True)
+        return
+    if args.serve_only:
+        big_d = synth.uniform_keys_torch(int(args.serve_n), seed + 70, "cuda")
+        big = cp.CPMA(big_d)
+        big_host = big_d.cpu().numpy().view(np.uint64)
+        del big_d
+        torch.cuda.empty_cache()
+        print(json.dumps(serving_section(cp, torch, big, big_host, args.serve_requests, seed + 90)), flush=True)
         return
 
     # ---- base set: exactly n0 distinct uniform 40-bit keys -----------------------

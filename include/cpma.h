@@ -242,10 +242,10 @@ cpma_status cpma_fgraph_pagerank(const cpma* set, uint32_t nv, int iters, double
  * flight; the admitted requests form one step.  A step runs every range
  * request it holds as one batched cpma_range_map launch against the state left
  * by the previous steps, then applies its insert / delete requests in arrival
- * order (the paper phases updates and queries with a single writer, Section
- * "Evaluation on graph workloads").  Each request's result therefore equals
- * replaying all requests in (step, queries first, updates in arrival order)
- * order one call each.
+ * order with one cpma_apply_updates call (the paper phases updates and queries
+ * with a single writer, Section "Evaluation on graph workloads").  Each
+ * request's result therefore equals replaying all requests in (step, queries
+ * first, updates in arrival order) order one call each.
  *
  * All request buffers are host memory and must stay valid until the request
  * is done.  `done` becomes nonzero (release store) when the outputs are
@@ -268,6 +268,29 @@ typedef struct {
   uint64_t t_done_ns;
   uint64_t step;
 } cpma_request;
+
+/*
+ * Applies nreq insert / delete requests with the result of calling
+ * cpma_insert_batch / cpma_delete_batch once per request in order (batch
+ * updates of Section "Parallel Batch Updates in a PMA", phased by one writer as
+ * in Section "Evaluation on graph workloads"), but with one sort of all their
+ * keys and at most one delete batch and one insert batch of net changes.
+ * The final set is the same; its leaf layout may differ from the one-call-per-
+ * request layout (the paper fixes the set, not the placement).
+ *
+ * kind: nreq host entries, CPMA_REQ_INSERT or CPMA_REQ_DELETE.
+ * keys, n: nreq host entries; request r's keys are keys[r][0 .. n[r]) in
+ *   memory space `mem` (any order, repeats allowed; keys[r] may be NULL when
+ *   n[r] == 0).  The total of n must be below 2^31.
+ * result: nreq host words; result[r] = keys request r added (insert) or
+ *   removed (delete), counted against the state its own call would have seen.
+ * Errors: CPMA_ERR_INVALID for a bad kind, NULL pointer or total, nothing
+ * changed; CPMA_ERR_RESERVED_KEY if any key is UINT64_MAX, nothing changed;
+ * CPMA_ERR_DEVICE if the device failed (the set is then unusable).
+ * Synchronises `stream`.
+ */
+cpma_status cpma_apply_updates(cpma* set, uint32_t nreq, const int32_t* kind, const uint64_t* const* keys,
+                               const uint64_t* n, cpma_mem mem, uint64_t* result, void* stream);
 
 typedef struct {
   uint64_t hbm_budget;   /* bytes of in-flight request data; 0 = 16 GiB */

@@ -86,6 +86,7 @@ def lib():
         L.cpma_insert_batch.argtypes = [vp, vp, u64, ctypes.c_int, ctypes.c_int, vp,
                                         ctypes.POINTER(u64)]
         L.cpma_delete_batch.argtypes = L.cpma_insert_batch.argtypes
+        L.cpma_apply_updates.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, ctypes.c_int, vp, vp]
         L.cpma_contains.argtypes = [vp, vp, u64, ctypes.c_int, vp, vp]
         L.cpma_range_map.argtypes = [vp, vp, vp, u64, ctypes.c_int, vp, vp, vp]
         L.cpma_size.argtypes = [vp]
@@ -219,6 +220,32 @@ class CPMA:
     def delete_batch(self, keys, sorted=False, stream=None):
         """Deletes keys; returns how many were present."""
         return self._update(lib().cpma_delete_batch, keys, sorted, stream, "cpma_delete_batch")
+
+    def apply_updates(self, requests, stream=None):
+        """Applies [(kind, keys), ...] (kind REQ_INSERT or REQ_DELETE; keys host
+        arrays or device tensors, all in one memory space) as if one
+        insert_batch / delete_batch call ran per request in order, with one
+        fused pass; returns each request's count."""
+        nreq = len(requests)
+        kinds = np.array([int(k) for k, _ in requests], dtype=np.int32)
+        ptrs = np.zeros(nreq, dtype=np.uint64)
+        ns = np.zeros(nreq, dtype=np.uint64)
+        keep, mem = [], MEM_HOST
+        for i, (_, ks) in enumerate(requests):
+            p, k, m, kp = _keys(ks)
+            if i == 0:
+                mem = m
+            elif m != mem:
+                raise ValueError("all requests' keys must be in one memory space")
+            keep.append(kp)
+            ptrs[i] = p.value if (k and p is not None and p.value) else 0
+            ns[i] = k
+        res = np.zeros(nreq, dtype=np.uint64)
+        _check(lib().cpma_apply_updates(self._h, nreq, ctypes.c_void_p(kinds.ctypes.data),
+                                        ctypes.c_void_p(ptrs.ctypes.data), ctypes.c_void_p(ns.ctypes.data),
+                                        mem, ctypes.c_void_p(res.ctypes.data),
+                                        _stream(stream, mem == MEM_DEVICE)), "cpma_apply_updates")
+        return [int(x) for x in res]
 
     def contains(self, keys, stream=None):
         p, q, mem, keep = _keys(keys)

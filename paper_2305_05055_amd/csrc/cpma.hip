@@ -23,6 +23,7 @@
 #include "resize.hpp"
 #include "tune.hpp"
 #include "small.hpp"
+#include "fuse.hpp"
 
 using namespace cpma_dev;
 
@@ -102,7 +103,7 @@ struct cpma {
       stage, pyr, win, wargs, cnt, koff, win_id, welem, P, ccost, ncost, lstart, planU, plan_used,
       spare_bytes, spare_used, spare_head, fg_level, fg_deg, fg_p, fg_c, fg_acc,
       win_of_leaf, fail, qa, qb, qfirst, qnvis, qvoff, qsum, qcount, qout, lastk, ne_rank, ne_list, chain_pfx,
-      srec, wide, srcinfo;
+      srec, wide, srcinfo, fz_meta, fz_v0, fz_v1, fz_byte, fz_member, fz_code, fz_ctr, fz_res;
   Counters* dctr = nullptr;
   Counters* hctr = nullptr;
   BatchInfo* dinfo = nullptr;
@@ -910,6 +911,36 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   return rebalance(s, st, insert ? 1 : 0);
 }
 
+// Batch of k <= kSmallBatch keys at device address src (any order, repeats
+// allowed): one launch prepares it (sort, repeats, leaves, segments), then the
+// merge and rebalance phases run.  Counters must be zero.
+uint64_t apply_small(cpma* s, const uint64_t* src, uint64_t k, bool insert, hipStream_t st) {
+  ensure(s->kdedup, k * sizeof(uint64_t));
+  ensure(s->seg_leaf, k * sizeof(uint32_t));
+  ensure(s->seg_begin, (k + 1) * sizeof(uint32_t));
+  ensure(s->seg_desc, (k + 1) * sizeof(uint4));
+  ensure(s->spill, k * sizeof(uint32_t));
+  PhaseMark pm = phase_begin(s, CPMA_PHASE_SORT, st);
+  hipLaunchKernelGGL(k_small_prep, dim3(1), dim3(kSmallThreads), 0, st, src, (uint32_t)k,
+                     (const uint64_t*)s->head.as<uint64_t>(), s->L, (const uint32_t*)s->used.as<uint32_t>(),
+                     s->kdedup.as<uint64_t>(), s->seg_leaf.as<uint32_t>(), s->seg_begin.as<uint32_t>(),
+                     s->seg_desc.as<uint4>(), insert ? 1 : 0, s->S <= kWaveMaxS ? kWaveSlice : 0xffffffffu,
+                     s->spill.as<uint32_t>(), s->dctr);
+  HIPCHK(hipGetLastError());
+  phase_end(s, pm, st, 16ull * k);
+  return apply_batch(s, s->kdedup.as<uint64_t>(), k, insert, st, true);
+}
+
+// Sorted repeat-free batch of k keys at device address B.  Zeroes the counters.
+uint64_t apply_sorted(cpma* s, const uint64_t* B, uint64_t k, bool insert, hipStream_t st) {
+  zero_counters(s, st);
+  if (k <= kSmallBatch) return apply_small(s, B, k, insert, st);
+  hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(64), 0, st, &s->dctr->kprime, (uint64_t)1,
+                     (unsigned long long)k);
+  HIPCHK(hipGetLastError());
+  return apply_batch(s, B, k, insert, st);
+}
+
 cpma_status check_config(const cpma_config& c) {
   if (c.leaf_bytes < 64 || c.leaf_bytes > 4096 || (c.leaf_bytes & (c.leaf_bytes - 1))) return CPMA_ERR_INVALID;
   if (c.range_chunk < 1 || c.range_chunk > 64 || (c.range_chunk & (c.range_chunk - 1))) return CPMA_ERR_INVALID;
@@ -1049,27 +1080,13 @@ static cpma_status update(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem me
     HIPCHK(hipSetDevice(s->device));
     zero_counters(s, st);
     if (k <= kSmallBatch) {
-      // one launch prepares the whole batch
       const uint64_t* src = keys;
       if (mem == CPMA_MEM_HOST) {
         ensure(s->kin, k * sizeof(uint64_t));
         HIPCHK(hipMemcpyAsync(s->kin.p, keys, k * sizeof(uint64_t), hipMemcpyHostToDevice, st));
         src = s->kin.as<uint64_t>();
       }
-      ensure(s->kdedup, k * sizeof(uint64_t));
-      ensure(s->seg_leaf, k * sizeof(uint32_t));
-      ensure(s->seg_begin, (k + 1) * sizeof(uint32_t));
-      ensure(s->seg_desc, (k + 1) * sizeof(uint4));
-      PhaseMark pm = phase_begin(s, CPMA_PHASE_SORT, st);
-      ensure(s->spill, k * sizeof(uint32_t));
-      hipLaunchKernelGGL(k_small_prep, dim3(1), dim3(kSmallThreads), 0, st, src, (uint32_t)k,
-                         (const uint64_t*)s->head.as<uint64_t>(), s->L, (const uint32_t*)s->used.as<uint32_t>(),
-                         s->kdedup.as<uint64_t>(), s->seg_leaf.as<uint32_t>(), s->seg_begin.as<uint32_t>(),
-                         s->seg_desc.as<uint4>(), insert ? 1 : 0, s->S <= kWaveMaxS ? kWaveSlice : 0xffffffffu,
-                         s->spill.as<uint32_t>(), s->dctr);
-      HIPCHK(hipGetLastError());
-      phase_end(s, pm, st, 16ull * k);
-      delta = apply_batch(s, s->kdedup.as<uint64_t>(), k, insert, st, true);
+      delta = apply_small(s, src, k, insert, st);
     } else {
       const uint64_t* B = prepare_batch(s, keys, k, mem, st);
       delta = apply_batch(s, B, k, insert, st);
@@ -1088,6 +1105,190 @@ cpma_status cpma_insert_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
 cpma_status cpma_delete_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem mem, int sorted, void* stream,
                               uint64_t* n_removed) {
   return update(s, keys, k, mem, sorted, stream, n_removed, false);
+}
+
+static QueryArgs query_args(const cpma* s);
+
+cpma_status cpma_apply_updates(cpma* s, uint32_t nreq, const int32_t* kind, const uint64_t* const* keys,
+                               const uint64_t* n, cpma_mem mem, uint64_t* result, void* stream) {
+  if (!s || (nreq && (!kind || !keys || !n || !result))) return CPMA_ERR_INVALID;
+  if (s->broken) return CPMA_ERR_DEVICE;
+  uint64_t m = 0;
+  for (uint32_t r = 0; r < nreq; r++) {
+    if (kind[r] != CPMA_REQ_INSERT && kind[r] != CPMA_REQ_DELETE) return CPMA_ERR_INVALID;
+    if (n[r] && !keys[r]) return CPMA_ERR_INVALID;
+    m += n[r];
+    if (m >= (1ull << 31)) return CPMA_ERR_INVALID;
+  }
+  for (uint32_t r = 0; r < nreq; r++) result[r] = 0;
+  if (m == 0) return CPMA_OK;
+  hipStream_t st = (hipStream_t)stream;
+  return guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    // pinned staging: request table (off: nreq + 1 words, then a delete flag
+    // per request), the counts read back, then either the gather table
+    // (device requests) or the small host requests packed back to back
+    const size_t meta = 8ull * (nreq + 1) + nreq;
+    const size_t res_at = (meta + 63) & ~size_t(63);
+    const size_t tab_at = (res_at + 8ull * (nreq + 3) + 63) & ~size_t(63);
+    constexpr uint64_t kDirect = 1u << 15;  // host requests of at least this many keys copy directly
+    uint64_t small = 0;
+    if (mem == CPMA_MEM_HOST) {
+      for (uint32_t r = 0; r < nreq; r++)
+        if (n[r] < kDirect) small += n[r];
+    }
+    const size_t tab_bytes = mem == CPMA_MEM_HOST ? 8 * small : sizeof(GatherReq) * (size_t)nreq;
+    uint8_t* hp = (uint8_t*)host_pin(s, tab_at + tab_bytes + 64);
+    uint64_t* hoff = reinterpret_cast<uint64_t*>(hp);
+    hoff[0] = 0;
+    for (uint32_t r = 0; r < nreq; r++) {
+      hoff[r + 1] = hoff[r] + n[r];
+      hp[8ull * (nreq + 1) + r] = kind[r] == CPMA_REQ_DELETE ? 1 : 0;
+    }
+    ensure(s->fz_meta, meta);
+    HIPCHK(hipMemcpyAsync(s->fz_meta.p, hp, meta, hipMemcpyHostToDevice, st));
+    ensure(s->kin, m * sizeof(uint64_t));
+    uint64_t* dkeys = s->kin.as<uint64_t>();
+    if (mem == CPMA_MEM_HOST) {
+      // large requests straight from their buffers; runs of small ones packed
+      // in the staging buffer, one copy per run
+      uint64_t* stage = reinterpret_cast<uint64_t*>(hp + tab_at);
+      uint64_t sp = 0, run_sp = 0, run_dst = 0, run_n = 0;
+      for (uint32_t r = 0; r <= nreq; r++) {
+        const bool direct = r < nreq && n[r] >= kDirect;
+        if ((r == nreq || direct) && run_n) {
+          HIPCHK(hipMemcpyAsync(dkeys + run_dst, stage + run_sp, 8 * run_n, hipMemcpyHostToDevice, st));
+          run_n = 0;
+        }
+        if (r == nreq) break;
+        if (direct) {
+          HIPCHK(hipMemcpyAsync(dkeys + hoff[r], keys[r], 8 * n[r], hipMemcpyHostToDevice, st));
+        } else if (n[r]) {
+          if (!run_n) {
+            run_sp = sp;
+            run_dst = hoff[r];
+          }
+          std::memcpy(stage + sp, keys[r], 8 * n[r]);
+          sp += n[r];
+          run_n += n[r];
+        }
+      }
+    } else {
+      GatherReq* tab = reinterpret_cast<GatherReq*>(hp + tab_at);
+      for (uint32_t r = 0; r < nreq; r++) tab[r] = GatherReq{keys[r], hoff[r], n[r]};
+      ensure(s->fz_res, std::max<size_t>(8ull * nreq, sizeof(GatherReq) * (size_t)nreq));
+      HIPCHK(hipMemcpyAsync(s->fz_res.p, tab, sizeof(GatherReq) * nreq, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_fuse_gather, dim3(std::min<uint32_t>(nreq, 65535u)), dim3(256), 0, st,
+                         (const GatherReq*)s->fz_res.as<GatherReq>(), nreq, dkeys);
+      HIPCHK(hipGetLastError());
+    }
+    const uint64_t* doff = s->fz_meta.as<uint64_t>();
+    const uint8_t* drdel = s->fz_meta.as<uint8_t>() + 8ull * (nreq + 1);
+    const uint64_t* src = dkeys;
+    // validation before anything changes
+    hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(s->dinfo),
+                       (uint64_t)(sizeof(BatchInfo) / 4), 0u);
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(m, 256, 4096)), dim3(256), 0, st, src, m, s->dinfo);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(s->hinfo, s->dinfo, sizeof(BatchInfo), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (s->hinfo->has_reserved) throw Fail{CPMA_ERR_RESERVED_KEY};
+
+    // stable key-value sort; values carry position and kind
+    ensure(s->fz_byte, m);
+    hipLaunchKernelGGL(k_fuse_kinds, dim3(std::min<uint32_t>(nreq, 65535u)), dim3(256), 0, st, doff, drdel, nreq,
+                       s->fz_byte.as<uint8_t>());
+    HIPCHK(hipGetLastError());
+    const int bits = 64 - __builtin_clzll(s->hinfo->or_all | 1);
+    const int passes = (bits + 7) / 8;
+    ensure(s->kb0, (m + 1) * sizeof(uint64_t));
+    ensure(s->kb1, m * sizeof(uint64_t));
+    ensure(s->fz_v0, m * sizeof(uint32_t));
+    ensure(s->fz_v1, m * sizeof(uint32_t));
+    const uint32_t nblk = (uint32_t)((m + kSortTile - 1) / kSortTile);
+    ensure(s->cnt, ((uint64_t)nblk * 256 + 1) * sizeof(uint32_t));
+    ensure(s->koff, ((uint64_t)nblk * 256 + 1) * sizeof(uint32_t));
+    const uint64_t* kin = src;
+    const uint32_t* vin = nullptr;
+    for (int p = 0; p < passes; p++) {
+      uint64_t* kout = (p & 1) ? s->kb1.as<uint64_t>() : s->kb0.as<uint64_t>();
+      uint32_t* vout = (p & 1) ? s->fz_v1.as<uint32_t>() : s->fz_v0.as<uint32_t>();
+      hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, st, kin, (uint32_t)m, 8 * p,
+                         s->cnt.as<uint32_t>());
+      HIPCHK(hipGetLastError());
+      scan<uint32_t>(s, s->koff.as<uint32_t>(), (uint64_t)nblk * 256, st, LoadFn<uint32_t>{s->cnt.as<uint32_t>()});
+      hipLaunchKernelGGL(k_radix_scatter_kv, dim3(nblk), dim3(kSortThreads), 0, st, kin, kout, (uint32_t)m, 8 * p,
+                         (const uint32_t*)s->koff.as<uint32_t>(), vin, (const uint8_t*)s->fz_byte.as<uint8_t>(),
+                         vout);
+      HIPCHK(hipGetLastError());
+      kin = kout;
+      vin = vout;
+    }
+    const uint64_t* skeys = kin;
+    const uint32_t* svals = vin;
+
+    // distinct keys, their membership, per-item credits and net changes
+    ensure(s->segpos, (m + 1) * sizeof(uint32_t));
+    ensure(s->kdedup, m * sizeof(uint64_t));
+    ensure(s->fz_ctr, 64);
+    ensure(s->fz_member, m);
+    ensure(s->fz_code, m);
+    unsigned long long* fctr = s->fz_ctr.as<unsigned long long>();
+    scan<uint32_t>(s, s->segpos.as<uint32_t>(), m, st, FirstFlag{skeys});
+    hipLaunchKernelGGL(k_compact_unique, dim3(grid_for(m, 256)), dim3(256), 0, st, skeys, m,
+                       (const uint32_t*)s->segpos.as<uint32_t>(), s->kdedup.as<uint64_t>(), fctr);
+    QueryArgs qa = query_args(s);
+    if (m >= s->L / 8) {
+      // most leaves hold batch keys: decode each such leaf once
+      ensure(s->leafid, (s->L + 1) * sizeof(uint32_t));
+      hipLaunchKernelGGL(k_leaf_slices, dim3(grid_for(s->L + 1, 256, 1u << 16)), dim3(256), 0, st,
+                         (const uint64_t*)s->kdedup.as<uint64_t>(), (const unsigned long long*)fctr,
+                         (const uint64_t*)s->head.as<uint64_t>(), s->L, s->leafid.as<uint32_t>());
+      hipLaunchKernelGGL(k_fuse_member_leaf, dim3((uint32_t)std::min<uint64_t>(s->L, (uint64_t)s->num_cus * 32)),
+                         dim3(kWave), 8ull * s->S, st, qa, (const uint64_t*)s->kdedup.as<uint64_t>(),
+                         (const uint32_t*)s->leafid.as<uint32_t>(), s->fz_member.as<uint8_t>());
+    } else {
+      hipLaunchKernelGGL(k_fuse_member, dim3(grid_for(m, 256, (uint32_t)s->num_cus * 16)), dim3(256), 0, st, qa,
+                         (const uint64_t*)s->kdedup.as<uint64_t>(), (const unsigned long long*)fctr,
+                         s->fz_member.as<uint8_t>());
+    }
+    hipLaunchKernelGGL(k_fuse_credit, dim3(grid_for(m, 256)), dim3(256), 0, st, skeys, svals, m,
+                       (const uint32_t*)s->segpos.as<uint32_t>(), (const uint8_t*)s->fz_member.as<uint8_t>(),
+                       s->fz_byte.as<uint8_t>(), s->fz_code.as<uint8_t>());
+    HIPCHK(hipGetLastError());
+    // net batches: inserts into kb1, deletes into kin (both free once sorted);
+    // packed positions in kb0
+    ensure(s->kin, m * sizeof(uint64_t));
+    uint64_t* dpos = s->kb0.as<uint64_t>();
+    uint64_t* dins = s->kb1.as<uint64_t>();
+    uint64_t* ddel = s->kin.as<uint64_t>();
+    scan<uint64_t>(s, dpos, m, st, FuseSplitFn{s->fz_code.as<uint8_t>(), fctr});
+    hipLaunchKernelGGL(k_fuse_split, dim3(grid_for(m, 256)), dim3(256), 0, st,
+                       (const uint64_t*)s->kdedup.as<uint64_t>(), (const uint8_t*)s->fz_code.as<uint8_t>(),
+                       (const uint64_t*)dpos, dins, ddel, fctr);
+    // per-request counts
+    ensure(s->fz_res, 8ull * nreq);
+    unsigned long long* dres = s->fz_res.as<unsigned long long>();
+    hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(grid_for(nreq, 256)), dim3(256), 0, st, dres,
+                       (uint64_t)nreq, 0ull);
+    hipLaunchKernelGGL(k_fuse_reduce, dim3(grid_for((m + 1023) / 1024, 4, (uint32_t)s->num_cus * 16)), dim3(256),
+                       0, st, (const uint8_t*)s->fz_byte.as<uint8_t>(), m, doff, nreq, dres);
+    HIPCHK(hipGetLastError());
+    uint64_t* hres = reinterpret_cast<uint64_t*>(hp + res_at);
+    HIPCHK(hipMemcpyAsync(hres, dres, 8ull * nreq, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hres + nreq, fctr, 24, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const uint64_t nins = hres[nreq + 1], ndel = hres[nreq + 2];
+    std::vector<uint64_t> counts(hres, hres + nreq);  // the pinned staging may move below
+    uint64_t net = 0;
+    for (uint32_t r = 0; r < nreq; r++) net += kind[r] == CPMA_REQ_INSERT ? counts[r] : (0 - counts[r]);
+    if (net != nins - ndel) throw Fail{CPMA_ERR_DEVICE};  // credits disagree with the net batches
+    // deletes first (they only free room), then inserts
+    if (ndel && apply_sorted(s, ddel, ndel, false, st) != ndel) throw Fail{CPMA_ERR_DEVICE};
+    if (nins && apply_sorted(s, dins, nins, true, st) != nins) throw Fail{CPMA_ERR_DEVICE};
+    std::copy(counts.begin(), counts.end(), result);
+    resolve_phases(s);
+  });
 }
 
 static QueryArgs query_args(const cpma* s) {
@@ -1353,7 +1554,8 @@ void cpma_destroy(cpma* s) {
                     &s->fg_level, &s->fg_deg, &s->fg_p, &s->fg_c, &s->fg_acc, &s->lstart, &s->planU,
                     &s->plan_used, &s->win_of_leaf, &s->fail, &s->qa,        &s->qb,    &s->qfirst, &s->qnvis,
                     &s->qvoff,  &s->qsum,     &s->qcount,    &s->qout,  &s->lastk, &s->ne_rank, &s->ne_list,
-                    &s->chain_pfx, &s->srec, &s->wide, &s->srcinfo};
+                    &s->chain_pfx, &s->srec, &s->wide, &s->srcinfo, &s->fz_meta, &s->fz_v0, &s->fz_v1,
+                    &s->fz_byte, &s->fz_member, &s->fz_code, &s->fz_ctr, &s->fz_res};
   for (DevBuf* b : bufs) release(*b);
   if (s->dctr) hipFree(s->dctr);
   if (s->dinfo) hipFree(s->dinfo);

@@ -4,7 +4,8 @@
 // order; each step admits the longest prefix of the queue that fits the slot
 // cap and the in-flight HBM budget, runs all admitted range requests as one
 // batched range_map launch (they see the state left by earlier steps), then
-// applies the admitted inserts and deletes in arrival order.  Updates and
+// applies the admitted inserts and deletes in arrival order with one fused
+// call (one sort of all their keys, net delete and insert batches).  Updates and
 // queries are thereby phased as in the paper's F-Graph (a single writer, no
 // locks on the structure).
 #include <atomic>
@@ -28,6 +29,9 @@ struct cpma_server {
   uint64_t steps = 0;
   std::thread worker;
   std::vector<uint64_t> lo, hi, sum, cnt;  // fused range batch (host)
+  std::vector<const uint64_t*> ukeys;  // fused update batch (host)
+  std::vector<uint64_t> un, ures;
+  std::vector<int32_t> ukind;
 };
 
 extern "C" uint64_t cpma_clock_ns(void) {
@@ -39,10 +43,14 @@ extern "C" uint64_t cpma_clock_ns(void) {
 namespace {
 
 // Device bytes a request occupies while in flight: its inputs and outputs plus
-// the per-key scratch of an update (sorted copy, leaf ids, segments).
+// the per-key scratch of the fused update (key copies, sort buffers with
+// positions, per-key flags, leaf segments, overflow room).
 uint64_t footprint(const cpma_request* r) {
-  return r->kind == CPMA_REQ_RANGE ? 48ull * r->n + 64 : 40ull * r->n + 64;
+  return r->kind == CPMA_REQ_RANGE ? 48ull * r->n + 64 : 128ull * r->n + 64;
 }
+
+// Keys one fused update call takes (positions are 31-bit).
+constexpr uint64_t kMaxStepUpdateKeys = (1ull << 31) - 1;
 
 void finish(cpma_request* r, cpma_status st, uint64_t step) {
   r->status = (int32_t)st;
@@ -87,16 +95,25 @@ void run_step(cpma_server* s, const std::vector<cpma_request*>& step) {
     for (cpma_request* r : step)
       if (r->kind == CPMA_REQ_RANGE) finish(r, CPMA_OK, id);
   }
-  // 2. updates in arrival order
+  // 2. updates in arrival order, as one fused call
+  s->ukeys.clear();
+  s->un.clear();
+  s->ukind.clear();
+  std::vector<cpma_request*> ups;
   for (cpma_request* r : step) {
-    cpma_status st = CPMA_OK;
-    if (r->kind == CPMA_REQ_INSERT)
-      st = cpma_insert_batch(s->set, r->keys, r->n, CPMA_MEM_HOST, 0, nullptr, &r->result);
-    else if (r->kind == CPMA_REQ_DELETE)
-      st = cpma_delete_batch(s->set, r->keys, r->n, CPMA_MEM_HOST, 0, nullptr, &r->result);
-    else
-      continue;
-    finish(r, st, id);
+    if (r->kind == CPMA_REQ_RANGE) continue;
+    ups.push_back(r);
+    s->ukeys.push_back(r->keys);
+    s->un.push_back(r->n);
+    s->ukind.push_back(r->kind);
+  }
+  if (ups.empty()) return;
+  s->ures.assign(ups.size(), 0);
+  const cpma_status st = cpma_apply_updates(s->set, (uint32_t)ups.size(), s->ukind.data(), s->ukeys.data(),
+                                            s->un.data(), CPMA_MEM_HOST, s->ures.data(), nullptr);
+  for (size_t i = 0; i < ups.size(); i++) {
+    ups[i]->result = st == CPMA_OK ? s->ures[i] : 0;
+    finish(ups[i], st, id);
   }
 }
 
@@ -107,12 +124,14 @@ void work(cpma_server* s) {
       std::unique_lock<std::mutex> lk(s->m);
       s->cv.wait(lk, [&] { return s->stopping || !s->q.empty(); });
       if (s->q.empty()) return;  // stopping and drained
-      uint64_t bytes = 0;
+      uint64_t bytes = 0, ukeys = 0;
       while (!s->q.empty() && step.size() < s->slots) {
         cpma_request* r = s->q.front();
         const uint64_t f = footprint(r);
-        if (!step.empty() && bytes + f > s->budget) break;
+        const uint64_t u = r->kind == CPMA_REQ_RANGE ? 0 : r->n;
+        if (!step.empty() && (bytes + f > s->budget || ukeys + u > kMaxStepUpdateKeys)) break;
         bytes += f;
+        ukeys += u;
         step.push_back(r);
         s->q.pop_front();
       }

@@ -76,17 +76,21 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t* __r
 // across rounds, so no barrier is needed while ranking.  The tile is then
 // placed in LDS in digit order and written with consecutive threads on
 // consecutive output positions inside each digit's run.
-__global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint64_t* __restrict__ in,
-                                                                uint64_t* __restrict__ out,
-                                                                uint32_t n, int shift,
-                                                                const uint32_t* __restrict__ goff) {
-  constexpr int kW = kSortThreads / kWave;
+//
+// With kKV every key carries a 32-bit value that moves with it (the values
+// take a second LDS tile).  A pass without input values (vin null) makes them:
+// value i is i | vgen[i] << 31.
+constexpr int kScatterWaves = kSortThreads / kWave;
+
+template <bool kKV>
+__device__ __forceinline__ void radix_scatter_tile(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+                                                   uint32_t n, int shift, const uint32_t* __restrict__ goff,
+                                                   const uint32_t* __restrict__ vin, const uint8_t* __restrict__ vgen,
+                                                   uint32_t* __restrict__ vout, uint64_t* tile, uint32_t* vtile,
+                                                   uint32_t (*cnt)[256], uint32_t* toff, uint32_t* gbase,
+                                                   uint32_t* wsum) {
+  constexpr int kW = kScatterWaves;
   constexpr int kRounds = kSortTile / kSortThreads;  // rounds per wave (16)
-  __shared__ uint64_t tile[kSortTile];
-  __shared__ uint32_t cnt[kW][256];
-  __shared__ uint32_t toff[256];
-  __shared__ uint32_t gbase[256];
-  __shared__ uint32_t wsum[kW];
   const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
 #pragma unroll
   for (int w = 0; w < kW; w++) cnt[w][tid] = 0;
@@ -96,10 +100,12 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint64_t* 
   const uint32_t wbase = base + (uint32_t)wid * (kRounds * kWave);
   const uint64_t lt_mask = (1ull << lane) - 1ull;
   uint64_t x[kRounds];
+  uint32_t v[kKV ? kRounds : 1];
 #pragma unroll
   for (int r = 0; r < kRounds; r++) {
     const uint32_t i = wbase + (uint32_t)r * kWave + lane;
     x[r] = i < n ? in[i] : 0;
+    if constexpr (kKV) v[r] = i < n ? (vin ? vin[i] : (i | ((uint32_t)vgen[i] << 31))) : 0u;
   }
   uint32_t rk[kRounds];
 #pragma unroll
@@ -147,15 +153,47 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint64_t* 
     if (wbase + (uint32_t)r * kWave + lane < n) {
       const uint32_t d = (uint32_t)(x[r] >> shift) & 255u;
       tile[cnt[wid][d] + rk[r]] = x[r];
+      if constexpr (kKV) vtile[cnt[wid][d] + rk[r]] = v[r];
     }
   }
   __syncthreads();
   const uint32_t m = min(kSortTile, n - base);
   for (uint32_t i = tid; i < m; i += kSortThreads) {
-    const uint64_t v = tile[i];
-    const uint32_t d = (uint32_t)(v >> shift) & 255u;
-    out[gbase[d] + (i - toff[d])] = v;
+    const uint64_t y = tile[i];
+    const uint32_t d = (uint32_t)(y >> shift) & 255u;
+    out[gbase[d] + (i - toff[d])] = y;
+    if constexpr (kKV) vout[gbase[d] + (i - toff[d])] = vtile[i];
   }
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint64_t* __restrict__ in,
+                                                                uint64_t* __restrict__ out,
+                                                                uint32_t n, int shift,
+                                                                const uint32_t* __restrict__ goff) {
+  __shared__ uint64_t tile[kSortTile];
+  __shared__ uint32_t cnt[kScatterWaves][256];
+  __shared__ uint32_t toff[256];
+  __shared__ uint32_t gbase[256];
+  __shared__ uint32_t wsum[kScatterWaves];
+  radix_scatter_tile<false>(in, out, n, shift, goff, nullptr, nullptr, nullptr, tile, nullptr, cnt, toff, gbase,
+                            wsum);
+}
+
+// Key-value scatter (stable, so equal keys keep the order of their values'
+// positions through every pass).
+__global__ void __launch_bounds__(kSortThreads) k_radix_scatter_kv(const uint64_t* __restrict__ in,
+                                                                   uint64_t* __restrict__ out, uint32_t n, int shift,
+                                                                   const uint32_t* __restrict__ goff,
+                                                                   const uint32_t* __restrict__ vin,
+                                                                   const uint8_t* __restrict__ vgen,
+                                                                   uint32_t* __restrict__ vout) {
+  __shared__ uint64_t tile[kSortTile];
+  __shared__ uint32_t vtile[kSortTile];
+  __shared__ uint32_t cnt[kScatterWaves][256];
+  __shared__ uint32_t toff[256];
+  __shared__ uint32_t gbase[256];
+  __shared__ uint32_t wsum[kScatterWaves];
+  radix_scatter_tile<true>(in, out, n, shift, goff, vin, vgen, vout, tile, vtile, cnt, toff, gbase, wsum);
 }
 
 // Flags of first occurrences in a sorted array.
