@@ -103,7 +103,7 @@ struct cpma {
       stage, pyr, win, wargs, cnt, koff, win_id, welem, P, ccost, ncost, lstart, planU, plan_used,
       spare_bytes, spare_used, spare_head, fg_level, fg_deg, fg_p, fg_c, fg_acc,
       win_of_leaf, fail, qa, qb, qfirst, qnvis, qvoff, qsum, qcount, qout, lastk, ne_rank, ne_list, chain_pfx,
-      srec, wide, srcinfo, fz_meta, fz_v0, fz_v1, fz_byte, fz_member, fz_code, fz_ctr, fz_res;
+      srec, wide, srcinfo, parts, fz_meta, fz_v0, fz_v1, fz_byte, fz_member, fz_code, fz_ctr, fz_res;
   Counters* dctr = nullptr;
   Counters* hctr = nullptr;
   BatchInfo* dinfo = nullptr;
@@ -801,8 +801,9 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   ensure(s->spill, kbound * sizeof(uint32_t));
   ensure(s->wide, kbound * sizeof(uint32_t));
   ensure(s->ovf, std::max<uint64_t>(s->L, 1) * sizeof(uint64_t));
-  // overflow arena: every leaf that outgrows S holds at most S + 10 bytes per new key
-  const uint64_t arena_cap = insert ? std::min<uint64_t>(s->L, kbound) * (uint64_t)(s->S + 16) + 10 * kbound + 256 : 256;
+  // overflow arena: segment s owns s * (S + 16) + 16 * (its first batch index)
+  // onwards (a leaf that outgrows S holds at most S + 10 bytes per new key)
+  const uint64_t arena_cap = insert ? std::min<uint64_t>(s->L, kbound) * (uint64_t)(s->S + 16) + 16 * kbound + 256 : 256;
   ensure(s->arena, arena_cap, 1.0);
   // heavy-merge staging: each heavy slice (more than kLaneHeavy keys) stages at
   // most its own keys plus one leaf's keys
@@ -871,25 +872,44 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   a.is_insert = insert ? 1 : 0;
   const uint64_t segs = std::min<uint64_t>(kbound, s->L);
   const uint32_t lgrid = (uint32_t)std::min<uint64_t>((segs + 255) / 256, (uint64_t)s->num_cus * 16);
+  const uint32_t wgrid = std::max(1u, (uint32_t)std::min<uint64_t>(segs, (uint64_t)s->num_cus * 40));
+  const uint32_t lwaves = std::max(1u, lgrid) * (256 / kWave);
+  // per-wave totals: each launch owns a run of slot pairs, main-merge launches
+  // first, follow-up launches after them
+  ensure(s->parts, 16ull * (2ull * wgrid + 2ull * lwaves));
+  unsigned long long* parts = s->parts.as<unsigned long long>();
+  uint32_t n_narrow = 0, n_wide = 0;
+  auto slots = [&](uint32_t waves, bool narrow) {
+    unsigned long long* p = parts + 2ull * (n_narrow + n_wide);
+    (narrow ? n_narrow : n_wide) += waves;
+    return p;
+  };
 
   // MERGE times exactly the main merge kernel; HEAVY the follow-up kernels for
   // wide, long and heavy slices
   PhaseMark pmg = phase_begin(s, CPMA_PHASE_MERGE, st);
   if (small && s->S <= kWaveMaxS) {
     // every segment in one 64-bit wave pass; long insert slices in the lane merge
-    const uint32_t wgrid = (uint32_t)std::min<uint64_t>(segs, (uint64_t)s->num_cus * 40);
-    hipLaunchKernelGGL(k_merge_wave<uint64_t>, dim3(std::max(1u, wgrid)), dim3(kWave), 0, st, a, 1);
-    if (insert) hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 1);
+    a.part = slots(wgrid, false);
+    hipLaunchKernelGGL(k_merge_wave<uint64_t>, dim3(wgrid), dim3(kWave), 0, st, a, 1);
+    if (insert) {
+      a.part = slots(lwaves, false);
+      hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 1);
+    }
     HIPCHK(hipGetLastError());
     phase_end(s, pmg, st);
   } else if (s->S <= kWaveMaxS) {
-    const uint32_t wgrid = (uint32_t)std::min<uint64_t>(segs, (uint64_t)s->num_cus * 40);
-    hipLaunchKernelGGL(k_merge_wave<uint32_t>, dim3(std::max(1u, wgrid)), dim3(kWave), 0, st, a);
+    a.part = slots(wgrid, true);
+    hipLaunchKernelGGL(k_merge_wave<uint32_t>, dim3(wgrid), dim3(kWave), 0, st, a);
     HIPCHK(hipGetLastError());
     phase_end(s, pmg, st);
     PhaseMark ph = phase_begin(s, CPMA_PHASE_HEAVY, st);
-    hipLaunchKernelGGL(k_merge_wave<uint64_t>, dim3(std::max(1u, wgrid)), dim3(kWave), 0, st, a);
-    if (insert) hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 1);
+    a.part = slots(wgrid, false);
+    hipLaunchKernelGGL(k_merge_wave<uint64_t>, dim3(wgrid), dim3(kWave), 0, st, a);
+    if (insert) {
+      a.part = slots(lwaves, false);
+      hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 1);
+    }
     if (insert) {
       const uint32_t hgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, kbound / kLaneHeavy), 1024);
       hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid), dim3(kWave), heavy_smem(s->S), st, a);
@@ -897,6 +917,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
     HIPCHK(hipGetLastError());
     phase_end(s, ph, st);
   } else {
+    a.part = slots(lwaves, true);
     hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 0);
     HIPCHK(hipGetLastError());
     phase_end(s, pmg, st);
@@ -908,6 +929,9 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
       phase_end(s, ph, st);
     }
   }
+  hipLaunchKernelGGL(k_fold_parts, dim3(1), dim3(1024), 0, st, (const unsigned long long*)parts, n_narrow, n_wide,
+                     s->dctr);
+  HIPCHK(hipGetLastError());
   return rebalance(s, st, insert ? 1 : 0);
 }
 
@@ -1554,7 +1578,7 @@ void cpma_destroy(cpma* s) {
                     &s->fg_level, &s->fg_deg, &s->fg_p, &s->fg_c, &s->fg_acc, &s->lstart, &s->planU,
                     &s->plan_used, &s->win_of_leaf, &s->fail, &s->qa,        &s->qb,    &s->qfirst, &s->qnvis,
                     &s->qvoff,  &s->qsum,     &s->qcount,    &s->qout,  &s->lastk, &s->ne_rank, &s->ne_list,
-                    &s->chain_pfx, &s->srec, &s->wide, &s->srcinfo, &s->fz_meta, &s->fz_v0, &s->fz_v1,
+                    &s->chain_pfx, &s->srec, &s->wide, &s->srcinfo, &s->parts, &s->fz_meta, &s->fz_v0, &s->fz_v1,
                     &s->fz_byte, &s->fz_member, &s->fz_code, &s->fz_ctr, &s->fz_res};
   for (DevBuf* b : bufs) release(*b);
   if (s->dctr) hipFree(s->dctr);

@@ -242,7 +242,7 @@ __global__ void __launch_bounds__(256) k_merge_lane(MergeArgs a, int from_list) 
       uint8_t* dst = lp;
       if (size > S) {
         const uint64_t need = (size + 15) & ~15ull;
-        const uint64_t off = atomicAdd(&a.ctr->arena_cursor, (unsigned long long)need);
+        const uint64_t off = arena_region(a, s);
         if (off + need > a.arena_cap) {
           atomicOr(&a.ctr->error, 1u);
           continue;
@@ -327,9 +327,11 @@ __global__ void __launch_bounds__(256) k_merge_lane(MergeArgs a, int from_list) 
   }
   delta = wave_sum((uint64_t)delta);
   alg = wave_sum((uint64_t)alg);
+  // per-wave slot, summed by k_fold_parts
+  const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (lane_id() == 0) {
-    if (delta) atomicAdd(&a.ctr->delta, delta);
-    if (alg) atomicAdd(from_list ? &a.ctr->alg_bytes_h : &a.ctr->alg_bytes, alg);
+    a.part[2 * w] = delta;
+    a.part[2 * w + 1] = alg;
   }
 }
 

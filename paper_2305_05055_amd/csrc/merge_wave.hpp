@@ -230,9 +230,7 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segme
       U = lane63_u32(lincl);
       if (U > S) {
         const uint64_t need = ((uint64_t)U + 15) & ~15ull;
-        uint64_t off = 0;
-        if (lane == 0) off = atomicAdd(&a.ctr->arena_cursor, (unsigned long long)need);
-        off = __shfl(off, 0, kWave);
+        const uint64_t off = arena_region(a, s);
         if (off + need > a.arena_cap) {
           if (lane == 0) atomicOr(&a.ctr->error, 1u);
           continue;
@@ -339,9 +337,11 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segme
     }
     __syncthreads();
   }
+  // no atomics on shared counters (thousands of waves would serialise on
+  // them): each wave leaves its totals in its own slot, summed by k_fold_parts
   if (lane == 0) {
-    if (delta) atomicAdd(&a.ctr->delta, delta);
-    if (alg) atomicAdd(kNarrow ? &a.ctr->alg_bytes : &a.ctr->alg_bytes_h, alg);
+    a.part[2 * blockIdx.x] = delta;
+    a.part[2 * blockIdx.x + 1] = alg;
   }
 }
 

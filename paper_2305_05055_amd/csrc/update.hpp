@@ -11,7 +11,7 @@ namespace cpma_dev {
 // Device-side counters of one update, read back by the host at its sync points.
 struct Counters {
   unsigned long long delta;         // keys added (insert) or removed (delete)
-  unsigned long long arena_cursor;  // bytes used in the overflow arena
+  unsigned long long arena_cursor;  // unused (arena regions are fixed per segment)
   unsigned long long stage_cursor;  // keys used in the staging buffer by heavy merges
   unsigned long long kprime;        // batch size after removing repeats
   unsigned long long T;             // touched leaves (segments)
@@ -202,9 +202,54 @@ struct MergeArgs {
   uint32_t* spill_list;   // segments routed from the wave merge to the lane merge
   uint32_t* wide_list;    // segments whose keys span more than 2^32
   Counters* ctr;
+  unsigned long long* part;  // per wave of the launch: {keys added / removed, algorithmic bytes}
   uint32_t S;
   int is_insert;
 };
+
+// Arena region of segment s: s * (S + 16) + 16 * (its first batch index).  A
+// merge grows a leaf by at most 10 bytes per new key (the new key's code; the
+// old key after it only gets a smaller delta), so segment s needs at most
+// S + 10 * nb + 15 bytes: the regions are disjoint, 16-byte aligned and need
+// no shared cursor.
+__device__ __forceinline__ uint64_t arena_region(const MergeArgs& a, uint64_t s) {
+  return s * (uint64_t)(a.S + 16) + 16ull * a.seg_begin[s];
+}
+
+// Sums the per-wave parts of the merge launches into the counters: the first
+// n_narrow pairs count as main-merge bytes, the next n_wide as follow-up bytes.
+__global__ void __launch_bounds__(1024) k_fold_parts(const unsigned long long* __restrict__ part,
+                                                     uint32_t n_narrow, uint32_t n_wide, Counters* ctr) {
+  __shared__ uint64_t red[3][1024 / kWave];
+  uint64_t d = 0, an = 0, aw = 0;
+  for (uint32_t w = threadIdx.x; w < n_narrow + n_wide; w += blockDim.x) {
+    d += part[2 * w];
+    if (w < n_narrow)
+      an += part[2 * w + 1];
+    else
+      aw += part[2 * w + 1];
+  }
+  d = wave_sum(d);
+  an = wave_sum(an);
+  aw = wave_sum(aw);
+  const int wid = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    red[0][wid] = d;
+    red[1][wid] = an;
+    red[2][wid] = aw;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x / kWave); i++) {
+      d += red[0][i];
+      an += red[1][i];
+      aw += red[2][i];
+    }
+    if (d) atomicAdd(&ctr->delta, (unsigned long long)d);
+    if (an) atomicAdd(&ctr->alg_bytes, (unsigned long long)an);
+    if (aw) atomicAdd(&ctr->alg_bytes_h, (unsigned long long)aw);
+  }
+}
 
 template <typename KT>
 __device__ __forceinline__ uint32_t lds_lower_bound(const KT* A, uint32_t n, KT x) {
@@ -237,7 +282,7 @@ __device__ __forceinline__ void wave_scan_inplace(uint32_t* F, uint32_t n) {
 // bytes are rewritten: the rest of the leaf is already zero.  Updates used /
 // head / ovf and returns the bytes written.
 template <class Get>
-__device__ uint64_t wave_store_leaf(const MergeArgs& a, uint64_t leaf, Get&& get, uint32_t m,
+__device__ uint64_t wave_store_leaf(const MergeArgs& a, uint64_t seg, uint64_t leaf, Get&& get, uint32_t m,
                                     uint8_t* buf, uint32_t old_used) {
   const int lane = lane_id();
   uint8_t* dst = a.bytes + leaf * (uint64_t)a.S;
@@ -261,9 +306,7 @@ __device__ uint64_t wave_store_leaf(const MergeArgs& a, uint64_t leaf, Get&& get
     written = len;
   } else {
     const uint64_t need = (T + 15) & ~15ull;
-    uint64_t off = 0;
-    if (lane == 0) off = atomicAdd(&a.ctr->arena_cursor, (unsigned long long)need);
-    off = __shfl(off, 0, kWave);
+    const uint64_t off = arena_region(a, seg);
     if (off + need > a.arena_cap) {
       if (lane == 0) atomicOr(&a.ctr->error, 1u);
       return 0;
@@ -333,7 +376,7 @@ __global__ void __launch_bounds__(kWave) k_merge_heavy(MergeArgs a) {
     delta += nb - present;
     __threadfence_block();
     __syncthreads();
-    wave_store_leaf(a, leaf, [&](uint32_t i) { return C[i]; }, nC, buf, used0);
+    wave_store_leaf(a, s, leaf, [&](uint32_t i) { return C[i]; }, nC, buf, used0);
     __syncthreads();
   }
   if (lane == 0 && delta) atomicAdd(&a.ctr->delta, delta);
