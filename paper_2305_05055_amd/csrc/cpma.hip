@@ -103,7 +103,7 @@ struct cpma {
       stage, pyr, win, wargs, cnt, koff, win_id, welem, P, ccost, ncost, lstart, planU, plan_used,
       spare_bytes, spare_used, spare_head, fg_level, fg_deg, fg_p, fg_c, fg_acc,
       win_of_leaf, fail, qa, qb, qfirst, qnvis, qvoff, qsum, qcount, qout, lastk, ne_rank, ne_list, chain_pfx,
-      srec, wide, srcinfo, parts, fz_meta, fz_v0, fz_v1, fz_byte, fz_member, fz_code, fz_ctr, fz_res;
+      srec, wide, srcinfo, parts, qparts, fz_meta, fz_v0, fz_v1, fz_byte, fz_member, fz_code, fz_ctr, fz_res;
   Counters* dctr = nullptr;
   Counters* hctr = nullptr;
   BatchInfo* dinfo = nullptr;
@@ -1358,22 +1358,37 @@ cpma_status cpma_range_map(const cpma* cs, const uint64_t* lo, const uint64_t* h
     ensure(s->qnvis, q * 8);
     ensure(s->qvoff, (q + 1) * 8);
     PhaseMark pq = phase_begin(s, CPMA_PHASE_QUERY, st);
-    unsigned long long* qalg = s->stats_on ? s->dqalg : (unsigned long long*)nullptr;
-    if (q <= (uint64_t)s->num_cus * 64)  // few queries: a wave per query
-      hipLaunchKernelGGL(k_rm_ends_wave, dim3(grid_for(q, 1, (uint32_t)s->num_cus * 64)), dim3(kWave), 0, st, a,
-                         s->qfirst.as<uint64_t>(), s->qnvis.as<uint64_t>(), dsum, dcount, qalg);
+    // statistics: one byte-count slot per wave of the end and interior kernels
+    const bool wave_ends = q <= (uint64_t)s->num_cus * 64;  // few queries: a wave per query
+    const uint32_t egrid = wave_ends ? grid_for(q, 1, (uint32_t)s->num_cus * 64)
+                                     : grid_for(q, 256, (uint32_t)s->num_cus * 16);
+    const uint64_t ewaves = wave_ends ? egrid : 4ull * egrid;
+    const uint32_t blocks = (uint32_t)s->num_cus * 8;
+    const uint64_t nslots = ewaves + 4ull * blocks;
+    unsigned long long* qalg = nullptr;
+    if (s->stats_on) {
+      ensure(s->qparts, 8 * nslots);
+      qalg = s->qparts.as<unsigned long long>();
+    }
+    if (wave_ends)
+      hipLaunchKernelGGL(k_rm_ends_wave, dim3(egrid), dim3(kWave), 0, st, a, s->qfirst.as<uint64_t>(),
+                         s->qnvis.as<uint64_t>(), dsum, dcount, qalg);
     else
-      hipLaunchKernelGGL(k_rm_ends, dim3(grid_for(q, 256, (uint32_t)s->num_cus * 16)), dim3(256), 0, st, a,
-                         s->qfirst.as<uint64_t>(), s->qnvis.as<uint64_t>(), dsum, dcount, qalg);
+      hipLaunchKernelGGL(k_rm_ends, dim3(egrid), dim3(256), 0, st, a, s->qfirst.as<uint64_t>(),
+                         s->qnvis.as<uint64_t>(), dsum, dcount, qalg);
     HIPCHK(hipGetLastError());
     scan<uint64_t>(s, s->qvoff.as<uint64_t>(), q, st, LoadFn<uint64_t>{s->qnvis.as<uint64_t>()});
-    const uint32_t blocks = (uint32_t)s->num_cus * 8;
     PhaseMark ps = phase_begin(s, CPMA_PHASE_RANGE_SCAN, st);
     hipLaunchKernelGGL(k_rm_interior, dim3(blocks), dim3(256), 0, st, a, (const uint64_t*)s->qvoff.as<uint64_t>(),
-                       (const uint64_t*)s->qfirst.as<uint64_t>(), s->cfg.range_chunk, dsum, dcount, qalg);
+                       (const uint64_t*)s->qfirst.as<uint64_t>(), s->cfg.range_chunk, dsum, dcount,
+                       qalg ? qalg + ewaves : qalg);
     HIPCHK(hipGetLastError());
     phase_end(s, ps, st, 32ull * q);
     phase_end(s, pq, st);
+    if (qalg) {
+      hipLaunchKernelGGL(k_fold_sum, dim3(1), dim3(1024), 0, st, (const unsigned long long*)qalg, nslots, s->dqalg);
+      HIPCHK(hipGetLastError());
+    }
     if (mem == CPMA_MEM_HOST) {
       HIPCHK(hipMemcpyAsync(sum, dsum, q * 8, hipMemcpyDeviceToHost, st));
       HIPCHK(hipMemcpyAsync(count, dcount, q * 8, hipMemcpyDeviceToHost, st));
@@ -1578,7 +1593,7 @@ void cpma_destroy(cpma* s) {
                     &s->fg_level, &s->fg_deg, &s->fg_p, &s->fg_c, &s->fg_acc, &s->lstart, &s->planU,
                     &s->plan_used, &s->win_of_leaf, &s->fail, &s->qa,        &s->qb,    &s->qfirst, &s->qnvis,
                     &s->qvoff,  &s->qsum,     &s->qcount,    &s->qout,  &s->lastk, &s->ne_rank, &s->ne_list,
-                    &s->chain_pfx, &s->srec, &s->wide, &s->srcinfo, &s->parts, &s->fz_meta, &s->fz_v0, &s->fz_v1,
+                    &s->chain_pfx, &s->srec, &s->wide, &s->srcinfo, &s->parts, &s->qparts, &s->fz_meta, &s->fz_v0, &s->fz_v1,
                     &s->fz_byte, &s->fz_member, &s->fz_code, &s->fz_ctr, &s->fz_res};
   for (DevBuf* b : bufs) release(*b);
   if (s->dctr) hipFree(s->dctr);

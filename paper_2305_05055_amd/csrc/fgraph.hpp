@@ -139,8 +139,10 @@ __global__ void __launch_bounds__(256) k_fg_bfs_step(FgArgs g, uint32_t* __restr
       }
     }
   }
-  claimed = wave_sum(claimed);
-  if (lane_id() == 0 && claimed) atomicAdd(found, claimed);
+  // the host only tests for zero: a plain store of 1, not a counter every
+  // wave would serialise on
+  if (__ballot(claimed != 0) && lane_id() == 0)
+    __hip_atomic_store(found, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // PageRank vertex kernels: contrib[u] = p[u] / deg[u] (0 for isolated vertices),

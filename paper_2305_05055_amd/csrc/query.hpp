@@ -60,9 +60,9 @@ __global__ void __launch_bounds__(256) k_rm_ends(QueryArgs a, uint64_t* __restri
     sum[i] = r.sum;
     count[i] = r.count;
   }
-  if (alg) {
+  if (alg) {  // statistics: one slot per wave (no shared counter), summed by k_fold_sum
     const uint64_t t = wave_sum(visited);
-    if (lane_id() == 0 && t) atomicAdd(alg, (unsigned long long)t);
+    if (lane_id() == 0) alg[((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave] = t;
   }
 }
 
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(kWave) k_rm_ends_wave(QueryArgs a, uint64_t* _
       count[i] = r.count;
     }
   }
-  if (alg && lane_id() == 0 && visited) atomicAdd(alg, (unsigned long long)visited);
+  if (alg && lane_id() == 0) alg[blockIdx.x] = visited;
 }
 
 // Interior visits, flattened over all queries: each lane takes `chunk`
@@ -208,7 +208,22 @@ __global__ void __launch_bounds__(256) k_rm_interior(QueryArgs a, const uint64_t
   }
   if (alg) {
     const uint64_t t = wave_sum(visited);
-    if (lane_id() == 0 && t) atomicAdd(alg, (unsigned long long)t);
+    if (lane_id() == 0) alg[((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave] = t;
+  }
+}
+
+// Sum of n per-wave statistics slots, added to *out (one block).
+__global__ void __launch_bounds__(1024) k_fold_sum(const unsigned long long* __restrict__ part, uint64_t n,
+                                                   unsigned long long* out) {
+  __shared__ uint64_t red[1024 / kWave];
+  uint64_t t = 0;
+  for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) t += part[i];
+  t = wave_sum(t);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x / kWave); i++) t += red[i];
+    atomicAdd(out, (unsigned long long)t);
   }
 }
 
