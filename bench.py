@@ -130,16 +130,23 @@ def fgraph_section(cp, torch, scale, seed):
     out = {"scale": scale, "vertices": nv, "edges": g.size(), "build_s": time.perf_counter() - t0,
            "bytes_per_edge": g.bytes() / g.size()}
     del keys
-    g.bfs(nv, 0)
+    # outputs stay in HBM while timed (a host copy of 2^24 levels would add a
+    # 64 MB PCIe transfer to an algorithm that runs in memory)
+    g.bfs(nv, 0, symmetric=True, device=True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lv = g.bfs(nv, 0)
+    lv = g.bfs(nv, 0, symmetric=True, device=True)
+    torch.cuda.synchronize()
     out["bfs_ms"] = (time.perf_counter() - t0) * 1e3
+    lv = lv.cpu().numpy().view(np.uint32)
     reach = lv[lv != 0xFFFFFFFF]
     out["bfs_levels"] = int(reach.max()) + 1
     out["bfs_reached"] = int(len(reach))
-    g.pagerank(nv, iters=1)
+    g.pagerank(nv, iters=1, device=True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    g.pagerank(nv, iters=10)
+    g.pagerank(nv, iters=10, device=True)
+    torch.cuda.synchronize()
     out["pagerank_10_iters_ms"] = (time.perf_counter() - t0) * 1e3
     ins = {}
     for k in (10 ** 5, 10 ** 6, 10 ** 7):

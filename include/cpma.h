@@ -221,6 +221,11 @@ cpma_status cpma_export(const cpma* set, uint8_t* bytes, uint32_t* used,
  * cpma_fgraph_bfs: level[v] = hop distance from `source` (UINT32_MAX when
  * unreachable), following edges u -> v.  level is nv entries in memory space
  * `mem`.  The result is unique; the traversal is level-synchronous.
+ * symmetric != 0 promises that every edge u -> v has its reverse v -> u (an
+ * undirected graph, as F-Graph stores); levels may then be expanded bottom-up
+ * (unvisited vertices looking for a parent), whichever direction has fewer
+ * vertices to expand.  With symmetric == 0 every level runs top-down; a wrong
+ * promise gives the levels of the reversed edges on bottom-up levels.
  *
  * cpma_fgraph_pagerank: `iters` rounds (the paper runs 10) of
  *   p'(v) = (1 - damping) / nv + damping * sum over edges (v, u) of p(u) / deg(u)
@@ -229,7 +234,7 @@ cpma_status cpma_export(const cpma* set, uint8_t* bytes, uint32_t* used,
  * in the paper's F-Graph); then this equals pushing p(u)/deg(u) along every
  * edge u -> v.  p is nv floats in memory space `mem`.
  */
-cpma_status cpma_fgraph_bfs(const cpma* set, uint32_t nv, uint32_t source, cpma_mem mem,
+cpma_status cpma_fgraph_bfs(const cpma* set, uint32_t nv, uint32_t source, int symmetric, cpma_mem mem,
                             uint32_t* level, void* stream);
 cpma_status cpma_fgraph_pagerank(const cpma* set, uint32_t nv, int iters, double damping,
                                  cpma_mem mem, float* p, void* stream);

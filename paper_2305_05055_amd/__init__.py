@@ -97,7 +97,7 @@ def lib():
         L.cpma_export.argtypes = [vp, vp, vp, vp, vp]
         L.cpma_destroy.argtypes = [vp]
         L.cpma_destroy.restype = None
-        L.cpma_fgraph_bfs.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, vp, vp]
+        L.cpma_fgraph_bfs.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, vp, vp]
         L.cpma_fgraph_pagerank.argtypes = [vp, ctypes.c_uint32, ctypes.c_int, ctypes.c_double,
                                            ctypes.c_int, vp, vp]
         L.cpma_server_start.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
@@ -295,8 +295,9 @@ class CPMA:
         return int(L.value), int(S.value)
 
     # ---- F-Graph: edge keys u<<32 | v --------------------------------------------
-    def bfs(self, nv, source=0, device=False, stream=None):
-        """Hop distance of every vertex from `source` (0xFFFFFFFF if unreachable)."""
+    def bfs(self, nv, source=0, symmetric=False, device=False, stream=None):
+        """Hop distance of every vertex from `source` (0xFFFFFFFF if unreachable).
+        symmetric=True promises every edge has its reverse (allows bottom-up levels)."""
         if device:
             import torch
             out = torch.empty(nv, dtype=torch.int32, device="cuda")
@@ -304,7 +305,8 @@ class CPMA:
         else:
             out = np.empty(nv, dtype=np.uint32)
             ptr, mem = ctypes.c_void_p(out.ctypes.data), MEM_HOST
-        _check(lib().cpma_fgraph_bfs(self._h, nv, source, mem, ptr, _stream(stream, device)),
+        _check(lib().cpma_fgraph_bfs(self._h, nv, source, 1 if symmetric else 0, mem, ptr,
+                                     _stream(stream, device)),
                "cpma_fgraph_bfs")
         return out
 

@@ -1435,6 +1435,7 @@ static FgArgs fg_args(const cpma* s, uint32_t nv) {
   FgArgs g;
   g.bytes = (const uint8_t*)s->bytes.p;
   g.used = (const uint32_t*)s->used.p;
+  g.head = (const uint64_t*)s->head.p;
   g.L = s->L;
   g.S = s->S;
   g.nv = nv;
@@ -1445,8 +1446,8 @@ static uint32_t fg_grid(const cpma* s) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((s->L + 3) / 4, (uint64_t)s->num_cus * 16));
 }
 
-cpma_status cpma_fgraph_bfs(const cpma* cs, uint32_t nv, uint32_t source, cpma_mem mem, uint32_t* level,
-                            void* stream) {
+cpma_status cpma_fgraph_bfs(const cpma* cs, uint32_t nv, uint32_t source, int symmetric, cpma_mem mem,
+                            uint32_t* level, void* stream) {
   cpma* s = const_cast<cpma*>(cs);
   if (!s || !level || nv == 0 || source >= nv) return CPMA_ERR_INVALID;
   if (s->S > kWaveMaxS) return CPMA_ERR_INVALID;
@@ -1464,12 +1465,38 @@ cpma_status cpma_fgraph_bfs(const cpma* cs, uint32_t nv, uint32_t source, cpma_m
     hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, lv + source, (uint64_t)1, 0u);
     HIPCHK(hipGetLastError());
     const FgArgs g = fg_args(s, nv);
-    for (uint32_t cur = 0; cur < nv; cur++) {
-      zero_counters(s, st);
-      hipLaunchKernelGGL(k_fg_bfs_step, dim3(fg_grid(s)), dim3(256), 0, st, g, lv, cur, &s->dctr->found);
+    // bitmaps of the current level and of the visited vertices, rebuilt after
+    // every level together with the level sizes (one slot pair per block,
+    // summed into the last pair)
+    const uint32_t nw = (nv + 31) / 32;
+    const uint32_t cgrid = grid_for(nw, 256, (uint32_t)s->num_cus * 8);
+    const uint64_t bits_words = 2ull * ((nw + 1) & ~1u);  // keeps the slots 8-byte aligned
+    ensure(s->fg_c, 4 * bits_words + 16ull * (cgrid + 1));
+    uint32_t* front = s->fg_c.as<uint32_t>();
+    uint32_t* seen = front + (bits_words / 2);
+    unsigned long long* cpart = reinterpret_cast<unsigned long long*>(front + bits_words);
+    const BfsBits bb{front, seen};
+    uint64_t* hc = reinterpret_cast<uint64_t*>(host_pin(s, 16));
+    hipLaunchKernelGGL(k_fg_level_bits, dim3(cgrid), dim3(256), 0, st, (const uint32_t*)lv, nv, 0u, front, seen,
+                       cpart);
+    HIPCHK(hipGetLastError());
+    // the step runs bottom-up once the level is large against the unvisited
+    // set (its vertices have the most edges, so top-down gets dear early)
+    uint64_t frontier = 1, unvisited = nv - 1;
+    for (uint32_t cur = 0; frontier > 0 && cur < nv; cur++) {
+      if (!symmetric || 4 * frontier <= unvisited)
+        hipLaunchKernelGGL(k_fg_bfs_step<false>, dim3(fg_grid(s)), dim3(256), 0, st, g, bb, lv, cur);
+      else
+        hipLaunchKernelGGL(k_fg_bfs_step<true>, dim3(fg_grid(s)), dim3(256), 0, st, g, bb, lv, cur);
+      hipLaunchKernelGGL(k_fg_level_bits, dim3(cgrid), dim3(256), 0, st, (const uint32_t*)lv, nv, cur + 1, front,
+                         seen, cpart);
+      hipLaunchKernelGGL(k_fg_fold_counts, dim3(1), dim3(1024), 0, st, (const unsigned long long*)cpart, cgrid,
+                         cpart + 2ull * cgrid);
       HIPCHK(hipGetLastError());
-      read_counters(s, st);
-      if (s->hctr->found == 0) break;
+      HIPCHK(hipMemcpyAsync(hc, cpart + 2ull * cgrid, 16, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      frontier = hc[0];
+      unvisited = hc[1];
     }
     if (mem == CPMA_MEM_HOST) {
       HIPCHK(hipMemcpyAsync(level, lv, (uint64_t)nv * 4, hipMemcpyDeviceToHost, st));

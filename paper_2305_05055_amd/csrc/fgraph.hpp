@@ -9,8 +9,9 @@
 // each lane folds its keys into runs of equal source and flushes a run with one
 // atomic.  PageRank (a fixed number of iterations) runs in pull form, which on
 // a symmetric edge set (an undirected graph, the case F-Graph supports) equals
-// pushing p(u)/deg(u) along every edge.  BFS is level synchronous: a pass over
-// all edges claims the unvisited targets of the current level's vertices.
+// pushing p(u)/deg(u) along every edge.  BFS is level synchronous and
+// direction optimising: each level passes over the leaves holding the current
+// level's vertices (top-down) or the unvisited ones (bottom-up).
 #pragma once
 #include "leaf.hpp"
 
@@ -19,6 +20,7 @@ namespace cpma_dev {
 struct FgArgs {
   const uint8_t* bytes;
   const uint32_t* used;
+  const uint64_t* head;
   uint64_t L;
   uint32_t S;   // at most 1024: one 16-byte chunk per lane
   uint32_t nv;  // vertex ids are < nv; keys with a larger id are ignored
@@ -113,36 +115,169 @@ __global__ void __launch_bounds__(256) k_fg_pull(FgArgs g, const float* __restri
   }
 }
 
-// Level-synchronous BFS step as a full pass: for every edge (u, v) with u at
-// level `cur` and v unvisited, v is claimed for level cur + 1 (compare-and-swap,
-// so each vertex is counted once); *found counts the claims.
-__global__ void __launch_bounds__(256) k_fg_bfs_step(FgArgs g, uint32_t* __restrict__ level, uint32_t cur,
-                                                     unsigned int* __restrict__ found) {
-  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
-  uint32_t claimed = 0;
-  for (uint64_t leaf = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; leaf < g.L;
-       leaf += waves) {
-    uint64_t kk[16];
-    const uint32_t tm = wave_leaf_keys(g.bytes + leaf * (uint64_t)g.S, g.used[leaf], kk);
-    bool hit[16];
+// BFS state besides the levels: two bitmaps over the vertices, rebuilt from the
+// levels after every level (2 MB each at 2^24 vertices, so the random tests of
+// a step hit L2 instead of the 4-byte level entries):
+//   front: level == cur (the vertices being expanded);
+//   seen:  level != unvisited.
+constexpr uint32_t kUnvisited = 0xffffffffu;
+
+struct BfsBits {
+  const uint32_t* front;
+  const uint32_t* seen;
+};
+
+__device__ __forceinline__ bool bit_of(const uint32_t* b, uint32_t v) { return (b[v >> 5] >> (v & 31)) & 1u; }
+
+// Whether bits [s0, s1] of b (xor `flip`) hold a one.
+__device__ __forceinline__ bool any_bit(const uint32_t* b, uint32_t flip, uint32_t s0, uint32_t s1) {
+  const uint32_t w0 = s0 >> 5, w1 = s1 >> 5;
+  uint32_t acc = 0;
+  for (uint32_t w = w0; w <= w1; w++) {
+    uint32_t x = b[w] ^ flip;
+    if (w == w0) x &= ~0u << (s0 & 31);
+    if (w == w1) x &= ~0u >> (31 - (s1 & 31));
+    acc |= x;
+  }
+  return acc != 0;
+}
+
+// Whether leaf f holds a source whose bit in b (xor `flip`) is set (one lane).
+// The leaf's keys lie in [head[f], head[f + 1]), so its sources lie in
+// [src(head[f]), src(head[f + 1])]: a few bitmap words instead of a decode.
+// Spans wider than kFgSkipSpan vertices (the last leaf, sparse id ranges) are
+// not tested and count as holding one.
+constexpr uint32_t kFgSkipSpan = 256;
+
+__device__ __forceinline__ bool fg_leaf_has(const FgArgs& g, const uint32_t* b, uint32_t flip, uint64_t f) {
+  const uint64_t h = g.head[f];
+  if (h == kNoKey) return false;  // the empty leaf of an empty set
+  const uint32_t s0 = src_of(h);
+  if (s0 >= g.nv) return false;  // every key of the leaf is ignored
+  if (f + 1 >= g.L) return true;
+  const uint32_t s1 = min(src_of(g.head[f + 1]), g.nv - 1);
+  if (s1 - s0 >= kFgSkipSpan) return true;
+  return any_bit(b, flip, s0, s1);
+}
+
+// One level of a level-synchronous BFS (the hop distance of every vertex
+// reached from the source).  On a symmetric edge set a vertex v joins level
+// cur + 1 iff it is unvisited and some neighbour u has level cur, which can be
+// found from either end of the edge (u, v):
+//   top-down:  for edges (u, v) with u at level cur, mark v if unvisited;
+//   bottom-up: for edges (v, u) with v unvisited, mark v if u is at level cur.
+// Each direction decodes only the leaves holding a source it needs (level cur,
+// resp. unvisited): a wave takes 64 leaves, each lane tests one, and the wave
+// then decodes the needed ones one after another.  A mark is a plain store of
+// cur + 1 into the levels: every writer stores the same value, and the tests
+// read only the bitmaps, which this level does not change.
+template <bool kBottomUp>
+__global__ void __launch_bounds__(256) k_fg_bfs_step(FgArgs g, BfsBits bb, uint32_t* __restrict__ level,
+                                                     uint32_t cur) {
+  const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / kWave);
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  for (uint64_t base = wave * kWave; base < g.L; base += nwaves * kWave) {
+    const uint64_t f = base + (uint64_t)lane_id();
+    const bool need = f < g.L && (kBottomUp ? fg_leaf_has(g, bb.seen, ~0u, f) : fg_leaf_has(g, bb.front, 0u, f));
+    uint64_t m = __ballot(need);
+    while (m) {
+      const uint64_t leaf = base + (uint64_t)(__ffsll((unsigned long long)m) - 1);
+      m &= m - 1;
+      uint64_t kk[16];
+      const uint32_t tm = wave_leaf_keys(g.bytes + leaf * (uint64_t)g.S, g.used[leaf], kk);
 #pragma unroll
-    for (int i = 0; i < 16; i++) {
-      const uint32_t s = src_of(kk[i]), d = dst_of(kk[i]);
-      const bool ok = (tm & (1u << i)) && s < g.nv && d < g.nv;
-      hit[i] = ok && level[s] == cur && level[d] == 0xffffffffu;
-    }
-#pragma unroll
-    for (int i = 0; i < 16; i++) {
-      if (hit[i]) {
-        const uint32_t d = dst_of(kk[i]);
-        if (atomicCAS(&level[d], 0xffffffffu, cur + 1) == 0xffffffffu) claimed++;
+      for (int i = 0; i < 16; i++) {
+        const uint32_t s = src_of(kk[i]), d = dst_of(kk[i]);
+        const bool ok = (tm & (1u << i)) && s < g.nv && d < g.nv;
+        if (kBottomUp) {
+          if (ok && !bit_of(bb.seen, s) && bit_of(bb.front, d)) level[s] = cur + 1;
+        } else {
+          if (ok && bit_of(bb.front, s) && !bit_of(bb.seen, d)) level[d] = cur + 1;
+        }
       }
     }
   }
-  // the host only tests for zero: a plain store of 1, not a counter every
-  // wave would serialise on
-  if (__ballot(claimed != 0) && lane_id() == 0)
-    __hip_atomic_store(found, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// After a level: the bitmaps for the next one (front: level == next; seen:
+// level != unvisited), one 32-bit word per thread, and per block the number of
+// vertices at level `next` and of unvisited vertices as one slot pair (summed by
+// k_fg_fold_counts; no counter shared by all blocks).
+__global__ void __launch_bounds__(256) k_fg_level_bits(const uint32_t* __restrict__ level, uint32_t nv, uint32_t next,
+                                                       uint32_t* __restrict__ front, uint32_t* __restrict__ seen,
+                                                       unsigned long long* __restrict__ part) {
+  __shared__ uint64_t red[2][256 / kWave];
+  uint64_t a = 0, b = 0;
+  const uint32_t nw = (nv + 31) / 32;
+  const bool vec = (reinterpret_cast<uintptr_t>(level) & 15) == 0;  // 16-byte loads of 4 levels
+  for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += gridDim.x * blockDim.x) {
+    uint32_t fw = 0, sw = 0;
+    const uint32_t v0 = w * 32;
+    if (v0 + 32 <= nv && vec) {
+      const uint4* p = reinterpret_cast<const uint4*>(level + v0);
+#pragma unroll
+      for (int q = 0; q < 8; q++) {
+        const uint4 x = p[q];
+        const uint32_t l[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          fw |= (uint32_t)(l[j] == next) << (4 * q + j);
+          sw |= (uint32_t)(l[j] != kUnvisited) << (4 * q + j);
+        }
+      }
+    } else {
+      for (uint32_t j = 0; v0 + j < nv; j++) {
+        const uint32_t l = level[v0 + j];
+        fw |= (uint32_t)(l == next) << j;
+        sw |= (uint32_t)(l != kUnvisited) << j;
+      }
+    }
+    front[w] = fw;
+    seen[w] = sw;
+    a += (uint32_t)__popc(fw);
+    b += (uint32_t)(min(32u, nv - v0) - (uint32_t)__popc(sw));
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (lane_id() == 0) {
+    red[0][threadIdx.x / kWave] = a;
+    red[1][threadIdx.x / kWave] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 256 / kWave; w++) {
+      a += red[0][w];
+      b += red[1][w];
+    }
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
+  }
+}
+
+// Sums n slot pairs into out[0], out[1] (one block; out is overwritten).
+__global__ void __launch_bounds__(1024) k_fg_fold_counts(const unsigned long long* __restrict__ part, uint32_t n,
+                                                         unsigned long long* __restrict__ out) {
+  __shared__ uint64_t red[2][1024 / kWave];
+  uint64_t a = 0, b = 0;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (lane_id() == 0) {
+    red[0][threadIdx.x / kWave] = a;
+    red[1][threadIdx.x / kWave] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 1024 / kWave; w++) {
+      a += red[0][w];
+      b += red[1][w];
+    }
+    out[0] = a;
+    out[1] = b;
+  }
 }
 
 // PageRank vertex kernels: contrib[u] = p[u] / deg[u] (0 for isolated vertices),

@@ -21,7 +21,6 @@ struct Counters {
   unsigned int root_viol;           // violation bits of the root
   unsigned int error;               // internal capacity overflow (bug guard)
   unsigned int nspill;              // segments the wave merge hands to the lane merge
-  unsigned int found;               // nonzero once a BFS step claimed a vertex
   unsigned int nwide;               // segments whose key span needs 64-bit merge keys
   unsigned long long alg_bytes;     // algorithmic HBM bytes of the merge (statistics)
   unsigned long long alg_bytes_q;   // algorithmic HBM bytes of range scans (statistics)

@@ -22,9 +22,11 @@ def graph(scale, samples, seed):
     return synth.edge_keys(s, d)
 
 
-def check_graph(c, keys_sorted, nv, orc, src=0, pagerank=True):
-    lv = c.bfs(nv, src)
-    assert np.array_equal(lv, orc.bfs(keys_sorted, nv, src))
+def check_graph(c, keys_sorted, nv, orc, src=0, pagerank=True, symmetric=True):
+    want = orc.bfs(keys_sorted, nv, src)
+    assert np.array_equal(c.bfs(nv, src), want)                    # top-down levels only
+    if symmetric:
+        assert np.array_equal(c.bfs(nv, src, symmetric=True), want)  # bottom-up where cheaper
     if not pagerank:
         return
     p32 = c.pagerank(nv, iters=10).astype(np.float64)
@@ -78,8 +80,8 @@ def test_bfs_directed_edges(cp, orc):
     s, d = synth.rmat_edges(20000, 505, scale=12)
     ks = orc.build_set(synth.edge_keys(s, d, symmetric=False))
     c = cp.CPMA(ks, leaf_bytes=256)
-    check_graph(c, ks, nv, orc, pagerank=False)
-    check_graph(c, ks, nv, orc, src=1, pagerank=False)
+    check_graph(c, ks, nv, orc, pagerank=False, symmetric=False)
+    check_graph(c, ks, nv, orc, src=1, pagerank=False, symmetric=False)
 
 
 def test_rmat_scale20(cp, orc):
