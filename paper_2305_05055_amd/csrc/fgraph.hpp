@@ -59,6 +59,25 @@ __device__ __forceinline__ uint32_t wave_leaf_keys(const uint8_t* __restrict__ s
 __device__ __forceinline__ uint32_t src_of(uint64_t k) { return (uint32_t)(k >> 32); }
 __device__ __forceinline__ uint32_t dst_of(uint64_t k) { return (uint32_t)k; }
 
+// The leaf's first source if every key of the leaf has it (a high-degree
+// vertex whose edges fill whole leaves), else UINT32_MAX.  Such leaves reduce
+// across the wave first: per-lane atomics would all hit that one vertex.
+__device__ __forceinline__ uint32_t fg_single_source(const FgArgs& g, uint64_t leaf, const uint64_t (&kk)[16],
+                                                    uint32_t tm) {
+  if (!__ballot(tm != 0)) return 0xffffffffu;  // no keys
+  const uint32_t first = src_of(g.head[leaf]);  // the head is the leaf's first key
+  bool other = false;
+#pragma unroll
+  for (int i = 0; i < 16; i++) other |= (tm & (1u << i)) && src_of(kk[i]) != first;
+  return __ballot(other) ? 0xffffffffu : first;
+}
+
+__device__ __forceinline__ float wave_sum_f32(float x) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+  return x;
+}
+
 // deg[u] += number of edges with source u.
 __global__ void __launch_bounds__(256) k_fg_degree(FgArgs g, uint32_t* __restrict__ deg) {
   const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
@@ -66,6 +85,15 @@ __global__ void __launch_bounds__(256) k_fg_degree(FgArgs g, uint32_t* __restric
        leaf += waves) {
     uint64_t kk[16];
     const uint32_t tm = wave_leaf_keys(g.bytes + leaf * (uint64_t)g.S, g.used[leaf], kk);
+    const uint32_t one = fg_single_source(g, leaf, kk, tm);
+    if (one != 0xffffffffu) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int i = 0; i < 16; i++) c += ((tm & (1u << i)) && dst_of(kk[i]) < g.nv) ? 1u : 0u;
+      c = wave_sum(c);
+      if (lane_id() == 0 && one < g.nv && c) atomicAdd(&deg[one], c);
+      continue;
+    }
     uint32_t run = 0xffffffffu, cnt = 0;
 #pragma unroll
     for (int i = 0; i < 16; i++) {
@@ -96,6 +124,15 @@ __global__ void __launch_bounds__(256) k_fg_pull(FgArgs g, const float* __restri
     for (int i = 0; i < 16; i++) {
       const uint32_t d = dst_of(kk[i]);
       val[i] = ((tm & (1u << i)) && d < g.nv) ? contrib[d] : 0.f;
+    }
+    const uint32_t one = fg_single_source(g, leaf, kk, tm);
+    if (one != 0xffffffffu) {
+      float t = 0.f;
+#pragma unroll
+      for (int i = 0; i < 16; i++) t += val[i];
+      t = wave_sum_f32(t);
+      if (lane_id() == 0 && one < g.nv) atomicAdd(&acc[one], t);
+      continue;
     }
     uint32_t run = 0xffffffffu;
     float sum = 0.f;
