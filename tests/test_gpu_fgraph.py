@@ -94,3 +94,22 @@ def test_rmat_scale20(cp, orc):
     ks = orc.build_set(dk.cpu().numpy().view(np.uint64))
     assert c.size() == len(ks)
     check_graph(c, ks, 1 << scale, orc)
+
+
+def test_rmat_scale24_benchmarked_size(cp, orc):
+    """The F-Graph benchmark's graph itself (scale 24, 2^27 samples, ~2.7e8
+    symmetric edge keys, drawn on the GPU by the same generator): BFS levels
+    from vertex 0 bit-exact in both directions, 10 FP32 PageRank iterations
+    within 1e-5 relative of the FP64 oracle."""
+    import torch
+    scale = 24
+    nv = 1 << scale
+    s, d = synth.rmat_edges_torch(1 << 27, synth.SEED_BASE + 2 + 60, scale=scale, device="cuda")
+    dk = synth.edge_keys_torch(s, d)
+    del s, d
+    c = cp.CPMA(dk)
+    ks = orc.build_set(dk.cpu().numpy().view(np.uint64))
+    del dk
+    torch.cuda.empty_cache()
+    assert c.size() == len(ks)
+    check_graph(c, ks, nv, orc)
