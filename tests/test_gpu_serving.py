@@ -74,3 +74,65 @@ def test_served_equals_alone_and_oracle(cp, orc, slots):
         code, msg = orc.check_image(*c.export(), c.geometry()[1], S)
         assert code == 0, msg
         assert c.size() == len(S)
+
+
+def test_serving_at_1e9_keys_properties(cp):
+    """The serving benchmark's set size: 1e9 uniform 40-bit keys built on the
+    GPU, then a mixed request stream through the server (inserts of fresh keys,
+    deletes of present keys and of keys inserted earlier in the stream,
+    re-inserts of deleted keys, ranges).  A replay by the oracle would sort 1e9
+    keys on the host, so the checks are properties that hold at any size: every
+    request succeeds; the set grows by exactly the added minus the removed
+    counts; the full range counts the set; and every key an update touched ends
+    present iff the last update on it was an insert."""
+    import torch
+    n = 10 ** 9
+    dk = synth.uniform_keys_torch(n, synth.SEED_BASE + 2 + 70, "cuda")
+    c = cp.CPMA(dk)
+    n0 = c.size()
+    pick = torch.from_numpy(synth.sample_indices(n, 200000, 911).astype(np.int64)).cuda()
+    present = dk[pick].cpu().numpy().view(np.uint64)
+    del dk, pick
+    torch.cuda.empty_cache()
+
+    kinds = synth.uniform_float(400, 912)
+    sizes = synth.log_uniform_sizes(400, 913, lo_exp=1.0, hi_exp=5.0)
+    reqs, inserted, deleted = [], [], []
+    for i in range(400):
+        m = int(sizes[i])
+        if kinds[i] < 0.5:
+            lo = synth.uniform_keys(4, 914 + i)
+            reqs.append(cp.ServedRequest(cp.REQ_RANGE, lo, lo + np.uint64(1 << 30)))
+        elif kinds[i] < 0.8:
+            ks = synth.uniform_keys(m, 915 + i, offset=1 << 20)
+            if deleted and i % 5 == 0:
+                ks = np.concatenate([ks, deleted[-1][: m // 2]])  # re-insert deleted keys
+            inserted.append(ks)
+            reqs.append(cp.ServedRequest(cp.REQ_INSERT, ks))
+        else:
+            j = (7 * i) % (len(present) - m)
+            ks = present[j:j + m]
+            if inserted and i % 3 == 0:
+                ks = np.concatenate([ks, inserted[-1][: m // 2]])  # delete keys inserted earlier
+            deleted.append(ks)
+            reqs.append(cp.ServedRequest(cp.REQ_DELETE, ks))
+    srv = cp.Server(c)
+    for r in reqs:
+        srv.submit(r)
+    srv.stop()
+    assert all(r.done and r.req.status == 0 for r in reqs)
+    net = sum(int(r.req.result) for r in reqs if r.kind == cp.REQ_INSERT) - \
+        sum(int(r.req.result) for r in reqs if r.kind == cp.REQ_DELETE)
+    assert c.size() == n0 + net
+    _, cnt = c.range_map(np.array([0], np.uint64), np.array([(1 << 64) - 1], np.uint64))
+    assert int(cnt[0]) == c.size()
+    # final membership of every touched key: the last update on it decides
+    # (the server applies updates in arrival order)
+    ups = [(r.keys, 1 if r.kind == cp.REQ_INSERT else 0) for r in reqs if r.kind != cp.REQ_RANGE]
+    keys = np.concatenate([k for k, _ in ups])
+    state = np.concatenate([np.full(len(k), s, np.uint8) for k, s in ups])
+    order = np.arange(len(keys))
+    srt = np.lexsort((order, keys))
+    keys, state = keys[srt], state[srt]
+    last = np.r_[keys[1:] != keys[:-1], True]
+    assert np.array_equal(c.contains(keys[last]), state[last])
