@@ -80,6 +80,17 @@ typedef enum { CPMA_MEM_HOST = 0, CPMA_MEM_DEVICE = 1 } cpma_mem;
  *                  row (a range query is a search then a scan, Section "Packed
  *                  Memory Array", "Design and operations"); a power of two in
  *                  [1, 64]; default 8.  Layout and results do not depend on it.
+ *   alloc, free, ctx
+ *                  device memory for everything the handle owns (leaves, heads,
+ *                  used counts, counters, scratch): alloc(bytes, ctx) returns a
+ *                  device pointer aligned to 256 bytes, or NULL when out of
+ *                  memory (the call then fails with CPMA_ERR_NOMEM; a pointer
+ *                  not so aligned fails it with CPMA_ERR_INVALID); free(ptr,
+ *                  ctx) releases one.  Set both or neither (CPMA_ERR_INVALID);
+ *                  NULL: hipMalloc / hipFree.  They run on the calling thread
+ *                  (the worker thread for a served set); cpma_destroy frees
+ *                  everything through them.  Pinned host staging is not
+ *                  included.
  */
 typedef struct {
   uint32_t leaf_bytes;
@@ -87,6 +98,9 @@ typedef struct {
   double up_leaf, up_root, lo_leaf, lo_root;
   double build_density;
   uint32_t range_chunk;
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
 } cpma_config;
 
 /* Fills *cfg with the defaults above.  Returns CPMA_ERR_INVALID if cfg is NULL. */

@@ -31,7 +31,8 @@ class Config(ctypes.Structure):
     _fields_ = [("leaf_bytes", ctypes.c_uint32), ("grow", ctypes.c_double),
                 ("up_leaf", ctypes.c_double), ("up_root", ctypes.c_double),
                 ("lo_leaf", ctypes.c_double), ("lo_root", ctypes.c_double),
-                ("build_density", ctypes.c_double), ("range_chunk", ctypes.c_uint32)]
+                ("build_density", ctypes.c_double), ("range_chunk", ctypes.c_uint32),
+                ("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p), ("ctx", ctypes.c_void_p)]
 
 
 class TuneHint(ctypes.Structure):

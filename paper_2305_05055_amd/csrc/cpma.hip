@@ -32,6 +32,7 @@ namespace {
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  const cpma_config* al = nullptr;  // the owner's allocator hooks (NULL hooks: hipMalloc)
   template <typename T>
   T* as() const {
     return reinterpret_cast<T*>(p);
@@ -48,30 +49,53 @@ struct Fail {
     if (_e != hipSuccess) throw Fail{CPMA_ERR_DEVICE}; \
   } while (0)
 
+// Device memory through the owner's hooks, else hipMalloc / hipFree.
+void* dev_alloc(const cpma_config* al, size_t bytes) {
+  if (al && al->alloc) {
+    void* p = al->alloc(bytes, al->ctx);
+    if (p && (reinterpret_cast<uintptr_t>(p) & 255)) {  // the hooks promise 256-byte alignment
+      al->free(p, al->ctx);
+      throw Fail{CPMA_ERR_INVALID};
+    }
+    return p;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dev_free(const cpma_config* al, void* p) {
+  if (!p) return;
+  if (al && al->free)
+    al->free(p, al->ctx);
+  else
+    hipFree(p);
+}
+
 // Grows b to at least `bytes` (contents are not kept), with `slack` extra room.
 void ensure(DevBuf& b, size_t bytes, double slack = 1.0) {
   if (bytes == 0) bytes = 16;
   if (b.cap >= bytes) return;
   if (b.p) {
-    hipFree(b.p);
+    dev_free(b.al, b.p);
     b.p = nullptr;
     b.cap = 0;
   }
   size_t want = bytes + (size_t)((double)bytes * slack) + 256;
-  if (hipMalloc(&b.p, want) != hipSuccess) {
-    hipGetLastError();
-    if (hipMalloc(&b.p, bytes) != hipSuccess) {
-      hipGetLastError();
-      b.p = nullptr;
-      throw Fail{CPMA_ERR_NOMEM};
-    }
+  b.p = dev_alloc(b.al, want);
+  if (!b.p) {
+    b.p = dev_alloc(b.al, bytes);
+    if (!b.p) throw Fail{CPMA_ERR_NOMEM};
     want = bytes;
   }
   b.cap = want;
 }
 
 void release(DevBuf& b) {
-  if (b.p) hipFree(b.p);
+  dev_free(b.al, b.p);
   b.p = nullptr;
   b.cap = 0;
 }
@@ -103,7 +127,8 @@ struct cpma {
       stage, pyr, win, wargs, cnt, koff, win_id, welem, P, ccost, ncost, lstart, planU, plan_used,
       spare_bytes, spare_used, spare_head, fg_level, fg_deg, fg_p, fg_c, fg_acc,
       win_of_leaf, fail, qa, qb, qfirst, qnvis, qvoff, qsum, qcount, qout, lastk, ne_rank, ne_list, chain_pfx,
-      srec, wide, srcinfo, parts, qparts, fz_meta, fz_v0, fz_v1, fz_byte, fz_member, fz_code, fz_ctr, fz_res;
+      srec, wide, srcinfo, parts, qparts, fz_meta, fz_v0, fz_v1, fz_byte, fz_member, fz_code, fz_ctr, fz_res,
+      ctr_buf, info_buf, qalg_buf;
   Counters* dctr = nullptr;
   Counters* hctr = nullptr;
   BatchInfo* dinfo = nullptr;
@@ -122,6 +147,19 @@ struct cpma {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> evpool;
   unsigned long long* dqalg = nullptr;  // range-scan byte counter
+
+  // every device buffer the handle owns (allocator hooks, release)
+  std::vector<DevBuf*> bufs() {
+    return {&bytes,     &used,      &head,      &kin,         &kb0,        &kb1,         &kdedup,     &leafid,
+            &segpos,    &seg_leaf,  &seg_begin, &seg_desc,    &heavy,      &spill,       &scan_tmp,   &ovf,
+            &arena,     &stage,     &pyr,       &win,         &wargs,      &cnt,         &koff,       &win_id,
+            &welem,     &P,         &ccost,     &ncost,       &lstart,     &planU,       &plan_used,  &spare_bytes,
+            &spare_used, &spare_head, &fg_level, &fg_deg,     &fg_p,       &fg_c,        &fg_acc,     &win_of_leaf,
+            &fail,      &qa,        &qb,        &qfirst,      &qnvis,      &qvoff,       &qsum,       &qcount,
+            &qout,      &lastk,     &ne_rank,   &ne_list,     &chain_pfx,  &srec,        &wide,       &srcinfo,
+            &parts,     &qparts,    &fz_meta,   &fz_v0,       &fz_v1,      &fz_byte,     &fz_member,  &fz_code,
+            &fz_ctr,    &fz_res,    &ctr_buf,   &info_buf,    &qalg_buf};
+  }
 
   Bounds bounds(uint64_t Lx) const {
     Bounds b;
@@ -968,6 +1006,7 @@ uint64_t apply_sorted(cpma* s, const uint64_t* B, uint64_t k, bool insert, hipSt
 cpma_status check_config(const cpma_config& c) {
   if (c.leaf_bytes < 64 || c.leaf_bytes > 4096 || (c.leaf_bytes & (c.leaf_bytes - 1))) return CPMA_ERR_INVALID;
   if (c.range_chunk < 1 || c.range_chunk > 64 || (c.range_chunk & (c.range_chunk - 1))) return CPMA_ERR_INVALID;
+  if (!c.alloc != !c.free) return CPMA_ERR_INVALID;  // both hooks or neither
   if (!(c.grow > 1.0 && c.grow <= 4.0)) return CPMA_ERR_INVALID;
   if (!(c.lo_leaf > 0 && c.lo_leaf <= c.lo_root && c.lo_root < c.up_root && c.up_root <= c.up_leaf &&
         c.up_leaf < 1.0))
@@ -1005,6 +1044,9 @@ cpma_status cpma_config_default(cpma_config* cfg) {
   cfg->lo_root = 0.30;
   cfg->build_density = cfg->up_root / cfg->grow;
   cfg->range_chunk = 8;
+  cfg->alloc = nullptr;
+  cfg->free = nullptr;
+  cfg->ctx = nullptr;
   return CPMA_OK;
 }
 
@@ -1035,11 +1077,15 @@ cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpm
     if (cfg_in->lo_root > 0) cfg.lo_root = cfg_in->lo_root;
     cfg.build_density = cfg_in->build_density > 0 ? cfg_in->build_density : cfg.up_root / cfg.grow;
     if (cfg_in->range_chunk) cfg.range_chunk = cfg_in->range_chunk;
+    cfg.alloc = cfg_in->alloc;
+    cfg.free = cfg_in->free;
+    cfg.ctx = cfg_in->ctx;
   }
   cpma_status cs = check_config(cfg);
   if (cs != CPMA_OK) return cs;
   cpma* s = new cpma();
   s->cfg = cfg;
+  for (DevBuf* b : s->bufs()) b->al = &s->cfg;
   s->S = cfg.leaf_bytes;
   s->q_up_leaf = llround(cfg.up_leaf * (double)kQ);
   s->q_up_root = llround(cfg.up_root * (double)kQ);
@@ -1051,9 +1097,11 @@ cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpm
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, s->device));
     s->num_cus = prop.multiProcessorCount;
-    HIPCHK(hipMalloc(&s->dctr, sizeof(Counters)));
+    ensure(s->ctr_buf, sizeof(Counters), 0.0);
+    s->dctr = s->ctr_buf.as<Counters>();
     HIPCHK(hipHostMalloc(&s->hctr, sizeof(Counters), hipHostMallocDefault));
-    HIPCHK(hipMalloc(&s->dinfo, sizeof(BatchInfo)));
+    ensure(s->info_buf, sizeof(BatchInfo), 0.0);
+    s->dinfo = s->info_buf.as<BatchInfo>();
     HIPCHK(hipHostMalloc(&s->hinfo, sizeof(BatchInfo), hipHostMallocDefault));
     zero_counters(s, st);
     uint64_t K = 0;
@@ -1577,7 +1625,8 @@ cpma_status cpma_stats_enable(cpma* s, int on) {
     HIPCHK(hipDeviceSynchronize());
     resolve_phases(s);
     if (on) {
-      if (!s->dqalg) HIPCHK(hipMalloc(&s->dqalg, sizeof(unsigned long long)));
+      ensure(s->qalg_buf, sizeof(unsigned long long), 0.0);
+      s->dqalg = s->qalg_buf.as<unsigned long long>();
       HIPCHK(hipMemset(s->dqalg, 0, sizeof(unsigned long long)));
       HIPCHK(hipDeviceSynchronize());
       memset(s->stats, 0, sizeof(s->stats));
@@ -1612,19 +1661,7 @@ void cpma_destroy(cpma* s) {
     hipEventDestroy(p.b);
   }
   for (hipEvent_t e : s->evpool) hipEventDestroy(e);
-  if (s->dqalg) hipFree(s->dqalg);
-  DevBuf* bufs[] = {&s->bytes,  &s->used,     &s->head,      &s->kin,       &s->kb0,   &s->kb1,    &s->kdedup,
-                    &s->leafid, &s->segpos,   &s->seg_leaf,  &s->seg_begin, &s->seg_desc, &s->heavy, &s->spill, &s->scan_tmp,
-                    &s->ovf,    &s->arena,    &s->stage,     &s->pyr,       &s->win,   &s->wargs,  &s->cnt,
-                    &s->koff,   &s->win_id,   &s->welem,     &s->P,         &s->ccost, &s->ncost, &s->spare_bytes, &s->spare_used, &s->spare_head,
-                    &s->fg_level, &s->fg_deg, &s->fg_p, &s->fg_c, &s->fg_acc, &s->lstart, &s->planU,
-                    &s->plan_used, &s->win_of_leaf, &s->fail, &s->qa,        &s->qb,    &s->qfirst, &s->qnvis,
-                    &s->qvoff,  &s->qsum,     &s->qcount,    &s->qout,  &s->lastk, &s->ne_rank, &s->ne_list,
-                    &s->chain_pfx, &s->srec, &s->wide, &s->srcinfo, &s->parts, &s->qparts, &s->fz_meta, &s->fz_v0, &s->fz_v1,
-                    &s->fz_byte, &s->fz_member, &s->fz_code, &s->fz_ctr, &s->fz_res};
-  for (DevBuf* b : bufs) release(*b);
-  if (s->dctr) hipFree(s->dctr);
-  if (s->dinfo) hipFree(s->dinfo);
+  for (DevBuf* b : s->bufs()) release(*b);
   if (s->hctr) hipHostFree(s->hctr);
   if (s->hinfo) hipHostFree(s->hinfo);
   if (s->hpin) hipHostFree(s->hpin);

@@ -95,13 +95,15 @@ def test_struct_layouts_match_the_header(tmp_path):
     prog = tmp_path / "sizes.c"
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "cpma.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(cpma_config),"
-        " offsetof(cpma_config, range_chunk), sizeof(cpma_tune_hint), sizeof(cpma_tune_report),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(cpma_config),"
+        " offsetof(cpma_config, range_chunk), offsetof(cpma_config, alloc), offsetof(cpma_config, ctx),"
+        " sizeof(cpma_tune_hint), sizeof(cpma_tune_report),"
         " offsetof(cpma_tune_report, best_chunk), sizeof(cpma_request), sizeof(cpma_phase_stat));return 0;}\n")
     exe = tmp_path / "sizes"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
-    want = [ctypes.sizeof(p.Config), p.Config.range_chunk.offset, ctypes.sizeof(p.TuneHint),
+    want = [ctypes.sizeof(p.Config), p.Config.range_chunk.offset, p.Config.alloc.offset, p.Config.ctx.offset,
+            ctypes.sizeof(p.TuneHint),
             ctypes.sizeof(p.TuneReport), p.TuneReport.best_chunk.offset, ctypes.sizeof(p.Request),
             ctypes.sizeof(p.PhaseStat)]
     assert got == want
@@ -120,5 +122,8 @@ def test_config_defaults_and_checks_without_gpu():
         bad = p.Config()
         bad.leaf_bytes, bad.range_chunk = S, chunk
         assert L.cpma_build(None, 0, 0, ctypes.byref(bad), None, ctypes.byref(h)) == 1
+    one_hook = p.Config()
+    one_hook.alloc = 1  # an allocator without a matching free
+    assert L.cpma_build(None, 0, 0, ctypes.byref(one_hook), None, ctypes.byref(h)) == 1
     out = p.Config()
     assert L.cpma_autotune(None, 0, 0, None, None, None, ctypes.byref(out), None) == 1

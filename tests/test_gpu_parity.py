@@ -228,3 +228,54 @@ def test_device_tensors(cp, orc):
     got = c.contains(q).cpu().numpy()
     assert np.array_equal(got, orc.contains(expect, q.cpu().numpy().view(np.uint64)))
     check(c, expect, orc)
+
+
+def test_allocator_hooks(cp, orc):
+    """cpma_config.alloc / free: every device buffer of the handle comes from the
+    hooks and goes back at destroy; an allocator that runs out makes the build
+    fail with CPMA_ERR_NOMEM and returns what it had taken."""
+    import ctypes
+    import torch
+    ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+    FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+    live, budget = {}, [None]
+
+    def _alloc(n, ctx):
+        if budget[0] is not None and sum(live.values()) + n > budget[0]:
+            return None
+        p = torch.cuda.caching_allocator_alloc(n)
+        live[p] = n
+        return p
+
+    def _free(p, ctx):
+        live.pop(p)
+        torch.cuda.caching_allocator_delete(p)
+
+    a_cb, f_cb = ALLOC(_alloc), FREE(_free)
+    cfg = cp.default_config()
+    cfg.leaf_bytes = 256
+    cfg.alloc = ctypes.cast(a_cb, ctypes.c_void_p).value
+    cfg.free = ctypes.cast(f_cb, ctypes.c_void_p).value
+    keys = synth.uniform_keys(100000, 71, bits=40)
+    expect = orc.build_set(keys)
+    c = cp.CPMA(keys, config=cfg)
+    assert live
+    for b in range(3):  # grows the array several times
+        batch = synth.uniform_keys(100000, 72 + b, bits=40)
+        expect, added = orc.insert(expect, batch)
+        assert c.insert_batch(batch) == added
+    dels = expect[synth.sample_indices(len(expect), 50000, 75)]
+    expect, removed = orc.delete(expect, dels)
+    assert c.delete_batch(dels) == removed
+    check(c, expect, orc)
+    lo, hi = synth.range_queries_width(1000, 76, 1 << 30)
+    s, n = c.range_map(lo, hi)
+    es, en = orc.range_map(expect, lo, hi)
+    assert np.array_equal(n, en) and np.array_equal(s, es)
+    c.close()
+    assert not live
+    budget[0] = 1 << 20  # far below what 1e5 keys need
+    with pytest.raises(cp.CpmaError) as e:
+        cp.CPMA(keys, config=cfg)
+    assert e.value.code == 2
+    assert not live
