@@ -215,9 +215,38 @@ def range_section(cp, torch, c, base_dev, q, seed):
     out["one_launch_per_query_s_per_query"] = per_q
     out["batched_speedup_on_prefix"] = (per_q * m) / (time.perf_counter() - t0)
     out["batched_speedup_extrapolated"] = (per_q * q) / (res["ms_per_pass"] * 1e-3)
+    # a small batch (64 of the queries of at most 8 keys, so launches rather
+    # than scanning set the time) back to back: eager calls against replays of
+    # the same call captured once in a HIP graph
+    short = torch.from_numpy(np.flatnonzero(lens <= 8)[:64]).cuda()
+    slo, shi = dlo[short].clone(), dhi[short].clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        tuned.range_map(slo, shi)  # sizes the scratch buffers before capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        tuned.range_map(slo, shi)
+    reps = 500
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        tuned.range_map(slo, shi)
+    torch.cuda.synchronize()
+    out["small_batch_64_eager_us"] = (time.perf_counter() - t0) / reps * 1e6
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        graph.replay()
+    torch.cuda.synchronize()
+    out["small_batch_64_graph_us"] = (time.perf_counter() - t0) / reps * 1e6
+    del graph
     tuned.close()
     log(f"range_map: default {out['default']['keys_per_s']:.3e} keys/s, autotuned (S={res['leaf_bytes']}, "
-        f"chunk={res['range_chunk']}) {res['keys_per_s']:.3e} keys/s, scan {res['scan_alg_GBps']:.0f} GB/s alg")
+        f"chunk={res['range_chunk']}) {res['keys_per_s']:.3e} keys/s, scan {res['scan_alg_GBps']:.0f} GB/s alg; "
+        f"64 short queries {out['small_batch_64_eager_us']:.1f} us eager, {out['small_batch_64_graph_us']:.1f} us "
+        f"from a HIP graph")
     return out
 
 
