@@ -39,14 +39,23 @@ def log(*a):
 MERGE_KERNEL = "k_merge_wave<unsigned int>"
 MERGE_SOURCES = ["common.hpp", "leaf.hpp", "update.hpp", "merge_wave.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_merge_wave_traffic_insert_batch1e7_n1e8.md")
+VALU_FILE = os.path.join(ROOT, "profiles", "k_merge_wave_valu_insert_batch1e7_n1e8.md")
+# VALU issue peak: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD every
+# 4 cycles (16 lanes), 2.4 GHz peak engine clock
+VALU_PEAK_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
 
 
-def merge_source_hash():
-    """Hash of the sources that define the main merge kernel: traffic measured on
-    another version of it is not reported."""
+SCAN_KERNEL = "k_rm_interior"
+SCAN_SOURCES = ["common.hpp", "scan_lane.hpp", "query.hpp"]
+SCAN_VALU_FILE = os.path.join(ROOT, "profiles", "k_rm_interior_valu_gate_n1e9.md")
+
+
+def merge_source_hash(sources=None):
+    """Hash of the sources that define a kernel (default: the main merge kernel):
+    counters taken on another version of it are not reported."""
     import hashlib
     h = hashlib.sha256()
-    for f in MERGE_SOURCES:
+    for f in (sources or MERGE_SOURCES):
         with open(os.path.join(ROOT, "paper_2305_05055_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -97,6 +106,49 @@ def pmc_summary(fetch_csv, write_csv, steps, cmd_fetch, cmd_write):
               "when the counters were taken):", "", "```",
               f"traffic_bytes_per_launch={total:.6e}", f"source={merge_source_hash()}", "```", ""]
     return "\n".join(lines)
+
+
+def valu_summary(csv_path, kernel, pick, title, what, cmd, sources):
+    """VALU (and LDS, SALU) instructions and waves per launch of `kernel` from one
+    rocprofv3 --pmc run; pick(list) selects the launches to average."""
+    ctrs = ("SQ_INSTS_VALU", "SQ_WAVES", "SQ_INSTS_LDS", "SQ_INSTS_SALU")
+    rows = pmc_rows(csv_path)
+    avg = {}
+    for ctr in ctrs:
+        timed = pick([v for _, n, c, v in rows if n == kernel and c == ctr])
+        avg[ctr] = sum(timed) / len(timed)
+        nl = len(timed)
+    lines = [
+        f"# {kernel}: instructions per launch, {title}", "",
+        f"One counter run of {what} (from the repository root, after "
+        "`cd /tmp && export TMPDIR=/tmp`):", "", "```", cmd, "```", "",
+        "Counts are chip totals per dispatch (SQ_WAVES equals the launched waves).  A wave64 VALU "
+        "instruction occupies its SIMD for 4 cycles, so the VALU issue peak is 256 CUs x 4 SIMDs x "
+        "2.4 GHz / 4 = 6.1e11 wave instructions/s; bench.py divides the per-launch count by the "
+        "launch time it measures.", "",
+        "| counter | per timed launch |", "|---|---|"]
+    for ctr in ctrs:
+        lines.append(f"| {ctr} | {avg[ctr]:.4e} |")
+    lines += ["", f"Launches averaged: {nl}.", "",
+              "Machine-readable (read by bench.py; `source` is the hash of the kernel's sources "
+              "when the counters were taken):", "", "```",
+              f"valu_insts_per_launch={avg['SQ_INSTS_VALU']:.6e}", f"waves_per_launch={avg['SQ_WAVES']:.6e}",
+              f"source={merge_source_hash(sources)}", "```", ""]
+    return "\n".join(lines)
+
+
+def kernel_valu(path=None, sources=None):
+    """VALU instructions per launch from a committed counter summary (default:
+    the merge kernel's), or None when it is missing or was taken on other
+    kernel sources."""
+    try:
+        with open(path or VALU_FILE) as fh:
+            kv = dict(l.strip().split("=", 1) for l in fh if "=" in l and not l.startswith("|"))
+    except OSError:
+        return None
+    if kv.get("source") != merge_source_hash(sources):
+        return None
+    return float(kv["valu_insts_per_launch"])
 
 
 def merge_traffic():
@@ -262,6 +314,10 @@ def gate_section(cp, torch, c, n0, seed):
     res = time_range(torch, c, to_dev(lo), to_dev(hi))
     res["n0"] = c.size()
     res["queries"] = "1e3 of ~1e6 keys + 1 full range"
+    # what bounds the scan instead of HBM: VALU issue (counted instructions per
+    # launch over the launch time, against the issue peak)
+    valu = kernel_valu(SCAN_VALU_FILE, SCAN_SOURCES)
+    res["valu_issue_frac"] = valu / (res["scan_kernel_ms"] * 1e-3) / VALU_PEAK_INSTS_PER_S if valu else None
     log(f"range gate: {res['keys_per_s']:.3e} keys/s, scan {res['scan_alg_GBps']:.0f} GB/s "
         f"({100 * res['frac_hbm_alg']:.1f}% of HBM peak)")
     return res
@@ -348,8 +404,31 @@ def main():
     ap.add_argument("--sweep-only", action="store_true", help="run only the batch-size sweep (diagnostics)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the merge kernel's traffic summary from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--valu-summary", metavar="CSV",
+                    help="write the merge kernel's instruction summary from one rocprofv3 --pmc run and exit")
+    ap.add_argument("--scan-valu-summary", metavar="CSV",
+                    help="write the range scan kernel's instruction summary from a --pmc run of --gate-only")
     args = ap.parse_args()
 
+    if args.valu_summary or args.scan_valu_summary:
+        ctr = "rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES SQ_INSTS_LDS SQ_INSTS_SALU --output-format csv "
+        if args.valu_summary:
+            cmd = (ctr + "-d /root/repo/gpurun_out/pmc_valu -o run -- python3 /root/repo/bench.py --only-steps "
+                   f"--no-cpu-baseline --steps {args.steps}")
+            text = valu_summary(args.valu_summary, MERGE_KERNEL, lambda v: v[-(args.steps + 2):-2],
+                                "insert batches of 1e7 into 1e8 keys", "the headline steps (the run ends "
+                                "with two delete batches, which are left out)", cmd, MERGE_SOURCES)
+            path = VALU_FILE
+        else:
+            cmd = ctr + "-d /root/repo/gpurun_out/pmc_scan -o run -- python3 /root/repo/bench.py --gate-only"
+            text = valu_summary(args.scan_valu_summary, SCAN_KERNEL, lambda v: v[-3:],
+                                "the cold range gate on 1e9 keys", "the cold range gate (its last three "
+                                "timed passes)", cmd, SCAN_SOURCES)
+            path = SCAN_VALU_FILE
+        with open(path, "w") as fh:
+            fh.write(text)
+        print(text)
+        return
     if args.pmc_summary:
         base = "rocprofv3 --pmc {c} --output-format csv -d /root/repo/gpurun_out/pmc_{t} -o run -- " \
                f"python3 /root/repo/bench.py --only-steps --no-cpu-baseline --calibrate-copy --steps {args.steps}"
@@ -502,6 +581,10 @@ def main():
                 "frac": ach / HBM_PEAK_GBS, "traffic": merge_traffic(),
                 "alg_bytes_per_launch": mg_b / mg_l, "avg_launch_ms": mg_ms / mg_l,
                 "dominant_phase": dominant}
+        # what bounds it instead: VALU issue (counted instructions per launch over
+        # the launch time, against the issue peak)
+        valu = kernel_valu()
+        roof["valu_issue_frac"] = (valu / ((mg_ms / mg_l) * 1e-3) / VALU_PEAK_INSTS_PER_S) if valu else None
 
     # delete throughput at the headline batch size (present keys from the base set)
     dsel = synth.sample_indices(len(base_all), 2 * k, seed + 50)
