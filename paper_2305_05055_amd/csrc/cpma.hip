@@ -930,7 +930,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
     // every segment in one 64-bit wave pass; long insert slices in the lane merge
     a.part = slots(wgrid, false);
     hipLaunchKernelGGL(k_merge_wave<uint64_t>, dim3(wgrid), dim3(kWave), 0, st, a, 1);
-    if (insert) {
+    if (insert && kbound > kWaveSlice) {  // a slice of more than kWaveSlice keys spills
       a.part = slots(lwaves, false);
       hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 1);
     }
@@ -974,8 +974,8 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
 }
 
 // Batch of k <= kSmallBatch keys at device address src (any order, repeats
-// allowed): one launch prepares it (sort, repeats, leaves, segments), then the
-// merge and rebalance phases run.  Counters must be zero.
+// allowed): one launch zeroes the counters and prepares it (sort, repeats,
+// leaves, segments), then the merge and rebalance phases run.
 uint64_t apply_small(cpma* s, const uint64_t* src, uint64_t k, bool insert, hipStream_t st) {
   ensure(s->kdedup, k * sizeof(uint64_t));
   ensure(s->seg_leaf, k * sizeof(uint32_t));
@@ -995,8 +995,8 @@ uint64_t apply_small(cpma* s, const uint64_t* src, uint64_t k, bool insert, hipS
 
 // Sorted repeat-free batch of k keys at device address B.  Zeroes the counters.
 uint64_t apply_sorted(cpma* s, const uint64_t* B, uint64_t k, bool insert, hipStream_t st) {
-  zero_counters(s, st);
   if (k <= kSmallBatch) return apply_small(s, B, k, insert, st);
+  zero_counters(s, st);
   hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(64), 0, st, &s->dctr->kprime, (uint64_t)1,
                      (unsigned long long)k);
   HIPCHK(hipGetLastError());
@@ -1150,7 +1150,6 @@ static cpma_status update(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem me
   uint64_t delta = 0;
   cpma_status r = guarded(s, [&] {
     HIPCHK(hipSetDevice(s->device));
-    zero_counters(s, st);
     if (k <= kSmallBatch) {
       const uint64_t* src = keys;
       if (mem == CPMA_MEM_HOST) {
@@ -1160,6 +1159,7 @@ static cpma_status update(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem me
       }
       delta = apply_small(s, src, k, insert, st);
     } else {
+      zero_counters(s, st);
       const uint64_t* B = prepare_batch(s, keys, k, mem, st);
       delta = apply_batch(s, B, k, insert, st);
     }

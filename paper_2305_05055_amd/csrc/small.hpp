@@ -1,10 +1,12 @@
 // Small batches (at most kSmallBatch keys): one workgroup does the whole batch
 // preparation that large batches spread over some thirty launches -- the
 // reserved-key check, a bitonic sort in LDS, removal of repeats, the leaf of
-// every key (binary search on the heads), the touched-leaf segments and their
-// routing -- so a small update is bound by a handful of launches instead of
-// dozens.
+// every key (binary search on the heads; a 64-ary search by a whole wave when
+// there are few keys), the touched-leaf segments and their routing -- so a
+// small update is bound by a handful of launches instead of dozens.  It also
+// zeroes the update's counters (it is the update's first kernel).
 #pragma once
+#include "query.hpp"
 #include "update.hpp"
 
 namespace cpma_dev {
@@ -50,6 +52,8 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __
   uint32_t n = 1;
   while (n < k) n <<= 1;
   if (tid == 0) bad = 0;
+  for (uint32_t i = tid; i < (uint32_t)(sizeof(Counters) / 4); i += kSmallThreads)
+    reinterpret_cast<uint32_t*>(ctr)[i] = 0u;
   __syncthreads();
   for (uint32_t i = tid; i < n; i += kSmallThreads) {
     const uint64_t x = i < k ? in[i] : kNoKey;  // padding sorts last
@@ -103,16 +107,27 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __
     pos += first ? 1u : 0u;
   }
   __syncthreads();
-  // unique keys back to A[0, kp) and to B; their leaves to LF
+  // unique keys back to A[0, kp) and to B; their leaves to LF: one binary
+  // search per key, or with few keys one 64-ary wave search per key (a few
+  // dependent steps instead of ~log2 L)
+  constexpr uint32_t kWaves = kSmallThreads / kWave;
+  const bool by_wave = kp <= 2 * kWaves;
 #pragma unroll
   for (uint32_t q = 0; q < kPer; q++) {
     if (mypos[q] != ~0u) {
       A[mypos[q]] = mykeys[q];
       B[mypos[q]] = mykeys[q];
-      LF[mypos[q]] = (uint32_t)locate_leaf(head, L, mykeys[q]);
+      if (!by_wave) LF[mypos[q]] = (uint32_t)locate_leaf(head, L, mykeys[q]);
     }
   }
   __syncthreads();
+  if (by_wave) {
+    for (uint32_t i = tid / kWave; i < kp; i += kWaves) {
+      const uint32_t lf = (uint32_t)wave_locate_leaf(head, L, A[i]);
+      if (lane_id() == 0) LF[i] = lf;
+    }
+    __syncthreads();
+  }
   // segments: runs of equal leaf ids
   uint32_t starts = 0;
 #pragma unroll
