@@ -413,14 +413,14 @@ def main():
     if args.valu_summary or args.scan_valu_summary:
         ctr = "rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES SQ_INSTS_LDS SQ_INSTS_SALU --output-format csv "
         if args.valu_summary:
-            cmd = (ctr + "-d /root/repo/gpurun_out/pmc_valu -o run -- python3 /root/repo/bench.py --only-steps "
+            cmd = (ctr + "-d /tmp/cpma_prof/pmc_valu -o run -- python3 /root/repo/bench.py --only-steps "
                    f"--no-cpu-baseline --steps {args.steps}")
             text = valu_summary(args.valu_summary, MERGE_KERNEL, lambda v: v[-(args.steps + 2):-2],
                                 "insert batches of 1e7 into 1e8 keys", "the headline steps (the run ends "
                                 "with two delete batches, which are left out)", cmd, MERGE_SOURCES)
             path = VALU_FILE
         else:
-            cmd = ctr + "-d /root/repo/gpurun_out/pmc_scan -o run -- python3 /root/repo/bench.py --gate-only"
+            cmd = ctr + "-d /tmp/cpma_prof/pmc_scan -o run -- python3 /root/repo/bench.py --gate-only"
             text = valu_summary(args.scan_valu_summary, SCAN_KERNEL, lambda v: v[-3:],
                                 "the cold range gate on 1e9 keys", "the cold range gate (its last three "
                                 "timed passes)", cmd, SCAN_SOURCES)
@@ -430,7 +430,7 @@ def main():
         print(text)
         return
     if args.pmc_summary:
-        base = "rocprofv3 --pmc {c} --output-format csv -d /root/repo/gpurun_out/pmc_{t} -o run -- " \
+        base = "rocprofv3 --pmc {c} --output-format csv -d /tmp/cpma_prof/pmc_{t} -o run -- " \
                f"python3 /root/repo/bench.py --only-steps --no-cpu-baseline --calibrate-copy --steps {args.steps}"
         text = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.steps,
                            base.format(c="FETCH_SIZE", t="fetch"), base.format(c="WRITE_SIZE", t="write"))

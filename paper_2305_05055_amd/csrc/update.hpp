@@ -11,7 +11,6 @@ namespace cpma_dev {
 // Device-side counters of one update, read back by the host at its sync points.
 struct Counters {
   unsigned long long delta;         // keys added (insert) or removed (delete)
-  unsigned long long arena_cursor;  // unused (arena regions are fixed per segment)
   unsigned long long stage_cursor;  // keys used in the staging buffer by heavy merges
   unsigned long long kprime;        // batch size after removing repeats
   unsigned long long T;             // touched leaves (segments)
