@@ -27,8 +27,8 @@
  *     outputs written to device memory are complete when the stream reaches
  *     the point after the call.
  *   - Ownership: the handle owns all device memory it allocates (leaves,
- *     heads, used counts, scratch); cpma_destroy frees it.  Caller buffers are
- *     never retained.
+ *     heads, used counts, scratch), through cpma_config's allocator hooks when
+ *     they are set; cpma_destroy frees it.  Caller buffers are never retained.
  *   - Concurrency: one writer per handle (the paper phases updates and queries,
  *     Section "Evaluation on graph workloads", F-Graph description).  Queries
  *     may run concurrently with each other on one stream, never with an
