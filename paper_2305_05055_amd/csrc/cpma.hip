@@ -967,7 +967,8 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
       phase_end(s, ph, st);
     }
   }
-  hipLaunchKernelGGL(k_fold_parts, dim3(1), dim3(1024), 0, st, (const unsigned long long*)parts, n_narrow, n_wide,
+  hipLaunchKernelGGL(k_fold_parts, dim3(grid_for(n_narrow + n_wide, 1024, 32)), dim3(1024), 0, st,
+                     (const unsigned long long*)parts, n_narrow, n_wide,
                      s->dctr);
   HIPCHK(hipGetLastError());
   return rebalance(s, st, insert ? 1 : 0);

@@ -216,11 +216,12 @@ __device__ __forceinline__ uint64_t arena_region(const MergeArgs& a, uint64_t s)
 
 // Sums the per-wave parts of the merge launches into the counters: the first
 // n_narrow pairs count as main-merge bytes, the next n_wide as follow-up bytes.
+// A few blocks, each adding its partial sums with three atomics.
 __global__ void __launch_bounds__(1024) k_fold_parts(const unsigned long long* __restrict__ part,
                                                      uint32_t n_narrow, uint32_t n_wide, Counters* ctr) {
   __shared__ uint64_t red[3][1024 / kWave];
   uint64_t d = 0, an = 0, aw = 0;
-  for (uint32_t w = threadIdx.x; w < n_narrow + n_wide; w += blockDim.x) {
+  for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < n_narrow + n_wide; w += gridDim.x * blockDim.x) {
     d += part[2 * w];
     if (w < n_narrow)
       an += part[2 * w + 1];
