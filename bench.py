@@ -243,10 +243,22 @@ def range_section(cp, torch, c, base_dev, q, seed):
     keys_sorted = torch.unique(base_dev).cpu().numpy().view(np.uint64)
     lens = synth.zipf_lengths(q, seed, alpha=1.2, lmax=10 ** 6)
     lo, hi = synth.range_queries_by_count(keys_sorted, lens, seed + 1)
+    # membership: 1e6 keys, half drawn from the set and half fresh
+    probe = np.concatenate([keys_sorted[synth.sample_indices(len(keys_sorted), 500000, seed + 2)],
+                            synth.uniform_keys(500000, seed + 3)])
     del keys_sorted
     dlo, dhi = to_dev(lo), to_dev(hi)
     out = {"queries": q, "lengths": "Zipf(1.2) on 1..1e6 keys, exact counts",
            "default": time_range(torch, c, dlo, dhi)}
+    dprobe = to_dev(probe)
+    c.contains(dprobe)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        hit = c.contains(dprobe)
+    torch.cuda.synchronize()
+    out["contains_1e6_per_s"] = 5 * len(probe) / (time.perf_counter() - t0)
+    out["contains_hits"] = int(hit.sum().item())
     cfg, rep = cp.autotune(base_dev, insert_weight=0.0, range_keys=int(lens.mean()), queries=100_000)
     out["autotune"] = rep
     tuned = cp.CPMA(base_dev, config=cfg)
@@ -298,7 +310,7 @@ def range_section(cp, torch, c, base_dev, q, seed):
     log(f"range_map: default {out['default']['keys_per_s']:.3e} keys/s, autotuned (S={res['leaf_bytes']}, "
         f"chunk={res['range_chunk']}) {res['keys_per_s']:.3e} keys/s, scan {res['scan_alg_GBps']:.0f} GB/s alg; "
         f"64 short queries {out['small_batch_64_eager_us']:.1f} us eager, {out['small_batch_64_graph_us']:.1f} us "
-        f"from a HIP graph")
+        f"from a HIP graph; contains {out['contains_1e6_per_s']:.3e} keys/s")
     return out
 
 
