@@ -329,12 +329,18 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
     sorted = in;
     passes_done = passes;
   }
-  ensure(s->segpos, (k + 1) * sizeof(uint32_t));
   ensure(s->kdedup, k * sizeof(uint64_t));
-  scan<uint32_t>(s, s->segpos.as<uint32_t>(), k, st, FirstFlag{sorted});
-  hipLaunchKernelGGL(k_compact_unique, dim3(grid_for(k, 256)), dim3(256), 0, st, sorted, k,
-                     (const uint32_t*)s->segpos.as<uint32_t>(), s->kdedup.as<uint64_t>(), &s->dctr->kprime);
-  HIPCHK(hipGetLastError());
+  {
+    const uint32_t nt = (uint32_t)std::max<uint64_t>(1, (k + kSortTile - 1) / kSortTile);
+    ensure(s->cnt, ((uint64_t)nt + 1) * sizeof(uint32_t));
+    ensure(s->koff, ((uint64_t)nt + 1) * sizeof(uint32_t));
+    hipLaunchKernelGGL(k_unique_count, dim3(nt), dim3(kSortThreads), 0, st, sorted, k, s->cnt.as<uint32_t>());
+    HIPCHK(hipGetLastError());
+    scan<uint32_t>(s, s->koff.as<uint32_t>(), nt, st, LoadFn<uint32_t>{s->cnt.as<uint32_t>()});
+    hipLaunchKernelGGL(k_unique_write, dim3(nt), dim3(kSortThreads), 0, st, sorted, k,
+                       (const uint32_t*)s->koff.as<uint32_t>(), nt, s->kdedup.as<uint64_t>(), &s->dctr->kprime);
+    HIPCHK(hipGetLastError());
+  }
   phase_end(s, pm, st, 24ull * k * (uint64_t)(passes_done + 1));
   return s->kdedup.as<uint64_t>();
 }
@@ -671,7 +677,7 @@ bool split_resize(cpma* s, uint64_t Lt, uint64_t total_used, hipStream_t st, uin
   a.L = L;
   scan<uint64_t>(s, s->chain_pfx.as<uint64_t>(), L, st, ChainFn{sl.used, a.head, a.lastk, a.rank, a.ne});
   ensure(s->srcinfo, std::max<uint64_t>(L, 1) * sizeof(SrcInfo));
-  hipLaunchKernelGGL(k_src_info, dim3(grid_for(L, 256, 1u << 16)), dim3(256), 0, st, sl.used, a.head, a.lastk,
+  hipLaunchKernelGGL(k_src_info, dim3(grid_for(L, 256, 1u << 16)), dim3(256), 0, st, sl, a.head, a.lastk,
                      a.rank, a.ne, L, s->srcinfo.as<SrcInfo>());
   HIPCHK(hipGetLastError());
   a.info = s->srcinfo.as<SrcInfo>();
@@ -709,7 +715,8 @@ bool split_resize(cpma* s, uint64_t Lt, uint64_t total_used, hipStream_t st, uin
       ensure(s->spare_bytes, Lt * (uint64_t)s->S, room);
       ensure(s->spare_head, Lt * sizeof(uint64_t), room);
       zero_counters(s, st);
-      hipLaunchKernelGGL(k_split_write, dim3(grid_for(Lt, 1, 1u << 20)), dim3(kWave), s->S, st, a, s->S,
+      auto wr = s->S <= 1024 ? k_split_write<1> : k_split_write<4>;
+      hipLaunchKernelGGL(wr, dim3(grid_for(Lt, kWave, 1u << 16)), dim3(kWave), 0, st, a, s->S,
                          (const SplitRec*)s->srec.as<SplitRec>(), s->spare_bytes.as<uint8_t>(),
                          s->spare_used.as<uint32_t>(), s->spare_head.as<uint64_t>(), s->dctr);
       HIPCHK(hipGetLastError());
@@ -832,6 +839,7 @@ uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1) {
 uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, hipStream_t st, bool small = false) {
   const bool segments_ready = small;
   ensure(s->leafid, kbound * sizeof(uint32_t));
+  ensure(s->segpos, (kbound + 1) * sizeof(uint32_t));
   ensure(s->seg_leaf, kbound * sizeof(uint32_t));
   ensure(s->seg_begin, (kbound + 1) * sizeof(uint32_t));
   ensure(s->seg_desc, (kbound + 1) * sizeof(uint4));

@@ -118,22 +118,23 @@ struct SrcInfo {
   uint64_t lastk;
   uint32_t used;
   uint32_t next;  // next non-empty old leaf (L after the last)
-  uint64_t pad;
+  uint64_t img;   // byte offset of the leaf's image: main array, or overflow arena with kImgArena set
 };
+constexpr uint64_t kImgArena = 1ull << 63;
 
-__global__ void k_src_info(const uint32_t* __restrict__ used, const uint64_t* __restrict__ head,
-                           const uint64_t* __restrict__ lastk, const uint32_t* __restrict__ rank,
-                           const uint32_t* __restrict__ ne, uint64_t L, SrcInfo* __restrict__ info) {
+__global__ void k_src_info(SrcLeaves src, const uint64_t* __restrict__ head, const uint64_t* __restrict__ lastk,
+                           const uint32_t* __restrict__ rank, const uint32_t* __restrict__ ne, uint64_t L,
+                           SrcInfo* __restrict__ info) {
   for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < L;
        f += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t u = used[f];
+    const uint32_t u = src.used[f];
     if (u == 0) continue;
     SrcInfo I;
     I.head = head[f];
     I.lastk = lastk[f];
     I.used = u;
     I.next = ne[rank[f] + 1];
-    I.pad = 0;
+    I.img = u > src.S ? (src.ovf[f] | kImgArena) : f * (uint64_t)src.S;
     info[f] = I;
   }
 }
@@ -314,77 +315,356 @@ __global__ void k_split_plan(Bounds dstb, uint64_t Lt, const SplitRec* __restric
   }
 }
 
-// dst[i - bs] = src[i] for i in [bs, be), one wave; src is 16-byte aligned and
-// readable in whole 16-byte chunks below round16(be); writes stop at dst_cap.
-__device__ __forceinline__ void wave_copy_bytes(uint8_t* dst, uint32_t dst_cap, const uint8_t* __restrict__ src,
-                                                uint32_t bs, uint32_t be) {
-  for (uint32_t base = bs & ~15u; base < be; base += 16u * kWave) {
-    const uint32_t p0 = base + 16u * lane_id();
-    if (p0 < be) {
-      const uint4 w = *reinterpret_cast<const uint4*>(src + p0);
-      const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+// Destination image in registers: lane l holds bytes [16 l + 1024 t, + 16) of
+// stripe t (kStripes stripes: leaves up to 1024 * kStripes bytes).  Pieces are
+// ORed in, so a piece only has to zero the bytes outside its own range.
+template <int kStripes>
+struct SplitImage {
+  uint4 o[kStripes];
+};
+
+// Bytes [a, b) of a dword as a mask (a, b clamped to [0, 4]).
+__device__ __forceinline__ uint32_t byte_mask(int32_t a, int32_t b) {
+  a = max(a, 0);
+  b = min(b, 4);
+  if (a >= b) return 0u;
+  const uint32_t hi = b == 4 ? 0xffffffffu : (1u << (8 * b)) - 1u;
+  return hi & ~((1u << (8 * a)) - 1u);
+}
+
+// Output bytes [ob, ob + n) take source bytes [sb, sb + n) of src, which is
+// 16-byte aligned and readable in whole 16-byte chunks that hold any of those
+// bytes.  Each lane loads the (at most two) aligned source chunks under its
+// output chunk and shifts them into place with byte aligns; the shift is the
+// same for every lane.
+template <int kStripes>
+__device__ __forceinline__ void image_or_run(SplitImage<kStripes>& im, uint32_t S, const uint8_t* __restrict__ src,
+                                             uint32_t sb, uint32_t ob, uint32_t n) {
+  const int32_t lane = lane_id();
+  const int32_t lo = (int32_t)sb, hi = (int32_t)(sb + n);
+  const uint32_t R = (sb - ob) & 15u;
+  const uint32_t qw = R >> 2, r = R & 3u;
 #pragma unroll
-      for (int k = 0; k < 16; k++) {
-        const uint32_t i = p0 + (uint32_t)k;
-        if (i >= bs && i < be && i - bs < dst_cap) dst[i - bs] = (uint8_t)(words[k >> 2] >> (8 * (k & 3)));
-      }
-    }
+  for (int t = 0; t < kStripes; t++) {
+    const int32_t q16 = 1024 * t + 16 * lane;
+    if (q16 >= (int32_t)S || q16 + 16 <= (int32_t)ob || q16 >= (int32_t)(ob + n)) continue;
+    const int32_t s0 = q16 - (int32_t)ob + (int32_t)sb;  // may be below 0 by up to 15
+    const int32_t c0 = (s0 >> 4) * 16, c1 = c0 + 16;
+    uint4 A = make_uint4(0, 0, 0, 0), B = A;
+    if (c0 < hi && c0 + 16 > lo) A = load16(src + c0);
+    if (c1 < hi && c1 + 16 > lo) B = load16(src + c1);
+    const uint32_t w[8] = {A.x, A.y, A.z, A.w, B.x, B.y, B.z, B.w};
+    uint32_t x[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) x[k] = qw == 0 ? w[k] : qw == 1 ? w[k + 1] : qw == 2 ? w[k + 2] : w[k + 3];
+    const int32_t a = (int32_t)ob - q16, b = (int32_t)(ob + n) - q16;
+    im.o[t].x |= __builtin_amdgcn_alignbyte(x[1], x[0], r) & byte_mask(a, b);
+    im.o[t].y |= __builtin_amdgcn_alignbyte(x[2], x[1], r) & byte_mask(a - 4, b - 4);
+    im.o[t].z |= __builtin_amdgcn_alignbyte(x[3], x[2], r) & byte_mask(a - 8, b - 8);
+    im.o[t].w |= __builtin_amdgcn_alignbyte(x[4], x[3], r) & byte_mask(a - 12, b - 12);
   }
 }
 
-// Writes destination leaf j from the old images (a planned split: no leaf is
-// empty or above S bytes).  A length that disagrees with the plan sets the
-// error counter.  The next source leaf's record loads while the current
-// leaf's bytes are copied.
+// The code of d (len bytes) at output byte cp.
+template <int kStripes>
+__device__ __forceinline__ void image_or_code(SplitImage<kStripes>& im, uint32_t S, uint32_t cp, uint64_t d, uint32_t len) {
+  const int32_t lane = lane_id();
+#pragma unroll
+  for (int t = 0; t < kStripes; t++) {
+    const int32_t q16 = 1024 * t + 16 * lane;
+    if (q16 >= (int32_t)S || q16 + 16 <= (int32_t)cp || q16 >= (int32_t)(cp + len)) continue;
+    uint32_t w[4] = {0, 0, 0, 0};
+    for (int i = 0; i < 16; i++) {
+      const uint32_t k = (uint32_t)(q16 + i) - cp;
+      if (k < len) {
+        const uint32_t byte = (uint32_t)((d >> (7 * k)) & 0x7fu) | (k + 1 < len ? 0x80u : 0u);
+        w[i >> 2] |= byte << (8 * (i & 3));
+      }
+    }
+    im.o[t].x |= w[0];
+    im.o[t].y |= w[1];
+    im.o[t].z |= w[2];
+    im.o[t].w |= w[3];
+  }
+}
+
+// Value of lane t (uniform t) of a per-lane struct of whole dwords.
+template <class T>
+__device__ __forceinline__ T lane_value(const T& v, uint32_t t) {
+  static_assert(sizeof(T) % 4 == 0, "whole dwords");
+  uint32_t w[sizeof(T) / 4];
+  __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+  for (uint32_t k = 0; k < sizeof(T) / 4; k++) w[k] = (uint32_t)__builtin_amdgcn_readlane((int)w[k], (int)t);
+  T r;
+  __builtin_memcpy(&r, w, sizeof(T));
+  return r;
+}
+
+// Address of an image offset (global memory: both bases are kernel arguments).
+__device__ __forceinline__ const uint8_t* img_ptr(const SrcLeaves& src, uint64_t img) {
+  return (img & kImgArena) ? src.arena + (img & ~kImgArena) : src.bytes + img;
+}
+
+// One run of old bytes in a destination image: output bytes [ob, ob + n) are
+// source bytes [sb, sb + n) of the image at src.
+struct RunDesc {
+  uint64_t img;  // image offset (img_ptr)
+  uint32_t sb, ob, n;
+};
+
+// The two aligned source chunks under the lane's output chunk q16 (stripe 0).
+// Loads are unconditional: a chunk that holds no byte of the run is clamped to
+// one that does (n = 0: the image's first chunk), and its bytes are masked off.
+struct RunChunks {
+  uint4 A, B;
+};
+
+__device__ __forceinline__ RunChunks run_load(const SrcLeaves& src, const RunDesc& r, int32_t q16) {
+  int32_t c0 = 0, c1 = 0;
+  if (r.n) {
+    const int32_t s0 = q16 - (int32_t)r.ob + (int32_t)r.sb;
+    const int32_t cf = ((int32_t)r.sb >> 4) * 16, cl = ((int32_t)(r.sb + r.n - 1) >> 4) * 16;
+    c0 = min(max((s0 >> 4) * 16, cf), cl);
+    c1 = min(max((s0 >> 4) * 16 + 16, cf), cl);
+  }
+  const uint8_t* p = img_ptr(src, r.img);
+  RunChunks c;
+  c.A = load16(p + c0);
+  c.B = load16(p + c1);
+  return c;
+}
+
+__device__ __forceinline__ void run_apply(uint4& o, const RunChunks& c, const RunDesc& r, int32_t q16) {
+  if (r.n == 0 || q16 + 16 <= (int32_t)r.ob || q16 >= (int32_t)(r.ob + r.n)) return;
+  const uint32_t R = (r.sb - r.ob) & 15u;
+  const uint32_t qw = R >> 2, rr = R & 3u;
+  const uint32_t w[8] = {c.A.x, c.A.y, c.A.z, c.A.w, c.B.x, c.B.y, c.B.z, c.B.w};
+  uint32_t x[5];
+#pragma unroll
+  for (int k = 0; k < 5; k++) x[k] = qw == 0 ? w[k] : qw == 1 ? w[k + 1] : qw == 2 ? w[k + 2] : w[k + 3];
+  const int32_t a = (int32_t)r.ob - q16, b = (int32_t)(r.ob + r.n) - q16;
+  o.x |= __builtin_amdgcn_alignbyte(x[1], x[0], rr) & byte_mask(a, b);
+  o.y |= __builtin_amdgcn_alignbyte(x[2], x[1], rr) & byte_mask(a - 4, b - 4);
+  o.z |= __builtin_amdgcn_alignbyte(x[3], x[2], rr) & byte_mask(a - 8, b - 8);
+  o.w |= __builtin_amdgcn_alignbyte(x[4], x[3], rr) & byte_mask(a - 12, b - 12);
+}
+
+// A destination leaf made of at most two runs of old bytes with one spliced
+// code between them (the common case: the leaf starts inside one old leaf and
+// ends in it or in the next non-empty one).  fast = false: more runs follow,
+// the writer walks them.
+struct LeafPlan {
+  RunDesc r1, r2;       // r2.n = 0 when absent
+  uint64_t clo, chi;    // bytes of the spliced code, little-endian (zero past its length)
+  uint32_t cpos, clen;  // its output position and length (clen = 0: none)
+  uint32_t end;         // output length after r2
+  uint32_t fast, bad;
+};
+
+__device__ __forceinline__ bool split_hops(const SplitArgs& a, uint64_t f, const SrcInfo& I, const SplitRec& B) {
+  return f != B.leaf && I.next < a.L && !(I.next == B.leaf && B.p == 0);
+}
+
+__device__ __forceinline__ LeafPlan make_plan(const SplitArgs& a, uint32_t S, const SplitRec& A, const SplitRec& B,
+                                              const SrcInfo& I, const SrcInfo& N) {
+  LeafPlan P;
+  P.r1 = RunDesc{0, 0, 0, 0};
+  P.r2 = P.r1;
+  P.clo = P.chi = 0;
+  P.cpos = P.clen = 0;
+  P.end = 8;
+  P.fast = false;
+  P.bad = A.leaf >= a.L;
+  if (P.bad) return P;
+  const uint64_t f = A.leaf;
+  const uint32_t bs = A.p == 0 ? 8u : A.p + A.cost;
+  const uint32_t be = f == B.leaf ? B.p : I.used;
+  if (be < bs || be > I.used || 8u + (be - bs) > S) {
+    P.bad = true;
+    return P;
+  }
+  P.r1 = RunDesc{I.img, bs, 8u, be - bs};
+  uint32_t pos = 8u + (be - bs);
+  P.end = pos;
+  P.fast = true;
+  if (!split_hops(a, f, I, B)) return P;
+  const uint64_t d = N.head - I.lastk;
+  const uint32_t len = vlen(d);
+  if (pos + len > S) {
+    P.bad = true;
+    return P;
+  }
+  uint64_t v = d;
+  for (uint32_t k = 0; k < len; k++) {
+    const uint64_t byte = (v & 0x7fu) | (k + 1 < len ? 0x80u : 0u);
+    v >>= 7;
+    if (k < 8)
+      P.clo |= byte << (8 * k);
+    else
+      P.chi |= byte << (8 * (k - 8));
+  }
+  P.cpos = pos;
+  P.clen = len;
+  pos += len;
+  P.end = pos;
+  const uint64_t f2 = I.next;
+  if (split_hops(a, f2, N, B)) {
+    P.fast = false;
+    return P;
+  }
+  const uint32_t be2 = f2 == B.leaf ? B.p : N.used;
+  if (be2 < 8u || be2 > N.used || pos + (be2 - 8u) > S) {
+    P.bad = true;
+    return P;
+  }
+  P.r2 = RunDesc{N.img, 8u, pos, be2 - 8u};
+  P.end = pos + (be2 - 8u);
+  return P;
+}
+
+// The spliced code into the lane's output chunk q16: the code's bytes shifted
+// into place (bytes past its length are zero).
+__device__ __forceinline__ void code_apply(uint4& o, const LeafPlan& P, int32_t q16) {
+  if (P.clen == 0 || q16 + 16 <= (int32_t)P.cpos || q16 >= (int32_t)(P.cpos + P.clen)) return;
+  const unsigned __int128 C = ((unsigned __int128)P.chi << 64) | P.clo;
+  const int32_t sh = q16 - (int32_t)P.cpos;  // in (-16, 10)
+  const unsigned __int128 W = sh >= 0 ? (C >> (8 * sh)) : (C << (8 * -sh));
+  o.x |= (uint32_t)W;
+  o.y |= (uint32_t)(W >> 32);
+  o.z |= (uint32_t)(W >> 64);
+  o.w |= (uint32_t)(W >> 96);
+}
+
+// Writes the destination leaves (a planned split: no leaf is empty or above S
+// bytes).  A wave takes 64 consecutive destination leaves.  For leaves up to
+// 1024 bytes, lane l first plans leaf j0 + l (its records, the descriptors of
+// its first two source leaves, runs and spliced code), so the dependent
+// metadata loads of 64 leaves overlap; the wave then builds each leaf's image
+// in registers (head, runs of old bytes shifted into place, the code) and
+// stores it with one 16-byte store per lane, zero fill included, loading the
+// next leaf's source chunks before it stores the current one.  Leaves of more
+// than two runs, and larger leaves, walk their source leaves one by one.  A
+// leaf whose length disagrees with the plan sets the error counter and is not
+// written.
+template <int kStripes>
 __global__ void __launch_bounds__(kWave) k_split_write(SplitArgs a, uint32_t S, const SplitRec* __restrict__ rec,
                                                        uint8_t* __restrict__ dbytes, uint32_t* __restrict__ dused,
                                                        uint64_t* __restrict__ dhead, Counters* ctr) {
-  extern __shared__ __align__(16) uint8_t buf[];
-  for (uint64_t j = blockIdx.x; j < a.Lt; j += gridDim.x) {
-    const SplitRec A = rec[j], B = rec[j + 1];
-    bool bad = A.leaf >= a.L;
-    uint64_t f = bad ? 0 : A.leaf;
+  const int lane = lane_id();
+  const int32_t q16 = 16 * lane;
+  // any number of runs, descriptors and source chunks loaded on demand
+  auto walk = [&](SplitImage<kStripes>& im, const SplitRec& A, const SplitRec& B, uint32_t& pos) -> bool {
+    uint64_t f = A.leaf;
     SrcInfo I = a.info[f];
-    wave_zero(buf, S);
-    __syncthreads();
-    if (lane_id() == 0) put_le64(buf, A.x);
-    uint32_t pos = 8;
     uint32_t bs = A.p == 0 ? 8u : A.p + A.cost;
-    while (!bad) {
+    for (;;) {
       const uint32_t u = I.used;
       const bool last = f == B.leaf;  // the end lies inside leaf f (B.p >= 8)
       const uint64_t fn = I.next;
-      const bool hop = !last && fn < a.L && !(fn == B.leaf && B.p == 0);
-      SrcInfo In;
+      const bool hop = split_hops(a, f, I, B);
+      SrcInfo In{};
       if (hop) In = a.info[fn];
       const uint32_t be = last ? B.p : u;
-      if (be < bs || be > u) {
-        bad = true;
-        break;
-      }
-      wave_copy_bytes(buf + min(pos, S), S - min(pos, S), a.src.ptr(f, u), bs, be);
+      if (be < bs || be > u || pos + (be - bs) > S) return false;
+      image_or_run(im, S, img_ptr(a.src, I.img), bs, pos, be - bs);
       pos += be - bs;
-      if (!hop) break;
+      if (!hop) return true;
       const uint64_t d = In.head - I.lastk;
       const uint32_t len = vlen(d);
-      if (lane_id() == 0 && pos + len <= S) vput(buf + pos, d);
+      if (pos + len > S) return false;
+      image_or_code(im, S, pos, d, len);
       pos += len;
       f = fn;
       I = In;
       bs = 8;
     }
-    __syncthreads();
-    const uint64_t want = 8u + (B.P - A.P - A.cost);
-    if (bad || pos != want || pos > S) {
-      if (lane_id() == 0) atomicOr(&ctr->error, 1u);
+  };
+  auto finish = [&](uint64_t j, uint64_t x, uint64_t want, bool ok, uint32_t pos, const SplitImage<kStripes>& im) {
+    if (!ok || pos != want) {
+      if (lane == 0) atomicOr(&ctr->error, 1u);
+      return;
+    }
+    uint8_t* dst = dbytes + j * (uint64_t)S;
+#pragma unroll
+    for (int s = 0; s < kStripes; s++) {
+      const uint32_t q = 1024u * s + 16u * (uint32_t)lane;
+      if (q < S) *reinterpret_cast<uint4*>(dst + q) = im.o[s];
+    }
+    if (lane == 0) {
+      dused[j] = pos;
+      dhead[j] = x;
+    }
+  };
+  for (uint64_t j0 = (uint64_t)blockIdx.x * kWave; j0 < a.Lt; j0 += (uint64_t)gridDim.x * kWave) {
+    const uint32_t nj = (uint32_t)min<uint64_t>(kWave, a.Lt - j0);
+    if constexpr (kStripes == 1) {
+      struct LeafWork {
+        LeafPlan P;
+        uint64_t x, want;
+      };
+      LeafWork Wl;
+      {
+        const SplitRec A = rec[j0 + min<uint32_t>((uint32_t)lane, nj - 1)];
+        const SplitRec B = rec[j0 + min<uint32_t>((uint32_t)lane, nj - 1) + 1];
+        SrcInfo I{}, N{};
+        if (A.leaf < a.L) {
+          I = a.info[A.leaf];
+          if (split_hops(a, A.leaf, I, B)) N = a.info[I.next];
+        }
+        Wl.P = make_plan(a, S, A, B, I, N);
+        Wl.x = A.x;
+        Wl.want = 8u + (B.P - A.P - A.cost);
+      }
+      // two buffers of source chunks, used in turn (no register copies
+      // between steps, so waiting for one never waits for the other)
+      auto step = [&](uint32_t t, const LeafWork& W, const RunChunks& C1, const RunChunks& C2, LeafWork& Wn,
+                      RunChunks& D1, RunChunks& D2) {
+        // next leaf's source chunks first (the last leaf reloads its own)
+        Wn = lane_value(Wl, t + 1 < nj ? t + 1 : t);
+        D1 = run_load(a.src, Wn.P.r1, q16);
+        D2 = run_load(a.src, Wn.P.r2, q16);
+        SplitImage<1> im;
+        im.o[0] = make_uint4(0, 0, 0, 0);
+        if (lane == 0) {
+          im.o[0].x = (uint32_t)W.x;
+          im.o[0].y = (uint32_t)(W.x >> 32);
+        }
+        bool ok = !W.P.bad;
+        uint32_t pos = W.P.end;
+        if (ok) {
+          if (W.P.fast) {
+            run_apply(im.o[0], C1, W.P.r1, q16);
+            run_apply(im.o[0], C2, W.P.r2, q16);
+            code_apply(im.o[0], W.P, q16);
+          } else {
+            pos = 8;
+            ok = walk(im, rec[j0 + t], rec[j0 + t + 1], pos);
+          }
+        }
+        finish(j0 + t, W.x, W.want, ok, pos, im);
+      };
+      LeafWork W0 = lane_value(Wl, 0), W1;
+      RunChunks C1 = run_load(a.src, W0.P.r1, q16), C2 = run_load(a.src, W0.P.r2, q16), D1, D2;
+      for (uint32_t t = 0; t < nj; t += 2) {
+        step(t, W0, C1, C2, W1, D1, D2);
+        if (t + 1 < nj) step(t + 1, W1, D1, D2, W0, C1, C2);
+      }
     } else {
-      wave_copy16(dbytes + j * (uint64_t)S, buf, S);
-      if (lane_id() == 0) {
-        dused[j] = pos;
-        dhead[j] = A.x;
+      for (uint32_t t = 0; t < nj; t++) {
+        const SplitRec A = rec[j0 + t], B = rec[j0 + t + 1];
+        SplitImage<kStripes> im;
+#pragma unroll
+        for (int s = 0; s < kStripes; s++) im.o[s] = make_uint4(0, 0, 0, 0);
+        if (lane == 0) {
+          im.o[0].x = (uint32_t)A.x;
+          im.o[0].y = (uint32_t)(A.x >> 32);
+        }
+        uint32_t pos = 8;
+        const bool ok = A.leaf < a.L && walk(im, A, B, pos);
+        finish(j0 + t, A.x, 8u + (B.P - A.P - A.cost), ok, pos, im);
       }
     }
-    __syncthreads();
   }
 }
 

@@ -81,6 +81,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t* __r
 // take a second LDS tile).  A pass without input values (vin null) makes them:
 // value i is i | vgen[i] << 31.
 constexpr int kScatterWaves = kSortThreads / kWave;
+static_assert(kSortItems * kScatterWaves == kWave, "one wave scans the (round, wave) counts of a tile");
 
 template <bool kKV>
 __device__ __forceinline__ void radix_scatter_tile(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
@@ -210,6 +211,80 @@ __global__ void k_compact_unique(const uint64_t* __restrict__ a, uint64_t n,
     if (i == 0 || a[i] != a[i - 1]) out[pos[i]] = a[i];
     if (i == 0) *n_out = pos[n];
   }
+}
+
+// Removal of repeats from a sorted batch in two passes over it: per tile of
+// kSortTile keys the number of first occurrences, an exclusive scan of those
+// (one small launch), then every tile writes its first occurrences to its
+// offset.  Inside a tile, item i = base + 256 r + 64 w + l (round r, wave w,
+// lane l), so the tile's order is (r, w, l): a ballot per round gives the lane
+// offsets, and one wave scan over the 16 x 4 (round, wave) counts the rest.
+__device__ __forceinline__ bool first_occurrence(const uint64_t* __restrict__ a, uint64_t i, uint64_t x,
+                                                 uint64_t prev_lane) {
+  if (i == 0) return true;
+  const uint64_t prev = lane_id() == 0 ? a[i - 1] : prev_lane;
+  return prev != x;
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_unique_count(const uint64_t* __restrict__ a, uint64_t n,
+                                                               uint32_t* __restrict__ tcnt) {
+  __shared__ uint32_t red[kSortThreads / kWave];
+  const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+  const int wid = threadIdx.x / kWave;
+  uint32_t c = 0;
+#pragma unroll
+  for (int r = 0; r < kSortItems; r++) {
+    const uint64_t i = base + (uint64_t)r * kSortThreads + threadIdx.x;
+    const uint64_t x = i < n ? a[i] : 0;
+    const uint64_t pl = dpp_prev64(x);
+    if (i < n && first_occurrence(a, i, x, pl)) c++;
+  }
+  c = wave_sum(c);
+  if (lane_id() == 0) red[wid] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kSortThreads / kWave; w++) t += red[w];
+    tcnt[blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_unique_write(const uint64_t* __restrict__ a, uint64_t n,
+                                                               const uint32_t* __restrict__ toff, uint32_t ntiles,
+                                                               uint64_t* __restrict__ out,
+                                                               unsigned long long* __restrict__ n_out) {
+  constexpr int kW = kSortThreads / kWave;
+  __shared__ uint32_t rc[kSortItems * kW];  // (round, wave) counts, then their exclusive offsets
+  const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+  const int lane = lane_id(), wid = threadIdx.x / kWave;
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  uint64_t x[kSortItems];
+  uint64_t fm[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; r++) {
+    const uint64_t i = base + (uint64_t)r * kSortThreads + threadIdx.x;
+    x[r] = i < n ? a[i] : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < kSortItems; r++) {
+    const uint64_t i = base + (uint64_t)r * kSortThreads + threadIdx.x;
+    const uint64_t pl = dpp_prev64(x[r]);
+    fm[r] = __ballot(i < n && first_occurrence(a, i, x[r], pl));
+    if (lane == 0) rc[r * kW + wid] = (uint32_t)__popcll(fm[r]);
+  }
+  __syncthreads();
+  if (wid == 0) {
+    const uint32_t v = rc[lane];  // kSortItems * kW == 64 entries
+    rc[lane] = wave_incl_scan(v) - v;
+  }
+  __syncthreads();
+  const uint64_t tb = toff[blockIdx.x];
+#pragma unroll
+  for (int r = 0; r < kSortItems; r++) {
+    if ((fm[r] >> lane) & 1ull) out[tb + rc[r * kW + wid] + (uint32_t)__popcll(fm[r] & lt_mask)] = x[r];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = toff[ntiles];
 }
 
 }  // namespace cpma_dev

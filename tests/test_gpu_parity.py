@@ -151,6 +151,24 @@ def test_heavy_slice_sequential_batch(cp, orc):
     check(c, expect, orc)
 
 
+def test_first_batches_locate_per_key(cp, orc):
+    """The first updates of a freshly built set are batches above the one-launch
+    size but below the leaf count, so the batch keys are located one by one
+    (and every per-batch buffer of that branch is sized by the batch itself)."""
+    base = synth.uniform_keys(2_000_000, 43, bits=40)
+    expect = orc.build_set(base)
+    c = cp.CPMA(base, leaf_bytes=64)
+    assert c.geometry()[0] > 20000
+    batch = synth.uniform_keys(6000, 44, bits=40)
+    expect, added = orc.insert(expect, batch)
+    assert c.insert_batch(batch) == added
+    check(c, expect, orc)
+    dels = np.concatenate([expect[::400], synth.uniform_keys(1000, 45, bits=40)])
+    expect, removed = orc.delete(expect, dels)
+    assert c.delete_batch(dels) == removed
+    check(c, expect, orc)
+
+
 def test_delete_all_then_reinsert(cp, orc):
     keys = synth.uniform_keys(5000, 41, bits=40)
     expect = orc.build_set(keys)
