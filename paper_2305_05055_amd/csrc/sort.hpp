@@ -25,12 +25,32 @@ __global__ void __launch_bounds__(256) k_validate(const uint64_t* __restrict__ k
   __shared__ uint64_t red[4];
   uint64_t orv = 0;
   uint32_t res = 0, uns = 0;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    uint64_t x = keys[i];
-    orv |= x;
-    res |= (x == kNoKey);
-    if (i + 1 < k && keys[i + 1] < x) uns = 1;
+  // four independent loads per thread in flight; the right neighbour of a
+  // key comes from the next lane (lane 63 loads it)
+  constexpr int kU = 4;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const bool last_lane = lane_id() == kWave - 1;
+  // wave-uniform trip count, so every lane takes part in the neighbour shifts
+  for (uint64_t w0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(uint32_t)(kWave - 1)); w0 < k;
+       w0 += kU * stride) {
+    const uint64_t i0 = w0 + (uint64_t)lane_id();
+    uint64_t x[kU];
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const uint64_t i = i0 + u * stride;
+      x[u] = i < k ? keys[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const uint64_t i = i0 + u * stride;
+      uint64_t nx = dpp_next64(x[u]);
+      if (last_lane && i + 1 < k) nx = keys[i + 1];
+      if (i < k) {
+        orv |= x[u];
+        res |= (x[u] == kNoKey);
+        if (i + 1 < k && nx < x[u]) uns = 1;
+      }
+    }
   }
   orv = wave_or(orv);
   const uint64_t flags = wave_or((uint64_t)(res | (uns << 1)));

@@ -169,6 +169,20 @@ def test_first_batches_locate_per_key(cp, orc):
     check(c, expect, orc)
 
 
+@pytest.mark.parametrize("p", [63, 64 * 4 * 4096 - 1])
+def test_single_descent_detected(cp, orc, p):
+    """A batch sorted except for one adjacent pair, placed where the sortedness
+    check takes the right neighbour from another wave (and, for the second
+    position, from the next grid-stride round): it must be sorted."""
+    keys = orc.build_set(synth.uniform_keys(1_100_000, 47, bits=40))
+    keys[p], keys[p + 1] = keys[p + 1], keys[p]
+    base = orc.build_set(synth.uniform_keys(50_000, 48, bits=40))
+    c = cp.CPMA(base)
+    expect, added = orc.insert(base, keys)
+    assert c.insert_batch(keys) == added
+    check(c, expect, orc)
+
+
 def test_delete_all_then_reinsert(cp, orc):
     keys = synth.uniform_keys(5000, 41, bits=40)
     expect = orc.build_set(keys)
