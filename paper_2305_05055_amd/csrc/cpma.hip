@@ -126,7 +126,7 @@ struct cpma {
   DevBuf kin, kb0, kb1, kdedup, leafid, segpos, seg_leaf, seg_begin, seg_desc, heavy, spill, scan_tmp, ovf, arena,
       stage, pyr, win, wargs, cnt, koff, win_id, welem, P, ccost, ncost, lstart, planU, plan_used,
       spare_bytes, spare_used, spare_head, fg_level, fg_deg, fg_p, fg_c, fg_acc,
-      win_of_leaf, fail, qa, qb, qfirst, qnvis, qvoff, qsum, qcount, qout, lastk, ne_rank, ne_list, chain_pfx,
+      win_of_leaf, fail, qa, qb, qfirst, qnvis, qvoff, qsum, qcount, qout, lastk, lckpt, ne_rank, ne_list, chain_pfx,
       srec, wide, srcinfo, parts, qparts, fz_meta, fz_v0, fz_v1, fz_byte, fz_member, fz_code, fz_ctr, fz_res,
       ctr_buf, info_buf, qalg_buf;
   Counters* dctr = nullptr;
@@ -158,7 +158,7 @@ struct cpma {
             &fail,      &qa,        &qb,        &qfirst,      &qnvis,      &qvoff,       &qsum,       &qcount,
             &qout,      &lastk,     &ne_rank,   &ne_list,     &chain_pfx,  &srec,        &wide,       &srcinfo,
             &parts,     &qparts,    &fz_meta,   &fz_v0,       &fz_v1,      &fz_byte,     &fz_member,  &fz_code,
-            &fz_ctr,    &fz_res,    &ctr_buf,   &info_buf,    &qalg_buf};
+            &fz_ctr,    &fz_res,    &ctr_buf,   &info_buf,    &qalg_buf,   &lckpt};
   }
 
   Bounds bounds(uint64_t Lx) const {
@@ -656,12 +656,13 @@ bool split_resize(cpma* s, uint64_t Lt, uint64_t total_used, hipStream_t st, uin
   auto fits = [&](uint64_t lt) { return (__int128)(total_used + 2 * L + 16) * (lt + 1) < ((__int128)1 << 62); };
   if (!fits(Lt)) return false;
   ensure(s->lastk, L * sizeof(uint64_t));
+  ensure(s->lckpt, L * 3 * sizeof(LeafCkpt));
   ensure(s->ne_rank, (L + 1) * sizeof(uint32_t));
   ensure(s->ne_list, (L + 1) * sizeof(uint32_t));
   ensure(s->chain_pfx, (L + 1) * sizeof(uint64_t));
   const SrcLeaves sl = src_leaves(s);
-  hipLaunchKernelGGL(k_leaf_last, dim3(grid_for(L, 256, 1u << 16)), dim3(256), 0, st, sl,
-                     (const uint64_t*)s->head.as<uint64_t>(), L, s->lastk.as<uint64_t>());
+  hipLaunchKernelGGL(k_leaf_last, dim3(grid_for(4 * L, 256, 1u << 16)), dim3(256), 0, st, sl,
+                     (const uint64_t*)s->head.as<uint64_t>(), L, s->lastk.as<uint64_t>(), s->lckpt.as<LeafCkpt>());
   HIPCHK(hipGetLastError());
   scan<uint32_t>(s, s->ne_rank.as<uint32_t>(), L, st, NonEmptyFn{sl.used});
   hipLaunchKernelGGL(k_ne_compact, dim3(grid_for(L + 1, 256, 1u << 16)), dim3(256), 0, st, sl.used,
@@ -671,6 +672,7 @@ bool split_resize(cpma* s, uint64_t Lt, uint64_t total_used, hipStream_t st, uin
   a.src = sl;
   a.head = s->head.as<uint64_t>();
   a.lastk = s->lastk.as<uint64_t>();
+  a.ck = s->lckpt.as<LeafCkpt>();
   a.rank = s->ne_rank.as<uint32_t>();
   a.ne = s->ne_list.as<uint32_t>();
   a.CP = s->chain_pfx.as<uint64_t>();

@@ -62,19 +62,114 @@ __device__ __forceinline__ uint64_t leaf_last_wide(const uint8_t* __restrict__ l
   return last;
 }
 
-// lastk[f] = last key of every non-empty old leaf.  head[f + 1] bounds the keys
-// of leaf f from above (an empty leaf keeps a head above every earlier key), so
-// a span below 2^28 selects the narrow decoder.
+// Decoder state at a 16-byte chunk boundary c of a narrow leaf, for walks that
+// start there instead of at the head: K = payload contributions of the bytes in
+// [8, c) (each byte's 7 bits shifted by its place in its code), and the code
+// still open at c: its run of continuation bytes before c and their
+// contributions (partial).  The last complete key before c is head + K -
+// partial; the open code started at c - run.  c = ~0: none.
+struct LeafCkpt {
+  uint32_t c, K, partial, shrun;  // shrun: shift (7 run) | run << 8
+};
+
+// lastk[f] = last key of every non-empty old leaf, and for narrow leaves (key
+// span below 2^28: every code at most 4 bytes, every sum in 32 bits) the
+// decoder state at the starts of the second, third and fourth quarters.  Four
+// lanes share a leaf: lane q sums the contributions of its quarter's bytes,
+// starting from the shift that the continuation bytes just before its quarter
+// imply, and a prefix over the four lanes gives the checkpoints and the total.
+// head[f + 1] bounds the keys of leaf f from above (an empty leaf keeps a head
+// above every earlier key), so it selects the narrow form.
 __global__ void __launch_bounds__(256) k_leaf_last(SrcLeaves src, const uint64_t* __restrict__ head, uint64_t L,
-                                                   uint64_t* __restrict__ lastk) {
-  for (uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; f < L;
-       f += (uint64_t)gridDim.x * blockDim.x) {
+                                                   uint64_t* __restrict__ lastk, LeafCkpt* __restrict__ ck) {
+  const uint32_t q = threadIdx.x & 3u;
+  const uint64_t quads = ((uint64_t)gridDim.x * blockDim.x) >> 2;
+  for (uint64_t f = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2; f < L; f += quads) {
     const uint32_t u = src.used[f];
-    if (u == 0) continue;
+    if (u == 0) continue;  // the same for the four lanes of a leaf
     const uint64_t h = head[f];
     const uint64_t nx = f + 1 < L ? head[f + 1] : ~0ull;
     const uint8_t* p = src.ptr(f, u);
-    lastk[f] = (nx > h && nx - h < (1ull << 28)) ? leaf_last_narrow(p, u, h) : leaf_last_wide(p, u, h);
+    if (!(nx > h && nx - h < (1ull << 28))) {
+      if (q == 0) lastk[f] = leaf_last_wide(p, u, h);
+      else ck[f * 3 + q - 1] = LeafCkpt{~0u, 0, 0, 0};
+      continue;
+    }
+    const uint32_t Q = ((u + 3) / 4 + 15) & ~15u;
+    const uint32_t b = q * Q, e = min(u, b + Q);
+    uint32_t D = 0, sh = 0, run = 0, partial = 0;
+    if (b < u) {
+      if (q > 0) {
+        // continuation bytes that end the previous chunk (never the head's)
+        const uint4 pc = load16(p + b - 16);
+        const uint32_t pw[4] = {pc.x, pc.y, pc.z, pc.w};
+        uint32_t m = 0;  // high bits of the chunk's bytes (the head's bytes count as clear)
+#pragma unroll
+        for (int i = 0; i < 16; i++)
+          if (b - 16 + (uint32_t)i >= 8) m |= ((pw[i >> 2] >> (8 * (i & 3) + 7)) & 1u) << i;
+        run = min((uint32_t)__clz((int)~(m << 16)), 3u);  // a narrow code has at most 3 continuation bytes
+#pragma unroll
+        for (int i = 0; i < 16; i++)
+          if ((uint32_t)i + run >= 16) partial += ((pw[i >> 2] >> (8 * (i & 3))) & 0x7fu) << (7 * (i + run - 16));
+        sh = 7 * run;
+      }
+      auto chunk = [&](const uint4 cur, uint32_t c) {
+        uint32_t w[4] = {cur.x, cur.y, cur.z, cur.w};
+        if (c == 0) {
+          w[0] = 0x80808080u;
+          w[1] = 0x00808080u;
+        }
+        const int32_t nv = (int32_t)u - (int32_t)c;
+        if (nv < 16) {
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const int32_t v = nv - 4 * k;
+            const uint32_t keep = v >= 4 ? 0xffffffffu : (v <= 0 ? 0u : ((1u << (8 * v)) - 1u));
+            w[k] = (w[k] & keep) | (0x80808080u & ~keep);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+          const uint32_t x = w[i >> 2];
+          const int o = 8 * (i & 3);
+          const uint32_t cm = 0u - ((x >> (o + 7)) & 1u);
+          D += ((x >> o) & 0x7fu) << (sh & 31u);
+          sh = (sh + 7u) & cm;
+        }
+      };
+      // 64-byte rounds with the next round's four loads in flight
+      const uint4 z = make_uint4(0, 0, 0, 0);
+      uint4 a0 = load16(p + b);
+      uint4 a1 = b + 16 < e ? load16(p + b + 16) : z;
+      uint4 a2 = b + 32 < e ? load16(p + b + 32) : z;
+      uint4 a3 = b + 48 < e ? load16(p + b + 48) : z;
+      for (uint32_t c = b; c < e; c += 64) {
+        uint4 b0 = z, b1 = z, b2 = z, b3 = z;
+        if (c + 64 < e) b0 = load16(p + c + 64);
+        if (c + 80 < e) b1 = load16(p + c + 80);
+        if (c + 96 < e) b2 = load16(p + c + 96);
+        if (c + 112 < e) b3 = load16(p + c + 112);
+        chunk(a0, c);
+        if (c + 16 < e) chunk(a1, c + 16);
+        if (c + 32 < e) chunk(a2, c + 32);
+        if (c + 48 < e) chunk(a3, c + 48);
+        a0 = b0;
+        a1 = b1;
+        a2 = b2;
+        a3 = b3;
+      }
+    }
+    // prefix over the four lanes of the leaf
+    uint32_t incl = D;
+    uint32_t v = (uint32_t)__shfl_up((int)incl, 1, 4);
+    if (q >= 1) incl += v;
+    v = (uint32_t)__shfl_up((int)incl, 2, 4);
+    if (q >= 2) incl += v;
+    const uint32_t total = (uint32_t)__shfl((int)incl, 3, 4);
+    if (q == 0)
+      lastk[f] = h + total;
+    else
+      ck[f * 3 + q - 1] = b < u ? LeafCkpt{b, incl - D, partial, (7 * run) | (run << 8)} : LeafCkpt{~0u, 0, 0, 0};
   }
 }
 
@@ -147,6 +242,7 @@ struct SplitArgs {
   const uint32_t* rank;   // non-empty rank of each old leaf
   const uint32_t* ne;     // non-empty old leaf ids, closed by L
   const uint64_t* CP;     // L + 1 entries
+  const LeafCkpt* ck;     // three per old leaf (narrow leaves)
   uint64_t L;             // old leaves
   uint64_t Lt;            // destination leaves
 };
@@ -203,51 +299,71 @@ __global__ void __launch_bounds__(256) k_split_locate(SplitArgs a, SplitRec* __r
       // flight; bytes past `used` become payload-free continuation bytes and the
       // head a zero terminator, as in the range scan's decoder.  The code that
       // starts at byte s (s >= 8) reaches threshold T when s >= T - c0 - hc + 8.
+      // Each threshold's walk starts at the last quarter checkpoint at or
+      // before that byte (the head for the first quarter).
       auto first_byte = [&](uint64_t t) -> uint32_t {
         const uint64_t over = t - c0;
         return over <= hc ? 8u : (uint32_t)min<uint64_t>(over - hc + 8u, 0xffffffffull);
       };
+      const LeafCkpt K1 = a.ck[f * 3], K2 = a.ck[f * 3 + 1], K3 = a.ck[f * 3 + 2];
       uint32_t bp = first_byte(T);
-      uint32_t key32 = 0, acc = 0, sh = 0, start = 0;
-      uint4 nxt = load16(leaf);
-      for (uint32_t c = 0; c < u && j < jend; c += 16) {
-        const uint4 cur = nxt;
-        if (c + 16 < u) nxt = load16(leaf + c + 16);
-        uint32_t w[4] = {cur.x, cur.y, cur.z, cur.w};
-        if (c == 0) {
-          w[0] = 0x80808080u;
-          w[1] = 0x00808080u;
-        }
-        const int32_t nv = (int32_t)u - (int32_t)c;
-        if (nv < 16) {
+      while (j < jend) {
+        uint32_t cs = 0, key32 = 0, acc = 0, sh = 0, start = 0;
+        auto take = [&](const LeafCkpt& k) {
+          if (k.c != ~0u && k.c <= bp) {
+            cs = k.c;
+            key32 = k.K - k.partial;
+            acc = k.partial;
+            sh = k.shrun & 0xffu;
+            start = k.c - (k.shrun >> 8);
+          }
+        };
+        take(K1);
+        take(K2);
+        take(K3);
+        bool hit = false;
+        uint4 nxt = load16(leaf + cs);
+        for (uint32_t c = cs; c < u && !hit; c += 16) {
+          const uint4 cur = nxt;
+          if (c + 16 < u) nxt = load16(leaf + c + 16);
+          uint32_t w[4] = {cur.x, cur.y, cur.z, cur.w};
+          if (c == 0) {
+            w[0] = 0x80808080u;
+            w[1] = 0x00808080u;
+          }
+          const int32_t nv = (int32_t)u - (int32_t)c;
+          if (nv < 16) {
 #pragma unroll
-          for (int k = 0; k < 4; k++) {
-            const int32_t v = nv - 4 * k;
-            const uint32_t keep = v >= 4 ? 0xffffffffu : (v <= 0 ? 0u : ((1u << (8 * v)) - 1u));
-            w[k] = (w[k] & keep) | (0x80808080u & ~keep);
+            for (int k = 0; k < 4; k++) {
+              const int32_t v = nv - 4 * k;
+              const uint32_t keep = v >= 4 ? 0xffffffffu : (v <= 0 ? 0u : ((1u << (8 * v)) - 1u));
+              w[k] = (w[k] & keep) | (0x80808080u & ~keep);
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < 16; i++) {
+            const uint32_t x = w[i >> 2];
+            const int o = 8 * (i & 3);
+            const uint32_t cm = 0u - ((x >> (o + 7)) & 1u);  // all ones on a continuation byte
+            acc |= ((x >> o) & 0x7fu) << (sh & 31u);
+            key32 += acc & ~cm;
+            if (!cm && !hit && start >= 8u && start >= bp) {
+              const uint32_t end = c + (uint32_t)i;
+              const uint64_t P = c0 + hc + start - 8u;
+              do {
+                put_rec(rec, j, f, h + key32, P, start, end + 1u - start);
+                j++;
+                T = split_threshold(j, total, Lt);
+                bp = first_byte(T);
+              } while (j < jend && start >= bp);
+              hit = true;
+            }
+            acc &= cm;
+            start = cm ? start : c + (uint32_t)i + 1u;
+            sh = (sh + 7u) & cm;
           }
         }
-#pragma unroll
-        for (int i = 0; i < 16; i++) {
-          const uint32_t x = w[i >> 2];
-          const int o = 8 * (i & 3);
-          const uint32_t cm = 0u - ((x >> (o + 7)) & 1u);  // all ones on a continuation byte
-          acc |= ((x >> o) & 0x7fu) << (sh & 31u);
-          key32 += acc & ~cm;
-          if (!cm && start >= 8u && start >= bp && j < jend) {
-            const uint32_t end = c + (uint32_t)i;
-            const uint64_t P = c0 + hc + start - 8u;
-            do {
-              put_rec(rec, j, f, h + key32, P, start, end + 1u - start);
-              j++;
-              T = split_threshold(j, total, Lt);
-              bp = first_byte(T);
-            } while (j < jend && start >= bp);
-          }
-          acc &= cm;
-          start = cm ? start : c + (uint32_t)i + 1u;
-          sh = (sh + 7u) & cm;
-        }
+        if (!hit) break;  // no code of f starts at or past bp
       }
     } else {
     // walk the codes of f: the code starting at byte s has chain prefix c0 + hc + s - 8
