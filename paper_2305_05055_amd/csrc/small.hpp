@@ -107,17 +107,50 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __
     pos += first ? 1u : 0u;
   }
   __syncthreads();
-  // unique keys back to A[0, kp) and to B; their leaves to LF: one binary
-  // search per key, or with few keys one 64-ary wave search per key (a few
-  // dependent steps instead of ~log2 L)
+  // unique keys to B and their leaves to LF.  With few keys: one 64-ary wave
+  // search per key (a few dependent steps instead of ~log2 L; the keys go
+  // back to A for it).  Otherwise one binary search per key, whose first
+  // levels run in LDS: A (no longer needed) takes every st-th head, and only
+  // the last ~log2 st steps read the heads in HBM.
   constexpr uint32_t kWaves = kSmallThreads / kWave;
   const bool by_wave = kp <= 2 * kWaves;
+  if (by_wave) {
 #pragma unroll
-  for (uint32_t q = 0; q < kPer; q++) {
-    if (mypos[q] != ~0u) {
-      A[mypos[q]] = mykeys[q];
-      B[mypos[q]] = mykeys[q];
-      if (!by_wave) LF[mypos[q]] = (uint32_t)locate_leaf(head, L, mykeys[q]);
+    for (uint32_t q = 0; q < kPer; q++) {
+      if (mypos[q] != ~0u) {
+        A[mypos[q]] = mykeys[q];
+        B[mypos[q]] = mykeys[q];
+      }
+    }
+  } else {
+    const uint64_t st = (L + kSmallBatch - 1) / kSmallBatch;
+    const uint32_t ns = (uint32_t)((L + st - 1) / st);  // samples head[i st], i < ns <= kSmallBatch
+    for (uint32_t i = tid; i < ns; i += kSmallThreads) A[i] = head[(uint64_t)i * st];
+    __syncthreads();
+#pragma unroll
+    for (uint32_t q = 0; q < kPer; q++) {
+      if (mypos[q] == ~0u) continue;
+      const uint64_t x = mykeys[q];
+      B[mypos[q]] = x;
+      uint32_t lo = 0, hi = ns;  // first sample above x
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (A[mid] <= x)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      // the first head above x has an index in ((lo - 1) st, lo st], within [0, L]
+      uint64_t a = lo == 0 ? 0 : (uint64_t)(lo - 1) * st + 1;
+      uint64_t b = min((uint64_t)lo * st, L);
+      while (a < b) {
+        const uint64_t mid = (a + b) >> 1;
+        if (head[mid] <= x)
+          a = mid + 1;
+        else
+          b = mid;
+      }
+      LF[mypos[q]] = (uint32_t)(a ? a - 1 : 0);
     }
   }
   __syncthreads();
