@@ -160,11 +160,17 @@ __device__ __forceinline__ uint32_t wave_decode_regs(const uint4 w, uint32_t use
 
 // Narrow single-chunk decode (leaf size <= 1024): every key lies within 2^32 of
 // `base`, so every delta fits 32 bits and a code has at most 5 bytes.  Keys are
-// produced as 32-bit offsets from base (head_rel = head - base).  Branch-free per
-// byte: the shift of a byte inside its code comes from a per-lane mask of
-// continuation bytes, and the shift a code carries in from the previous lane is
-// 7 times that lane's run of trailing continuation bytes, known before parsing.
-// emit(index, key offset) runs for every key in order; returns the key count.
+// produced as 32-bit offsets from base (head_rel = head - base).
+//
+// A key is the head plus the payload of every code byte before it, each byte's
+// 7 bits shifted by 7 times its place in its code; so a running sum of shifted
+// payloads over the bytes, read at a code's last byte, is that key's offset.
+// Per lane: the running sum over its 16 bytes (the shift a code carries in
+// from the previous lane is 7 times that lane's run of trailing continuation
+// bytes, known before parsing), then one wave scan of the lane totals gives
+// every lane its starting offset, codes that straddle lanes included.  The
+// head and bytes past `used` carry no payload.  emit(index, key offset) runs
+// for every key in order; returns the key count.
 __device__ __forceinline__ uint32_t msb_nibble(uint32_t x) {
   x = (x >> 7) & 0x01010101u;
   return (x | (x >> 7) | (x >> 14) | (x >> 21)) & 0xfu;
@@ -182,26 +188,29 @@ __device__ __forceinline__ uint32_t wave_decode_narrow(uint4 w, uint32_t used, u
     w.x = 0;
     w.y = 0;
   }
-  const uint32_t msb = msb_nibble(w.x) | (msb_nibble(w.y) << 4) | (msb_nibble(w.z) << 8) | (msb_nibble(w.w) << 12);
+  uint32_t words[4] = {w.x, w.y, w.z, w.w};
+  if (nvalid < 16u) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int32_t v = (int32_t)nvalid - 4 * k;
+      words[k] &= v >= 4 ? 0xffffffffu : (v <= 0 ? 0u : ((1u << (8 * v)) - 1u));
+    }
+  }
+  const uint32_t msb = msb_nibble(words[0]) | (msb_nibble(words[1]) << 4) | (msb_nibble(words[2]) << 8) |
+                       (msb_nibble(words[3]) << 12);
   const uint32_t tm = vm & ~msb;  // code ends
   const uint32_t cm = vm & msb;   // continuation bytes
   const uint32_t tc = __clz(~(cm << 16));
   uint32_t sh = 7u * dpp_prev32(tc);
-  const uint32_t words[4] = {w.x, w.y, w.z, w.w};
-  uint32_t acc = 0, run = 0;
+  uint32_t run = 0;
   uint32_t kv[16];
 #pragma unroll
   for (int j = 0; j < 16; j++) {
-    const uint32_t pb = (words[j >> 2] >> (8 * (j & 3))) & 0x7fu;
-    acc |= pb << sh;
-    const uint32_t tmask = 0u - ((tm >> j) & 1u);
-    run += acc & tmask;
+    run += ((words[j >> 2] >> (8 * (j & 3))) & 0x7fu) << sh;
     kv[j] = run;
-    acc &= ~tmask;
     sh = (sh + 7u) & (0u - ((cm >> j) & 1u));
   }
-  const uint32_t cin = dpp_prev32(acc);  // low bits of the code continuing into this lane
-  const uint32_t lead = (hl ? head_rel : 0u) + (tm ? cin : 0u);
+  const uint32_t lead = hl ? head_rel : 0u;
   const uint32_t tot = run + lead;
   const uint32_t lcnt = (uint32_t)__popc(tm) + (hl ? 1u : 0u);
   const uint32_t ex = wave_incl_scan(tot) - tot;
