@@ -219,7 +219,7 @@ def time_range(torch, c, dlo, dhi, reps=3):
     kernel's algorithmic bytes and device time from the library's HIP events."""
     c.range_map(dlo, dhi)
     torch.cuda.synchronize()
-    c.stats_enable(True)
+    c.stats_select(["range_scan"])
     t0 = time.perf_counter()
     for _ in range(reps):
         s_, n_ = c.range_map(dlo, dhi)
@@ -561,12 +561,16 @@ def main():
 
     # ---- headline: W warm-up + K timed insert batches of k keys ------------------
     nb = args.warmup + args.steps
-    batches = [to_dev(synth.uniform_keys(k, seed + 40, offset=i * k)) for i in range(nb)]
+    n_phase_steps = 3
+    batches = [to_dev(synth.uniform_keys(k, seed + 40, offset=i * k)) for i in range(nb + n_phase_steps)]
     torch.cuda.synchronize()
     for i in range(args.warmup):
         c.insert_batch(batches[i])
     torch.cuda.synchronize()
-    c.stats_enable(True)
+    # the timed steps record HIP events around the merge kernel only (each event
+    # record idles the GPU for a few microseconds); every phase is timed on
+    # separate steps afterwards
+    c.stats_select(["merge"])
     lat = []
     t0 = time.perf_counter()
     for i in range(args.warmup, nb):
@@ -580,11 +584,17 @@ def main():
     dt = t1 - t0
     value = args.steps * k / dt
     log(f"headline: {value:.3e} inserts/s, {dt / args.steps * 1e3:.2f} ms/step, n={c.size()}")
-    phases = {name: {"launches": v[0], "ms": v[1], "alg_bytes": v[2]} for name, v in st.items()}
+    c.stats_enable(True)
+    for i in range(nb, nb + n_phase_steps):
+        c.insert_batch(batches[i])
+    stp = c.stats()
+    c.stats_enable(False)
+    phases = {name: {"launches": v[0], "ms": v[1], "alg_bytes": v[2]} for name, v in stp.items()}
+    phases["steps"] = n_phase_steps
 
     # roofline of the dominant single kernel of the step (the merge, or the sort's passes)
     mg_l, mg_ms, mg_b = st["merge"]
-    dominant = max(("merge", "sort", "locate", "count", "redist"), key=lambda p: st[p][1])
+    dominant = max(("merge", "sort", "locate", "count", "redist"), key=lambda p: stp[p][1])
     roof = None
     if mg_l > 0 and mg_ms > 0:
         ach = (mg_b / mg_l) / ((mg_ms / mg_l) * 1e-3) / 1e9

@@ -345,7 +345,13 @@ uint64_t cpma_clock_ns(void);
  *   CPMA_PHASE_RANGE_SCAN  the range_map scan kernel; bytes = used bytes of every
  *                          visited leaf + 32 per query
  *   CPMA_PHASE_QUERY       a whole range_map or contains call
- * cpma_stats_enable(set, 1) zeroes the statistics and starts timing; 0 stops.
+ * cpma_stats_enable(set, 1) zeroes the statistics and starts timing every
+ * phase; 0 stops.  cpma_stats_select(set, mask) does the same for the phases
+ * whose bit (1u << phase) is set in mask (0 stops; a bit at or above
+ * CPMA_PHASE_NUM is CPMA_ERR_INVALID).  Each timed phase records two HIP events
+ * on the call's stream per occurrence, and each event record leaves the GPU
+ * idle for a few microseconds, so a caller that times one kernel selects its
+ * phase alone.
  * cpma_stats_get copies min(n, CPMA_PHASE_NUM) entries and synchronises the
  * device.
  */
@@ -368,6 +374,7 @@ typedef struct {
 } cpma_phase_stat;
 
 cpma_status cpma_stats_enable(cpma* set, int on);
+cpma_status cpma_stats_select(cpma* set, uint32_t phase_mask);
 cpma_status cpma_stats_get(const cpma* set, cpma_phase_stat* out, int n);
 
 /* Frees the handle and all its device memory.  NULL is a no-op. */

@@ -107,6 +107,7 @@ def lib():
         L.cpma_clock_ns.argtypes = []
         L.cpma_clock_ns.restype = u64
         L.cpma_stats_enable.argtypes = [vp, ctypes.c_int]
+        L.cpma_stats_select.argtypes = [vp, ctypes.c_uint32]
         L.cpma_stats_get.argtypes = [vp, ctypes.POINTER(PhaseStat), ctypes.c_int]
         L.cpma_autotune.argtypes = [vp, u64, ctypes.c_int, ctypes.POINTER(TuneHint), ctypes.POINTER(Config),
                                     vp, ctypes.POINTER(Config), ctypes.POINTER(TuneReport)]
@@ -327,6 +328,14 @@ class CPMA:
     def stats_enable(self, on=True):
         """Starts (zeroing) or stops per-phase HIP-event timing inside the library."""
         _check(lib().cpma_stats_enable(self._h, 1 if on else 0), "cpma_stats_enable")
+
+    def stats_select(self, phases):
+        """Starts (zeroing) HIP-event timing of the named phases only (see PHASES);
+        an empty list stops it."""
+        mask = 0
+        for name in phases:
+            mask |= 1 << PHASES.index(name)
+        _check(lib().cpma_stats_select(self._h, mask), "cpma_stats_select")
 
     def stats(self):
         """{phase: (launches, ms, algorithmic bytes)} accumulated since stats_enable."""

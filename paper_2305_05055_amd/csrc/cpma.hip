@@ -139,6 +139,7 @@ struct cpma {
   bool broken = false;
   // phase statistics (cpma_stats_*)
   bool stats_on = false;
+  uint32_t stats_mask = 0;  // phases timed while stats_on: bit (1 << phase)
   cpma_phase_stat stats[CPMA_PHASE_NUM];
   struct Pending {
     int phase;
@@ -239,7 +240,7 @@ hipEvent_t get_event(cpma* s) {
 }
 
 PhaseMark phase_begin(cpma* s, int phase, hipStream_t st) {
-  if (!s->stats_on) return PhaseMark{-1, nullptr};
+  if (!s->stats_on || !((s->stats_mask >> phase) & 1u)) return PhaseMark{-1, nullptr};
   hipEvent_t e = get_event(s);
   HIPCHK(hipEventRecord(e, st));
   return PhaseMark{phase, e};
@@ -802,8 +803,8 @@ uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1) {
     if (after_merge) {
       if (c.reserved) throw Fail{CPMA_ERR_RESERVED_KEY};  // small batch: nothing was merged
       if (s->stats_on) {
-        s->stats[CPMA_PHASE_MERGE].alg_bytes += c.alg_bytes;
-        s->stats[CPMA_PHASE_HEAVY].alg_bytes += c.alg_bytes_h;
+        if ((s->stats_mask >> CPMA_PHASE_MERGE) & 1u) s->stats[CPMA_PHASE_MERGE].alg_bytes += c.alg_bytes;
+        if ((s->stats_mask >> CPMA_PHASE_HEAVY) & 1u) s->stats[CPMA_PHASE_HEAVY].alg_bytes += c.alg_bytes_h;
       }
       delta = c.delta;
       if (merged)
@@ -1425,7 +1426,7 @@ cpma_status cpma_range_map(const cpma* cs, const uint64_t* lo, const uint64_t* h
     const uint32_t blocks = (uint32_t)s->num_cus * 8;
     const uint64_t nslots = ewaves + 4ull * blocks;
     unsigned long long* qalg = nullptr;
-    if (s->stats_on) {
+    if (s->stats_on && ((s->stats_mask >> CPMA_PHASE_RANGE_SCAN) & 1u)) {
       ensure(s->qparts, 8 * nslots);
       qalg = s->qparts.as<unsigned long long>();
     }
@@ -1629,21 +1630,26 @@ cpma_status cpma_export(const cpma* cs, uint8_t* bytes, uint32_t* used, uint64_t
   });
 }
 
-cpma_status cpma_stats_enable(cpma* s, int on) {
-  if (!s) return CPMA_ERR_INVALID;
+cpma_status cpma_stats_select(cpma* s, uint32_t phase_mask) {
+  if (!s || (phase_mask >> CPMA_PHASE_NUM) != 0) return CPMA_ERR_INVALID;
   return guarded(s, [&] {
     HIPCHK(hipSetDevice(s->device));
     HIPCHK(hipDeviceSynchronize());
     resolve_phases(s);
-    if (on) {
+    if (phase_mask) {
       ensure(s->qalg_buf, sizeof(unsigned long long), 0.0);
       s->dqalg = s->qalg_buf.as<unsigned long long>();
       HIPCHK(hipMemset(s->dqalg, 0, sizeof(unsigned long long)));
       HIPCHK(hipDeviceSynchronize());
       memset(s->stats, 0, sizeof(s->stats));
     }
-    s->stats_on = on != 0;
+    s->stats_on = phase_mask != 0;
+    s->stats_mask = phase_mask;
   });
+}
+
+cpma_status cpma_stats_enable(cpma* s, int on) {
+  return cpma_stats_select(s, on ? (1u << CPMA_PHASE_NUM) - 1u : 0u);
 }
 
 cpma_status cpma_stats_get(const cpma* cs, cpma_phase_stat* out, int n) {

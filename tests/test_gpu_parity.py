@@ -183,6 +183,27 @@ def test_single_descent_detected(cp, orc, p):
     check(c, expect, orc)
 
 
+def test_phase_statistics_select(cp, orc):
+    """Phase timing: a selected phase alone accumulates launches, time and bytes;
+    the others stay zero; all phases when enabled; a mask bit past the last
+    phase is rejected."""
+    import ctypes
+    base = synth.uniform_keys(200_000, 49, bits=40)
+    c = cp.CPMA(base)
+    c.stats_select(["merge"])
+    c.insert_batch(synth.uniform_keys(100_000, 50, bits=40))
+    st = c.stats()
+    assert st["merge"][0] == 1 and st["merge"][1] > 0 and st["merge"][2] > 0
+    assert all(v == (0, 0.0, 0) for name, v in st.items() if name != "merge")
+    c.stats_enable(True)
+    c.insert_batch(synth.uniform_keys(100_000, 51, bits=40))
+    st = c.stats()
+    for name in ("sort", "locate", "merge", "count"):
+        assert st[name][0] >= 1 and st[name][1] > 0, name
+    c.stats_enable(False)
+    assert cp.lib().cpma_stats_select(c._h, ctypes.c_uint32(1 << 8)) == 1
+
+
 def test_delete_all_then_reinsert(cp, orc):
     keys = synth.uniform_keys(5000, 41, bits=40)
     expect = orc.build_set(keys)
