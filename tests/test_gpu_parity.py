@@ -242,6 +242,35 @@ def test_reserved_key_rejected_and_set_unchanged(cp, orc):
         cp.CPMA(bad)
 
 
+def test_large_batches_sorted_or_reserved(cp, orc):
+    """Batches large enough that their first radix pass is queued before the
+    validation result is known: one holding the reserved key (rejected, set
+    unchanged, the same batch then accepted without it), and an already sorted
+    one (the queued pass is unused)."""
+    base = synth.uniform_keys(300_000, 63, bits=40)
+    expect = orc.build_set(base)
+    c = cp.CPMA(base)
+    bad = synth.uniform_keys(200_000, 64, bits=40)
+    bad[123_456] = M64
+    with pytest.raises(cp.CpmaError) as e:
+        c.insert_batch(bad)
+    assert e.value.code == 4
+    with pytest.raises(cp.CpmaError):
+        c.delete_batch(bad)
+    check(c, expect, orc)
+    good = np.delete(bad, 123_456)
+    expect, added = orc.insert(expect, good)
+    assert c.insert_batch(good) == added
+    check(c, expect, orc)
+    srt = orc.build_set(synth.uniform_keys(150_000, 65, bits=40))
+    expect, added = orc.insert(expect, srt)
+    assert c.insert_batch(srt) == added  # sorted input, sorted flag not given
+    check(c, expect, orc)
+    expect, removed = orc.delete(expect, srt[::2])
+    assert c.delete_batch(srt[::2]) == removed
+    check(c, expect, orc)
+
+
 def test_growth_and_shrink_tiny_leaves(cp, orc):
     """64-byte leaves: many resizes up, then deletes shrink the array again."""
     c = cp.CPMA(np.empty(0, np.uint64), leaf_bytes=64)
