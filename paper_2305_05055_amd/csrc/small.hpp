@@ -70,7 +70,37 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __
     }
     return;
   }
-  // bitonic sort of n (a power of two) keys
+  // bitonic sort of n (a power of two) keys.  Up to one key per thread, a
+  // thread keeps key `tid` in a register: a stage whose partner index differs
+  // in the low 6 bits is a shuffle inside the wave, and only strides of 64 and
+  // more go through LDS (one barrier per stage).
+  if (n <= kSmallThreads) {
+    uint64_t x = tid < n ? A[tid] : kNoKey;
+    uint32_t lds_stages = 0;
+    for (uint32_t size = 2; size <= n; size <<= 1) {
+      for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+        uint64_t y;
+        if (stride >= kWave) {
+          // A[0, 1024) and A[1024, 2048) serve consecutive LDS stages in turn:
+          // a write to one follows the barrier of the stage that read the
+          // other, which every thread passed after its last read of this one
+          uint64_t* buf = A + ((lds_stages++ & 1u) ? kSmallThreads : 0u);
+          buf[tid] = x;
+          __syncthreads();
+          y = buf[tid ^ stride];
+        } else {
+          y = ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), (int)stride, kWave) << 32) |
+              (uint32_t)__shfl_xor((int)(uint32_t)x, (int)stride, kWave);
+        }
+        const bool up = (tid & size) == 0;
+        const bool lower = (tid & stride) == 0;
+        x = (lower == up) ? (x < y ? x : y) : (x < y ? y : x);
+      }
+    }
+    __syncthreads();
+    if (tid < n) A[tid] = x;
+    __syncthreads();
+  } else {
   for (uint32_t size = 2; size <= n; size <<= 1) {
     for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
       for (uint32_t t = tid; t < n / 2; t += kSmallThreads) {
@@ -85,6 +115,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __
       }
       __syncthreads();
     }
+  }
   }
   // drop repeats: each thread owns kPer consecutive positions
   const uint32_t i0 = tid * kPer;

@@ -204,6 +204,26 @@ def test_phase_statistics_select(cp, orc):
     assert cp.lib().cpma_stats_select(c._h, ctypes.c_uint32(1 << 8)) == 1
 
 
+@pytest.mark.parametrize("k", [2, 3, 63, 64, 65, 127, 128, 129, 511, 1000, 1024, 1025, 4096])
+def test_small_batch_sorting(cp, orc, k):
+    """Batches of the one-launch path, across the sort's shapes (in-wave and LDS
+    stages, one key per thread or several): random order with repeats, and
+    reversed order."""
+    base = synth.uniform_keys(20_000, 70 + k, bits=30)
+    expect = orc.build_set(base)
+    c = cp.CPMA(base, leaf_bytes=256)
+    batch = synth.uniform_keys(k, 71 + k, bits=30)
+    batch[: k // 3] = batch[k // 3: 2 * (k // 3)]  # repeats
+    expect, added = orc.insert(expect, batch)
+    assert c.insert_batch(batch) == added
+    check(c, expect, orc)
+    present = expect[:: max(1, len(expect) // (k - k // 2))][: k - k // 2]
+    rev = orc.build_set(np.concatenate([synth.uniform_keys(k // 2, 72 + k, bits=30), present]))[::-1].copy()
+    expect, removed = orc.delete(expect, rev)
+    assert c.delete_batch(rev) == removed
+    check(c, expect, orc)
+
+
 def test_delete_all_then_reinsert(cp, orc):
     keys = synth.uniform_keys(5000, 41, bits=40)
     expect = orc.build_set(keys)
