@@ -47,6 +47,10 @@ VALU_PEAK_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
 
 SCAN_KERNEL = "k_rm_interior"
 SCAN_SOURCES = ["common.hpp", "scan_lane.hpp", "query.hpp"]
+# after the timed insert steps the headline run inserts PHASE_STEPS more batches
+# (every phase timed) and deletes two: the merge launches that follow the timed ones
+PHASE_STEPS = 3
+TAIL_MERGES = PHASE_STEPS + 2
 SCAN_VALU_FILE = os.path.join(ROOT, "profiles", "k_rm_interior_valu_gate_n1e9.md")
 
 
@@ -82,7 +86,7 @@ def pmc_summary(fetch_csv, write_csv, steps, cmd_fetch, cmd_write):
         copy = max(v for _, n, _, v in rows if n == "__amd_rocclr_copyBuffer")
         factor = float(1 << 30) / (copy * 1024.0)
         merge = [v for _, n, _, v in rows if n == MERGE_KERNEL]
-        timed = merge[-(steps + 2):-2]   # the run ends with two delete batches
+        timed = merge[-(steps + TAIL_MERGES):-TAIL_MERGES]
         out[tag] = {"copy_kib": copy, "factor": factor,
                     "kib_per_launch": sum(timed) / len(timed),
                     "bytes_per_launch": sum(timed) / len(timed) * 1024.0 * factor,
@@ -427,7 +431,7 @@ def main():
         if args.valu_summary:
             cmd = (ctr + "-d /tmp/cpma_prof/pmc_valu -o run -- python3 /root/repo/bench.py --only-steps "
                    f"--no-cpu-baseline --steps {args.steps}")
-            text = valu_summary(args.valu_summary, MERGE_KERNEL, lambda v: v[-(args.steps + 2):-2],
+            text = valu_summary(args.valu_summary, MERGE_KERNEL, lambda v: v[-(args.steps + TAIL_MERGES):-TAIL_MERGES],
                                 "insert batches of 1e7 into 1e8 keys", "the headline steps (the run ends "
                                 "with two delete batches, which are left out)", cmd, MERGE_SOURCES)
             path = VALU_FILE
@@ -561,7 +565,7 @@ def main():
 
     # ---- headline: W warm-up + K timed insert batches of k keys ------------------
     nb = args.warmup + args.steps
-    n_phase_steps = 3
+    n_phase_steps = PHASE_STEPS
     batches = [to_dev(synth.uniform_keys(k, seed + 40, offset=i * k)) for i in range(nb + n_phase_steps)]
     torch.cuda.synchronize()
     for i in range(args.warmup):
