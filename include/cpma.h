@@ -29,6 +29,10 @@
  *   - Ownership: the handle owns all device memory it allocates (leaves,
  *     heads, used counts, scratch), through cpma_config's allocator hooks when
  *     they are set; cpma_destroy frees it.  Caller buffers are never retained.
+ *     cpma_build also reserves what the next growth steps need (spare leaf
+ *     arrays for one growing factor with room for another, resize scratch for
+ *     three), so that a resize soon after a build allocates nothing; scratch
+ *     buffers grow with room and are kept for reuse.
  *   - Concurrency: one writer per handle (the paper phases updates and queries,
  *     Section "Evaluation on graph workloads", F-Graph description).  Queries
  *     may run concurrently with each other on one stream, never with an

@@ -209,7 +209,7 @@ void* host_pin(cpma* s, size_t bytes) {
       hipHostFree(s->hpin);
     }
     s->hpin = nullptr;
-    size_t want = std::max<size_t>(bytes, 1 << 16);
+    size_t want = std::max<size_t>(2 * bytes, 1 << 16);  // room, so a slowly growing need reallocates rarely
     HIPCHK(hipHostMalloc(&s->hpin, want, hipHostMallocDefault));
     s->hpin_cap = want;
   }
@@ -742,6 +742,32 @@ bool split_resize(cpma* s, uint64_t Lt, uint64_t total_used, hipStream_t st, uin
   throw Fail{CPMA_ERR_DEVICE};
 }
 
+// Device memory for the next growth steps, taken when a set is built: the
+// resize's scratch arrays for three growing factors ahead, and the spare leaf
+// arrays (which trade places with the live ones at every resize) for the next
+// growth with the same room a resize leaves.  A resize then allocates nothing
+// until the set has grown well past its built size; each allocation
+// synchronises the device and takes tens to hundreds of microseconds.
+void reserve_growth(cpma* s) {
+  const double g = s->cfg.grow;
+  const uint64_t L = s->L;
+  const uint64_t Lr = (uint64_t)std::ceil((double)L * g * g * g) + 1;
+  ensure(s->lastk, Lr * sizeof(uint64_t));
+  ensure(s->lckpt, Lr * 3 * sizeof(LeafCkpt));
+  ensure(s->ne_rank, (Lr + 1) * sizeof(uint32_t));
+  ensure(s->ne_list, (Lr + 1) * sizeof(uint32_t));
+  ensure(s->chain_pfx, (Lr + 1) * sizeof(uint64_t));
+  ensure(s->srcinfo, Lr * sizeof(SrcInfo));
+  ensure(s->srec, (Lr + 1) * sizeof(SplitRec));
+  ensure(s->fail, 16);
+  make_pyramid(s, Lr);
+  const uint64_t Ln = (uint64_t)std::ceil((double)L * g) + 1;
+  const double room = std::max(0.25, g * g - 1.0 + 0.05);
+  ensure(s->spare_used, Ln * sizeof(uint32_t), room);
+  ensure(s->spare_head, Ln * sizeof(uint64_t), room);
+  ensure(s->spare_bytes, Ln * (uint64_t)s->S, room);
+}
+
 // Root out of bounds: move everything to an array grown (or shrunk) by the
 // growing factor, spread evenly (Section "Packed Memory Array", "Resizing a
 // PMA").  Returns the algorithmic bytes moved (old used bytes read, new array
@@ -1141,6 +1167,7 @@ cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpm
     }
     spread_fresh(s, K, Lt, st, K > 0);
     rebalance(s, st);
+    reserve_growth(s);
   });
   if (r != CPMA_OK) {
     cpma_destroy(s);
