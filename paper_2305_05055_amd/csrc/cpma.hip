@@ -842,7 +842,10 @@ uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1) {
       PhaseMark pr = phase_begin(s, CPMA_PHASE_REDIST, st);
       const uint64_t moved = resize(s, c.root_sum, c.root_viol, st);
       phase_end(s, pr, st, moved);
-      continue;
+      // a resize checks every node of the new tree (leaves at planning, the
+      // rest on its pyramid) before it writes, so another count would find
+      // nothing
+      return delta;
     }
     if (c.nwin == 0) return delta;
     uint64_t* hw = reinterpret_cast<uint64_t*>(host_pin(s, c.nwin * 8ull));
