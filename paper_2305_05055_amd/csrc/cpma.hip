@@ -708,22 +708,26 @@ bool split_resize(cpma* s, uint64_t Lt, uint64_t total_used, hipStream_t st, uin
                        (const uint32_t*)s->spare_used.as<uint32_t>(), (const int32_t*)nullptr,
                        (const uint32_t*)nullptr, 1, s->fail.as<uint32_t>());
     HIPCHK(hipGetLastError());
+    // the write is queued behind the check and does nothing if the check
+    // failed, so one read-back serves both
+    const double room = std::max(0.25, s->cfg.grow * s->cfg.grow - 1.0 + 0.05);
+    ensure(s->spare_bytes, Lt * (uint64_t)s->S, room);
+    ensure(s->spare_head, Lt * sizeof(uint64_t), room);
+    zero_counters(s, st);
+    auto wr = s->S <= 1024 ? k_split_write<1> : k_split_write<4>;
+    hipLaunchKernelGGL(wr, dim3(grid_for(Lt, kWave, 1u << 16)), dim3(kWave), 0, st, a, s->S,
+                       (const SplitRec*)s->srec.as<SplitRec>(), s->spare_bytes.as<uint8_t>(),
+                       s->spare_used.as<uint32_t>(), s->spare_head.as<uint64_t>(), s->dctr,
+                       (const uint32_t*)s->fail.as<uint32_t>());
+    HIPCHK(hipGetLastError());
     uint32_t* hf = reinterpret_cast<uint32_t*>(host_pin(s, 16));
     HIPCHK(hipMemcpyAsync(hf, s->fail.p, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(s->hctr, s->dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    resolve_phases(s);
     const uint32_t fail = hf[0];
     if (fail == 0) {
-      // room for the next growth too, so that alternating arrays stop reallocating
-      const double room = std::max(0.25, s->cfg.grow * s->cfg.grow - 1.0 + 0.05);
-      ensure(s->spare_bytes, Lt * (uint64_t)s->S, room);
-      ensure(s->spare_head, Lt * sizeof(uint64_t), room);
-      zero_counters(s, st);
-      auto wr = s->S <= 1024 ? k_split_write<1> : k_split_write<4>;
-      hipLaunchKernelGGL(wr, dim3(grid_for(Lt, kWave, 1u << 16)), dim3(kWave), 0, st, a, s->S,
-                         (const SplitRec*)s->srec.as<SplitRec>(), s->spare_bytes.as<uint8_t>(),
-                         s->spare_used.as<uint32_t>(), s->spare_head.as<uint64_t>(), s->dctr);
-      HIPCHK(hipGetLastError());
-      read_counters(s, st);
+      if (s->hctr->error) throw Fail{CPMA_ERR_DEVICE};
       swap_in_spare(s, Lt);
       *moved = Lt * ((uint64_t)s->S + 12);
       return true;

@@ -662,11 +662,13 @@ __device__ __forceinline__ void code_apply(uint4& o, const LeafPlan& P, int32_t 
 // next leaf's source chunks before it stores the current one.  Leaves of more
 // than two runs, and larger leaves, walk their source leaves one by one.  A
 // leaf whose length disagrees with the plan sets the error counter and is not
-// written.
+// written.  Nothing is written when the plan's check failed (*fail != 0).
 template <int kStripes>
 __global__ void __launch_bounds__(kWave) k_split_write(SplitArgs a, uint32_t S, const SplitRec* __restrict__ rec,
                                                        uint8_t* __restrict__ dbytes, uint32_t* __restrict__ dused,
-                                                       uint64_t* __restrict__ dhead, Counters* ctr) {
+                                                       uint64_t* __restrict__ dhead, Counters* ctr,
+                                                       const uint32_t* __restrict__ fail) {
+  if (*fail) return;  // the plan failed its check: nothing to write
   const int lane = lane_id();
   const int32_t q16 = 16 * lane;
   // any number of runs, descriptors and source chunks loaded on demand
