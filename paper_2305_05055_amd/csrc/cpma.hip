@@ -296,7 +296,13 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
   }
   hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(s->dinfo),
                      (uint64_t)(sizeof(BatchInfo) / 4), 0u);
-  hipLaunchKernelGGL(k_validate, dim3(grid_for(k, 256, 4096)), dim3(256), 0, st, src, k, s->dinfo);
+  // validation reads every key once and counts the first radix digit per sort
+  // tile on the way (used if the batch turns out unsorted)
+  const uint32_t nblk = (uint32_t)((k + kSortTile - 1) / kSortTile);
+  ensure(s->cnt, ((uint64_t)nblk * 256 + 1) * sizeof(uint32_t));
+  ensure(s->koff, ((uint64_t)nblk * 256 + 1) * sizeof(uint32_t));
+  hipLaunchKernelGGL(k_validate_hist, dim3(nblk), dim3(kSortThreads), 0, st, src, (uint32_t)k, s->dinfo,
+                     s->cnt.as<uint32_t>());
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(s->hinfo, s->dinfo, sizeof(BatchInfo), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -311,14 +317,12 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
     int passes = (bits + 7) / 8;
     ensure(s->kb0, k * sizeof(uint64_t));
     ensure(s->kb1, k * sizeof(uint64_t));
-    const uint32_t nblk = (uint32_t)((k + kSortTile - 1) / kSortTile);
-    ensure(s->cnt, ((uint64_t)nblk * 256 + 1) * sizeof(uint32_t));
-    ensure(s->koff, ((uint64_t)nblk * 256 + 1) * sizeof(uint32_t));
     const uint64_t* in = src;
     for (int p = 0; p < passes; p++) {
       uint64_t* out = (p & 1) ? s->kb1.as<uint64_t>() : s->kb0.as<uint64_t>();
-      hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, st, in, (uint32_t)k, 8 * p,
-                         s->cnt.as<uint32_t>());
+      if (p > 0)  // the first pass's counts came with the validation
+        hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, st, in, (uint32_t)k, 8 * p,
+                           s->cnt.as<uint32_t>());
       HIPCHK(hipGetLastError());
       scan<uint32_t>(s, s->koff.as<uint32_t>(), (uint64_t)nblk * 256, st,
                      LoadFn<uint32_t>{s->cnt.as<uint32_t>()});

@@ -73,6 +73,64 @@ __global__ void __launch_bounds__(256) k_validate(const uint64_t* __restrict__ k
   }
 }
 
+// Validation and the first radix pass's histogram in one read: one block per
+// sort tile (item i = base + 256 r + tid), the tile's digit-0 counts written as
+// k_radix_hist writes them, the batch flags as k_validate sets them.
+__global__ void __launch_bounds__(kSortThreads) k_validate_hist(const uint64_t* __restrict__ keys, uint32_t k,
+                                                                BatchInfo* info, uint32_t* __restrict__ ghist) {
+  __shared__ uint32_t h[256];
+  __shared__ uint64_t red[kSortThreads / kWave];
+  __shared__ uint32_t fl[kSortThreads / kWave];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t base = blockIdx.x * kSortTile;
+  const bool last_lane = lane_id() == kWave - 1;
+  uint64_t orv = 0;
+  uint32_t res = 0, uns = 0;
+  uint64_t x[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; r++) {
+    const uint32_t i = base + r * kSortThreads + threadIdx.x;
+    x[r] = i < k ? keys[i] : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < kSortItems; r++) {
+    const uint32_t i = base + r * kSortThreads + threadIdx.x;
+    uint64_t nx = dpp_next64(x[r]);
+    if (last_lane && i + 1 < k) nx = keys[i + 1];
+    if (i < k) {
+      orv |= x[r];
+      res |= (x[r] == kNoKey);
+      if (i + 1 < k && nx < x[r]) uns = 1;
+      atomicAdd(&h[x[r] & 255u], 1u);
+    }
+  }
+  orv = wave_or(orv);
+  const uint64_t flags = wave_or((uint64_t)(res | (uns << 1)));
+  const int wid = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    red[wid] = orv;
+    fl[wid] = (uint32_t)flags;
+  }
+  __syncthreads();
+  ghist[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+  if (threadIdx.x == 0) {
+    uint64_t o = 0;
+    uint32_t f = 0;
+#pragma unroll
+    for (int w = 0; w < kSortThreads / kWave; w++) {
+      o |= red[w];
+      f |= fl[w];
+    }
+    if (o & ~__hip_atomic_load(&info->or_all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicOr(&info->or_all, (unsigned long long)o);
+    if ((f & 1) && !__hip_atomic_load(&info->has_reserved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicOr(&info->has_reserved, 1u);
+    if ((f & 2) && !__hip_atomic_load(&info->unsorted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicOr(&info->unsorted, 1u);
+  }
+}
+
 __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t* __restrict__ in,
                                                              uint32_t n, int shift,
                                                              uint32_t* __restrict__ ghist) {
