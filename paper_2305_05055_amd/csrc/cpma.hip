@@ -823,10 +823,9 @@ uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1) {
     Pyramid P = make_pyramid(s, s->L);
     build_pyramid(s, P, s->used.as<uint32_t>(), s->L, st);
     ensure(s->win, std::max<uint64_t>(s->L, 1) * sizeof(uint64_t));
-    if (after_merge)
-      hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, &s->dctr->nwin, (uint64_t)1, 0u);
-    else
-      zero_counters(s, st);
+    // after a merge the counters are those cleared when the update began (its
+    // window count is still zero) plus the merge's totals, which are kept
+    if (!after_merge) zero_counters(s, st);
     const uint64_t nodes = (P.H == 0) ? 1 : P.off[P.H] + P.cnt[P.H];
     hipLaunchKernelGGL(k_select, dim3(grid_for(nodes, 256, 1u << 16)), dim3(256), 0, st, s->bounds(s->L), P,
                        (const uint32_t*)s->used.as<uint32_t>(), s->win.as<uint64_t>(), s->dctr);

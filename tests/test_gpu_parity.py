@@ -224,6 +224,33 @@ def test_small_batch_sorting(cp, orc, k):
     check(c, expect, orc)
 
 
+def test_many_small_batches(cp, orc):
+    """Many small batches in a row (the one-launch preparation): dense runs
+    overflow leaves and windows (redistribution, growth), scattered keys touch
+    one leaf each, and deletes of contiguous runs empty regions (lower bounds):
+    the structure is checked after every batch."""
+    base = synth.uniform_keys(30_000, 81, bits=32)
+    expect = orc.build_set(base)
+    c = cp.CPMA(base, leaf_bytes=256)
+    for step in range(45):
+        kind = step % 3
+        if kind == 0:      # a dense run of new keys inside one key range
+            x0 = int(synth.uniform_keys(1, 900 + step, bits=32)[0])
+            batch = np.arange(x0, x0 + 3 * 60, 3, dtype=np.uint64)
+        elif kind == 1:    # scattered keys
+            batch = synth.uniform_keys(20, 900 + step, bits=32)
+        else:              # deletes of a contiguous run of present keys
+            i0 = int(synth.uniform_keys(1, 900 + step, bits=20)[0]) % max(1, len(expect) - 200)
+            batch = expect[i0:i0 + 150].copy()
+        if kind == 2:
+            expect, n = orc.delete(expect, batch)
+            assert c.delete_batch(batch) == n
+        else:
+            expect, n = orc.insert(expect, batch)
+            assert c.insert_batch(batch) == n
+        check(c, expect, orc)
+
+
 def test_delete_all_then_reinsert(cp, orc):
     keys = synth.uniform_keys(5000, 41, bits=40)
     expect = orc.build_set(keys)
