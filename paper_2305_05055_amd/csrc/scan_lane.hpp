@@ -105,8 +105,14 @@ __device__ __forceinline__ LeafSum leaf_sum_range(const uint8_t* __restrict__ le
                                                   uint64_t lo, uint64_t hi) {
   LeafSum r{0, 0};
   if (used < 8) return r;
-  uint4 cur = load16(leaf);
-  uint64_t key = ((uint64_t)cur.y << 32) | cur.x;
+  // 64-byte rounds with the next round's four loads in flight (a lane walks
+  // its leaf alone, so every load would otherwise be a full round trip)
+  const uint4 z = make_uint4(0, 0, 0, 0);
+  uint4 a0 = load16(leaf);
+  uint4 a1 = 16 < used ? load16(leaf + 16) : z;
+  uint4 a2 = 32 < used ? load16(leaf + 32) : z;
+  uint4 a3 = 48 < used ? load16(leaf + 48) : z;
+  uint64_t key = ((uint64_t)a0.y << 32) | a0.x;
   if (key >= hi) return r;
   if (key >= lo) {
     r.sum += key;
@@ -115,8 +121,7 @@ __device__ __forceinline__ LeafSum leaf_sum_range(const uint8_t* __restrict__ le
   uint64_t acc = 0;
   uint32_t sh = 0;
   bool done = false;
-  for (uint32_t c = 0; c < used && !done; c += 16) {
-    if (c) cur = load16(leaf + c);
+  auto chunk = [&](const uint4 cur, uint32_t c) {
     const uint32_t words[4] = {cur.x, cur.y, cur.z, cur.w};
     const uint32_t nvalid = min(16u, used - c);
 #pragma unroll
@@ -139,6 +144,21 @@ __device__ __forceinline__ LeafSum leaf_sum_range(const uint8_t* __restrict__ le
         }
       }
     }
+  };
+  for (uint32_t c = 0; c < used && !done; c += 64) {
+    uint4 b0 = z, b1 = z, b2 = z, b3 = z;
+    if (c + 64 < used) b0 = load16(leaf + c + 64);
+    if (c + 80 < used) b1 = load16(leaf + c + 80);
+    if (c + 96 < used) b2 = load16(leaf + c + 96);
+    if (c + 112 < used) b3 = load16(leaf + c + 112);
+    chunk(a0, c);
+    if (c + 16 < used && !done) chunk(a1, c + 16);
+    if (c + 32 < used && !done) chunk(a2, c + 32);
+    if (c + 48 < used && !done) chunk(a3, c + 48);
+    a0 = b0;
+    a1 = b1;
+    a2 = b2;
+    a3 = b3;
   }
   return r;
 }
