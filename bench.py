@@ -240,6 +240,39 @@ def time_range(torch, c, dlo, dhi, reps=3):
     return out
 
 
+def redist_section(cp, torch, seed, n=10 ** 7, batches=8, k=20000):
+    """Window redistribution: a set of n uniform 40-bit keys, then insert batches
+    whose k keys all fall in one narrow key range (2^28 of the 2^40 key space, a
+    different range per batch), so that a few leaves overflow and windows of many
+    leaves are rebuilt without growing the set.  REDIST phase time and
+    algorithmic bytes (every window leaf read and rewritten) from the library's
+    HIP events."""
+    c = cp.CPMA(to_dev(synth.uniform_keys(n, seed)))
+    starts = synth.uniform_keys(batches + 1, seed + 1, bits=40)
+    bs = [to_dev(int(x0) + synth.uniform_keys(k, seed + 2 + i, bits=28)) for i, x0 in enumerate(starts)]
+    c.insert_batch(bs[0])  # warm-up
+    torch.cuda.synchronize()
+    L0 = c.geometry()[0]
+    c.stats_select(["redist"])
+    t0 = time.perf_counter()
+    for b in bs[1:]:
+        c.insert_batch(b)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = c.stats()
+    c.stats_enable(False)
+    launches, ms, alg = st["redist"]
+    out = {"n": n, "batches": batches, "batch_keys": k, "key_range_bits": 28,
+           "leaves_before": L0, "leaves_after": c.geometry()[0],
+           "insert_keys_s": batches * k / dt, "redist_rounds": launches,
+           "redist_ms_per_batch": ms / batches,
+           "redist_alg_GBps": (alg / (ms * 1e-3) / 1e9) if ms > 0 else None}
+    out["redist_frac_hbm_alg"] = out["redist_alg_GBps"] / HBM_PEAK_GBS if out["redist_alg_GBps"] else None
+    log(f"redistribution: {out}")
+    c.close()
+    return out
+
+
 def range_section(cp, torch, c, base_dev, q, seed):
     """Batched range_map on the 1e8-key set: q queries whose lengths (in keys)
     are Zipf(1.2) on 1..1e6, each covering exactly its length of the sorted set;
@@ -626,6 +659,9 @@ def main():
 
     c.close()
     torch.cuda.empty_cache()
+    if not args.only_steps:
+        result_extra["redistribution"] = redist_section(cp, torch, seed + 50)
+        torch.cuda.empty_cache()
     if not args.only_steps and args.fg_scale > 0:
         result_extra["fgraph"] = fgraph_section(cp, torch, args.fg_scale, seed + 60)
         torch.cuda.empty_cache()

@@ -534,7 +534,7 @@ void ensure_win_map(cpma* s) {
 }
 
 // Returns true when done, false when a window escalated past the root.
-bool redistribute(cpma* s, std::vector<Win> wins, hipStream_t st) {
+bool redistribute(cpma* s, std::vector<Win> wins, hipStream_t st, uint64_t* moved) {
   const int H = tree_height(s->L);
   ensure_win_map(s);
   for (int attempt = 0; attempt < 4 * (H + 2); attempt++) {
@@ -559,6 +559,9 @@ bool redistribute(cpma* s, std::vector<Win> wins, hipStream_t st) {
     for (uint32_t f : fails) any |= (f != 0);
     if (!any) {
       encode_spread(s, wa, ndst, s->bytes.as<uint8_t>(), s->used.as<uint32_t>(), s->head.as<uint64_t>(), st);
+      // algorithmic bytes: every window leaf read (at most S) and rewritten
+      // whole with its used count and head
+      *moved = ndst * (2ull * s->S + 12);
       return true;
     }
     for (size_t w = 0; w < wins.size(); w++) {
@@ -861,8 +864,9 @@ uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1) {
     std::vector<Win> wins(c.nwin);
     for (uint32_t w = 0; w < c.nwin; w++) wins[w] = Win{(int)(hw[w] >> 48), hw[w] & ((1ull << 48) - 1)};
     PhaseMark pr = phase_begin(s, CPMA_PHASE_REDIST, st);
-    const bool done = redistribute(s, wins, st);
-    phase_end(s, pr, st);
+    uint64_t moved = 0;
+    const bool done = redistribute(s, wins, st, &moved);
+    phase_end(s, pr, st, moved);
     if (!done) {
       // Escalation past the root: grow if the structure is dense, else shrink.
       const uint64_t total = c.root_sum;
