@@ -18,6 +18,7 @@
 #include "sort.hpp"
 #include "update.hpp"
 #include "merge_lane.hpp"
+#include "merge_heavy.hpp"
 #include "merge_wave.hpp"
 #include "fgraph.hpp"
 #include "resize.hpp"
@@ -350,10 +351,7 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
   return s->kdedup.as<uint64_t>();
 }
 
-size_t heavy_smem(uint32_t S) {
-  const uint32_t maxA = S - 7;
-  return 8ull * (maxA + 1) + 4ull * ((maxA + 4) & ~3u) + S;
-}
+size_t heavy_smem(uint32_t S, uint32_t cap) { return HeavyLayout(S, cap).total; }
 
 // ---------------------------------------------------------------------------
 // Redistribution of a set of windows (level, index) in place.  Returns false if
@@ -894,9 +892,9 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   // onwards (a leaf that outgrows S holds at most S + 10 bytes per new key)
   const uint64_t arena_cap = insert ? std::min<uint64_t>(s->L, kbound) * (uint64_t)(s->S + 16) + 16 * kbound + 256 : 256;
   ensure(s->arena, arena_cap, 1.0);
-  // heavy-merge staging: each heavy slice (more than kLaneHeavy keys) stages at
+  // heavy-merge staging: only slices of more than kHeavyLds keys stage, each at
   // most its own keys plus one leaf's keys
-  const uint64_t stage_cap = insert ? kbound + (kbound / kLaneHeavy + 1) * (uint64_t)s->S + 64 : 64;
+  const uint64_t stage_cap = insert ? kbound + (kbound / kHeavyLds + 1) * (uint64_t)s->S + 64 : 64;
   ensure(s->stage, stage_cap * sizeof(uint64_t));
   PhaseMark pl = phase_begin(s, CPMA_PHASE_LOCATE, st);
   const uint64_t L = s->L;
@@ -963,9 +961,13 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   const uint32_t lgrid = (uint32_t)std::min<uint64_t>((segs + 255) / 256, (uint64_t)s->num_cus * 16);
   const uint32_t wgrid = std::max(1u, (uint32_t)std::min<uint64_t>(segs, (uint64_t)s->num_cus * 40));
   const uint32_t lwaves = std::max(1u, lgrid) * (256 / kWave);
+  // heavy merge of spilled slices: at most kbound / (kWaveSlice + 1) of them,
+  // a few LDS-bound waves per CU
+  const uint32_t hgrid_spill =
+      (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, kbound / (kWaveSlice + 1)), (uint64_t)s->num_cus * 4);
   // per-wave totals: each launch owns a run of slot pairs, main-merge launches
   // first, follow-up launches after them
-  ensure(s->parts, 16ull * (2ull * wgrid + 2ull * lwaves));
+  ensure(s->parts, 16ull * (2ull * wgrid + 2ull * lwaves + std::max(hgrid_spill, 1024u)));
   unsigned long long* parts = s->parts.as<unsigned long long>();
   uint32_t n_narrow = 0, n_wide = 0;
   auto slots = [&](uint32_t waves, bool narrow) {
@@ -984,6 +986,9 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
     if (insert && kbound > kWaveSlice) {  // a slice of more than kWaveSlice keys spills
       a.part = slots(lwaves, false);
       hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 1);
+      a.part = slots(hgrid_spill, false);
+      hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid_spill), dim3(kWave), heavy_smem(s->S, kHeavyLds), st, a,
+                         kHeavyLds);
     }
     HIPCHK(hipGetLastError());
     phase_end(s, pmg, st);
@@ -998,10 +1003,9 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
     if (insert) {
       a.part = slots(lwaves, false);
       hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 1);
-    }
-    if (insert) {
-      const uint32_t hgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, kbound / kLaneHeavy), 1024);
-      hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid), dim3(kWave), heavy_smem(s->S), st, a);
+      a.part = slots(hgrid_spill, false);
+      hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid_spill), dim3(kWave), heavy_smem(s->S, kHeavyLds), st, a,
+                         kHeavyLds);
     }
     HIPCHK(hipGetLastError());
     phase_end(s, ph, st);
@@ -1013,7 +1017,8 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
     if (insert) {
       const uint32_t hgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, kbound / kLaneHeavy), 1024);
       PhaseMark ph = phase_begin(s, CPMA_PHASE_HEAVY, st);
-      hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid), dim3(kWave), heavy_smem(s->S), st, a);
+      a.part = slots(hgrid, false);
+      hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid), dim3(kWave), heavy_smem(s->S, 0), st, a, 0u);
       HIPCHK(hipGetLastError());
       phase_end(s, ph, st);
     }

@@ -1,0 +1,114 @@
+// One-wave merge of a long insert slice into its leaf (the batch-merge phase of
+// Section "Parallel Batch Updates in a PMA" for slices too long for the
+// one-key-per-lane wave merge or for one lane).
+#pragma once
+#include "update.hpp"
+
+namespace cpma_dev {
+
+// Heavy inserts: one wave merges one long insert slice into its leaf.  Each
+// output position comes from two binary searches (a batch key's rank among the
+// old keys, an old key's rank in the slice), then the merged keys are encoded
+// in place or into the arena.  A slice of at most `cap` keys is merged entirely
+// in LDS (slice and merged keys held there); a longer one reads the slice from
+// HBM and stages the merged keys in the HBM staging buffer.
+constexpr uint32_t kHeavyLds = 1024;  // longest slice merged in LDS
+
+// LDS of k_merge_heavy for leaf size S and slice capacity cap (byte offsets,
+// each 16-byte aligned for even S): old keys A (a leaf holds at most S - 7
+// keys: an 8-byte head and one byte per further key), their presence flags F,
+// the encode buffer, the slice and the merged keys.
+struct HeavyLayout {
+  uint32_t f, buf, b, c, total;
+  __host__ __device__ HeavyLayout(uint32_t S, uint32_t cap) {
+    const uint32_t maxA = S - 7;
+    f = 8u * (maxA + 1);
+    buf = f + 4u * ((maxA + 4) & ~3u);
+    b = buf + ((S + 15u) & ~15u);
+    c = b + 8u * cap;
+    total = cap ? c + 8u * (maxA + cap) : b;
+  }
+};
+
+template <bool kLds>
+__device__ __forceinline__ void heavy_slice(const MergeArgs& a, uint32_t s, uint8_t* smem, const HeavyLayout& lay,
+                                            unsigned long long& delta, unsigned long long& alg) {
+  const uint32_t S = a.S;
+  const int lane = lane_id();
+  uint64_t* A = reinterpret_cast<uint64_t*>(smem);
+  uint32_t* F = reinterpret_cast<uint32_t*>(smem + lay.f);
+  uint8_t* buf = smem + lay.buf;
+  const uint64_t leaf = a.seg_leaf[s];
+  const uint32_t b = a.seg_begin[s];
+  const uint32_t nb = a.seg_begin[s + 1] - b;
+  const uint8_t* src = a.bytes + leaf * (uint64_t)S;
+  const uint32_t used0 = a.used[leaf];
+  uint64_t* Bl = reinterpret_cast<uint64_t*>(smem + lay.b);
+  if (kLds)
+    for (uint32_t j = lane; j < nb; j += kWave) Bl[j] = a.B[b + j];
+  const uint64_t* Bs = kLds ? Bl : a.B + b;
+  const uint32_t nA = wave_decode_leaf(src, used0, [&](uint32_t i, uint64_t x, uint64_t) { A[i] = x; });
+  for (uint32_t i = lane; i <= nA; i += kWave) F[i] = 0;
+  __syncthreads();
+  for (uint32_t j = lane; j < nb; j += kWave) {
+    const uint64_t x = Bs[j];
+    const uint32_t r = lds_lower_bound(A, nA, x);
+    if (r < nA && A[r] == x) F[r] = 1;
+  }
+  __syncthreads();
+  wave_scan_inplace(F, nA + 1);
+  __syncthreads();
+  const uint32_t present = F[nA];
+  const uint32_t nC = nA + nb - present;
+  uint64_t* C;
+  if (kLds) {
+    C = reinterpret_cast<uint64_t*>(smem + lay.c);
+  } else {
+    uint64_t off = 0;
+    if (lane == 0) off = atomicAdd(&a.ctr->stage_cursor, (unsigned long long)nC);
+    off = __shfl(off, 0, kWave);
+    if (off + nC > a.stage_cap) {
+      if (lane == 0) atomicOr(&a.ctr->error, 2u);
+      return;
+    }
+    C = a.stage + off;
+  }
+  for (uint32_t j = lane; j < nb; j += kWave) {
+    const uint64_t x = Bs[j];
+    const uint32_t r = lds_lower_bound(A, nA, x);
+    if (!(r < nA && A[r] == x)) C[r + j - F[r]] = x;
+  }
+  for (uint32_t i = lane; i < nA; i += kWave) {
+    const uint32_t lb = lds_lower_bound(Bs, nb, A[i]);
+    C[i + lb - F[i]] = A[i];
+  }
+  delta += nb - present;
+  __threadfence_block();
+  __syncthreads();
+  const uint64_t written = wave_store_leaf(a, s, leaf, [&](uint32_t i) { return C[i]; }, nC, buf, used0);
+  alg += used0 + written + 8ull * nb + 20;
+  __syncthreads();
+}
+
+// Merges the slices of the heavy list.  Slices of at most cap keys stay in
+// LDS; the launch's dynamic LDS is HeavyLayout(S, cap).total.  Every block
+// writes its {keys added, algorithmic bytes} slot of a.part.
+__global__ void __launch_bounds__(kWave) k_merge_heavy(MergeArgs a, uint32_t cap) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const HeavyLayout lay(a.S, cap);
+  const uint32_t n = a.ctr->heavy;
+  unsigned long long delta = 0, alg = 0;
+  for (uint32_t h = blockIdx.x; h < n; h += gridDim.x) {
+    const uint32_t s = a.heavy_list[h];
+    if (a.seg_begin[s + 1] - a.seg_begin[s] <= cap)
+      heavy_slice<true>(a, s, smem, lay, delta, alg);
+    else
+      heavy_slice<false>(a, s, smem, lay, delta, alg);
+  }
+  if (lane_id() == 0) {
+    a.part[2 * blockIdx.x] = delta;
+    a.part[2 * blockIdx.x + 1] = alg;
+  }
+}
+
+}  // namespace cpma_dev

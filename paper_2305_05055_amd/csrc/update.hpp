@@ -321,66 +321,6 @@ __device__ uint64_t wave_store_leaf(const MergeArgs& a, uint64_t seg, uint64_t l
   return written;
 }
 
-// Heavy inserts: a slice too long for one lane.  The merged keys go to the
-// staging buffer in HBM (each output position from two binary searches), then
-// are encoded in place or into the arena.
-__global__ void __launch_bounds__(kWave) k_merge_heavy(MergeArgs a) {
-  extern __shared__ __align__(16) uint8_t smem[];
-  const uint32_t S = a.S;
-  const uint32_t maxA = S - 7;
-  uint64_t* A = reinterpret_cast<uint64_t*>(smem);
-  uint32_t* F = reinterpret_cast<uint32_t*>(A + maxA + 1);
-  uint8_t* buf = reinterpret_cast<uint8_t*>(F + ((maxA + 4) & ~3u));
-  const int lane = lane_id();
-  const uint32_t nheavy = a.ctr->heavy;
-  unsigned long long delta = 0;
-  for (uint32_t h = blockIdx.x; h < nheavy; h += gridDim.x) {
-    const uint32_t s = a.heavy_list[h];
-    const uint64_t leaf = a.seg_leaf[s];
-    const uint32_t b = a.seg_begin[s], e = a.seg_begin[s + 1];
-    const uint32_t nb = e - b;
-    const uint64_t* Bs = a.B + b;
-    const uint8_t* src = a.bytes + leaf * (uint64_t)S;
-    const uint32_t used0 = a.used[leaf];
-    const uint32_t nA = wave_decode_leaf(src, used0, [&](uint32_t i, uint64_t x, uint64_t) { A[i] = x; });
-    for (uint32_t i = lane; i <= nA; i += kWave) F[i] = 0;
-    __syncthreads();
-    for (uint32_t j = lane; j < nb; j += kWave) {
-      const uint64_t x = Bs[j];
-      const uint32_t r = (uint32_t)lds_lower_bound(A, nA, x);
-      if (r < nA && A[r] == x) F[r] = 1;
-    }
-    __syncthreads();
-    wave_scan_inplace(F, nA + 1);
-    __syncthreads();
-    const uint32_t present = F[nA];
-    const uint32_t nC = nA + nb - present;
-    uint64_t off = 0;
-    if (lane == 0) off = atomicAdd(&a.ctr->stage_cursor, (unsigned long long)nC);
-    off = __shfl(off, 0, kWave);
-    if (off + nC > a.stage_cap) {
-      if (lane == 0) atomicOr(&a.ctr->error, 2u);
-      continue;
-    }
-    uint64_t* C = a.stage + off;
-    for (uint32_t j = lane; j < nb; j += kWave) {
-      const uint64_t x = Bs[j];
-      const uint32_t r = (uint32_t)lds_lower_bound(A, nA, x);
-      if (!(r < nA && A[r] == x)) C[r + j - F[r]] = x;
-    }
-    for (uint32_t i = lane; i < nA; i += kWave) {
-      const uint32_t lb = (uint32_t)lower_bound_u64(Bs, nb, A[i]);
-      C[i + lb - F[i]] = A[i];
-    }
-    delta += nb - present;
-    __threadfence_block();
-    __syncthreads();
-    wave_store_leaf(a, s, leaf, [&](uint32_t i) { return C[i]; }, nC, buf, used0);
-    __syncthreads();
-  }
-  if (lane == 0 && delta) atomicAdd(&a.ctr->delta, delta);
-}
-
 // ---- counting phase: byte sums of every node of the implicit tree ----------------
 constexpr int kPyrThreads = 256;
 constexpr int kPyrLowLevels = 9;  // levels 1..9 per block of 512 leaves

@@ -151,6 +151,61 @@ def test_heavy_slice_sequential_batch(cp, orc):
     check(c, expect, orc)
 
 
+def skewed_batch(expect, sizes, seed):
+    """Clusters of consecutive keys, each starting just above a present key (so
+    each cluster lands in one leaf), with every fourth cluster key replaced by a
+    present key of the set."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    starts = rng.choice(len(expect) - 1, size=len(sizes), replace=False)
+    for st, nb in zip(starts, sizes):
+        x0 = int(expect[st]) + 1
+        gap = max(1, (int(expect[st + 1]) - x0) // (2 * nb + 1))
+        cl = np.uint64(x0) + np.arange(nb, dtype=np.uint64) * np.uint64(gap)
+        pres = expect[st: st + (nb + 3) // 4]
+        cl[::4] = pres[: len(cl[::4])]
+        parts.append(cl)
+    batch = np.concatenate(parts)
+    rng.shuffle(batch)
+    return batch
+
+
+@pytest.mark.parametrize("sizes", [[65, 100, 300, 700, 1024], [1025, 1700, 2500, 65, 4096]])
+def test_skewed_insert_slices(cp, orc, sizes):
+    """Few long insert slices (65 to 4096 keys): each goes to the one-wave heavy
+    merge, through LDS up to 1024 keys and through the staging buffer above."""
+    base = synth.uniform_keys(200000, 71, bits=40)
+    expect = orc.build_set(base)
+    c = cp.CPMA(base)
+    for seed in (1, 2):
+        batch = skewed_batch(expect, sizes, seed)
+        expect, added = orc.insert(expect, batch)
+        assert c.insert_batch(batch) == added
+        check(c, expect, orc)
+    # a small batch (the one-launch path) with the same shape
+    batch = skewed_batch(expect, [70, 1200, 300], 3)
+    assert len(batch) <= 4096
+    expect, added = orc.insert(expect, batch)
+    assert c.insert_batch(batch) == added
+    check(c, expect, orc)
+
+
+def test_many_spilled_slices(cp, orc):
+    """A batch as large as the set: every leaf gets a long slice, more slices than
+    the heavy merge takes alone, so the lane merge keeps the shorter ones and
+    the heavy merge the longer ones."""
+    base = synth.uniform_keys(1_000_000, 73, bits=40)
+    expect = orc.build_set(base)
+    c = cp.CPMA(base)
+    L, _ = c.geometry()
+    assert L > 2048
+    batch = np.concatenate([synth.uniform_keys(900_000, 74, bits=40),
+                            skewed_batch(expect, [400, 900, 2000], 5)])
+    expect, added = orc.insert(expect, batch)
+    assert c.insert_batch(batch) == added
+    check(c, expect, orc)
+
+
 def test_first_batches_locate_per_key(cp, orc):
     """The first updates of a freshly built set are batches above the one-launch
     size but below the leaf count, so the batch keys are located one by one
