@@ -983,12 +983,13 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
     // every segment in one 64-bit wave pass; long insert slices in the lane merge
     a.part = slots(wgrid, false);
     hipLaunchKernelGGL(k_merge_wave<uint64_t>, dim3(wgrid), dim3(kWave), 0, st, a, 1);
-    if (insert && kbound > kWaveSlice) {  // a slice of more than kWaveSlice keys spills
-      a.part = slots(lwaves, false);
-      hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 1);
+    if (insert && kbound > kWaveSlice) {
+      // a slice of more than kWaveSlice keys spills; a small batch spills fewer
+      // than kSpillFew slices, so the heavy merge takes them all
+      static_assert(kSmallBatch / (kWaveSlice + 1) <= kSpillFew, "small batches spill few slices");
       a.part = slots(hgrid_spill, false);
       hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid_spill), dim3(kWave), heavy_smem(s->S, kHeavyLds), st, a,
-                         kHeavyLds);
+                         kHeavyLds, 1);
     }
     HIPCHK(hipGetLastError());
     phase_end(s, pmg, st);
@@ -1005,7 +1006,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
       hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 1);
       a.part = slots(hgrid_spill, false);
       hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid_spill), dim3(kWave), heavy_smem(s->S, kHeavyLds), st, a,
-                         kHeavyLds);
+                         kHeavyLds, 0);
     }
     HIPCHK(hipGetLastError());
     phase_end(s, ph, st);
@@ -1018,7 +1019,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
       const uint32_t hgrid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, kbound / kLaneHeavy), 1024);
       PhaseMark ph = phase_begin(s, CPMA_PHASE_HEAVY, st);
       a.part = slots(hgrid, false);
-      hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid), dim3(kWave), heavy_smem(s->S, 0), st, a, 0u);
+      hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid), dim3(kWave), heavy_smem(s->S, 0), st, a, 0u, 0);
       HIPCHK(hipGetLastError());
       phase_end(s, ph, st);
     }

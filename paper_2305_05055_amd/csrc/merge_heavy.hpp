@@ -90,16 +90,19 @@ __device__ __forceinline__ void heavy_slice(const MergeArgs& a, uint32_t s, uint
   __syncthreads();
 }
 
-// Merges the slices of the heavy list.  Slices of at most cap keys stay in
-// LDS; the launch's dynamic LDS is HeavyLayout(S, cap).total.  Every block
-// writes its {keys added, algorithmic bytes} slot of a.part.
-__global__ void __launch_bounds__(kWave) k_merge_heavy(MergeArgs a, uint32_t cap) {
+// Merges the slices of the heavy list, or with from_spill those of the spill
+// list (the wave merge's long inserts, when no lane merge sorts them first).
+// Slices of at most cap keys stay in LDS; the launch's dynamic LDS is
+// HeavyLayout(S, cap).total.  Every block writes its {keys added, algorithmic
+// bytes} slot of a.part.
+__global__ void __launch_bounds__(kWave) k_merge_heavy(MergeArgs a, uint32_t cap, int from_spill) {
   extern __shared__ __align__(16) uint8_t smem[];
   const HeavyLayout lay(a.S, cap);
-  const uint32_t n = a.ctr->heavy;
+  const uint32_t n = from_spill ? a.ctr->nspill : a.ctr->heavy;
+  const uint32_t* list = from_spill ? a.spill_list : a.heavy_list;
   unsigned long long delta = 0, alg = 0;
   for (uint32_t h = blockIdx.x; h < n; h += gridDim.x) {
-    const uint32_t s = a.heavy_list[h];
+    const uint32_t s = list[h];
     if (a.seg_begin[s + 1] - a.seg_begin[s] <= cap)
       heavy_slice<true>(a, s, smem, lay, delta, alg);
     else

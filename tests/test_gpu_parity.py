@@ -170,13 +170,15 @@ def skewed_batch(expect, sizes, seed):
     return batch
 
 
+@pytest.mark.parametrize("S", [64, 1024])
 @pytest.mark.parametrize("sizes", [[65, 100, 300, 700, 1024], [1025, 1700, 2500, 65, 4096]])
-def test_skewed_insert_slices(cp, orc, sizes):
+def test_skewed_insert_slices(cp, orc, sizes, S):
     """Few long insert slices (65 to 4096 keys): each goes to the one-wave heavy
-    merge, through LDS up to 1024 keys and through the staging buffer above."""
+    merge, through LDS up to 1024 keys and through the staging buffer above
+    (with 64-byte leaves every such leaf overflows into the arena)."""
     base = synth.uniform_keys(200000, 71, bits=40)
     expect = orc.build_set(base)
-    c = cp.CPMA(base)
+    c = cp.CPMA(base, leaf_bytes=S)
     for seed in (1, 2):
         batch = skewed_batch(expect, sizes, seed)
         expect, added = orc.insert(expect, batch)
