@@ -123,6 +123,10 @@ struct cpma {
   uint64_t L = 0, n = 0;
   int64_t q_up_leaf = 0, q_up_root = 0, q_lo_leaf = 0, q_lo_root = 0;
   DevBuf bytes, used, head;
+  // the pyramid holds every node's byte sum of the current layout: set by a
+  // count that found every node within bounds, cleared by any other use of
+  // the pyramid's memory
+  bool pyr_valid = false;
   // scratch
   DevBuf kin, kb0, kb1, kdedup, leafid, segpos, seg_leaf, seg_begin, seg_desc, heavy, spill, scan_tmp, ovf, arena,
       stage, pyr, win, wargs, cnt, koff, win_id, welem, P, ccost, ncost, lstart, planU, plan_used,
@@ -178,7 +182,7 @@ struct cpma {
 
 namespace {
 
-Pyramid make_pyramid(cpma* s, uint64_t L) {
+Pyramid pyramid_layout(uint64_t L) {
   Pyramid P;
   memset(&P, 0, sizeof(P));
   P.H = tree_height(L);
@@ -189,7 +193,16 @@ Pyramid make_pyramid(cpma* s, uint64_t L) {
     P.off[h] = off;
     off += P.cnt[h];
   }
-  ensure(s->pyr, (off + 1) * sizeof(uint64_t));
+  return P;
+}
+
+// Layout of the pyramid of L leaves with its memory; the memory's contents are
+// the caller's from here on.
+Pyramid make_pyramid(cpma* s, uint64_t L) {
+  Pyramid P = pyramid_layout(L);
+  s->pyr_valid = false;
+  const uint64_t nodes = P.H == 0 ? 0 : P.off[P.H] + P.cnt[P.H];  // above the leaves
+  ensure(s->pyr, (nodes + 1) * sizeof(uint64_t));
   P.base = s->pyr.as<uint64_t>();
   return P;
 }
@@ -816,10 +829,46 @@ uint64_t resize(cpma* s, uint64_t total, uint32_t viol, hipStream_t st) {
 // counters are still on the device: the first count only reads the structure,
 // so one read-back serves both (the merge's errors are checked before anything
 // is redistributed).  Returns the merge's delta.
-uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1) {
+// small_k: the keys of a small batch (0: not one).
+uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1, uint64_t small_k = 0) {
   uint64_t delta = 0;
+  // the merge's totals, from the first read-back after it
+  auto take_merge = [&](const Counters& c) {
+    if (c.reserved) throw Fail{CPMA_ERR_RESERVED_KEY};  // small batch: nothing was merged
+    if (s->stats_on) {
+      if ((s->stats_mask >> CPMA_PHASE_MERGE) & 1u) s->stats[CPMA_PHASE_MERGE].alg_bytes += c.alg_bytes;
+      if ((s->stats_mask >> CPMA_PHASE_HEAVY) & 1u) s->stats[CPMA_PHASE_HEAVY].alg_bytes += c.alg_bytes_h;
+    }
+    delta = c.delta;
+    if (merged)
+      s->n += delta;
+    else
+      s->n -= delta;
+  };
+  bool taken = false;
+  if (small_k && merged >= 0 && s->pyr_valid) {
+    // every node was within bounds before this batch and the pyramid is
+    // current: check only the paths of the touched leaves
+    Pyramid P = pyramid_layout(s->L);
+    P.base = s->pyr.as<uint64_t>();
+    PhaseMark pc = phase_begin(s, CPMA_PHASE_COUNT, st);
+    // (level, segment) pairs: at most min(k, L) segments on H + 1 levels
+    const uint64_t pairs = std::min<uint64_t>(small_k, s->L) * (uint64_t)(P.H + 1);
+    const uint32_t pgrid = (uint32_t)std::min<uint64_t>((pairs + kPathThreads - 1) / kPathThreads, 128);
+    hipLaunchKernelGGL(k_path_check, dim3(std::max(1u, pgrid)), dim3(kPathThreads), 0, st, s->bounds(s->L), P,
+                       (const uint32_t*)s->used.as<uint32_t>(), (const uint32_t*)s->seg_leaf.as<uint32_t>(),
+                       (const uint4*)s->seg_desc.as<uint4>(), s->dctr);
+    HIPCHK(hipGetLastError());
+    phase_end(s, pc, st);
+    read_counters(s, st);
+    const Counters c = *s->hctr;
+    take_merge(c);
+    taken = true;
+    if (!c.path_unsafe) return delta;  // the pyramid now holds the new sums
+    s->pyr_valid = false;
+  }
   for (int round = 0; round < 256; round++) {
-    const bool after_merge = round == 0 && merged >= 0;
+    const bool after_merge = round == 0 && merged >= 0 && !taken;
     PhaseMark pc = phase_begin(s, CPMA_PHASE_COUNT, st);
     Pyramid P = make_pyramid(s, s->L);
     build_pyramid(s, P, s->used.as<uint32_t>(), s->L, st);
@@ -834,18 +883,7 @@ uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1) {
     phase_end(s, pc, st, 4ull * s->L + 16ull * nodes);
     read_counters(s, st);
     const Counters c = *s->hctr;
-    if (after_merge) {
-      if (c.reserved) throw Fail{CPMA_ERR_RESERVED_KEY};  // small batch: nothing was merged
-      if (s->stats_on) {
-        if ((s->stats_mask >> CPMA_PHASE_MERGE) & 1u) s->stats[CPMA_PHASE_MERGE].alg_bytes += c.alg_bytes;
-        if ((s->stats_mask >> CPMA_PHASE_HEAVY) & 1u) s->stats[CPMA_PHASE_HEAVY].alg_bytes += c.alg_bytes_h;
-      }
-      delta = c.delta;
-      if (merged)
-        s->n += delta;
-      else
-        s->n -= delta;
-    }
+    if (after_merge) take_merge(c);
     if (c.root_viol) {
       PhaseMark pr = phase_begin(s, CPMA_PHASE_REDIST, st);
       const uint64_t moved = resize(s, c.root_sum, c.root_viol, st);
@@ -855,7 +893,10 @@ uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1) {
       // nothing
       return delta;
     }
-    if (c.nwin == 0) return delta;
+    if (c.nwin == 0) {
+      s->pyr_valid = true;  // built this round from the current sizes, all within bounds
+      return delta;
+    }
     uint64_t* hw = reinterpret_cast<uint64_t*>(host_pin(s, c.nwin * 8ull));
     HIPCHK(hipMemcpyAsync(hw, s->win.p, c.nwin * 8ull, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1028,7 +1069,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
                      (const unsigned long long*)parts, n_narrow, n_wide,
                      s->dctr);
   HIPCHK(hipGetLastError());
-  return rebalance(s, st, insert ? 1 : 0);
+  return rebalance(s, st, insert ? 1 : 0, small ? kbound : 0);
 }
 
 // Batch of k <= kSmallBatch keys at device address src (any order, repeats

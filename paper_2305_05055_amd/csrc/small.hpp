@@ -244,4 +244,112 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __
   }
 }
 
+// ---- counting for a small batch: the paths of the touched leaves only ----------
+// A rebalance ends only when its count finds no node to redistribute, so then
+// every node of the implicit tree is within its density bounds (a violating
+// node below a root within bounds has a highest violating ancestor, whose
+// parent would have been selected), and the pyramid holds every node's byte
+// sum.  A small batch changes only the leaves it touched, so only their
+// ancestors can leave their bounds.  This one-block kernel gives each of them
+// its exact new sum (old sum plus the byte growth of the touched leaves below
+// it, from a prefix sum over the segments, which are in leaf order), writes it
+// into the pyramid and checks it against the bounds of its level.  Any
+// violation sets ctr->path_unsafe, and the full count runs instead.  Every
+// block builds the prefix sum (at most kSmallBatch segments) and takes its
+// share of the (level, segment) pairs.
+constexpr uint32_t kPathThreads = 1024;
+
+__global__ void __launch_bounds__(kPathThreads) k_path_check(Bounds bd, Pyramid P, const uint32_t* __restrict__ used,
+                                                             const uint32_t* __restrict__ seg_leaf,
+                                                             const uint4* __restrict__ seg_desc, Counters* ctr) {
+  __shared__ uint32_t lf[kSmallBatch];
+  __shared__ uint64_t G[kSmallBatch + 1];  // G[t]: growth of the segments before t (mod 2^64)
+  __shared__ uint64_t wsum[kPathThreads / kWave];
+  __shared__ uint32_t bad;
+  constexpr uint32_t kPer = kSmallBatch / kPathThreads;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t T = (uint32_t)ctr->T;
+  if (T == 0 || T > kSmallBatch) {  // nothing touched (or not a small batch: let the full count decide)
+    if (tid == 0 && T > kSmallBatch) ctr->path_unsafe = 1;
+    return;
+  }
+  if (tid == 0) bad = 0;
+  uint64_t g[kPer];
+  uint64_t mine = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; q++) {
+    const uint32_t t = tid * kPer + q;
+    g[q] = 0;
+    if (t < T) {
+      const uint32_t f = seg_leaf[t];
+      lf[t] = f;
+      g[q] = (uint64_t)used[f] - (uint64_t)seg_desc[t].z;
+    }
+    mine += g[q];
+  }
+  const uint64_t incl = wave_incl_scan<uint64_t>(mine);
+  if (lane_id() == kWave - 1) wsum[tid / kWave] = incl;
+  __syncthreads();
+  uint64_t run = incl - mine;
+  for (uint32_t w = 0; w < tid / kWave; w++) run += wsum[w];
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; q++) {
+    const uint32_t t = tid * kPer + q;
+    if (t < T) {
+      G[t] = run;
+      run += g[q];
+      if (t == T - 1) G[T] = run;
+    }
+  }
+  __syncthreads();
+  // (level, segment) pairs spread over the grid; each thread first issues the
+  // loads of a chunk of pairs, then checks and stores them, so the chunk's
+  // pyramid reads are in flight together.  Only a node's first segment works.
+  constexpr uint32_t kChunk = 8;
+  const uint32_t npairs = T * (uint32_t)(bd.H + 1);
+  const uint32_t stride = gridDim.x * kPathThreads;
+  uint32_t v = 0;
+  for (uint32_t base = blockIdx.x * kPathThreads; base < npairs; base += stride * kChunk) {
+    uint64_t old[kChunk];
+    uint32_t pt[kChunk], ph[kChunk];
+#pragma unroll
+    for (uint32_t c = 0; c < kChunk; c++) {
+      const uint32_t j = base + c * stride + tid;
+      ph[c] = ~0u;
+      old[c] = 0;
+      if (j >= npairs) continue;
+      const uint32_t h = j / T, t = j - h * T;
+      const uint64_t node = (uint64_t)lf[t] >> h;
+      if (t > 0 && ((uint64_t)lf[t - 1] >> h) == node) continue;  // not the node's first segment
+      ph[c] = h;
+      pt[c] = t;
+      old[c] = h == 0 ? (uint64_t)used[node] : P.base[P.off[h] + node];  // a leaf: its new size
+    }
+#pragma unroll
+    for (uint32_t c = 0; c < kChunk; c++) {
+      if (ph[c] == ~0u) continue;
+      const uint32_t h = ph[c], t = pt[c];
+      const uint64_t node = (uint64_t)lf[t] >> h;
+      uint64_t sum = old[c];
+      if (h > 0) {
+        const uint64_t lim = (node + 1) << h;  // first leaf past the node
+        uint32_t lo = t + 1, hi = T;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if ((uint64_t)lf[mid] < lim)
+            lo = mid + 1;
+          else
+            hi = mid;
+        }
+        sum += G[lo] - G[t];
+        P.base[P.off[h] + node] = sum;
+      }
+      v |= violation(bd, (int)h, sum, node_leaves(bd.L, (int)h, node));
+    }
+  }
+  if (v) bad = 1;
+  __syncthreads();
+  if (tid == 0 && bad) ctr->path_unsafe = 1;
+}
+
 }  // namespace cpma_dev

@@ -25,6 +25,7 @@ struct Counters {
   unsigned long long alg_bytes_q;   // algorithmic HBM bytes of range scans (statistics)
   unsigned long long alg_bytes_h;   // algorithmic HBM bytes of the follow-up merges (statistics)
   unsigned int reserved;            // a small batch held the reserved key (nothing was changed)
+  unsigned int path_unsafe;         // a node on a touched path left its bounds (small-batch count)
 };
 
 __device__ __forceinline__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t x) {

@@ -308,6 +308,36 @@ def test_many_small_batches(cp, orc):
         check(c, expect, orc)
 
 
+@pytest.mark.parametrize("S,n0", [(64, 5000), (1024, 50000), (1024, 3)])
+def test_small_batch_path_counts(cp, orc, S, n0):
+    """Small batches count only the paths of the touched leaves while every node
+    was within bounds before them; a batch that pushes a path node out of bounds,
+    a resize, a large batch and deletes that shrink the set all hand over to the
+    full count.  The density bounds of every node are checked after each batch."""
+    rng = np.random.default_rng(S + n0)
+    expect = orc.build_set(synth.uniform_keys(n0, 91, bits=36))
+    c = cp.CPMA(expect, leaf_bytes=S)
+    for step in range(40):
+        r = step % 8
+        if r == 5:      # a large batch (the full pipeline and the full count)
+            batch = synth.uniform_keys(6000, 950 + step, bits=36)
+        elif r == 6 and len(expect) > 100:  # deletes of a run, then of scattered keys
+            i0 = int(rng.integers(0, len(expect) - 50))
+            batch = np.concatenate([expect[i0:i0 + 50], rng.choice(expect, size=min(300, len(expect) // 3))])
+        elif r in (2, 3):  # a dense run: overfills a leaf and its window
+            x0 = int(synth.uniform_keys(1, 950 + step, bits=36)[0])
+            batch = np.arange(x0, x0 + 2 * 200, 2, dtype=np.uint64)
+        else:           # scattered keys, 1 to 4096 of them
+            batch = synth.uniform_keys(int(rng.choice([1, 7, 100, 1000, 4096])), 950 + step, bits=36)
+        if r == 6:
+            expect, n = orc.delete(expect, batch)
+            assert c.delete_batch(batch) == n
+        else:
+            expect, n = orc.insert(expect, batch)
+            assert c.insert_batch(batch) == n
+        check(c, expect, orc)
+
+
 def test_delete_all_then_reinsert(cp, orc):
     keys = synth.uniform_keys(5000, 41, bits=40)
     expect = orc.build_set(keys)
