@@ -971,7 +971,8 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   }
   HIPCHK(hipGetLastError());
   if (s->S <= kWaveMaxS && !small) {
-    // route segments: narrow (32-bit wave merge), wide (64-bit), long insert slices (lane merge)
+    // route segments: narrow (32-bit wave merge), wide (64-bit), long insert slices
+    // (spill list: lane or heavy merge)
     const uint64_t nseg = std::min<uint64_t>(kbound, L);
     hipLaunchKernelGGL(k_classify, dim3(grid_for(nseg, 256, (uint32_t)s->num_cus * 8)), dim3(256), 0, st,
                        s->seg_desc.as<uint4>(), (const uint32_t*)s->seg_begin.as<uint32_t>(), kWaveSlice,
@@ -1021,7 +1022,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   // wide, long and heavy slices
   PhaseMark pmg = phase_begin(s, CPMA_PHASE_MERGE, st);
   if (small && s->S <= kWaveMaxS) {
-    // every segment in one 64-bit wave pass; long insert slices in the lane merge
+    // every segment in one 64-bit wave pass; long insert slices in the heavy merge
     a.part = slots(wgrid, false);
     hipLaunchKernelGGL(k_merge_wave<uint64_t>, dim3(wgrid), dim3(kWave), 0, st, a, 1);
     if (insert && kbound > kWaveSlice) {

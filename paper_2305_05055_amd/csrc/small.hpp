@@ -33,8 +33,8 @@ __device__ __forceinline__ uint32_t block_scan_u32(uint32_t v, uint32_t* wsum, u
 }
 
 // Also routes the segments: an insert slice longer than `slice` keys goes to the
-// lane merge (desc.w = 2, spill list); every other segment is merged by the
-// 64-bit wave instance (desc.w = 0).
+// spill list (desc.w = 2), which the heavy merge takes; every other segment is
+// merged by the 64-bit wave instance (desc.w = 0).
 __global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __restrict__ in, uint32_t k,
                                                               const uint64_t* __restrict__ head, uint64_t L,
                                                               const uint32_t* __restrict__ used,
