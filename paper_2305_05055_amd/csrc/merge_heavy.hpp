@@ -7,9 +7,10 @@
 namespace cpma_dev {
 
 // Heavy inserts: one wave merges one long insert slice into its leaf.  Each
-// output position comes from two binary searches (a batch key's rank among the
-// old keys, an old key's rank in the slice), then the merged keys are encoded
-// in place or into the arena.  A slice of at most `cap` keys is merged entirely
+// batch key is ranked among the old keys by binary search in LDS; an old key's
+// output position is its index plus the number of new batch keys ranked at or
+// below it (an LDS histogram of those ranks, scanned), so the slice is never
+// searched.  The merged keys are then encoded in place or into the arena.  A slice of at most `cap` keys is merged entirely
 // in LDS (slice and merged keys held there); a longer one reads the slice from
 // HBM and stages the merged keys in the HBM staging buffer.
 constexpr uint32_t kHeavyLds = 1024;  // longest slice merged in LDS
@@ -17,13 +18,15 @@ constexpr uint32_t kHeavyLds = 1024;  // longest slice merged in LDS
 // LDS of k_merge_heavy for leaf size S and slice capacity cap (byte offsets,
 // each 16-byte aligned for even S): old keys A (a leaf holds at most S - 7
 // keys: an 8-byte head and one byte per further key), their presence flags F,
-// the encode buffer, the slice and the merged keys.
+// the histogram N of the new batch keys' ranks, the encode buffer, the slice
+// and the merged keys.
 struct HeavyLayout {
-  uint32_t f, buf, b, c, total;
+  uint32_t f, n, buf, b, c, total;
   __host__ __device__ HeavyLayout(uint32_t S, uint32_t cap) {
     const uint32_t maxA = S - 7;
     f = 8u * (maxA + 1);
-    buf = f + 4u * ((maxA + 4) & ~3u);
+    n = f + 4u * ((maxA + 4) & ~3u);
+    buf = n + 4u * ((maxA + 4) & ~3u);
     b = buf + ((S + 15u) & ~15u);
     c = b + 8u * cap;
     total = cap ? c + 8u * (maxA + cap) : b;
@@ -37,6 +40,7 @@ __device__ __forceinline__ void heavy_slice(const MergeArgs& a, uint32_t s, uint
   const int lane = lane_id();
   uint64_t* A = reinterpret_cast<uint64_t*>(smem);
   uint32_t* F = reinterpret_cast<uint32_t*>(smem + lay.f);
+  uint32_t* N = reinterpret_cast<uint32_t*>(smem + lay.n);
   uint8_t* buf = smem + lay.buf;
   const uint64_t leaf = a.seg_leaf[s];
   const uint32_t b = a.seg_begin[s];
@@ -48,15 +52,24 @@ __device__ __forceinline__ void heavy_slice(const MergeArgs& a, uint32_t s, uint
     for (uint32_t j = lane; j < nb; j += kWave) Bl[j] = a.B[b + j];
   const uint64_t* Bs = kLds ? Bl : a.B + b;
   const uint32_t nA = wave_decode_leaf(src, used0, [&](uint32_t i, uint64_t x, uint64_t) { A[i] = x; });
-  for (uint32_t i = lane; i <= nA; i += kWave) F[i] = 0;
+  for (uint32_t i = lane; i <= nA; i += kWave) {
+    F[i] = 0;
+    N[i] = 0;
+  }
   __syncthreads();
   for (uint32_t j = lane; j < nb; j += kWave) {
     const uint64_t x = Bs[j];
     const uint32_t r = lds_lower_bound(A, nA, x);
-    if (r < nA && A[r] == x) F[r] = 1;
+    if (r < nA && A[r] == x)
+      F[r] = 1;
+    else
+      atomicAdd(&N[r], 1u);
   }
   __syncthreads();
+  // exclusive scans: F[i] = batch keys already present among A[0, i),
+  // N[i] = new batch keys whose rank among the old keys is below i
   wave_scan_inplace(F, nA + 1);
+  wave_scan_inplace(N, nA + 1);
   __syncthreads();
   const uint32_t present = F[nA];
   const uint32_t nC = nA + nb - present;
@@ -78,10 +91,8 @@ __device__ __forceinline__ void heavy_slice(const MergeArgs& a, uint32_t s, uint
     const uint32_t r = lds_lower_bound(A, nA, x);
     if (!(r < nA && A[r] == x)) C[r + j - F[r]] = x;
   }
-  for (uint32_t i = lane; i < nA; i += kWave) {
-    const uint32_t lb = lds_lower_bound(Bs, nb, A[i]);
-    C[i + lb - F[i]] = A[i];
-  }
+  // new batch keys before A[i]: those ranked at most i
+  for (uint32_t i = lane; i < nA; i += kWave) C[i + N[i + 1]] = A[i];
   delta += nb - present;
   __threadfence_block();
   __syncthreads();
