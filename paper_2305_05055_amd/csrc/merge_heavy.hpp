@@ -9,31 +9,50 @@ namespace cpma_dev {
 // Heavy inserts: one wave merges one long insert slice into its leaf.  Each
 // batch key is ranked among the old keys by binary search in LDS; an old key's
 // output position is its index plus the number of new batch keys ranked at or
-// below it (an LDS histogram of those ranks, scanned), so the slice is never
-// searched.  The merged keys are then encoded in place or into the arena.  A slice of at most `cap` keys is merged entirely
-// in LDS (slice and merged keys held there); a longer one reads the slice from
-// HBM and stages the merged keys in the HBM staging buffer.
-constexpr uint32_t kHeavyLds = 1024;  // longest slice merged in LDS
+// below it (an LDS histogram of those ranks, scanned), so the slice is only
+// streamed, twice.  The merged keys are built in LDS when at most ccap of them
+// result, else in the HBM staging buffer, then encoded in place or into the
+// arena.
+constexpr uint32_t kHeavyLds = 2048;  // merged keys held in LDS beyond a full leaf's
 
-// LDS of k_merge_heavy for leaf size S and slice capacity cap (byte offsets,
-// each 16-byte aligned for even S): old keys A (a leaf holds at most S - 7
-// keys: an 8-byte head and one byte per further key), their presence flags F,
-// the histogram N of the new batch keys' ranks, the encode buffer, the slice
-// and the merged keys.
+// LDS of k_merge_heavy for leaf size S and merged-key room cap beyond a full
+// leaf (byte offsets, each 16-byte aligned for even S): old keys A (a leaf
+// holds at most S - 7 keys: an 8-byte head and one byte per further key),
+// their presence flags F, the histogram N of the new batch keys' ranks, the
+// encode buffer and, with cap > 0, ccap = S - 7 + cap merged keys.
 struct HeavyLayout {
-  uint32_t f, n, buf, b, c, total;
+  uint32_t f, n, buf, c, ccap, total;
   __host__ __device__ HeavyLayout(uint32_t S, uint32_t cap) {
     const uint32_t maxA = S - 7;
     f = 8u * (maxA + 1);
     n = f + 4u * ((maxA + 4) & ~3u);
     buf = n + 4u * ((maxA + 4) & ~3u);
-    b = buf + ((S + 15u) & ~15u);
-    c = b + 8u * cap;
-    total = cap ? c + 8u * (maxA + cap) : b;
+    c = buf + ((S + 15u) & ~15u);
+    ccap = cap ? maxA + cap : 0u;
+    total = c + 8u * ccap;
   }
 };
 
-template <bool kLds>
+// Places the new batch keys and the old keys into C (LDS or staging), then
+// encodes C into the leaf.
+__device__ __forceinline__ void heavy_place(const MergeArgs& a, uint32_t s, uint64_t leaf, const uint64_t* Bs,
+                                            uint32_t nb, const uint64_t* A, const uint32_t* F, const uint32_t* N,
+                                            uint32_t nA, uint64_t* C, uint32_t nC, uint8_t* buf, uint32_t used0,
+                                            unsigned long long& alg) {
+  const int lane = lane_id();
+  for (uint32_t j = lane; j < nb; j += kWave) {
+    const uint64_t x = Bs[j];
+    const uint32_t r = lds_lower_bound(A, nA, x);
+    if (!(r < nA && A[r] == x)) C[r + j - F[r]] = x;
+  }
+  // new batch keys before A[i]: those ranked at most i
+  for (uint32_t i = lane; i < nA; i += kWave) C[i + N[i + 1]] = A[i];
+  __threadfence_block();
+  __syncthreads();
+  const uint64_t written = wave_store_leaf(a, s, leaf, [&](uint32_t i) { return C[i]; }, nC, buf, used0);
+  alg += used0 + written + 8ull * nb + 20;
+}
+
 __device__ __forceinline__ void heavy_slice(const MergeArgs& a, uint32_t s, uint8_t* smem, const HeavyLayout& lay,
                                             unsigned long long& delta, unsigned long long& alg) {
   const uint32_t S = a.S;
@@ -47,10 +66,7 @@ __device__ __forceinline__ void heavy_slice(const MergeArgs& a, uint32_t s, uint
   const uint32_t nb = a.seg_begin[s + 1] - b;
   const uint8_t* src = a.bytes + leaf * (uint64_t)S;
   const uint32_t used0 = a.used[leaf];
-  uint64_t* Bl = reinterpret_cast<uint64_t*>(smem + lay.b);
-  if (kLds)
-    for (uint32_t j = lane; j < nb; j += kWave) Bl[j] = a.B[b + j];
-  const uint64_t* Bs = kLds ? Bl : a.B + b;
+  const uint64_t* Bs = a.B + b;
   const uint32_t nA = wave_decode_leaf(src, used0, [&](uint32_t i, uint64_t x, uint64_t) { A[i] = x; });
   for (uint32_t i = lane; i <= nA; i += kWave) {
     F[i] = 0;
@@ -73,9 +89,8 @@ __device__ __forceinline__ void heavy_slice(const MergeArgs& a, uint32_t s, uint
   __syncthreads();
   const uint32_t present = F[nA];
   const uint32_t nC = nA + nb - present;
-  uint64_t* C;
-  if (kLds) {
-    C = reinterpret_cast<uint64_t*>(smem + lay.c);
+  if (nC <= lay.ccap) {
+    heavy_place(a, s, leaf, Bs, nb, A, F, N, nA, reinterpret_cast<uint64_t*>(smem + lay.c), nC, buf, used0, alg);
   } else {
     uint64_t off = 0;
     if (lane == 0) off = atomicAdd(&a.ctr->stage_cursor, (unsigned long long)nC);
@@ -84,26 +99,15 @@ __device__ __forceinline__ void heavy_slice(const MergeArgs& a, uint32_t s, uint
       if (lane == 0) atomicOr(&a.ctr->error, 2u);
       return;
     }
-    C = a.stage + off;
+    heavy_place(a, s, leaf, Bs, nb, A, F, N, nA, a.stage + off, nC, buf, used0, alg);
   }
-  for (uint32_t j = lane; j < nb; j += kWave) {
-    const uint64_t x = Bs[j];
-    const uint32_t r = lds_lower_bound(A, nA, x);
-    if (!(r < nA && A[r] == x)) C[r + j - F[r]] = x;
-  }
-  // new batch keys before A[i]: those ranked at most i
-  for (uint32_t i = lane; i < nA; i += kWave) C[i + N[i + 1]] = A[i];
   delta += nb - present;
-  __threadfence_block();
-  __syncthreads();
-  const uint64_t written = wave_store_leaf(a, s, leaf, [&](uint32_t i) { return C[i]; }, nC, buf, used0);
-  alg += used0 + written + 8ull * nb + 20;
   __syncthreads();
 }
 
 // Merges the slices of the heavy list, or with from_spill those of the spill
 // list (the wave merge's long inserts, when no lane merge sorts them first).
-// Slices of at most cap keys stay in LDS; the launch's dynamic LDS is
+// Up to S - 7 + cap merged keys stay in LDS; the launch's dynamic LDS is
 // HeavyLayout(S, cap).total.  Every block writes its {keys added, algorithmic
 // bytes} slot of a.part.
 __global__ void __launch_bounds__(kWave) k_merge_heavy(MergeArgs a, uint32_t cap, int from_spill) {
@@ -114,10 +118,7 @@ __global__ void __launch_bounds__(kWave) k_merge_heavy(MergeArgs a, uint32_t cap
   unsigned long long delta = 0, alg = 0;
   for (uint32_t h = blockIdx.x; h < n; h += gridDim.x) {
     const uint32_t s = list[h];
-    if (a.seg_begin[s + 1] - a.seg_begin[s] <= cap)
-      heavy_slice<true>(a, s, smem, lay, delta, alg);
-    else
-      heavy_slice<false>(a, s, smem, lay, delta, alg);
+    heavy_slice(a, s, smem, lay, delta, alg);
   }
   if (lane_id() == 0) {
     a.part[2 * blockIdx.x] = delta;
