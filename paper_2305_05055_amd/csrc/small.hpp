@@ -157,12 +157,15 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __
     const uint64_t st = (L + kSmallBatch - 1) / kSmallBatch;
     const uint32_t ns = (uint32_t)((L + st - 1) / st);  // samples head[i st], i < ns <= kSmallBatch
     for (uint32_t i = tid; i < ns; i += kSmallThreads) A[i] = head[(uint64_t)i * st];
-    __syncthreads();
 #pragma unroll
-    for (uint32_t q = 0; q < kPer; q++) {
-      if (mypos[q] == ~0u) continue;
-      const uint64_t x = mykeys[q];
-      B[mypos[q]] = x;
+    for (uint32_t q = 0; q < kPer; q++)
+      if (mypos[q] != ~0u) B[mypos[q]] = mykeys[q];
+    __threadfence_block();
+    __syncthreads();
+    // one key per thread (round robin): each search is a chain of dependent
+    // loads, so the keys' chains run side by side rather than kPer in a row
+    for (uint32_t u = tid; u < kp; u += kSmallThreads) {
+      const uint64_t x = B[u];
       uint32_t lo = 0, hi = ns;  // first sample above x
       while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
@@ -181,7 +184,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __
         else
           b = mid;
       }
-      LF[mypos[q]] = (uint32_t)(a ? a - 1 : 0);
+      LF[u] = (uint32_t)(a ? a - 1 : 0);
     }
   }
   __syncthreads();
