@@ -344,7 +344,10 @@ uint64_t cpma_clock_ns(void);
  *                          batch key + 20 per touched leaf
  *   CPMA_PHASE_HEAVY       the follow-up merges: leaves of wide key span, slices
  *                          longer than a wave takes, heavy slices (same bytes)
- *   CPMA_PHASE_COUNT       density counting up the implicit tree
+ *   CPMA_PHASE_COUNT       density counting up the implicit tree (a batch of at
+ *                          most 4096 keys checks only its touched leaves' paths
+ *                          when the previous count left every node within
+ *                          bounds, and counts the whole tree otherwise)
  *   CPMA_PHASE_REDIST      window redistribution and resizing
  *   CPMA_PHASE_RANGE_SCAN  the range_map scan kernel; bytes = used bytes of every
  *                          visited leaf + 32 per query
