@@ -972,7 +972,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   HIPCHK(hipGetLastError());
   if (s->S <= kWaveMaxS && !small) {
     // route segments: narrow (32-bit wave merge), wide (64-bit), long insert slices
-    // (spill list: lane or heavy merge)
+    // (spill list: heavy merge)
     const uint64_t nseg = std::min<uint64_t>(kbound, L);
     hipLaunchKernelGGL(k_classify, dim3(grid_for(nseg, 256, (uint32_t)s->num_cus * 8)), dim3(256), 0, st,
                        s->seg_desc.as<uint4>(), (const uint32_t*)s->seg_begin.as<uint32_t>(), kWaveSlice,
@@ -1026,9 +1026,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
     a.part = slots(wgrid, false);
     hipLaunchKernelGGL(k_merge_wave<uint64_t>, dim3(wgrid), dim3(kWave), 0, st, a, 1);
     if (insert && kbound > kWaveSlice) {
-      // a slice of more than kWaveSlice keys spills; a small batch spills fewer
-      // than kSpillFew slices, so the heavy merge takes them all
-      static_assert(kSmallBatch / (kWaveSlice + 1) <= kSpillFew, "small batches spill few slices");
+      // a slice of more than kWaveSlice keys spills to the heavy merge
       a.part = slots(hgrid_spill, false);
       hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid_spill), dim3(kWave), heavy_smem(s->S, kHeavyLds), st, a,
                          kHeavyLds, 1);
@@ -1043,18 +1041,16 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
     PhaseMark ph = phase_begin(s, CPMA_PHASE_HEAVY, st);
     a.part = slots(wgrid, false);
     hipLaunchKernelGGL(k_merge_wave<uint64_t>, dim3(wgrid), dim3(kWave), 0, st, a);
-    if (insert) {
-      a.part = slots(lwaves, false);
-      hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 1);
+    if (insert) {  // long insert slices, one wave each
       a.part = slots(hgrid_spill, false);
       hipLaunchKernelGGL(k_merge_heavy, dim3(hgrid_spill), dim3(kWave), heavy_smem(s->S, kHeavyLds), st, a,
-                         kHeavyLds, 0);
+                         kHeavyLds, 1);
     }
     HIPCHK(hipGetLastError());
     phase_end(s, ph, st);
   } else {
     a.part = slots(lwaves, true);
-    hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a, 0);
+    hipLaunchKernelGGL(k_merge_lane, dim3(std::max(1u, lgrid)), dim3(256), 0, st, a);
     HIPCHK(hipGetLastError());
     phase_end(s, pmg, st);
     if (insert) {

@@ -105,8 +105,8 @@ __device__ __forceinline__ void heavy_slice(const MergeArgs& a, uint32_t s, uint
   __syncthreads();
 }
 
-// Merges the slices of the heavy list, or with from_spill those of the spill
-// list (the wave merge's long inserts, when no lane merge sorts them first).
+// Merges the slices of the heavy list (the lane merge's longest), or with
+// from_spill those of the spill list (the wave merge's long inserts).
 // Up to S - 7 + cap merged keys stay in LDS; the launch's dynamic LDS is
 // HeavyLayout(S, cap).total.  Every block writes its {keys added, algorithmic
 // bytes} slot of a.part.

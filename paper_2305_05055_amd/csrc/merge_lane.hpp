@@ -188,22 +188,17 @@ struct BwdWriter {
 };
 
 constexpr uint32_t kLaneHeavy = 4096;  // inserts with longer slices take the wave path
-// Spilled slices from the wave merge: while there are at most kSpillFew of them
-// the heavy merge (one wave per slice) takes them all, since one lane walking a
-// long slice key by key is latency-bound; with more, the lane merge keeps those
-// of at most kLaneMid keys, which it runs many at a time.
-constexpr uint32_t kSpillFew = 2048;
-constexpr uint32_t kLaneMid = 256;
 
-// from_list: process the segments listed by the wave merge instead of all of them.
-__global__ void __launch_bounds__(256) k_merge_lane(MergeArgs a, int from_list) {
-  const uint64_t T = from_list ? (uint64_t)a.ctr->nspill : a.ctr->T;
-  const uint32_t lane_max = !from_list ? kLaneHeavy : (T <= kSpillFew ? 0u : kLaneMid);
+// The main merge for leaves larger than the wave merge takes: every segment.
+// (Long insert slices of smaller leaves go to the heavy merge instead: one lane
+// walking a slice key by key is latency-bound, about 2 us per key.)
+__global__ void __launch_bounds__(256) k_merge_lane(MergeArgs a) {
+  const uint64_t T = a.ctr->T;
   const uint64_t lanes = (uint64_t)gridDim.x * blockDim.x;
   unsigned long long delta = 0, alg = 0;
   const uint32_t S = a.S;
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < T; t += lanes) {
-    const uint64_t s = from_list ? (uint64_t)a.spill_list[t] : t;
+    const uint64_t s = t;
     const uint64_t leaf = a.seg_leaf[s];
     const uint32_t b = a.seg_begin[s], e = a.seg_begin[s + 1];
     const uint32_t nb = e - b;
@@ -211,7 +206,7 @@ __global__ void __launch_bounds__(256) k_merge_lane(MergeArgs a, int from_list) 
     uint8_t* lp = a.bytes + leaf * (uint64_t)S;
     const uint32_t used0 = a.used[leaf];
     if (a.is_insert) {
-      if (nb > lane_max) {
+      if (nb > kLaneHeavy) {
         a.heavy_list[atomicAdd(&a.ctr->heavy, 1u)] = (uint32_t)s;
         continue;
       }

@@ -57,7 +57,7 @@ __device__ __forceinline__ void put_key_bytes(uint8_t* dst, bool head, KT x, KT 
 // KT = uint32_t: keys are stored in LDS as offsets from the segment's smallest
 // possible key (segments flagged wide are handed to the 64-bit instance), which
 // halves the dominant LDS array.  KT = uint64_t: processes the handed-over list,
-// or with all_segments every segment not routed to the lane merge (small
+// or with all_segments every segment not routed to the heavy merge (small
 // batches: one launch instead of two).
 template <typename KT>
 __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segments = 0) {

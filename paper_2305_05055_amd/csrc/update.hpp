@@ -19,7 +19,7 @@ struct Counters {
   unsigned int nwin;                // windows selected for redistribution
   unsigned int root_viol;           // violation bits of the root
   unsigned int error;               // internal capacity overflow (bug guard)
-  unsigned int nspill;              // segments the wave merge hands to the lane merge
+  unsigned int nspill;              // segments the wave merge hands to the heavy merge
   unsigned int nwide;               // segments whose key span needs 64-bit merge keys
   unsigned long long alg_bytes;     // algorithmic HBM bytes of the merge (statistics)
   unsigned long long alg_bytes_q;   // algorithmic HBM bytes of range scans (statistics)
@@ -160,7 +160,7 @@ __device__ __forceinline__ void wave_append(uint32_t* __restrict__ list, unsigne
 }
 
 // Segment routing for the wave merge: inserts with more keys than one wave takes
-// go to the lane merge (spill list), segments of wide key span to the 64-bit
+// go to the heavy merge (spill list), segments of wide key span to the 64-bit
 // instance (wide list); desc.w becomes 0 (narrow instance), 1 (wide) or 2 (spill).
 __global__ void k_classify(uint4* __restrict__ seg_desc, const uint32_t* __restrict__ seg_begin, uint32_t slice,
                            int is_insert, uint32_t* __restrict__ wide_list, uint32_t* __restrict__ spill_list,
@@ -198,7 +198,7 @@ struct MergeArgs {
   const uint32_t* seg_begin;
   const uint4* seg_desc;  // {leaf, slice begin, used before the merge, wide span}
   uint32_t* heavy_list;
-  uint32_t* spill_list;   // segments routed from the wave merge to the lane merge
+  uint32_t* spill_list;   // segments routed from the wave merge to the heavy merge
   uint32_t* wide_list;    // segments whose keys span more than 2^32
   Counters* ctr;
   unsigned long long* part;  // per wave of the launch: {keys added / removed, algorithmic bytes}
