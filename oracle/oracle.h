@@ -20,8 +20,10 @@
  *     from src<<32|dst keys and run BFS and PageRank in double precision.
  *
  * Parity pins: every function is checked by tests/test_oracle_pins.py against
- * brute force, closed forms, published LEB128 byte patterns or graph special
- * cases.  No function here is "parity unpinned".
+ * brute force, closed forms, published LEB128 byte patterns, graph special
+ * cases, a hand-computed table of the density bounds and two hand-built leaf
+ * images (one of five leaves with truncated windows at every height) with
+ * mistakes planted in them.
  */
 #ifndef CPMA_ORACLE_H
 #define CPMA_ORACLE_H

@@ -126,6 +126,24 @@ def test_codec_length_boundaries_and_roundtrip(orc):
 
 
 # ------------------------------------------------------------------------ bounds
+def test_bounds_match_hand_computed_table(orc):
+    """Every interior bound, not only the ends, against the table worked out by
+    hand in tests/golden/density_bounds_table.txt (H = 3, 5, 19)."""
+    rows = 0
+    with open(os.path.join(GOLDEN, "density_bounds_table.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            H, which, *vals = line.split()
+            H = int(H)
+            assert len(vals) == H + 1
+            w = 0 if which == "up" else 1
+            assert [orc.bound_q(w, h, H) for h in range(H + 1)] == [int(v) for v in vals]
+            rows += 1
+    assert rows == 6
+
+
 def test_bounds_interpolate_between_leaf_and_root(orc):
     for H in (0, 1, 5, 19):
         ups = [orc.bound_q(0, h, H) for h in range(H + 1)]
@@ -139,12 +157,12 @@ def test_bounds_interpolate_between_leaf_and_root(orc):
 
 
 # ----------------------------------------------------------------------- checker
-def _golden_image():
+def _golden_image(name="leaf_image_s64.txt"):
     S = None
     params = None
     keys = []
     leaves = []
-    with open(os.path.join(GOLDEN, "leaf_image_s64.txt")) as f:
+    with open(os.path.join(GOLDEN, name)) as f:
         for line in f:
             line = line.strip()
             if not line or line.startswith("#"):
@@ -209,6 +227,93 @@ def test_checker_rejects_planted_mistakes(orc):
     ks = np.arange(7, 7 + 50, dtype=np.uint64)
     code, msg = orc.check_image(big, np.array([57], np.uint32), np.array([7], np.uint64), 64, ks)
     assert code == 0, msg                                                # 57 <= 57.6
+
+
+def _edit_leaf(img, used, keys, leaf, S, new_used=None, append=None, step=1):
+    """Shrinks leaf `leaf` of a golden image to new_used bytes (cut at a code
+    boundary) or appends `append` one-byte deltas of `step`; returns new
+    (img, used, keys)."""
+    img, used = img.copy(), used.copy()
+    ks = keys.tolist()
+    base = leaf * S
+    first = sum(_leaf_key_count(img, used, j, S) for j in range(leaf))
+    cnt = _leaf_key_count(img, used, leaf, S)
+    mine = ks[first:first + cnt]
+    u = int(used[leaf])
+    if new_used is not None:
+        assert img[base + new_used - 1] < 0x80 or new_used == 8  # a code ends there
+        img[base + new_used:base + u] = 0
+        used[leaf] = new_used
+        mine = mine[:_leaf_key_count(img, used, leaf, S)]
+    if append:
+        img[base + u:base + u + append] = step
+        mine = mine + [mine[-1] + step * (j + 1) for j in range(append)]
+        used[leaf] = u + append
+    ks = ks[:first] + mine + ks[first + cnt:]
+    return img, used, np.array(ks, dtype=np.uint64)
+
+
+def _leaf_key_count(img, used, j, S):
+    u = int(used[j])
+    if u == 0:
+        return 0
+    codes = img[j * S + 8:j * S + u]
+    return 1 + int(np.count_nonzero(codes < 0x80))  # one terminator per code
+
+
+def test_checker_accepts_multilevel_golden_image(orc):
+    """Five leaves, H = 3: windows at h = 1, 2 and the root are close to their
+    bounds, with truncated last windows; the hand-worked figures are in the
+    fixture's header.  A checker that measured a truncated window against the
+    full 2^h * S bytes, or took H = floor(log2 L), would reject this image."""
+    S, params, keys, img, used, head = _golden_image("window_image_l5_s64.txt")
+    assert len(used) == 5 and used.tolist() == [48, 47, 48, 47, 20]
+    assert params == (0.90, 0.70, 0.10, 0.30)
+    code, msg = orc.check_image(img, used, head, S, keys)
+    assert code == 0, msg
+    assert orc.decode_image(img, used, S, 1000).tolist() == keys.tolist()
+
+
+def test_checker_multilevel_plants_rejected_for_their_reason(orc):
+    S, params, keys, img, used, head = _golden_image("window_image_l5_s64.txt")
+
+    def check(i2, u2, k2, h2=None):
+        return orc.check_image(i2, u2, head if h2 is None else h2, S, k2)
+
+    # interior window above its bound: leaves 0 and 1 grow to 55 bytes each
+    # (within 57.6 at the leaves), [0,2) = 110 > 106.7 at h = 1
+    i2, u2, k2 = _edit_leaf(img, used, keys, 0, S, append=7, step=5)
+    i2, u2, k2 = _edit_leaf(i2, u2, k2, 1, S, append=8, step=7)
+    assert u2.tolist()[:2] == [55, 55]
+    code, msg = check(i2, u2, k2)
+    assert code == 13 and msg.startswith("upper density bound violated") and "(1, 0)" in msg, msg
+    # truncated last window below its lower bound: leaf 4 keeps its head and
+    # one code, 9 bytes: 9 / 64 >= 0.10 at the leaf, < 10.7 bytes at h = 1
+    i2, u2, k2 = _edit_leaf(img, used, keys, 4, S, new_used=9)
+    code, msg = check(i2, u2, k2)
+    assert code == 14 and msg.startswith("lower density bound violated") and "(1, 4)" in msg, msg
+    # the root alone above its bound: leaf 4 grows to 40 bytes (within 49.1
+    # bytes for [4,5) at h = 2), the root holds 230 > 224.0
+    i2, u2, k2 = _edit_leaf(img, used, keys, 4, S, append=20, step=1)
+    code, msg = check(i2, u2, k2)
+    assert code == 13 and "(3, 0)" in msg, msg
+    # the root alone below its bound: leaves 0..3 shrink to 16 bytes each
+    # ([0,2) = 32 >= 21.3, [0,4) = 64 >= 59.7), the root holds 84 < 96.0
+    i2, u2, k2 = img, used, keys
+    for j in range(4):
+        i2, u2, k2 = _edit_leaf(i2, u2, k2, j, S, new_used=16)
+    code, msg = check(i2, u2, k2)
+    assert code == 14 and "(3, 0)" in msg, msg
+    # an empty leaf in a set of more than one leaf (its head takes the next
+    # leaf's head, the empty-leaf convention): rejected as an empty leaf
+    i2, u2, k2 = _edit_leaf(img, used, keys, 2, S, new_used=8)
+    i2[2 * S:3 * S] = 0
+    u2[2] = 0
+    k2 = np.array([k for k in k2.tolist() if k != 3000], dtype=np.uint64)
+    h2 = head.copy()
+    h2[2] = h2[3]
+    code, msg = check(i2, u2, k2, h2)
+    assert code == 3 and msg.startswith("empty leaf"), msg
 
 
 # ------------------------------------------------------------------------- graph
