@@ -209,6 +209,23 @@ cpma_status cpma_range_map(const cpma* set, const uint64_t* lo, const uint64_t* 
                            uint64_t q, cpma_mem mem, uint64_t* sum,
                            uint64_t* count, void* stream);
 
+/*
+ * range_map for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops that forbid hipMalloc): the same results as
+ * cpma_range_map, with every pointer (lo, hi, sum, count) in device memory of
+ * the set's GPU.  The call allocates nothing: its per-query scratch (24 bytes
+ * per query, about 1.5 MiB in all) is a fixed array that each GPU the library
+ * runs on holds until the process ends.  q is at most
+ * CPMA_NOALLOC_MAX_QUERIES (larger: CPMA_ERR_INVALID, nothing launched).
+ * Every call on one GPU shares that array: two calls whose work overlaps on
+ * one GPU (different streams, or different sets on the same GPU, without
+ * ordering between them) race and give wrong results.  Phase statistics are
+ * not recorded.  Does not synchronise `stream`.
+ */
+#define CPMA_NOALLOC_MAX_QUERIES 65536u
+cpma_status cpma_range_map_noalloc(const cpma* set, const uint64_t* lo, const uint64_t* hi,
+                                   uint64_t q, uint64_t* sum, uint64_t* count, void* stream);
+
 /* size(): number of keys.  0 for a NULL handle. */
 uint64_t cpma_size(const cpma* set);
 

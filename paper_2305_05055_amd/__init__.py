@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libcpma.so")
 
 MEM_HOST = 0
 MEM_DEVICE = 1
+NOALLOC_MAX_QUERIES = 65536  # CPMA_NOALLOC_MAX_QUERIES
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "device allocation failed", 3: "device error",
           4: "reserved key (UINT64_MAX)"}
@@ -90,6 +91,7 @@ def lib():
         L.cpma_apply_updates.argtypes = [vp, ctypes.c_uint32, vp, vp, vp, ctypes.c_int, vp, vp]
         L.cpma_contains.argtypes = [vp, vp, u64, ctypes.c_int, vp, vp]
         L.cpma_range_map.argtypes = [vp, vp, vp, u64, ctypes.c_int, vp, vp, vp]
+        L.cpma_range_map_noalloc.argtypes = [vp, vp, vp, u64, vp, vp, vp]
         L.cpma_size.argtypes = [vp]
         L.cpma_size.restype = u64
         L.cpma_bytes.argtypes = [vp]
@@ -279,6 +281,22 @@ class CPMA:
             ps, pc = ctypes.c_void_p(s.ctypes.data), ctypes.c_void_p(c.ctypes.data)
         _check(lib().cpma_range_map(self._h, plo, phi, q, mem, ps, pc,
                                     _stream(stream, mem == MEM_DEVICE)), "cpma_range_map")
+        return s, c
+
+    def range_map_noalloc(self, lo, hi, sum_out=None, count_out=None, stream=None):
+        """range_map through the entry point that allocates nothing: lo, hi and
+        the outputs are device tensors (outputs allocated here by torch unless
+        given), at most NOALLOC_MAX_QUERIES queries."""
+        plo, q, mem, klo = _keys(lo)
+        phi, q2, mem2, khi = _keys(hi)
+        if q != q2 or mem != MEM_DEVICE or mem2 != MEM_DEVICE:
+            raise ValueError("lo and hi must be device tensors of the same length")
+        import torch
+        s = torch.empty(q, dtype=torch.int64, device=lo.device) if sum_out is None else sum_out
+        c = torch.empty(q, dtype=torch.int64, device=lo.device) if count_out is None else count_out
+        _check(lib().cpma_range_map_noalloc(self._h, plo, phi, q, ctypes.c_void_p(s.data_ptr()),
+                                            ctypes.c_void_p(c.data_ptr()), _stream(stream, True)),
+               "cpma_range_map_noalloc")
         return s, c
 
     def __len__(self):

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "cpma.h"
@@ -1540,6 +1541,81 @@ cpma_status cpma_range_map(const cpma* cs, const uint64_t* lo, const uint64_t* h
       HIPCHK(hipStreamSynchronize(st));
       resolve_phases(s);
     }
+  });
+}
+
+}  // extern "C"
+
+// ---- range_map without allocation ---------------------------------------------
+// Per-query scratch of cpma_range_map_noalloc: first interior leaf, interior
+// leaf count and their prefix sums (q, q and q + 1 words), then the prefix
+// sum's block totals.  Each GPU holds one copy for the life of the process.
+namespace {
+constexpr uint64_t kNoAllocScratchWords = 3ull * CPMA_NOALLOC_MAX_QUERIES + 1024;
+}  // namespace
+static __device__ __align__(256) uint64_t scratch[kNoAllocScratchWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+uint64_t* g_noalloc_ptr[kMaxDevices];  // device address of `scratch` on each GPU, once looked up
+
+// The device address of the scratch array on `dev` (current), looked up once.
+uint64_t* noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) throw Fail{CPMA_ERR_DEVICE};
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      hipGetLastError();
+      throw Fail{CPMA_ERR_DEVICE};
+    }
+    g_noalloc_ptr[dev] = reinterpret_cast<uint64_t*>(p);
+  }
+  return g_noalloc_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+cpma_status cpma_range_map_noalloc(const cpma* cs, const uint64_t* lo, const uint64_t* hi, uint64_t q,
+                                   uint64_t* sum, uint64_t* count, void* stream) {
+  cpma* s = const_cast<cpma*>(cs);
+  if (!s) return CPMA_ERR_INVALID;
+  if (s->broken) return CPMA_ERR_DEVICE;
+  if (q > CPMA_NOALLOC_MAX_QUERIES) return CPMA_ERR_INVALID;
+  if (q == 0) return CPMA_OK;
+  if (!lo || !hi || !sum || !count) return CPMA_ERR_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  return guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    if (3 * q + 1 + scan_scratch_elems(q) > kNoAllocScratchWords) throw Fail{CPMA_ERR_DEVICE};
+    uint64_t* w = noalloc_scratch(s->device);
+    uint64_t* first = w;
+    uint64_t* nvis = w + q;
+    uint64_t* voff = w + 2 * q;          // q + 1 words
+    uint64_t* tmp = w + 3 * q + 1;       // the prefix sum's block totals
+    QueryArgs a = query_args(s);
+    a.q = q;
+    a.lo = lo;
+    a.hi = hi;
+    unsigned long long* dsum = (unsigned long long*)sum;
+    unsigned long long* dcount = (unsigned long long*)count;
+    // the same kernels as cpma_range_map, without statistics
+    const bool wave_ends = q <= (uint64_t)s->num_cus * 64;
+    const uint32_t egrid = wave_ends ? grid_for(q, 1, (uint32_t)s->num_cus * 64)
+                                     : grid_for(q, 256, (uint32_t)s->num_cus * 16);
+    if (wave_ends)
+      hipLaunchKernelGGL(k_rm_ends_wave, dim3(egrid), dim3(kWave), 0, st, a, first, nvis, dsum, dcount,
+                         (unsigned long long*)nullptr);
+    else
+      hipLaunchKernelGGL(k_rm_ends, dim3(egrid), dim3(256), 0, st, a, first, nvis, dsum, dcount,
+                         (unsigned long long*)nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(scan_exclusive<uint64_t>(LoadFn<uint64_t>{nvis}, q, voff, tmp, st));
+    hipLaunchKernelGGL(k_rm_interior, dim3((uint32_t)s->num_cus * 8), dim3(256), 0, st, a, (const uint64_t*)voff,
+                       (const uint64_t*)first, s->cfg.range_chunk, dsum, dcount, (unsigned long long*)nullptr);
+    HIPCHK(hipGetLastError());
   });
 }
 
