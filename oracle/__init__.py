@@ -31,7 +31,7 @@ def build(force=True):
     if not force and os.path.exists(_LIB):
         return _LIB
     tmp = _LIB + ".tmp"
-    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", tmp, _SRC]
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC]
     subprocess.check_call(cmd)
     os.replace(tmp, _LIB)
     return _LIB
@@ -59,6 +59,7 @@ def lib():
         L.orc_delete.restype = c_u64
         L.orc_contains.argtypes = [u64p, c_u64, u64p, c_u64, u8p]
         L.orc_range_map.argtypes = [u64p, c_u64, u64p, u64p, c_u64, u64p, u64p]
+        L.orc_range_map_threads.argtypes = [u64p, c_u64, u64p, u64p, c_u64, u64p, u64p, ctypes.c_int]
         L.orc_range_map_brute.argtypes = [u64p, c_u64, u64p, u64p, c_u64, u64p, u64p]
         L.orc_varint_encode.argtypes = [c_u64, u8p]
         L.orc_varint_encode.restype = ctypes.c_int
@@ -121,13 +122,17 @@ def contains(S, q):
     return out
 
 
-def range_map(S, lo, hi, brute=False):
+def range_map(S, lo, hi, brute=False, threads=0):
+    """threads > 0: the queries split over that many host threads."""
     S, lo, hi = _u64(S), _u64(lo), _u64(hi)
     s = np.empty(len(lo), dtype=np.uint64)
     c = np.empty(len(lo), dtype=np.uint64)
-    f = lib().orc_range_map_brute if brute else lib().orc_range_map
-    f(_p(S, ctypes.c_uint64), len(S), _p(lo, ctypes.c_uint64), _p(hi, ctypes.c_uint64),
-      len(lo), _p(s, ctypes.c_uint64), _p(c, ctypes.c_uint64))
+    args = (_p(S, ctypes.c_uint64), len(S), _p(lo, ctypes.c_uint64), _p(hi, ctypes.c_uint64),
+            len(lo), _p(s, ctypes.c_uint64), _p(c, ctypes.c_uint64))
+    if threads > 0:
+        lib().orc_range_map_threads(*args, int(threads))
+    else:
+        (lib().orc_range_map_brute if brute else lib().orc_range_map)(*args)
     return s, c
 
 

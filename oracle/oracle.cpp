@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <queue>
+#include <thread>
 #include <vector>
 
 typedef std::vector<uint64_t> Vec;
@@ -72,6 +73,21 @@ extern "C" void orc_range_map(const uint64_t* S, uint64_t n, const uint64_t* lo,
     sum[i] = s;
     count[i] = c;
   }
+}
+
+// The same queries split into contiguous blocks over `threads` host threads
+// (each block is the plain loop above); for timing the CPU baseline on all
+// host cores.
+extern "C" void orc_range_map_threads(const uint64_t* S, uint64_t n, const uint64_t* lo,
+                                      const uint64_t* hi, uint64_t q, uint64_t* sum,
+                                      uint64_t* count, int threads) {
+  if (threads < 1) threads = 1;
+  std::vector<std::thread> pool;
+  for (int t = 0; t < threads; t++) {
+    uint64_t b = q * (uint64_t)t / (uint64_t)threads, e = q * (uint64_t)(t + 1) / (uint64_t)threads;
+    pool.emplace_back([=] { orc_range_map(S, n, lo + b, hi + b, e - b, sum + b, count + b); });
+  }
+  for (auto& th : pool) th.join();
 }
 
 extern "C" void orc_range_map_brute(const uint64_t* S, uint64_t n, const uint64_t* lo,

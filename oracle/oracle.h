@@ -47,6 +47,11 @@ void orc_contains(const uint64_t* S, uint64_t n, const uint64_t* q, uint64_t nq,
 /* sum[i] = sum of x in S with lo[i] <= x < hi[i], wrapping mod 2^64; count[i] = #such x. */
 void orc_range_map(const uint64_t* S, uint64_t n, const uint64_t* lo,
                    const uint64_t* hi, uint64_t q, uint64_t* sum, uint64_t* count);
+/* orc_range_map with the queries split into contiguous blocks over `threads`
+ * host threads (timing of the CPU baseline on all host cores). */
+void orc_range_map_threads(const uint64_t* S, uint64_t n, const uint64_t* lo,
+                           const uint64_t* hi, uint64_t q, uint64_t* sum,
+                           uint64_t* count, int threads);
 /* The same by a full scan with the predicate, for tiny inputs (pins orc_range_map). */
 void orc_range_map_brute(const uint64_t* S, uint64_t n, const uint64_t* lo,
                          const uint64_t* hi, uint64_t q, uint64_t* sum,

@@ -87,6 +87,8 @@ def test_range_matches_predicate_scan(orc, seed):
     s1, c1 = orc.range_map(S, lo, hi)
     s2, c2 = orc.range_map(S, lo, hi, brute=True)
     assert np.array_equal(s1, s2) and np.array_equal(c1, c2)
+    s3, c3 = orc.range_map(S, lo, hi, threads=7)   # uneven blocks
+    assert np.array_equal(s3, s2) and np.array_equal(c3, c2)
     assert (c1[:20] == 0).all() and (s1[:20] == 0).all()
 
 
