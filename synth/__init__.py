@@ -40,6 +40,20 @@ def uniform_keys(n, seed, bits=40, offset=0):
     return z
 
 
+def uniform_keys_at(idx, seed, bits=40):
+    """The keys at positions idx of the uniform_keys stream `seed` (the stream
+    is counter-based, so any position is drawn directly)."""
+    with np.errstate(over="ignore"):
+        i = np.asarray(idx, dtype=np.uint64) + np.uint64(1)
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + i * GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    if bits < 64:
+        z &= np.uint64((1 << bits) - 1)
+    return z
+
+
 def unique_uniform_keys(n, seed, bits=40):
     """Exactly n distinct uniform keys of `bits` bits, returned in generation order.
 
@@ -97,6 +111,49 @@ def zipf_lengths(n, seed, alpha=1.2, lmax=10**6):
     cdf /= cdf[-1]
     u = uniform_float(n, seed)
     return (np.searchsorted(cdf, u, side="right") + 1).clip(1, lmax).astype(np.int64)
+
+
+def zipf_zeta(N, theta, head=1 << 20):
+    """zeta(N, theta) = sum_{i=1..N} i^-theta: the first `head` terms summed,
+    the rest by the Euler-Maclaurin formula (the integral, the end terms and
+    the first- and third-derivative corrections), which leaves an error far
+    below double rounding for the smooth tail of i^-theta."""
+    m = min(N, head)
+    i = np.arange(1, m + 1, dtype=np.float64)
+    s = float(np.sum(i ** (-theta)))
+    if N <= head:
+        return s
+    a, b = float(m), float(N)
+
+    def f(x, d=0):  # d-th derivative of x^-theta, d in {0, 1, 3}
+        c = {0: 1.0, 1: -theta, 3: -theta * (theta + 1) * (theta + 2)}[d]
+        return c * x ** (-theta - d)
+
+    integral = (b ** (1 - theta) - a ** (1 - theta)) / (1 - theta)
+    tail = integral + (f(b) - f(a)) / 2 + (f(b, 1) - f(a, 1)) / 12 - (f(b, 3) - f(a, 3)) / 720
+    return s + tail
+
+
+def zipf_keys(n, seed, bits=34, theta=0.99, offset=0):
+    """n keys in [0, 2^bits) with P(key = r - 1) proportional to r^-theta for
+    rank r in 1..2^bits, unscrambled, so the popular keys are the small ones.
+
+    The sampler is the one of Gray, Sundaresan, Englert, Baclawski and
+    Weinberger ("Quickly generating billion-record synthetic databases",
+    SIGMOD 1994), which YCSB uses with its skew constant 0.99: ranks 1 and 2
+    exactly, the others from the inverse of a continuous approximation."""
+    N = float(1 << bits)
+    zetan = zipf_zeta(1 << bits, theta)
+    zeta2 = 1.0 + 0.5 ** theta
+    alpha = 1.0 / (1.0 - theta)
+    eta = (1.0 - (2.0 / N) ** (1.0 - theta)) / (1.0 - zeta2 / zetan)
+    u = uniform_float(n, seed, offset)
+    uz = u * zetan
+    r = 1.0 + np.floor(N * (eta * u - eta + 1.0) ** alpha)
+    r = np.where(uz < zeta2, 2.0, r)
+    r = np.where(uz < 1.0, 1.0, r)
+    r = np.clip(r, 1.0, N)
+    return (r - 1.0).astype(np.uint64)
 
 
 def range_queries_width(n, seed, width, bits=40):

@@ -193,9 +193,9 @@ def test_skewed_insert_slices(cp, orc, sizes, S):
 
 
 def test_many_spilled_slices(cp, orc):
-    """A batch as large as the set: every leaf gets a long slice, more slices than
-    the heavy merge takes alone, so the lane merge keeps the shorter ones and
-    the heavy merge the longer ones."""
+    """A batch as large as the set: every leaf gets a slice of more than 64 keys,
+    and all of them (thousands) go to the one-wave heavy merge, through LDS or
+    the staging buffer."""
     base = synth.uniform_keys(1_000_000, 73, bits=40)
     expect = orc.build_set(base)
     c = cp.CPMA(base)

@@ -32,3 +32,27 @@ def test_rmat_torch_matches_numpy():
     s3, d3 = synth.rmat_edges(200000, 12, scale=10)
     deg = np.bincount(np.concatenate([s3, d3]).astype(np.int64))
     assert deg.argmax() == 0
+
+
+def test_uniform_keys_at_matches_stream():
+    full = synth.uniform_keys(5000, 77, bits=40, offset=123)
+    idx = np.array([0, 1, 17, 4999, 2500], dtype=np.int64)
+    assert np.array_equal(synth.uniform_keys_at(idx + 123, 77, bits=40), full[idx])
+
+
+def test_zipf_keys_shape():
+    """Zipf(0.99) over 2^34 ranks: keys below 2^34, the two most popular keys
+    drawn exactly with their probabilities 1 / zeta and 2^-0.99 / zeta (within
+    sampling error), rank frequencies falling, and zeta against a direct sum."""
+    n = 400000
+    k = synth.zipf_keys(n, 31)
+    assert k.dtype == np.uint64 and int(k.max()) < (1 << 34)
+    z = synth.zipf_zeta(1 << 34, 0.99)
+    f = np.bincount(k[k < 8].astype(np.int64), minlength=8) / n
+    for r, p in ((1, 1.0 / z), (2, 2.0 ** -0.99 / z)):
+        sd = (p * (1 - p) / n) ** 0.5
+        assert abs(f[r - 1] - p) < 5 * sd
+    assert all(f[i] > f[i + 1] for i in range(4))
+    i = np.arange(1, 3_000_001, dtype=np.float64)
+    assert abs(synth.zipf_zeta(3_000_000, 0.99, head=1 << 12) - float(np.sum(i ** -0.99))) < 1e-9
+    assert np.array_equal(synth.zipf_keys(100, 31, offset=50), k[50:150])
