@@ -38,9 +38,16 @@
  *     may run concurrently with each other on one stream, never with an
  *     update.
  *   - Errors: argument errors (CPMA_ERR_INVALID, CPMA_ERR_RESERVED_KEY) are
- *     detected before any mutation and leave the set unchanged.  A device or
- *     allocation failure in the middle of an update (CPMA_ERR_DEVICE,
- *     CPMA_ERR_NOMEM) leaves the handle unusable except for cpma_destroy.
+ *     detected before any mutation and leave the set unchanged.  An update
+ *     takes every device allocation it can need before it writes the
+ *     structure: its batch buffers, the overflow arena, and what a resize of
+ *     the worst case can need (the root is within its bound before the batch
+ *     and each new key adds at most 10 code bytes); a window redistribution
+ *     that cannot get its staging memory spreads the whole structure over its
+ *     own leaves instead, with the memory already taken.  So CPMA_ERR_NOMEM
+ *     from an update leaves the set unchanged and the handle usable.  A device
+ *     failure (CPMA_ERR_DEVICE: a failed launch or copy, an internal limit)
+ *     leaves the handle unusable except for cpma_destroy.
  */
 #ifndef CPMA_H
 #define CPMA_H
@@ -84,6 +91,14 @@ typedef enum { CPMA_MEM_HOST = 0, CPMA_MEM_DEVICE = 1 } cpma_mem;
  *                  row (a range query is a search then a scan, Section "Packed
  *                  Memory Array", "Design and operations"); a power of two in
  *                  [1, 64]; default 8.  Layout and results do not depend on it.
+ *   rebuild_frac   batch-size threshold of the full rebuild: an insert or
+ *                  delete batch of k >= rebuild_frac * n keys (n the set's size
+ *                  before the batch) rebuilds the whole structure -- every
+ *                  leaf merged with its slice, then all of them spread over a
+ *                  fresh array sized for build_density -- instead of counting
+ *                  and redistributing windows (Section "Parallel Batch Updates
+ *                  in a PMA" rebuilds above about n / 10, its example value).
+ *                  Default 0.1; results do not depend on it.
  *   alloc, free, ctx
  *                  device memory for everything the handle owns (leaves, heads,
  *                  used counts, counters, scratch): alloc(bytes, ctx) returns a
@@ -105,6 +120,7 @@ typedef struct {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*free)(void* ptr, void* ctx);
   void* ctx;
+  double rebuild_frac;
 } cpma_config;
 
 /* Fills *cfg with the defaults above.  Returns CPMA_ERR_INVALID if cfg is NULL. */
@@ -235,6 +251,15 @@ uint64_t cpma_size(const cpma* set);
  * Scratch buffers kept for later batches are not counted.
  */
 uint64_t cpma_bytes(const cpma* set);
+
+/*
+ * Bytes of device memory the handle holds in all: the structure (cpma_bytes),
+ * the spare leaf arrays a resize writes into, and every scratch buffer kept for
+ * later calls, each with its allocated room.  The fixed scratch of
+ * cpma_range_map_noalloc belongs to the library, not to a handle, and is not
+ * counted.  0 for a NULL handle.
+ */
+uint64_t cpma_bytes_held(const cpma* set);
 
 /* Number of leaves and leaf size in bytes of the current layout. */
 cpma_status cpma_geometry(const cpma* set, uint64_t* num_leaves, uint32_t* leaf_bytes);

@@ -33,7 +33,8 @@ class Config(ctypes.Structure):
                 ("up_leaf", ctypes.c_double), ("up_root", ctypes.c_double),
                 ("lo_leaf", ctypes.c_double), ("lo_root", ctypes.c_double),
                 ("build_density", ctypes.c_double), ("range_chunk", ctypes.c_uint32),
-                ("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p), ("ctx", ctypes.c_void_p)]
+                ("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p), ("ctx", ctypes.c_void_p),
+                ("rebuild_frac", ctypes.c_double)]
 
 
 class TuneHint(ctypes.Structure):
@@ -96,6 +97,8 @@ def lib():
         L.cpma_size.restype = u64
         L.cpma_bytes.argtypes = [vp]
         L.cpma_bytes.restype = u64
+        L.cpma_bytes_held.argtypes = [vp]
+        L.cpma_bytes_held.restype = u64
         L.cpma_geometry.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_uint32)]
         L.cpma_export.argtypes = [vp, vp, vp, vp, vp]
         L.cpma_destroy.argtypes = [vp]
@@ -307,6 +310,10 @@ class CPMA:
 
     def bytes(self):
         return int(lib().cpma_bytes(self._h))
+
+    def bytes_held(self):
+        """All device bytes the handle holds (structure, spare arrays, scratch)."""
+        return int(lib().cpma_bytes_held(self._h))
 
     def geometry(self):
         L = ctypes.c_uint64(0)

@@ -143,6 +143,9 @@ struct cpma {
   size_t hpin_cap = 0;
   uint64_t wol_L = 0;    // leaves covered by win_of_leaf's -1 initialisation
   bool broken = false;
+  // set when the current call has started writing the structure: an
+  // allocation failure after that point cannot leave the set unchanged
+  bool mutating = false;
   // phase statistics (cpma_stats_*)
   bool stats_on = false;
   uint32_t stats_mask = 0;  // phases timed while stats_on: bit (1 << phase)
@@ -269,11 +272,12 @@ void phase_end(cpma* s, const PhaseMark& m, hipStream_t st, uint64_t alg_bytes =
   s->stats[m.phase].alg_bytes += alg_bytes;
 }
 
-// Folds completed event pairs into the statistics (call after a synchronisation).
+// Folds the recorded event pairs into the statistics (waits for each pair's
+// end event: a phase may end after the call's last synchronisation).
 void resolve_phases(cpma* s) {
   for (const auto& p : s->pending) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       s->stats[p.phase].ms += ms;
       s->stats[p.phase].launches += 1;
     }
@@ -791,6 +795,56 @@ void reserve_growth(cpma* s) {
   ensure(s->spare_bytes, Ln * (uint64_t)s->S, room);
 }
 
+// Pyramid memory for Lx leaves; contents survive unless the buffer has to grow.
+void reserve_pyramid(cpma* s, uint64_t Lx) {
+  const Pyramid P = pyramid_layout(Lx);
+  const uint64_t nodes = P.H == 0 ? 0 : P.off[P.H] + P.cnt[P.H];
+  const size_t need = (nodes + 1) * sizeof(uint64_t);
+  if (s->pyr.cap < need) {
+    s->pyr_valid = false;
+    ensure(s->pyr, need);
+  }
+}
+
+// Everything the density count, a resize and the redistribution fallback can
+// need once a batch of k keys has been merged into the leaves.  Before the
+// batch the root is within its upper bound (bytes <= tau_H * L * S), and a new
+// key adds at most 10 code bytes (bytes(x - a) + bytes(b - x) - bytes(b - a)
+// <= bytes(b - x)), so after the merge the structure fits in the leaves that
+// the growth steps reach once tau_H * L * S + 10 k bytes, and 8 per leaf,
+// are under the root bound; one step more covers a fresh layout that fails a
+// bound and steps again.  A shrink needs no more than L leaves.
+void reserve_after_merge(cpma* s, uint64_t k, bool insert) {
+  const double g = s->cfg.grow;
+  const uint64_t L = s->L;
+  const __int128 total = (__int128)s->q_up_root * L * s->S / kQ + 1 + (insert ? 10 * (__int128)k : 0);
+  uint64_t Lmax = L;
+  while ((total + 8 * (__int128)Lmax) * kQ > (__int128)s->q_up_root * Lmax * s->S)
+    Lmax = std::max<uint64_t>(Lmax + 1, (uint64_t)std::ceil(g * (double)Lmax));
+  Lmax = std::max<uint64_t>(Lmax + 1, (uint64_t)std::ceil(g * (double)Lmax));
+  // a rebuild lays the keys out at build density, one step more if that fails
+  const uint64_t Lb = (uint64_t)std::ceil((double)total / (s->cfg.build_density * (double)s->S)) + 1;
+  Lmax = std::max<uint64_t>(Lmax, std::max<uint64_t>(Lb + 1, (uint64_t)std::ceil(g * (double)Lb)));
+  const double room = std::max(0.25, g * g - 1.0 + 0.05);
+  // resize: tables over the source leaves, split records and spare arrays of
+  // the destination (the same room split_resize asks for)
+  ensure(s->lastk, std::max<uint64_t>(L, 1) * sizeof(uint64_t));
+  ensure(s->lckpt, std::max<uint64_t>(L, 1) * 3 * sizeof(LeafCkpt));
+  ensure(s->ne_rank, (L + 1) * sizeof(uint32_t));
+  ensure(s->ne_list, (L + 1) * sizeof(uint32_t));
+  ensure(s->chain_pfx, (L + 1) * sizeof(uint64_t));
+  ensure(s->srcinfo, std::max<uint64_t>(L, 1) * sizeof(SrcInfo));
+  ensure(s->srec, (Lmax + 1) * sizeof(SplitRec));
+  ensure(s->fail, 16);
+  ensure(s->spare_used, Lmax * sizeof(uint32_t), room);
+  ensure(s->spare_head, Lmax * sizeof(uint64_t), room);
+  ensure(s->spare_bytes, Lmax * (uint64_t)s->S, room);
+  // counting: the pyramid and the window list; prefix sums over leaves
+  reserve_pyramid(s, Lmax);
+  ensure(s->win, Lmax * sizeof(uint64_t));
+  ensure(s->scan_tmp, scan_scratch_elems(Lmax + 1) * sizeof(uint64_t));
+}
+
 // Root out of bounds: move everything to an array grown (or shrunk) by the
 // growing factor, spread evenly (Section "Packed Memory Array", "Resizing a
 // PMA").  Returns the algorithmic bytes moved (old used bytes read, new array
@@ -824,6 +878,21 @@ uint64_t resize(cpma* s, uint64_t total, uint32_t viol, hipStream_t st) {
   return total + Lt * ((uint64_t)s->S + 12);
 }
 
+// The merge's totals from the counters read back after it: the keys it added
+// or removed, and its algorithmic bytes for the statistics.
+uint64_t take_merge(cpma* s, const Counters& c, int merged) {
+  if (c.reserved) throw Fail{CPMA_ERR_RESERVED_KEY};  // small batch: nothing was merged
+  if (s->stats_on) {
+    if ((s->stats_mask >> CPMA_PHASE_MERGE) & 1u) s->stats[CPMA_PHASE_MERGE].alg_bytes += c.alg_bytes;
+    if ((s->stats_mask >> CPMA_PHASE_HEAVY) & 1u) s->stats[CPMA_PHASE_HEAVY].alg_bytes += c.alg_bytes_h;
+  }
+  if (merged)
+    s->n += c.delta;
+  else
+    s->n -= c.delta;
+  return c.delta;
+}
+
 // Counting + redistribution until every node of the implicit tree is within its
 // bounds.
 // merged: -1 after a build; 0 / 1 right after a delete / insert merge, whose
@@ -833,19 +902,6 @@ uint64_t resize(cpma* s, uint64_t total, uint32_t viol, hipStream_t st) {
 // small_k: the keys of a small batch (0: not one).
 uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1, uint64_t small_k = 0) {
   uint64_t delta = 0;
-  // the merge's totals, from the first read-back after it
-  auto take_merge = [&](const Counters& c) {
-    if (c.reserved) throw Fail{CPMA_ERR_RESERVED_KEY};  // small batch: nothing was merged
-    if (s->stats_on) {
-      if ((s->stats_mask >> CPMA_PHASE_MERGE) & 1u) s->stats[CPMA_PHASE_MERGE].alg_bytes += c.alg_bytes;
-      if ((s->stats_mask >> CPMA_PHASE_HEAVY) & 1u) s->stats[CPMA_PHASE_HEAVY].alg_bytes += c.alg_bytes_h;
-    }
-    delta = c.delta;
-    if (merged)
-      s->n += delta;
-    else
-      s->n -= delta;
-  };
   bool taken = false;
   if (small_k && merged >= 0 && s->pyr_valid) {
     // every node was within bounds before this batch and the pyramid is
@@ -863,7 +919,7 @@ uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1, uint64_t small_k = 
     phase_end(s, pc, st);
     read_counters(s, st);
     const Counters c = *s->hctr;
-    take_merge(c);
+    delta = take_merge(s, c, merged);
     taken = true;
     if (!c.path_unsafe) return delta;  // the pyramid now holds the new sums
     s->pyr_valid = false;
@@ -884,7 +940,7 @@ uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1, uint64_t small_k = 
     phase_end(s, pc, st, 4ull * s->L + 16ull * nodes);
     read_counters(s, st);
     const Counters c = *s->hctr;
-    if (after_merge) take_merge(c);
+    if (after_merge) delta = take_merge(s, c, merged);
     if (c.root_viol) {
       PhaseMark pr = phase_begin(s, CPMA_PHASE_REDIST, st);
       const uint64_t moved = resize(s, c.root_sum, c.root_viol, st);
@@ -905,7 +961,18 @@ uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1, uint64_t small_k = 
     for (uint32_t w = 0; w < c.nwin; w++) wins[w] = Win{(int)(hw[w] >> 48), hw[w] & ((1ull << 48) - 1)};
     PhaseMark pr = phase_begin(s, CPMA_PHASE_REDIST, st);
     uint64_t moved = 0;
-    const bool done = redistribute(s, wins, st, &moved);
+    bool done;
+    try {
+      done = redistribute(s, wins, st, &moved);
+    } catch (const Fail& f) {
+      if (f.st != CPMA_ERR_NOMEM) throw;
+      // no memory for the windows' staging (it allocates before it writes):
+      // spread the whole structure over its own leaf count instead, with the
+      // memory reserved before the merge
+      if (!split_resize(s, s->L, c.root_sum, st, &moved)) throw Fail{CPMA_ERR_DEVICE};
+      phase_end(s, pr, st, moved);
+      return delta;
+    }
     phase_end(s, pr, st, moved);
     if (!done) {
       // Escalation past the root: grow if the structure is dense, else shrink.
@@ -918,34 +985,107 @@ uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1, uint64_t small_k = 
   throw Fail{CPMA_ERR_DEVICE};
 }
 
-// small: the small-batch kernel already wrote kprime, the segments, their routing and T.
-uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, hipStream_t st, bool small = false) {
-  const bool segments_ready = small;
-  ensure(s->leafid, kbound * sizeof(uint32_t));
-  ensure(s->segpos, (kbound + 1) * sizeof(uint32_t));
+// Full rebuild after a batch of at least rebuild_frac * n keys has been merged
+// into every leaf it touches: the whole structure is spread over a fresh array
+// sized for the build density (Section "Parallel Batch Updates in a PMA":
+// large batches rebuild the structure by merging the batch with all its
+// elements).  One count reads the merge's totals and the byte total; the
+// split writer then lays everything out with the same even byte split as a
+// resize, checking every node of the new tree before it writes.  Returns the
+// merge's delta.
+uint64_t rebuild(cpma* s, hipStream_t st, int merged) {
+  PhaseMark pc = phase_begin(s, CPMA_PHASE_COUNT, st);
+  Pyramid P = make_pyramid(s, s->L);
+  build_pyramid(s, P, s->used.as<uint32_t>(), s->L, st);
+  ensure(s->win, std::max<uint64_t>(s->L, 1) * sizeof(uint64_t));
+  const uint64_t nodes = (P.H == 0) ? 1 : P.off[P.H] + P.cnt[P.H];
+  hipLaunchKernelGGL(k_select, dim3(grid_for(nodes, 256, 1u << 16)), dim3(256), 0, st, s->bounds(s->L), P,
+                     (const uint32_t*)s->used.as<uint32_t>(), s->win.as<uint64_t>(), s->dctr);
+  HIPCHK(hipGetLastError());
+  phase_end(s, pc, st, 4ull * s->L + 16ull * nodes);
+  read_counters(s, st);
+  const Counters c = *s->hctr;
+  const uint64_t delta = take_merge(s, c, merged);
+  PhaseMark pr = phase_begin(s, CPMA_PHASE_REDIST, st);
+  if (s->n == 0) {
+    spread_fresh(s, 0, 1, st);
+    phase_end(s, pr, st);
+    return delta;
+  }
+  const uint64_t total = c.root_sum;
+  const uint64_t Lt =
+      std::max<uint64_t>(1, (uint64_t)std::ceil((double)total / (s->cfg.build_density * (double)s->S)));
+  uint64_t moved = 0;
+  if (!split_resize(s, Lt, total, st, &moved)) {
+    phase_end(s, pr, st);
+    rebalance(s, st);  // thresholds beyond 64 bits: the counted path
+    return delta;
+  }
+  phase_end(s, pr, st, total + moved);
+  return delta;
+}
+
+// Launch shapes of the merge kernels for a batch of at most kbound keys.
+struct MergeGrids {
+  uint32_t lgrid, wgrid, lwaves, hgrid_spill;
+  uint64_t part_slots;  // (keys changed, bytes) slot pairs of every launch
+};
+
+MergeGrids merge_grids(const cpma* s, uint64_t kbound) {
+  MergeGrids m;
+  const uint64_t segs = std::min<uint64_t>(kbound, s->L);
+  m.lgrid = (uint32_t)std::min<uint64_t>((segs + 255) / 256, (uint64_t)s->num_cus * 16);
+  m.wgrid = std::max(1u, (uint32_t)std::min<uint64_t>(segs, (uint64_t)s->num_cus * 40));
+  m.lwaves = std::max(1u, m.lgrid) * (256 / kWave);
+  // heavy merge of spilled slices: at most kbound / (kWaveSlice + 1) of them,
+  // a few LDS-bound waves per CU
+  m.hgrid_spill =
+      (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, kbound / (kWaveSlice + 1)), (uint64_t)s->num_cus * 4);
+  m.part_slots = 2ull * m.wgrid + 2ull * m.lwaves + std::max(m.hgrid_spill, 1024u);
+  return m;
+}
+
+// Every allocation a batch of at most kbound keys can need, taken before the
+// batch writes the structure: batch preparation and segments, the merge's
+// overflow arena and staging, and what follows the merge.
+void reserve_batch(cpma* s, uint64_t kbound, bool insert) {
+  const uint64_t L = s->L;
+  const uint64_t kl = std::max(kbound, L);
+  ensure(s->kdedup, kbound * sizeof(uint64_t));
+  ensure(s->leafid, (kl + 1) * sizeof(uint32_t));
+  ensure(s->segpos, (kl + 1) * sizeof(uint32_t));
   ensure(s->seg_leaf, kbound * sizeof(uint32_t));
   ensure(s->seg_begin, (kbound + 1) * sizeof(uint32_t));
   ensure(s->seg_desc, (kbound + 1) * sizeof(uint4));
   ensure(s->heavy, kbound * sizeof(uint32_t));
   ensure(s->spill, kbound * sizeof(uint32_t));
   ensure(s->wide, kbound * sizeof(uint32_t));
-  ensure(s->ovf, std::max<uint64_t>(s->L, 1) * sizeof(uint64_t));
+  ensure(s->ovf, std::max<uint64_t>(L, 1) * sizeof(uint64_t));
   // overflow arena: segment s owns s * (S + 16) + 16 * (its first batch index)
   // onwards (a leaf that outgrows S holds at most S + 10 bytes per new key)
-  const uint64_t arena_cap = insert ? std::min<uint64_t>(s->L, kbound) * (uint64_t)(s->S + 16) + 16 * kbound + 256 : 256;
+  const uint64_t arena_cap = insert ? std::min<uint64_t>(L, kbound) * (uint64_t)(s->S + 16) + 16 * kbound + 256 : 256;
   ensure(s->arena, arena_cap, 1.0);
   // heavy-merge staging: only slices of more than kHeavyLds keys stage, each at
   // most its own keys plus one leaf's keys
   const uint64_t stage_cap = insert ? kbound + (kbound / kHeavyLds + 1) * (uint64_t)s->S + 64 : 64;
   ensure(s->stage, stage_cap * sizeof(uint64_t));
+  ensure(s->parts, 16ull * merge_grids(s, kbound).part_slots);
+  ensure(s->scan_tmp, scan_scratch_elems(kl + 1) * sizeof(uint64_t));
+  reserve_after_merge(s, kbound, insert);
+}
+
+// small: the small-batch kernel already wrote kprime, the segments, their routing and T.
+// rebuild: the batch is large enough for a full rebuild instead of counting.
+uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, hipStream_t st, bool small = false,
+                     bool rebuild_all = false) {
+  const bool segments_ready = small;
+  reserve_batch(s, kbound, insert);
   PhaseMark pl = phase_begin(s, CPMA_PHASE_LOCATE, st);
   const uint64_t L = s->L;
   if (segments_ready) {
     // nothing to do: the segments come with the batch
   } else if (kbound >= L) {
     // per leaf: one search of head[f] in the batch
-    ensure(s->leafid, (L + 1) * sizeof(uint32_t));
-    ensure(s->segpos, (std::max(kbound, L) + 1) * sizeof(uint32_t));
     hipLaunchKernelGGL(k_leaf_slices, dim3(grid_for(L + 1, 256, 1u << 16)), dim3(256), 0, st, B,
                        (const unsigned long long*)&s->dctr->kprime, (const uint64_t*)s->head.as<uint64_t>(), L,
                        s->leafid.as<uint32_t>());
@@ -1000,17 +1140,10 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   a.ctr = s->dctr;
   a.S = s->S;
   a.is_insert = insert ? 1 : 0;
-  const uint64_t segs = std::min<uint64_t>(kbound, s->L);
-  const uint32_t lgrid = (uint32_t)std::min<uint64_t>((segs + 255) / 256, (uint64_t)s->num_cus * 16);
-  const uint32_t wgrid = std::max(1u, (uint32_t)std::min<uint64_t>(segs, (uint64_t)s->num_cus * 40));
-  const uint32_t lwaves = std::max(1u, lgrid) * (256 / kWave);
-  // heavy merge of spilled slices: at most kbound / (kWaveSlice + 1) of them,
-  // a few LDS-bound waves per CU
-  const uint32_t hgrid_spill =
-      (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, kbound / (kWaveSlice + 1)), (uint64_t)s->num_cus * 4);
+  const MergeGrids mg = merge_grids(s, kbound);
+  const uint32_t lgrid = mg.lgrid, wgrid = mg.wgrid, lwaves = mg.lwaves, hgrid_spill = mg.hgrid_spill;
   // per-wave totals: each launch owns a run of slot pairs, main-merge launches
   // first, follow-up launches after them
-  ensure(s->parts, 16ull * (2ull * wgrid + 2ull * lwaves + std::max(hgrid_spill, 1024u)));
   unsigned long long* parts = s->parts.as<unsigned long long>();
   uint32_t n_narrow = 0, n_wide = 0;
   auto slots = [&](uint32_t waves, bool narrow) {
@@ -1020,7 +1153,8 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   };
 
   // MERGE times exactly the main merge kernel; HEAVY the follow-up kernels for
-  // wide, long and heavy slices
+  // wide, long and heavy slices.  From here on the structure is written.
+  s->mutating = true;
   PhaseMark pmg = phase_begin(s, CPMA_PHASE_MERGE, st);
   if (small && s->S <= kWaveMaxS) {
     // every segment in one 64-bit wave pass; long insert slices in the heavy merge
@@ -1067,18 +1201,20 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
                      (const unsigned long long*)parts, n_narrow, n_wide,
                      s->dctr);
   HIPCHK(hipGetLastError());
+  if (rebuild_all) return rebuild(s, st, insert ? 1 : 0);
   return rebalance(s, st, insert ? 1 : 0, small ? kbound : 0);
+}
+
+// Whether a batch of k keys rebuilds the whole structure.
+bool wants_rebuild(const cpma* s, uint64_t k) {
+  return s->n > 0 && (double)k >= s->cfg.rebuild_frac * (double)s->n;
 }
 
 // Batch of k <= kSmallBatch keys at device address src (any order, repeats
 // allowed): one launch zeroes the counters and prepares it (sort, repeats,
 // leaves, segments), then the merge and rebalance phases run.
 uint64_t apply_small(cpma* s, const uint64_t* src, uint64_t k, bool insert, hipStream_t st) {
-  ensure(s->kdedup, k * sizeof(uint64_t));
-  ensure(s->seg_leaf, k * sizeof(uint32_t));
-  ensure(s->seg_begin, (k + 1) * sizeof(uint32_t));
-  ensure(s->seg_desc, (k + 1) * sizeof(uint4));
-  ensure(s->spill, k * sizeof(uint32_t));
+  reserve_batch(s, k, insert);
   PhaseMark pm = phase_begin(s, CPMA_PHASE_SORT, st);
   hipLaunchKernelGGL(k_small_prep, dim3(1), dim3(kSmallThreads), 0, st, src, (uint32_t)k,
                      (const uint64_t*)s->head.as<uint64_t>(), s->L, (const uint32_t*)s->used.as<uint32_t>(),
@@ -1097,7 +1233,7 @@ uint64_t apply_sorted(cpma* s, const uint64_t* B, uint64_t k, bool insert, hipSt
   hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(64), 0, st, &s->dctr->kprime, (uint64_t)1,
                      (unsigned long long)k);
   HIPCHK(hipGetLastError());
-  return apply_batch(s, B, k, insert, st);
+  return apply_batch(s, B, k, insert, st, false, wants_rebuild(s, k));
 }
 
 cpma_status check_config(const cpma_config& c) {
@@ -1110,16 +1246,26 @@ cpma_status check_config(const cpma_config& c) {
     return CPMA_ERR_INVALID;
   if (!(c.lo_root * c.grow < c.up_root)) return CPMA_ERR_INVALID;
   if (!(c.build_density > c.lo_root && c.build_density < c.up_root)) return CPMA_ERR_INVALID;
+  if (!(c.rebuild_frac > 0)) return CPMA_ERR_INVALID;
   return CPMA_OK;
 }
 
+// Runs one entry point's work.  An update takes every allocation it can need
+// before it writes the structure (reserve_batch), so CPMA_ERR_NOMEM leaves the
+// set unchanged; a device error, or an allocation that failed after the first
+// write, leaves the handle unusable.
 template <class F>
 cpma_status guarded(cpma* s, F&& f) {
+  if (s) s->mutating = false;
   try {
     f();
     return CPMA_OK;
   } catch (const Fail& e) {
-    if (s && (e.st == CPMA_ERR_DEVICE || e.st == CPMA_ERR_NOMEM)) s->broken = true;
+    if (s && e.st == CPMA_ERR_NOMEM && s->mutating) {
+      s->broken = true;
+      return CPMA_ERR_DEVICE;
+    }
+    if (s && e.st == CPMA_ERR_DEVICE) s->broken = true;
     return e.st;
   }
 }
@@ -1141,6 +1287,7 @@ cpma_status cpma_config_default(cpma_config* cfg) {
   cfg->lo_root = 0.30;
   cfg->build_density = cfg->up_root / cfg->grow;
   cfg->range_chunk = 8;
+  cfg->rebuild_frac = 1.0;
   cfg->alloc = nullptr;
   cfg->free = nullptr;
   cfg->ctx = nullptr;
@@ -1174,6 +1321,7 @@ cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpm
     if (cfg_in->lo_root > 0) cfg.lo_root = cfg_in->lo_root;
     cfg.build_density = cfg_in->build_density > 0 ? cfg_in->build_density : cfg.up_root / cfg.grow;
     if (cfg_in->range_chunk) cfg.range_chunk = cfg_in->range_chunk;
+    if (cfg_in->rebuild_frac > 0) cfg.rebuild_frac = cfg_in->rebuild_frac;
     cfg.alloc = cfg_in->alloc;
     cfg.free = cfg_in->free;
     cfg.ctx = cfg_in->ctx;
@@ -1259,7 +1407,7 @@ static cpma_status update(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem me
     } else {
       zero_counters(s, st);
       const uint64_t* B = prepare_batch(s, keys, k, mem, st);
-      delta = apply_batch(s, B, k, insert, st);
+      delta = apply_batch(s, B, k, insert, st, false, wants_rebuild(s, k));
     }
     resolve_phases(s);
   });
@@ -1453,7 +1601,9 @@ cpma_status cpma_apply_updates(cpma* s, uint32_t nreq, const int32_t* kind, cons
     uint64_t net = 0;
     for (uint32_t r = 0; r < nreq; r++) net += kind[r] == CPMA_REQ_INSERT ? counts[r] : (0 - counts[r]);
     if (net != nins - ndel) throw Fail{CPMA_ERR_DEVICE};  // credits disagree with the net batches
-    // deletes first (they only free room), then inserts
+    // deletes first (they only free room), then inserts; the insert batch's
+    // memory is taken before the deletes write anything
+    if (nins) reserve_batch(s, nins, true);
     if (ndel && apply_sorted(s, ddel, ndel, false, st) != ndel) throw Fail{CPMA_ERR_DEVICE};
     if (nins && apply_sorted(s, dins, nins, true, st) != nins) throw Fail{CPMA_ERR_DEVICE};
     std::copy(counts.begin(), counts.end(), result);
@@ -1769,6 +1919,14 @@ cpma_status cpma_fgraph_pagerank(const cpma* cs, uint32_t nv, int iters, double 
 uint64_t cpma_size(const cpma* s) { return s ? s->n : 0; }
 
 uint64_t cpma_bytes(const cpma* s) { return s ? s->L * ((uint64_t)s->S + 8 + 4) : 0; }
+
+uint64_t cpma_bytes_held(const cpma* cs) {
+  if (!cs) return 0;
+  cpma* s = const_cast<cpma*>(cs);
+  uint64_t total = 0;
+  for (DevBuf* b : s->bufs()) total += b->cap;
+  return total;
+}
 
 cpma_status cpma_geometry(const cpma* s, uint64_t* num_leaves, uint32_t* leaf_bytes) {
   if (!s) return CPMA_ERR_INVALID;
