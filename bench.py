@@ -1,11 +1,14 @@
 #!/usr/bin/env python3
 """CPMA benchmark on one MI355X.
 
-Headline (printed as one JSON line): batch-insert throughput of uniform 40-bit
-keys into a CPMA that starts with 1e8 keys, batches of 1e7 -- the paper's
-microbenchmark (Section "Evaluation on microbenchmarks": 100 M start, 100 M
-inserted in batches).  A step is one insert batch (sort, locate, merge, density
-count, redistribute, grow) over keys already resident in HBM.
+Headline (printed as one JSON line): batch-update throughput of uniform 40-bit
+keys on a CPMA of 1e8 keys, batches of 1e7 -- the paper's microbenchmark
+(Section "Evaluation on microbenchmarks": 100 M start, batches of uniform
+keys), with every insert batch followed by a delete batch of as many present
+keys so that the set stays at 1e8 keys whatever the step count.  A step is one
+insert batch and one delete batch (each: sort, locate, merge, density count,
+redistribute, resize) over keys already resident in HBM; the value counts the
+keys of both batches.
 
 Beside it: per-batch-size insert / delete throughput and p50 / p99 latency
 (1e1 .. 1e6, each insert followed by a delete of present keys), a batched
@@ -27,7 +30,6 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 METRIC = "insert keys/s at batch 1e3–1e7; range_map keys/s (%HBM peak); p99 latency"
-PAPER_CPMA_INSERT_1E7 = 2.4e8   # paper, CPMA batch insert, uniform, batch 1e7 (64 cores)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -38,8 +40,8 @@ def log(*a):
 # ---- HBM traffic of the main merge kernel from rocprofv3 counter runs ------------
 MERGE_KERNEL = "k_merge_wave<unsigned int>"
 MERGE_SOURCES = ["common.hpp", "leaf.hpp", "update.hpp", "merge_wave.hpp"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_merge_wave_traffic_insert_batch1e7_n1e8.md")
-VALU_FILE = os.path.join(ROOT, "profiles", "k_merge_wave_valu_insert_batch1e7_n1e8.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_merge_wave_traffic_update_pairs1e7_n1e8.md")
+VALU_FILE = os.path.join(ROOT, "profiles", "k_merge_wave_valu_update_pairs1e7_n1e8.md")
 # VALU issue peak: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD every
 # 4 cycles (16 lanes), 2.4 GHz peak engine clock
 VALU_PEAK_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
@@ -47,11 +49,38 @@ VALU_PEAK_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
 
 SCAN_KERNEL = "k_rm_interior"
 SCAN_SOURCES = ["common.hpp", "scan_lane.hpp", "query.hpp"]
-# after the timed insert steps the headline run inserts PHASE_STEPS more batches
-# (every phase timed) and deletes two: the merge launches that follow the timed ones
+# after the timed steps the headline run takes PHASE_STEPS more steps (every
+# phase timed); each step merges twice (its insert and its delete batch)
 PHASE_STEPS = 3
-TAIL_MERGES = PHASE_STEPS + 2
+MERGES_PER_STEP = 2
+TAIL_MERGES = MERGES_PER_STEP * PHASE_STEPS
 SCAN_VALU_FILE = os.path.join(ROOT, "profiles", "k_rm_interior_valu_gate_n1e9.md")
+
+
+def run_key(args, kind="steps"):
+    """What a counter summary must have been taken on to be reported beside this
+    run: the kernel's sources and the run's shape."""
+    if kind == "gate":
+        return {"source": merge_source_hash(SCAN_SOURCES), "serve_n": str(int(args.serve_n))}
+    return {"source": merge_source_hash(), "steps": str(args.steps), "warmup": str(args.warmup),
+            "n0": str(int(args.n)), "batch": str(int(args.batch))}
+
+
+def key_lines(key):
+    return [f"{k}={v}" for k, v in key.items()]
+
+
+def read_summary(path, key):
+    """The key=value block of a committed counter summary, or None when it is
+    missing or was taken on other sources or another run shape."""
+    try:
+        with open(path) as fh:
+            kv = dict(l.strip().split("=", 1) for l in fh if "=" in l and not l.startswith("|"))
+    except OSError:
+        return None
+    if any(kv.get(k) != v for k, v in key.items()):
+        return None
+    return kv
 
 
 def merge_source_hash(sources=None):
@@ -76,7 +105,7 @@ def pmc_rows(path):
     return rows
 
 
-def pmc_summary(fetch_csv, write_csv, steps, cmd_fetch, cmd_write):
+def pmc_summary(fetch_csv, write_csv, steps, cmd_fetch, cmd_write, key):
     """Traffic per timed launch of the merge kernel: FETCH_SIZE and WRITE_SIZE
     (KiB per dispatch), each scaled by what the counter reads for the 1 GiB
     calibration copy (the largest copy dispatch of the run)."""
@@ -86,14 +115,14 @@ def pmc_summary(fetch_csv, write_csv, steps, cmd_fetch, cmd_write):
         copy = max(v for _, n, _, v in rows if n == "__amd_rocclr_copyBuffer")
         factor = float(1 << 30) / (copy * 1024.0)
         merge = [v for _, n, _, v in rows if n == MERGE_KERNEL]
-        timed = merge[-(steps + TAIL_MERGES):-TAIL_MERGES]
+        timed = merge[-(MERGES_PER_STEP * steps + TAIL_MERGES):-TAIL_MERGES]
         out[tag] = {"copy_kib": copy, "factor": factor,
                     "kib_per_launch": sum(timed) / len(timed),
                     "bytes_per_launch": sum(timed) / len(timed) * 1024.0 * factor,
                     "launches": len(timed)}
     total = out["read"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
     lines = [
-        f"# {MERGE_KERNEL}: HBM traffic per launch, insert batches of 1e7 into 1e8 keys", "",
+        f"# {MERGE_KERNEL}: HBM traffic per launch, insert + delete batch pairs of 1e7 on 1e8 keys", "",
         "Two counter runs of the headline steps (each from the repository root, after "
         "`cd /tmp && export TMPDIR=/tmp`):", "", "```", cmd_fetch, cmd_write, "```", "",
         "The first dispatch of each run is a 1 GiB device-to-device copy "
@@ -106,13 +135,14 @@ def pmc_summary(fetch_csv, write_csv, steps, cmd_fetch, cmd_write):
         lines.append(f"| {ctr} | {o['copy_kib']:.1f} | {o['factor']:.4f} | {o['kib_per_launch']:.1f} | "
                      f"{o['bytes_per_launch']:.4e} |")
     lines += ["", f"Timed launches averaged: {out['read']['launches']}.", "",
-              "Machine-readable (read by bench.py; `source` is the hash of the kernel's sources "
+              "Machine-readable (read by bench.py, which reports the figure only for a run of the "
+              "same shape on the same kernel sources; `source` is the hash of the kernel's sources "
               "when the counters were taken):", "", "```",
-              f"traffic_bytes_per_launch={total:.6e}", f"source={merge_source_hash()}", "```", ""]
+              f"traffic_bytes_per_launch={total:.6e}"] + key_lines(key) + ["```", ""]
     return "\n".join(lines)
 
 
-def valu_summary(csv_path, kernel, pick, title, what, cmd, sources):
+def valu_summary(csv_path, kernel, pick, title, what, cmd, key):
     """VALU (and LDS, SALU) instructions and waves per launch of `kernel` from one
     rocprofv3 --pmc run; pick(list) selects the launches to average."""
     ctrs = ("SQ_INSTS_VALU", "SQ_WAVES", "SQ_INSTS_LDS", "SQ_INSTS_SALU")
@@ -134,43 +164,152 @@ def valu_summary(csv_path, kernel, pick, title, what, cmd, sources):
     for ctr in ctrs:
         lines.append(f"| {ctr} | {avg[ctr]:.4e} |")
     lines += ["", f"Launches averaged: {nl}.", "",
-              "Machine-readable (read by bench.py; `source` is the hash of the kernel's sources "
+              "Machine-readable (read by bench.py, which reports the figure only for a run of the "
+              "same shape on the same kernel sources; `source` is the hash of the kernel's sources "
               "when the counters were taken):", "", "```",
-              f"valu_insts_per_launch={avg['SQ_INSTS_VALU']:.6e}", f"waves_per_launch={avg['SQ_WAVES']:.6e}",
-              f"source={merge_source_hash(sources)}", "```", ""]
+              f"valu_insts_per_launch={avg['SQ_INSTS_VALU']:.6e}", f"waves_per_launch={avg['SQ_WAVES']:.6e}"]
+    lines += key_lines(key) + ["```", ""]
     return "\n".join(lines)
 
 
-def kernel_valu(path=None, sources=None):
-    """VALU instructions per launch from a committed counter summary (default:
-    the merge kernel's), or None when it is missing or was taken on other
-    kernel sources."""
-    try:
-        with open(path or VALU_FILE) as fh:
-            kv = dict(l.strip().split("=", 1) for l in fh if "=" in l and not l.startswith("|"))
-    except OSError:
-        return None
-    if kv.get("source") != merge_source_hash(sources):
-        return None
-    return float(kv["valu_insts_per_launch"])
+def kernel_valu(path, key):
+    """VALU instructions per launch from a committed counter summary, or None."""
+    kv = read_summary(path, key)
+    return float(kv["valu_insts_per_launch"]) if kv else None
 
 
-def merge_traffic():
-    """Traffic per launch from the committed counter summary, or None when it is
-    missing or was taken on other kernel sources."""
+def merge_traffic(key):
+    """HBM bytes per merge launch from the committed counter summary, or None."""
+    kv = read_summary(TRAFFIC_FILE, key)
+    return float(kv["traffic_bytes_per_launch"]) if kv else None
+
+
+def host_info():
+    """The host CPU the oracle ran on: model name and usable cores."""
+    model = None
     try:
-        with open(TRAFFIC_FILE) as fh:
-            kv = dict(l.strip().split("=", 1) for l in fh if "=" in l and not l.startswith("|"))
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
     except OSError:
-        return None
-    if kv.get("source") != merge_source_hash():
-        return None
-    return float(kv["traffic_bytes_per_launch"])
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
 
 
 def to_dev(a):
     import torch
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def zipf_section(cp, torch, c, seed, sizes=(10 ** 5, 10 ** 6, 10 ** 7), reps=3):
+    """Skewed batches on the uniform set c: inserts of k Zipf(0.99) 34-bit keys
+    (Section "Evaluation on microbenchmarks", setup), each followed by a delete
+    batch of k keys from the same distribution (mostly present, repeats
+    included), as the paper's Zipf insert / delete table."""
+    out = {"keys": "Zipf(0.99) over 34-bit keys, unscrambled (popular keys are small)",
+           "paper_context": "paper, 64-core Xeon, inserts/s (deletes/s): 1e5 7.2e7 (8.7e7), "
+                            "1e6 1.7e8 (2.2e8), 1e7 3.1e8 (4.6e8)"}
+    off = 0
+    for k in sizes:
+        ins = [to_dev(synth.zipf_keys(k, seed, offset=off + 2 * i * k)) for i in range(reps)]
+        dls = [to_dev(synth.zipf_keys(k, seed, offset=off + (2 * i + 1) * k)) for i in range(reps)]
+        off += 2 * reps * k
+        torch.cuda.synchronize()
+        ti, td, added, removed = [], [], 0, 0
+        for i in range(reps):
+            t0 = time.perf_counter()
+            added += c.insert_batch(ins[i])
+            t1 = time.perf_counter()
+            removed += c.delete_batch(dls[i])
+            t2 = time.perf_counter()
+            ti.append(t1 - t0)
+            td.append(t2 - t1)
+        out[f"{k:.0e}"] = {"insert_keys_s": k / float(np.mean(ti)), "delete_keys_s": k / float(np.mean(td)),
+                           "distinct_added_per_batch": added / reps, "removed_per_batch": removed / reps,
+                           "insert_p50_ms": float(np.percentile(ti, 50) * 1e3), "reps": reps}
+    log(f"zipf: {out}")
+    return out
+
+
+def growth_section(cp, torch, base_dev, seed, factors=(1.1, 1.2, 1.5, 2.0), batches=10, k=10 ** 7):
+    """The growing-factor sweep of the paper's appendix: for each factor, the
+    set of 1e8 uniform keys takes 1e8 more in batches of 1e7; total insert time,
+    bytes per key after each batch (average and worst) and a full-range scan
+    after each batch (average)."""
+    out = {"setup": "build 1e8 uniform 40-bit keys, insert 10 batches of 1e7 fresh keys; "
+                    "after each batch: bytes/key and one full-range range_map"}
+    full_lo = to_dev(np.array([0], np.uint64))
+    full_hi = to_dev(np.array([(1 << 64) - 1], np.uint64))
+    bs = [to_dev(synth.uniform_keys(k, seed, offset=i * k)) for i in range(batches)]
+    for g in factors:
+        cfg = cp.default_config()
+        cfg.grow = g
+        cfg.build_density = 0.0
+        c = cp.CPMA(base_dev, config=cfg)
+        c.range_map(full_lo, full_hi)
+        torch.cuda.synchronize()
+        t_ins, sizes, scans, grows = 0.0, [], [], 0
+        L_prev = c.geometry()[0]
+        for b in bs:
+            t0 = time.perf_counter()
+            c.insert_batch(b)
+            t_ins += time.perf_counter() - t0
+            L = c.geometry()[0]
+            grows += L > L_prev
+            L_prev = L
+            sizes.append(c.bytes() / c.size())
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.range_map(full_lo, full_hi)
+            torch.cuda.synchronize()
+            scans.append(time.perf_counter() - t0)
+        out[str(g)] = {"insert_keys_s": batches * k / t_ins, "bytes_per_key_avg": float(np.mean(sizes)),
+                       "bytes_per_key_max": float(np.max(sizes)), "full_scan_ms_avg": float(np.mean(scans)) * 1e3,
+                       "grows": int(grows)}
+        c.close()
+        torch.cuda.empty_cache()
+    best_ins = max(out[str(g)]["insert_keys_s"] for g in factors)
+    for g in factors:
+        out[str(g)]["insert_ratio_from_best"] = out[str(g)]["insert_keys_s"] / best_ins
+    log(f"growth: {out}")
+    return out
+
+
+def rebuild_section(cp, torch, base_dev, seed, fracs=(0.1, 1.0)):
+    """Both branches of a large insert batch on the 1e8-key set, at k = n / 10
+    and k = n: the full rebuild (every leaf merged, then everything spread at
+    build density) and the counted batch path (count, redistribute, grow).
+    Each insert is timed once after a warm-up of the same size, on a fresh
+    set."""
+    n = int(base_dev.numel())
+    out = {}
+    for f in fracs:
+        k = int(f * n)
+        bs = [to_dev(synth.uniform_keys(k, seed, offset=i * k)) for i in range(2)]
+        row = {}
+        for tag, rf in (("rebuild", f * 0.5), ("batch_path", 1e9)):
+            cfg = cp.default_config()
+            cfg.rebuild_frac = rf
+            c = cp.CPMA(base_dev, config=cfg)
+            c.insert_batch(bs[0])           # warm-up: sizes the scratch
+            c.delete_batch(bs[0])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.insert_batch(bs[1])
+            torch.cuda.synchronize()
+            row[tag + "_insert_ms"] = (time.perf_counter() - t0) * 1e3
+            t0 = time.perf_counter()
+            c.delete_batch(bs[1])
+            torch.cuda.synchronize()
+            row[tag + "_delete_ms"] = (time.perf_counter() - t0) * 1e3
+            c.close()
+            torch.cuda.empty_cache()
+        out[f"k_over_n_{f:g}"] = row
+        del bs
+    log(f"rebuild vs batch path: {out}")
+    return out
 
 
 def fgraph_section(cp, torch, scale, seed):
@@ -273,7 +412,28 @@ def redist_section(cp, torch, seed, n=10 ** 7, batches=8, k=20000):
     return out
 
 
-def range_section(cp, torch, c, base_dev, q, seed):
+def range_cpu_baseline(keys_sorted, lo, hi, target_keys=6e9):
+    """The oracle's lower_bound + sum on a prefix of the same queries holding
+    about target_keys keys, on one host core and on every usable core."""
+    import oracle
+    lens_est = np.searchsorted(keys_sorted, hi) - np.searchsorted(keys_sorted, lo)
+    m = int(np.searchsorted(np.cumsum(lens_est), target_keys)) + 1
+    m = min(m, len(lo))
+    keys = int(lens_est[:m].sum())
+    out = {"queries": m, "keys": keys, "kind": "oracle", "unit": "keys/s",
+           "sample": f"the first {m} of the Zipf(1.2) queries ({keys:.3e} keys): lower_bound + sum"}
+    threads = len(os.sched_getaffinity(0))
+    for tag, th in (("one_core", 0), ("all_cores", threads)):
+        t0 = time.perf_counter()
+        oracle.range_map(keys_sorted, lo[:m], hi[:m], threads=th)
+        dt = time.perf_counter() - t0
+        out[tag] = {"value": keys / dt, "cores": max(1, th), "s": dt}
+    out["host"] = host_info()
+    log(f"range cpu baseline: {out}")
+    return out
+
+
+def range_section(cp, torch, c, base_dev, q, seed, with_cpu=False):
     """Batched range_map on the 1e8-key set: q queries whose lengths (in keys)
     are Zipf(1.2) on 1..1e6, each covering exactly its length of the sorted set;
     on the default layout and on the autotuned one; against one launch per query."""
@@ -283,10 +443,11 @@ def range_section(cp, torch, c, base_dev, q, seed):
     # membership: 1e6 keys, half drawn from the set and half fresh
     probe = np.concatenate([keys_sorted[synth.sample_indices(len(keys_sorted), 500000, seed + 2)],
                             synth.uniform_keys(500000, seed + 3)])
+    cpu = range_cpu_baseline(keys_sorted, lo, hi) if with_cpu else None
     del keys_sorted
     dlo, dhi = to_dev(lo), to_dev(hi)
     out = {"queries": q, "lengths": "Zipf(1.2) on 1..1e6 keys, exact counts",
-           "default": time_range(torch, c, dlo, dhi)}
+           "default": time_range(torch, c, dlo, dhi), "cpu_baseline": cpu}
     dprobe = to_dev(probe)
     c.contains(dprobe)
     torch.cuda.synchronize()
@@ -305,16 +466,23 @@ def range_section(cp, torch, c, base_dev, q, seed):
     out["autotuned"] = res
     # one launch per query on a prefix of the same queries
     m = min(2000, q)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(m):
         tuned.range_map(dlo[i:i + 1], dhi[i:i + 1])
     torch.cuda.synchronize()
     per_q = (time.perf_counter() - t0) / m
+    one = [tuned.range_map(dlo[i:i + 1], dhi[i:i + 1]) for i in range(m)]  # untimed: their results
+    one_s = torch.cat([x[0] for x in one])
+    one_n = torch.cat([x[1] for x in one])
+    del one
     t0 = time.perf_counter()
-    tuned.range_map(dlo[:m], dhi[:m])
+    bs, bn = tuned.range_map(dlo[:m], dhi[:m])
     torch.cuda.synchronize()
     out["one_launch_per_query_s_per_query"] = per_q
     out["batched_speedup_on_prefix"] = (per_q * m) / (time.perf_counter() - t0)
+    # the two forms must give identical results
+    out["batched_equals_one_per_query"] = bool(torch.equal(bs, one_s) and torch.equal(bn, one_n))
     out["batched_speedup_extrapolated"] = (per_q * q) / (res["ms_per_pass"] * 1e-3)
     # a small batch (64 of the queries of at most 8 keys, so launches rather
     # than scanning set the time) back to back: eager calls against replays of
@@ -351,7 +519,7 @@ def range_section(cp, torch, c, base_dev, q, seed):
     return out
 
 
-def gate_section(cp, torch, c, n0, seed):
+def gate_section(cp, torch, c, n0, seed, gate_key):
     """range_map on cold data: 1e3 queries of about 1e6 keys at random starts
     (width = 1e6 * floor(2^40 / n0)) plus one query over the whole key space, on
     a set far larger than the 256 MB last-level cache."""
@@ -365,7 +533,7 @@ def gate_section(cp, torch, c, n0, seed):
     res["queries"] = "1e3 of ~1e6 keys + 1 full range"
     # what bounds the scan instead of HBM: VALU issue (counted instructions per
     # launch over the launch time, against the issue peak)
-    valu = kernel_valu(SCAN_VALU_FILE, SCAN_SOURCES)
+    valu = kernel_valu(SCAN_VALU_FILE, gate_key)
     res["valu_issue_frac"] = valu / (res["scan_kernel_ms"] * 1e-3) / VALU_PEAK_INSTS_PER_S if valu else None
     log(f"range gate: {res['keys_per_s']:.3e} keys/s, scan {res['scan_alg_GBps']:.0f} GB/s "
         f"({100 * res['frac_hbm_alg']:.1f}% of HBM peak)")
@@ -437,7 +605,7 @@ def main():
     ap.add_argument("--sweep", default="1e1,1e2,1e3,1e4,1e5,1e6")
     ap.add_argument("--queries", type=float, default=1e6)
     ap.add_argument("--leaf-bytes", type=int, default=0)
-    ap.add_argument("--cpu-batches", type=int, default=4)
+    ap.add_argument("--cpu-batches", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-steps", action="store_true", help="skip every side measurement")
     ap.add_argument("--fg-scale", type=int, default=24, help="R-MAT scale of the F-Graph section (0: skip)")
@@ -459,20 +627,23 @@ def main():
                     help="write the range scan kernel's instruction summary from a --pmc run of --gate-only")
     args = ap.parse_args()
 
+    shape = f"--steps {args.steps} --warmup {args.warmup}"
     if args.valu_summary or args.scan_valu_summary:
         ctr = "rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES SQ_INSTS_LDS SQ_INSTS_SALU --output-format csv "
         if args.valu_summary:
             cmd = (ctr + "-d /tmp/cpma_prof/pmc_valu -o run -- python3 /root/repo/bench.py --only-steps "
-                   f"--no-cpu-baseline --steps {args.steps}")
-            text = valu_summary(args.valu_summary, MERGE_KERNEL, lambda v: v[-(args.steps + TAIL_MERGES):-TAIL_MERGES],
-                                "insert batches of 1e7 into 1e8 keys", "the headline steps (the run ends "
-                                "with two delete batches, which are left out)", cmd, MERGE_SOURCES)
+                   f"--no-cpu-baseline {shape}")
+            m = MERGES_PER_STEP * args.steps
+            text = valu_summary(args.valu_summary, MERGE_KERNEL, lambda v: v[-(m + TAIL_MERGES):-TAIL_MERGES],
+                                "insert + delete batch pairs of 1e7 on 1e8 keys",
+                                "the headline steps (the merges of the timed steps' inserts and deletes)", cmd,
+                                run_key(args))
             path = VALU_FILE
         else:
             cmd = ctr + "-d /tmp/cpma_prof/pmc_scan -o run -- python3 /root/repo/bench.py --gate-only"
             text = valu_summary(args.scan_valu_summary, SCAN_KERNEL, lambda v: v[-3:],
                                 "the cold range gate on 1e9 keys", "the cold range gate (its last three "
-                                "timed passes)", cmd, SCAN_SOURCES)
+                                "timed passes)", cmd, run_key(args, "gate"))
             path = SCAN_VALU_FILE
         with open(path, "w") as fh:
             fh.write(text)
@@ -480,9 +651,10 @@ def main():
         return
     if args.pmc_summary:
         base = "rocprofv3 --pmc {c} --output-format csv -d /tmp/cpma_prof/pmc_{t} -o run -- " \
-               f"python3 /root/repo/bench.py --only-steps --no-cpu-baseline --calibrate-copy --steps {args.steps}"
+               f"python3 /root/repo/bench.py --only-steps --no-cpu-baseline --calibrate-copy {shape}"
         text = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.steps,
-                           base.format(c="FETCH_SIZE", t="fetch"), base.format(c="WRITE_SIZE", t="write"))
+                           base.format(c="FETCH_SIZE", t="fetch"), base.format(c="WRITE_SIZE", t="write"),
+                           run_key(args))
         with open(TRAFFIC_FILE, "w") as fh:
             fh.write(text)
         print(text)
@@ -518,7 +690,8 @@ def main():
         big = cp.CPMA(big_d)
         del big_d
         torch.cuda.empty_cache()
-        print(json.dumps(gate_section(cp, torch, big, int(args.serve_n), seed + 80)), flush=True)
+        print(json.dumps(gate_section(cp, torch, big, int(args.serve_n), seed + 80, run_key(args, "gate"))),
+              flush=True)
         return
     if args.serve_only:
         big_d = synth.uniform_keys_torch(int(args.serve_n), seed + 70, "cuda")
@@ -554,7 +727,8 @@ def main():
         return
     # ---- batched range_map (Zipf(1.2) lengths 1..1e6) vs one launch per query -----
     if not args.only_steps and args.queries > 0:
-        result_extra["range_map"] = range_section(cp, torch, c, base_dev, int(args.queries), seed + 10)
+        result_extra["range_map"] = range_section(cp, torch, c, base_dev, int(args.queries), seed + 10,
+                                                  with_cpu=not args.no_cpu_baseline)
     base_dev = None
     torch.cuda.empty_cache()
 
@@ -596,69 +770,99 @@ def main():
             print(json.dumps(per_batch), flush=True)
             return
 
-    # ---- headline: W warm-up + K timed insert batches of k keys ------------------
+    # ---- headline: W warm-up + K timed steps, each an insert batch of k fresh
+    # keys and a delete batch of k present keys (the previous step's insert
+    # batch; the first step deletes k keys sampled from the base set), so the
+    # set stays at n0 .. n0 + k keys ------------------------------------------
     nb = args.warmup + args.steps
     n_phase_steps = PHASE_STEPS
-    batches = [to_dev(synth.uniform_keys(k, seed + 40, offset=i * k)) for i in range(nb + n_phase_steps)]
+    ins = [to_dev(synth.uniform_keys(k, seed + 40, offset=i * k)) for i in range(nb + n_phase_steps)]
+    first_del = to_dev(base_all[synth.sample_indices(len(base_all), k, seed + 50)])
+
+    def dels(i):
+        return first_del if i == 0 else ins[i - 1]
+
     torch.cuda.synchronize()
+    n_seen = [c.size()]
     for i in range(args.warmup):
-        c.insert_batch(batches[i])
+        c.insert_batch(ins[i])
+        n_seen.append(c.size())
+        c.delete_batch(dels(i))
+        n_seen.append(c.size())
     torch.cuda.synchronize()
     # the timed steps record HIP events around the merge kernel only (each event
     # record idles the GPU for a few microseconds); every phase is timed on
     # separate steps afterwards
     c.stats_select(["merge"])
-    lat = []
+    lat, lat_i, lat_d = [], [], []
+    added = removed = 0
     t0 = time.perf_counter()
     for i in range(args.warmup, nb):
         ts = time.perf_counter()
-        c.insert_batch(batches[i])
-        lat.append(time.perf_counter() - ts)
+        added += c.insert_batch(ins[i])
+        tm = time.perf_counter()
+        n_seen.append(c.size())
+        removed += c.delete_batch(dels(i))
+        te = time.perf_counter()
+        n_seen.append(c.size())
+        lat.append(te - ts)
+        lat_i.append(tm - ts)
+        lat_d.append(te - tm)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = c.stats()
     c.stats_enable(False)
+    n_after = c.size()
     dt = t1 - t0
-    value = args.steps * k / dt
-    log(f"headline: {value:.3e} inserts/s, {dt / args.steps * 1e3:.2f} ms/step, n={c.size()}")
+    value = args.steps * 2 * k / dt
+    log(f"headline: {value:.3e} keys/s (inserted + deleted), {dt / args.steps * 1e3:.2f} ms/step, "
+        f"insert {k / np.mean(lat_i):.3e}/s, delete {k / np.mean(lat_d):.3e}/s, n={n_after}")
     c.stats_enable(True)
     for i in range(nb, nb + n_phase_steps):
-        c.insert_batch(batches[i])
+        c.insert_batch(ins[i])
+        c.delete_batch(dels(i))
     stp = c.stats()
     c.stats_enable(False)
     phases = {name: {"launches": v[0], "ms": v[1], "alg_bytes": v[2]} for name, v in stp.items()}
     phases["steps"] = n_phase_steps
 
-    # roofline of the dominant single kernel of the step (the merge, or the sort's passes)
+    # roofline of the dominant single kernel of the step (the merge)
     mg_l, mg_ms, mg_b = st["merge"]
     dominant = max(("merge", "sort", "locate", "count", "redist"), key=lambda p: stp[p][1])
     roof = None
+    key = run_key(args)
     if mg_l > 0 and mg_ms > 0:
         ach = (mg_b / mg_l) / ((mg_ms / mg_l) * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": "k_merge_wave<unsigned int>" if S <= 1024 else "k_merge_lane",
+        roof = {"bound": "hbm", "kernel": MERGE_KERNEL if S <= 1024 else "k_merge_lane",
                 "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": merge_traffic(),
+                "frac": ach / HBM_PEAK_GBS, "traffic": merge_traffic(key),
                 "alg_bytes_per_launch": mg_b / mg_l, "avg_launch_ms": mg_ms / mg_l,
-                "dominant_phase": dominant}
+                "launches": mg_l, "dominant_phase": dominant}
         # what bounds it instead: VALU issue (counted instructions per launch over
         # the launch time, against the issue peak)
-        valu = kernel_valu()
+        valu = kernel_valu(VALU_FILE, key)
         roof["valu_issue_frac"] = (valu / ((mg_ms / mg_l) * 1e-3) / VALU_PEAK_INSTS_PER_S) if valu else None
-
-    # delete throughput at the headline batch size (present keys from the base set)
-    dsel = synth.sample_indices(len(base_all), 2 * k, seed + 50)
-    dels = [to_dev(base_all[dsel[i * k:(i + 1) * k]]) for i in range(2)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for d in dels:
-        c.delete_batch(d)
-    torch.cuda.synchronize()
-    result_extra["delete_keys_s_at_batch"] = 2 * k / (time.perf_counter() - t0)
+    result_extra["steps_detail"] = {
+        "insert_keys_s": k / float(np.mean(lat_i)), "delete_keys_s": k / float(np.mean(lat_d)),
+        "insert_p50_ms": float(np.percentile(lat_i, 50) * 1e3), "insert_p99_ms": float(np.percentile(lat_i, 99) * 1e3),
+        "delete_p50_ms": float(np.percentile(lat_d, 50) * 1e3), "delete_p99_ms": float(np.percentile(lat_d, 99) * 1e3),
+        "keys_added": added, "keys_removed": removed,
+        "paper_context": "paper, 64-core Xeon, batch 1e7: 2.4e8 inserts/s and 4.7e8 deletes/s (uniform keys)"}
+    n_seen.append(n_after)
     result_extra["bytes_per_key_final"] = c.bytes() / c.size()
-    del batches, dels
+    result_extra["bytes_held_per_key_final"] = c.bytes_held() / c.size()
+    del ins, first_del
+    if not args.only_steps:
+        result_extra["zipf"] = zipf_section(cp, torch, c, seed + 45)
 
     c.close()
     torch.cuda.empty_cache()
+    if not args.only_steps:
+        bd = to_dev(base_all)
+        result_extra["rebuild"] = rebuild_section(cp, torch, bd, seed + 46)
+        result_extra["growth"] = growth_section(cp, torch, bd, seed + 47)
+        del bd
+        torch.cuda.empty_cache()
     if not args.only_steps:
         result_extra["redistribution"] = redist_section(cp, torch, seed + 50)
         torch.cuda.empty_cache()
@@ -677,37 +881,46 @@ def main():
         big_host = big_d.cpu().numpy().view(np.uint64)
         del big_d
         torch.cuda.empty_cache()
-        result_extra["range_gate"] = gate_section(cp, torch, big, n_big, seed + 80)
+        result_extra["range_gate"] = gate_section(cp, torch, big, n_big, seed + 80, run_key(args, "gate"))
         result_extra["serving"] = serving_section(cp, torch, big, big_host, args.serve_requests, seed + 90)
         big.close()
         del big_host
 
-    # ---- CPU baseline: the oracle inserting the same kind of batches ------------
+    # ---- CPU baseline: the oracle taking the same kind of steps -----------------
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
         log("cpu baseline: oracle set of n0 keys ...")
         S_host = oracle.build_set(base_all)
         nbat = args.cpu_batches
+        prev = base_all[synth.sample_indices(len(base_all), k, seed + 50)]
         t0 = time.perf_counter()
         for i in range(nbat):
-            S_host, _ = oracle.insert(S_host, synth.uniform_keys(k, seed + 40, offset=i * k))
+            b = synth.uniform_keys(k, seed + 40, offset=i * k)
+            S_host, _ = oracle.insert(S_host, b)
+            S_host, _ = oracle.delete(S_host, prev)
+            prev = b
         tc = time.perf_counter() - t0
-        cpu = {"value": nbat * k / tc, "unit": "keys/s", "cores": 1, "kind": "oracle",
-               "sample": f"{nbat} insert batches of {k:.0e} uniform 40-bit keys into the {n0:.0e}-key "
-                         f"set (sorted-vector set_union, single thread), {tc:.1f} s"}
+        cpu = {"value": nbat * 2 * k / tc, "unit": "keys/s", "cores": 1, "kind": "oracle",
+               "sample": f"{nbat} steps of the same workload (insert {k:.0e} uniform 40-bit keys into the "
+                         f"{n0:.0e}-key set, then delete {k:.0e} present keys; sorted-vector set_union / "
+                         f"set_difference, single thread), {tc:.1f} s",
+               "host": host_info()}
         log(f"cpu baseline {cpu['value']:.3e} keys/s")
 
     out = {
         "metric": METRIC, "value": value, "unit": "keys/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": value / PAPER_CPMA_INSERT_1E7, "dtype": "u64",
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "plain CPMA at scale: 1e8 uniform 40-bit keys, insert batches of 1e7",
-                   "n0": n0, "batch": k, "leaf_bytes": S, "key_bits": 40},
+        "config": {"workload": "plain CPMA at scale: 1e8 uniform 40-bit keys; each step inserts a batch of 1e7 "
+                               "fresh uniform keys and deletes a batch of 1e7 present keys",
+                   "value_counts": "keys of the insert and the delete batch", "n0": n0, "batch": k,
+                   "n_range": [int(min(n_seen)), int(max(n_seen))], "leaf_bytes": S, "key_bits": 40},
         "roofline": roof, "cpu_baseline": cpu,
         "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
         "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
+        "latency_of": "one step (insert batch + delete batch)",
         "phases": phases,
     }
     out.update(result_extra)
