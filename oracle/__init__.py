@@ -75,6 +75,9 @@ def lib():
         L.orc_decode_image.argtypes = [u8p, u32p, c_u64, ctypes.c_uint32, u64p, c_u64]
         L.orc_decode_image.restype = ctypes.c_int64
         L.orc_bfs.argtypes = [u64p, c_u64, ctypes.c_uint32, ctypes.c_uint32, u32p]
+        L.orc_offsets.argtypes = [u64p, c_u64, ctypes.c_uint32, u64p]
+        L.orc_cc.argtypes = [u64p, c_u64, ctypes.c_uint32, u32p]
+        L.orc_bc.argtypes = [u64p, c_u64, ctypes.c_uint32, ctypes.c_uint32, dp, dp]
         L.orc_pagerank.argtypes = [u64p, c_u64, ctypes.c_uint32, ctypes.c_int,
                                    ctypes.c_double, dp]
         _lib = L
@@ -190,6 +193,29 @@ def bfs(edges, nv, src=0):
     lv = np.empty(nv, dtype=np.uint32)
     lib().orc_bfs(_p(e, ctypes.c_uint64), len(e), nv, src, _p(lv, ctypes.c_uint32))
     return lv
+
+
+def offsets(edges, nv):
+    e = _u64(edges)
+    off = np.empty(nv + 1, dtype=np.uint64)
+    lib().orc_offsets(_p(e, ctypes.c_uint64), len(e), nv, _p(off, ctypes.c_uint64))
+    return off
+
+
+def cc(edges, nv):
+    e = _u64(edges)
+    lab = np.empty(nv, dtype=np.uint32)
+    lib().orc_cc(_p(e, ctypes.c_uint64), len(e), nv, _p(lab, ctypes.c_uint32))
+    return lab
+
+
+def bc(edges, nv, src=0):
+    """(sigma, delta) of Brandes' single-source betweenness from src."""
+    e = _u64(edges)
+    sg = np.empty(nv, dtype=np.float64)
+    dl = np.empty(nv, dtype=np.float64)
+    lib().orc_bc(_p(e, ctypes.c_uint64), len(e), nv, src, _p(sg, ctypes.c_double), _p(dl, ctypes.c_double))
+    return sg, dl
 
 
 def pagerank(edges, nv, iters=10, damping=0.85):

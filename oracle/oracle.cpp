@@ -307,6 +307,80 @@ extern "C" void orc_bfs(const uint64_t* edges, uint64_t m, uint32_t nv, uint32_t
   }
 }
 
+// The vertex array of offsets that a CSR keeps and the flat edge array lacks
+// (Section "Evaluation on graph workloads": the reconstruction cost of the
+// vertex array): off[v] = number of edges whose source is below v.
+extern "C" void orc_offsets(const uint64_t* edges, uint64_t m, uint32_t nv, uint64_t* off) {
+  std::vector<uint64_t> o;
+  std::vector<uint32_t> adj;
+  build_csr(edges, m, nv, o, adj);
+  std::copy(o.begin(), o.end(), off);
+}
+
+// Connected components of an undirected graph (each edge stored in both
+// directions): label[v] = the smallest vertex id of v's component, found by
+// a breadth-first search from every not yet labelled vertex in id order.
+extern "C" void orc_cc(const uint64_t* edges, uint64_t m, uint32_t nv, uint32_t* label) {
+  std::vector<uint64_t> off;
+  std::vector<uint32_t> adj;
+  build_csr(edges, m, nv, off, adj);
+  for (uint32_t v = 0; v < nv; v++) label[v] = UINT32_MAX;
+  for (uint32_t r = 0; r < nv; r++) {
+    if (label[r] != UINT32_MAX) continue;
+    std::queue<uint32_t> q;
+    label[r] = r;
+    q.push(r);
+    while (!q.empty()) {
+      uint32_t u = q.front();
+      q.pop();
+      for (uint64_t e = off[u]; e < off[u + 1]; e++)
+        if (label[adj[e]] == UINT32_MAX) {
+          label[adj[e]] = r;
+          q.push(adj[e]);
+        }
+    }
+  }
+}
+
+// Single-source betweenness centrality (Brandes): sigma[v] = number of
+// shortest paths from src to v; delta[v] = sum over the vertices w whose
+// shortest paths from src pass through v of sigma[v] / sigma[w] * (1 +
+// delta[w]) (the dependency of src on v), in double precision.  Vertices
+// unreachable from src get sigma = delta = 0.
+extern "C" void orc_bc(const uint64_t* edges, uint64_t m, uint32_t nv, uint32_t src, double* sigma,
+                       double* delta) {
+  std::vector<uint64_t> off;
+  std::vector<uint32_t> adj;
+  build_csr(edges, m, nv, off, adj);
+  std::vector<uint32_t> level(nv, UINT32_MAX), order;
+  for (uint32_t v = 0; v < nv; v++) sigma[v] = delta[v] = 0.0;
+  if (src >= nv) return;
+  std::queue<uint32_t> q;
+  level[src] = 0;
+  sigma[src] = 1.0;
+  q.push(src);
+  while (!q.empty()) {
+    uint32_t u = q.front();
+    q.pop();
+    order.push_back(u);
+    for (uint64_t e = off[u]; e < off[u + 1]; e++) {
+      uint32_t w = adj[e];
+      if (level[w] == UINT32_MAX) {
+        level[w] = level[u] + 1;
+        q.push(w);
+      }
+      if (level[w] == level[u] + 1) sigma[w] += sigma[u];
+    }
+  }
+  for (size_t i = order.size(); i-- > 0;) {
+    uint32_t v = order[i];
+    for (uint64_t e = off[v]; e < off[v + 1]; e++) {
+      uint32_t w = adj[e];
+      if (level[w] == level[v] + 1) delta[v] += sigma[v] / sigma[w] * (1.0 + delta[w]);
+    }
+  }
+}
+
 // PageRank with a fixed iteration count (the paper runs 10): every vertex u
 // pushes p(u)/deg(u) along each of its edges; a vertex without edges pushes
 // nothing (no dangling-mass redistribution).

@@ -88,6 +88,14 @@ int64_t orc_decode_image(const uint8_t* bytes, const uint32_t* used, uint64_t L,
 /* level[v] = hop distance from src, UINT32_MAX if unreachable. */
 void orc_bfs(const uint64_t* edges, uint64_t m, uint32_t nv, uint32_t src,
              uint32_t* level);
+/* off[v] = number of edges with source < v, v = 0..nv (nv + 1 entries). */
+void orc_offsets(const uint64_t* edges, uint64_t m, uint32_t nv, uint64_t* off);
+/* label[v] = smallest vertex id in v's connected component (symmetric edges). */
+void orc_cc(const uint64_t* edges, uint64_t m, uint32_t nv, uint32_t* label);
+/* Brandes single-source betweenness: path counts sigma and dependencies delta
+ * from src, double precision (symmetric edges). */
+void orc_bc(const uint64_t* edges, uint64_t m, uint32_t nv, uint32_t src, double* sigma,
+            double* delta);
 /* iters rounds of p'(v) = (1-d)/nv + d * sum_{u in N(v)} p(u)/deg(u), p0 = 1/nv. */
 void orc_pagerank(const uint64_t* edges, uint64_t m, uint32_t nv, int iters,
                   double damping, double* p);

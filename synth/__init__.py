@@ -9,7 +9,9 @@ OOPSLA 2014): value i of stream `seed` is mix64(seed + (i + 1) * golden_gamma).
 Workload recipes follow the paper's experiments:
   * uniform 40-bit keys (Section "Evaluation on microbenchmarks", setup);
   * Zipf-distributed range lengths (skewed batch of queries);
-  * R-MAT edges with a=0.5, b=c=0.1, d=0.3 (graph batch-insert setup).
+  * R-MAT edges with a=0.5, b=c=0.1, d=0.3 (graph batch-insert setup);
+  * Erdos-Renyi edges, uniform vertex pairs (the synthetic graph of the graph
+    evaluation's datasets).
 """
 import numpy as np
 
@@ -199,6 +201,15 @@ def rmat_edges(m, seed, scale=24, a=0.5, b=0.1, c=0.1):
     return src, dst
 
 
+def er_edges(m, seed, nv):
+    """m ordered vertex pairs (src, dst) drawn uniformly from [0, nv)^2: an
+    Erdos-Renyi graph (each of the nv^2 ordered pairs appears with probability
+    about m / nv^2) before self-loops are dropped and edges symmetrised."""
+    src = np.floor(uniform_float(m, seed) * nv).astype(np.uint64)
+    dst = np.floor(uniform_float(m, seed + 1) * nv).astype(np.uint64)
+    return src, dst
+
+
 def edge_keys(src, dst, symmetric=True, drop_self_loops=True):
     """Edge keys src<<32|dst (unsorted, possibly with repeats)."""
     src = np.asarray(src, dtype=np.uint64)
@@ -251,6 +262,14 @@ def rmat_edges_torch(m, seed, scale=24, a=0.5, b=0.1, c=0.1, device="cpu"):
         down = u >= ab
         dst |= right.to(torch.int64) * bit
         src |= down.to(torch.int64) * bit
+    return src, dst
+
+
+def er_edges_torch(m, seed, nv, device="cpu"):
+    """er_edges drawn with torch: same values, int64 tensors on `device`."""
+    import torch
+    src = torch.floor(uniform_float_torch(m, seed, device) * nv).to(torch.int64)
+    dst = torch.floor(uniform_float_torch(m, seed + 1, device) * nv).to(torch.int64)
     return src, dst
 
 

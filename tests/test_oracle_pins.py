@@ -386,3 +386,101 @@ def test_bfs_matches_python_bfs(orc):
                     nxt.append(v)
         frontier = nxt
     assert orc.bfs(e, nv).tolist() == ref
+
+
+# ------------------------------------------------ vertex offsets, CC, BC (F-Graph)
+def test_offsets_star_and_degree_prefix(orc):
+    star = _sym([(0, i) for i in range(1, 10)])
+    assert orc.offsets(star, 12).tolist() == [0, 9] + list(range(10, 19)) + [18, 18]
+    src, dst = synth.rmat_edges(5000, 31, scale=10)
+    e = np.unique(synth.edge_keys(src, dst))
+    deg = np.bincount((e >> np.uint64(32)).astype(np.int64), minlength=1024)
+    assert orc.offsets(e, 1024).tolist() == [0] + np.cumsum(deg).tolist()
+
+
+def test_cc_known_components_and_union_find(orc):
+    pairs = [(i, j) for i in range(3, 8) for j in range(i + 1, 8)]          # clique 3..7
+    pairs += [(10, 11), (11, 12), (12, 9)]                                   # path 9..12
+    pairs += [(20, 15)]                                                      # edge 15-20
+    lab = orc.cc(_sym(pairs), 22)
+    want = list(range(22))
+    for v in range(3, 8):
+        want[v] = 3
+    for v in (9, 10, 11, 12):
+        want[v] = 9
+    want[20] = 15
+    assert lab.tolist() == want
+    # a random sparse graph against a union-find written here
+    src, dst = synth.rmat_edges(3000, 41, scale=11)
+    e = np.unique(synth.edge_keys(src, dst))
+    nv = 2048
+    parent = list(range(nv))
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+
+    for x in e.tolist():
+        a, b = find(x >> 32), find(x & 0xffffffff)
+        if a != b:
+            parent[max(a, b)] = min(a, b)
+    roots = [find(v) for v in range(nv)]
+    lo = {}
+    for v in range(nv):
+        lo.setdefault(roots[v], v)          # smallest id of each set (ids visited in order)
+    assert orc.cc(e, nv).tolist() == [lo[roots[v]] for v in range(nv)]
+
+
+def test_bc_closed_forms(orc):
+    n = 12
+    sg, dl = orc.bc(_sym([(i, i + 1) for i in range(n - 1)]), n, 0)          # path from an end
+    assert sg.tolist() == [1.0] * n and dl.tolist() == [float(n - 1 - v) for v in range(n)]
+    sg, dl = orc.bc(_sym([(0, 1), (0, 2), (1, 3), (2, 3)]), 5, 0)          # diamond + isolated 4
+    assert sg.tolist() == [1, 1, 1, 2, 0] and dl.tolist() == [3.0, 0.5, 0.5, 0.0, 0.0]
+    sg, dl = orc.bc(_sym([(0, i) for i in range(1, 9)]), 9, 0)              # star from its centre
+    assert dl.tolist() == [8.0] + [0.0] * 8
+    sg, dl = orc.bc(_sym([(0, i) for i in range(1, 9)]), 9, 3)              # star from a leaf
+    assert dl[3] == 8.0 and dl[0] == 7.0 and all(dl[v] == 0 for v in range(9) if v not in (0, 3))
+
+
+def test_bc_brute_force_path_counts(orc):
+    """delta_s(v) = sum over t != v of sigma_sv * sigma_vt / sigma_st over the t
+    with d(s, v) + d(v, t) = d(s, t): all-pairs distances and path counts by a
+    breadth-first search from every vertex, on small random graphs."""
+    for seed in (3, 4, 5):
+        src, dst = synth.rmat_edges(150, seed, scale=6)
+        e = np.unique(synth.edge_keys(src, dst))
+        nv = 64
+        adj = [[] for _ in range(nv)]
+        for x in e.tolist():
+            adj[x >> 32].append(x & 0xffffffff)
+        D, C = [], []
+        for s0 in range(nv):
+            d = [-1] * nv
+            c = [0] * nv
+            d[s0], c[s0] = 0, 1
+            fr = [s0]
+            while fr:
+                nxt = []
+                for u in fr:
+                    for w in adj[u]:
+                        if d[w] < 0:
+                            d[w] = d[u] + 1
+                            nxt.append(w)
+                        if d[w] == d[u] + 1:
+                            c[w] += c[u]
+                fr = nxt
+            D.append(d)
+            C.append(c)
+        for s0 in (0, 7):
+            sg, dl = orc.bc(e, nv, s0)
+            for v in range(nv):
+                assert sg[v] == C[s0][v]
+                want = 0.0
+                if D[s0][v] >= 0:
+                    for t in range(nv):
+                        if t != v and D[s0][t] >= 0 and D[v][t] >= 0 and D[s0][v] + D[v][t] == D[s0][t]:
+                            want += C[s0][v] * C[v][t] / C[s0][t]
+                assert abs(dl[v] - want) <= 1e-12 * max(1.0, want), (seed, s0, v, dl[v], want)

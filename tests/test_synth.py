@@ -56,3 +56,13 @@ def test_zipf_keys_shape():
     i = np.arange(1, 3_000_001, dtype=np.float64)
     assert abs(synth.zipf_zeta(3_000_000, 0.99, head=1 << 12) - float(np.sum(i ** -0.99))) < 1e-9
     assert np.array_equal(synth.zipf_keys(100, 31, offset=50), k[50:150])
+
+
+def test_er_edges_uniform_and_torch_twin():
+    import torch
+    s, d = synth.er_edges(200000, 61, 1000)
+    assert int(s.max()) < 1000 and int(d.max()) < 1000
+    counts = np.bincount(s.astype(np.int64), minlength=1000)
+    assert abs(counts.mean() - 200) < 1e-9 and counts.std() < 3 * 200 ** 0.5   # about Poisson(200)
+    ts, td = synth.er_edges_torch(200000, 61, 1000)
+    assert np.array_equal(ts.numpy().astype(np.uint64), s) and np.array_equal(td.numpy().astype(np.uint64), d)
