@@ -98,7 +98,10 @@ typedef enum { CPMA_MEM_HOST = 0, CPMA_MEM_DEVICE = 1 } cpma_mem;
  *                  fresh array sized for build_density -- instead of counting
  *                  and redistributing windows (Section "Parallel Batch Updates
  *                  in a PMA" rebuilds above about n / 10, its example value).
- *                  Default 0.1; results do not depend on it.
+ *                  Default 1.0: on this GPU the counted path is faster at
+ *                  k = n / 10, where every leaf already takes part in the
+ *                  merge (cpma_autotune measures the cut-over for a set).
+ *                  Results do not depend on it.
  *   alloc, free, ctx
  *                  device memory for everything the handle owns (leaves, heads,
  *                  used counts, counters, scratch): alloc(bytes, ctx) returns a
@@ -140,14 +143,18 @@ cpma_status cpma_config_default(cpma_config* cfg);
  * sample's key range is timed, then hint->queries range queries covering about
  * hint->range_keys sample keys each; the score is
  * insert_weight * insert_ms + (1 - insert_weight) * range_ms.  At the winning
- * size, range_chunk in {1, 2, 4, 8, 16, 32} is timed on the same queries.  Each
- * time is the least of three runs after a warm-up.
+ * size, range_chunk in {1, 2, 4, 8, 16, 32} is timed on the same queries, and
+ * the insert batch (with a delete of it) once with the full rebuild forced
+ * and once with the counted path: rebuild_frac becomes min(base value, batch
+ * / sample) when the rebuild was faster, else max(base value, 2 * batch /
+ * sample).  Each time is the least of three runs after a warm-up.
  *
  * keys: n keys in `mem` (host or device), any order; UINT64_MAX is rejected.
  * hint: NULL or zero fields take defaults (batch n / 10, range_keys 1000,
  *       queries 1e5, sample_keys 2^22, insert_weight 0.5 when negative).
  * base: the other configuration fields (NULL = defaults).
- * out:  receives base with leaf_bytes and range_chunk set to the winners.
+ * out:  receives base with leaf_bytes, range_chunk and rebuild_frac set to the
+ *       winners.
  * report: NULL or receives every measured time.
  * Synchronises `stream`; allocates and frees its own trial sets.
  */
@@ -168,6 +175,9 @@ typedef struct {
   double chunk_ms[6];        /* range query batch time per chunk at the winning size */
   uint32_t best_leaf_bytes;
   uint32_t best_chunk;
+  double rebuild_ms;         /* insert + delete of the batch, full rebuild forced */
+  double batch_path_ms;      /* the same with the counted batch path */
+  double best_rebuild_frac;  /* rebuild_frac of the returned configuration */
 } cpma_tune_report;
 
 cpma_status cpma_autotune(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpma_tune_hint* hint,
@@ -300,22 +310,59 @@ cpma_status cpma_fgraph_pagerank(const cpma* set, uint32_t nv, int iters, double
                                  cpma_mem mem, float* p, void* stream);
 
 /*
- * Serving: a request queue in front of one set, served by a worker thread.
+ * The rest of F-Graph's kernels (Section "Evaluation on graph workloads":
+ * PageRank, connected components and single-source betweenness centrality,
+ * and the vertex array of offsets that the flat edge array has to rebuild).
+ * Same edge-key and leaf-size rules as above; all three synchronise `stream`.
  *
- * Requests are admitted in arrival order while the in-flight HBM footprint
- * stays under `hbm_budget` bytes and at most `max_slots` requests are in
- * flight; the admitted requests form one step.  A step runs every range
- * request it holds as one batched cpma_range_map launch against the state left
- * by the previous steps, then applies its insert / delete requests in arrival
- * order with one cpma_apply_updates call (the paper phases updates and queries
- * with a single writer, Section "Evaluation on graph workloads").  Each
- * request's result therefore equals replaying all requests in (step, queries
- * first, updates in arrival order) order one call each.
+ * cpma_fgraph_offsets: off[v] = number of edges (u, w) with u < v (both ids
+ * below nv), v = 0 .. nv: the offsets array of the graph's CSR form, from one
+ * degree pass and a prefix sum.  off has nv + 1 entries in memory space `mem`.
+ *
+ * cpma_fgraph_cc: connected components of the undirected graph the symmetric
+ * edge set stores: label[v] = the smallest vertex id of v's component (so the
+ * result is unique).  Label propagation over the edges, one atomic minimum per
+ * run of equal source, with pointer jumping between passes, until a pass
+ * changes no label.  label is nv entries in memory space `mem`.
+ *
+ * cpma_fgraph_bc: single-source betweenness centrality from `source` (Brandes'
+ * dependency accumulation) on the symmetric edge set: sigma[v] = number of
+ * shortest paths from source to v, delta[v] = sum over the vertices w whose
+ * shortest paths pass through v of sigma[v] / sigma[w] * (1 + delta[w]); both
+ * 0 for unreachable vertices, FP64 arithmetic (path counts are exact integers
+ * while below 2^53).  Levels come from the BFS above; each level then takes
+ * one pass over the leaves holding its vertices, outwards for sigma and inwards
+ * for delta.  delta (and sigma unless NULL) are nv doubles in memory space
+ * `mem`.
+ */
+cpma_status cpma_fgraph_offsets(const cpma* set, uint32_t nv, cpma_mem mem, uint64_t* off, void* stream);
+cpma_status cpma_fgraph_cc(const cpma* set, uint32_t nv, cpma_mem mem, uint32_t* label, void* stream);
+cpma_status cpma_fgraph_bc(const cpma* set, uint32_t nv, uint32_t source, cpma_mem mem, double* sigma,
+                           double* delta, void* stream);
+
+/*
+ * Serving: continuous batching of a request stream in front of one set.
+ *
+ * A stager thread admits requests in arrival order while the in-flight HBM
+ * footprint (admitted requests not yet done) stays under `hbm_budget` bytes and
+ * at most `max_slots` requests are in flight, and uploads each admitted
+ * request's data to the device on a copy stream at once: requests that arrive
+ * while a step runs on the GPU join the next step, and their uploads overlap
+ * that step's work.  An executor thread, the set's single writer, takes the
+ * next step as soon as the current one ends: it runs every range request of the
+ * step as one batched cpma_range_map launch against the state left by the
+ * previous steps, then the step's insert / delete requests in arrival order
+ * with one cpma_apply_updates call (the paper phases updates and queries with
+ * a single writer, Section "Evaluation on graph workloads").  A request's
+ * footprint and slot return to the budget when it is done.  Each request's
+ * result therefore equals replaying all requests in (step, queries first,
+ * updates in arrival order) order one call each.
  *
  * All request buffers are host memory and must stay valid until the request
  * is done.  `done` becomes nonzero (release store) when the outputs are
- * written; `t_done_ns` is the completion time on the steady clock that
- * cpma_clock_ns reads, `step` the step that served it.
+ * written; `t_admit_ns` / `t_done_ns` are the admission and completion times on
+ * the steady clock that cpma_clock_ns reads, `step` the step that served it.
+ * While a server runs, the set must not be used by anyone else.
  */
 typedef enum { CPMA_REQ_RANGE = 0, CPMA_REQ_INSERT = 1, CPMA_REQ_DELETE = 2 } cpma_req_kind;
 
@@ -332,6 +379,7 @@ typedef struct {
   volatile int32_t done;
   uint64_t t_done_ns;
   uint64_t step;
+  uint64_t t_admit_ns;
 } cpma_request;
 
 /*
@@ -364,7 +412,7 @@ typedef struct {
 
 typedef struct cpma_server cpma_server;
 
-/* Starts a worker thread serving `set` (which it must be the only writer of). */
+/* Starts the stager and executor threads serving `set` on the current GPU. */
 cpma_status cpma_server_start(cpma* set, const cpma_server_config* cfg, cpma_server** out);
 /* Queues a request (stamped with its arrival); thread safe. */
 cpma_status cpma_server_submit(cpma_server* srv, cpma_request* req);

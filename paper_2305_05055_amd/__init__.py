@@ -46,7 +46,9 @@ class TuneReport(ctypes.Structure):
     _fields_ = [("sample_n", ctypes.c_uint64), ("leaf_bytes", ctypes.c_uint32 * 5),
                 ("insert_ms", ctypes.c_double * 5), ("range_ms", ctypes.c_double * 5),
                 ("chunk", ctypes.c_uint32 * 6), ("chunk_ms", ctypes.c_double * 6),
-                ("best_leaf_bytes", ctypes.c_uint32), ("best_chunk", ctypes.c_uint32)]
+                ("best_leaf_bytes", ctypes.c_uint32), ("best_chunk", ctypes.c_uint32),
+                ("rebuild_ms", ctypes.c_double), ("batch_path_ms", ctypes.c_double),
+                ("best_rebuild_frac", ctypes.c_double)]
 
 
 class Request(ctypes.Structure):
@@ -54,7 +56,8 @@ class Request(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("pad", ctypes.c_uint32), ("n", ctypes.c_uint64),
                 ("keys", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("sum", ctypes.c_void_p),
                 ("count", ctypes.c_void_p), ("result", ctypes.c_uint64), ("status", ctypes.c_int32),
-                ("done", ctypes.c_int32), ("t_done_ns", ctypes.c_uint64), ("step", ctypes.c_uint64)]
+                ("done", ctypes.c_int32), ("t_done_ns", ctypes.c_uint64), ("step", ctypes.c_uint64),
+                ("t_admit_ns", ctypes.c_uint64)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -104,6 +107,9 @@ def lib():
         L.cpma_destroy.argtypes = [vp]
         L.cpma_destroy.restype = None
         L.cpma_fgraph_bfs.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_int, vp, vp]
+        L.cpma_fgraph_offsets.argtypes = [vp, ctypes.c_uint32, ctypes.c_int, vp, vp]
+        L.cpma_fgraph_cc.argtypes = [vp, ctypes.c_uint32, ctypes.c_int, vp, vp]
+        L.cpma_fgraph_bc.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, vp, vp, vp]
         L.cpma_fgraph_pagerank.argtypes = [vp, ctypes.c_uint32, ctypes.c_int, ctypes.c_double,
                                            ctypes.c_int, vp, vp]
         L.cpma_server_start.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
@@ -160,7 +166,7 @@ def default_config():
 
 def autotune(keys, batch=0, range_keys=0, queries=0, sample_keys=0, insert_weight=-1.0, base=None,
              stream=None):
-    """cpma_autotune: (Config with the chosen leaf_bytes and range_chunk, report dict)."""
+    """cpma_autotune: (Config with the chosen leaf_bytes, range_chunk and rebuild_frac, report dict)."""
     p, n, mem, keep = _keys(keys)
     hint = TuneHint(batch, range_keys, queries, sample_keys, insert_weight)
     out = Config()
@@ -172,7 +178,9 @@ def autotune(keys, batch=0, range_keys=0, queries=0, sample_keys=0, insert_weigh
     report = {"sample_n": rep.sample_n, "best_leaf_bytes": rep.best_leaf_bytes, "best_chunk": rep.best_chunk,
               "leaf_bytes": {int(rep.leaf_bytes[i]): {"insert_ms": rep.insert_ms[i], "range_ms": rep.range_ms[i]}
                              for i in range(5)},
-              "range_chunk_ms": {int(rep.chunk[i]): rep.chunk_ms[i] for i in range(6)}}
+              "range_chunk_ms": {int(rep.chunk[i]): rep.chunk_ms[i] for i in range(6)},
+              "rebuild_ms": rep.rebuild_ms, "batch_path_ms": rep.batch_path_ms,
+              "best_rebuild_frac": rep.best_rebuild_frac}
     return out, report
 
 
@@ -349,6 +357,36 @@ class CPMA:
         _check(lib().cpma_fgraph_pagerank(self._h, nv, iters, damping, mem, ptr,
                                           _stream(stream, device)), "cpma_fgraph_pagerank")
         return out
+
+    def _out(self, n, np_dtype, torch_dtype, device):
+        if device:
+            import torch
+            out = torch.empty(n, dtype=torch_dtype, device="cuda")
+            return out, ctypes.c_void_p(out.data_ptr()), MEM_DEVICE
+        out = np.empty(n, dtype=np_dtype)
+        return out, ctypes.c_void_p(out.ctypes.data), MEM_HOST
+
+    def offsets(self, nv, device=False, stream=None):
+        """Vertex offset array: off[v] = number of edges with source below v (nv + 1 entries)."""
+        import torch
+        out, ptr, mem = self._out(nv + 1, np.uint64, torch.int64, device)
+        _check(lib().cpma_fgraph_offsets(self._h, nv, mem, ptr, _stream(stream, device)), "cpma_fgraph_offsets")
+        return out
+
+    def cc(self, nv, device=False, stream=None):
+        """Connected components: the smallest vertex id of each vertex's component."""
+        import torch
+        out, ptr, mem = self._out(nv, np.uint32, torch.int32, device)
+        _check(lib().cpma_fgraph_cc(self._h, nv, mem, ptr, _stream(stream, device)), "cpma_fgraph_cc")
+        return out
+
+    def bc(self, nv, source=0, device=False, stream=None):
+        """Single-source betweenness from `source`: (sigma, delta), FP64."""
+        import torch
+        sg, psg, mem = self._out(nv, np.float64, torch.float64, device)
+        dl, pdl, _ = self._out(nv, np.float64, torch.float64, device)
+        _check(lib().cpma_fgraph_bc(self._h, nv, source, mem, psg, pdl, _stream(stream, device)), "cpma_fgraph_bc")
+        return sg, dl
 
     def stats_enable(self, on=True):
         """Starts (zeroing) or stops per-phase HIP-event timing inside the library."""

@@ -1817,6 +1817,65 @@ static uint32_t fg_grid(const cpma* s) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((s->L + 3) / 4, (uint64_t)s->num_cus * 16));
 }
 
+}  // extern "C"
+
+namespace {
+
+// Level-synchronous BFS from `source` into lv (nv entries, device); returns the
+// number of levels.  front / seen bitmaps and the per-block counts live in
+// s->fg_c; on return `front` holds the last level's bitmap.
+uint32_t bfs_levels(cpma* s, uint32_t nv, uint32_t source, bool symmetric, uint32_t* lv, hipStream_t st,
+                    BfsBits* bits_out = nullptr, unsigned long long** cpart_out = nullptr,
+                    uint32_t* cgrid_out = nullptr) {
+  hipLaunchKernelGGL((k_fill<uint32_t>), dim3(grid_for(nv, 256, 4096)), dim3(256), 0, st, lv, (uint64_t)nv,
+                     0xffffffffu);
+  hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, lv + source, (uint64_t)1, 0u);
+  HIPCHK(hipGetLastError());
+  const FgArgs g = fg_args(s, nv);
+  // bitmaps of the current level and of the visited vertices, rebuilt after
+  // every level together with the level sizes (one slot pair per block,
+  // summed into the last pair)
+  const uint32_t nw = (nv + 31) / 32;
+  const uint32_t cgrid = grid_for(nw, 256, (uint32_t)s->num_cus * 8);
+  const uint64_t bits_words = 2ull * ((nw + 1) & ~1u);  // keeps the slots 8-byte aligned
+  ensure(s->fg_c, 4 * bits_words + 16ull * (cgrid + 1));
+  uint32_t* front = s->fg_c.as<uint32_t>();
+  uint32_t* seen = front + (bits_words / 2);
+  unsigned long long* cpart = reinterpret_cast<unsigned long long*>(front + bits_words);
+  const BfsBits bb{front, seen};
+  uint64_t* hc = reinterpret_cast<uint64_t*>(host_pin(s, 16));
+  hipLaunchKernelGGL(k_fg_level_bits, dim3(cgrid), dim3(256), 0, st, (const uint32_t*)lv, nv, 0u, front, seen,
+                     cpart);
+  HIPCHK(hipGetLastError());
+  // the step runs bottom-up once the level is large against the unvisited
+  // set (its vertices have the most edges, so top-down gets dear early)
+  uint64_t frontier = 1, unvisited = nv - 1;
+  uint32_t cur = 0;
+  for (; frontier > 0 && cur < nv; cur++) {
+    if (!symmetric || 4 * frontier <= unvisited)
+      hipLaunchKernelGGL(k_fg_bfs_step<false>, dim3(fg_grid(s)), dim3(256), 0, st, g, bb, lv, cur);
+    else
+      hipLaunchKernelGGL(k_fg_bfs_step<true>, dim3(fg_grid(s)), dim3(256), 0, st, g, bb, lv, cur);
+    hipLaunchKernelGGL(k_fg_level_bits, dim3(cgrid), dim3(256), 0, st, (const uint32_t*)lv, nv, cur + 1, front,
+                       seen, cpart);
+    hipLaunchKernelGGL(k_fg_fold_counts, dim3(1), dim3(1024), 0, st, (const unsigned long long*)cpart, cgrid,
+                       cpart + 2ull * cgrid);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(hc, cpart + 2ull * cgrid, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    frontier = hc[0];
+    unvisited = hc[1];
+  }
+  if (bits_out) *bits_out = bb;
+  if (cpart_out) *cpart_out = cpart;
+  if (cgrid_out) *cgrid_out = cgrid;
+  return cur;  // levels 0 .. cur - 1 are non-empty
+}
+
+}  // namespace
+
+extern "C" {
+
 cpma_status cpma_fgraph_bfs(const cpma* cs, uint32_t nv, uint32_t source, int symmetric, cpma_mem mem,
                             uint32_t* level, void* stream) {
   cpma* s = const_cast<cpma*>(cs);
@@ -1831,46 +1890,123 @@ cpma_status cpma_fgraph_bfs(const cpma* cs, uint32_t nv, uint32_t source, int sy
       ensure(s->fg_level, (uint64_t)nv * 4);
       lv = s->fg_level.as<uint32_t>();
     }
-    hipLaunchKernelGGL((k_fill<uint32_t>), dim3(grid_for(nv, 256, 4096)), dim3(256), 0, st, lv, (uint64_t)nv,
-                       0xffffffffu);
-    hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, lv + source, (uint64_t)1, 0u);
-    HIPCHK(hipGetLastError());
-    const FgArgs g = fg_args(s, nv);
-    // bitmaps of the current level and of the visited vertices, rebuilt after
-    // every level together with the level sizes (one slot pair per block,
-    // summed into the last pair)
-    const uint32_t nw = (nv + 31) / 32;
-    const uint32_t cgrid = grid_for(nw, 256, (uint32_t)s->num_cus * 8);
-    const uint64_t bits_words = 2ull * ((nw + 1) & ~1u);  // keeps the slots 8-byte aligned
-    ensure(s->fg_c, 4 * bits_words + 16ull * (cgrid + 1));
-    uint32_t* front = s->fg_c.as<uint32_t>();
-    uint32_t* seen = front + (bits_words / 2);
-    unsigned long long* cpart = reinterpret_cast<unsigned long long*>(front + bits_words);
-    const BfsBits bb{front, seen};
-    uint64_t* hc = reinterpret_cast<uint64_t*>(host_pin(s, 16));
-    hipLaunchKernelGGL(k_fg_level_bits, dim3(cgrid), dim3(256), 0, st, (const uint32_t*)lv, nv, 0u, front, seen,
-                       cpart);
-    HIPCHK(hipGetLastError());
-    // the step runs bottom-up once the level is large against the unvisited
-    // set (its vertices have the most edges, so top-down gets dear early)
-    uint64_t frontier = 1, unvisited = nv - 1;
-    for (uint32_t cur = 0; frontier > 0 && cur < nv; cur++) {
-      if (!symmetric || 4 * frontier <= unvisited)
-        hipLaunchKernelGGL(k_fg_bfs_step<false>, dim3(fg_grid(s)), dim3(256), 0, st, g, bb, lv, cur);
-      else
-        hipLaunchKernelGGL(k_fg_bfs_step<true>, dim3(fg_grid(s)), dim3(256), 0, st, g, bb, lv, cur);
-      hipLaunchKernelGGL(k_fg_level_bits, dim3(cgrid), dim3(256), 0, st, (const uint32_t*)lv, nv, cur + 1, front,
-                         seen, cpart);
-      hipLaunchKernelGGL(k_fg_fold_counts, dim3(1), dim3(1024), 0, st, (const unsigned long long*)cpart, cgrid,
-                         cpart + 2ull * cgrid);
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(hc, cpart + 2ull * cgrid, 16, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      frontier = hc[0];
-      unvisited = hc[1];
-    }
+    bfs_levels(s, nv, source, symmetric != 0, lv, st);
     if (mem == CPMA_MEM_HOST) {
       HIPCHK(hipMemcpyAsync(level, lv, (uint64_t)nv * 4, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
+cpma_status cpma_fgraph_offsets(const cpma* cs, uint32_t nv, cpma_mem mem, uint64_t* off, void* stream) {
+  cpma* s = const_cast<cpma*>(cs);
+  if (!s || !off || nv == 0) return CPMA_ERR_INVALID;
+  if (s->S > kWaveMaxS) return CPMA_ERR_INVALID;
+  if (s->broken) return CPMA_ERR_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  return guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    uint64_t* dof = off;
+    if (mem == CPMA_MEM_HOST) {
+      ensure(s->fg_acc, ((uint64_t)nv + 1) * 8);
+      dof = s->fg_acc.as<uint64_t>();
+    }
+    ensure(s->fg_deg, (uint64_t)nv * 4);
+    hipLaunchKernelGGL((k_fill<uint32_t>), dim3(grid_for(nv, 256, 8192)), dim3(256), 0, st, s->fg_deg.as<uint32_t>(),
+                       (uint64_t)nv, 0u);
+    const FgArgs g = fg_args(s, nv);
+    hipLaunchKernelGGL(k_fg_degree, dim3(fg_grid(s)), dim3(256), 0, st, g, s->fg_deg.as<uint32_t>());
+    HIPCHK(hipGetLastError());
+    scan<uint64_t>(s, dof, nv, st, U32AsU64Fn{s->fg_deg.as<uint32_t>()});
+    if (mem == CPMA_MEM_HOST)
+      HIPCHK(hipMemcpyAsync(off, dof, ((uint64_t)nv + 1) * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
+cpma_status cpma_fgraph_cc(const cpma* cs, uint32_t nv, cpma_mem mem, uint32_t* label, void* stream) {
+  cpma* s = const_cast<cpma*>(cs);
+  if (!s || !label || nv == 0) return CPMA_ERR_INVALID;
+  if (s->S > kWaveMaxS) return CPMA_ERR_INVALID;
+  if (s->broken) return CPMA_ERR_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  return guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    uint32_t* lab = label;
+    if (mem == CPMA_MEM_HOST) {
+      ensure(s->fg_level, (uint64_t)nv * 4);
+      lab = s->fg_level.as<uint32_t>();
+    }
+    ensure(s->fg_c, 16);
+    uint32_t* changed = s->fg_c.as<uint32_t>();
+    uint32_t* hc = reinterpret_cast<uint32_t*>(host_pin(s, 16));
+    const uint32_t vg = grid_for(nv, 256, 8192);
+    hipLaunchKernelGGL(k_fg_iota, dim3(vg), dim3(256), 0, st, lab, nv);
+    const FgArgs g = fg_args(s, nv);
+    for (uint32_t it = 0; it <= nv; it++) {
+      hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, changed, (uint64_t)1, 0u);
+      hipLaunchKernelGGL(k_fg_cc_prop, dim3(fg_grid(s)), dim3(256), 0, st, g, lab, changed);
+      hipLaunchKernelGGL(k_fg_cc_jump, dim3(vg), dim3(256), 0, st, lab, nv);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(hc, changed, 4, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (!hc[0]) break;
+    }
+    if (mem == CPMA_MEM_HOST) HIPCHK(hipMemcpyAsync(label, lab, (uint64_t)nv * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
+cpma_status cpma_fgraph_bc(const cpma* cs, uint32_t nv, uint32_t source, cpma_mem mem, double* sigma,
+                           double* delta, void* stream) {
+  cpma* s = const_cast<cpma*>(cs);
+  if (!s || !delta || nv == 0 || source >= nv) return CPMA_ERR_INVALID;
+  if (s->S > kWaveMaxS) return CPMA_ERR_INVALID;
+  if (s->broken) return CPMA_ERR_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  return guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    ensure(s->fg_level, (uint64_t)nv * 4);
+    uint32_t* lv = s->fg_level.as<uint32_t>();
+    double* sg = (mem == CPMA_MEM_DEVICE && sigma) ? sigma : nullptr;
+    double* dl = mem == CPMA_MEM_DEVICE ? delta : nullptr;
+    if (!sg) {
+      ensure(s->fg_p, (uint64_t)nv * 8);
+      sg = s->fg_p.as<double>();
+    }
+    if (!dl) {
+      ensure(s->fg_acc, (uint64_t)nv * 8);
+      dl = s->fg_acc.as<double>();
+    }
+    BfsBits bb;
+    unsigned long long* cpart = nullptr;
+    uint32_t cgrid = 0;
+    const uint32_t nlev = bfs_levels(s, nv, source, true, lv, st, &bb, &cpart, &cgrid);
+    const uint32_t vg = grid_for(nv, 256, 8192);
+    hipLaunchKernelGGL((k_fill<double>), dim3(vg), dim3(256), 0, st, sg, (uint64_t)nv, 0.0);
+    hipLaunchKernelGGL((k_fill<double>), dim3(vg), dim3(256), 0, st, dl, (uint64_t)nv, 0.0);
+    hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(64), 0, st, sg + source, (uint64_t)1, 1.0);
+    const FgArgs g = fg_args(s, nv);
+    uint32_t* front = const_cast<uint32_t*>(bb.front);
+    uint32_t* seen = const_cast<uint32_t*>(bb.seen);
+    // path counts, level by level outwards, then dependencies inwards
+    for (uint32_t l = 1; l < nlev; l++) {
+      hipLaunchKernelGGL(k_fg_level_bits, dim3(cgrid), dim3(256), 0, st, (const uint32_t*)lv, nv, l, front, seen,
+                         cpart);
+      hipLaunchKernelGGL(k_fg_bc_level<false>, dim3(fg_grid(s)), dim3(256), 0, st, g, bb, (const uint32_t*)lv, l,
+                         (const double*)sg, (const double*)dl, sg);
+    }
+    for (uint32_t l = nlev; l-- > 0;) {
+      if (l + 1 >= nlev) continue;  // the last level depends on nothing
+      hipLaunchKernelGGL(k_fg_level_bits, dim3(cgrid), dim3(256), 0, st, (const uint32_t*)lv, nv, l, front, seen,
+                         cpart);
+      hipLaunchKernelGGL(k_fg_bc_level<true>, dim3(fg_grid(s)), dim3(256), 0, st, g, bb, (const uint32_t*)lv, l,
+                         (const double*)sg, (const double*)dl, dl);
+    }
+    HIPCHK(hipGetLastError());
+    if (mem == CPMA_MEM_HOST) {
+      HIPCHK(hipMemcpyAsync(delta, dl, (uint64_t)nv * 8, hipMemcpyDeviceToHost, st));
+      if (sigma) HIPCHK(hipMemcpyAsync(sigma, sg, (uint64_t)nv * 8, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipStreamSynchronize(st));
   });
@@ -2073,6 +2209,7 @@ extern "C" cpma_status cpma_autotune(const uint64_t* keys, uint64_t n, cpma_mem 
     if (base->lo_root > 0) cfg.lo_root = base->lo_root;
     cfg.build_density = base->build_density > 0 ? base->build_density : cfg.up_root / cfg.grow;
     if (base->range_chunk) cfg.range_chunk = base->range_chunk;
+    if (base->rebuild_frac > 0) cfg.rebuild_frac = base->rebuild_frac;
   }
   cpma_status cs = check_config(cfg);
   if (cs != CPMA_OK) return cs;
@@ -2199,6 +2336,29 @@ extern "C" cpma_status cpma_autotune(const uint64_t* keys, uint64_t n, cpma_mem 
     cfg.range_chunk = bestC;
     rep.best_leaf_bytes = bestS;
     rep.best_chunk = bestC;
+    // rebuild cut-over: the insert batch (and a delete of it) with the full
+    // rebuild forced and with the counted path, at the winning leaf size
+    {
+      const double r = (double)kk / (double)ns;
+      double ms2[2];
+      for (int v = 0; v < 2; v++) {
+        cpma_config tc = cfg;
+        tc.rebuild_frac = v == 0 ? std::max(1e-9, 0.5 * r) : 1e30;
+        Handle h;
+        st_check(cpma_build(sample, ns, CPMA_MEM_DEVICE, &tc, st, &h.h));
+        ms2[v] = time_min(st, 3, [&](int rr) {
+          hipLaunchKernelGGL(k_gen_uniform, dim3(grid_for(kk, 256, 4096)), dim3(256), 0, st, ins, kk, T,
+                             0x2000ull + (uint64_t)rr);
+          st_check(cpma_insert_batch(h.h, ins, kk, CPMA_MEM_DEVICE, 0, st, nullptr));
+          st_check(cpma_delete_batch(h.h, ins, kk, CPMA_MEM_DEVICE, 0, st, nullptr));
+        });
+      }
+      rep.rebuild_ms = ms2[0];
+      rep.batch_path_ms = ms2[1];
+      // batches of this relative size rebuild only where that was faster
+      cfg.rebuild_frac = ms2[0] < ms2[1] ? std::min(cfg.rebuild_frac, r) : std::max(cfg.rebuild_frac, 2.0 * r);
+      rep.best_rebuild_frac = cfg.rebuild_frac;
+    }
   } catch (const Fail& e) {
     return e.st;
   }

@@ -317,6 +317,129 @@ __global__ void __launch_bounds__(1024) k_fg_fold_counts(const unsigned long lon
   }
 }
 
+// Degree counts widened for a 64-bit prefix sum (the vertex offset array).
+struct U32AsU64Fn {
+  const uint32_t* p;
+  __device__ uint64_t operator()(uint64_t i) const { return p[i]; }
+};
+
+// ---- connected components (label propagation with pointer jumping) -----------
+// lab[u] = min(lab[u], min over edges (u, v) of lab[v]), one atomic per run of
+// equal source; *changed is set when a label fell.  Labels only fall, and only
+// to the label of a vertex of the same component, so the component's smallest
+// id keeps its own label and, once no label falls, every vertex holds it.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, off, kWave));
+  return x;
+}
+
+__global__ void __launch_bounds__(256) k_fg_cc_prop(FgArgs g, uint32_t* __restrict__ lab,
+                                                    uint32_t* __restrict__ changed) {
+  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
+  bool ch = false;
+  for (uint64_t leaf = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; leaf < g.L;
+       leaf += waves) {
+    uint64_t kk[16];
+    const uint32_t tm = wave_leaf_keys(g.bytes + leaf * (uint64_t)g.S, g.used[leaf], kk);
+    uint32_t val[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      const uint32_t sv = src_of(kk[i]), d = dst_of(kk[i]);
+      val[i] = ((tm & (1u << i)) && d < g.nv && sv < g.nv) ? lab[d] : 0xffffffffu;
+    }
+    const uint32_t one = fg_single_source(g, leaf, kk, tm);
+    if (one != 0xffffffffu) {
+      uint32_t m = 0xffffffffu;
+#pragma unroll
+      for (int i = 0; i < 16; i++) m = min(m, val[i]);
+      m = wave_min_u32(m);
+      if (lane_id() == 0 && one < g.nv && m != 0xffffffffu) ch |= atomicMin(&lab[one], m) > m;
+      continue;
+    }
+    uint32_t run = 0xffffffffu, rmin = 0xffffffffu;
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+      if (tm & (1u << i)) {
+        const uint32_t sv = src_of(kk[i]);
+        if (sv != run) {
+          if (run < g.nv && rmin != 0xffffffffu) ch |= atomicMin(&lab[run], rmin) > rmin;
+          run = sv;
+          rmin = 0xffffffffu;
+        }
+        rmin = min(rmin, val[i]);
+      }
+    }
+    if (run < g.nv && rmin != 0xffffffffu) ch |= atomicMin(&lab[run], rmin) > rmin;
+  }
+  if (__ballot(ch) && lane_id() == 0) *changed = 1u;  // every writer stores the same value
+}
+
+// Pointer jumping: lab[v] = lab[lab[v]] until it stops falling (every label
+// on the chain is a vertex of v's component, so the result is too).
+__global__ void k_fg_cc_jump(uint32_t* __restrict__ lab, uint32_t nv) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+    uint32_t l = lab[v];
+    for (;;) {
+      const uint32_t ll = lab[l];
+      if (ll >= l) break;
+      l = ll;
+    }
+    lab[v] = l;
+  }
+}
+
+__global__ void k_fg_iota(uint32_t* __restrict__ lab, uint32_t nv) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) lab[v] = v;
+}
+
+// ---- single-source betweenness (Brandes), level by level --------------------
+// With BFS levels from the source known, on a symmetric edge set:
+//   sigma[v] = sum over edges (v, u) with level[u] = level[v] - 1 of sigma[u]
+//   delta[v] = sigma[v] * sum over edges (v, w) with level[w] = level[v] + 1 of
+//              (1 + delta[w]) / sigma[w]
+// A level's pass decodes only the leaves holding a source of that level (the
+// `front` bitmap), folds each run of equal source and adds it with one FP64
+// atomic.  kDelta selects the second formula.
+template <bool kDelta>
+__global__ void __launch_bounds__(256) k_fg_bc_level(FgArgs g, BfsBits bb, const uint32_t* __restrict__ level,
+                                                     uint32_t cur, const double* sigma_in, const double* delta_in,
+                                                     double* out) {
+  const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / kWave);
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const uint32_t want = kDelta ? cur + 1 : cur - 1;  // the neighbours' level
+  for (uint64_t base = wave * kWave; base < g.L; base += nwaves * kWave) {
+    const uint64_t f = base + (uint64_t)lane_id();
+    const bool need = f < g.L && fg_leaf_has(g, bb.front, 0u, f);
+    uint64_t m = __ballot(need);
+    while (m) {
+      const uint64_t leaf = base + (uint64_t)(__ffsll((unsigned long long)m) - 1);
+      m &= m - 1;
+      uint64_t kk[16];
+      const uint32_t tm = wave_leaf_keys(g.bytes + leaf * (uint64_t)g.S, g.used[leaf], kk);
+      uint32_t run = 0xffffffffu;
+      double acc = 0.0;
+      bool any = false;
+#pragma unroll
+      for (int i = 0; i < 16; i++) {
+        if (!(tm & (1u << i))) continue;
+        const uint32_t sv = src_of(kk[i]), d = dst_of(kk[i]);
+        if (sv != run) {
+          if (any) atomicAdd(&out[run], kDelta ? sigma_in[run] * acc : acc);
+          run = sv;
+          acc = 0.0;
+          any = false;
+        }
+        if (sv < g.nv && d < g.nv && bit_of(bb.front, sv) && level[d] == want) {
+          acc += kDelta ? (1.0 + delta_in[d]) / sigma_in[d] : sigma_in[d];
+          any = true;
+        }
+      }
+      if (any) atomicAdd(&out[run], kDelta ? sigma_in[run] * acc : acc);
+    }
+  }
+}
+
 // PageRank vertex kernels: contrib[u] = p[u] / deg[u] (0 for isolated vertices),
 // and the update p[v] = (1 - d) / N + d * acc[v].
 __global__ void k_pr_contrib(const float* __restrict__ p, const uint32_t* __restrict__ deg, uint32_t nv,

@@ -88,7 +88,7 @@ def test_server_argument_checks_without_gpu():
     assert L.cpma_server_stop(None, None) == 1
     t0 = p.clock_ns()
     assert p.clock_ns() >= t0 > 0
-    assert ctypes.sizeof(p.Request) == 80
+    assert ctypes.sizeof(p.Request) == 88
 
 
 def test_struct_layouts_match_the_header(tmp_path):

@@ -113,3 +113,75 @@ def test_rmat_scale24_benchmarked_size(cp, orc):
     torch.cuda.empty_cache()
     assert c.size() == len(ks)
     check_graph(c, ks, nv, orc)
+
+
+# ---- vertex offsets, connected components, single-source betweenness --------------
+def check_more(c, ks, nv, orc, sources=(0,)):
+    assert np.array_equal(c.offsets(nv), orc.offsets(ks, nv))
+    assert np.array_equal(c.cc(nv), orc.cc(ks, nv))
+    for src in sources:
+        sg, dl = c.bc(nv, src)
+        osg, odl = orc.bc(ks, nv, src)
+        small = osg < 2.0 ** 50                       # path counts exact while well inside FP64
+        assert np.array_equal(sg[small], osg[small])
+        assert np.allclose(sg[~small], osg[~small], rtol=1e-12, atol=0)
+        err = np.abs(dl - odl) / np.maximum(1.0, np.abs(odl))
+        assert err.max() <= 1e-9, (src, err.max())
+
+
+@pytest.mark.parametrize("S", [128, 1024])
+def test_offsets_cc_bc_small_rmat(cp, orc, S):
+    scale = 12
+    keys = graph(scale, 30000, 111)
+    ks = orc.build_set(keys)
+    c = cp.CPMA(keys, leaf_bytes=S)
+    check_more(c, ks, 1 << scale, orc, sources=(0, 17, (1 << scale) - 1))
+
+
+def test_cc_many_components_and_isolated(cp, orc):
+    """Several disjoint R-MAT graphs on separate id ranges, plus isolated ids and
+    edges whose ids lie beyond nv (ignored)."""
+    parts = []
+    for i in range(5):
+        s, d = synth.rmat_edges(3000, 500 + i, scale=10)
+        parts.append(synth.edge_keys(s + np.uint64(2048 * i), d + np.uint64(2048 * i)))
+    nv = 5 * 2048 + 100
+    beyond = synth.edge_keys(np.array([5, nv + 3], np.uint64), np.array([nv + 7, 9], np.uint64))
+    keys = np.concatenate(parts + [beyond])
+    ks = orc.build_set(keys)
+    c = cp.CPMA(keys, leaf_bytes=256)
+    inside = ks[((ks >> np.uint64(32)) < nv) & ((ks & np.uint64(0xffffffff)) < nv)]
+    assert np.array_equal(c.cc(nv), orc.cc(inside, nv))
+    assert np.array_equal(c.offsets(nv), orc.offsets(inside, nv))
+    lab = c.cc(nv, device=True).cpu().numpy().view(np.uint32)
+    assert np.array_equal(lab, orc.cc(inside, nv))
+
+
+def test_erdos_renyi_graph(cp, orc):
+    nv = 1 << 15
+    s, d = synth.er_edges(200000, 701, nv)
+    keys = synth.edge_keys(s, d)
+    ks = orc.build_set(keys)
+    c = cp.CPMA(keys)
+    check_more(c, ks, nv, orc, sources=(0, 12345))
+    check_graph(c, ks, nv, orc)
+
+
+def test_offsets_cc_bc_after_edge_batches(cp, orc):
+    scale = 16
+    keys = graph(scale, 400000, 811)
+    ks = orc.build_set(keys)
+    c = cp.CPMA(keys)
+    for b in range(2):
+        batch = graph(scale, 60000, 820 + b)
+        ks, added = orc.insert(ks, batch)
+        assert c.insert_batch(batch) == added
+    fwd = ks[::7]
+    rev = ((fwd & np.uint64(0xffffffff)) << np.uint64(32)) | (fwd >> np.uint64(32))
+    ks, removed = orc.delete(ks, np.concatenate([fwd, rev]))
+    assert c.delete_batch(np.concatenate([fwd, rev])) == removed
+    check_more(c, ks, 1 << scale, orc, sources=(0, 3))
+    sg, dl = c.bc(1 << scale, 0, device=True)
+    osg, odl = orc.bc(ks, 1 << scale, 0)
+    err = np.abs(dl.cpu().numpy() - odl) / np.maximum(1.0, np.abs(odl))
+    assert err.max() <= 1e-9

@@ -34,6 +34,14 @@ def test_autotune_report_and_tuned_set(cp, orc):
     assert 1 << 16 <= rep["sample_n"] <= 1 << 20
     for S, t in rep["leaf_bytes"].items():
         assert t["insert_ms"] > 0 and t["range_ms"] > 0
+    # the rebuild cut-over: batches of this relative size rebuild iff that was faster
+    assert rep["rebuild_ms"] > 0 and rep["batch_path_ms"] > 0
+    r = 100_000 / 1_500_000
+    assert cfg.rebuild_frac == rep["best_rebuild_frac"]
+    if rep["rebuild_ms"] < rep["batch_path_ms"]:
+        assert cfg.rebuild_frac <= r * (1 + 1e-9)
+    else:
+        assert cfg.rebuild_frac >= 2 * r * (1 - 1e-9)
     # the tuned configuration gives a valid set with oracle-exact results
     expect = orc.build_set(keys)
     c = cp.CPMA(keys, config=cfg)
