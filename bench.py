@@ -312,6 +312,59 @@ def rebuild_section(cp, torch, base_dev, seed, fracs=(0.1, 1.0)):
     return out
 
 
+def graph_kernels(g, torch, nv):
+    """The vertex offset array, connected components and single-source
+    betweenness from vertex 0 (outputs in HBM), each timed once after a warm-up."""
+    out = {}
+    for name, fn in (("offsets_ms", lambda: g.offsets(nv, device=True)),
+                     ("cc_ms", lambda: g.cc(nv, device=True)),
+                     ("bc_ms", lambda: g.bc(nv, 0, device=True))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0) * 1e3
+        if name == "cc_ms":
+            lab = r
+            out["components"] = int((lab == torch.arange(nv, device=lab.device, dtype=lab.dtype)).sum().item())
+    return out
+
+
+def er_section(cp, torch, seed, n=10 ** 7, p=5e-6):
+    """The paper's synthetic graph: Erdos-Renyi with n = 1e7 vertices and edge
+    probability 5e-6 (n^2 p ordered pairs drawn uniformly, self-loops dropped,
+    symmetrised), stored as one CPMA; BFS, 10 PageRank iterations, CC, BC."""
+    m = int(n * n * p)
+    s, d = synth.er_edges_torch(m, seed, n, device="cuda")
+    keys = synth.edge_keys_torch(s, d)
+    del s, d
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = cp.CPMA(keys)
+    torch.cuda.synchronize()
+    out = {"vertices": n, "edge_prob": p, "edges": g.size(), "build_s": time.perf_counter() - t0,
+           "bytes_per_edge": g.bytes() / g.size(), "gbytes": g.bytes() / 1e9}
+    del keys
+    torch.cuda.empty_cache()
+    g.bfs(n, 0, symmetric=True, device=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.bfs(n, 0, symmetric=True, device=True)
+    torch.cuda.synchronize()
+    out["bfs_ms"] = (time.perf_counter() - t0) * 1e3
+    g.pagerank(n, iters=1, device=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.pagerank(n, iters=10, device=True)
+    torch.cuda.synchronize()
+    out["pagerank_10_iters_ms"] = (time.perf_counter() - t0) * 1e3
+    out.update(graph_kernels(g, torch, n))
+    log(f"er graph: {out}")
+    g.close()
+    return out
+
+
 def fgraph_section(cp, torch, scale, seed):
     """F-Graph: symmetric R-MAT graph with 2^scale vertices from 2^(scale+3) samples."""
     nv = 1 << scale
@@ -343,6 +396,7 @@ def fgraph_section(cp, torch, scale, seed):
     g.pagerank(nv, iters=10, device=True)
     torch.cuda.synchronize()
     out["pagerank_10_iters_ms"] = (time.perf_counter() - t0) * 1e3
+    out.update(graph_kernels(g, torch, nv))
     ins = {}
     for k in (10 ** 5, 10 ** 6, 10 ** 7):
         s2, d2 = synth.rmat_edges_torch(k // 2, seed + k, scale=scale, device="cuda")
@@ -579,14 +633,23 @@ def serving_section(cp, torch, c, base, nreq, seed):
         steps = srv.stop()
         t1 = max(r.req.t_done_ns for r in reqs)
         lat = np.array([(r.req.t_done_ns - r.t_submit_ns) * 1e-6 for r in reqs])
+        wait = np.array([(r.req.t_admit_ns - r.t_submit_ns) * 1e-6 for r in reqs])
+        ends = {}
+        for r in reqs:
+            ends[r.req.step] = max(ends.get(r.req.step, 0), r.req.t_done_ns)
+        early = sum(1 for r in reqs if r.req.step > 0 and r.req.t_admit_ns < ends[r.req.step - 1])
         return {"ops_s": len(reqs) / ((t1 - t0) * 1e-9), "steps": steps,
-                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "admit_wait_p50_ms": float(np.percentile(wait, 50)),
+                "admitted_while_previous_step_ran": early}
 
     out = {"n0": c.size(), "requests": nreq, "mix": "70% range (Zipf(1.2) 1..1e5), 25% insert, 5% delete "
            "(log-uniform 10..1e6 keys)"}
     sat = run(requests(nreq, seed + 100), 4096)
+    sat256 = run(requests(nreq, seed + 150), 256)
     fifo = run(requests(nreq // 4, seed + 200), 1)
     out["saturation_batched"] = sat
+    out["saturation_batched_256_slots"] = sat256
     out["saturation_one_request_per_step"] = fifo
     for frac in (0.5, 0.8):
         out[f"poisson_{frac}"] = run(requests(nreq // 2, seed + int(300 + 100 * frac)), 4096,
@@ -683,7 +746,8 @@ def main():
     k = int(args.batch)
     seed = synth.SEED_BASE + 2
     if args.fg_only:
-        print(json.dumps(fgraph_section(cp, torch, args.fg_scale, seed + 60)), flush=True)
+        print(json.dumps({"rmat": fgraph_section(cp, torch, args.fg_scale, seed + 60),
+                          "er": er_section(cp, torch, seed + 65)}), flush=True)
         return
     if args.gate_only:
         big_d = synth.uniform_keys_torch(int(args.serve_n), seed + 70, "cuda")
@@ -868,6 +932,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.only_steps and args.fg_scale > 0:
         result_extra["fgraph"] = fgraph_section(cp, torch, args.fg_scale, seed + 60)
+        torch.cuda.empty_cache()
+        result_extra["er_graph"] = er_section(cp, torch, seed + 65)
         torch.cuda.empty_cache()
     if not args.only_steps and args.serve_n > 0:
         # one resident set of serve_n keys: the cold range gate, then the serving loop

@@ -303,3 +303,42 @@ def test_serving_at_1e9_keys_properties(cp):
     keys, state = keys[srt], state[srt]
     last = np.r_[keys[1:] != keys[:-1], True]
     assert np.array_equal(c.contains(keys[last]), state[last])
+
+
+def test_requests_admitted_while_a_step_runs(cp, orc):
+    """Continuous batching: requests that arrive while a step is on the GPU are
+    admitted (and their data uploaded) before that step ends, then served in
+    the next step; results still equal the replays."""
+    import time
+    base = orc.build_set(synth.uniform_keys(400000, 9301, bits=40))
+    a = cp.CPMA(base, leaf_bytes=256)
+    b = cp.CPMA(base, leaf_bytes=256)
+    reqs = []
+    kinds = synth.uniform_float(240, 9302)
+    for i in range(240):
+        if kinds[i] < 0.6:
+            lo = synth.uniform_keys(8, 9303, offset=8 * i)
+            reqs.append(cp.ServedRequest(cp.REQ_RANGE, lo, lo + np.uint64(1 << 28)))
+        elif kinds[i] < 0.9:
+            reqs.append(cp.ServedRequest(cp.REQ_INSERT, synth.uniform_keys(30000, 9304, offset=30000 * i)))
+        else:
+            idx = synth.sample_indices(len(base), 5000, 9305 + i)
+            reqs.append(cp.ServedRequest(cp.REQ_DELETE, base[idx]))
+    srv = cp.Server(a)
+    for r in reqs:
+        srv.submit(r)
+        t_end = time.perf_counter() + 200e-6   # a request every 200 us
+        while time.perf_counter() < t_end:
+            pass
+    steps = srv.stop()
+    assert all(r.done and r.req.status == 0 for r in reqs)
+    assert steps > 2
+    ends = {}
+    for r in reqs:
+        ends[r.req.step] = max(ends.get(r.req.step, 0), r.req.t_done_ns)
+    early = sum(1 for r in reqs if r.req.step > 0 and r.req.t_admit_ns < ends[r.req.step - 1])
+    assert early > 0, "no request was admitted while the step before it ran"
+    assert all(r.req.t_admit_ns >= r.t_submit_ns and r.req.t_done_ns >= r.req.t_admit_ns for r in reqs)
+    S = replay_and_check(cp, orc, reqs, base, b)
+    code, msg = orc.check_image(*a.export(), a.geometry()[1], S)
+    assert code == 0, msg
