@@ -123,7 +123,7 @@ def pmc_summary(fetch_csv, write_csv, steps, cmd_fetch, cmd_write, key):
     total = out["read"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
     lines = [
         f"# {MERGE_KERNEL}: HBM traffic per launch, insert + delete batch pairs of 1e7 on 1e8 keys", "",
-        "Two counter runs of the headline steps (each from the repository root, after "
+        "Two counter runs of the headline steps (each run in /tmp after "
         "`cd /tmp && export TMPDIR=/tmp`):", "", "```", cmd_fetch, cmd_write, "```", "",
         "The first dispatch of each run is a 1 GiB device-to-device copy "
         "(`--calibrate-copy`); the counter's reading for it gives the scale factor "
@@ -154,7 +154,7 @@ def valu_summary(csv_path, kernel, pick, title, what, cmd, key):
         nl = len(timed)
     lines = [
         f"# {kernel}: instructions per launch, {title}", "",
-        f"One counter run of {what} (from the repository root, after "
+        f"One counter run of {what} (run in /tmp after "
         "`cd /tmp && export TMPDIR=/tmp`):", "", "```", cmd, "```", "",
         "Counts are chip totals per dispatch (SQ_WAVES equals the launched waves).  A wave64 VALU "
         "instruction occupies its SIMD for 4 cycles, so the VALU issue peak is 256 CUs x 4 SIMDs x "
@@ -182,6 +182,84 @@ def merge_traffic(key):
     """HBM bytes per merge launch from the committed counter summary, or None."""
     kv = read_summary(TRAFFIC_FILE, key)
     return float(kv["traffic_bytes_per_launch"]) if kv else None
+
+
+PROF_DIR = "/tmp/cpma_prof"
+STEPS_TRACE_FILE = os.path.join(ROOT, "profiles", "update_pairs1e7_n1e8_kernel_trace.md")
+GATE_TRACE_FILE = os.path.join(ROOT, "profiles", "range_gate_n1e9_kernel_trace.md")
+
+
+def trace_rows(path):
+    """(dispatch id, kernel name, duration ns) of every row of a rocprofv3
+    kernel_trace.csv, in dispatch order."""
+    import csv
+    rows = []
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("cpma_dev::", "")
+            rows.append((int(r["Dispatch_Id"]), name, int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    rows.sort()
+    return rows
+
+
+def trace_table(rows):
+    per = {}
+    for _, name, ns in rows:
+        c, t = per.get(name, (0, 0))
+        per[name] = (c + 1, t + ns)
+    total = sum(t for _, t in per.values())
+    lines = ["| kernel | calls | total ms | avg us | share |", "|---|---|---|---|---|"]
+    for name, (c, t) in sorted(per.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"| `{name}` | {c} | {t * 1e-6:.3f} | {t * 1e-3 / c:.1f} | {100.0 * t / total:.1f}% |")
+    return lines, total
+
+
+def trace_summary(kind, csv_path, args):
+    """Markdown summary of a rocprofv3 --kernel-trace run.  steps: the kernels of
+    the timed headline steps (every update batch opens with one launch of
+    k_validate_hist; the timed batches are the 2K before the last PHASE_STEPS
+    steps' 2 * PHASE_STEPS); gate: every launch from the first range_map kernel
+    on (one warm-up and three timed passes of the cold range gate)."""
+    rows = trace_rows(csv_path)
+    shape = f"--steps {args.steps} --warmup {args.warmup}"
+    if kind == "steps":
+        cmd = ("rocprofv3 --kernel-trace --stats --output-format csv -d " + PROF_DIR + "/tr_steps -o run -- "
+               f"python3 /root/repo/bench.py --only-steps --no-cpu-baseline {shape}")
+        starts = [i for i, r in enumerate(rows) if r[1] == "k_validate_hist"]
+        nb = MERGES_PER_STEP * args.steps
+        first, last = starts[-(nb + TAIL_MERGES)], starts[-TAIL_MERGES]
+        # each batch's validation follows one k_fill that clears its flags
+        if rows[first - 1][1].startswith("k_fill"):
+            first -= 1
+        if rows[last - 1][1].startswith("k_fill"):
+            last -= 1
+        sel = rows[first:last]
+        title = "insert + delete batch pairs of 1e7 uniform 40-bit keys on a 1e8-key CPMA"
+        what = (f"The run builds the 1e8-key set, takes {args.warmup} warm-up and {args.steps} timed steps "
+                f"(each an insert batch of 1e7 fresh keys and a delete batch of 1e7 present keys), then "
+                f"{PHASE_STEPS} more steps with every phase timed.  The table covers the {nb} batches of the "
+                "timed steps: from the first launch of the first timed batch to the last launch before the "
+                "first of the phase-timed batches.")
+        out = STEPS_TRACE_FILE
+    else:
+        cmd = ("rocprofv3 --kernel-trace --stats --output-format csv -d " + PROF_DIR + "/tr_gate -o run -- "
+               "python3 /root/repo/bench.py --gate-only")
+        first = next(i for i, r in enumerate(rows) if r[1].startswith("k_rm_"))
+        sel = rows[first:]
+        title = "range_map on cold data, 1e9 keys"
+        what = ("The run builds a set of 1e9 uniform 40-bit keys and runs the cold range gate: 1e3 queries "
+                "of about 1e6 keys at random starts plus one query over the whole key space, one warm-up "
+                "pass and three timed passes.  The table covers every launch from the first range_map "
+                "kernel on.")
+        out = GATE_TRACE_FILE
+    table, total = trace_table(sel)
+    lines = [f"# Kernel trace: {title}", "", "Command (run in /tmp after "
+             "`cd /tmp && export TMPDIR=/tmp`):", "", "```", cmd, "```", "", what, "",
+             f"Launches: {len(sel)}; kernel time: {total * 1e-6:.3f} ms.", ""] + table + [""]
+    text = "\n".join(lines)
+    with open(out, "w") as fh:
+        fh.write(text)
+    print(text)
 
 
 def host_info():
@@ -688,13 +766,19 @@ def main():
                     help="write the merge kernel's instruction summary from one rocprofv3 --pmc run and exit")
     ap.add_argument("--scan-valu-summary", metavar="CSV",
                     help="write the range scan kernel's instruction summary from a --pmc run of --gate-only")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("KIND", "CSV"),
+                    help="KIND steps or gate: write the kernel time summary of a rocprofv3 --kernel-trace "
+                         "run of the headline steps or of --gate-only, and exit")
     args = ap.parse_args()
 
     shape = f"--steps {args.steps} --warmup {args.warmup}"
+    if args.trace_summary:
+        trace_summary(args.trace_summary[0], args.trace_summary[1], args)
+        return
     if args.valu_summary or args.scan_valu_summary:
         ctr = "rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES SQ_INSTS_LDS SQ_INSTS_SALU --output-format csv "
         if args.valu_summary:
-            cmd = (ctr + "-d /tmp/cpma_prof/pmc_valu -o run -- python3 /root/repo/bench.py --only-steps "
+            cmd = (ctr + "-d " + PROF_DIR + "/pmc_valu -o run -- python3 /root/repo/bench.py --only-steps "
                    f"--no-cpu-baseline {shape}")
             m = MERGES_PER_STEP * args.steps
             text = valu_summary(args.valu_summary, MERGE_KERNEL, lambda v: v[-(m + TAIL_MERGES):-TAIL_MERGES],
@@ -703,7 +787,7 @@ def main():
                                 run_key(args))
             path = VALU_FILE
         else:
-            cmd = ctr + "-d /tmp/cpma_prof/pmc_scan -o run -- python3 /root/repo/bench.py --gate-only"
+            cmd = ctr + "-d " + PROF_DIR + "/pmc_scan -o run -- python3 /root/repo/bench.py --gate-only"
             text = valu_summary(args.scan_valu_summary, SCAN_KERNEL, lambda v: v[-3:],
                                 "the cold range gate on 1e9 keys", "the cold range gate (its last three "
                                 "timed passes)", cmd, run_key(args, "gate"))
@@ -713,7 +797,7 @@ def main():
         print(text)
         return
     if args.pmc_summary:
-        base = "rocprofv3 --pmc {c} --output-format csv -d /tmp/cpma_prof/pmc_{t} -o run -- " \
+        base = "rocprofv3 --pmc {c} --output-format csv -d " + PROF_DIR + "/pmc_{t} -o run -- " \
                f"python3 /root/repo/bench.py --only-steps --no-cpu-baseline --calibrate-copy {shape}"
         text = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.steps,
                            base.format(c="FETCH_SIZE", t="fetch"), base.format(c="WRITE_SIZE", t="write"),
