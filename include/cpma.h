@@ -271,6 +271,18 @@ uint64_t cpma_bytes(const cpma* set);
  */
 uint64_t cpma_bytes_held(const cpma* set);
 
+/*
+ * Releases every device buffer counted by cpma_bytes_held beyond the structure
+ * itself: the spare leaf arrays and the scratch kept from earlier calls (a set
+ * that took one large batch otherwise keeps that batch's scratch), and moves
+ * the leaf arrays into allocations that fit them.  The set is unchanged; later
+ * calls allocate again what they need, and an update still takes all of it
+ * before its first write.  Synchronises `stream`.
+ * Errors: CPMA_ERR_INVALID for a NULL handle; CPMA_ERR_DEVICE for a broken one
+ * or a failed synchronisation (nothing released).
+ */
+cpma_status cpma_trim(cpma* set, void* stream);
+
 /* Number of leaves and leaf size in bytes of the current layout. */
 cpma_status cpma_geometry(const cpma* set, uint64_t* num_leaves, uint32_t* leaf_bytes);
 

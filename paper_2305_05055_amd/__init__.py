@@ -102,6 +102,7 @@ def lib():
         L.cpma_bytes.restype = u64
         L.cpma_bytes_held.argtypes = [vp]
         L.cpma_bytes_held.restype = u64
+        L.cpma_trim.argtypes = [vp, vp]
         L.cpma_geometry.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_uint32)]
         L.cpma_export.argtypes = [vp, vp, vp, vp, vp]
         L.cpma_destroy.argtypes = [vp]
@@ -322,6 +323,10 @@ class CPMA:
     def bytes_held(self):
         """All device bytes the handle holds (structure, spare arrays, scratch)."""
         return int(lib().cpma_bytes_held(self._h))
+
+    def trim(self, stream=None):
+        """Releases the spare arrays and every scratch buffer kept from earlier calls."""
+        _check(lib().cpma_trim(self._h, _stream(stream, True)), "cpma_trim")
 
     def geometry(self):
         L = ctypes.c_uint64(0)

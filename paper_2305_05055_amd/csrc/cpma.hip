@@ -78,7 +78,7 @@ void dev_free(const cpma_config* al, void* p) {
 }
 
 // Grows b to at least `bytes` (contents are not kept), with `slack` extra room.
-void ensure(DevBuf& b, size_t bytes, double slack = 1.0) {
+void ensure(DevBuf& b, size_t bytes, double slack = 0.5) {
   if (bytes == 0) bytes = 16;
   if (b.cap >= bytes) return;
   if (b.p) {
@@ -2062,6 +2062,48 @@ uint64_t cpma_bytes_held(const cpma* cs) {
   uint64_t total = 0;
   for (DevBuf* b : s->bufs()) total += b->cap;
   return total;
+}
+
+cpma_status cpma_trim(cpma* s, void* stream) {
+  if (!s) return CPMA_ERR_INVALID;
+  if (s->broken) return CPMA_ERR_DEVICE;
+  if (hipSetDevice(s->device) != hipSuccess || hipStreamSynchronize((hipStream_t)stream) != hipSuccess) {
+    hipGetLastError();
+    return CPMA_ERR_DEVICE;
+  }
+  // the structure and the small counters the handle's pointers refer to stay
+  const DevBuf* keep[] = {&s->bytes, &s->used, &s->head, &s->ctr_buf, &s->info_buf, &s->qalg_buf};
+  for (DevBuf* b : s->bufs()) {
+    if (std::find(std::begin(keep), std::end(keep), b) != std::end(keep)) continue;
+    release(*b);
+  }
+  // the leaf arrays keep the room of the growth that made them: copy each to
+  // a fitting allocation (an array stays as it is if that allocation fails)
+  const size_t fit[3] = {(size_t)(s->L * (uint64_t)s->S), (size_t)(s->L * 4), (size_t)(s->L * 8)};
+  DevBuf* arr[3] = {&s->bytes, &s->used, &s->head};
+  for (int i = 0; i < 3; i++) {
+    const size_t want = fit[i] + 256;
+    if (arr[i]->cap <= want) continue;
+    void* p = nullptr;
+    try {
+      p = dev_alloc(arr[i]->al, want);
+    } catch (const Fail&) {
+      p = nullptr;
+    }
+    if (!p) continue;
+    if (hipMemcpyAsync(p, arr[i]->p, fit[i], hipMemcpyDeviceToDevice, (hipStream_t)stream) != hipSuccess ||
+        hipStreamSynchronize((hipStream_t)stream) != hipSuccess) {
+      hipGetLastError();
+      dev_free(arr[i]->al, p);
+      return CPMA_ERR_DEVICE;
+    }
+    dev_free(arr[i]->al, arr[i]->p);
+    arr[i]->p = p;
+    arr[i]->cap = want;
+  }
+  s->pyr_valid = false;
+  s->wol_L = 0;
+  return CPMA_OK;
 }
 
 cpma_status cpma_geometry(const cpma* s, uint64_t* num_leaves, uint32_t* leaf_bytes) {

@@ -56,6 +56,7 @@ def test_host_only_calls_without_gpu():
     assert L.cpma_build(None, 0, 0, ctypes.byref(bad), None, ctypes.byref(h)) == 1
     assert L.cpma_insert_batch(None, None, 1, 0, 0, None, None) == 1
     assert L.cpma_range_map_noalloc(None, None, None, 1, None, None, None) == 1
+    assert L.cpma_trim(None, None) == 1
     assert L.cpma_stats_enable(None, 1) == 1
     assert L.cpma_stats_select(None, 1 << 2) == 1
     L.cpma_destroy(None)

@@ -156,3 +156,35 @@ def test_bytes_held_counts_spares_and_scratch(cp, orc):
     c.insert_batch(synth.uniform_keys(50000, 9142, bits=40))
     assert c.bytes_held() > c.bytes()
     c.close()
+
+
+def test_trim_releases_scratch_and_later_calls_still_agree(cp, orc):
+    """After a large batch the handle keeps that batch's scratch; trim releases
+    everything but the structure and a few counters, and later updates and
+    queries (which allocate again) still match the oracle."""
+    base = synth.uniform_keys(200000, 9151, bits=40)
+    ins = synth.uniform_keys(150000, 9152, bits=40)
+    c = cp.CPMA(base)
+    c.insert_batch(ins)
+    held = c.bytes_held()
+    assert held > 2 * c.bytes()
+    c.trim()
+    assert c.bytes_held() <= c.bytes() + 4096
+    assert c.bytes_held() < held
+    ref = orc.insert(orc.build_set(base), ins)[0]
+    dels = ins[::3]
+    assert c.delete_batch(dels) == len(np.unique(dels))
+    ref = orc.delete(ref, dels)[0]
+    more = synth.uniform_keys(30000, 9153, bits=40)
+    c.insert_batch(more)
+    ref = orc.insert(ref, more)[0]
+    c.trim()
+    b, u, h = c.export()
+    code, msg = orc.check_image(b, u, h, c.geometry()[1], ref)
+    assert code == 0, msg
+    lo = np.array([0, ref[100]], np.uint64)
+    hi = np.array([np.uint64(1) << np.uint64(40), ref[5000]], np.uint64)
+    s, n = c.range_map(lo, hi)
+    es, en = orc.range_map(ref, lo, hi)
+    assert np.array_equal(s, es) and np.array_equal(n, en)
+    c.close()
