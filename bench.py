@@ -355,6 +355,65 @@ def growth_section(cp, torch, base_dev, seed, factors=(1.1, 1.2, 1.5, 2.0), batc
     return out
 
 
+def pma_section(cp, torch, base_dev, seed, k=10 ** 7, warm=2, steps=5, q=100_000):
+    """The paper's compression ablation: the same 1e8 uniform 40-bit keys as the
+    CPMA and as the uncompressed PMA (raw 8-byte keys per leaf, same leaves,
+    bounds and batch algorithm).  For each: bytes per key, insert + delete
+    steps of 1e7-key batches (as the headline), batched range_map of q Zipf(1.2)
+    exact-count queries on 1..1e6 keys, and one scan of the whole set."""
+    keys_sorted = torch.unique(base_dev).cpu().numpy().view(np.uint64)
+    lens = synth.zipf_lengths(q, seed, alpha=1.2, lmax=10 ** 6)
+    lo, hi = synth.range_queries_by_count(keys_sorted, lens, seed + 1)
+    first_del = to_dev(keys_sorted[synth.sample_indices(len(keys_sorted), k, seed + 2)])
+    del keys_sorted
+    dlo, dhi = to_dev(lo), to_dev(hi)
+    ins = [to_dev(synth.uniform_keys(k, seed + 3, offset=(i + 50) * k)) for i in range(warm + steps)]
+    full_lo = to_dev(np.array([0], np.uint64))
+    full_hi = to_dev(np.array([(1 << 64) - 1], np.uint64))
+    out = {"n0": int(base_dev.numel()), "batch": k, "steps": steps, "queries": q,
+           "paper_context": "paper, 64 cores: the CPMA beats the PMA on batch inserts from 16 cores up "
+                            "(memory bandwidth) and on the largest range queries (1.3x); the PMA wins small "
+                            "ranges (no decoding)"}
+    for name, unc in (("cpma", False), ("pma", True)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c = cp.CPMA(base_dev, uncompressed=unc)
+        torch.cuda.synchronize()
+        r = {"build_s": time.perf_counter() - t0, "bytes_per_key": c.bytes() / c.size(),
+             "leaves": c.geometry()[0]}
+        for i in range(warm):
+            c.insert_batch(ins[i])
+            c.delete_batch(first_del if i == 0 else ins[i - 1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(warm, warm + steps):
+            c.insert_batch(ins[i])
+            c.delete_batch(ins[i - 1])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        r["update_keys_s"] = 2 * k * steps / dt
+        r["ms_per_step"] = dt / steps * 1e3
+        tr = time_range(torch, c, dlo, dhi)
+        r["range_keys_s"] = tr["keys_per_s"]
+        r["range_scan_alg_GBps"] = tr["scan_alg_GBps"]
+        c.range_map(full_lo, full_hi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            c.range_map(full_lo, full_hi)
+        torch.cuda.synchronize()
+        r["full_scan_ms"] = (time.perf_counter() - t0) / 5 * 1e3
+        r["full_scan_keys_s"] = c.size() / (r["full_scan_ms"] * 1e-3)
+        r["bytes_after"] = c.bytes()
+        out[name] = r
+        c.close()
+        torch.cuda.empty_cache()
+    out["pma_over_cpma"] = {key: out["pma"][key] / out["cpma"][key]
+                            for key in ("bytes_per_key", "update_keys_s", "range_keys_s", "full_scan_keys_s")}
+    log(f"pma vs cpma: {out}")
+    return out
+
+
 def rebuild_section(cp, torch, base_dev, seed, fracs=(0.1, 1.0)):
     """Both branches of a large insert batch on the 1e8-key set, at k = n / 10
     and k = n: the full rebuild (every leaf merged, then everything spread at
@@ -758,6 +817,8 @@ def main():
     ap.add_argument("--fg-only", action="store_true", help="run only the F-Graph section (diagnostics)")
     ap.add_argument("--gate-only", action="store_true", help="run only the cold range gate (diagnostics)")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving loop (diagnostics)")
+    ap.add_argument("--pma-only", action="store_true",
+                    help="run only the comparison with the uncompressed PMA (diagnostics)")
     ap.add_argument("--range-only", action="store_true", help="run only the batched range_map section (diagnostics)")
     ap.add_argument("--sweep-only", action="store_true", help="run only the batch-size sweep (diagnostics)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -848,6 +909,10 @@ def main():
         del big_d
         torch.cuda.empty_cache()
         print(json.dumps(serving_section(cp, torch, big, big_host, args.serve_requests, seed + 90)), flush=True)
+        return
+
+    if args.pma_only:
+        print(json.dumps(pma_section(cp, torch, synth.uniform_keys_torch(n0, seed, "cuda"), seed + 48)), flush=True)
         return
 
     # ---- base set: exactly n0 distinct uniform 40-bit keys -----------------------
@@ -1009,6 +1074,7 @@ def main():
         bd = to_dev(base_all)
         result_extra["rebuild"] = rebuild_section(cp, torch, bd, seed + 46)
         result_extra["growth"] = growth_section(cp, torch, bd, seed + 47)
+        result_extra["pma_vs_cpma"] = pma_section(cp, torch, bd, seed + 48)
         del bd
         torch.cuda.empty_cache()
     if not args.only_steps:

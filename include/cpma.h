@@ -102,6 +102,18 @@ typedef enum { CPMA_MEM_HOST = 0, CPMA_MEM_DEVICE = 1 } cpma_mem;
  *                  k = n / 10, where every leaf already takes part in the
  *                  merge (cpma_autotune measures the cut-over for a set).
  *                  Results do not depend on it.
+ *   uncompressed   0 (default): the CPMA, delta-coded leaves.  1: the plain
+ *                  PMA the paper measures compression against (Section
+ *                  "Packed Memory Array"; Section "Evaluation on
+ *                  microbenchmarks" compares the two): the same leaves, tree,
+ *                  byte-density bounds and batch algorithm, but a leaf holds
+ *                  its keys as raw little-endian 8-byte words packed to the
+ *                  left (used = 8 x keys, zero bytes after them); a resize
+ *                  restages every key.  cpma_build, the batch updates,
+ *                  range_map (both forms), contains, export, sizes and trim
+ *                  support it; cpma_apply_updates (and so the updates of a
+ *                  server), the F-Graph calls and cpma_autotune return
+ *                  CPMA_ERR_INVALID for it.
  *   alloc, free, ctx
  *                  device memory for everything the handle owns (leaves, heads,
  *                  used counts, counters, scratch): alloc(bytes, ctx) returns a
@@ -124,6 +136,7 @@ typedef struct {
   void (*free)(void* ptr, void* ctx);
   void* ctx;
   double rebuild_frac;
+  int32_t uncompressed;
 } cpma_config;
 
 /* Fills *cfg with the defaults above.  Returns CPMA_ERR_INVALID if cfg is NULL. */

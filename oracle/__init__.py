@@ -72,6 +72,8 @@ def lib():
         L.orc_check_image.argtypes = [u8p, u32p, u64p, c_u64, ctypes.c_uint32, dp, u64p,
                                       c_u64, ctypes.c_char_p, ctypes.c_int]
         L.orc_check_image.restype = ctypes.c_int
+        L.orc_check_image_pma.argtypes = L.orc_check_image.argtypes
+        L.orc_check_image_pma.restype = ctypes.c_int
         L.orc_decode_image.argtypes = [u8p, u32p, c_u64, ctypes.c_uint32, u64p, c_u64]
         L.orc_decode_image.restype = ctypes.c_int64
         L.orc_bfs.argtypes = [u64p, c_u64, ctypes.c_uint32, ctypes.c_uint32, u32p]
@@ -174,6 +176,22 @@ def check_image(bytes_, used, head, S, expect, params=DEFAULT_PARAMS):
     code = lib().orc_check_image(_p(b, ctypes.c_uint8), _p(u, ctypes.c_uint32),
                                  _p(h, ctypes.c_uint64), L, S, pa, _p(e, ctypes.c_uint64),
                                  len(e), msg, 256)
+    return int(code), msg.value.decode()
+
+
+def check_image_pma(bytes_, used, head, S, expect, params=DEFAULT_PARAMS):
+    """check_image for the uncompressed variant (raw 8-byte keys per leaf)."""
+    b = np.ascontiguousarray(bytes_, dtype=np.uint8)
+    u = np.ascontiguousarray(used, dtype=np.uint32)
+    h = _u64(head)
+    e = _u64(expect)
+    L = len(u)
+    assert len(b) == L * S and len(h) == L
+    pa = (ctypes.c_double * 4)(*params)
+    msg = ctypes.create_string_buffer(256)
+    code = lib().orc_check_image_pma(_p(b, ctypes.c_uint8), _p(u, ctypes.c_uint32),
+                                     _p(h, ctypes.c_uint64), L, S, pa, _p(e, ctypes.c_uint64),
+                                     len(e), msg, 256)
     return int(code), msg.value.decode()
 
 

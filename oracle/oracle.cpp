@@ -270,6 +270,70 @@ extern "C" int orc_check_image(const uint8_t* bytes, const uint32_t* used,
 }
 
 // ---------------------------------------------------------------------------
+// Checker of the uncompressed variant, the plain PMA (Section "Packed Memory
+// Array": elements in sorted order in leaves with empty space after them).
+// A leaf holds its elements as 8-byte little-endian words from its start, so
+// its filled bytes are 8 per element; the head array names each leaf's first
+// element; the density bounds are those of the CPMA, over filled bytes.
+// ---------------------------------------------------------------------------
+static int density_walk(const uint32_t* used, uint64_t L, uint32_t S, const double* params,
+                        char* msg, int msglen) {
+  int H = orc_tree_height(L);
+  for (int h = 0; h <= H; h++) {
+    uint64_t width = 1ull << h;
+    int64_t up = orc_bound_q(params, 0, h, H);
+    int64_t lo = orc_bound_q(params, 1, h, H);
+    for (uint64_t first = 0; first < L; first += width) {
+      uint64_t last = std::min(L, first + width);
+      uint64_t sum = 0;
+      for (uint64_t j = first; j < last; j++) sum += used[j];
+      __int128 cap = (__int128)(last - first) * S;
+      __int128 lhs = (__int128)sum * kQ;
+      if (lhs > (__int128)up * cap)
+        return fail(msg, msglen, 13, "upper density bound violated at (h, first)", (uint64_t)h, first);
+      bool root_single_leaf = (h == H && L == 1);
+      if (!root_single_leaf && lhs < (__int128)lo * cap)
+        return fail(msg, msglen, 14, "lower density bound violated at (h, first)", (uint64_t)h, first);
+    }
+  }
+  return 0;
+}
+
+extern "C" int orc_check_image_pma(const uint8_t* bytes, const uint32_t* used,
+                                   const uint64_t* head, uint64_t L, uint32_t S,
+                                   const double* params, const uint64_t* expect,
+                                   uint64_t n, char* msg, int msglen) {
+  if (L == 0) return fail(msg, msglen, 1, "no leaves", 0, 0);
+  Vec all;
+  for (uint64_t i = 0; i < L; i++) {
+    const uint8_t* leaf = bytes + i * (uint64_t)S;
+    uint32_t u = used[i];
+    if (u > S) return fail(msg, msglen, 2, "used exceeds leaf size", i, u);
+    if (u % 8 != 0) return fail(msg, msglen, 15, "used is not a whole number of elements", i, u);
+    if (u == 0) {
+      if (!(L == 1 && n == 0)) return fail(msg, msglen, 3, "empty leaf", i, L);
+      if (head[i] != UINT64_MAX) return fail(msg, msglen, 4, "empty leaf head", i, head[i]);
+    } else {
+      for (uint32_t p = 0; p < u; p += 8) all.push_back(load_le64(leaf + p));
+      if (head[i] != load_le64(leaf)) return fail(msg, msglen, 6, "head mismatch", i, head[i]);
+    }
+    for (uint32_t b = u; b < S; b++)
+      if (leaf[b] != 0) return fail(msg, msglen, 8, "nonzero byte past used", i, b);
+    if (i > 0 && head[i] <= head[i - 1])
+      return fail(msg, msglen, 9, "heads not increasing", i, head[i]);
+  }
+  for (size_t j = 1; j < all.size(); j++)
+    if (all[j] <= all[j - 1]) return fail(msg, msglen, 10, "keys not increasing", j, all[j]);
+  if (all.size() != n) return fail(msg, msglen, 11, "size mismatch", all.size(), n);
+  for (uint64_t j = 0; j < n; j++)
+    if (all[j] != expect[j]) return fail(msg, msglen, 12, "content mismatch", j, all[j]);
+  int code = density_walk(used, L, S, params, msg, msglen);
+  if (code) return code;
+  if (msg && msglen > 0) msg[0] = 0;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // F-Graph (Section "Evaluation on graph workloads"): an edge (u, v) is the key
 // u<<32 | v; the CSR is the canonical two-array form the paper contrasts with.
 // ---------------------------------------------------------------------------

@@ -80,6 +80,13 @@ int orc_check_image(const uint8_t* bytes, const uint32_t* used,
                     const uint64_t* head, uint64_t L, uint32_t S,
                     const double* params, const uint64_t* expect, uint64_t n,
                     char* msg, int msglen);
+/* The same checks for the uncompressed variant (the plain PMA): a leaf holds
+ * its keys as 8-byte little-endian words from its start (used = 8 x keys), zero
+ * bytes after them; code 15 flags a used count that is not a multiple of 8. */
+int orc_check_image_pma(const uint8_t* bytes, const uint32_t* used,
+                        const uint64_t* head, uint64_t L, uint32_t S,
+                        const double* params, const uint64_t* expect, uint64_t n,
+                        char* msg, int msglen);
 /* Decodes an image into keys (capacity cap); returns the key count or -1. */
 int64_t orc_decode_image(const uint8_t* bytes, const uint32_t* used, uint64_t L,
                          uint32_t S, uint64_t* out, uint64_t cap);

@@ -34,7 +34,7 @@ class Config(ctypes.Structure):
                 ("lo_leaf", ctypes.c_double), ("lo_root", ctypes.c_double),
                 ("build_density", ctypes.c_double), ("range_chunk", ctypes.c_uint32),
                 ("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p), ("ctx", ctypes.c_void_p),
-                ("rebuild_frac", ctypes.c_double)]
+                ("rebuild_frac", ctypes.c_double), ("uncompressed", ctypes.c_int32)]
 
 
 class TuneHint(ctypes.Structure):
@@ -189,7 +189,8 @@ class CPMA:
     """A device-resident compressed packed memory array of uint64 keys."""
 
     def __init__(self, keys=(), leaf_bytes=0, grow=0.0, bounds=None, build_density=0.0,
-                 stream=None, config=None, range_chunk=0):
+                 stream=None, config=None, range_chunk=0, uncompressed=False):
+        """uncompressed=True builds the plain PMA (raw 8-byte keys per leaf)."""
         if config is not None:
             cfg = Config.from_buffer_copy(config)
         else:
@@ -200,6 +201,7 @@ class CPMA:
                 cfg.up_leaf, cfg.up_root, cfg.lo_leaf, cfg.lo_root = bounds
             cfg.build_density = build_density
             cfg.range_chunk = range_chunk
+            cfg.uncompressed = 1 if uncompressed else 0
         p, n, mem, keep = _keys(keys)
         h = ctypes.c_void_p()
         _check(lib().cpma_build(p if n else None, n, mem, ctypes.byref(cfg),

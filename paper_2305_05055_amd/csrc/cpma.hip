@@ -26,6 +26,7 @@
 #include "tune.hpp"
 #include "small.hpp"
 #include "fuse.hpp"
+#include "pma.hpp"
 
 using namespace cpma_dev;
 
@@ -441,6 +442,7 @@ WinArgs upload_windows(cpma* s, const std::vector<uint64_t>& src_begin, const st
   wa.dst_n = d + 3 * (W + 1);
   wa.dst_flat = d + 4 * (W + 1);
   wa.level = reinterpret_cast<const uint32_t*>(d + 6 * (W + 1));
+  wa.raw = s->cfg.uncompressed ? 1u : 0u;
   return wa;
 }
 
@@ -494,7 +496,7 @@ void plan_spread(cpma* s, const WinArgs& wa, uint64_t nsrc, uint64_t K, uint64_t
   hipLaunchKernelGGL(k_win_elems, dim3(grid_for(W + 1, 256)), dim3(256), 0, st, wa,
                      (const uint64_t*)s->koff.as<uint64_t>(), s->welem.as<uint64_t>(), s->fail.as<uint32_t>());
   HIPCHK(hipGetLastError());
-  if (nsrc > 0)
+  if (nsrc > 0 && !s->cfg.uncompressed)
     hipLaunchKernelGGL(k_head_costs, dim3(grid_for(nsrc, 256, 1u << 16)), dim3(256), 0, st, wa, nsrc,
                        (const uint64_t*)s->koff.as<uint64_t>(), (const uint64_t*)s->welem.as<uint64_t>(),
                        (const uint64_t*)s->stage.as<uint64_t>(), s->ccost.as<uint8_t>());
@@ -624,8 +626,12 @@ void spread_fresh(cpma* s, uint64_t K, uint64_t Lt, hipStream_t st, bool costs_r
                      K, 0u);
   if (!costs_ready) {
     ensure(s->ccost, K);
-    hipLaunchKernelGGL(k_chain_costs, dim3(grid_for(K, 256, 1u << 16)), dim3(256), 0, st,
-                       (const uint64_t*)s->stage.as<uint64_t>(), K, s->ccost.as<uint8_t>());
+    if (s->cfg.uncompressed)
+      hipLaunchKernelGGL((k_fill<uint8_t>), dim3(grid_for(K, 256, 4096)), dim3(256), 0, st, s->ccost.as<uint8_t>(), K,
+                         (uint8_t)8);
+    else
+      hipLaunchKernelGGL(k_chain_costs, dim3(grid_for(K, 256, 1u << 16)), dim3(256), 0, st,
+                         (const uint64_t*)s->stage.as<uint64_t>(), K, s->ccost.as<uint8_t>());
     HIPCHK(hipGetLastError());
   }
   // One window over all staged keys: its source is one flat entry, so the
@@ -674,7 +680,24 @@ void spread_fresh(cpma* s, uint64_t K, uint64_t Lt, hipStream_t st, bool costs_r
 // images into the spare arrays.  Returns the algorithmic bytes moved.
 // total_used: sum of the old used bytes (bounds the chain total from above).
 // Returns false, with nothing changed, when thresholds would overflow 64 bits.
+// Uncompressed leaves: a resize stages every key (one window over all leaves)
+// and spreads them over a fresh array of about Lt leaves, which steps by the
+// growing factor until every node is within its bounds.  Returns the
+// algorithmic bytes moved through *moved.
+bool raw_resize(cpma* s, uint64_t Lt, hipStream_t st, uint64_t* moved) {
+  uint64_t nsrc = 0, ndst = 0;
+  std::vector<uint64_t> sb{0}, sn{s->L};
+  std::vector<uint32_t> lv{(uint32_t)tree_height(s->L)};
+  WinArgs wa = upload_windows(s, sb, sn, sb, sn, lv, st, nsrc, ndst);
+  const uint64_t K = pack_windows(s, wa, nsrc, st);
+  const uint64_t L0 = s->L;
+  spread_fresh(s, K, std::max<uint64_t>(Lt, 1), st, true);
+  *moved = 16ull * K + 12ull * (L0 + s->L);
+  return true;
+}
+
 bool split_resize(cpma* s, uint64_t Lt, uint64_t total_used, hipStream_t st, uint64_t* moved) {
+  if (s->cfg.uncompressed) return raw_resize(s, Lt, st, moved);
   const uint64_t L = s->L;
   // a head's chain cost can exceed its 8 bytes by 2 (64-bit distances)
   auto fits = [&](uint64_t lt) { return (__int128)(total_used + 2 * L + 16) * (lt + 1) < ((__int128)1 << 62); };
@@ -843,6 +866,21 @@ void reserve_after_merge(cpma* s, uint64_t k, bool insert) {
   reserve_pyramid(s, Lmax);
   ensure(s->win, Lmax * sizeof(uint64_t));
   ensure(s->scan_tmp, scan_scratch_elems(Lmax + 1) * sizeof(uint64_t));
+  if (s->cfg.uncompressed) {
+    // an uncompressed resize stages every key and spreads it afresh
+    const uint64_t K = std::max<uint64_t>(1, s->n + (insert ? k : 0));
+    ensure(s->cnt, std::max<uint64_t>(L, 1) * sizeof(uint64_t));
+    ensure(s->koff, (L + 1) * sizeof(uint64_t));
+    ensure(s->stage, K * sizeof(uint64_t));
+    ensure(s->win_id, K * sizeof(uint32_t));
+    ensure(s->ccost, K);
+    ensure(s->P, (K + 1) * sizeof(uint64_t));
+    ensure(s->ncost, K);
+    ensure(s->lstart, (Lmax + 1) * sizeof(uint64_t));
+    ensure(s->planU, (Lmax + 1) * sizeof(uint32_t));
+    ensure(s->welem, 2 * sizeof(uint64_t));
+    ensure(s->scan_tmp, scan_scratch_elems(std::max<uint64_t>(K, Lmax) + 1) * sizeof(uint64_t));
+  }
 }
 
 // Root out of bounds: move everything to an array grown (or shrunk) by the
@@ -1111,7 +1149,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
                        (const uint64_t*)s->head.as<uint64_t>(), L, B, s->dctr);
   }
   HIPCHK(hipGetLastError());
-  if (s->S <= kWaveMaxS && !small) {
+  if (s->S <= kWaveMaxS && !small && !s->cfg.uncompressed) {
     // route segments: narrow (32-bit wave merge), wide (64-bit), long insert slices
     // (spill list: heavy merge)
     const uint64_t nseg = std::min<uint64_t>(kbound, L);
@@ -1156,7 +1194,13 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   // wide, long and heavy slices.  From here on the structure is written.
   s->mutating = true;
   PhaseMark pmg = phase_begin(s, CPMA_PHASE_MERGE, st);
-  if (small && s->S <= kWaveMaxS) {
+  if (s->cfg.uncompressed) {
+    // uncompressed leaves: one wave per touched leaf, any slice length
+    a.part = slots(wgrid, true);
+    hipLaunchKernelGGL(k_pma_merge, dim3(wgrid), dim3(kWave), 0, st, a);
+    HIPCHK(hipGetLastError());
+    phase_end(s, pmg, st);
+  } else if (small && s->S <= kWaveMaxS) {
     // every segment in one 64-bit wave pass; long insert slices in the heavy merge
     a.part = slots(wgrid, false);
     hipLaunchKernelGGL(k_merge_wave<uint64_t>, dim3(wgrid), dim3(kWave), 0, st, a, 1);
@@ -1219,7 +1263,8 @@ uint64_t apply_small(cpma* s, const uint64_t* src, uint64_t k, bool insert, hipS
   hipLaunchKernelGGL(k_small_prep, dim3(1), dim3(kSmallThreads), 0, st, src, (uint32_t)k,
                      (const uint64_t*)s->head.as<uint64_t>(), s->L, (const uint32_t*)s->used.as<uint32_t>(),
                      s->kdedup.as<uint64_t>(), s->seg_leaf.as<uint32_t>(), s->seg_begin.as<uint32_t>(),
-                     s->seg_desc.as<uint4>(), insert ? 1 : 0, s->S <= kWaveMaxS ? kWaveSlice : 0xffffffffu,
+                     s->seg_desc.as<uint4>(), insert ? 1 : 0,
+                     (s->S <= kWaveMaxS && !s->cfg.uncompressed) ? kWaveSlice : 0xffffffffu,
                      s->spill.as<uint32_t>(), s->dctr);
   HIPCHK(hipGetLastError());
   phase_end(s, pm, st, 16ull * k);
@@ -1247,6 +1292,7 @@ cpma_status check_config(const cpma_config& c) {
   if (!(c.lo_root * c.grow < c.up_root)) return CPMA_ERR_INVALID;
   if (!(c.build_density > c.lo_root && c.build_density < c.up_root)) return CPMA_ERR_INVALID;
   if (!(c.rebuild_frac > 0)) return CPMA_ERR_INVALID;
+  if (c.uncompressed != 0 && c.uncompressed != 1) return CPMA_ERR_INVALID;
   return CPMA_OK;
 }
 
@@ -1288,6 +1334,7 @@ cpma_status cpma_config_default(cpma_config* cfg) {
   cfg->build_density = cfg->up_root / cfg->grow;
   cfg->range_chunk = 8;
   cfg->rebuild_frac = 1.0;
+  cfg->uncompressed = 0;
   cfg->alloc = nullptr;
   cfg->free = nullptr;
   cfg->ctx = nullptr;
@@ -1322,6 +1369,7 @@ cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpm
     cfg.build_density = cfg_in->build_density > 0 ? cfg_in->build_density : cfg.up_root / cfg.grow;
     if (cfg_in->range_chunk) cfg.range_chunk = cfg_in->range_chunk;
     if (cfg_in->rebuild_frac > 0) cfg.rebuild_frac = cfg_in->rebuild_frac;
+    cfg.uncompressed = cfg_in->uncompressed;
     cfg.alloc = cfg_in->alloc;
     cfg.free = cfg_in->free;
     cfg.ctx = cfg_in->ctx;
@@ -1360,10 +1408,15 @@ cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpm
     s->n = K;
     uint64_t Lt = 1;
     if (K > 0) {
-      // Total bytes of the keys as one delta chain: the head plus every delta code.
+      // Total bytes of the keys as one delta chain: the head plus every delta
+      // code (8 bytes per key for uncompressed leaves).
       ensure(s->ccost, K);
-      hipLaunchKernelGGL(k_chain_costs, dim3(grid_for(K, 256, 1u << 16)), dim3(256), 0, st,
-                         (const uint64_t*)s->stage.as<uint64_t>(), K, s->ccost.as<uint8_t>());
+      if (cfg.uncompressed)
+        hipLaunchKernelGGL((k_fill<uint8_t>), dim3(grid_for(K, 256, 4096)), dim3(256), 0, st, s->ccost.as<uint8_t>(),
+                           K, (uint8_t)8);
+      else
+        hipLaunchKernelGGL(k_chain_costs, dim3(grid_for(K, 256, 1u << 16)), dim3(256), 0, st,
+                           (const uint64_t*)s->stage.as<uint64_t>(), K, s->ccost.as<uint8_t>());
       HIPCHK(hipGetLastError());
       ensure(s->P, (K + 1) * sizeof(uint64_t));
       scan<uint64_t>(s, s->P.as<uint64_t>(), K, st, U8Fn{s->ccost.as<uint8_t>()});
@@ -1429,7 +1482,7 @@ static QueryArgs query_args(const cpma* s);
 
 cpma_status cpma_apply_updates(cpma* s, uint32_t nreq, const int32_t* kind, const uint64_t* const* keys,
                                const uint64_t* n, cpma_mem mem, uint64_t* result, void* stream) {
-  if (!s || (nreq && (!kind || !keys || !n || !result))) return CPMA_ERR_INVALID;
+  if (!s || (nreq && (!kind || !keys || !n || !result)) || s->cfg.uncompressed) return CPMA_ERR_INVALID;
   if (s->broken) return CPMA_ERR_DEVICE;
   uint64_t m = 0;
   for (uint32_t r = 0; r < nreq; r++) {
@@ -1618,6 +1671,7 @@ static QueryArgs query_args(const cpma* s) {
   a.used = (const uint32_t*)s->used.p;
   a.L = s->L;
   a.S = s->S;
+  a.raw = s->cfg.uncompressed ? 1u : 0u;
   return a;
 }
 
@@ -1880,7 +1934,7 @@ cpma_status cpma_fgraph_bfs(const cpma* cs, uint32_t nv, uint32_t source, int sy
                             uint32_t* level, void* stream) {
   cpma* s = const_cast<cpma*>(cs);
   if (!s || !level || nv == 0 || source >= nv) return CPMA_ERR_INVALID;
-  if (s->S > kWaveMaxS) return CPMA_ERR_INVALID;
+  if (s->S > kWaveMaxS || s->cfg.uncompressed) return CPMA_ERR_INVALID;
   if (s->broken) return CPMA_ERR_DEVICE;
   hipStream_t st = (hipStream_t)stream;
   return guarded(s, [&] {
@@ -1901,7 +1955,7 @@ cpma_status cpma_fgraph_bfs(const cpma* cs, uint32_t nv, uint32_t source, int sy
 cpma_status cpma_fgraph_offsets(const cpma* cs, uint32_t nv, cpma_mem mem, uint64_t* off, void* stream) {
   cpma* s = const_cast<cpma*>(cs);
   if (!s || !off || nv == 0) return CPMA_ERR_INVALID;
-  if (s->S > kWaveMaxS) return CPMA_ERR_INVALID;
+  if (s->S > kWaveMaxS || s->cfg.uncompressed) return CPMA_ERR_INVALID;
   if (s->broken) return CPMA_ERR_DEVICE;
   hipStream_t st = (hipStream_t)stream;
   return guarded(s, [&] {
@@ -1927,7 +1981,7 @@ cpma_status cpma_fgraph_offsets(const cpma* cs, uint32_t nv, cpma_mem mem, uint6
 cpma_status cpma_fgraph_cc(const cpma* cs, uint32_t nv, cpma_mem mem, uint32_t* label, void* stream) {
   cpma* s = const_cast<cpma*>(cs);
   if (!s || !label || nv == 0) return CPMA_ERR_INVALID;
-  if (s->S > kWaveMaxS) return CPMA_ERR_INVALID;
+  if (s->S > kWaveMaxS || s->cfg.uncompressed) return CPMA_ERR_INVALID;
   if (s->broken) return CPMA_ERR_DEVICE;
   hipStream_t st = (hipStream_t)stream;
   return guarded(s, [&] {
@@ -1961,7 +2015,7 @@ cpma_status cpma_fgraph_bc(const cpma* cs, uint32_t nv, uint32_t source, cpma_me
                            double* delta, void* stream) {
   cpma* s = const_cast<cpma*>(cs);
   if (!s || !delta || nv == 0 || source >= nv) return CPMA_ERR_INVALID;
-  if (s->S > kWaveMaxS) return CPMA_ERR_INVALID;
+  if (s->S > kWaveMaxS || s->cfg.uncompressed) return CPMA_ERR_INVALID;
   if (s->broken) return CPMA_ERR_DEVICE;
   hipStream_t st = (hipStream_t)stream;
   return guarded(s, [&] {
@@ -2016,7 +2070,7 @@ cpma_status cpma_fgraph_pagerank(const cpma* cs, uint32_t nv, int iters, double 
                                  void* stream) {
   cpma* s = const_cast<cpma*>(cs);
   if (!s || !p || nv == 0 || iters < 0 || !(damping >= 0.0 && damping <= 1.0)) return CPMA_ERR_INVALID;
-  if (s->S > kWaveMaxS) return CPMA_ERR_INVALID;
+  if (s->S > kWaveMaxS || s->cfg.uncompressed) return CPMA_ERR_INVALID;
   if (s->broken) return CPMA_ERR_DEVICE;
   hipStream_t st = (hipStream_t)stream;
   return guarded(s, [&] {
@@ -2252,6 +2306,7 @@ extern "C" cpma_status cpma_autotune(const uint64_t* keys, uint64_t n, cpma_mem 
     cfg.build_density = base->build_density > 0 ? base->build_density : cfg.up_root / cfg.grow;
     if (base->range_chunk) cfg.range_chunk = base->range_chunk;
     if (base->rebuild_frac > 0) cfg.rebuild_frac = base->rebuild_frac;
+    if (base->uncompressed) return CPMA_ERR_INVALID;  // the tuner times the compressed leaves
   }
   cpma_status cs = check_config(cfg);
   if (cs != CPMA_OK) return cs;

@@ -24,7 +24,15 @@ struct QueryArgs {
   const uint32_t* used;
   uint64_t L;
   uint32_t S;
+  uint32_t raw;  // uncompressed leaves (raw 8-byte keys)
 };
+
+// Keys of [lo, hi) in one leaf, one lane, for either leaf format.
+__device__ __forceinline__ LeafSum leaf_range_any(const QueryArgs& a, uint64_t leaf, uint32_t used, uint64_t lo,
+                                                  uint64_t hi) {
+  const uint8_t* p = a.bytes + leaf * (uint64_t)a.S;
+  return a.raw ? raw_sum_range(p, used, lo, hi) : leaf_sum_range(p, used, lo, hi);
+}
 
 // End leaves of every query (the leaf of lo and the leaf of hi - 1), scanned with
 // comparisons by one lane per query; the result initialises sum / count.  The
@@ -44,11 +52,11 @@ __global__ void __launch_bounds__(256) k_rm_ends(QueryArgs a, uint64_t* __restri
       f = locate_leaf(a.head, a.L, lo);
       const uint64_t l = locate_leaf(a.head, a.L, hi - 1);
       const uint32_t uf = a.used[f];
-      r = leaf_sum_range(a.bytes + f * (uint64_t)a.S, uf, lo, hi);
+      r = leaf_range_any(a, f, uf, lo, hi);
       visited += uf;
       if (l != f) {
         const uint32_t ul = a.used[l];
-        const LeafSum r2 = leaf_sum_range(a.bytes + l * (uint64_t)a.S, ul, lo, hi);
+        const LeafSum r2 = leaf_range_any(a, l, ul, lo, hi);
         r.sum += r2.sum;
         r.count += r2.count;
         visited += ul;
@@ -114,11 +122,13 @@ __global__ void __launch_bounds__(kWave) k_rm_ends_wave(QueryArgs a, uint64_t* _
       f = wave_locate_leaf(a.head, a.L, lo);
       const uint64_t l = wave_locate_leaf(a.head, a.L, hi - 1);
       const uint32_t uf = a.used[f];
-      r = wave_leaf_sum_range(a.bytes + f * (uint64_t)a.S, uf, lo, hi);
+      r = a.raw ? wave_raw_sum_range(a.bytes + f * (uint64_t)a.S, uf, lo, hi)
+                : wave_leaf_sum_range(a.bytes + f * (uint64_t)a.S, uf, lo, hi);
       visited += uf;
       if (l != f) {
         const uint32_t ul = a.used[l];
-        const LeafSum r2 = wave_leaf_sum_range(a.bytes + l * (uint64_t)a.S, ul, lo, hi);
+        const LeafSum r2 = a.raw ? wave_raw_sum_range(a.bytes + l * (uint64_t)a.S, ul, lo, hi)
+                                 : wave_leaf_sum_range(a.bytes + l * (uint64_t)a.S, ul, lo, hi);
         r.sum += r2.sum;
         r.count += r2.count;
         visited += ul;
@@ -182,7 +192,9 @@ __global__ void __launch_bounds__(256) k_rm_interior(QueryArgs a, const uint64_t
         const uint64_t h = a.head[leaf];
         const uint64_t span = a.head[leaf + 1] - h;  // interior leaves always have a successor
         const uint8_t* lp = a.bytes + leaf * (uint64_t)a.S;
-        const LeafSum r = span < (1ull << 28) ? leaf_sum_fast(lp, u, h) : leaf_sum_range(lp, u, 0, kNoKey);
+        const LeafSum r = a.raw                ? raw_sum_all(lp, u)
+                          : span < (1ull << 28) ? leaf_sum_fast(lp, u, h)
+                                                : leaf_sum_range(lp, u, 0, kNoKey);
         s += r.sum;
         n += r.count;
         visited += u;
@@ -234,7 +246,7 @@ __global__ void __launch_bounds__(256) k_contains(QueryArgs a, const uint64_t* _
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t x = keys[i];
     const uint64_t leaf = locate_leaf(a.head, a.L, x);
-    const LeafSum r = leaf_sum_range(a.bytes + leaf * (uint64_t)a.S, a.used[leaf], x, x + 1);
+    const LeafSum r = leaf_range_any(a, leaf, a.used[leaf], x, x + 1);
     out[i] = r.count ? 1 : 0;
   }
 }

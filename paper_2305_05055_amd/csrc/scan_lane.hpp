@@ -163,4 +163,74 @@ __device__ __forceinline__ LeafSum leaf_sum_range(const uint8_t* __restrict__ le
   return r;
 }
 
+// ---- uncompressed leaves (the plain PMA) ---------------------------------------
+// The uncompressed variant keeps the same leaves, tree and byte-density bounds,
+// but a leaf holds its keys as raw little-endian 8-byte words packed to the
+// left (used = 8 x keys, zero fill after them), with no delta codes (Section
+// "Packed Memory Array"; the ablation of Section "Evaluation on
+// microbenchmarks" that isolates what compression buys).
+
+// Sum and count of the keys in [lo, hi) of an uncompressed leaf, one lane.
+__device__ __forceinline__ LeafSum raw_sum_range(const uint8_t* __restrict__ leaf, uint32_t used, uint64_t lo,
+                                                 uint64_t hi) {
+  LeafSum r{0, 0};
+  const uint64_t* k = reinterpret_cast<const uint64_t*>(leaf);
+  const uint32_t m = used / 8;
+  for (uint32_t i = 0; i < m; i += 2) {
+    const uint4 w = *reinterpret_cast<const uint4*>(k + i);
+    const uint64_t a = ((uint64_t)w.y << 32) | w.x;
+    const uint64_t b = ((uint64_t)w.w << 32) | w.z;
+    if (a >= hi) break;
+    if (a >= lo) {
+      r.sum += a;
+      r.count++;
+    }
+    if (i + 1 < m) {
+      if (b >= hi) break;
+      if (b >= lo) {
+        r.sum += b;
+        r.count++;
+      }
+    }
+  }
+  return r;
+}
+
+// Sum and count of every key of an uncompressed leaf, one lane (16-byte loads,
+// four in flight).
+__device__ __forceinline__ LeafSum raw_sum_all(const uint8_t* __restrict__ leaf, uint32_t used) {
+  const uint4* w = reinterpret_cast<const uint4*>(leaf);
+  const uint32_t m = used / 8, nw = m / 2;
+  uint64_t s0 = 0, s1 = 0;
+  uint32_t i = 0;
+  for (; i + 4 <= nw; i += 4) {
+    const uint4 a = w[i], b = w[i + 1], c = w[i + 2], d = w[i + 3];
+    s0 += (((uint64_t)a.y << 32) | a.x) + (((uint64_t)a.w << 32) | a.z) + (((uint64_t)b.y << 32) | b.x) +
+          (((uint64_t)b.w << 32) | b.z);
+    s1 += (((uint64_t)c.y << 32) | c.x) + (((uint64_t)c.w << 32) | c.z) + (((uint64_t)d.y << 32) | d.x) +
+          (((uint64_t)d.w << 32) | d.z);
+  }
+  for (; i < nw; i++) {
+    const uint4 a = w[i];
+    s0 += (((uint64_t)a.y << 32) | a.x) + (((uint64_t)a.w << 32) | a.z);
+  }
+  if (m & 1u) s1 += reinterpret_cast<const uint64_t*>(leaf)[m - 1];
+  return LeafSum{s0 + s1, m};
+}
+
+// The same for a whole wave on one leaf (keys i = lane, lane + 64, ...).
+__device__ __forceinline__ LeafSum wave_raw_sum_range(const uint8_t* __restrict__ leaf, uint32_t used, uint64_t lo,
+                                                      uint64_t hi) {
+  const uint64_t* k = reinterpret_cast<const uint64_t*>(leaf);
+  uint64_t s = 0, n = 0;
+  for (uint32_t i = lane_id(); i < used / 8; i += kWave) {
+    const uint64_t x = k[i];
+    if (x >= lo && x < hi) {
+      s += x;
+      n++;
+    }
+  }
+  return LeafSum{wave_sum(s), wave_sum(n)};
+}
+
 }  // namespace cpma_dev

@@ -423,6 +423,7 @@ struct WinArgs {
   const uint64_t* dst_n;
   const uint64_t* dst_flat;  // W + 1
   const uint32_t* level;     // window height (subtree check bound)
+  uint32_t raw;              // uncompressed leaves (raw 8-byte keys)
 };
 
 __device__ __forceinline__ uint32_t find_window(const uint64_t* flat, uint32_t W, uint64_t f) {
@@ -446,7 +447,7 @@ __global__ void __launch_bounds__(kWave) k_win_count(WinArgs wa, SrcLeaves src, 
     const uint32_t w = find_window(wa.src_flat, wa.W, f);
     const uint64_t leaf = wa.src_begin[w] + (f - wa.src_flat[w]);
     const uint32_t u = src.used[leaf];
-    const uint32_t c = wave_count_keys(src.ptr(leaf, u), u);
+    const uint32_t c = wa.raw ? u / 8 : wave_count_keys(src.ptr(leaf, u), u);
     if (lane_id() == 0) cnt[f] = c;
   }
 }
@@ -466,6 +467,15 @@ __global__ void __launch_bounds__(kWave) k_win_pack(WinArgs wa, SrcLeaves src, u
     uint64_t* out = stage + koff[f];
     uint32_t* wid = win_id + koff[f];
     uint8_t* cc = ccost + koff[f];
+    if (wa.raw) {
+      const uint64_t* k = reinterpret_cast<const uint64_t*>(src.ptr(leaf, u));
+      for (uint32_t i = lane_id(); i < u / 8; i += kWave) {
+        out[i] = k[i];
+        wid[i] = w;
+        cc[i] = 8;
+      }
+      continue;
+    }
     wave_decode_leaf(src.ptr(leaf, u), u, [&](uint32_t i, uint64_t x, uint64_t d) {
       out[i] = x;
       wid[i] = w;
@@ -630,7 +640,11 @@ __global__ void __launch_bounds__(kWave) k_leaf_encode(WinArgs wa, uint64_t nfla
     wave_zero(buf, S);
     __syncthreads();
     const uint64_t* xs = x + s;
-    wave_encode_bytes([&](uint32_t i) { return xs[i]; }, (uint32_t)(e - s), buf);
+    if (wa.raw) {
+      for (uint32_t i = lane_id(); i < (uint32_t)(e - s); i += kWave) reinterpret_cast<uint64_t*>(buf)[i] = xs[i];
+    } else {
+      wave_encode_bytes([&](uint32_t i) { return xs[i]; }, (uint32_t)(e - s), buf);
+    }
     __syncthreads();
     wave_copy16(dst_bytes + d * (uint64_t)S, buf, S);
     if (lane_id() == 0) {

@@ -99,16 +99,16 @@ def test_struct_layouts_match_the_header(tmp_path):
     prog = tmp_path / "sizes.c"
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "cpma.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(cpma_config),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(cpma_config),"
         " offsetof(cpma_config, range_chunk), offsetof(cpma_config, alloc), offsetof(cpma_config, ctx),"
-        " offsetof(cpma_config, rebuild_frac),"
+        " offsetof(cpma_config, rebuild_frac), offsetof(cpma_config, uncompressed),"
         " sizeof(cpma_tune_hint), sizeof(cpma_tune_report),"
         " offsetof(cpma_tune_report, best_chunk), sizeof(cpma_request), sizeof(cpma_phase_stat));return 0;}\n")
     exe = tmp_path / "sizes"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     want = [ctypes.sizeof(p.Config), p.Config.range_chunk.offset, p.Config.alloc.offset, p.Config.ctx.offset,
-            p.Config.rebuild_frac.offset, ctypes.sizeof(p.TuneHint),
+            p.Config.rebuild_frac.offset, p.Config.uncompressed.offset, ctypes.sizeof(p.TuneHint),
             ctypes.sizeof(p.TuneReport), p.TuneReport.best_chunk.offset, ctypes.sizeof(p.Request),
             ctypes.sizeof(p.PhaseStat)]
     assert got == want

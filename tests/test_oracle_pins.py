@@ -484,3 +484,77 @@ def test_bc_brute_force_path_counts(orc):
                         if t != v and D[s0][t] >= 0 and D[v][t] >= 0 and D[s0][v] + D[v][t] == D[s0][t]:
                             want += C[s0][v] * C[v][t] / C[s0][t]
                 assert abs(dl[v] - want) <= 1e-12 * max(1.0, want), (seed, s0, v, dl[v], want)
+
+
+# ---- the uncompressed variant's checker (the plain PMA) ----------------------------
+def _pma_image(leaves, S=64):
+    """Hand-built image of the uncompressed layout: each leaf's keys as 8-byte
+    little-endian words from its start, zero bytes after them."""
+    L = len(leaves)
+    img = np.zeros(L * S, dtype=np.uint8)
+    used = np.zeros(L, dtype=np.uint32)
+    head = np.full(L, np.iinfo(np.uint64).max, dtype=np.uint64)
+    for j, ks in enumerate(leaves):
+        for t, k in enumerate(ks):
+            img[j * S + 8 * t: j * S + 8 * t + 8] = np.frombuffer(int(k).to_bytes(8, "little"), dtype=np.uint8)
+        used[j] = 8 * len(ks)
+        if ks:
+            head[j] = ks[0]
+    keys = np.array([k for ks in leaves for k in ks], dtype=np.uint64)
+    return img, used, head, keys
+
+
+# Three leaves of 64 bytes, H = 2, bounds 0.9 / 0.7 (upper, leaf / root) and
+# 0.1 / 0.3 (lower), so at h = 1 the bounds are 0.8 and 0.2.  Filled bytes
+# 32, 24, 16: leaves 0.5 / 0.375 / 0.25; [0, 2) 56 / 128 = 0.4375; the
+# truncated window [2, 3) 16 / 64 = 0.25 (against the full 128 bytes it would
+# be 0.125, below 0.2); root 72 / 192 = 0.375.
+PMA_GOLDEN = [[10, 20, 30, 40], [50, 60, 70], [80, 90]]
+
+
+def test_pma_checker_accepts_hand_built_image(orc):
+    img, used, head, keys = _pma_image(PMA_GOLDEN)
+    code, msg = orc.check_image_pma(img, used, head, 64, keys)
+    assert code == 0, msg
+    # the same image is no valid delta-coded leaf set (its words are not codes)
+    assert orc.check_image(img, used, head, 64, keys)[0] != 0
+
+
+def test_pma_checker_plants_rejected_for_their_reason(orc):
+    S = 64
+    # a used count that is not a whole number of keys
+    img, used, head, keys = _pma_image(PMA_GOLDEN)
+    used[1] = 20
+    code, msg = orc.check_image_pma(img, used, head, S, keys)
+    assert code == 15, msg
+    # keys out of order inside a leaf (the head stays the leaf's first word)
+    img, used, head, keys = _pma_image([[10, 30, 20, 40], [50, 60, 70], [80, 90]])
+    code, msg = orc.check_image_pma(img, used, head, S, np.sort(keys))
+    assert code == 10, msg
+    # a head that is not the leaf's first key
+    img, used, head, keys = _pma_image(PMA_GOLDEN)
+    head[1] = 55
+    code, msg = orc.check_image_pma(img, used, head, S, keys)
+    assert code == 6, msg
+    # a nonzero byte in the free part of a leaf
+    img, used, head, keys = _pma_image(PMA_GOLDEN)
+    img[2 * S + 20] = 1
+    code, msg = orc.check_image_pma(img, used, head, S, keys)
+    assert code == 8 and "(2, 20)" in msg, msg
+    # a full leaf: 64 / 64 > 0.9 at the leaf level
+    img, used, head, keys = _pma_image([[1, 2, 3, 4, 5, 6, 7, 8], [50, 60, 70], [80, 90]])
+    code, msg = orc.check_image_pma(img, used, head, S, keys)
+    assert code == 13 and "(0, 0)" in msg, msg
+    # the truncated last window below 0.2 at h = 1: leaf 2 keeps one key,
+    # 8 / 64 = 0.125 (the leaf itself is within 0.1, the root at 64 / 192)
+    img, used, head, keys = _pma_image([[10, 20, 30, 40], [50, 60, 70], [80]])
+    code, msg = orc.check_image_pma(img, used, head, S, keys)
+    assert code == 14 and "(1, 2)" in msg, msg
+    # an empty leaf in a set of more than one leaf
+    img, used, head, keys = _pma_image([[10, 20, 30, 40], [], [80, 90]])
+    code, msg = orc.check_image_pma(img, used, head, S, keys)
+    assert code == 3, msg
+    # contents that differ from the expected set
+    img, used, head, keys = _pma_image(PMA_GOLDEN)
+    code, msg = orc.check_image_pma(img, used, head, S, keys + np.uint64(1))
+    assert code == 12, msg
