@@ -114,6 +114,23 @@ typedef enum { CPMA_MEM_HOST = 0, CPMA_MEM_DEVICE = 1 } cpma_mem;
  *                  support it; cpma_apply_updates (and so the updates of a
  *                  server), the F-Graph calls and cpma_autotune return
  *                  CPMA_ERR_INVALID for it.
+ *   values         0 (default): a set of keys.  1: a key-value CPMA (the
+ *                  extension the paper names as future work for weighted
+ *                  graphs, Section "Evaluation on graph workloads"): every key
+ *                  carries an 8-byte value.  A leaf keeps its keys exactly as
+ *                  the CPMA does (head and delta codes from byte 0) and the
+ *                  values as 8-byte words in key order at the end of the leaf;
+ *                  the density bounds count both (every key costs its code and
+ *                  8 bytes).  Build with cpma_build_kv (cpma_build gives every
+ *                  key the value 0); cpma_insert_kv inserts or overwrites;
+ *                  cpma_insert_batch adds keys with value 0 and leaves present
+ *                  keys' values; cpma_delete_batch, range_map (of keys),
+ *                  contains, the F-Graph calls and trim work as for a set;
+ *                  cpma_get and cpma_range_map_values read values;
+ *                  cpma_export_code_bytes returns each leaf's code bytes.  A
+ *                  resize restages every key and value.  Not with
+ *                  uncompressed = 1; cpma_apply_updates and cpma_autotune
+ *                  return CPMA_ERR_INVALID for it.
  *   alloc, free, ctx
  *                  device memory for everything the handle owns (leaves, heads,
  *                  used counts, counters, scratch): alloc(bytes, ctx) returns a
@@ -137,6 +154,7 @@ typedef struct {
   void* ctx;
   double rebuild_frac;
   int32_t uncompressed;
+  int32_t values;
 } cpma_config;
 
 /* Fills *cfg with the defaults above.  Returns CPMA_ERR_INVALID if cfg is NULL. */
@@ -270,7 +288,8 @@ uint64_t cpma_size(const cpma* set);
 
 /*
  * get_size(): bytes of device memory held by the structure itself -- leaves
- * (num_leaves * leaf_bytes), leaf heads (8 B each) and used counts (4 B each).
+ * (num_leaves * leaf_bytes), leaf heads (8 B each) and used counts (4 B each),
+ * and for a key-value set the code byte counts (4 B each).
  * Scratch buffers kept for later batches are not counted.
  */
 uint64_t cpma_bytes(const cpma* set);
@@ -306,6 +325,42 @@ cpma_status cpma_geometry(const cpma* set, uint64_t* num_leaves, uint32_t* leaf_
  */
 cpma_status cpma_export(const cpma* set, uint8_t* bytes, uint32_t* used,
                         uint64_t* head, void* stream);
+
+/*
+ * Key-value sets (cpma_config.values = 1; the key-value CPMA, Section
+ * "Evaluation on graph workloads" names it as future work for weighted graphs).
+ *
+ * cpma_build_kv: cpma_build with a value per key; values[0..n) in the same
+ * memory space as keys, values[i] belongs to keys[i]; a key given more than
+ * once takes the value of its first occurrence.  cfg->values is taken as 1;
+ * cfg->uncompressed must be 0 (CPMA_ERR_INVALID).  n < 2^31.
+ *
+ * cpma_insert_kv: inserts or overwrites (upsert): a key not in the set is added
+ * with its value, a present key takes the new value.  Repeats in the batch:
+ * the first occurrence's value.  *n_added = keys added (overwrites are not
+ * counted).  k < 2^31.  CPMA_ERR_INVALID on a set without values.
+ * Synchronises `stream`.
+ *
+ * cpma_get: values[i] = the value of keys[i] and found[i] = 1, or 0 and 0 when
+ * it is absent; keys, values, found in memory space `mem`.
+ *
+ * cpma_range_map_values: range_map with f = (sum of the values mod 2^64,
+ * count) over the keys in [lo[i], hi[i]); the weighted degree of a vertex u of
+ * a weighted F-Graph is the range [u << 32, (u + 1) << 32).
+ *
+ * cpma_export_code_bytes: clen[num_leaves] (host) = each leaf's key code bytes
+ * (used counts codes and values: used = clen + 8 x keys).  Synchronises.
+ */
+cpma_status cpma_build_kv(const uint64_t* keys, const uint64_t* values, uint64_t n, cpma_mem mem,
+                          const cpma_config* cfg, void* stream, cpma** out);
+cpma_status cpma_insert_kv(cpma* set, const uint64_t* keys, const uint64_t* values, uint64_t k,
+                           cpma_mem mem, void* stream, uint64_t* n_added);
+cpma_status cpma_get(const cpma* set, const uint64_t* keys, uint64_t q, cpma_mem mem,
+                     uint64_t* values, uint8_t* found, void* stream);
+cpma_status cpma_range_map_values(const cpma* set, const uint64_t* lo, const uint64_t* hi,
+                                  uint64_t q, cpma_mem mem, uint64_t* vsum, uint64_t* count,
+                                  void* stream);
+cpma_status cpma_export_code_bytes(const cpma* set, uint32_t* clen, void* stream);
 
 /*
  * F-Graph (Section "Evaluation on graph workloads"): the set holds a graph's

@@ -74,6 +74,9 @@ def lib():
         L.orc_check_image.restype = ctypes.c_int
         L.orc_check_image_pma.argtypes = L.orc_check_image.argtypes
         L.orc_check_image_pma.restype = ctypes.c_int
+        L.orc_check_image_kv.argtypes = [u8p, u32p, u32p, u64p, c_u64, ctypes.c_uint32, dp, u64p, u64p,
+                                         c_u64, ctypes.c_char_p, ctypes.c_int]
+        L.orc_check_image_kv.restype = ctypes.c_int
         L.orc_decode_image.argtypes = [u8p, u32p, c_u64, ctypes.c_uint32, u64p, c_u64]
         L.orc_decode_image.restype = ctypes.c_int64
         L.orc_bfs.argtypes = [u64p, c_u64, ctypes.c_uint32, ctypes.c_uint32, u32p]
@@ -193,6 +196,76 @@ def check_image_pma(bytes_, used, head, S, expect, params=DEFAULT_PARAMS):
                                      _p(h, ctypes.c_uint64), L, S, pa, _p(e, ctypes.c_uint64),
                                      len(e), msg, 256)
     return int(code), msg.value.decode()
+
+
+def check_image_kv(bytes_, used, clen, head, S, expect, expect_vals, params=DEFAULT_PARAMS):
+    """check_image for key-value leaves (codes, then values at the leaf's end)."""
+    b = np.ascontiguousarray(bytes_, dtype=np.uint8)
+    u = np.ascontiguousarray(used, dtype=np.uint32)
+    c = np.ascontiguousarray(clen, dtype=np.uint32)
+    h = _u64(head)
+    e = _u64(expect)
+    ev = _u64(expect_vals)
+    L = len(u)
+    assert len(b) == L * S and len(h) == L and len(c) == L and len(ev) == len(e)
+    pa = (ctypes.c_double * 4)(*params)
+    msg = ctypes.create_string_buffer(256)
+    code = lib().orc_check_image_kv(_p(b, ctypes.c_uint8), _p(u, ctypes.c_uint32), _p(c, ctypes.c_uint32),
+                                    _p(h, ctypes.c_uint64), L, S, pa, _p(e, ctypes.c_uint64),
+                                    _p(ev, ctypes.c_uint64), len(e), msg, 256)
+    return int(code), msg.value.decode()
+
+
+# ---- the key-value set (sorted keys with their values) -----------------------------
+# A key-value set is a pair (K, V): K the sorted distinct keys, V[i] the value
+# of K[i].  Batches may repeat a key; its first occurrence counts.
+
+def kv_build(keys, vals):
+    k = _u64(keys)
+    v = _u64(vals)
+    K, first = np.unique(k, return_index=True)
+    return K, v[first].copy()
+
+
+def kv_insert(K, V, keys, vals):
+    """Upsert: new keys join with their values, present keys take the new
+    value.  Returns (K', V', number of keys added)."""
+    bk, bv = kv_build(keys, vals)
+    pos = np.searchsorted(K, bk)
+    present = (pos < len(K)) & (K[np.minimum(pos, max(len(K) - 1, 0))] == bk) if len(K) else np.zeros(len(bk), bool)
+    V2 = V.copy()
+    V2[pos[present]] = bv[present]
+    nk = np.concatenate([K, bk[~present]])
+    nv = np.concatenate([V2, bv[~present]])
+    order = np.argsort(nk, kind="stable")
+    return nk[order], nv[order], int((~present).sum())
+
+
+def kv_delete(K, V, keys):
+    """Removes the keys present; returns (K', V', number removed)."""
+    gone = np.isin(K, _u64(keys))
+    return K[~gone].copy(), V[~gone].copy(), int(gone.sum())
+
+
+def kv_get(K, V, keys):
+    q = _u64(keys)
+    pos = np.searchsorted(K, q)
+    ok = pos < len(K)
+    found = np.zeros(len(q), dtype=np.uint8)
+    found[ok] = (K[pos[ok]] == q[ok])
+    val = np.zeros(len(q), dtype=np.uint64)
+    val[found == 1] = V[pos[found == 1]]
+    return val, found
+
+
+def kv_range_values(K, V, lo, hi):
+    """(sum of the values mod 2^64, count) of the keys in each [lo, hi)."""
+    lo, hi = _u64(lo), _u64(hi)
+    cs = np.concatenate([np.zeros(1, np.uint64), np.cumsum(V, dtype=np.uint64)])
+    i0 = np.searchsorted(K, lo, side="left")
+    i1 = np.searchsorted(K, hi, side="left")
+    i1 = np.maximum(i0, i1)
+    return cs[i1] - cs[i0], (i1 - i0).astype(np.uint64)
 
 
 def decode_image(bytes_, used, S, cap):

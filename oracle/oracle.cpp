@@ -334,6 +334,59 @@ extern "C" int orc_check_image_pma(const uint8_t* bytes, const uint32_t* used,
 }
 
 // ---------------------------------------------------------------------------
+// Checker of key-value leaves (the key-value CPMA): a leaf holds its keys as
+// the CPMA does in its first clen bytes, and one 8-byte little-endian value
+// per key, in key order, in its last bytes; the bytes between are zero and its
+// filled bytes are clen + 8 per key.
+// ---------------------------------------------------------------------------
+extern "C" int orc_check_image_kv(const uint8_t* bytes, const uint32_t* used,
+                                  const uint32_t* clen, const uint64_t* head, uint64_t L,
+                                  uint32_t S, const double* params, const uint64_t* expect,
+                                  const uint64_t* expect_vals, uint64_t n, char* msg,
+                                  int msglen) {
+  if (L == 0) return fail(msg, msglen, 1, "no leaves", 0, 0);
+  Vec all, vals;
+  for (uint64_t i = 0; i < L; i++) {
+    const uint8_t* leaf = bytes + i * (uint64_t)S;
+    uint32_t u = used[i], c = clen[i];
+    if (u > S) return fail(msg, msglen, 2, "used exceeds leaf size", i, u);
+    if (c > u) return fail(msg, msglen, 16, "code bytes exceed used", i, c);
+    if (u == 0) {
+      if (!(L == 1 && n == 0)) return fail(msg, msglen, 3, "empty leaf", i, L);
+      if (head[i] != UINT64_MAX) return fail(msg, msglen, 4, "empty leaf head", i, head[i]);
+    } else {
+      size_t before = all.size();
+      if (c < 8 || decode_leaf(leaf, c, S, all) < 0) return fail(msg, msglen, 5, "malformed leaf", i, c);
+      if (head[i] != all[before]) return fail(msg, msglen, 6, "head mismatch", i, head[i]);
+      uint64_t bytes_needed = 8;
+      uint8_t tmp[10];
+      for (size_t j = before + 1; j < all.size(); j++)
+        bytes_needed += (uint64_t)orc_varint_encode(all[j] - all[j - 1], tmp);
+      if (bytes_needed != c) return fail(msg, msglen, 7, "code bytes != encoded length", i, c);
+      uint64_t m = all.size() - before;
+      if ((uint64_t)c + 8 * m != u) return fail(msg, msglen, 17, "used != code bytes + 8 per key", i, u);
+      for (uint64_t j = 0; j < m; j++) vals.push_back(load_le64(leaf + S - 8 * m + 8 * j));
+    }
+    uint64_t m_here = u ? (u - c) / 8 : 0;
+    for (uint32_t b = c; b < S - 8 * m_here; b++)
+      if (leaf[b] != 0) return fail(msg, msglen, 8, "nonzero byte between codes and values", i, b);
+    if (i > 0 && head[i] <= head[i - 1])
+      return fail(msg, msglen, 9, "heads not increasing", i, head[i]);
+  }
+  for (size_t j = 1; j < all.size(); j++)
+    if (all[j] <= all[j - 1]) return fail(msg, msglen, 10, "keys not increasing", j, all[j]);
+  if (all.size() != n) return fail(msg, msglen, 11, "size mismatch", all.size(), n);
+  for (uint64_t j = 0; j < n; j++)
+    if (all[j] != expect[j]) return fail(msg, msglen, 12, "content mismatch", j, all[j]);
+  for (uint64_t j = 0; j < n; j++)
+    if (vals[j] != expect_vals[j]) return fail(msg, msglen, 18, "value mismatch", j, vals[j]);
+  int code = density_walk(used, L, S, params, msg, msglen);
+  if (code) return code;
+  if (msg && msglen > 0) msg[0] = 0;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // F-Graph (Section "Evaluation on graph workloads"): an edge (u, v) is the key
 // u<<32 | v; the CSR is the canonical two-array form the paper contrasts with.
 // ---------------------------------------------------------------------------

@@ -87,6 +87,15 @@ int orc_check_image_pma(const uint8_t* bytes, const uint32_t* used,
                         const uint64_t* head, uint64_t L, uint32_t S,
                         const double* params, const uint64_t* expect, uint64_t n,
                         char* msg, int msglen);
+/* The same checks for key-value leaves: codes in each leaf's first clen[i]
+ * bytes, one 8-byte value per key at its end (used = clen + 8 x keys), zero
+ * bytes between; expect_vals[n] are the values in key order.  Codes 16, 17
+ * and 18 flag code bytes above used, a used count that is not the codes plus
+ * 8 per key, and a wrong value. */
+int orc_check_image_kv(const uint8_t* bytes, const uint32_t* used, const uint32_t* clen,
+                       const uint64_t* head, uint64_t L, uint32_t S, const double* params,
+                       const uint64_t* expect, const uint64_t* expect_vals, uint64_t n,
+                       char* msg, int msglen);
 /* Decodes an image into keys (capacity cap); returns the key count or -1. */
 int64_t orc_decode_image(const uint8_t* bytes, const uint32_t* used, uint64_t L,
                          uint32_t S, uint64_t* out, uint64_t cap);

@@ -34,7 +34,8 @@ class Config(ctypes.Structure):
                 ("lo_leaf", ctypes.c_double), ("lo_root", ctypes.c_double),
                 ("build_density", ctypes.c_double), ("range_chunk", ctypes.c_uint32),
                 ("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p), ("ctx", ctypes.c_void_p),
-                ("rebuild_frac", ctypes.c_double), ("uncompressed", ctypes.c_int32)]
+                ("rebuild_frac", ctypes.c_double), ("uncompressed", ctypes.c_int32),
+                ("values", ctypes.c_int32)]
 
 
 class TuneHint(ctypes.Structure):
@@ -103,6 +104,11 @@ def lib():
         L.cpma_bytes_held.argtypes = [vp]
         L.cpma_bytes_held.restype = u64
         L.cpma_trim.argtypes = [vp, vp]
+        L.cpma_build_kv.argtypes = [vp, vp, u64, ctypes.c_int, vp, vp, ctypes.POINTER(vp)]
+        L.cpma_insert_kv.argtypes = [vp, vp, vp, u64, ctypes.c_int, vp, ctypes.POINTER(u64)]
+        L.cpma_get.argtypes = [vp, vp, u64, ctypes.c_int, vp, vp, vp]
+        L.cpma_range_map_values.argtypes = [vp, vp, vp, u64, ctypes.c_int, vp, vp, vp]
+        L.cpma_export_code_bytes.argtypes = [vp, vp, vp]
         L.cpma_geometry.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_uint32)]
         L.cpma_export.argtypes = [vp, vp, vp, vp, vp]
         L.cpma_destroy.argtypes = [vp]
@@ -189,8 +195,9 @@ class CPMA:
     """A device-resident compressed packed memory array of uint64 keys."""
 
     def __init__(self, keys=(), leaf_bytes=0, grow=0.0, bounds=None, build_density=0.0,
-                 stream=None, config=None, range_chunk=0, uncompressed=False):
-        """uncompressed=True builds the plain PMA (raw 8-byte keys per leaf)."""
+                 stream=None, config=None, range_chunk=0, uncompressed=False, values=None):
+        """uncompressed=True builds the plain PMA (raw 8-byte keys per leaf);
+        values (an array beside keys, same memory space) builds a key-value set."""
         if config is not None:
             cfg = Config.from_buffer_copy(config)
         else:
@@ -204,8 +211,16 @@ class CPMA:
             cfg.uncompressed = 1 if uncompressed else 0
         p, n, mem, keep = _keys(keys)
         h = ctypes.c_void_p()
-        _check(lib().cpma_build(p if n else None, n, mem, ctypes.byref(cfg),
-                                _stream(stream, mem == MEM_DEVICE), ctypes.byref(h)), "cpma_build")
+        if values is not None:
+            pv, nv, memv, keepv = _keys(values)
+            if nv != n or memv != mem:
+                raise ValueError("values must match keys in length and memory space")
+            _check(lib().cpma_build_kv(p if n else None, pv if n else None, n, mem, ctypes.byref(cfg),
+                                       _stream(stream, mem == MEM_DEVICE), ctypes.byref(h)), "cpma_build_kv")
+            keep = (keep, keepv)
+        else:
+            _check(lib().cpma_build(p if n else None, n, mem, ctypes.byref(cfg),
+                                    _stream(stream, mem == MEM_DEVICE), ctypes.byref(h)), "cpma_build")
         self._h = h
         self._keep = keep
 
@@ -234,6 +249,44 @@ class CPMA:
     def insert_batch(self, keys, sorted=False, stream=None):
         """Inserts keys; returns how many were not present before."""
         return self._update(lib().cpma_insert_batch, keys, sorted, stream, "cpma_insert_batch")
+
+    def insert_kv(self, keys, values, stream=None):
+        """Inserts or overwrites key-value pairs; returns how many keys were new."""
+        p, k, mem, keep = _keys(keys)
+        pv, kv, memv, keepv = _keys(values)
+        if kv != k or memv != mem:
+            raise ValueError("values must match keys in length and memory space")
+        out = ctypes.c_uint64(0)
+        _check(lib().cpma_insert_kv(self._h, p if k else None, pv if k else None, k, mem,
+                                    _stream(stream, mem == MEM_DEVICE), ctypes.byref(out)), "cpma_insert_kv")
+        return int(out.value)
+
+    def get(self, keys, stream=None):
+        """(values, found) of a key-value set for each key."""
+        p, q, mem, keep = _keys(keys)
+        if mem == MEM_DEVICE:
+            import torch
+            v = torch.empty(q, dtype=torch.int64, device=keys.device)
+            f = torch.empty(q, dtype=torch.uint8, device=keys.device)
+            pv, pf = ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(f.data_ptr())
+        else:
+            v = np.empty(q, dtype=np.uint64)
+            f = np.empty(q, dtype=np.uint8)
+            pv, pf = ctypes.c_void_p(v.ctypes.data), ctypes.c_void_p(f.ctypes.data)
+        _check(lib().cpma_get(self._h, p, q, mem, pv, pf, _stream(stream, mem == MEM_DEVICE)), "cpma_get")
+        return v, f
+
+    def range_map_values(self, lo, hi, stream=None):
+        """(sum of the values mod 2^64, count) of the keys in each [lo[i], hi[i])."""
+        return self.range_map(lo, hi, stream, _fn=lib().cpma_range_map_values, _what="cpma_range_map_values")
+
+    def code_bytes(self, stream=None):
+        """Each leaf's key code bytes (key-value sets)."""
+        L, _ = self.geometry()
+        c = np.empty(L, dtype=np.uint32)
+        _check(lib().cpma_export_code_bytes(self._h, ctypes.c_void_p(c.ctypes.data), _stream(stream, False)),
+               "cpma_export_code_bytes")
+        return c
 
     def delete_batch(self, keys, sorted=False, stream=None):
         """Deletes keys; returns how many were present."""
@@ -278,7 +331,7 @@ class CPMA:
                "cpma_contains")
         return out
 
-    def range_map(self, lo, hi, stream=None):
+    def range_map(self, lo, hi, stream=None, _fn=None, _what="cpma_range_map"):
         """(sum mod 2^64, count) of the keys in each [lo[i], hi[i])."""
         plo, q, mem, klo = _keys(lo)
         phi, q2, mem2, khi = _keys(hi)
@@ -293,8 +346,8 @@ class CPMA:
             s = np.empty(q, dtype=np.uint64)
             c = np.empty(q, dtype=np.uint64)
             ps, pc = ctypes.c_void_p(s.ctypes.data), ctypes.c_void_p(c.ctypes.data)
-        _check(lib().cpma_range_map(self._h, plo, phi, q, mem, ps, pc,
-                                    _stream(stream, mem == MEM_DEVICE)), "cpma_range_map")
+        _check((_fn or lib().cpma_range_map)(self._h, plo, phi, q, mem, ps, pc,
+                                             _stream(stream, mem == MEM_DEVICE)), _what)
         return s, c
 
     def range_map_noalloc(self, lo, hi, sum_out=None, count_out=None, stream=None):

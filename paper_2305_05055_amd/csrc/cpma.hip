@@ -27,6 +27,7 @@
 #include "small.hpp"
 #include "fuse.hpp"
 #include "pma.hpp"
+#include "kv.hpp"
 
 using namespace cpma_dev;
 
@@ -135,7 +136,14 @@ struct cpma {
       spare_bytes, spare_used, spare_head, fg_level, fg_deg, fg_p, fg_c, fg_acc,
       win_of_leaf, fail, qa, qb, qfirst, qnvis, qvoff, qsum, qcount, qout, lastk, lckpt, ne_rank, ne_list, chain_pfx,
       srec, wide, srcinfo, parts, qparts, fz_meta, fz_v0, fz_v1, fz_byte, fz_member, fz_code, fz_ctr, fz_res,
-      ctr_buf, info_buf, qalg_buf;
+      ctr_buf, info_buf, qalg_buf, clen, spare_clen, vstage, kvals, kvdedup;
+  // key-value sets: the current update batch's values (device, repeat-free and
+  // in batch order), NULL for key-only updates
+  const uint64_t* batch_vals = nullptr;
+  bool kv() const { return cfg.values != 0; }
+  // the leaf array the key decoders read as "used": the code bytes of a
+  // key-value set, else the filled bytes
+  const uint32_t* code_bytes() const { return (const uint32_t*)(cfg.values ? clen.p : used.p); }
   Counters* dctr = nullptr;
   Counters* hctr = nullptr;
   BatchInfo* dinfo = nullptr;
@@ -169,7 +177,8 @@ struct cpma {
             &fail,      &qa,        &qb,        &qfirst,      &qnvis,      &qvoff,       &qsum,       &qcount,
             &qout,      &lastk,     &ne_rank,   &ne_list,     &chain_pfx,  &srec,        &wide,       &srcinfo,
             &parts,     &qparts,    &fz_meta,   &fz_v0,       &fz_v1,      &fz_byte,     &fz_member,  &fz_code,
-            &fz_ctr,    &fz_res,    &ctr_buf,   &info_buf,    &qalg_buf,   &lckpt};
+            &fz_ctr,    &fz_res,    &ctr_buf,   &info_buf,    &qalg_buf,   &lckpt,      &clen,        &spare_clen,
+            &vstage,    &kvals,     &kvdedup};
   }
 
   Bounds bounds(uint64_t Lx) const {
@@ -370,6 +379,73 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
   return s->kdedup.as<uint64_t>();
 }
 
+// Batch prep with values: validation, a stable radix sort of the keys carrying
+// their input positions, then the first occurrence of every key with the value
+// at its position (vals NULL: values 0).  Returns the repeat-free keys; their
+// values are in s->kvdedup and their number in dctr->kprime.  Throws
+// CPMA_ERR_RESERVED_KEY before any mutation.
+const uint64_t* kv_prepare(cpma* s, const uint64_t* keys, const uint64_t* vals, uint64_t k, cpma_mem mem,
+                           hipStream_t st) {
+  if (k >= (1ull << 31)) throw Fail{CPMA_ERR_INVALID};  // positions travel in 31 bits
+  const uint64_t* src = keys;
+  const uint64_t* vsrc = vals;
+  if (mem == CPMA_MEM_HOST) {
+    ensure(s->kin, k * sizeof(uint64_t));
+    HIPCHK(hipMemcpyAsync(s->kin.p, keys, k * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    src = s->kin.as<uint64_t>();
+    if (vals) {
+      ensure(s->kvals, k * sizeof(uint64_t));
+      HIPCHK(hipMemcpyAsync(s->kvals.p, vals, k * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+      vsrc = s->kvals.as<uint64_t>();
+    }
+  }
+  hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(s->dinfo),
+                     (uint64_t)(sizeof(BatchInfo) / 4), 0u);
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(k, 256, 4096)), dim3(256), 0, st, src, k, s->dinfo);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(s->hinfo, s->dinfo, sizeof(BatchInfo), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (s->hinfo->has_reserved) throw Fail{CPMA_ERR_RESERVED_KEY};
+  PhaseMark pm = phase_begin(s, CPMA_PHASE_SORT, st);
+  const int bits = 64 - __builtin_clzll(s->hinfo->or_all | 1);
+  const int passes = (bits + 7) / 8;
+  ensure(s->kb0, k * sizeof(uint64_t));
+  ensure(s->kb1, k * sizeof(uint64_t));
+  ensure(s->fz_v0, k * sizeof(uint32_t));
+  ensure(s->fz_v1, k * sizeof(uint32_t));
+  ensure(s->fz_byte, k);
+  hipLaunchKernelGGL((k_fill<uint8_t>), dim3(grid_for(k, 256, 4096)), dim3(256), 0, st, s->fz_byte.as<uint8_t>(), k,
+                     (uint8_t)0);  // the first pass's values are the positions
+  const uint32_t nblk = (uint32_t)((k + kSortTile - 1) / kSortTile);
+  ensure(s->cnt, ((uint64_t)nblk * 256 + 1) * sizeof(uint32_t));
+  ensure(s->koff, ((uint64_t)nblk * 256 + 1) * sizeof(uint32_t));
+  const uint64_t* kin = src;
+  const uint32_t* vin = nullptr;
+  for (int p = 0; p < passes; p++) {
+    uint64_t* kout = (p & 1) ? s->kb1.as<uint64_t>() : s->kb0.as<uint64_t>();
+    uint32_t* vout = (p & 1) ? s->fz_v1.as<uint32_t>() : s->fz_v0.as<uint32_t>();
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, st, kin, (uint32_t)k, 8 * p,
+                       s->cnt.as<uint32_t>());
+    HIPCHK(hipGetLastError());
+    scan<uint32_t>(s, s->koff.as<uint32_t>(), (uint64_t)nblk * 256, st, LoadFn<uint32_t>{s->cnt.as<uint32_t>()});
+    hipLaunchKernelGGL(k_radix_scatter_kv, dim3(nblk), dim3(kSortThreads), 0, st, kin, kout, (uint32_t)k, 8 * p,
+                       (const uint32_t*)s->koff.as<uint32_t>(), vin, (const uint8_t*)s->fz_byte.as<uint8_t>(), vout);
+    HIPCHK(hipGetLastError());
+    kin = kout;
+    vin = vout;
+  }
+  ensure(s->segpos, (k + 1) * sizeof(uint32_t));
+  ensure(s->kdedup, k * sizeof(uint64_t));
+  ensure(s->kvdedup, k * sizeof(uint64_t));
+  scan<uint32_t>(s, s->segpos.as<uint32_t>(), k, st, FirstFlag{kin});
+  hipLaunchKernelGGL(k_kv_compact, dim3(grid_for(k, 256)), dim3(256), 0, st, kin, vin, k,
+                     (const uint32_t*)s->segpos.as<uint32_t>(), vsrc, s->kdedup.as<uint64_t>(),
+                     s->kvdedup.as<uint64_t>(), &s->dctr->kprime);
+  HIPCHK(hipGetLastError());
+  phase_end(s, pm, st, (16ull * passes + 28) * k);
+  return s->kdedup.as<uint64_t>();
+}
+
 size_t heavy_smem(uint32_t S, uint32_t cap) { return HeavyLayout(S, cap).total; }
 
 // ---------------------------------------------------------------------------
@@ -443,6 +519,7 @@ WinArgs upload_windows(cpma* s, const std::vector<uint64_t>& src_begin, const st
   wa.dst_flat = d + 4 * (W + 1);
   wa.level = reinterpret_cast<const uint32_t*>(d + 6 * (W + 1));
   wa.raw = s->cfg.uncompressed ? 1u : 0u;
+  wa.vbytes = s->kv() ? 8u : 0u;
   return wa;
 }
 
@@ -453,6 +530,7 @@ SrcLeaves src_leaves(cpma* s) {
   sl.ovf = s->ovf.as<uint64_t>();
   sl.arena = s->arena.as<uint8_t>();
   sl.S = s->S;
+  sl.clen = s->clen.as<uint32_t>();
   return sl;
 }
 
@@ -473,9 +551,10 @@ uint64_t pack_windows(cpma* s, const WinArgs& wa, uint64_t nsrc, hipStream_t st)
   ensure(s->stage, std::max<uint64_t>(K, 1) * sizeof(uint64_t));
   ensure(s->win_id, std::max<uint64_t>(K, 1) * sizeof(uint32_t));
   ensure(s->ccost, std::max<uint64_t>(K, 1));
+  if (s->kv()) ensure(s->vstage, std::max<uint64_t>(K, 1) * sizeof(uint64_t));
   hipLaunchKernelGGL(k_win_pack, dim3(grid_for(nsrc, 1, 1u << 20)), dim3(kWave), 0, st, wa, sl, nsrc,
                      (const uint64_t*)s->koff.as<uint64_t>(), s->stage.as<uint64_t>(), s->win_id.as<uint32_t>(),
-                     s->ccost.as<uint8_t>());
+                     s->ccost.as<uint8_t>(), s->kv() ? s->vstage.as<uint64_t>() : (uint64_t*)nullptr);
   HIPCHK(hipGetLastError());
   return K;
 }
@@ -533,11 +612,12 @@ void plan_spread(cpma* s, const WinArgs& wa, uint64_t nsrc, uint64_t K, uint64_t
 }
 
 void encode_spread(cpma* s, const WinArgs& wa, uint64_t ndst, uint8_t* dbytes, uint32_t* dused, uint64_t* dhead,
-                   hipStream_t st) {
+                   hipStream_t st, uint32_t* dclen = nullptr) {
   hipLaunchKernelGGL(k_leaf_encode, dim3(grid_for(ndst, 1, 1u << 20)), dim3(kWave), s->S, st, wa, ndst, s->S,
                      (const uint64_t*)s->welem.as<uint64_t>(), (const uint64_t*)s->lstart.as<uint64_t>(),
                      (const uint64_t*)s->stage.as<uint64_t>(), (const uint32_t*)s->planU.as<uint32_t>(), dbytes,
-                     dused, dhead);
+                     dused, dhead, s->kv() ? (const uint64_t*)s->vstage.as<uint64_t>() : (const uint64_t*)nullptr,
+                     dclen);
   HIPCHK(hipGetLastError());
 }
 
@@ -576,7 +656,8 @@ bool redistribute(cpma* s, std::vector<Win> wins, hipStream_t st, uint64_t* move
     bool any = false;
     for (uint32_t f : fails) any |= (f != 0);
     if (!any) {
-      encode_spread(s, wa, ndst, s->bytes.as<uint8_t>(), s->used.as<uint32_t>(), s->head.as<uint64_t>(), st);
+      encode_spread(s, wa, ndst, s->bytes.as<uint8_t>(), s->used.as<uint32_t>(), s->head.as<uint64_t>(), st,
+                    s->kv() ? s->clen.as<uint32_t>() : nullptr);
       // algorithmic bytes: every window leaf read (at most S) and rewritten
       // whole with its used count and head
       *moved = ndst * (2ull * s->S + 12);
@@ -598,6 +679,7 @@ void swap_in_spare(cpma* s, uint64_t Lt) {
   std::swap(s->bytes, s->spare_bytes);
   std::swap(s->used, s->spare_used);
   std::swap(s->head, s->spare_head);
+  if (s->kv()) std::swap(s->clen, s->spare_clen);
   s->L = Lt;
 }
 
@@ -610,6 +692,10 @@ void spread_fresh(cpma* s, uint64_t K, uint64_t Lt, hipStream_t st, bool costs_r
     ensure(s->spare_bytes, s->S);
     ensure(s->spare_used, 4);
     ensure(s->spare_head, 8);
+    if (s->kv()) {
+      ensure(s->spare_clen, 4);
+      hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, s->spare_clen.as<uint32_t>(), (uint64_t)1, 0u);
+    }
     hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(256), 0, st, s->spare_bytes.as<uint32_t>(),
                        (uint64_t)(s->S / 4), 0u);
     hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, s->spare_used.as<uint32_t>(), (uint64_t)1, 0u);
@@ -631,7 +717,7 @@ void spread_fresh(cpma* s, uint64_t K, uint64_t Lt, hipStream_t st, bool costs_r
                          (uint8_t)8);
     else
       hipLaunchKernelGGL(k_chain_costs, dim3(grid_for(K, 256, 1u << 16)), dim3(256), 0, st,
-                         (const uint64_t*)s->stage.as<uint64_t>(), K, s->ccost.as<uint8_t>());
+                         (const uint64_t*)s->stage.as<uint64_t>(), K, s->ccost.as<uint8_t>(), s->kv() ? 8u : 0u);
     HIPCHK(hipGetLastError());
   }
   // One window over all staged keys: its source is one flat entry, so the
@@ -654,8 +740,9 @@ void spread_fresh(cpma* s, uint64_t K, uint64_t Lt, hipStream_t st, bool costs_r
     if (fails[0] == 0) {
       ensure(s->spare_bytes, Lt * (uint64_t)s->S);
       ensure(s->spare_head, Lt * sizeof(uint64_t));
+      if (s->kv()) ensure(s->spare_clen, Lt * sizeof(uint32_t));
       encode_spread(s, wa, ndst, s->spare_bytes.as<uint8_t>(), s->spare_used.as<uint32_t>(),
-                    s->spare_head.as<uint64_t>(), st);
+                    s->spare_head.as<uint64_t>(), st, s->kv() ? s->spare_clen.as<uint32_t>() : nullptr);
       HIPCHK(hipStreamSynchronize(st));
       swap_in_spare(s, Lt);
       return;
@@ -680,7 +767,8 @@ void spread_fresh(cpma* s, uint64_t K, uint64_t Lt, hipStream_t st, bool costs_r
 // images into the spare arrays.  Returns the algorithmic bytes moved.
 // total_used: sum of the old used bytes (bounds the chain total from above).
 // Returns false, with nothing changed, when thresholds would overflow 64 bits.
-// Uncompressed leaves: a resize stages every key (one window over all leaves)
+// Uncompressed and key-value leaves: a resize stages every key (and value;
+// one window over all leaves)
 // and spreads them over a fresh array of about Lt leaves, which steps by the
 // growing factor until every node is within its bounds.  Returns the
 // algorithmic bytes moved through *moved.
@@ -691,13 +779,20 @@ bool raw_resize(cpma* s, uint64_t Lt, hipStream_t st, uint64_t* moved) {
   WinArgs wa = upload_windows(s, sb, sn, sb, sn, lv, st, nsrc, ndst);
   const uint64_t K = pack_windows(s, wa, nsrc, st);
   const uint64_t L0 = s->L;
+  if (s->kv() && K > 0) {
+    // the staged keys form one chain: every source leaf's head but the first
+    // costs its delta's code, not a head's 8 bytes
+    hipLaunchKernelGGL(k_chain_costs, dim3(grid_for(K, 256, 1u << 16)), dim3(256), 0, st,
+                       (const uint64_t*)s->stage.as<uint64_t>(), K, s->ccost.as<uint8_t>(), 8u);
+    HIPCHK(hipGetLastError());
+  }
   spread_fresh(s, K, std::max<uint64_t>(Lt, 1), st, true);
   *moved = 16ull * K + 12ull * (L0 + s->L);
   return true;
 }
 
 bool split_resize(cpma* s, uint64_t Lt, uint64_t total_used, hipStream_t st, uint64_t* moved) {
-  if (s->cfg.uncompressed) return raw_resize(s, Lt, st, moved);
+  if (s->cfg.uncompressed || s->kv()) return raw_resize(s, Lt, st, moved);
   const uint64_t L = s->L;
   // a head's chain cost can exceed its 8 bytes by 2 (64-bit distances)
   auto fits = [&](uint64_t lt) { return (__int128)(total_used + 2 * L + 16) * (lt + 1) < ((__int128)1 << 62); };
@@ -816,6 +911,7 @@ void reserve_growth(cpma* s) {
   ensure(s->spare_used, Ln * sizeof(uint32_t), room);
   ensure(s->spare_head, Ln * sizeof(uint64_t), room);
   ensure(s->spare_bytes, Ln * (uint64_t)s->S, room);
+  if (s->kv()) ensure(s->spare_clen, Ln * sizeof(uint32_t), room);
 }
 
 // Pyramid memory for Lx leaves; contents survive unless the buffer has to grow.
@@ -866,9 +962,13 @@ void reserve_after_merge(cpma* s, uint64_t k, bool insert) {
   reserve_pyramid(s, Lmax);
   ensure(s->win, Lmax * sizeof(uint64_t));
   ensure(s->scan_tmp, scan_scratch_elems(Lmax + 1) * sizeof(uint64_t));
-  if (s->cfg.uncompressed) {
-    // an uncompressed resize stages every key and spreads it afresh
+  if (s->cfg.uncompressed || s->kv()) {
+    // an uncompressed or key-value resize stages every key and spreads it afresh
     const uint64_t K = std::max<uint64_t>(1, s->n + (insert ? k : 0));
+    if (s->kv()) {
+      ensure(s->vstage, K * sizeof(uint64_t));
+      ensure(s->spare_clen, Lmax * sizeof(uint32_t), room);
+    }
     ensure(s->cnt, std::max<uint64_t>(L, 1) * sizeof(uint64_t));
     ensure(s->koff, (L + 1) * sizeof(uint64_t));
     ensure(s->stage, K * sizeof(uint64_t));
@@ -1101,11 +1201,18 @@ void reserve_batch(cpma* s, uint64_t kbound, bool insert) {
   ensure(s->ovf, std::max<uint64_t>(L, 1) * sizeof(uint64_t));
   // overflow arena: segment s owns s * (S + 16) + 16 * (its first batch index)
   // onwards (a leaf that outgrows S holds at most S + 10 bytes per new key)
-  const uint64_t arena_cap = insert ? std::min<uint64_t>(L, kbound) * (uint64_t)(s->S + 16) + 16 * kbound + 256 : 256;
+  const uint64_t arena_cap =
+      insert ? std::min<uint64_t>(L, kbound) * (uint64_t)(s->S + 16) + (s->kv() ? 32 : 16) * kbound + 256 : 256;
   ensure(s->arena, arena_cap, 1.0);
   // heavy-merge staging: only slices of more than kHeavyLds keys stage, each at
   // most its own keys plus one leaf's keys
-  const uint64_t stage_cap = insert ? kbound + (kbound / kHeavyLds + 1) * (uint64_t)s->S + 64 : 64;
+  uint64_t stage_cap = insert ? kbound + (kbound / kHeavyLds + 1) * (uint64_t)s->S + 64 : 64;
+  if (s->kv()) {
+    // key-value merges stage a merged leaf of more than kKvLds keys: its new
+    // keys (more than kKvLds - kKvOld) plus at most kKvOld old ones
+    stage_cap = insert ? 2 * kbound + 2 * kKvLds : 64;
+    ensure(s->vstage, stage_cap * sizeof(uint64_t));
+  }
   ensure(s->stage, stage_cap * sizeof(uint64_t));
   ensure(s->parts, 16ull * merge_grids(s, kbound).part_slots);
   ensure(s->scan_tmp, scan_scratch_elems(kl + 1) * sizeof(uint64_t));
@@ -1149,7 +1256,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
                        (const uint64_t*)s->head.as<uint64_t>(), L, B, s->dctr);
   }
   HIPCHK(hipGetLastError());
-  if (s->S <= kWaveMaxS && !small && !s->cfg.uncompressed) {
+  if (s->S <= kWaveMaxS && !small && !s->cfg.uncompressed && !s->kv()) {
     // route segments: narrow (32-bit wave merge), wide (64-bit), long insert slices
     // (spill list: heavy merge)
     const uint64_t nseg = std::min<uint64_t>(kbound, L);
@@ -1178,6 +1285,10 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   a.ctr = s->dctr;
   a.S = s->S;
   a.is_insert = insert ? 1 : 0;
+  a.kv = s->kv() ? 1u : 0u;
+  a.clen = s->clen.as<uint32_t>();
+  a.Bv = insert ? s->batch_vals : nullptr;
+  a.vstage = s->vstage.as<uint64_t>();
   const MergeGrids mg = merge_grids(s, kbound);
   const uint32_t lgrid = mg.lgrid, wgrid = mg.wgrid, lwaves = mg.lwaves, hgrid_spill = mg.hgrid_spill;
   // per-wave totals: each launch owns a run of slot pairs, main-merge launches
@@ -1198,6 +1309,12 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
     // uncompressed leaves: one wave per touched leaf, any slice length
     a.part = slots(wgrid, true);
     hipLaunchKernelGGL(k_pma_merge, dim3(wgrid), dim3(kWave), 0, st, a);
+    HIPCHK(hipGetLastError());
+    phase_end(s, pmg, st);
+  } else if (s->kv()) {
+    // key-value leaves: one wave per touched leaf, any slice length
+    a.part = slots(wgrid, true);
+    hipLaunchKernelGGL(k_kv_merge, dim3(wgrid), dim3(kWave), s->S, st, a);
     HIPCHK(hipGetLastError());
     phase_end(s, pmg, st);
   } else if (small && s->S <= kWaveMaxS) {
@@ -1273,7 +1390,7 @@ uint64_t apply_small(cpma* s, const uint64_t* src, uint64_t k, bool insert, hipS
 
 // Sorted repeat-free batch of k keys at device address B.  Zeroes the counters.
 uint64_t apply_sorted(cpma* s, const uint64_t* B, uint64_t k, bool insert, hipStream_t st) {
-  if (k <= kSmallBatch) return apply_small(s, B, k, insert, st);
+  if (k <= kSmallBatch && !s->kv()) return apply_small(s, B, k, insert, st);
   zero_counters(s, st);
   hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(64), 0, st, &s->dctr->kprime, (uint64_t)1,
                      (unsigned long long)k);
@@ -1293,6 +1410,8 @@ cpma_status check_config(const cpma_config& c) {
   if (!(c.build_density > c.lo_root && c.build_density < c.up_root)) return CPMA_ERR_INVALID;
   if (!(c.rebuild_frac > 0)) return CPMA_ERR_INVALID;
   if (c.uncompressed != 0 && c.uncompressed != 1) return CPMA_ERR_INVALID;
+  if (c.values != 0 && c.values != 1) return CPMA_ERR_INVALID;
+  if (c.values && c.uncompressed) return CPMA_ERR_INVALID;  // key-value leaves are compressed ones
   return CPMA_OK;
 }
 
@@ -1335,6 +1454,7 @@ cpma_status cpma_config_default(cpma_config* cfg) {
   cfg->range_chunk = 8;
   cfg->rebuild_frac = 1.0;
   cfg->uncompressed = 0;
+  cfg->values = 0;
   cfg->alloc = nullptr;
   cfg->free = nullptr;
   cfg->ctx = nullptr;
@@ -1352,11 +1472,11 @@ const char* cpma_status_str(cpma_status s) {
   return "unknown status";
 }
 
-cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpma_config* cfg_in, void* stream,
-                       cpma** out) {
+static cpma_status build_impl(const uint64_t* keys, const uint64_t* vals, uint64_t n, cpma_mem mem,
+                              const cpma_config* cfg_in, void* stream, cpma** out, bool with_values) {
   if (!out) return CPMA_ERR_INVALID;
   *out = nullptr;
-  if (n > 0 && !keys) return CPMA_ERR_INVALID;
+  if (n > 0 && (!keys || (with_values && !vals))) return CPMA_ERR_INVALID;
   cpma_config cfg;
   cpma_config_default(&cfg);
   if (cfg_in) {
@@ -1370,10 +1490,12 @@ cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpm
     if (cfg_in->range_chunk) cfg.range_chunk = cfg_in->range_chunk;
     if (cfg_in->rebuild_frac > 0) cfg.rebuild_frac = cfg_in->rebuild_frac;
     cfg.uncompressed = cfg_in->uncompressed;
+    cfg.values = cfg_in->values;
     cfg.alloc = cfg_in->alloc;
     cfg.free = cfg_in->free;
     cfg.ctx = cfg_in->ctx;
   }
+  if (with_values) cfg.values = 1;
   cpma_status cs = check_config(cfg);
   if (cs != CPMA_OK) return cs;
   cpma* s = new cpma();
@@ -1399,11 +1521,15 @@ cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpm
     zero_counters(s, st);
     uint64_t K = 0;
     if (n > 0) {
-      const uint64_t* B = prepare_batch(s, keys, n, mem, st);
+      const uint64_t* B = s->kv() ? kv_prepare(s, keys, vals, n, mem, st) : prepare_batch(s, keys, n, mem, st);
       read_counters(s, st);
       K = s->hctr->kprime;
       ensure(s->stage, std::max<uint64_t>(K, 1) * sizeof(uint64_t));
       HIPCHK(hipMemcpyAsync(s->stage.p, B, K * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+      if (s->kv()) {
+        ensure(s->vstage, std::max<uint64_t>(K, 1) * sizeof(uint64_t));
+        HIPCHK(hipMemcpyAsync(s->vstage.p, s->kvdedup.p, K * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+      }
     }
     s->n = K;
     uint64_t Lt = 1;
@@ -1416,7 +1542,8 @@ cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpm
                            K, (uint8_t)8);
       else
         hipLaunchKernelGGL(k_chain_costs, dim3(grid_for(K, 256, 1u << 16)), dim3(256), 0, st,
-                           (const uint64_t*)s->stage.as<uint64_t>(), K, s->ccost.as<uint8_t>());
+                           (const uint64_t*)s->stage.as<uint64_t>(), K, s->ccost.as<uint8_t>(),
+                           s->kv() ? 8u : 0u);
       HIPCHK(hipGetLastError());
       ensure(s->P, (K + 1) * sizeof(uint64_t));
       scan<uint64_t>(s, s->P.as<uint64_t>(), K, st, U8Fn{s->ccost.as<uint8_t>()});
@@ -1437,6 +1564,18 @@ cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpm
   return CPMA_OK;
 }
 
+cpma_status cpma_build(const uint64_t* keys, uint64_t n, cpma_mem mem, const cpma_config* cfg, void* stream,
+                       cpma** out) {
+  return build_impl(keys, nullptr, n, mem, cfg, stream, out, false);
+}
+
+cpma_status cpma_build_kv(const uint64_t* keys, const uint64_t* values, uint64_t n, cpma_mem mem,
+                          const cpma_config* cfg, void* stream, cpma** out) {
+  if (out) *out = nullptr;
+  if (cfg && cfg->uncompressed) return CPMA_ERR_INVALID;
+  return build_impl(keys, values, n, mem, cfg, stream, out, true);
+}
+
 static cpma_status update(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem mem, int sorted, void* stream,
                           uint64_t* delta_out, bool insert) {
   (void)sorted;  // sortedness is checked on the device either way
@@ -1449,7 +1588,7 @@ static cpma_status update(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem me
   uint64_t delta = 0;
   cpma_status r = guarded(s, [&] {
     HIPCHK(hipSetDevice(s->device));
-    if (k <= kSmallBatch) {
+    if (k <= kSmallBatch && !s->kv()) {
       const uint64_t* src = keys;
       if (mem == CPMA_MEM_HOST) {
         ensure(s->kin, k * sizeof(uint64_t));
@@ -1478,11 +1617,50 @@ cpma_status cpma_delete_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
   return update(s, keys, k, mem, sorted, stream, n_removed, false);
 }
 
+cpma_status cpma_insert_kv(cpma* s, const uint64_t* keys, const uint64_t* values, uint64_t k, cpma_mem mem,
+                           void* stream, uint64_t* n_added) {
+  if (n_added) *n_added = 0;
+  if (!s || !s->kv()) return CPMA_ERR_INVALID;
+  if (s->broken) return CPMA_ERR_DEVICE;
+  if (k == 0) return CPMA_OK;
+  if (!keys || !values || k >= (1ull << 31)) return CPMA_ERR_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  uint64_t delta = 0;
+  cpma_status r = guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    zero_counters(s, st);
+    const uint64_t* B = kv_prepare(s, keys, values, k, mem, st);
+    s->batch_vals = s->kvdedup.as<uint64_t>();
+    try {
+      delta = apply_batch(s, B, k, true, st, false, wants_rebuild(s, k));
+    } catch (...) {
+      s->batch_vals = nullptr;
+      throw;
+    }
+    s->batch_vals = nullptr;
+    resolve_phases(s);
+  });
+  if (r == CPMA_OK && n_added) *n_added = delta;
+  return r;
+}
+
+cpma_status cpma_export_code_bytes(const cpma* cs, uint32_t* clen, void* stream) {
+  cpma* s = const_cast<cpma*>(cs);
+  if (!s || !clen || !s->kv()) return CPMA_ERR_INVALID;
+  if (s->broken) return CPMA_ERR_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  return guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    HIPCHK(hipMemcpyAsync(clen, s->clen.p, s->L * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
 static QueryArgs query_args(const cpma* s);
 
 cpma_status cpma_apply_updates(cpma* s, uint32_t nreq, const int32_t* kind, const uint64_t* const* keys,
                                const uint64_t* n, cpma_mem mem, uint64_t* result, void* stream) {
-  if (!s || (nreq && (!kind || !keys || !n || !result)) || s->cfg.uncompressed) return CPMA_ERR_INVALID;
+  if (!s || (nreq && (!kind || !keys || !n || !result)) || s->cfg.uncompressed || s->kv()) return CPMA_ERR_INVALID;
   if (s->broken) return CPMA_ERR_DEVICE;
   uint64_t m = 0;
   for (uint32_t r = 0; r < nreq; r++) {
@@ -1668,17 +1846,21 @@ static QueryArgs query_args(const cpma* s) {
   QueryArgs a;
   a.head = (const uint64_t*)s->head.p;
   a.bytes = (const uint8_t*)s->bytes.p;
-  a.used = (const uint32_t*)s->used.p;
+  a.used = s->code_bytes();
   a.L = s->L;
   a.S = s->S;
   a.raw = s->cfg.uncompressed ? 1u : 0u;
+  a.fill = (const uint32_t*)s->used.p;
+  a.vals = 0;
   return a;
 }
 
-cpma_status cpma_range_map(const cpma* cs, const uint64_t* lo, const uint64_t* hi, uint64_t q, cpma_mem mem,
-                           uint64_t* sum, uint64_t* count, void* stream) {
+// values: sum the values of key-value leaves instead of the keys.
+static cpma_status range_map_impl(const cpma* cs, const uint64_t* lo, const uint64_t* hi, uint64_t q, cpma_mem mem,
+                                  uint64_t* sum, uint64_t* count, void* stream, bool values) {
   cpma* s = const_cast<cpma*>(cs);
   if (!s) return CPMA_ERR_INVALID;
+  if (values && !s->kv()) return CPMA_ERR_INVALID;
   if (s->broken) return CPMA_ERR_DEVICE;
   if (q == 0) return CPMA_OK;
   if (!lo || !hi || !sum || !count) return CPMA_ERR_INVALID;
@@ -1687,6 +1869,7 @@ cpma_status cpma_range_map(const cpma* cs, const uint64_t* lo, const uint64_t* h
     HIPCHK(hipSetDevice(s->device));
     QueryArgs a = query_args(s);
     a.q = q;
+    a.vals = values ? 1u : 0u;
     unsigned long long* dsum = (unsigned long long*)sum;
     unsigned long long* dcount = (unsigned long long*)count;
     if (mem == CPMA_MEM_HOST) {
@@ -1709,7 +1892,8 @@ cpma_status cpma_range_map(const cpma* cs, const uint64_t* lo, const uint64_t* h
     ensure(s->qvoff, (q + 1) * 8);
     PhaseMark pq = phase_begin(s, CPMA_PHASE_QUERY, st);
     // statistics: one byte-count slot per wave of the end and interior kernels
-    const bool wave_ends = q <= (uint64_t)s->num_cus * 64;  // few queries: a wave per query
+    // few queries: a wave per query (key sums only)
+    const bool wave_ends = q <= (uint64_t)s->num_cus * 64 && !values;
     const uint32_t egrid = wave_ends ? grid_for(q, 1, (uint32_t)s->num_cus * 64)
                                      : grid_for(q, 256, (uint32_t)s->num_cus * 16);
     const uint64_t ewaves = wave_ends ? egrid : 4ull * egrid;
@@ -1744,6 +1928,51 @@ cpma_status cpma_range_map(const cpma* cs, const uint64_t* lo, const uint64_t* h
       HIPCHK(hipMemcpyAsync(count, dcount, q * 8, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       resolve_phases(s);
+    }
+  });
+}
+
+cpma_status cpma_range_map(const cpma* cs, const uint64_t* lo, const uint64_t* hi, uint64_t q, cpma_mem mem,
+                           uint64_t* sum, uint64_t* count, void* stream) {
+  return range_map_impl(cs, lo, hi, q, mem, sum, count, stream, false);
+}
+
+cpma_status cpma_range_map_values(const cpma* cs, const uint64_t* lo, const uint64_t* hi, uint64_t q, cpma_mem mem,
+                                  uint64_t* vsum, uint64_t* count, void* stream) {
+  return range_map_impl(cs, lo, hi, q, mem, vsum, count, stream, true);
+}
+
+cpma_status cpma_get(const cpma* cs, const uint64_t* keys, uint64_t q, cpma_mem mem, uint64_t* values,
+                     uint8_t* found, void* stream) {
+  cpma* s = const_cast<cpma*>(cs);
+  if (!s || !s->kv()) return CPMA_ERR_INVALID;
+  if (s->broken) return CPMA_ERR_DEVICE;
+  if (q == 0) return CPMA_OK;
+  if (!keys || !values || !found) return CPMA_ERR_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  return guarded(s, [&] {
+    HIPCHK(hipSetDevice(s->device));
+    QueryArgs a = query_args(s);
+    a.q = q;
+    const uint64_t* dk = keys;
+    uint64_t* dv = values;
+    uint8_t* df = found;
+    if (mem == CPMA_MEM_HOST) {
+      ensure(s->qa, q * 8);
+      ensure(s->qsum, q * 8);
+      ensure(s->qout, q);
+      HIPCHK(hipMemcpyAsync(s->qa.p, keys, q * 8, hipMemcpyHostToDevice, st));
+      dk = s->qa.as<uint64_t>();
+      dv = s->qsum.as<uint64_t>();
+      df = s->qout.as<uint8_t>();
+    }
+    hipLaunchKernelGGL(k_kv_get, dim3(grid_for(q, 256, (uint32_t)s->num_cus * 16)), dim3(256), 0, st, a, dk, dv,
+                       df);
+    HIPCHK(hipGetLastError());
+    if (mem == CPMA_MEM_HOST) {
+      HIPCHK(hipMemcpyAsync(values, dv, q * 8, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(found, df, q, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
     }
   });
 }
@@ -1859,7 +2088,7 @@ cpma_status cpma_contains(const cpma* cs, const uint64_t* keys, uint64_t q, cpma
 static FgArgs fg_args(const cpma* s, uint32_t nv) {
   FgArgs g;
   g.bytes = (const uint8_t*)s->bytes.p;
-  g.used = (const uint32_t*)s->used.p;
+  g.used = s->code_bytes();
   g.head = (const uint64_t*)s->head.p;
   g.L = s->L;
   g.S = s->S;
@@ -2108,7 +2337,7 @@ cpma_status cpma_fgraph_pagerank(const cpma* cs, uint32_t nv, int iters, double 
 
 uint64_t cpma_size(const cpma* s) { return s ? s->n : 0; }
 
-uint64_t cpma_bytes(const cpma* s) { return s ? s->L * ((uint64_t)s->S + 8 + 4) : 0; }
+uint64_t cpma_bytes(const cpma* s) { return s ? s->L * ((uint64_t)s->S + 8 + 4 + (s->kv() ? 4 : 0)) : 0; }
 
 uint64_t cpma_bytes_held(const cpma* cs) {
   if (!cs) return 0;
@@ -2126,16 +2355,17 @@ cpma_status cpma_trim(cpma* s, void* stream) {
     return CPMA_ERR_DEVICE;
   }
   // the structure and the small counters the handle's pointers refer to stay
-  const DevBuf* keep[] = {&s->bytes, &s->used, &s->head, &s->ctr_buf, &s->info_buf, &s->qalg_buf};
+  const DevBuf* keep[] = {&s->bytes, &s->used, &s->head, &s->clen, &s->ctr_buf, &s->info_buf, &s->qalg_buf};
   for (DevBuf* b : s->bufs()) {
     if (std::find(std::begin(keep), std::end(keep), b) != std::end(keep)) continue;
     release(*b);
   }
   // the leaf arrays keep the room of the growth that made them: copy each to
   // a fitting allocation (an array stays as it is if that allocation fails)
-  const size_t fit[3] = {(size_t)(s->L * (uint64_t)s->S), (size_t)(s->L * 4), (size_t)(s->L * 8)};
-  DevBuf* arr[3] = {&s->bytes, &s->used, &s->head};
-  for (int i = 0; i < 3; i++) {
+  const size_t fit[4] = {(size_t)(s->L * (uint64_t)s->S), (size_t)(s->L * 4), (size_t)(s->L * 8),
+                         (size_t)(s->L * 4)};
+  DevBuf* arr[4] = {&s->bytes, &s->used, &s->head, &s->clen};
+  for (int i = 0; i < (s->kv() ? 4 : 3); i++) {
     const size_t want = fit[i] + 256;
     if (arr[i]->cap <= want) continue;
     void* p = nullptr;
@@ -2306,7 +2536,7 @@ extern "C" cpma_status cpma_autotune(const uint64_t* keys, uint64_t n, cpma_mem 
     cfg.build_density = base->build_density > 0 ? base->build_density : cfg.up_root / cfg.grow;
     if (base->range_chunk) cfg.range_chunk = base->range_chunk;
     if (base->rebuild_frac > 0) cfg.rebuild_frac = base->rebuild_frac;
-    if (base->uncompressed) return CPMA_ERR_INVALID;  // the tuner times the compressed leaves
+    if (base->uncompressed || base->values) return CPMA_ERR_INVALID;  // the tuner times key-only CPMA leaves
   }
   cpma_status cs = check_config(cfg);
   if (cs != CPMA_OK) return cs;

@@ -12,6 +12,7 @@
 #pragma once
 #include "scan_lane.hpp"
 #include "update.hpp"
+#include "kv.hpp"
 
 namespace cpma_dev {
 
@@ -25,12 +26,23 @@ struct QueryArgs {
   uint64_t L;
   uint32_t S;
   uint32_t raw;  // uncompressed leaves (raw 8-byte keys)
+  // key-value leaves: `used` above is each leaf's code bytes, `fill` its filled
+  // bytes (codes and values); vals: sum values instead of keys
+  const uint32_t* fill;
+  uint32_t vals;
 };
+
+// The values of a key-value leaf (m = (fill - codes) / 8 words at its end).
+__device__ __forceinline__ const uint64_t* leaf_vals(const QueryArgs& a, uint64_t leaf, uint32_t codes) {
+  const uint32_t m = (a.fill[leaf] - codes) / 8;
+  return reinterpret_cast<const uint64_t*>(a.bytes + leaf * (uint64_t)a.S + a.S - 8u * m);
+}
 
 // Keys of [lo, hi) in one leaf, one lane, for either leaf format.
 __device__ __forceinline__ LeafSum leaf_range_any(const QueryArgs& a, uint64_t leaf, uint32_t used, uint64_t lo,
                                                   uint64_t hi) {
   const uint8_t* p = a.bytes + leaf * (uint64_t)a.S;
+  if (a.vals) return kv_leaf_values(p, used, leaf_vals(a, leaf, used), lo, hi);
   return a.raw ? raw_sum_range(p, used, lo, hi) : leaf_sum_range(p, used, lo, hi);
 }
 
@@ -192,9 +204,24 @@ __global__ void __launch_bounds__(256) k_rm_interior(QueryArgs a, const uint64_t
         const uint64_t h = a.head[leaf];
         const uint64_t span = a.head[leaf + 1] - h;  // interior leaves always have a successor
         const uint8_t* lp = a.bytes + leaf * (uint64_t)a.S;
-        const LeafSum r = a.raw                ? raw_sum_all(lp, u)
-                          : span < (1ull << 28) ? leaf_sum_fast(lp, u, h)
-                                                : leaf_sum_range(lp, u, 0, kNoKey);
+        LeafSum r;
+        if (a.vals) {
+          // the values: m 8-byte words ending at the leaf's end (8-byte aligned)
+          const uint32_t m = (a.fill[leaf] - u) / 8;
+          const uint64_t* w = reinterpret_cast<const uint64_t*>(lp + a.S - 8u * m);
+          uint64_t s0 = 0, s1 = 0;
+          uint32_t i = 0;
+          for (; i + 2 <= m; i += 2) {
+            s0 += w[i];
+            s1 += w[i + 1];
+          }
+          if (i < m) s0 += w[i];
+          r = LeafSum{s0 + s1, m};
+        } else {
+          r = a.raw                ? raw_sum_all(lp, u)
+              : span < (1ull << 28) ? leaf_sum_fast(lp, u, h)
+                                    : leaf_sum_range(lp, u, 0, kNoKey);
+        }
         s += r.sum;
         n += r.count;
         visited += u;
@@ -236,6 +263,21 @@ __global__ void __launch_bounds__(1024) k_fold_sum(const unsigned long long* __r
   if (threadIdx.x == 0) {
     for (int i = 1; i < (int)(blockDim.x / kWave); i++) t += red[i];
     atomicAdd(out, (unsigned long long)t);
+  }
+}
+
+// Values of key-value leaves: one lane per key -- locate the leaf, walk its
+// codes to the key; found[i] = whether it is present, val[i] its value (0 if not).
+__global__ void __launch_bounds__(256) k_kv_get(QueryArgs a, const uint64_t* __restrict__ keys,
+                                                uint64_t* __restrict__ val, uint8_t* __restrict__ found) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.q;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t x = keys[i];
+    const uint64_t leaf = locate_leaf(a.head, a.L, x);
+    const uint32_t codes = a.used[leaf];
+    const LeafSum r = kv_leaf_values(a.bytes + leaf * (uint64_t)a.S, codes, leaf_vals(a, leaf, codes), x, x + 1);
+    val[i] = r.sum;
+    found[i] = r.count ? 1 : 0;
   }
 }
 

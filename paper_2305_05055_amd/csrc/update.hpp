@@ -204,6 +204,11 @@ struct MergeArgs {
   unsigned long long* part;  // per wave of the launch: {keys added / removed, algorithmic bytes}
   uint32_t S;
   int is_insert;
+  // key-value leaves
+  uint32_t kv;               // every key carries an 8-byte value
+  uint32_t* clen;            // code bytes of every leaf
+  const uint64_t* Bv;        // the batch keys' values (insert; NULL: new keys get 0, present keys keep theirs)
+  uint64_t* vstage;          // values of staged merged leaves (beside stage)
 };
 
 // Arena region of segment s: s * (S + 16) + 16 * (its first batch index).  A
@@ -212,7 +217,9 @@ struct MergeArgs {
 // S + 10 * nb + 15 bytes: the regions are disjoint, 16-byte aligned and need
 // no shared cursor.
 __device__ __forceinline__ uint64_t arena_region(const MergeArgs& a, uint64_t s) {
-  return s * (uint64_t)(a.S + 16) + 16ull * a.seg_begin[s];
+  // a key-value leaf grows by at most 18 bytes per new key (code and value);
+  // 32 per key keeps the regions 16-byte aligned
+  return s * (uint64_t)(a.S + 16) + (a.kv ? 32ull : 16ull) * a.seg_begin[s];
 }
 
 // Sums the per-wave parts of the merge launches into the counters: the first
@@ -424,6 +431,7 @@ struct WinArgs {
   const uint64_t* dst_flat;  // W + 1
   const uint32_t* level;     // window height (subtree check bound)
   uint32_t raw;              // uncompressed leaves (raw 8-byte keys)
+  uint32_t vbytes;           // 8 when every key carries a value, else 0
 };
 
 __device__ __forceinline__ uint32_t find_window(const uint64_t* flat, uint32_t W, uint64_t f) {
@@ -436,10 +444,18 @@ struct SrcLeaves {
   const uint64_t* ovf;
   const uint8_t* arena;
   uint32_t S;
+  const uint32_t* clen;  // key-value leaves: code bytes (used counts codes and values)
   __device__ const uint8_t* ptr(uint64_t leaf, uint32_t u) const {
     return u > S ? arena + ovf[leaf] : bytes + leaf * (uint64_t)S;
   }
 };
+
+// Key-value leaves: the key codes from byte 0 (clen bytes), the m values as
+// 8-byte words in key order at the end of the leaf (an overflow copy in the
+// arena keeps them right after the codes, from the next 8-byte boundary).
+__device__ __forceinline__ const uint8_t* kv_values(const uint8_t* base, uint32_t u, uint32_t clen, uint32_t S) {
+  return u > S ? base + ((clen + 7u) & ~7u) : base + S - (u - clen);
+}
 
 __global__ void __launch_bounds__(kWave) k_win_count(WinArgs wa, SrcLeaves src, uint64_t nflat,
                                                      uint64_t* __restrict__ cnt) {
@@ -447,7 +463,7 @@ __global__ void __launch_bounds__(kWave) k_win_count(WinArgs wa, SrcLeaves src, 
     const uint32_t w = find_window(wa.src_flat, wa.W, f);
     const uint64_t leaf = wa.src_begin[w] + (f - wa.src_flat[w]);
     const uint32_t u = src.used[leaf];
-    const uint32_t c = wa.raw ? u / 8 : wave_count_keys(src.ptr(leaf, u), u);
+    const uint32_t c = wa.raw ? u / 8 : (wa.vbytes ? (u - src.clen[leaf]) / 8 : wave_count_keys(src.ptr(leaf, u), u));
     if (lane_id() == 0) cnt[f] = c;
   }
 }
@@ -459,7 +475,8 @@ __global__ void __launch_bounds__(kWave) k_win_pack(WinArgs wa, SrcLeaves src, u
                                                     const uint64_t* __restrict__ koff,
                                                     uint64_t* __restrict__ stage,
                                                     uint32_t* __restrict__ win_id,
-                                                    uint8_t* __restrict__ ccost) {
+                                                    uint8_t* __restrict__ ccost,
+                                                    uint64_t* __restrict__ vstage = nullptr) {
   for (uint64_t f = blockIdx.x; f < nflat; f += gridDim.x) {
     const uint32_t w = find_window(wa.src_flat, wa.W, f);
     const uint64_t leaf = wa.src_begin[w] + (f - wa.src_flat[w]);
@@ -474,6 +491,19 @@ __global__ void __launch_bounds__(kWave) k_win_pack(WinArgs wa, SrcLeaves src, u
         wid[i] = w;
         cc[i] = 8;
       }
+      continue;
+    }
+    if (wa.vbytes) {
+      const uint32_t cl = src.clen[leaf];
+      const uint8_t* base = src.ptr(leaf, u);
+      const uint64_t* vals = reinterpret_cast<const uint64_t*>(kv_values(base, u, cl, src.S));
+      uint64_t* vo = vstage + koff[f];
+      for (uint32_t i = lane_id(); i < (u - cl) / 8; i += kWave) vo[i] = vals[i];
+      wave_decode_leaf(base, cl, [&](uint32_t i, uint64_t x, uint64_t d) {
+        out[i] = x;
+        wid[i] = w;
+        cc[i] = (uint8_t)((i == 0 ? 8u : vlen(d)) + 8u);
+      });
       continue;
     }
     wave_decode_leaf(src.ptr(leaf, u), u, [&](uint32_t i, uint64_t x, uint64_t d) {
@@ -494,15 +524,16 @@ __global__ void k_head_costs(WinArgs wa, uint64_t nflat, const uint64_t* __restr
     const uint64_t e = koff[f];
     if (koff[f + 1] == e) continue;
     const uint32_t w = find_window(wa.src_flat, wa.W, f);
-    if (e != welem[w]) ccost[e] = (uint8_t)vlen(x[e] - x[e - 1]);
+    if (e != welem[w]) ccost[e] = (uint8_t)(vlen(x[e] - x[e - 1]) + wa.vbytes);
   }
 }
 
 // Chain costs of a sorted key array that forms a single window.
-__global__ void k_chain_costs(const uint64_t* __restrict__ x, uint64_t K, uint8_t* __restrict__ ccost) {
+__global__ void k_chain_costs(const uint64_t* __restrict__ x, uint64_t K, uint8_t* __restrict__ ccost,
+                              uint32_t vbytes = 0) {
   for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < K;
        e += (uint64_t)gridDim.x * blockDim.x)
-    ccost[e] = e == 0 ? (uint8_t)8 : (uint8_t)vlen(x[e] - x[e - 1]);
+    ccost[e] = (uint8_t)((e == 0 ? 8u : vlen(x[e] - x[e - 1])) + vbytes);
 }
 
 struct U8Fn {
@@ -543,7 +574,7 @@ __global__ void k_assign(WinArgs wa, uint64_t K, const uint8_t* __restrict__ cco
       if (j > jp + 1) atomicOr(&fail[w], 2u);
     }
     if (e + 1 == end && j != n - 1) atomicOr(&fail[w], 2u);
-    ncost[e] = head ? (uint8_t)8 : ccost[e];
+    ncost[e] = head ? (uint8_t)(8 + wa.vbytes) : ccost[e];
     if (head) lstart[wa.dst_flat[w] + j] = e;
   }
 }
@@ -631,7 +662,9 @@ __global__ void __launch_bounds__(kWave) k_leaf_encode(WinArgs wa, uint64_t nfla
                                                        const uint32_t* __restrict__ planU,
                                                        uint8_t* __restrict__ dst_bytes,
                                                        uint32_t* __restrict__ dst_used,
-                                                       uint64_t* __restrict__ dst_head) {
+                                                       uint64_t* __restrict__ dst_head,
+                                                       const uint64_t* __restrict__ xv = nullptr,
+                                                       uint32_t* __restrict__ dst_clen = nullptr) {
   extern __shared__ __align__(16) uint8_t buf[];
   for (uint64_t fd = blockIdx.x; fd < nflat; fd += gridDim.x) {
     uint32_t w;
@@ -640,16 +673,22 @@ __global__ void __launch_bounds__(kWave) k_leaf_encode(WinArgs wa, uint64_t nfla
     wave_zero(buf, S);
     __syncthreads();
     const uint64_t* xs = x + s;
+    const uint32_t m = (uint32_t)(e - s);
     if (wa.raw) {
-      for (uint32_t i = lane_id(); i < (uint32_t)(e - s); i += kWave) reinterpret_cast<uint64_t*>(buf)[i] = xs[i];
+      for (uint32_t i = lane_id(); i < m; i += kWave) reinterpret_cast<uint64_t*>(buf)[i] = xs[i];
     } else {
-      wave_encode_bytes([&](uint32_t i) { return xs[i]; }, (uint32_t)(e - s), buf);
+      wave_encode_bytes([&](uint32_t i) { return xs[i]; }, m, buf);
+      if (wa.vbytes) {  // the values at the end of the leaf, in key order
+        uint64_t* vb = reinterpret_cast<uint64_t*>(buf + S - 8u * m);
+        for (uint32_t i = lane_id(); i < m; i += kWave) vb[i] = xv[s + i];
+      }
     }
     __syncthreads();
     wave_copy16(dst_bytes + d * (uint64_t)S, buf, S);
     if (lane_id() == 0) {
       dst_used[d] = planU[fd];
       dst_head[d] = xs[0];
+      if (wa.vbytes) dst_clen[d] = planU[fd] - 8u * m;
     }
     __syncthreads();
   }

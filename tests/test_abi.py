@@ -57,6 +57,14 @@ def test_host_only_calls_without_gpu():
     assert L.cpma_insert_batch(None, None, 1, 0, 0, None, None) == 1
     assert L.cpma_range_map_noalloc(None, None, None, 1, None, None, None) == 1
     assert L.cpma_trim(None, None) == 1
+    assert L.cpma_insert_kv(None, None, None, 1, 0, None, None) == 1
+    assert L.cpma_get(None, None, 1, 0, None, None, None) == 1
+    assert L.cpma_range_map_values(None, None, None, 1, 0, None, None, None) == 1
+    assert L.cpma_export_code_bytes(None, None, None) == 1
+    h = ctypes.c_void_p()
+    kv_unc = p.Config()
+    kv_unc.uncompressed = 1
+    assert L.cpma_build_kv(None, None, 0, 0, ctypes.byref(kv_unc), None, ctypes.byref(h)) == 1
     assert L.cpma_stats_enable(None, 1) == 1
     assert L.cpma_stats_select(None, 1 << 2) == 1
     L.cpma_destroy(None)
@@ -99,16 +107,18 @@ def test_struct_layouts_match_the_header(tmp_path):
     prog = tmp_path / "sizes.c"
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "cpma.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(cpma_config),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(cpma_config),"
         " offsetof(cpma_config, range_chunk), offsetof(cpma_config, alloc), offsetof(cpma_config, ctx),"
         " offsetof(cpma_config, rebuild_frac), offsetof(cpma_config, uncompressed),"
+        " offsetof(cpma_config, values),"
         " sizeof(cpma_tune_hint), sizeof(cpma_tune_report),"
         " offsetof(cpma_tune_report, best_chunk), sizeof(cpma_request), sizeof(cpma_phase_stat));return 0;}\n")
     exe = tmp_path / "sizes"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     want = [ctypes.sizeof(p.Config), p.Config.range_chunk.offset, p.Config.alloc.offset, p.Config.ctx.offset,
-            p.Config.rebuild_frac.offset, p.Config.uncompressed.offset, ctypes.sizeof(p.TuneHint),
+            p.Config.rebuild_frac.offset, p.Config.uncompressed.offset, p.Config.values.offset,
+            ctypes.sizeof(p.TuneHint),
             ctypes.sizeof(p.TuneReport), p.TuneReport.best_chunk.offset, ctypes.sizeof(p.Request),
             ctypes.sizeof(p.PhaseStat)]
     assert got == want

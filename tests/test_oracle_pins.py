@@ -558,3 +558,139 @@ def test_pma_checker_plants_rejected_for_their_reason(orc):
     img, used, head, keys = _pma_image(PMA_GOLDEN)
     code, msg = orc.check_image_pma(img, used, head, S, keys + np.uint64(1))
     assert code == 12, msg
+
+
+# ---- key-value sets: the oracle's upsert semantics and the leaf checker -------------
+def _kv_dict_replay(ops):
+    """Brute force with a Python dict: ('i', keys, vals) upserts (first
+    occurrence of a repeated key in a batch wins), ('d', keys) deletes."""
+    d = {}
+    counts = []
+    for op in ops:
+        if op[0] == "i":
+            seen = set()
+            added = 0
+            for k, v in zip(op[1].tolist(), op[2].tolist()):
+                if k in seen:
+                    continue
+                seen.add(k)
+                if k not in d:
+                    added += 1
+                d[k] = v
+            counts.append(added)
+        else:
+            removed = 0
+            for k in set(op[1].tolist()):
+                if k in d:
+                    del d[k]
+                    removed += 1
+            counts.append(removed)
+    return d, counts
+
+
+def test_kv_oracle_matches_dict_brute_force(orc):
+    rng = np.random.default_rng(5)
+    K = np.zeros(0, np.uint64)
+    V = np.zeros(0, np.uint64)
+    ops = []
+    got = []
+    for step in range(12):
+        if step % 3 == 2:
+            keys = rng.integers(0, 300, size=40, dtype=np.uint64)
+            ops.append(("d", keys))
+            K, V, r = orc.kv_delete(K, V, keys)
+        else:
+            keys = rng.integers(0, 300, size=60, dtype=np.uint64)
+            vals = rng.integers(0, 1 << 63, size=60, dtype=np.uint64)
+            ops.append(("i", keys, vals))
+            K, V, r = orc.kv_insert(K, V, keys, vals)
+        got.append(r)
+    d, counts = _kv_dict_replay(ops)
+    assert got == counts
+    assert K.tolist() == sorted(d) and V.tolist() == [d[k] for k in sorted(d)]
+    q = np.arange(0, 310, dtype=np.uint64)
+    val, found = orc.kv_get(K, V, q)
+    assert found.tolist() == [1 if int(x) in d else 0 for x in q]
+    assert val.tolist() == [d.get(int(x), 0) for x in q]
+    lo = rng.integers(0, 300, size=50, dtype=np.uint64)
+    hi = lo + rng.integers(0, 80, size=50, dtype=np.uint64)
+    vs, vc = orc.kv_range_values(K, V, lo, hi)
+    for a, b, s_, c_ in zip(lo.tolist(), hi.tolist(), vs.tolist(), vc.tolist()):
+        inside = [k for k in d if a <= k < b]
+        assert c_ == len(inside) and s_ == sum(d[k] for k in inside) % (1 << 64)
+    # values equal to the keys: the value sums are the key sums of the set oracle
+    vs, vc = orc.kv_range_values(K, K, lo, hi)
+    ks, kc = orc.range_map(K, lo, hi)
+    assert np.array_equal(vs, ks) and np.array_equal(vc, kc)
+
+
+def _kv_image(leaves, S=64):
+    """Hand-built key-value image: per leaf (keys, values); the head as 8 bytes
+    LE, the deltas as LEB128 codes (all below 128 here, one byte each), the
+    values as 8-byte LE words at the end of the leaf."""
+    L = len(leaves)
+    img = np.zeros(L * S, dtype=np.uint8)
+    used = np.zeros(L, dtype=np.uint32)
+    clen = np.zeros(L, dtype=np.uint32)
+    head = np.full(L, np.iinfo(np.uint64).max, dtype=np.uint64)
+    for j, (ks, vs) in enumerate(leaves):
+        base = j * S
+        if not ks:
+            continue
+        img[base: base + 8] = np.frombuffer(int(ks[0]).to_bytes(8, "little"), dtype=np.uint8)
+        p = 8
+        for a, b in zip(ks, ks[1:]):
+            assert 0 < b - a < 128
+            img[base + p] = b - a
+            p += 1
+        m = len(ks)
+        for t, v in enumerate(vs):
+            o = base + S - 8 * m + 8 * t
+            img[o: o + 8] = np.frombuffer(int(v).to_bytes(8, "little"), dtype=np.uint8)
+        clen[j] = p
+        used[j] = p + 8 * m
+        head[j] = ks[0]
+    keys = np.array([k for ks, _ in leaves for k in ks], dtype=np.uint64)
+    vals = np.array([v for _, vs in leaves for v in vs], dtype=np.uint64)
+    return img, used, clen, head, keys, vals
+
+
+# Two leaves of 64 bytes, H = 1 (bounds 0.9 / 0.7 upper, 0.1 / 0.3 lower):
+# leaf 0 keys 100, 103, 110 (8 + 2 code bytes, 3 values: 34 bytes), leaf 1 keys
+# 200, 201 (8 + 1, 2 values: 25 bytes); leaves 0.53 and 0.39, root 59 / 128
+# = 0.46.
+KV_GOLDEN = [([100, 103, 110], [7, 1 << 40, 9]), ([200, 201], [0, 5])]
+
+
+def test_kv_checker_accepts_hand_built_image(orc):
+    img, used, clen, head, keys, vals = _kv_image(KV_GOLDEN)
+    assert used.tolist() == [34, 25] and clen.tolist() == [10, 9]
+    code, msg = orc.check_image_kv(img, used, clen, head, 64, keys, vals)
+    assert code == 0, msg
+
+
+def test_kv_checker_plants_rejected_for_their_reason(orc):
+    S = 64
+    img, used, clen, head, keys, vals = _kv_image(KV_GOLDEN)
+    code, msg = orc.check_image_kv(img, used, clen, head, S, keys, vals + np.uint64(1))
+    assert code == 18, msg                                    # a wrong value
+    u2 = used.copy()
+    u2[1] = 26
+    code, msg = orc.check_image_kv(img, u2, clen, head, S, keys, vals)
+    assert code == 17, msg                                    # used != codes + 8 per key
+    c2 = clen.copy()
+    c2[0] = 40
+    code, msg = orc.check_image_kv(img, used, c2, head, S, keys, vals)
+    assert code == 16, msg                                    # codes beyond used
+    i2 = img.copy()
+    i2[20] = 3                                                # between leaf 0's codes and values
+    code, msg = orc.check_image_kv(i2, used, clen, head, S, keys, vals)
+    assert code == 8 and "(0, 20)" in msg, msg
+    i2 = img.copy()
+    i2[9] = 0x80 | 7                                          # a code that runs into the gap
+    code, msg = orc.check_image_kv(i2, used, clen, head, S, keys, vals)
+    assert code == 5, msg
+    # a leaf above its bound: 6 keys (8 + 5 + 48 = 61 > 57.6 bytes)
+    img, used, clen, head, keys, vals = _kv_image([([1, 2, 3, 4, 5, 6], [0] * 6), ([200, 201], [0, 5])])
+    code, msg = orc.check_image_kv(img, used, clen, head, S, keys, vals)
+    assert code == 13 and "(0, 0)" in msg, msg
