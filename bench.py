@@ -414,6 +414,106 @@ def pma_section(cp, torch, base_dev, seed, k=10 ** 7, warm=2, steps=5, q=100_000
     return out
 
 
+def kv_section(cp, torch, base_dev, seed, k=10 ** 7, warm=2, steps=5, q=100_000, fg_scale=24, leaf_bytes=0):
+    """The key-value CPMA: the 1e8 uniform 40-bit keys with random 8-byte values.
+    Bytes per key; steps of an upsert of 1e7 fresh key-value pairs and a delete
+    of 1e7 present keys (as the headline); the same upsert on present keys
+    (value overwrites); get of 1e6 keys; range_map_values of q Zipf(1.2)
+    exact-count queries.  Then a weighted F-Graph: the R-MAT graph of the
+    F-Graph section with random edge weights, and every vertex's weighted
+    degree (one range_map_values query per vertex)."""
+    n0 = int(base_dev.numel())
+    vals = synth.uniform_keys_torch(n0, seed, "cuda", bits=64)
+    keys_sorted = torch.unique(base_dev).cpu().numpy().view(np.uint64)
+    lens = synth.zipf_lengths(q, seed + 1, alpha=1.2, lmax=10 ** 6)
+    lo, hi = synth.range_queries_by_count(keys_sorted, lens, seed + 2)
+    first_del = to_dev(keys_sorted[synth.sample_indices(len(keys_sorted), k, seed + 3)])
+    probe = to_dev(np.concatenate([keys_sorted[synth.sample_indices(len(keys_sorted), 500000, seed + 4)],
+                                   synth.uniform_keys(500000, seed + 5)]))
+    over = to_dev(keys_sorted[synth.sample_indices(len(keys_sorted), k, seed + 6)])
+    del keys_sorted
+    dlo, dhi = to_dev(lo), to_dev(hi)
+    ins = [to_dev(synth.uniform_keys(k, seed + 7, offset=(i + 90) * k)) for i in range(warm + steps)]
+    ivals = synth.uniform_keys_torch(k, seed + 8, "cuda", bits=64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c = cp.CPMA(base_dev, values=vals, leaf_bytes=leaf_bytes)
+    torch.cuda.synchronize()
+    out = {"n0": n0, "batch": k, "steps": steps, "build_s": time.perf_counter() - t0,
+           "bytes_per_key": c.bytes() / c.size(), "leaf_bytes": c.geometry()[1], "leaves": c.geometry()[0],
+           "layout": "keys delta-coded as in the CPMA, 8-byte values at each leaf's end"}
+    for i in range(warm):
+        c.insert_kv(ins[i], ivals)
+        c.delete_batch(first_del if i == 0 else ins[i - 1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(warm, warm + steps):
+        c.insert_kv(ins[i], ivals)
+        c.delete_batch(ins[i - 1])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["upsert_delete_keys_s"] = 2 * k * steps / dt
+    out["ms_per_step"] = dt / steps * 1e3
+    c.insert_kv(over, ivals)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        c.insert_kv(over, ivals)
+    torch.cuda.synchronize()
+    out["overwrite_1e7_present_keys_s"] = 3 * k / (time.perf_counter() - t0)
+    c.get(probe)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        c.get(probe)
+    torch.cuda.synchronize()
+    out["get_1e6_per_s"] = 5 * probe.numel() / (time.perf_counter() - t0)
+    c.range_map_values(dlo, dhi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        s_, n_ = c.range_map_values(dlo, dhi)
+    torch.cuda.synchronize()
+    dtq = (time.perf_counter() - t0) / 3
+    out["range_values_keys_s"] = int(n_.sum().item()) / dtq
+    out["range_values_queries"] = q
+    c.close()
+    del vals, ivals, ins, first_del, probe, over, dlo, dhi
+    torch.cuda.empty_cache()
+    if fg_scale > 0:
+        nv = 1 << fg_scale
+        src, dst = synth.rmat_edges_torch(nv * 8, seed + 10, scale=fg_scale, device="cuda")
+        ekeys = synth.edge_keys_torch(src, dst)
+        del src, dst
+        w = synth.uniform_keys_torch(int(ekeys.numel()), seed + 11, "cuda", bits=20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = cp.CPMA(ekeys, values=w, leaf_bytes=min(leaf_bytes or 1024, 1024))
+        torch.cuda.synchronize()
+        wg = {"scale": fg_scale, "edges": g.size(), "build_s": time.perf_counter() - t0,
+              "bytes_per_edge": g.bytes() / g.size()}
+        del ekeys, w
+        vlo = torch.arange(nv, device="cuda", dtype=torch.int64) << 32
+        vhi = vlo + (1 << 32)
+        g.range_map_values(vlo, vhi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.range_map_values(vlo, vhi)
+        torch.cuda.synchronize()
+        wg["weighted_degrees_ms"] = (time.perf_counter() - t0) * 1e3
+        g.bfs(nv, 0, symmetric=True, device=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.bfs(nv, 0, symmetric=True, device=True)
+        torch.cuda.synchronize()
+        wg["bfs_ms"] = (time.perf_counter() - t0) * 1e3
+        out["weighted_fgraph"] = wg
+        g.close()
+        torch.cuda.empty_cache()
+    log(f"key-value: {out}")
+    return out
+
+
 def rebuild_section(cp, torch, base_dev, seed, fracs=(0.1, 1.0)):
     """Both branches of a large insert batch on the 1e8-key set, at k = n / 10
     and k = n: the full rebuild (every leaf merged, then everything spread at
@@ -819,6 +919,7 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="run only the serving loop (diagnostics)")
     ap.add_argument("--pma-only", action="store_true",
                     help="run only the comparison with the uncompressed PMA (diagnostics)")
+    ap.add_argument("--kv-only", action="store_true", help="run only the key-value section (diagnostics)")
     ap.add_argument("--range-only", action="store_true", help="run only the batched range_map section (diagnostics)")
     ap.add_argument("--sweep-only", action="store_true", help="run only the batch-size sweep (diagnostics)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -911,6 +1012,10 @@ def main():
         print(json.dumps(serving_section(cp, torch, big, big_host, args.serve_requests, seed + 90)), flush=True)
         return
 
+    if args.kv_only:
+        print(json.dumps(kv_section(cp, torch, synth.uniform_keys_torch(n0, seed, "cuda"), seed + 49,
+                                    fg_scale=args.fg_scale, leaf_bytes=args.leaf_bytes)), flush=True)
+        return
     if args.pma_only:
         print(json.dumps(pma_section(cp, torch, synth.uniform_keys_torch(n0, seed, "cuda"), seed + 48)), flush=True)
         return
@@ -1064,6 +1169,8 @@ def main():
     n_seen.append(n_after)
     result_extra["bytes_per_key_final"] = c.bytes() / c.size()
     result_extra["bytes_held_per_key_final"] = c.bytes_held() / c.size()
+    c.trim()
+    result_extra["bytes_held_per_key_after_trim"] = c.bytes_held() / c.size()
     del ins, first_del
     if not args.only_steps:
         result_extra["zipf"] = zipf_section(cp, torch, c, seed + 45)
@@ -1075,6 +1182,7 @@ def main():
         result_extra["rebuild"] = rebuild_section(cp, torch, bd, seed + 46)
         result_extra["growth"] = growth_section(cp, torch, bd, seed + 47)
         result_extra["pma_vs_cpma"] = pma_section(cp, torch, bd, seed + 48)
+        result_extra["key_value"] = kv_section(cp, torch, bd, seed + 49, fg_scale=args.fg_scale)
         del bd
         torch.cuda.empty_cache()
     if not args.only_steps:

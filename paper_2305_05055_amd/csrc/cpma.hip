@@ -1208,9 +1208,9 @@ void reserve_batch(cpma* s, uint64_t kbound, bool insert) {
   // most its own keys plus one leaf's keys
   uint64_t stage_cap = insert ? kbound + (kbound / kHeavyLds + 1) * (uint64_t)s->S + 64 : 64;
   if (s->kv()) {
-    // key-value merges stage a merged leaf of more than kKvLds keys: its new
-    // keys (more than kKvLds - kKvOld) plus at most kKvOld old ones
-    stage_cap = insert ? 2 * kbound + 2 * kKvLds : 64;
+    // key-value merges stage a merged leaf of more than KvLayout::cap keys:
+    // its new keys (more than its old ones) and its old ones
+    stage_cap = insert ? 2 * kbound + 64 : 64;
     ensure(s->vstage, stage_cap * sizeof(uint64_t));
   }
   ensure(s->stage, stage_cap * sizeof(uint64_t));
@@ -1314,7 +1314,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
   } else if (s->kv()) {
     // key-value leaves: one wave per touched leaf, any slice length
     a.part = slots(wgrid, true);
-    hipLaunchKernelGGL(k_kv_merge, dim3(wgrid), dim3(kWave), s->S, st, a);
+    hipLaunchKernelGGL(k_kv_merge, dim3(wgrid), dim3(kWave), KvLayout(s->S).total, st, a);
     HIPCHK(hipGetLastError());
     phase_end(s, pmg, st);
   } else if (small && s->S <= kWaveMaxS) {

@@ -11,8 +11,25 @@
 
 namespace cpma_dev {
 
-constexpr uint32_t kKvOld = 4096 / 9 + 2;  // keys of the fullest 4 KiB key-value leaf, and one
-constexpr uint32_t kKvLds = 1024;          // merged keys staged in LDS (more: the staging buffer)
+// LDS of the key-value merge, sized by the leaf size: the old keys and values
+// (at most S / 9 + 1 keys fit a leaf), the merged keys and values (a merged
+// leaf of more than `cap` keys is staged in HBM instead), the new leaf image
+// and the per-rank counts.
+struct KvLayout {
+  uint32_t nold, cap;
+  uint32_t k, v, mk, mv, img, c, total;
+  __host__ __device__ explicit KvLayout(uint32_t S) {
+    nold = S / 9 + 2;
+    cap = 2 * nold + 64;
+    k = 0;
+    v = k + 8 * nold;
+    mk = v + 8 * nold;
+    mv = mk + 8 * cap;
+    img = (mv + 8 * cap + 15) & ~15u;
+    c = img + S;
+    total = c + 4 * (nold + 1) + 16;
+  }
+};
 
 // Batch merge on key-value leaves: one wave per touched leaf, any slice length.
 // The wave decodes the old keys and copies the old values to LDS.  Insert:
@@ -24,13 +41,17 @@ constexpr uint32_t kKvLds = 1024;          // merged keys staged in LDS (more: t
 // one, a larger one goes to the segment's overflow-arena region (codes, then
 // the values from the next 8-byte boundary).
 __global__ void __launch_bounds__(kWave) k_kv_merge(MergeArgs a) {
-  __shared__ uint64_t K[kKvOld], V[kKvOld];
-  __shared__ uint32_t C[kKvOld + 1];
-  __shared__ uint64_t MK[kKvLds], MV[kKvLds];
+  extern __shared__ __align__(16) uint8_t smem[];
   __shared__ unsigned long long stage_off;
-  extern __shared__ __align__(16) uint8_t img[];  // S bytes: the new leaf
-  const int lane = lane_id();
   const uint32_t S = a.S;
+  const KvLayout lay(S);
+  uint64_t* K = reinterpret_cast<uint64_t*>(smem + lay.k);
+  uint64_t* V = reinterpret_cast<uint64_t*>(smem + lay.v);
+  uint64_t* MK = reinterpret_cast<uint64_t*>(smem + lay.mk);
+  uint64_t* MV = reinterpret_cast<uint64_t*>(smem + lay.mv);
+  uint8_t* img = smem + lay.img;  // S bytes: the new leaf
+  uint32_t* C = reinterpret_cast<uint32_t*>(smem + lay.c);
+  const int lane = lane_id();
   const uint64_t T = a.ctr->T;
   const uint64_t below = (1ull << lane) - 1ull;
   unsigned long long delta = 0, alg = 0;
@@ -70,7 +91,7 @@ __global__ void __launch_bounds__(kWave) k_kv_merge(MergeArgs a) {
         nnew += (uint32_t)__popcll(__ballot(isnew));
       }
       mn = m0 + nnew;
-      if (mn > kKvLds) {
+      if (mn > lay.cap) {
         if (lane == 0) stage_off = atomicAdd(&a.ctr->stage_cursor, (unsigned long long)mn);
         __syncthreads();
         const uint64_t off = stage_off;
