@@ -214,6 +214,29 @@ def trace_table(rows):
     return lines, total
 
 
+# diagnostic runs summarised whole: flag, summary file, title, what the run does
+WHOLE_RUN_TRACES = {
+    "range": ("--range-only", "range_map_zipf1e6_n1e8_kernel_trace.md",
+              "range_map: 1e6 Zipf(1.2) exact-count queries on a 1e8-key CPMA",
+              "The run builds the 1e8-key set and times the batched range_map on the default layout (3 passes "
+              "after a warm-up), runs the autotuner (its trial builds on a sample included), times the autotuned "
+              "layout, then 2000 single-query launches against one batched launch of the same 2000, 64 short "
+              "queries eager and from a HIP graph, and 6 contains calls of 1e6 keys.  Every kernel of the run."),
+    "sweep": ("--sweep-only", "small_batches_sweep_n1e8_kernel_trace.md",
+              "insert and delete batches of 10 to 1e6 keys on a 1e8-key CPMA",
+              "The run builds the 1e8-key set, then for each batch size alternates an insert of fresh keys "
+              "and a delete of present keys (30 / 30 / 20 / 10 / 5 / 3 of each at 10 / 100 / 1e3 / 1e4 / 1e5 "
+              "/ 1e6 keys; up to 4096 keys the one-workgroup preparation k_small_prep, above it the sorted "
+              "pipeline).  Every kernel of the run."),
+    "fg": ("--fg-only", "fgraph_rmat24_er_kernel_trace.md",
+           "F-Graph on a symmetric R-MAT graph (scale 24) and an Erdos-Renyi graph (1e7 vertices, p = 5e-6)",
+           "Each graph is built from device-generated edges, then BFS from vertex 0, 10 PageRank iterations, "
+           "the vertex offsets, connected components and single-source betweenness, each timed after a "
+           "warm-up; on the R-MAT graph also edge-insert batches of 1e5, 1e6 and 1e7.  Every kernel of the run "
+           "(torch's generator kernels included)."),
+}
+
+
 def trace_summary(kind, csv_path, args):
     """Markdown summary of a rocprofv3 --kernel-trace run.  steps: the kernels of
     the timed headline steps (every update batch opens with one launch of
@@ -241,6 +264,12 @@ def trace_summary(kind, csv_path, args):
                 "timed steps: from the first launch of the first timed batch to the last launch before the "
                 "first of the phase-timed batches.")
         out = STEPS_TRACE_FILE
+    elif kind in WHOLE_RUN_TRACES:
+        flag, fname, title, what = WHOLE_RUN_TRACES[kind]
+        cmd = ("rocprofv3 --kernel-trace --stats --output-format csv -d " + PROF_DIR + f"/tr_{kind} -o run -- "
+               f"python3 /root/repo/bench.py {flag}")
+        sel = rows
+        out = os.path.join(ROOT, "profiles", fname)
     else:
         cmd = ("rocprofv3 --kernel-trace --stats --output-format csv -d " + PROF_DIR + "/tr_gate -o run -- "
                "python3 /root/repo/bench.py --gate-only")
@@ -929,8 +958,9 @@ def main():
     ap.add_argument("--scan-valu-summary", metavar="CSV",
                     help="write the range scan kernel's instruction summary from a --pmc run of --gate-only")
     ap.add_argument("--trace-summary", nargs=2, metavar=("KIND", "CSV"),
-                    help="KIND steps or gate: write the kernel time summary of a rocprofv3 --kernel-trace "
-                         "run of the headline steps or of --gate-only, and exit")
+                    help="KIND steps, gate, range, sweep or fg: write the kernel time summary of a rocprofv3 "
+                         "--kernel-trace run of the headline steps, --gate-only, --range-only, --sweep-only or "
+                         "--fg-only, and exit")
     args = ap.parse_args()
 
     shape = f"--steps {args.steps} --warmup {args.warmup}"
@@ -1044,7 +1074,7 @@ def main():
                                        int(args.queries), seed + 10)), flush=True)
         return
     # ---- batched range_map (Zipf(1.2) lengths 1..1e6) vs one launch per query -----
-    if not args.only_steps and args.queries > 0:
+    if not args.only_steps and not args.sweep_only and args.queries > 0:
         result_extra["range_map"] = range_section(cp, torch, c, base_dev, int(args.queries), seed + 10,
                                                   with_cpu=not args.no_cpu_baseline)
     base_dev = None
@@ -1169,11 +1199,11 @@ def main():
     n_seen.append(n_after)
     result_extra["bytes_per_key_final"] = c.bytes() / c.size()
     result_extra["bytes_held_per_key_final"] = c.bytes_held() / c.size()
-    c.trim()
-    result_extra["bytes_held_per_key_after_trim"] = c.bytes_held() / c.size()
     del ins, first_del
     if not args.only_steps:
         result_extra["zipf"] = zipf_section(cp, torch, c, seed + 45)
+    c.trim()
+    result_extra["bytes_held_per_key_after_trim"] = c.bytes_held() / c.size()
 
     c.close()
     torch.cuda.empty_cache()
