@@ -47,7 +47,7 @@ VALU_FILE = os.path.join(ROOT, "profiles", "k_merge_wave_valu_update_pairs1e7_n1
 VALU_PEAK_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
 
 
-SCAN_KERNEL = "k_rm_interior"
+SCAN_KERNEL = "k_rm_interior<true>"
 SCAN_SOURCES = ["common.hpp", "scan_lane.hpp", "query.hpp"]
 # after the timed steps the headline run takes PHASE_STEPS more steps (every
 # phase timed); each step merges twice (its insert and its delete batch)

@@ -87,10 +87,12 @@ typedef enum { CPMA_MEM_HOST = 0, CPMA_MEM_DEVICE = 1 } cpma_mem;
  *                  up_root <= up_leaf < 1 and lo_root * grow < up_root.
  *   build_density  target root density after a build or resize; default
  *                  up_root / grow.
- *   range_chunk    interior leaves one lane of the range_map scan decodes in a
- *                  row (a range query is a search then a scan, Section "Packed
- *                  Memory Array", "Design and operations"); a power of two in
- *                  [1, 64]; default 8.  Layout and results do not depend on it.
+ *   range_chunk    steps a wave of the range_map scan takes in a row (a range
+ *                  query is a search then a scan, Section "Packed Memory
+ *                  Array", "Design and operations"): the scan visits its
+ *                  interior leaves 64 at a time, one per lane, and waves take
+ *                  runs of this many such steps; a power of two in [1, 64];
+ *                  default 2.  Layout and results do not depend on it.
  *   rebuild_frac   batch-size threshold of the full rebuild: an insert or
  *                  delete batch of k >= rebuild_frac * n keys (n the set's size
  *                  before the batch) rebuilds the whole structure -- every

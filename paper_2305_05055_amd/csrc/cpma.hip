@@ -1451,7 +1451,7 @@ cpma_status cpma_config_default(cpma_config* cfg) {
   cfg->lo_leaf = 0.10;
   cfg->lo_root = 0.30;
   cfg->build_density = cfg->up_root / cfg->grow;
-  cfg->range_chunk = 8;
+  cfg->range_chunk = 2;
   cfg->rebuild_frac = 1.0;
   cfg->uncompressed = 0;
   cfg->values = 0;
@@ -1842,6 +1842,17 @@ cpma_status cpma_apply_updates(cpma* s, uint32_t nreq, const int32_t* kind, cons
   });
 }
 
+// The interior scan of range_map: the plain-CPMA instance for compressed sets
+// without values, the general one otherwise.
+static void launch_interior(const QueryArgs& a, uint32_t blocks, hipStream_t st, const uint64_t* voff,
+                            const uint64_t* first, uint32_t chunk, unsigned long long* dsum, unsigned long long* dcount,
+                            unsigned long long* alg) {
+  if (a.zero_fill && !a.raw && !a.vals)
+    hipLaunchKernelGGL(k_rm_interior<true>, dim3(blocks), dim3(256), 0, st, a, voff, first, chunk, dsum, dcount, alg);
+  else
+    hipLaunchKernelGGL(k_rm_interior<false>, dim3(blocks), dim3(256), 0, st, a, voff, first, chunk, dsum, dcount, alg);
+}
+
 static QueryArgs query_args(const cpma* s) {
   QueryArgs a;
   a.head = (const uint64_t*)s->head.p;
@@ -1852,6 +1863,7 @@ static QueryArgs query_args(const cpma* s) {
   a.raw = s->cfg.uncompressed ? 1u : 0u;
   a.fill = (const uint32_t*)s->used.p;
   a.vals = 0;
+  a.zero_fill = s->cfg.values ? 0u : 1u;
   return a;
 }
 
@@ -1913,9 +1925,8 @@ static cpma_status range_map_impl(const cpma* cs, const uint64_t* lo, const uint
     HIPCHK(hipGetLastError());
     scan<uint64_t>(s, s->qvoff.as<uint64_t>(), q, st, LoadFn<uint64_t>{s->qnvis.as<uint64_t>()});
     PhaseMark ps = phase_begin(s, CPMA_PHASE_RANGE_SCAN, st);
-    hipLaunchKernelGGL(k_rm_interior, dim3(blocks), dim3(256), 0, st, a, (const uint64_t*)s->qvoff.as<uint64_t>(),
-                       (const uint64_t*)s->qfirst.as<uint64_t>(), s->cfg.range_chunk, dsum, dcount,
-                       qalg ? qalg + ewaves : qalg);
+    launch_interior(a, blocks, st, s->qvoff.as<uint64_t>(), s->qfirst.as<uint64_t>(), s->cfg.range_chunk, dsum,
+                    dcount, qalg ? qalg + ewaves : qalg);
     HIPCHK(hipGetLastError());
     phase_end(s, ps, st, 32ull * q);
     phase_end(s, pq, st);
@@ -2046,8 +2057,7 @@ cpma_status cpma_range_map_noalloc(const cpma* cs, const uint64_t* lo, const uin
                          (unsigned long long*)nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(scan_exclusive<uint64_t>(LoadFn<uint64_t>{nvis}, q, voff, tmp, st));
-    hipLaunchKernelGGL(k_rm_interior, dim3((uint32_t)s->num_cus * 8), dim3(256), 0, st, a, (const uint64_t*)voff,
-                       (const uint64_t*)first, s->cfg.range_chunk, dsum, dcount, (unsigned long long*)nullptr);
+    launch_interior(a, (uint32_t)s->num_cus * 8, st, voff, first, s->cfg.range_chunk, dsum, dcount, nullptr);
     HIPCHK(hipGetLastError());
   });
 }

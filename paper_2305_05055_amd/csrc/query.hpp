@@ -30,6 +30,7 @@ struct QueryArgs {
   // bytes (codes and values); vals: sum values instead of keys
   const uint32_t* fill;
   uint32_t vals;
+  uint32_t zero_fill;  // bytes past `used` are zero in place (every set without values)
 };
 
 // The values of a key-value leaf (m = (fill - codes) / 8 words at its end).
@@ -157,94 +158,133 @@ __global__ void __launch_bounds__(kWave) k_rm_ends_wave(QueryArgs a, uint64_t* _
   if (alg && lane_id() == 0) alg[blockIdx.x] = visited;
 }
 
-// Interior visits, flattened over all queries: each lane takes `chunk`
-// consecutive visits (consecutive leaves of one query, or the tail of one query
-// and the head of the next) and keeps running sums in registers while the query
-// is unchanged.  Partial sums are exact integers, so they may be combined in any
-// order: a lane flushes a finished query with 64-bit atomics, and the partials
-// still open at the end of a chunk are first reduced by query across the wave
-// (lanes hold consecutive chunks, so equal queries sit in runs of lanes), leaving
-// one atomic per run -- a query spanning millions of leaves would otherwise
-// serialise on one address.
+// Sum and count of one interior leaf (a leaf every key of which is in its
+// query's range), for any leaf format.
+template <bool kPlain>
+__device__ __forceinline__ LeafSum interior_leaf(const QueryArgs& a, uint64_t leaf, uint32_t u) {
+  const uint8_t* lp = a.bytes + leaf * (uint64_t)a.S;
+  const uint64_t h = a.head[leaf];
+  const uint64_t span = a.head[leaf + 1] - h;  // interior leaves always have a successor
+  if constexpr (kPlain) {
+    return span < (1ull << 28) ? leaf_sum_zf(lp, u, h) : leaf_sum_range(lp, u, 0, kNoKey);
+  } else {
+    if (a.vals) {
+      // the values: m 8-byte words ending at the leaf's end (8-byte aligned)
+      const uint32_t m = (a.fill[leaf] - u) / 8;
+      const uint64_t* w = reinterpret_cast<const uint64_t*>(lp + a.S - 8u * m);
+      uint64_t s0 = 0, s1 = 0;
+      uint32_t i = 0;
+      for (; i + 2 <= m; i += 2) {
+        s0 += w[i];
+        s1 += w[i + 1];
+      }
+      if (i < m) s0 += w[i];
+      return LeafSum{s0 + s1, m};
+    }
+    return a.raw                ? raw_sum_all(lp, u)
+           : span >= (1ull << 28) ? leaf_sum_range(lp, u, 0, kNoKey)
+                                  : leaf_sum_fast(lp, u, h);
+  }
+}
+
+// Interior visits, flattened over all queries.  The visits are cut into steps
+// of 64, and waves take groups of `chunk` consecutive steps, group g by wave
+// g mod (number of waves).  At a step, lane l decodes visit base + l, so the
+// wave's loads fall on 64 neighbouring leaves, and the waves running at the
+// same time sweep one region of the leaf array together.  (Giving each lane
+// `chunk` consecutive leaves instead spreads one load instruction over 64 *
+// chunk leaves, and the memory system delivers markedly fewer bytes per second
+// for that pattern.)  The query of a step's first visit is found by one binary
+// search over the visit offsets, with wave-uniform (scalar) loads; each lane
+// then walks forward to its own visit's query.  Partial sums are exact
+// integers, so they may be combined in any order:
+//  * while every lane's visit belongs to the same query, each lane adds its
+//    leaf to a running share; the shares are summed across the wave and
+//    flushed with one pair of 64-bit atomics when the query changes;
+//  * a step whose lanes span several queries is reduced at once by query
+//    (visits ascend with the lane, so equal queries sit in runs of lanes), one
+//    pair of atomics per run -- a query spanning millions of leaves would
+//    otherwise serialise on one address.
+//
+// kPlain: compressed leaves without values (zero past `used`), decoded with
+// leaf_sum_zf; this instance also keeps the register count of the other
+// formats' decoders out of the hot kernel.
+template <bool kPlain>
 __global__ void __launch_bounds__(256) k_rm_interior(QueryArgs a, const uint64_t* __restrict__ ioff,
                                                      const uint64_t* __restrict__ first_int, uint32_t chunk,
                                                      unsigned long long* __restrict__ sum,
                                                      unsigned long long* __restrict__ count,
                                                      unsigned long long* __restrict__ alg) {
-  const uint64_t lanes = (uint64_t)gridDim.x * blockDim.x;
   const uint64_t V = ioff[a.q];
-  const uint64_t nchunks = (V + chunk - 1) / chunk;
-  const uint64_t npad = (nchunks + kWave - 1) / kWave * kWave;  // whole waves iterate together
+  const uint64_t G = (uint64_t)kWave * chunk;
+  const uint64_t ngroups = (V + G - 1) / G;
+  const uint64_t nwaves = (uint64_t)gridDim.x * blockDim.x / kWave;
+  const uint64_t wave = (uint64_t)__builtin_amdgcn_readfirstlane((int)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave));
   const int lane = lane_id();
   uint64_t visited = 0;
-  for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < npad; c += lanes) {
-    uint64_t qi = ~0ull, s = 0, n = 0;
-    if (c < nchunks) {
-      const uint64_t v0 = c * chunk;
-      const uint64_t v1 = min(v0 + chunk, V);
-      qi = upper_bound_u64(ioff, a.q + 1, v0) - 1;
-      uint64_t qbeg = ioff[qi], qend = ioff[qi + 1];
-      uint64_t fl = first_int[qi];
-      for (uint64_t v = v0; v < v1; v++) {
-        if (v >= qend) {
-          if (n) {
-            atomicAdd(&sum[qi], (unsigned long long)s);
-            atomicAdd(&count[qi], (unsigned long long)n);
-          }
-          s = n = 0;
-          do {
-            qi++;
-            qbeg = ioff[qi];
-            qend = ioff[qi + 1];
-          } while (v >= qend);
-          fl = first_int[qi];
-        }
-        const uint64_t leaf = fl + (v - qbeg);
+  uint64_t cq = ~0ull, cs = 0, cn = 0;  // carried query (wave-uniform) and this lane's share
+  auto flush_carry = [&]() {
+    if (cq != ~0ull) {
+      const uint64_t ts = wave_sum<uint64_t>(cs), tn = wave_sum<uint64_t>(cn);
+      if (lane == 0 && tn) {
+        atomicAdd(&sum[cq], (unsigned long long)ts);
+        atomicAdd(&count[cq], (unsigned long long)tn);
+      }
+    }
+    cq = ~0ull;
+    cs = cn = 0;
+  };
+  for (uint64_t g = wave; g < ngroups; g += nwaves) {
+    const uint64_t Wend = min((g + 1) * G, V);
+    for (uint64_t base = g * G; base < Wend; base += kWave) {
+      const uint64_t v = base + lane;
+      uint64_t vq = ~0ull, s = 0, n = 0;
+      if (v < Wend) {
+        uint64_t qi = upper_bound_u64(ioff, a.q + 1, base) - 1;
+        while (ioff[qi + 1] <= v) qi++;
+        vq = qi;
+        const uint64_t leaf = first_int[qi] + (v - ioff[qi]);
         const uint32_t u = a.used[leaf];
-        const uint64_t h = a.head[leaf];
-        const uint64_t span = a.head[leaf + 1] - h;  // interior leaves always have a successor
-        const uint8_t* lp = a.bytes + leaf * (uint64_t)a.S;
-        LeafSum r;
-        if (a.vals) {
-          // the values: m 8-byte words ending at the leaf's end (8-byte aligned)
-          const uint32_t m = (a.fill[leaf] - u) / 8;
-          const uint64_t* w = reinterpret_cast<const uint64_t*>(lp + a.S - 8u * m);
-          uint64_t s0 = 0, s1 = 0;
-          uint32_t i = 0;
-          for (; i + 2 <= m; i += 2) {
-            s0 += w[i];
-            s1 += w[i + 1];
-          }
-          if (i < m) s0 += w[i];
-          r = LeafSum{s0 + s1, m};
-        } else {
-          r = a.raw                ? raw_sum_all(lp, u)
-              : span < (1ull << 28) ? leaf_sum_fast(lp, u, h)
-                                    : leaf_sum_range(lp, u, 0, kNoKey);
-        }
-        s += r.sum;
-        n += r.count;
+        const LeafSum r = interior_leaf<kPlain>(a, leaf, u);
+        s = r.sum;
+        n = r.count;
         visited += u;
       }
-    }
-    // segmented inclusive scan over runs of equal qi (qi is non-decreasing over lanes)
+      const uint64_t q0 = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(vq >> 32)) << 32) |
+                          (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)vq);
+      const bool uni = __ballot(vq != q0) == 0;
+      if (uni && q0 == cq) {
+        cs += s;
+        cn += n;
+        continue;
+      }
+      flush_carry();
+      if (uni) {
+        cq = q0;
+        cs = s;
+        cn = n;
+        continue;
+      }
+      // several queries in this step: segmented inclusive scan over runs of equal vq
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const uint64_t qu = __shfl_up(qi, d, kWave);
-      const uint64_t su = __shfl_up(s, d, kWave);
-      const uint64_t nu = __shfl_up(n, d, kWave);
-      if (lane >= d && qu == qi) {
-        s += su;
-        n += nu;
+      for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t qu = __shfl_up(vq, d, kWave);
+        const uint64_t su = __shfl_up(s, d, kWave);
+        const uint64_t nu = __shfl_up(n, d, kWave);
+        if (lane >= d && qu == vq) {
+          s += su;
+          n += nu;
+        }
+      }
+      const uint64_t qn = __shfl_down(vq, 1, kWave);
+      const bool run_end = lane == kWave - 1 || qn != vq;
+      if (run_end && vq != ~0ull && n) {
+        atomicAdd(&sum[vq], (unsigned long long)s);
+        atomicAdd(&count[vq], (unsigned long long)n);
       }
     }
-    const uint64_t qn = __shfl_down(qi, 1, kWave);
-    const bool run_end = lane == kWave - 1 || qn != qi;
-    if (run_end && qi != ~0ull && n) {
-      atomicAdd(&sum[qi], (unsigned long long)s);
-      atomicAdd(&count[qi], (unsigned long long)n);
-    }
   }
+  flush_carry();
   if (alg) {
     const uint64_t t = wave_sum(visited);
     if (lane_id() == 0) alg[((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave] = t;

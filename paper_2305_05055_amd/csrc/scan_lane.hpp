@@ -99,6 +99,103 @@ __device__ __forceinline__ LeafSum leaf_sum_fast(const uint8_t* __restrict__ lea
   return r;
 }
 
+// Keeps the loads above it above it: without this the compiler sinks each
+// round's loads down to their use in the next round, so that every round waits
+// for its own loads instead of finding them done.
+__device__ __forceinline__ void issue_now() { asm volatile("" ::: "memory"); }
+
+// One byte (byte J of word x) of leaf_sum_zf: the running offset D (key minus
+// head) grows by the byte's payload at its shift; a terminator's D is returned
+// for the sum, a continuation byte returns 0.  The continuation mask is one
+// sign-extending extract, written so that the compiler keeps it: left to
+// itself it rebuilds the mask from a compare and two selects per byte.
+template <int J>
+__device__ __forceinline__ uint32_t zf_byte(uint32_t x, uint32_t& D, uint32_t& sh) {
+  uint32_t cm;  // all ones on a continuation byte
+  asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(cm) : "v"(x), "i"(8 * J + 7));
+  D += __builtin_amdgcn_ubfe(x, 8 * J, 7) << (sh & 31u);
+  sh = (sh + 7u) & cm;
+  return D & ~cm;
+}
+
+// One 16-byte chunk of leaf_sum_zf.  Offsets stay below 2^28, so the chunk's
+// 16 terminator offsets sum below 2^32 and are folded into the 64-bit total
+// once.  `cont` counts continuation bytes.
+__device__ __forceinline__ void zf_chunk(const uint4 q, uint32_t& D, uint32_t& sh, uint64_t& Sc, uint32_t& cont) {
+  const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const uint32_t x = w[k];
+    const uint32_t t0 = zf_byte<0>(x, D, sh);
+    const uint32_t t1 = zf_byte<1>(x, D, sh);
+    const uint32_t t2 = zf_byte<2>(x, D, sh);
+    const uint32_t t3 = zf_byte<3>(x, D, sh);
+    s += (t0 + t1) + (t2 + t3);
+    cont += (uint32_t)__popc(x & 0x80808080u);
+  }
+  Sc += s;
+}
+
+// Sum and count of every key of a leaf read in place, for leaves whose key span
+// is below 2^28 and whose bytes past `used` are zero (the leaf layout's zero
+// fill; not key-value leaves, whose values sit at the leaf's end).  The leaf is
+// read in whole 64-byte rounds (S is a multiple of 64) with no bounds tests:
+//  * each zero byte past `used` decodes as a zero delta, one more copy of the
+//    last key; there are exactly 64 * rounds - used of them, taken back out of
+//    the sum at the end;
+//  * the key count is `used` minus the continuation bytes, once the head's
+//    eight bytes are replaced by seven payload-free continuation bytes and a
+//    terminator (the head: one key at offset 0);
+//  * every round's four loads are issued unconditionally (past the last round
+//    they reread it), so the next round is in flight while one is decoded.
+__device__ __forceinline__ LeafSum leaf_sum_zf(const uint8_t* __restrict__ leaf, uint32_t used, uint64_t head) {
+  if (used == 0) return LeafSum{0, 0};
+  const uint32_t lastr = (used - 1u) & ~63u;  // first byte of the last round
+  uint32_t D = 0, sh = 0, cont = 0;
+  uint64_t Sc = 0;
+  const uint4* pa = reinterpret_cast<const uint4*>(leaf);
+  uint4 a0 = pa[0], a1 = pa[1], a2 = pa[2], a3 = pa[3];
+  const uint4* pb = reinterpret_cast<const uint4*>(leaf + min(64u, lastr));
+  uint4 b0 = pb[0], b1 = pb[1], b2 = pb[2], b3 = pb[3];
+  issue_now();
+  a0.x = 0x80808080u;
+  a0.y = 0x00808080u;
+  zf_chunk(a0, D, sh, Sc, cont);
+  zf_chunk(a1, D, sh, Sc, cont);
+  zf_chunk(a2, D, sh, Sc, cont);
+  zf_chunk(a3, D, sh, Sc, cont);
+  // ping-pong between two register sets: no copies between rounds
+  for (uint32_t c = 64; c < used;) {
+    pa = reinterpret_cast<const uint4*>(leaf + min(c + 64u, lastr));
+    a0 = pa[0];
+    a1 = pa[1];
+    a2 = pa[2];
+    a3 = pa[3];
+    issue_now();
+    zf_chunk(b0, D, sh, Sc, cont);
+    zf_chunk(b1, D, sh, Sc, cont);
+    zf_chunk(b2, D, sh, Sc, cont);
+    zf_chunk(b3, D, sh, Sc, cont);
+    c += 64;
+    if (c >= used) break;
+    pb = reinterpret_cast<const uint4*>(leaf + min(c + 64u, lastr));
+    b0 = pb[0];
+    b1 = pb[1];
+    b2 = pb[2];
+    b3 = pb[3];
+    issue_now();
+    zf_chunk(a0, D, sh, Sc, cont);
+    zf_chunk(a1, D, sh, Sc, cont);
+    zf_chunk(a2, D, sh, Sc, cont);
+    zf_chunk(a3, D, sh, Sc, cont);
+    c += 64;
+  }
+  const uint32_t zeros = ((used + 63u) & ~63u) - used;
+  const uint64_t cnt = used - cont;
+  return LeafSum{cnt * head + (Sc - (uint64_t)zeros * D), cnt};
+}
+
 // General path: 64-bit decode; counts and sums keys in [lo, hi).  Stops early
 // once a key reaches hi.
 __device__ __forceinline__ LeafSum leaf_sum_range(const uint8_t* __restrict__ leaf, uint32_t used,

@@ -131,7 +131,7 @@ def test_config_defaults_and_checks_without_gpu():
         pytest.skip("libcpma.so not built")
     L = p.lib()
     c = p.default_config()
-    assert c.range_chunk == 8
+    assert c.range_chunk == 2
     h = ctypes.c_void_p()
     for S, chunk in ((8192, 0), (32, 0), (0, 3), (0, 128)):
         bad = p.Config()
