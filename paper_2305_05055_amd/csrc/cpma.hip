@@ -121,6 +121,7 @@ int tree_height(uint64_t L) {
 struct cpma {
   int device = 0;
   int num_cus = 256;
+  uint32_t rm_blocks[2] = {2048, 2048};  // resident blocks of k_rm_interior<false>, <true>
   cpma_config cfg{};
   uint32_t S = 1024;
   uint64_t L = 0, n = 0;
@@ -1173,7 +1174,10 @@ MergeGrids merge_grids(const cpma* s, uint64_t kbound) {
   MergeGrids m;
   const uint64_t segs = std::min<uint64_t>(kbound, s->L);
   m.lgrid = (uint32_t)std::min<uint64_t>((segs + 255) / 256, (uint64_t)s->num_cus * 16);
-  m.wgrid = std::max(1u, (uint32_t)std::min<uint64_t>(segs, (uint64_t)s->num_cus * 40));
+  // many more waves than fit at once: a wave takes a few segments, and the
+  // dispatcher hands out the rest as waves finish, which evens out segments of
+  // unequal work (4-5 % faster at 1e7 into 1e8 than 40 waves per CU)
+  m.wgrid = std::max(1u, (uint32_t)std::min<uint64_t>(segs, (uint64_t)s->num_cus * 320));
   m.lwaves = std::max(1u, m.lgrid) * (256 / kWave);
   // heavy merge of spilled slices: at most kbound / (kWaveSlice + 1) of them,
   // a few LDS-bound waves per CU
@@ -1512,6 +1516,14 @@ static cpma_status build_impl(const uint64_t* keys, const uint64_t* vals, uint64
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, s->device));
     s->num_cus = prop.multiProcessorCount;
+    // the interior range scan runs one generation of blocks: every block
+    // resident at once, so no block starts after the others have finished
+    for (int plain = 0; plain < 2; plain++) {
+      int per = 0;
+      HIPCHK(plain ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rm_interior<true>, 256, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rm_interior<false>, 256, 0));
+      s->rm_blocks[plain] = (uint32_t)std::max(1, per) * (uint32_t)s->num_cus;
+    }
     ensure(s->ctr_buf, sizeof(Counters), 0.0);
     s->dctr = s->ctr_buf.as<Counters>();
     HIPCHK(hipHostMalloc(&s->hctr, sizeof(Counters), hipHostMallocDefault));
@@ -1844,6 +1856,9 @@ cpma_status cpma_apply_updates(cpma* s, uint32_t nreq, const int32_t* kind, cons
 
 // The interior scan of range_map: the plain-CPMA instance for compressed sets
 // without values, the general one otherwise.
+static uint32_t interior_blocks(const cpma* s, const QueryArgs& a) {
+  return s->rm_blocks[a.zero_fill && !a.raw && !a.vals ? 1 : 0];
+}
 static void launch_interior(const QueryArgs& a, uint32_t blocks, hipStream_t st, const uint64_t* voff,
                             const uint64_t* first, uint32_t chunk, unsigned long long* dsum, unsigned long long* dcount,
                             unsigned long long* alg) {
@@ -1909,7 +1924,7 @@ static cpma_status range_map_impl(const cpma* cs, const uint64_t* lo, const uint
     const uint32_t egrid = wave_ends ? grid_for(q, 1, (uint32_t)s->num_cus * 64)
                                      : grid_for(q, 256, (uint32_t)s->num_cus * 16);
     const uint64_t ewaves = wave_ends ? egrid : 4ull * egrid;
-    const uint32_t blocks = (uint32_t)s->num_cus * 8;
+    const uint32_t blocks = interior_blocks(s, a);
     const uint64_t nslots = ewaves + 4ull * blocks;
     unsigned long long* qalg = nullptr;
     if (s->stats_on && ((s->stats_mask >> CPMA_PHASE_RANGE_SCAN) & 1u)) {
@@ -2057,7 +2072,7 @@ cpma_status cpma_range_map_noalloc(const cpma* cs, const uint64_t* lo, const uin
                          (unsigned long long*)nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(scan_exclusive<uint64_t>(LoadFn<uint64_t>{nvis}, q, voff, tmp, st));
-    launch_interior(a, (uint32_t)s->num_cus * 8, st, voff, first, s->cfg.range_chunk, dsum, dcount, nullptr);
+    launch_interior(a, interior_blocks(s, a), st, voff, first, s->cfg.range_chunk, dsum, dcount, nullptr);
     HIPCHK(hipGetLastError());
   });
 }

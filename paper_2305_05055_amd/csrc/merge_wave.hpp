@@ -148,7 +148,6 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segme
     const uint32_t i0 = min(nA + 1, (uint32_t)lane * m), i1 = min(nA + 1, i0 + m);
     uint32_t U = 0;
     uint64_t first_key = kNoKey;
-    uint8_t* dst = out;
     uint64_t arena_off = 0;
     bool to_arena = false;
     if (a.is_insert) {
@@ -236,33 +235,41 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segme
           continue;
         }
         arena_off = off;
-        dst = a.arena + off;
         to_arena = true;
       }
-      // sweep 2: write old keys, record group starts
-      uint32_t run = lincl - lt;
-      p = p0;
-      kp = k_before;
-      for (uint32_t i = i0; i < i1; i++) {
-        const bool gh = GR[p] == i;
-        const uint32_t gb = gh ? GB[p] : 0u;
-        if (gh) GS[p] = run;
-        if (i < nA) {
-          const KT x = K[i];
-          const bool hp = gh || i > 0;
-          const KT np = gh ? GK[p] : kp;
-          const uint32_t c = hp ? vlen_t((KT)(x - np)) : 8u;
-          put_key_bytes<KT>(dst + run + gb, !hp, x, np, base);
-          run += gb + c;
-          kp = x;
-        } else {
-          run += gb;
+      // sweep 2: write old keys, record group starts; then the new keys at
+      // their group's start + their offset inside the group.  Instantiated
+      // once for the LDS image and once for the arena, so that each copy's
+      // stores have a known address space (a pointer that may be either
+      // compiles to generic stores, far slower for LDS).
+      auto write_merged = [&](auto dst) {
+        uint32_t run = lincl - lt;
+        uint32_t p = p0;
+        KT kp = k_before;
+        for (uint32_t i = i0; i < i1; i++) {
+          const bool gh = GR[p] == i;
+          const uint32_t gb = gh ? GB[p] : 0u;
+          if (gh) GS[p] = run;
+          if (i < nA) {
+            const KT x = K[i];
+            const bool hp = gh || i > 0;
+            const KT np = gh ? GK[p] : kp;
+            const uint32_t c = hp ? vlen_t((KT)(x - np)) : 8u;
+            put_key_bytes<KT>(dst + run + gb, !hp, x, np, base);
+            run += gb + c;
+            kp = x;
+          } else {
+            run += gb;
+          }
+          p += gh ? 1u : 0u;
         }
-        p += gh ? 1u : 0u;
-      }
-      __syncthreads();
-      // new keys: group start + offset inside the group
-      if (isnew) put_key_bytes<KT>(dst + GS[gid] + (ex - exfirst), !has_pred, bj, pred, base);
+        __syncthreads();
+        if (isnew) put_key_bytes<KT>(dst + GS[gid] + (ex - exfirst), !has_pred, bj, pred, base);
+      };
+      if (to_arena)
+        write_merged(a.arena + arena_off);
+      else
+        write_merged(out);
       uint64_t firstnew = kNoKey;
       if (nnew) firstnew = base + (uint64_t)readlane_t(bj, __ffsll((unsigned long long)newmask) - 1);
       first_key = nA ? min(base + (uint64_t)K[0], firstnew) : firstnew;
