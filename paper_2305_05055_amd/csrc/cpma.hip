@@ -122,6 +122,9 @@ struct cpma {
   int device = 0;
   int num_cus = 256;
   uint32_t rm_blocks[2] = {2048, 2048};  // resident blocks of k_rm_interior<false>, <true>
+  // a small batch's merge totals, left for the single-block path check to fold
+  const unsigned long long* fin_parts = nullptr;
+  uint32_t fin_nn = 0, fin_nw = 0;
   cpma_config cfg{};
   uint32_t S = 1024;
   uint64_t L = 0, n = 0;
@@ -1050,13 +1053,22 @@ uint64_t rebalance(cpma* s, hipStream_t st, int merged = -1, uint64_t small_k = 
     PhaseMark pc = phase_begin(s, CPMA_PHASE_COUNT, st);
     // (level, segment) pairs: at most min(k, L) segments on H + 1 levels
     const uint64_t pairs = std::min<uint64_t>(small_k, s->L) * (uint64_t)(P.H + 1);
-    const uint32_t pgrid = (uint32_t)std::min<uint64_t>((pairs + kPathThreads - 1) / kPathThreads, 128);
+    const bool fin = s->fin_parts != nullptr;  // one block: fold the merge and return the counters too
+    const uint32_t pgrid = fin ? 1u : (uint32_t)std::min<uint64_t>((pairs + kPathThreads - 1) / kPathThreads, 128);
     hipLaunchKernelGGL(k_path_check, dim3(std::max(1u, pgrid)), dim3(kPathThreads), 0, st, s->bounds(s->L), P,
                        (const uint32_t*)s->used.as<uint32_t>(), (const uint32_t*)s->seg_leaf.as<uint32_t>(),
-                       (const uint4*)s->seg_desc.as<uint4>(), s->dctr);
+                       (const uint4*)s->seg_desc.as<uint4>(), s->dctr, s->fin_parts, s->fin_nn, s->fin_nw,
+                       fin ? s->hctr : nullptr);
+    s->fin_parts = nullptr;
     HIPCHK(hipGetLastError());
     phase_end(s, pc, st);
-    read_counters(s, st);
+    if (fin) {
+      HIPCHK(hipStreamSynchronize(st));
+      resolve_phases(s);
+      if (s->hctr->error) throw Fail{CPMA_ERR_DEVICE};
+    } else {
+      read_counters(s, st);
+    }
     const Counters c = *s->hctr;
     delta = take_merge(s, c, merged);
     taken = true;
@@ -1225,9 +1237,19 @@ void reserve_batch(cpma* s, uint64_t kbound, bool insert) {
 
 // small: the small-batch kernel already wrote kprime, the segments, their routing and T.
 // rebuild: the batch is large enough for a full rebuild instead of counting.
+// Whether a small batch's path check runs as one block that also folds the
+// merge's totals and writes the counters to the host (at most 8192 (level,
+// segment) pairs: each of its threads takes one chunk of eight).
+bool finish_in_path_check(const cpma* s, uint64_t k) {
+  if (!s->pyr_valid) return false;
+  const Pyramid P = pyramid_layout(s->L);
+  return std::min<uint64_t>(k, s->L) * (uint64_t)(P.H + 1) <= 8ull * kPathThreads;
+}
+
 uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, hipStream_t st, bool small = false,
                      bool rebuild_all = false) {
   const bool segments_ready = small;
+  s->fin_parts = nullptr;
   reserve_batch(s, kbound, insert);
   PhaseMark pl = phase_begin(s, CPMA_PHASE_LOCATE, st);
   const uint64_t L = s->L;
@@ -1362,9 +1384,14 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
       phase_end(s, ph, st);
     }
   }
-  hipLaunchKernelGGL(k_fold_parts, dim3(grid_for(n_narrow + n_wide, 1024, 32)), dim3(1024), 0, st,
-                     (const unsigned long long*)parts, n_narrow, n_wide,
-                     s->dctr);
+  if (!rebuild_all && small && finish_in_path_check(s, kbound)) {
+    s->fin_parts = parts;  // folded by the path check, which also returns the counters
+    s->fin_nn = n_narrow;
+    s->fin_nw = n_wide;
+  } else {
+    hipLaunchKernelGGL(k_fold_parts, dim3(grid_for(n_narrow + n_wide, 1024, 32)), dim3(1024), 0, st,
+                       (const unsigned long long*)parts, n_narrow, n_wide, s->dctr);
+  }
   HIPCHK(hipGetLastError());
   if (rebuild_all) return rebuild(s, st, insert ? 1 : 0);
   return rebalance(s, st, insert ? 1 : 0, small ? kbound : 0);
@@ -1378,10 +1405,13 @@ bool wants_rebuild(const cpma* s, uint64_t k) {
 // Batch of k <= kSmallBatch keys at device address src (any order, repeats
 // allowed): one launch zeroes the counters and prepares it (sort, repeats,
 // leaves, segments), then the merge and rebalance phases run.
-uint64_t apply_small(cpma* s, const uint64_t* src, uint64_t k, bool insert, hipStream_t st) {
+// Host keys (src null) come in `ak`, at most kArgKeys of them.
+uint64_t apply_small(cpma* s, const uint64_t* src, uint64_t k, bool insert, hipStream_t st,
+                     const ArgKeys* ak = nullptr) {
   reserve_batch(s, k, insert);
   PhaseMark pm = phase_begin(s, CPMA_PHASE_SORT, st);
-  hipLaunchKernelGGL(k_small_prep, dim3(1), dim3(kSmallThreads), 0, st, src, (uint32_t)k,
+  static const ArgKeys kNoArgKeys{};
+  hipLaunchKernelGGL(k_small_prep, dim3(1), dim3(kSmallThreads), 0, st, src, ak ? *ak : kNoArgKeys, (uint32_t)k,
                      (const uint64_t*)s->head.as<uint64_t>(), s->L, (const uint32_t*)s->used.as<uint32_t>(),
                      s->kdedup.as<uint64_t>(), s->seg_leaf.as<uint32_t>(), s->seg_begin.as<uint32_t>(),
                      s->seg_desc.as<uint4>(), insert ? 1 : 0,
@@ -1602,12 +1632,18 @@ static cpma_status update(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem me
     HIPCHK(hipSetDevice(s->device));
     if (k <= kSmallBatch && !s->kv()) {
       const uint64_t* src = keys;
-      if (mem == CPMA_MEM_HOST) {
-        ensure(s->kin, k * sizeof(uint64_t));
-        HIPCHK(hipMemcpyAsync(s->kin.p, keys, k * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-        src = s->kin.as<uint64_t>();
+      if (mem == CPMA_MEM_HOST && k <= kArgKeys) {
+        ArgKeys ak;
+        std::memcpy(ak.k, keys, k * sizeof(uint64_t));
+        delta = apply_small(s, nullptr, k, insert, st, &ak);
+      } else {
+        if (mem == CPMA_MEM_HOST) {
+          ensure(s->kin, k * sizeof(uint64_t));
+          HIPCHK(hipMemcpyAsync(s->kin.p, keys, k * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+          src = s->kin.as<uint64_t>();
+        }
+        delta = apply_small(s, src, k, insert, st);
       }
-      delta = apply_small(s, src, k, insert, st);
     } else {
       zero_counters(s, st);
       const uint64_t* B = prepare_batch(s, keys, k, mem, st);

@@ -14,6 +14,13 @@ namespace cpma_dev {
 constexpr uint32_t kSmallBatch = 4096;
 constexpr uint32_t kSmallThreads = 1024;
 
+// Up to kArgKeys host keys travel in the launch's arguments instead of a
+// separate copy to the device (one launch fewer on the small-batch path).
+constexpr uint32_t kArgKeys = 256;
+struct ArgKeys {
+  uint64_t k[kArgKeys];
+};
+
 // Exclusive scan of one value per thread over the workgroup; returns the
 // thread's offset, *total the sum.
 __device__ __forceinline__ uint32_t block_scan_u32(uint32_t v, uint32_t* wsum, uint32_t* total) {
@@ -35,7 +42,7 @@ __device__ __forceinline__ uint32_t block_scan_u32(uint32_t v, uint32_t* wsum, u
 // Also routes the segments: an insert slice longer than `slice` keys goes to the
 // spill list (desc.w = 2), which the heavy merge takes; every other segment is
 // merged by the 64-bit wave instance (desc.w = 0).
-__global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __restrict__ in, uint32_t k,
+__global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __restrict__ in, ArgKeys ak, uint32_t k,
                                                               const uint64_t* __restrict__ head, uint64_t L,
                                                               const uint32_t* __restrict__ used,
                                                               uint64_t* __restrict__ B, uint32_t* __restrict__ seg_leaf,
@@ -56,7 +63,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __
     reinterpret_cast<uint32_t*>(ctr)[i] = 0u;
   __syncthreads();
   for (uint32_t i = tid; i < n; i += kSmallThreads) {
-    const uint64_t x = i < k ? in[i] : kNoKey;  // padding sorts last
+    const uint64_t x = i < k ? (in ? in[i] : ak.k[i]) : kNoKey;  // padding sorts last; no `in`: keys in ak
     if (i < k && x == kNoKey) bad = 1;
     A[i] = x;
   }
@@ -262,21 +269,53 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __
 // share of the (level, segment) pairs.
 constexpr uint32_t kPathThreads = 1024;
 
+
+// Launched as a single block it can also finish the update (part and hout not
+// null): it first folds the merge's per-wave totals (what k_fold_parts does;
+// `part` holds n_narrow then n_wide slot pairs), and at the end copies the
+// counters to host memory `hout`, so the host reads them after one stream
+// synchronisation with no copy launch in between.
 __global__ void __launch_bounds__(kPathThreads) k_path_check(Bounds bd, Pyramid P, const uint32_t* __restrict__ used,
                                                              const uint32_t* __restrict__ seg_leaf,
-                                                             const uint4* __restrict__ seg_desc, Counters* ctr) {
+                                                             const uint4* __restrict__ seg_desc, Counters* ctr,
+                                                             const unsigned long long* __restrict__ part,
+                                                             uint32_t n_narrow, uint32_t n_wide, Counters* hout) {
   __shared__ uint32_t lf[kSmallBatch];
   __shared__ uint64_t G[kSmallBatch + 1];  // G[t]: growth of the segments before t (mod 2^64)
   __shared__ uint64_t wsum[kPathThreads / kWave];
+  __shared__ uint64_t red[3][kPathThreads / kWave];
   __shared__ uint32_t bad;
   constexpr uint32_t kPer = kSmallBatch / kPathThreads;
   const uint32_t tid = threadIdx.x;
-  const uint32_t T = (uint32_t)ctr->T;
-  if (T == 0 || T > kSmallBatch) {  // nothing touched (or not a small batch: let the full count decide)
-    if (tid == 0 && T > kSmallBatch) ctr->path_unsafe = 1;
-    return;
+  if (part) {
+    uint64_t d = 0, an = 0, aw = 0;
+    for (uint32_t w = tid; w < n_narrow + n_wide; w += kPathThreads) {
+      d += part[2 * w];
+      (w < n_narrow ? an : aw) += part[2 * w + 1];
+    }
+    d = wave_sum(d);
+    an = wave_sum(an);
+    aw = wave_sum(aw);
+    if (lane_id() == 0) {
+      red[0][tid / kWave] = d;
+      red[1][tid / kWave] = an;
+      red[2][tid / kWave] = aw;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (uint32_t i = 1; i < kPathThreads / kWave; i++) {
+        d += red[0][i];
+        an += red[1][i];
+        aw += red[2][i];
+      }
+      ctr->delta += d;
+      ctr->alg_bytes += an;
+      ctr->alg_bytes_h += aw;
+    }
   }
-  if (tid == 0) bad = 0;
+  const uint32_t T = (uint32_t)ctr->T;
+  if (tid == 0) bad = T > kSmallBatch;  // not a small batch: let the full count decide
+  if (T > 0 && T <= kSmallBatch) {
   uint64_t g[kPer];
   uint64_t mine = 0;
 #pragma unroll
@@ -351,8 +390,18 @@ __global__ void __launch_bounds__(kPathThreads) k_path_check(Bounds bd, Pyramid 
     }
   }
   if (v) bad = 1;
+  }
   __syncthreads();
-  if (tid == 0 && bad) ctr->path_unsafe = 1;
+  if (tid == 0) {
+    if (bad) ctr->path_unsafe = 1;
+    if (hout) {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(ctr);
+      uint32_t* dst = reinterpret_cast<uint32_t*>(hout);
+      for (uint32_t i = 0; i < sizeof(Counters) / 4; i++)
+        dst[i] = __hip_atomic_load(&src[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence_system();
+    }
+  }
 }
 
 }  // namespace cpma_dev
