@@ -176,7 +176,6 @@ __global__ void __launch_bounds__(kWave) k_kv_merge(MergeArgs a) {
     }
     cl = wave_sum(cl);
     const uint32_t U = cl + 8u * mn;
-    uint8_t* dst = img;
     uint64_t aoff = 0;
     const bool to_arena = U > S;
     if (to_arena) {
@@ -186,27 +185,34 @@ __global__ void __launch_bounds__(kWave) k_kv_merge(MergeArgs a) {
         __syncthreads();
         continue;
       }
-      dst = a.arena + aoff;
     } else {
       wave_zero(img, S);
       __syncthreads();
     }
-    uint64_t* vdst = reinterpret_cast<uint64_t*>(to_arena ? dst + ((cl + 7u) & ~7u) : img + S - 8u * mn);
-    uint32_t run = 0;
-    for (uint32_t c0 = 0; c0 < mn; c0 += kWave) {
-      const uint32_t p = c0 + lane;
-      const uint32_t c = p < mn ? cost(p) : 0u;
-      const uint32_t incl = wave_incl_scan(c);
-      if (p < mn) {
-        uint8_t* q = dst + run + incl - c;
-        if (p == 0)
-          put_le64(q, M[0]);
-        else
-          vput(q, M[p] - M[p - 1]);
-        vdst[p] = MVp[p];
+    // codes from dst, values at vdst; instantiated once for the LDS image and
+    // once for the arena, so that each copy's stores have a known address
+    // space (a pointer that may be either compiles to generic stores)
+    auto write_leaf = [&](auto dst, auto vdst) {
+      uint32_t run = 0;
+      for (uint32_t c0 = 0; c0 < mn; c0 += kWave) {
+        const uint32_t p = c0 + lane;
+        const uint32_t c = p < mn ? cost(p) : 0u;
+        const uint32_t incl = wave_incl_scan(c);
+        if (p < mn) {
+          auto q = dst + run + incl - c;
+          if (p == 0)
+            put_le64(q, M[0]);
+          else
+            vput(q, M[p] - M[p - 1]);
+          vdst[p] = MVp[p];
+        }
+        run += lane63_u32(incl);
       }
-      run += lane63_u32(incl);
-    }
+    };
+    if (to_arena)
+      write_leaf(a.arena + aoff, reinterpret_cast<uint64_t*>(a.arena + aoff + ((cl + 7u) & ~7u)));
+    else
+      write_leaf(img, reinterpret_cast<uint64_t*>(img + S - 8u * mn));
     __syncthreads();
     if (!to_arena) wave_copy16(lp, img, S);
     if (lane == 0) {
