@@ -1237,6 +1237,36 @@ void reserve_batch(cpma* s, uint64_t kbound, bool insert) {
 
 // small: the small-batch kernel already wrote kprime, the segments, their routing and T.
 // rebuild: the batch is large enough for a full rebuild instead of counting.
+// Arguments of the merge kernels for the batch B (sorted, repeat-free) and the
+// segments of the current update.
+MergeArgs merge_args(cpma* s, const uint64_t* B, bool insert) {
+  MergeArgs a;
+  a.bytes = s->bytes.as<uint8_t>();
+  a.used = s->used.as<uint32_t>();
+  a.head = s->head.as<uint64_t>();
+  a.ovf = s->ovf.as<uint64_t>();
+  a.arena = s->arena.as<uint8_t>();
+  a.arena_cap = s->arena.cap;
+  a.stage = s->stage.as<uint64_t>();
+  a.stage_cap = s->stage.cap / sizeof(uint64_t);
+  a.B = B;
+  a.seg_leaf = s->seg_leaf.as<uint32_t>();
+  a.seg_begin = s->seg_begin.as<uint32_t>();
+  a.seg_desc = s->seg_desc.as<uint4>();
+  a.heavy_list = s->heavy.as<uint32_t>();
+  a.spill_list = s->spill.as<uint32_t>();
+  a.wide_list = s->wide.as<uint32_t>();
+  a.ctr = s->dctr;
+  a.S = s->S;
+  a.is_insert = insert ? 1 : 0;
+  a.kv = s->kv() ? 1u : 0u;
+  a.clen = s->clen.as<uint32_t>();
+  a.Bv = insert ? s->batch_vals : nullptr;
+  a.vstage = s->vstage.as<uint64_t>();
+  a.part = s->parts.as<unsigned long long>();
+  return a;
+}
+
 // Whether a small batch's path check runs as one block that also folds the
 // merge's totals and writes the counters to the host (at most 8192 (level,
 // segment) pairs: each of its threads takes one chunk of eight).
@@ -1292,29 +1322,7 @@ uint64_t apply_batch(cpma* s, const uint64_t* B, uint64_t kbound, bool insert, h
     HIPCHK(hipGetLastError());
   }
   phase_end(s, pl, st, 24ull * kbound);
-  MergeArgs a;
-  a.bytes = s->bytes.as<uint8_t>();
-  a.used = s->used.as<uint32_t>();
-  a.head = s->head.as<uint64_t>();
-  a.ovf = s->ovf.as<uint64_t>();
-  a.arena = s->arena.as<uint8_t>();
-  a.arena_cap = s->arena.cap;
-  a.stage = s->stage.as<uint64_t>();
-  a.stage_cap = s->stage.cap / sizeof(uint64_t);
-  a.B = B;
-  a.seg_leaf = s->seg_leaf.as<uint32_t>();
-  a.seg_begin = s->seg_begin.as<uint32_t>();
-  a.seg_desc = s->seg_desc.as<uint4>();
-  a.heavy_list = s->heavy.as<uint32_t>();
-  a.spill_list = s->spill.as<uint32_t>();
-  a.wide_list = s->wide.as<uint32_t>();
-  a.ctr = s->dctr;
-  a.S = s->S;
-  a.is_insert = insert ? 1 : 0;
-  a.kv = s->kv() ? 1u : 0u;
-  a.clen = s->clen.as<uint32_t>();
-  a.Bv = insert ? s->batch_vals : nullptr;
-  a.vstage = s->vstage.as<uint64_t>();
+  MergeArgs a = merge_args(s, B, insert);
   const MergeGrids mg = merge_grids(s, kbound);
   const uint32_t lgrid = mg.lgrid, wgrid = mg.wgrid, lwaves = mg.lwaves, hgrid_spill = mg.hgrid_spill;
   // per-wave totals: each launch owns a run of slot pairs, main-merge launches
@@ -1409,8 +1417,30 @@ bool wants_rebuild(const cpma* s, uint64_t k) {
 uint64_t apply_small(cpma* s, const uint64_t* src, uint64_t k, bool insert, hipStream_t st,
                      const ArgKeys* ak = nullptr) {
   reserve_batch(s, k, insert);
-  PhaseMark pm = phase_begin(s, CPMA_PHASE_SORT, st);
   static const ArgKeys kNoArgKeys{};
+  if (k <= kWaveSlice && s->S <= kWaveMaxS && !s->cfg.uncompressed && !s->kv() && !s->stats_on &&
+      finish_in_path_check(s, k)) {
+    // the whole update in one launch; a violated bound on a touched path falls
+    // back to the full count
+    MergeArgs a = merge_args(s, s->kdedup.as<uint64_t>(), insert);
+    Pyramid P = pyramid_layout(s->L);
+    P.base = s->pyr.as<uint64_t>();
+    s->mutating = true;
+    hipLaunchKernelGGL(k_small_update, dim3(1), dim3(kSmallThreads), 0, st, src, ak ? *ak : kNoArgKeys,
+                       (uint32_t)k, (const uint64_t*)s->head.as<uint64_t>(), s->L, s->kdedup.as<uint64_t>(),
+                       insert ? 1 : 0, a, s->bounds(s->L), P, s->hctr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    if (s->hctr->error) throw Fail{CPMA_ERR_DEVICE};
+    const Counters c = *s->hctr;
+    const uint64_t delta = take_merge(s, c, insert ? 1 : 0);
+    if (c.path_unsafe) {
+      s->pyr_valid = false;
+      rebalance(s, st);
+    }
+    return delta;
+  }
+  PhaseMark pm = phase_begin(s, CPMA_PHASE_SORT, st);
   hipLaunchKernelGGL(k_small_prep, dim3(1), dim3(kSmallThreads), 0, st, src, ak ? *ak : kNoArgKeys, (uint32_t)k,
                      (const uint64_t*)s->head.as<uint64_t>(), s->L, (const uint32_t*)s->used.as<uint32_t>(),
                      s->kdedup.as<uint64_t>(), s->seg_leaf.as<uint32_t>(), s->seg_begin.as<uint32_t>(),

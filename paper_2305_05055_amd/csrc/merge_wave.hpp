@@ -59,16 +59,47 @@ __device__ __forceinline__ void put_key_bytes(uint8_t* dst, bool head, KT x, KT 
 // halves the dominant LDS array.  KT = uint64_t: processes the handed-over list,
 // or with all_segments every segment not routed to the heavy merge (small
 // batches: one launch instead of two).
+//
+// The body runs as one wave with its own LDS (MergeLds); the merge kernel is one
+// wave per block, and the fused small-batch kernel runs several such waves in
+// one block, each on its own segments.  The wave's first segment is t0, it
+// takes every tstep-th one after it, and it leaves its totals in slot `slot`.
 template <typename KT>
-__global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segments = 0) {
+struct MergeLds {
+  alignas(16) uint8_t out[kWaveMaxS];  // the merged leaf image
+  KT K[kWaveMaxS];                     // decoded old keys
+  KT GK[kWaveSlice];                   // group g: its last key (new predecessor of old key GR[g])
+  uint32_t GR[kWaveSlice + 1];         // group g: rank; GR[ng] closes the table
+  uint32_t GB[kWaveSlice];             // group g: bytes of its codes
+  uint32_t GS[kWaveSlice];             // group g: output offset
+  uint32_t DF[kWaveMaxS / 32];         // delete flags by old index
+};
+
+// Orders the LDS traffic of the lanes sharing one MergeLds: the whole (one-wave)
+// block in the merge kernel, one wave of a larger block otherwise -- the same
+// workgroup-scope fences, without the block-wide barrier.
+template <bool kWaveOnly>
+__device__ __forceinline__ void merge_sync() {
+  if constexpr (kWaveOnly) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <typename KT, bool kWaveOnly>
+__device__ __forceinline__ void merge_wave_body(MergeArgs a, int all_segments, MergeLds<KT>& L, uint64_t t0,
+                                                uint64_t tstep, uint64_t slot) {
   constexpr bool kNarrow = sizeof(KT) == 4;
-  __shared__ KT K[kWaveMaxS];
-  __shared__ KT GK[kWaveSlice];            // group g: its last key (new predecessor of old key GR[g])
-  __shared__ uint32_t GR[kWaveSlice + 1];  // group g: rank; GR[ng] closes the table
-  __shared__ uint32_t GB[kWaveSlice];      // group g: bytes of its codes
-  __shared__ uint32_t GS[kWaveSlice];      // group g: output offset
-  __shared__ uint32_t DF[kWaveMaxS / 32];  // delete flags by old index
-  __shared__ __align__(16) uint8_t out[kWaveMaxS];
+  KT* const K = L.K;
+  KT* const GK = L.GK;
+  uint32_t* const GR = L.GR;
+  uint32_t* const GB = L.GB;
+  uint32_t* const GS = L.GS;
+  uint32_t* const DF = L.DF;
+  uint8_t* const out = L.out;
   const int lane = lane_id();
   const uint32_t S = a.S;
   const bool listed = !kNarrow && !all_segments;
@@ -84,7 +115,7 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segme
   uint64_t s_cur = 0, s_nxt = 0;
   uint4 w_cur = make_uint4(0, 0, 0, 0), w_nxt = w_cur;
   uint64_t b_cur = 0, b_nxt = 0;
-  uint64_t t = blockIdx.x;
+  uint64_t t = t0;
   if (t < T) {
     s_cur = seg_of(t);
     d_cur = a.seg_desc[s_cur];
@@ -94,8 +125,8 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segme
       if ((uint32_t)lane < e_cur - d_cur.y) b_cur = a.B[d_cur.y + lane];
     }
   }
-  for (; t < T; t += gridDim.x) {
-    const uint64_t tn = t + gridDim.x;
+  for (; t < T; t += tstep) {
+    const uint64_t tn = t + tstep;
     if (tn < T) {
       s_nxt = seg_of(tn);
       d_nxt = a.seg_desc[s_nxt];
@@ -194,7 +225,7 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segme
       if (lane == 0) GR[ng] = 0xffffffffu;
       const uint64_t newmask = __ballot(isnew);
       const uint32_t nnew = (uint32_t)__popcll(newmask);
-      __syncthreads();
+      merge_sync<kWaveOnly>();
       // first group at or after this lane's block
       uint32_t p0 = 0;
       {
@@ -263,7 +294,7 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segme
           }
           p += gh ? 1u : 0u;
         }
-        __syncthreads();
+        merge_sync<kWaveOnly>();
         if (isnew) put_key_bytes<KT>(dst + GS[gid] + (ex - exfirst), !has_pred, bj, pred, base);
       };
       if (to_arena)
@@ -276,7 +307,7 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segme
       delta += nnew;
     } else {
       for (uint32_t i = lane; i < kWaveMaxS / 32; i += kWave) DF[i] = 0;
-      __syncthreads();
+      merge_sync<kWaveOnly>();
       for (uint32_t c0 = 0; c0 < nb; c0 += kWave) {
         const uint32_t j = c0 + lane;
         if (j < nb) {
@@ -285,7 +316,7 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segme
           if (r < nA && K[r] == xr) atomicOr(&DF[r >> 5], 1u << (r & 31));
         }
       }
-      __syncthreads();
+      merge_sync<kWaveOnly>();
       auto gone = [&](uint32_t i) { return (DF[i >> 5] >> (i & 31)) & 1u; };
       // last kept index (+1) inside this lane's block, then across lanes
       uint32_t lastk = 0, lt = 0, nrem = 0;
@@ -329,7 +360,7 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segme
       first_key = (fkmin != 0xffffffffu) ? base + (uint64_t)K[fkmin] : kNoKey;
       delta += wave_sum(nrem);
     }
-    __syncthreads();
+    merge_sync<kWaveOnly>();
     if (!to_arena) {
       const uint32_t len = ((max(used0, U) + 15u) & ~15u);
       wave_copy16(lp, out, len);
@@ -342,14 +373,20 @@ __global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segme
       a.used[leaf] = U;
       a.head[leaf] = U ? first_key : kNoKey;
     }
-    __syncthreads();
+    merge_sync<kWaveOnly>();
   }
   // no atomics on shared counters (thousands of waves would serialise on
   // them): each wave leaves its totals in its own slot, summed by k_fold_parts
   if (lane == 0) {
-    a.part[2 * blockIdx.x] = delta;
-    a.part[2 * blockIdx.x + 1] = alg;
+    a.part[2 * slot] = delta;
+    a.part[2 * slot + 1] = alg;
   }
+}
+
+template <typename KT>
+__global__ void __launch_bounds__(kWave) k_merge_wave(MergeArgs a, int all_segments = 0) {
+  __shared__ MergeLds<KT> L;
+  merge_wave_body<KT, false>(a, all_segments, L, blockIdx.x, gridDim.x, blockIdx.x);
 }
 
 }  // namespace cpma_dev

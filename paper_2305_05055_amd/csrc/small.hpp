@@ -6,6 +6,7 @@
 // small update is bound by a handful of launches instead of dozens.  It also
 // zeroes the update's counters (it is the update's first kernel).
 #pragma once
+#include "merge_wave.hpp"
 #include "query.hpp"
 #include "update.hpp"
 
@@ -42,18 +43,23 @@ __device__ __forceinline__ uint32_t block_scan_u32(uint32_t v, uint32_t* wsum, u
 // Also routes the segments: an insert slice longer than `slice` keys goes to the
 // spill list (desc.w = 2), which the heavy merge takes; every other segment is
 // merged by the 64-bit wave instance (desc.w = 0).
-__global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __restrict__ in, ArgKeys ak, uint32_t k,
-                                                              const uint64_t* __restrict__ head, uint64_t L,
-                                                              const uint32_t* __restrict__ used,
-                                                              uint64_t* __restrict__ B, uint32_t* __restrict__ seg_leaf,
-                                                              uint32_t* __restrict__ seg_begin,
-                                                              uint4* __restrict__ seg_desc, int is_insert,
-                                                              uint32_t slice, uint32_t* __restrict__ spill_list,
-                                                              Counters* ctr) {
-  __shared__ uint64_t A[kSmallBatch];
-  __shared__ uint32_t LF[kSmallBatch];  // leaf of each key, then segment starts
-  __shared__ uint32_t wsum[kSmallThreads / kWave];
-  __shared__ uint32_t bad;
+struct SmallPrepLds {
+  uint64_t A[kSmallBatch];
+  uint32_t LF[kSmallBatch];  // leaf of each key, then segment starts
+  uint32_t wsum[kSmallThreads / kWave];
+  uint32_t bad;
+};
+
+__device__ __forceinline__ void small_prep_body(const uint64_t* __restrict__ in, const ArgKeys& ak, uint32_t k,
+                                                const uint64_t* __restrict__ head, uint64_t L,
+                                                const uint32_t* __restrict__ used, uint64_t* __restrict__ B,
+                                                uint32_t* __restrict__ seg_leaf, uint32_t* __restrict__ seg_begin,
+                                                uint4* __restrict__ seg_desc, int is_insert, uint32_t slice,
+                                                uint32_t* __restrict__ spill_list, Counters* ctr, SmallPrepLds& sm) {
+  uint64_t* const A = sm.A;
+  uint32_t* const LF = sm.LF;
+  uint32_t* const wsum = sm.wsum;
+  uint32_t& bad = sm.bad;
   const uint32_t tid = threadIdx.x;
   constexpr uint32_t kPer = kSmallBatch / kSmallThreads;
   uint32_t n = 1;
@@ -254,6 +260,18 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __
   }
 }
 
+__global__ void __launch_bounds__(kSmallThreads) k_small_prep(const uint64_t* __restrict__ in, ArgKeys ak, uint32_t k,
+                                                              const uint64_t* __restrict__ head, uint64_t L,
+                                                              const uint32_t* __restrict__ used,
+                                                              uint64_t* __restrict__ B, uint32_t* __restrict__ seg_leaf,
+                                                              uint32_t* __restrict__ seg_begin,
+                                                              uint4* __restrict__ seg_desc, int is_insert,
+                                                              uint32_t slice, uint32_t* __restrict__ spill_list,
+                                                              Counters* ctr) {
+  __shared__ SmallPrepLds sm;
+  small_prep_body(in, ak, k, head, L, used, B, seg_leaf, seg_begin, seg_desc, is_insert, slice, spill_list, ctr, sm);
+}
+
 // ---- counting for a small batch: the paths of the touched leaves only ----------
 // A rebalance ends only when its count finds no node to redistribute, so then
 // every node of the implicit tree is within its density bounds (a violating
@@ -275,16 +293,24 @@ constexpr uint32_t kPathThreads = 1024;
 // `part` holds n_narrow then n_wide slot pairs), and at the end copies the
 // counters to host memory `hout`, so the host reads them after one stream
 // synchronisation with no copy launch in between.
-__global__ void __launch_bounds__(kPathThreads) k_path_check(Bounds bd, Pyramid P, const uint32_t* __restrict__ used,
-                                                             const uint32_t* __restrict__ seg_leaf,
-                                                             const uint4* __restrict__ seg_desc, Counters* ctr,
-                                                             const unsigned long long* __restrict__ part,
-                                                             uint32_t n_narrow, uint32_t n_wide, Counters* hout) {
-  __shared__ uint32_t lf[kSmallBatch];
-  __shared__ uint64_t G[kSmallBatch + 1];  // G[t]: growth of the segments before t (mod 2^64)
-  __shared__ uint64_t wsum[kPathThreads / kWave];
-  __shared__ uint64_t red[3][kPathThreads / kWave];
-  __shared__ uint32_t bad;
+struct PathLds {
+  uint32_t lf[kSmallBatch];
+  uint64_t G[kSmallBatch + 1];  // G[t]: growth of the segments before t (mod 2^64)
+  uint64_t wsum[kPathThreads / kWave];
+  uint64_t red[3][kPathThreads / kWave];
+  uint32_t bad;
+};
+
+__device__ __forceinline__ void path_check_body(Bounds bd, Pyramid P, const uint32_t* __restrict__ used,
+                                                const uint32_t* __restrict__ seg_leaf,
+                                                const uint4* __restrict__ seg_desc, Counters* ctr,
+                                                const unsigned long long* __restrict__ part, uint32_t n_narrow,
+                                                uint32_t n_wide, Counters* hout, PathLds& pl) {
+  uint32_t* const lf = pl.lf;
+  uint64_t* const G = pl.G;
+  uint64_t* const wsum = pl.wsum;
+  auto& red = pl.red;
+  uint32_t& bad = pl.bad;
   constexpr uint32_t kPer = kSmallBatch / kPathThreads;
   const uint32_t tid = threadIdx.x;
   if (part) {
@@ -402,6 +428,47 @@ __global__ void __launch_bounds__(kPathThreads) k_path_check(Bounds bd, Pyramid 
       __threadfence_system();
     }
   }
+}
+
+__global__ void __launch_bounds__(kPathThreads) k_path_check(Bounds bd, Pyramid P, const uint32_t* __restrict__ used,
+                                                             const uint32_t* __restrict__ seg_leaf,
+                                                             const uint4* __restrict__ seg_desc, Counters* ctr,
+                                                             const unsigned long long* __restrict__ part,
+                                                             uint32_t n_narrow, uint32_t n_wide, Counters* hout) {
+  __shared__ PathLds pl;
+  path_check_body(bd, P, used, seg_leaf, seg_desc, ctr, part, n_narrow, n_wide, hout, pl);
+}
+
+// ---- a whole small update in one launch --------------------------------------
+// For batches of at most kWaveSlice keys (no insert slice can then spill): the
+// preparation above, the merge of every touched leaf (kFusedMergeWaves waves of
+// the block, one leaf at a time each, as the merge kernel's waves do), and the
+// path check of the touched leaves, which also folds the merge's totals and
+// writes the counters to host memory.  The three phases run back to back on
+// one block, their intermediate results read from where the phase before
+// wrote them (block barriers in between), instead of as three launches.
+constexpr uint32_t kFusedMergeWaves = 12;
+
+__global__ void __launch_bounds__(kSmallThreads) k_small_update(const uint64_t* __restrict__ in, ArgKeys ak,
+                                                                uint32_t k, const uint64_t* __restrict__ head,
+                                                                uint64_t L, uint64_t* __restrict__ B,
+                                                                int is_insert, MergeArgs ma, Bounds bd, Pyramid P,
+                                                                Counters* hout) {
+  static_assert(kFusedMergeWaves * kWave <= kSmallThreads, "merge waves fit in the block");
+  __shared__ union {
+    SmallPrepLds prep;
+    MergeLds<uint64_t> merge[kFusedMergeWaves];
+    PathLds path;
+  } lds;
+  // the segment arrays the merge reads are the ones the preparation writes
+  small_prep_body(in, ak, k, head, L, ma.used, B, const_cast<uint32_t*>(ma.seg_leaf),
+                  const_cast<uint32_t*>(ma.seg_begin), const_cast<uint4*>(ma.seg_desc), is_insert, kWaveSlice,
+                  ma.spill_list, ma.ctr, lds.prep);
+  __syncthreads();
+  const uint32_t w = threadIdx.x / kWave;
+  if (w < kFusedMergeWaves) merge_wave_body<uint64_t, true>(ma, 1, lds.merge[w], w, kFusedMergeWaves, w);
+  __syncthreads();
+  path_check_body(bd, P, ma.used, ma.seg_leaf, ma.seg_desc, ma.ctr, ma.part, 0, kFusedMergeWaves, hout, lds.path);
 }
 
 }  // namespace cpma_dev

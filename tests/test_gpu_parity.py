@@ -495,3 +495,47 @@ def test_allocator_hooks(cp, orc):
         cp.CPMA(keys, config=cfg)
     assert e.value.code == 2
     assert not live
+
+
+@pytest.mark.parametrize("bounds", [None, (0.99, 0.90, 0.10, 0.30)])
+def test_dense_leaves(cp, orc, bounds):
+    """Leaves of 1-byte codes at their density bounds (up to about a thousand
+    keys in a 1 KiB leaf, the most the wave merge's key array holds): inserts
+    concentrated in one key range (large batches, then small ones) fill its
+    leaves, then deletes hit them, each batch checked against the oracle."""
+    params = bounds or orc.DEFAULT_PARAMS
+    base = np.arange(0, 400000, 2, dtype=np.uint64)  # gap 2: every code one byte
+    expect = orc.build_set(base)
+    c = cp.CPMA(base, leaf_bytes=1024, bounds=bounds)
+    check(c, expect, orc, params)
+    odd = np.arange(1, 80000, 2, dtype=np.uint64)  # the dense range: [0, 80000)
+    rng = np.random.default_rng(5)
+    rng.shuffle(odd)
+    # a leaf of 1-byte codes holds used - 7 keys; batches must meet leaves of
+    # more than 768 keys (more than 896 with the looser bounds)
+    dense = 903 if bounds else 775
+    seen = 0
+    pos = 0
+    for k in [8000, 8000, 8000, 6000, 4000, 2000, 1000, 1000, 500, 64, 7]:
+        batch = odd[pos:pos + k]
+        pos += k
+        new, added = orc.insert(expect, batch)
+        assert c.insert_batch(batch) == added
+        expect = new
+        check(c, expect, orc, params)
+        _, u, _ = c.export()
+        seen = max(seen, int(u.max()))
+    assert seen > dense
+    dense_keys = expect[expect < np.uint64(80000)]
+    for k in [5000, 3000, 700, 60, 5]:
+        batch = dense_keys[synth.sample_indices(len(dense_keys), k, 900 + k)]
+        new, removed = orc.delete(expect, batch)
+        assert c.delete_batch(batch) == removed
+        expect = new
+        dense_keys = expect[expect < np.uint64(80000)]
+        check(c, expect, orc, params)
+    lo = np.arange(0, 400000, 9973, dtype=np.uint64)
+    hi = lo + np.uint64(50000)
+    s, n = c.range_map(lo, hi)
+    es, en = orc.range_map(expect, lo, hi)
+    assert np.array_equal(s, es) and np.array_equal(n, en)
