@@ -314,6 +314,41 @@ void scan(cpma* s, T* out, uint64_t n, hipStream_t st, F fn) {
   HIPCHK(scan_exclusive<T>(fn, n, out, s->scan_tmp.as<T>(), st));
 }
 
+// MSD split of an unsorted batch into buckets small enough for one block's
+// LDS, then every bucket sorted there (src -> kb0 -> kb1).  The bucket count
+// makes an average bucket about 0.8 kBktCap keys; the low bits sorted inside a
+// bucket must fit 32 bits.  The largest bucket is read back before the split
+// is written: false (nothing written but the counts) if one exceeds kBktCap,
+// as skewed batches can, and the caller sorts with LSD passes instead.
+bool msd_split_sort(cpma* s, const uint64_t* src, uint64_t k, int bits, hipStream_t st) {
+  int b = kMsdMinBits;
+  while (b < kMsdMaxBits && (k >> b) > kBktTarget) b++;
+  b = std::min(b, bits);
+  const int r = bits - b;
+  if (r > 32 || (k >> b) > kBktTarget) return false;
+  const uint32_t nd = 1u << b;
+  const uint32_t nt = (uint32_t)((k + kMsdTile - 1) / kMsdTile);
+  const uint64_t nc = (uint64_t)nd * nt;
+  ensure(s->cnt, (nc + 1) * sizeof(uint32_t));
+  ensure(s->koff, (nc + 1) * sizeof(uint32_t));
+  hipLaunchKernelGGL(k_msd_hist, dim3(nt), dim3(kMsdThreads), 0, st, src, (uint32_t)k, r, nd, s->cnt.as<uint32_t>());
+  HIPCHK(hipGetLastError());
+  scan<uint32_t>(s, s->koff.as<uint32_t>(), nc, st, LoadFn<uint32_t>{s->cnt.as<uint32_t>()});
+  hipLaunchKernelGGL(k_msd_max, dim3(1), dim3(kMsdThreads), 0, st, (const uint32_t*)s->koff.as<uint32_t>(), nt, nd,
+                     s->dinfo);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(s->hinfo, s->dinfo, sizeof(BatchInfo), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (s->hinfo->max_bucket > kBktCap) return false;
+  hipLaunchKernelGGL(k_msd_scatter, dim3(nt), dim3(kMsdThreads), 0, st, src, s->kb0.as<uint64_t>(), (uint32_t)k, r,
+                     nd, (const uint32_t*)s->koff.as<uint32_t>());
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_bucket_sort, dim3(nd), dim3(kBktThreads), 0, st, (const uint64_t*)s->kb0.as<uint64_t>(),
+                     s->kb1.as<uint64_t>(), (const uint32_t*)s->koff.as<uint32_t>(), nt, r, s->dinfo);
+  HIPCHK(hipGetLastError());
+  return true;
+}
+
 // ---------------------------------------------------------------------------
 // Batch prep: device copy, validation, radix sort, removal of repeats.
 // Returns the device pointer of the sorted repeat-free batch; its length is in
@@ -329,31 +364,41 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
   }
   hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(s->dinfo),
                      (uint64_t)(sizeof(BatchInfo) / 4), 0u);
-  // validation reads every key once and counts the first radix digit per sort
-  // tile on the way (used if the batch turns out unsorted)
+  // validation reads every key once; below the MSD split's size it also
+  // counts the first radix digit per sort tile (used if the batch turns out
+  // unsorted)
   const uint32_t nblk = (uint32_t)((k + kSortTile - 1) / kSortTile);
   ensure(s->cnt, ((uint64_t)nblk * 256 + 1) * sizeof(uint32_t));
   ensure(s->koff, ((uint64_t)nblk * 256 + 1) * sizeof(uint32_t));
-  hipLaunchKernelGGL(k_validate_hist, dim3(nblk), dim3(kSortThreads), 0, st, src, (uint32_t)k, s->dinfo,
-                     s->cnt.as<uint32_t>());
+  const bool msd_size = k >= kMsdMinKeys && k <= kMsdMaxKeys;
+  if (msd_size)
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(k, 256, 4096)), dim3(256), 0, st, src, k, s->dinfo);
+  else
+    hipLaunchKernelGGL(k_validate_hist, dim3(nblk), dim3(kSortThreads), 0, st, src, (uint32_t)k, s->dinfo,
+                       s->cnt.as<uint32_t>());
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(s->hinfo, s->dinfo, sizeof(BatchInfo), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (s->hinfo->has_reserved) throw Fail{CPMA_ERR_RESERVED_KEY};
 
   const uint64_t* sorted = src;
-  int passes_done = 0;
   PhaseMark pm = phase_begin(s, CPMA_PHASE_SORT, st);
+  uint64_t sort_bytes = 0;
   if (s->hinfo->unsorted) {
     const uint64_t orv = s->hinfo->or_all;
     int bits = 64 - __builtin_clzll(orv | 1);
     int passes = (bits + 7) / 8;
     ensure(s->kb0, k * sizeof(uint64_t));
     ensure(s->kb1, k * sizeof(uint64_t));
+    if (msd_size && msd_split_sort(s, src, k, bits, st)) {
+      sorted = s->kb1.as<uint64_t>();
+      sort_bytes = 40ull * k;  // count (read), split (read + write), bucket sort (read + write)
+      passes = 0;
+    }
     const uint64_t* in = src;
     for (int p = 0; p < passes; p++) {
       uint64_t* out = (p & 1) ? s->kb1.as<uint64_t>() : s->kb0.as<uint64_t>();
-      if (p > 0)  // the first pass's counts came with the validation
+      if (p > 0 || msd_size)  // else the first pass's counts came with the validation
         hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, st, in, (uint32_t)k, 8 * p,
                            s->cnt.as<uint32_t>());
       HIPCHK(hipGetLastError());
@@ -364,8 +409,10 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
       HIPCHK(hipGetLastError());
       in = out;
     }
-    sorted = in;
-    passes_done = passes;
+    if (passes) {
+      sorted = in;
+      sort_bytes = 24ull * k * (uint64_t)passes;
+    }
   }
   ensure(s->kdedup, k * sizeof(uint64_t));
   {
@@ -379,7 +426,7 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
                        (const uint32_t*)s->koff.as<uint32_t>(), nt, s->kdedup.as<uint64_t>(), &s->dctr->kprime);
     HIPCHK(hipGetLastError());
   }
-  phase_end(s, pm, st, 24ull * k * (uint64_t)(passes_done + 1));
+  phase_end(s, pm, st, sort_bytes + 24ull * k);
   return s->kdedup.as<uint64_t>();
 }
 

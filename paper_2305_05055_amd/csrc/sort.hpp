@@ -18,6 +18,8 @@ struct BatchInfo {
   unsigned long long or_all;
   unsigned int has_reserved;
   unsigned int unsorted;
+  unsigned int max_bucket;  // largest MSD bucket of a split (large batches)
+  unsigned int pad;
 };
 
 __global__ void __launch_bounds__(256) k_validate(const uint64_t* __restrict__ keys, uint64_t k,
@@ -273,6 +275,254 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter_kv(const uint64_
   __shared__ uint32_t gbase[256];
   __shared__ uint32_t wsum[kScatterWaves];
   radix_scatter_tile<true>(in, out, n, shift, goff, vin, vgen, vout, tile, vtile, cnt, toff, gbase, wsum);
+}
+
+// Large batches: one MSD split, then every bucket sorted inside LDS.
+//
+// The top b bits of a key (b = 8..11, chosen by the host so that an average
+// bucket holds about 0.8 kBktCap keys) pick its bucket; the low r = bits - b
+// bits (r <= 32) are sorted inside the bucket.  k_msd_hist counts the buckets
+// per tile ([bucket][tile], scanned into output offsets as for the LSD
+// passes); k_msd_scatter moves every tile's keys to their buckets through an
+// LDS copy of the tile in bucket order, so each bucket's run of a tile is
+// written contiguously; k_bucket_sort then loads one bucket per block, sorts
+// the 32-bit low parts with stable 8-bit LSD passes inside LDS and writes the
+// bucket back in order.  Two passes over HBM replace the five of a 40-bit
+// LSD sort.  Order inside a bucket before its sort does not matter, so the
+// split ranks keys with LDS atomics.
+constexpr int kMsdThreads = 1024;
+constexpr int kMsdItems = 16;
+constexpr uint32_t kMsdTile = kMsdThreads * kMsdItems;  // keys per split block
+constexpr int kMsdMaxBits = 11;                          // at most 2048 buckets
+constexpr uint32_t kMsdMaxBuckets = 1u << kMsdMaxBits;
+constexpr int kBktThreads = 1024;
+constexpr int kBktWaves = kBktThreads / kWave;
+constexpr int kBktRounds = 12;                           // rounds of 64 keys per wave
+constexpr uint32_t kBktCap = kBktThreads * kBktRounds;   // keys per bucket (12288)
+constexpr uint64_t kBktTarget = kBktCap * 4 / 5;          // average bucket the host aims for
+constexpr int kMsdMinBits = 8;
+constexpr uint64_t kMsdMinKeys = 1ull << 19;              // smaller batches take the LSD passes
+constexpr uint64_t kMsdMaxKeys = kBktTarget << kMsdMaxBits;
+
+__device__ __forceinline__ uint32_t msd_bucket(uint64_t x, int r, uint32_t nd) {
+  // clamped so that a key outside the announced bit length cannot index past
+  // the counters (the host derives r from the OR of the same keys)
+  return (uint32_t)min<uint64_t>(x >> r, (uint64_t)(nd - 1));
+}
+
+__global__ void __launch_bounds__(kMsdThreads) k_msd_hist(const uint64_t* __restrict__ in, uint32_t n, int r,
+                                                          uint32_t nd, uint32_t* __restrict__ counts) {
+  __shared__ uint32_t h[kMsdMaxBuckets];
+  for (uint32_t d = threadIdx.x; d < kMsdMaxBuckets; d += kMsdThreads) h[d] = 0;
+  __syncthreads();
+  const uint32_t base = blockIdx.x * kMsdTile;
+  uint64_t x[kMsdItems];
+#pragma unroll
+  for (int j = 0; j < kMsdItems; j++) {
+    const uint32_t i = base + j * kMsdThreads + threadIdx.x;
+    x[j] = i < n ? in[i] : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < kMsdItems; j++)
+    if (base + j * kMsdThreads + threadIdx.x < n) atomicAdd(&h[msd_bucket(x[j], r, nd)], 1u);
+  __syncthreads();
+  for (uint32_t d = threadIdx.x; d < nd; d += kMsdThreads) counts[(uint64_t)d * gridDim.x + blockIdx.x] = h[d];
+}
+
+// Largest bucket after the scan of k_msd_hist's counts (koff[d * ntiles] is
+// where bucket d starts, koff[nd * ntiles] the total).
+__global__ void __launch_bounds__(kMsdThreads) k_msd_max(const uint32_t* __restrict__ koff, uint32_t ntiles,
+                                                         uint32_t nd, BatchInfo* __restrict__ info) {
+  uint32_t m = 0;
+  for (uint32_t d = threadIdx.x; d < nd; d += kMsdThreads)
+    m = max(m, koff[(uint64_t)(d + 1) * ntiles] - koff[(uint64_t)d * ntiles]);
+  m = __shfl(dpp_incl_max(m), kWave - 1);
+  if (lane_id() == 0 && m) atomicMax(&info->max_bucket, m);
+}
+
+__global__ void __launch_bounds__(kMsdThreads) k_msd_scatter(const uint64_t* __restrict__ in,
+                                                             uint64_t* __restrict__ out, uint32_t n, int r,
+                                                             uint32_t nd, const uint32_t* __restrict__ koff) {
+  __shared__ uint64_t tile[kMsdTile];
+  __shared__ uint32_t h[kMsdMaxBuckets];   // counts, then the tile's bucket offsets
+  __shared__ uint32_t gb[kMsdMaxBuckets];  // the tile's output position per bucket
+  __shared__ uint32_t wsum[kMsdThreads / kWave];
+  const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+  for (uint32_t d = tid; d < kMsdMaxBuckets; d += kMsdThreads) h[d] = 0;
+  for (uint32_t d = tid; d < nd; d += kMsdThreads) gb[d] = koff[(uint64_t)d * gridDim.x + blockIdx.x];
+  __syncthreads();
+  const uint32_t base = blockIdx.x * kMsdTile;
+  uint64_t x[kMsdItems];
+  uint32_t rk[kMsdItems];
+#pragma unroll
+  for (int j = 0; j < kMsdItems; j++) {
+    const uint32_t i = base + j * kMsdThreads + tid;
+    x[j] = i < n ? in[i] : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < kMsdItems; j++)
+    if (base + j * kMsdThreads + tid < n) rk[j] = atomicAdd(&h[msd_bucket(x[j], r, nd)], 1u);
+  __syncthreads();
+  // exclusive scan of the 2048 counters, two per thread
+  static_assert(kMsdMaxBuckets == 2 * kMsdThreads, "two counters per thread");
+  const uint32_t c0 = h[2 * tid], c1 = h[2 * tid + 1];
+  const uint32_t incl = wave_incl_scan(c0 + c1);
+  if (lane == kWave - 1) wsum[wid] = incl;
+  __syncthreads();
+  uint32_t wofs = 0;
+#pragma unroll
+  for (int w = 0; w < kMsdThreads / kWave; w++)
+    if (w < wid) wofs += wsum[w];
+  const uint32_t ex = wofs + incl - (c0 + c1);
+  h[2 * tid] = ex;
+  h[2 * tid + 1] = ex + c0;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kMsdItems; j++)
+    if (base + j * kMsdThreads + tid < n) tile[h[msd_bucket(x[j], r, nd)] + rk[j]] = x[j];
+  __syncthreads();
+  const uint32_t m = min(kMsdTile, n - base);
+  for (uint32_t i = tid; i < m; i += kMsdThreads) {
+    const uint64_t y = tile[i];
+    const uint32_t d = msd_bucket(y, r, nd);
+    out[gb[d] + (i - h[d])] = y;
+  }
+}
+
+// Lanes of the wave whose bit B of y matches this lane's, as two 32-bit
+// halves: the sign-extended bit is 0 or all ones, so ~(ballot ^ bit) keeps the
+// lanes that agree.
+template <int B>
+__device__ __forceinline__ void match_bit(uint32_t y, uint32_t& p0, uint32_t& p1) {
+  uint32_t sb;
+  asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(sb) : "v"(y), "i"(B));
+  const uint64_t m = __ballot(sb != 0);
+  p0 &= ~((uint32_t)m ^ sb);
+  p1 &= ~((uint32_t)(m >> 32) ^ sb);
+}
+
+// One block per bucket (nd blocks).  Wave w holds items w * 768 + 64 j + l of
+// the current order (round j, lane l) in registers; each pass sorts them by
+// one 8-bit digit of the low part, least significant first, through LDS.
+// The first pass may reorder equal digits (the order it starts from is
+// arbitrary), so it ranks with LDS atomics.  The later passes are stable: a
+// lane's rank among equal digits of its round comes from eight ballots, and
+// wave-private counters in LDS carry the count across rounds (every lane
+// reads its digit's counter, then the group's lowest lane adds the group;
+// LDS executes one wave's operations in order, so no wait is needed between
+// rounds).  The host launches this only when every bucket holds at most
+// kBktCap keys; a larger one is left unsorted and flagged.
+__global__ void __launch_bounds__(kBktThreads) k_bucket_sort(const uint64_t* __restrict__ in,
+                                                             uint64_t* __restrict__ out,
+                                                             const uint32_t* __restrict__ koff, uint32_t ntiles,
+                                                             int r, BatchInfo* __restrict__ info) {
+  __shared__ uint32_t buf[kBktCap];
+  __shared__ uint32_t cnt[kBktWaves][256];  // the first pass uses row 0 for the whole block
+  __shared__ uint32_t wsum[256 / kWave];
+  const uint32_t bkt = blockIdx.x;
+  const uint32_t beg = koff[(uint64_t)bkt * ntiles];
+  const uint32_t n = koff[(uint64_t)(bkt + 1) * ntiles] - beg;
+  if (n > kBktCap) {
+    if (threadIdx.x == 0) atomicOr(&info->unsorted, 2u);
+    return;
+  }
+  const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+  const uint32_t wb = (uint32_t)wid * (kBktRounds * kWave);
+  const uint32_t lowmask = r >= 32 ? 0xffffffffu : ((1u << r) - 1u);
+  uint32_t x[kBktRounds];
+#pragma unroll
+  for (int j = 0; j < kBktRounds; j++) {
+    const uint32_t i = wb + (uint32_t)j * kWave + lane;
+    x[j] = i < n ? (uint32_t)in[beg + i] & lowmask : 0u;
+  }
+  for (int sh = 0; sh < r; sh += 8) {
+    const bool first = sh == 0;
+#pragma unroll
+    for (int q = 0; q < kBktWaves * 256 / kBktThreads; q++) (&cnt[0][0])[q * kBktThreads + tid] = 0;
+    __syncthreads();
+    uint32_t rk[kBktRounds];
+    if (wb < n) {  // waves past the bucket's end rank nothing
+      if (first) {
+#pragma unroll
+        for (int j = 0; j < kBktRounds; j++)
+          if (wb + (uint32_t)j * kWave + lane < n) rk[j] = atomicAdd(&cnt[0][x[j] & 255u], 1u);
+      } else {
+        uint32_t pre[kBktRounds];
+#pragma unroll
+        for (int j = 0; j < kBktRounds; j++) {
+          const bool valid = wb + (uint32_t)j * kWave + lane < n;
+          const uint32_t y = x[j] >> sh;
+          const uint64_t vm = __ballot(valid);
+          uint32_t p0 = (uint32_t)vm, p1 = (uint32_t)(vm >> 32);
+          match_bit<0>(y, p0, p1);
+          match_bit<1>(y, p0, p1);
+          match_bit<2>(y, p0, p1);
+          match_bit<3>(y, p0, p1);
+          match_bit<4>(y, p0, p1);
+          match_bit<5>(y, p0, p1);
+          match_bit<6>(y, p0, p1);
+          match_bit<7>(y, p0, p1);
+          const uint32_t below = __builtin_amdgcn_mbcnt_hi(p1, __builtin_amdgcn_mbcnt_lo(p0, 0u));
+          uint32_t* c = &cnt[wid][y & 255u];
+          pre[j] = valid ? *c : 0u;
+          if (valid && below == 0) atomicAdd(c, (uint32_t)(__popc(p0) + __popc(p1)));
+          rk[j] = below;
+        }
+#pragma unroll
+        for (int j = 0; j < kBktRounds; j++) rk[j] += pre[j];
+      }
+    }
+    __syncthreads();
+    // digit offsets: threads 0..255 own one digit each
+    uint32_t tot = 0, incl = 0;
+    if (tid < 256) {
+      if (first) {
+        tot = cnt[0][tid];
+      } else {
+#pragma unroll
+        for (int w = 0; w < kBktWaves; w++) tot += cnt[w][tid];
+      }
+      incl = wave_incl_scan(tot);
+      if (lane == kWave - 1) wsum[wid] = incl;
+    }
+    __syncthreads();
+    if (tid < 256) {
+      uint32_t run = incl - tot;
+#pragma unroll
+      for (int w = 0; w < 256 / kWave; w++)
+        if (w < wid) run += wsum[w];
+      if (first) {
+        cnt[0][tid] = run;
+      } else {
+#pragma unroll
+        for (int w = 0; w < kBktWaves; w++) {
+          const uint32_t c = cnt[w][tid];
+          cnt[w][tid] = run;  // wave w's first slot for digit tid
+          run += c;
+        }
+      }
+    }
+    __syncthreads();
+    if (wb < n) {
+      const int row = first ? 0 : wid;
+#pragma unroll
+      for (int j = 0; j < kBktRounds; j++)
+        if (wb + (uint32_t)j * kWave + lane < n) buf[cnt[row][(x[j] >> sh) & 255u] + rk[j]] = x[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kBktRounds; j++) {
+      const uint32_t i = wb + (uint32_t)j * kWave + lane;
+      if (i < n) x[j] = buf[i];
+    }
+    __syncthreads();  // the next pass clears the counters the scatter read
+  }
+  const uint64_t hi = (uint64_t)bkt << r;
+#pragma unroll
+  for (int j = 0; j < kBktRounds; j++) {
+    const uint32_t i = wb + (uint32_t)j * kWave + lane;
+    if (i < n) out[beg + i] = hi | x[j];
+  }
 }
 
 // Flags of first occurrences in a sorted array.

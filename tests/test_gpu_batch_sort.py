@@ -1,0 +1,102 @@
+"""Batch preparation of large unsorted batches: the MSD split into buckets
+followed by a sort of every bucket in LDS, and its hand-off to the LSD radix
+passes (batches below the split's size, low parts wider than 32 bits, buckets
+larger than one block's LDS, batches above the split's size).  Every case
+inserts an unsorted batch (with repeats) into a CPMA and checks the whole
+exported image against the oracle's set through the structure checker; the
+path taken is read from the sort phase's algorithmic bytes per key: 64 for
+the split (count 8, split 16, bucket sort 16, repeat removal 24), 24 per LSD
+pass plus 24 for the LSD sort."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+MSD = "msd"
+
+
+def lsd(passes):
+    return 24 * passes + 24
+
+
+@pytest.fixture(scope="module")
+def cp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2305_05055_amd as p
+    p.lib()
+    return p
+
+
+def shuffled(a, seed):
+    return a[np.random.default_rng(seed).permutation(len(a))]
+
+
+def clustered(n, seed):
+    """Two thirds uniform 40-bit keys, one third inside one 2^20-wide window:
+    that window's bucket outgrows a block's LDS."""
+    u = synth.uniform_keys(n - n // 3, seed, bits=40)
+    c = np.uint64(0x5A5A500000) + synth.uniform_keys(n // 3, seed + 1, bits=20)
+    return shuffled(np.concatenate([u, c]), seed + 2)
+
+
+CASES = [
+    # (name, batch generator, expected path)
+    ("threshold_40bit", lambda s: synth.uniform_keys(1 << 19, s, bits=40), MSD),
+    ("below_threshold", lambda s: synth.uniform_keys((1 << 19) - 1, s, bits=40), lsd(5)),
+    ("narrow_20bit_repeats", lambda s: synth.uniform_keys(1_000_000, s, bits=20), MSD),
+    ("low_part_33_bits", lambda s: synth.uniform_keys(1_000_000, s, bits=41), lsd(6)),
+    ("byte_keys_no_low_part", lambda s: synth.uniform_keys(600_000, s, bits=8), MSD),
+    ("zipf_overflowing_bucket", lambda s: shuffled(synth.zipf_keys(1_000_000, s, bits=34), s + 9), lsd(5)),
+    ("clustered_overflowing_bucket", lambda s: clustered(3_000_000, s), lsd(5)),
+    ("top_bucket_count_40bit", lambda s: synth.uniform_keys(20_000_000, s, bits=40), MSD),
+]
+
+
+def sort_bytes_per_key(c, k):
+    return c.stats()["sort"][2] / k
+
+
+def check_image(c, expect, orc):
+    b, u, h = c.export()
+    code, msg = orc.check_image(b, u, h, c.geometry()[1], expect)
+    assert code == 0, msg
+    assert c.size() == len(expect)
+
+
+@pytest.mark.parametrize("name,gen,path", CASES, ids=[c[0] for c in CASES])
+def test_large_unsorted_insert(cp, orc, name, gen, path):
+    seed = synth.SEED_BASE + 1200 + 10 * CASES.index((name, gen, path))
+    base = synth.uniform_keys(100_000, seed, bits=40)
+    batch = gen(seed + 3)
+    print(f"[batch sort] {name}: k={len(batch)}", flush=True)
+    assert np.any(batch[1:] < batch[:-1]), "the batch must be unsorted"
+    c = cp.CPMA(base)
+    S = orc.build_set(base)
+    S, added = orc.insert(S, batch)
+    c.stats_select(["sort"])
+    assert c.insert_batch(batch) == added
+    per_key = sort_bytes_per_key(c, len(batch))
+    assert per_key == (64 if path == MSD else path), per_key
+    c.stats_select([])
+    check_image(c, S, orc)
+
+
+def test_large_unsorted_delete(cp, orc):
+    """A delete batch takes the same preparation: half its keys present, half
+    absent, with repeats, in random order."""
+    seed = synth.SEED_BASE + 1300
+    base = synth.unique_uniform_keys(2_000_000, seed, bits=40)
+    c = cp.CPMA(base)
+    S = orc.build_set(base)
+    present = base[synth.sample_indices(len(base), 400_000, seed + 1)]
+    absent = synth.uniform_keys(400_000, seed + 2, bits=40)
+    batch = shuffled(np.concatenate([present, present[:100_000], absent]), seed + 3)
+    S, removed = orc.delete(S, batch)
+    c.stats_select(["sort"])
+    assert c.delete_batch(batch) == removed
+    assert sort_bytes_per_key(c, len(batch)) == 64
+    c.stats_select([])
+    check_image(c, S, orc)
