@@ -315,11 +315,13 @@ void scan(cpma* s, T* out, uint64_t n, hipStream_t st, F fn) {
 }
 
 // MSD split of an unsorted batch into buckets small enough for one block's
-// LDS, then every bucket sorted there (src -> kb0 -> kb1).  The bucket count
-// makes an average bucket about 0.8 kBktCap keys; the low bits sorted inside a
-// bucket must fit 32 bits.  The largest bucket is read back before the split
-// is written: false (nothing written but the counts) if one exceeds kBktCap,
-// as skewed batches can, and the caller sorts with LSD passes instead.
+// LDS, then every bucket sorted there with its repeats removed (src -> kb0 ->
+// kb1), then the buckets' first occurrences packed into kdedup (their number
+// in dctr->kprime).  The bucket count makes an average bucket about 0.8
+// kBktCap keys; the low bits sorted inside a bucket must fit 32 bits.  The
+// largest bucket is read back before the split is written: false (nothing
+// written but the counts) if one exceeds kBktCap, as skewed batches can, and
+// the caller sorts with LSD passes instead.
 bool msd_split_sort(cpma* s, const uint64_t* src, uint64_t k, int bits, hipStream_t st) {
   int b = kMsdMinBits;
   while (b < kMsdMaxBits && (k >> b) > kBktTarget) b++;
@@ -331,6 +333,7 @@ bool msd_split_sort(cpma* s, const uint64_t* src, uint64_t k, int bits, hipStrea
   const uint64_t nc = (uint64_t)nd * nt;
   ensure(s->cnt, (nc + 1) * sizeof(uint32_t));
   ensure(s->koff, (nc + 1) * sizeof(uint32_t));
+  ensure(s->kdedup, k * sizeof(uint64_t));
   hipLaunchKernelGGL(k_msd_hist, dim3(nt), dim3(kMsdThreads), 0, st, src, (uint32_t)k, r, nd, s->cnt.as<uint32_t>());
   HIPCHK(hipGetLastError());
   scan<uint32_t>(s, s->koff.as<uint32_t>(), nc, st, LoadFn<uint32_t>{s->cnt.as<uint32_t>()});
@@ -343,8 +346,17 @@ bool msd_split_sort(cpma* s, const uint64_t* src, uint64_t k, int bits, hipStrea
   hipLaunchKernelGGL(k_msd_scatter, dim3(nt), dim3(kMsdThreads), 0, st, src, s->kb0.as<uint64_t>(), (uint32_t)k, r,
                      nd, (const uint32_t*)s->koff.as<uint32_t>());
   HIPCHK(hipGetLastError());
+  // the per-tile counts are consumed: their buffer takes the buckets' first
+  // occurrence counts and those counts' scan (nc >= 32 nd)
+  uint32_t* ucnt = s->cnt.as<uint32_t>();
+  uint32_t* uoff = ucnt + nd + 1;
   hipLaunchKernelGGL(k_bucket_sort, dim3(nd), dim3(kBktThreads), 0, st, (const uint64_t*)s->kb0.as<uint64_t>(),
-                     s->kb1.as<uint64_t>(), (const uint32_t*)s->koff.as<uint32_t>(), nt, r, s->dinfo);
+                     s->kb1.as<uint64_t>(), (const uint32_t*)s->koff.as<uint32_t>(), nt, r, ucnt, s->dinfo);
+  HIPCHK(hipGetLastError());
+  scan<uint32_t>(s, uoff, nd, st, LoadFn<uint32_t>{ucnt});
+  hipLaunchKernelGGL(k_bucket_compact, dim3(nd), dim3(256), 0, st, (const uint64_t*)s->kb1.as<uint64_t>(),
+                     (const uint32_t*)s->koff.as<uint32_t>(), nt, (const uint32_t*)uoff, nd,
+                     s->kdedup.as<uint64_t>(), &s->dctr->kprime);
   HIPCHK(hipGetLastError());
   return true;
 }
@@ -391,9 +403,10 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
     ensure(s->kb0, k * sizeof(uint64_t));
     ensure(s->kb1, k * sizeof(uint64_t));
     if (msd_size && msd_split_sort(s, src, k, bits, st)) {
-      sorted = s->kb1.as<uint64_t>();
-      sort_bytes = 40ull * k;  // count (read), split (read + write), bucket sort (read + write)
-      passes = 0;
+      // count (read), split (read + write), bucket sort (read + write),
+      // packing (read + write); repeats are already removed
+      phase_end(s, pm, st, 56ull * k);
+      return s->kdedup.as<uint64_t>();
     }
     const uint64_t* in = src;
     for (int p = 0; p < passes; p++) {

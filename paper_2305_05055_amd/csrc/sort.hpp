@@ -287,8 +287,9 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter_kv(const uint64_
 // LDS copy of the tile in bucket order, so each bucket's run of a tile is
 // written contiguously; k_bucket_sort then loads one bucket per block, sorts
 // the 32-bit low parts with stable 8-bit LSD passes inside LDS and writes the
-// bucket back in order.  Two passes over HBM replace the five of a 40-bit
-// LSD sort.  Order inside a bucket before its sort does not matter, so the
+// bucket's first occurrences back in order; k_bucket_compact closes the gaps
+// the removed repeats leave.  Three passes over HBM replace the five of a
+// 40-bit LSD sort and the two of removing repeats.  Order inside a bucket before its sort does not matter, so the
 // split ranks keys with LDS atomics.
 constexpr int kMsdThreads = 1024;
 constexpr int kMsdItems = 16;
@@ -415,10 +416,12 @@ __device__ __forceinline__ void match_bit(uint32_t y, uint32_t& p0, uint32_t& p1
 __global__ void __launch_bounds__(kBktThreads) k_bucket_sort(const uint64_t* __restrict__ in,
                                                              uint64_t* __restrict__ out,
                                                              const uint32_t* __restrict__ koff, uint32_t ntiles,
-                                                             int r, BatchInfo* __restrict__ info) {
+                                                             int r, uint32_t* __restrict__ ucnt,
+                                                             BatchInfo* __restrict__ info) {
   __shared__ uint32_t buf[kBktCap];
   __shared__ uint32_t cnt[kBktWaves][256];  // the first pass uses row 0 for the whole block
   __shared__ uint32_t wsum[256 / kWave];
+  __shared__ uint32_t wtot[kBktWaves];
   const uint32_t bkt = blockIdx.x;
   const uint32_t beg = koff[(uint64_t)bkt * ntiles];
   const uint32_t n = koff[(uint64_t)(bkt + 1) * ntiles] - beg;
@@ -517,12 +520,69 @@ __global__ void __launch_bounds__(kBktThreads) k_bucket_sort(const uint64_t* __r
     }
     __syncthreads();  // the next pass clears the counters the scatter read
   }
+  // Repeats removed on the way out: the first occurrences of the sorted
+  // bucket go to out[beg ..], in order (item order is wave, round, lane), and
+  // their number to ucnt[bkt].  Without a low part every key of the bucket is
+  // the same.
   const uint64_t hi = (uint64_t)bkt << r;
+  if (r == 0) {
+    if (tid == 0) {
+      if (n) out[beg] = hi;
+      ucnt[bkt] = n ? 1u : 0u;
+    }
+    return;
+  }
+  uint64_t fm[kBktRounds];
+  uint32_t rp[kBktRounds];
+  uint32_t tw = 0;
 #pragma unroll
   for (int j = 0; j < kBktRounds; j++) {
     const uint32_t i = wb + (uint32_t)j * kWave + lane;
-    if (i < n) out[beg + i] = hi | x[j];
+    const bool f = i < n && (i == 0 || buf[i - 1] != x[j]);
+    fm[j] = __ballot(f);
+    rp[j] = tw;
+    tw += (uint32_t)__popcll(fm[j]);
   }
+  if (lane == 0) wtot[wid] = tw;
+  __syncthreads();
+  uint32_t woff = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kBktWaves; w++) {
+    const uint32_t t = wtot[w];
+    if (w < wid) woff += t;
+    total += t;
+  }
+#pragma unroll
+  for (int j = 0; j < kBktRounds; j++) {
+    if ((fm[j] >> lane) & 1ull) {
+      const uint32_t lo = (uint32_t)fm[j], hi32 = (uint32_t)(fm[j] >> 32);
+      out[beg + woff + rp[j] + __builtin_amdgcn_mbcnt_hi(hi32, __builtin_amdgcn_mbcnt_lo(lo, 0u))] = hi | x[j];
+    }
+  }
+  if (tid == 0) ucnt[bkt] = total;
+}
+
+// Moves every bucket's first occurrences (ucnt of them at the bucket's start
+// in `in`) to their place in the repeat-free batch (uoff: exclusive scan of
+// ucnt, uoff[nd] the total, which block 0 also stores in *n_out).
+__global__ void __launch_bounds__(256) k_bucket_compact(const uint64_t* __restrict__ in,
+                                                        const uint32_t* __restrict__ koff, uint32_t ntiles,
+                                                        const uint32_t* __restrict__ uoff, uint32_t nd,
+                                                        uint64_t* __restrict__ out,
+                                                        unsigned long long* __restrict__ n_out) {
+  const uint32_t b = blockIdx.x;
+  const uint64_t* src = in + koff[(uint64_t)b * ntiles];
+  const uint32_t d0 = uoff[b], m = uoff[b + 1] - d0;
+  constexpr int kU = 4;
+  for (uint32_t i0 = threadIdx.x; i0 < m; i0 += kU * 256) {
+    uint64_t v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; u++) v[u] = i0 + u * 256 < m ? src[i0 + u * 256] : 0;
+#pragma unroll
+    for (int u = 0; u < kU; u++)
+      if (i0 + u * 256 < m) out[d0 + i0 + u * 256] = v[u];
+  }
+  if (b == 0 && threadIdx.x == 0) *n_out = uoff[nd];
 }
 
 // Flags of first occurrences in a sorted array.

@@ -4,9 +4,9 @@ passes (batches below the split's size, low parts wider than 32 bits, buckets
 larger than one block's LDS, batches above the split's size).  Every case
 inserts an unsorted batch (with repeats) into a CPMA and checks the whole
 exported image against the oracle's set through the structure checker; the
-path taken is read from the sort phase's algorithmic bytes per key: 64 for
-the split (count 8, split 16, bucket sort 16, repeat removal 24), 24 per LSD
-pass plus 24 for the LSD sort."""
+path taken is read from the sort phase's algorithmic bytes per key: 56 for
+the split (count 8, split 16, bucket sort with repeat removal 16, packing
+16), 24 per LSD pass plus 24 for the repeat removal after them."""
 import numpy as np
 import pytest
 
@@ -79,7 +79,7 @@ def test_large_unsorted_insert(cp, orc, name, gen, path):
     c.stats_select(["sort"])
     assert c.insert_batch(batch) == added
     per_key = sort_bytes_per_key(c, len(batch))
-    assert per_key == (64 if path == MSD else path), per_key
+    assert per_key == (56 if path == MSD else path), per_key
     c.stats_select([])
     check_image(c, S, orc)
 
@@ -97,6 +97,6 @@ def test_large_unsorted_delete(cp, orc):
     S, removed = orc.delete(S, batch)
     c.stats_select(["sort"])
     assert c.delete_batch(batch) == removed
-    assert sort_bytes_per_key(c, len(batch)) == 64
+    assert sort_bytes_per_key(c, len(batch)) == 56
     c.stats_select([])
     check_image(c, S, orc)
