@@ -413,7 +413,8 @@ __device__ __forceinline__ void match_bit(uint32_t y, uint32_t& p0, uint32_t& p1
 // LDS executes one wave's operations in order, so no wait is needed between
 // rounds).  The host launches this only when every bucket holds at most
 // kBktCap keys; a larger one is left unsorted and flagged.
-__global__ void __launch_bounds__(kBktThreads) k_bucket_sort(const uint64_t* __restrict__ in,
+__global__ void __launch_bounds__(kBktThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_bucket_sort(const uint64_t* __restrict__ in,
                                                              uint64_t* __restrict__ out,
                                                              const uint32_t* __restrict__ koff, uint32_t ntiles,
                                                              int r, uint32_t* __restrict__ ucnt,
@@ -450,7 +451,6 @@ __global__ void __launch_bounds__(kBktThreads) k_bucket_sort(const uint64_t* __r
         for (int j = 0; j < kBktRounds; j++)
           if (wb + (uint32_t)j * kWave + lane < n) rk[j] = atomicAdd(&cnt[0][x[j] & 255u], 1u);
       } else {
-        uint32_t pre[kBktRounds];
 #pragma unroll
         for (int j = 0; j < kBktRounds; j++) {
           const bool valid = wb + (uint32_t)j * kWave + lane < n;
@@ -467,12 +467,9 @@ __global__ void __launch_bounds__(kBktThreads) k_bucket_sort(const uint64_t* __r
           match_bit<7>(y, p0, p1);
           const uint32_t below = __builtin_amdgcn_mbcnt_hi(p1, __builtin_amdgcn_mbcnt_lo(p0, 0u));
           uint32_t* c = &cnt[wid][y & 255u];
-          pre[j] = valid ? *c : 0u;
+          rk[j] = below + (valid ? *c : 0u);
           if (valid && below == 0) atomicAdd(c, (uint32_t)(__popc(p0) + __popc(p1)));
-          rk[j] = below;
         }
-#pragma unroll
-        for (int j = 0; j < kBktRounds; j++) rk[j] += pre[j];
       }
     }
     __syncthreads();
@@ -532,17 +529,13 @@ __global__ void __launch_bounds__(kBktThreads) k_bucket_sort(const uint64_t* __r
     }
     return;
   }
-  uint64_t fm[kBktRounds];
-  uint32_t rp[kBktRounds];
+  auto first_occ = [&](int j) {
+    const uint32_t i = wb + (uint32_t)j * kWave + lane;
+    return i < n && (i == 0 || buf[i - 1] != x[j]);
+  };
   uint32_t tw = 0;
 #pragma unroll
-  for (int j = 0; j < kBktRounds; j++) {
-    const uint32_t i = wb + (uint32_t)j * kWave + lane;
-    const bool f = i < n && (i == 0 || buf[i - 1] != x[j]);
-    fm[j] = __ballot(f);
-    rp[j] = tw;
-    tw += (uint32_t)__popcll(fm[j]);
-  }
+  for (int j = 0; j < kBktRounds; j++) tw += (uint32_t)__popcll(__ballot(first_occ(j)));
   if (lane == 0) wtot[wid] = tw;
   __syncthreads();
   uint32_t woff = 0, total = 0;
@@ -552,12 +545,14 @@ __global__ void __launch_bounds__(kBktThreads) k_bucket_sort(const uint64_t* __r
     if (w < wid) woff += t;
     total += t;
   }
+  uint32_t pos = beg + woff;
 #pragma unroll
   for (int j = 0; j < kBktRounds; j++) {
-    if ((fm[j] >> lane) & 1ull) {
-      const uint32_t lo = (uint32_t)fm[j], hi32 = (uint32_t)(fm[j] >> 32);
-      out[beg + woff + rp[j] + __builtin_amdgcn_mbcnt_hi(hi32, __builtin_amdgcn_mbcnt_lo(lo, 0u))] = hi | x[j];
-    }
+    const bool f = first_occ(j);
+    const uint64_t fm = __ballot(f);
+    if (f) out[pos + __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0u))] =
+        hi | x[j];
+    pos += (uint32_t)__popcll(fm);
   }
   if (tid == 0) ucnt[bkt] = total;
 }
