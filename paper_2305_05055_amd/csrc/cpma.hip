@@ -122,6 +122,7 @@ struct cpma {
   int device = 0;
   int num_cus = 256;
   uint32_t rm_blocks[2] = {2048, 2048};  // resident blocks of k_rm_interior<false>, <true>
+  int msd_bits = 0;  // bit length of the last unsorted batch of the MSD split's size (0: none yet)
   // a small batch's merge totals, left for the single-block path check to fold
   const unsigned long long* fin_parts = nullptr;
   uint32_t fin_nn = 0, fin_nw = 0;
@@ -318,46 +319,80 @@ void scan(cpma* s, T* out, uint64_t n, hipStream_t st, F fn) {
 // LDS, then every bucket sorted there with its repeats removed (src -> kb0 ->
 // kb1), then the buckets' first occurrences packed into kdedup (their number
 // in dctr->kprime).  The bucket count makes an average bucket about 0.8
-// kBktCap keys; the low bits sorted inside a bucket must fit 32 bits.  The
-// largest bucket is read back before the split is written: false (nothing
-// written but the counts) if one exceeds kBktCap, as skewed batches can, and
-// the caller sorts with LSD passes instead.
-bool msd_split_sort(cpma* s, const uint64_t* src, uint64_t k, int bits, hipStream_t st) {
+// kBktCap keys; the low bits sorted inside a bucket must fit 32 bits.
+struct MsdPlan {
+  int r = 0;          // low bits sorted inside a bucket
+  uint32_t nd = 0;    // buckets
+  uint32_t nt = 0;    // split tiles
+  uint64_t nc() const { return (uint64_t)nd * nt; }
+};
+
+bool msd_plan(uint64_t k, int bits, MsdPlan* p) {
   int b = kMsdMinBits;
   while (b < kMsdMaxBits && (k >> b) > kBktTarget) b++;
   b = std::min(b, bits);
-  const int r = bits - b;
-  if (r > 32 || (k >> b) > kBktTarget) return false;
-  const uint32_t nd = 1u << b;
-  const uint32_t nt = (uint32_t)((k + kMsdTile - 1) / kMsdTile);
-  const uint64_t nc = (uint64_t)nd * nt;
-  ensure(s->cnt, (nc + 1) * sizeof(uint32_t));
-  ensure(s->koff, (nc + 1) * sizeof(uint32_t));
+  if (bits - b > 32 || (k >> b) > kBktTarget) return false;
+  p->r = bits - b;
+  p->nd = 1u << b;
+  p->nt = (uint32_t)((k + kMsdTile - 1) / kMsdTile);
+  return true;
+}
+
+void msd_buffers(cpma* s, uint64_t k, const MsdPlan& p) {
+  ensure(s->cnt, (p.nc() + 1) * sizeof(uint32_t));
+  ensure(s->koff, (p.nc() + 1) * sizeof(uint32_t));
+  ensure(s->kb0, k * sizeof(uint64_t));
+  ensure(s->kb1, k * sizeof(uint64_t));
   ensure(s->kdedup, k * sizeof(uint64_t));
-  hipLaunchKernelGGL(k_msd_hist, dim3(nt), dim3(kMsdThreads), 0, st, src, (uint32_t)k, r, nd, s->cnt.as<uint32_t>());
+}
+
+// Bucket starts from the per-tile counts in s->cnt, and the largest bucket
+// into dinfo->max_bucket.
+void msd_offsets(cpma* s, const MsdPlan& p, hipStream_t st) {
+  scan<uint32_t>(s, s->koff.as<uint32_t>(), p.nc(), st, LoadFn<uint32_t>{s->cnt.as<uint32_t>()});
+  hipLaunchKernelGGL(k_msd_max, dim3(1), dim3(kMsdThreads), 0, st, (const uint32_t*)s->koff.as<uint32_t>(), p.nt,
+                     p.nd, s->dinfo);
   HIPCHK(hipGetLastError());
-  scan<uint32_t>(s, s->koff.as<uint32_t>(), nc, st, LoadFn<uint32_t>{s->cnt.as<uint32_t>()});
-  hipLaunchKernelGGL(k_msd_max, dim3(1), dim3(kMsdThreads), 0, st, (const uint32_t*)s->koff.as<uint32_t>(), nt, nd,
-                     s->dinfo);
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(s->hinfo, s->dinfo, sizeof(BatchInfo), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  if (s->hinfo->max_bucket > kBktCap) return false;
-  hipLaunchKernelGGL(k_msd_scatter, dim3(nt), dim3(kMsdThreads), 0, st, src, s->kb0.as<uint64_t>(), (uint32_t)k, r,
-                     nd, (const uint32_t*)s->koff.as<uint32_t>());
+}
+
+// Split, bucket sorts and packing, once the bucket starts are known and no
+// bucket exceeds kBktCap.
+void msd_finish(cpma* s, const uint64_t* src, uint64_t k, const MsdPlan& p, hipStream_t st) {
+  const uint32_t* koff = s->koff.as<uint32_t>();
+  hipLaunchKernelGGL(k_msd_scatter, dim3(p.nt), dim3(kMsdThreads), 0, st, src, s->kb0.as<uint64_t>(), (uint32_t)k,
+                     p.r, p.nd, koff);
   HIPCHK(hipGetLastError());
   // the per-tile counts are consumed: their buffer takes the buckets' first
   // occurrence counts and those counts' scan (nc >= 32 nd)
   uint32_t* ucnt = s->cnt.as<uint32_t>();
-  uint32_t* uoff = ucnt + nd + 1;
-  hipLaunchKernelGGL(k_bucket_sort, dim3(nd), dim3(kBktThreads), 0, st, (const uint64_t*)s->kb0.as<uint64_t>(),
-                     s->kb1.as<uint64_t>(), (const uint32_t*)s->koff.as<uint32_t>(), nt, r, ucnt, s->dinfo);
+  uint32_t* uoff = ucnt + p.nd + 1;
+  hipLaunchKernelGGL(k_bucket_sort, dim3(p.nd), dim3(kBktThreads), 0, st, (const uint64_t*)s->kb0.as<uint64_t>(),
+                     s->kb1.as<uint64_t>(), koff, p.nt, p.r, ucnt, s->dinfo);
   HIPCHK(hipGetLastError());
-  scan<uint32_t>(s, uoff, nd, st, LoadFn<uint32_t>{ucnt});
-  hipLaunchKernelGGL(k_bucket_compact, dim3(nd), dim3(256), 0, st, (const uint64_t*)s->kb1.as<uint64_t>(),
-                     (const uint32_t*)s->koff.as<uint32_t>(), nt, (const uint32_t*)uoff, nd,
-                     s->kdedup.as<uint64_t>(), &s->dctr->kprime);
+  scan<uint32_t>(s, uoff, p.nd, st, LoadFn<uint32_t>{ucnt});
+  hipLaunchKernelGGL(k_bucket_compact, dim3(p.nd), dim3(256), 0, st, (const uint64_t*)s->kb1.as<uint64_t>(), koff,
+                     p.nt, (const uint32_t*)uoff, p.nd, s->kdedup.as<uint64_t>(), &s->dctr->kprime);
   HIPCHK(hipGetLastError());
+}
+
+// The split for a batch whose bit length is known: counts, then the largest
+// bucket read back before anything is written.  False if a bucket exceeds
+// kBktCap (skewed batches) or the plan does not apply; the caller then sorts
+// with LSD passes.
+bool msd_split_sort(cpma* s, const uint64_t* src, uint64_t k, int bits, hipStream_t st) {
+  MsdPlan p;
+  if (!msd_plan(k, bits, &p)) return false;
+  msd_buffers(s, k, p);
+  hipLaunchKernelGGL(k_msd_hist, dim3(p.nt), dim3(kMsdThreads), 0, st, src, (uint32_t)k, p.r, p.nd,
+                     s->cnt.as<uint32_t>());
+  HIPCHK(hipGetLastError());
+  // a count for a wrong bit length may have left its maximum
+  hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, &s->dinfo->max_bucket, (uint64_t)1, 0u);
+  msd_offsets(s, p, st);
+  HIPCHK(hipMemcpyAsync(s->hinfo, s->dinfo, sizeof(BatchInfo), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (s->hinfo->max_bucket > kBktCap) return false;
+  msd_finish(s, src, k, p, st);
   return true;
 }
 
@@ -382,12 +417,24 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
   const uint32_t nblk = (uint32_t)((k + kSortTile - 1) / kSortTile);
   ensure(s->cnt, ((uint64_t)nblk * 256 + 1) * sizeof(uint32_t));
   ensure(s->koff, ((uint64_t)nblk * 256 + 1) * sizeof(uint32_t));
+  // batches of the MSD split's size: with the bit length of the last such
+  // batch, validation also counts the split's buckets and the bucket starts
+  // are scanned before the one read-back
   const bool msd_size = k >= kMsdMinKeys && k <= kMsdMaxKeys;
-  if (msd_size)
+  MsdPlan guess;
+  const bool fused = msd_size && s->msd_bits > 0 && msd_plan(k, s->msd_bits, &guess);
+  if (fused) {
+    msd_buffers(s, k, guess);
+    hipLaunchKernelGGL(k_validate_msd, dim3(guess.nt), dim3(kMsdThreads), 0, st, src, (uint32_t)k, guess.r, guess.nd,
+                       s->dinfo, s->cnt.as<uint32_t>());
+    HIPCHK(hipGetLastError());
+    msd_offsets(s, guess, st);
+  } else if (msd_size) {
     hipLaunchKernelGGL(k_validate, dim3(grid_for(k, 256, 4096)), dim3(256), 0, st, src, k, s->dinfo);
-  else
+  } else {
     hipLaunchKernelGGL(k_validate_hist, dim3(nblk), dim3(kSortThreads), 0, st, src, (uint32_t)k, s->dinfo,
                        s->cnt.as<uint32_t>());
+  }
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(s->hinfo, s->dinfo, sizeof(BatchInfo), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -402,11 +449,23 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
     int passes = (bits + 7) / 8;
     ensure(s->kb0, k * sizeof(uint64_t));
     ensure(s->kb1, k * sizeof(uint64_t));
-    if (msd_size && msd_split_sort(s, src, k, bits, st)) {
-      // count (read), split (read + write), bucket sort (read + write),
-      // packing (read + write); repeats are already removed
-      phase_end(s, pm, st, 56ull * k);
-      return s->kdedup.as<uint64_t>();
+    if (msd_size) {
+      // the validation's counts hold if this batch has no more bits than the
+      // one they were counted for (fewer only leaves high buckets empty)
+      const bool counted = fused && bits <= s->msd_bits && s->hinfo->max_bucket <= kBktCap;
+      s->msd_bits = bits;
+      if (counted) {
+        msd_finish(s, src, k, guess, st);
+        // split (read + write), bucket sort (read + write), packing (read +
+        // write); the counts came with the validation, repeats are removed
+        phase_end(s, pm, st, 48ull * k);
+        return s->kdedup.as<uint64_t>();
+      }
+      if (msd_split_sort(s, src, k, bits, st)) {
+        // count (read), then as above
+        phase_end(s, pm, st, 56ull * k);
+        return s->kdedup.as<uint64_t>();
+      }
     }
     const uint64_t* in = src;
     for (int p = 0; p < passes; p++) {

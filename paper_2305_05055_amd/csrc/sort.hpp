@@ -330,6 +330,75 @@ __global__ void __launch_bounds__(kMsdThreads) k_msd_hist(const uint64_t* __rest
   for (uint32_t d = threadIdx.x; d < nd; d += kMsdThreads) counts[(uint64_t)d * gridDim.x + blockIdx.x] = h[d];
 }
 
+// Validation and k_msd_hist's counts in one read, for a bucket shift taken
+// from an earlier batch (the host discards the counts if this batch has more
+// bits).  One block per split tile, item i = base + 1024 j + tid; the right
+// neighbour of lane 63 is lane 0 of the next wave (or of wave 0 in the next
+// round), exchanged through LDS, and only the tile's last item reads the next
+// tile's first key.
+__global__ void __launch_bounds__(kMsdThreads) k_validate_msd(const uint64_t* __restrict__ keys, uint32_t n,
+                                                              int r, uint32_t nd, BatchInfo* __restrict__ info,
+                                                              uint32_t* __restrict__ counts) {
+  constexpr int kW = kMsdThreads / kWave;
+  __shared__ uint32_t h[kMsdMaxBuckets];
+  __shared__ uint64_t first[kMsdItems][kW];
+  __shared__ uint64_t red[kW];
+  __shared__ uint32_t fl[kW];
+  const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+  for (uint32_t d = tid; d < kMsdMaxBuckets; d += kMsdThreads) h[d] = 0;
+  const uint32_t base = blockIdx.x * kMsdTile;
+  uint64_t x[kMsdItems];
+#pragma unroll
+  for (int j = 0; j < kMsdItems; j++) {
+    const uint32_t i = base + j * kMsdThreads + tid;
+    x[j] = i < n ? keys[i] : 0;
+  }
+  const uint64_t after = base + kMsdTile < n ? keys[base + kMsdTile] : 0;  // the next tile's first key
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < kMsdItems; j++) first[j][wid] = x[j];
+  }
+  __syncthreads();
+  uint64_t orv = 0;
+  uint32_t res = 0, uns = 0;
+#pragma unroll
+  for (int j = 0; j < kMsdItems; j++) {
+    const uint32_t i = base + j * kMsdThreads + tid;
+    uint64_t nx = dpp_next64(x[j]);
+    if (lane == kWave - 1)
+      nx = wid + 1 < kW ? first[j][wid + 1] : (j + 1 < kMsdItems ? first[j + 1][0] : after);
+    if (i < n) {
+      orv |= x[j];
+      res |= (x[j] == kNoKey);
+      if (i + 1 < n && nx < x[j]) uns = 1;
+      atomicAdd(&h[msd_bucket(x[j], r, nd)], 1u);
+    }
+  }
+  orv = wave_or(orv);
+  const uint64_t flags = wave_or((uint64_t)(res | (uns << 1)));
+  if (lane == 0) {
+    red[wid] = orv;
+    fl[wid] = (uint32_t)flags;
+  }
+  __syncthreads();
+  for (uint32_t d = tid; d < nd; d += kMsdThreads) counts[(uint64_t)d * gridDim.x + blockIdx.x] = h[d];
+  if (tid == 0) {
+    uint64_t o = 0;
+    uint32_t f = 0;
+#pragma unroll
+    for (int w = 0; w < kW; w++) {
+      o |= red[w];
+      f |= fl[w];
+    }
+    if (o & ~__hip_atomic_load(&info->or_all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicOr(&info->or_all, (unsigned long long)o);
+    if ((f & 1) && !__hip_atomic_load(&info->has_reserved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicOr(&info->has_reserved, 1u);
+    if ((f & 2) && !__hip_atomic_load(&info->unsorted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicOr(&info->unsorted, 1u);
+  }
+}
+
 // Largest bucket after the scan of k_msd_hist's counts (koff[d * ntiles] is
 // where bucket d starts, koff[nd * ntiles] the total).
 __global__ void __launch_bounds__(kMsdThreads) k_msd_max(const uint32_t* __restrict__ koff, uint32_t ntiles,

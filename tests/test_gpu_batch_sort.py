@@ -6,7 +6,9 @@ inserts an unsorted batch (with repeats) into a CPMA and checks the whole
 exported image against the oracle's set through the structure checker; the
 path taken is read from the sort phase's algorithmic bytes per key: 56 for
 the split (count 8, split 16, bucket sort with repeat removal 16, packing
-16), 24 per LSD pass plus 24 for the repeat removal after them."""
+16), 48 when the validation counted the buckets with the bit length of the
+previous large batch, 24 per LSD pass plus 24 for the repeat removal after
+them, 24 for a sorted batch (repeat removal only)."""
 import numpy as np
 import pytest
 
@@ -86,7 +88,9 @@ def test_large_unsorted_insert(cp, orc, name, gen, path):
 
 def test_large_unsorted_delete(cp, orc):
     """A delete batch takes the same preparation: half its keys present, half
-    absent, with repeats, in random order."""
+    absent, with repeats, in random order.  Building from 2e6 unsorted keys
+    prepared them the same way, so the delete's validation already counts the
+    buckets with their bit length (48 bytes per key)."""
     seed = synth.SEED_BASE + 1300
     base = synth.unique_uniform_keys(2_000_000, seed, bits=40)
     c = cp.CPMA(base)
@@ -97,6 +101,39 @@ def test_large_unsorted_delete(cp, orc):
     S, removed = orc.delete(S, batch)
     c.stats_select(["sort"])
     assert c.delete_batch(batch) == removed
-    assert sort_bytes_per_key(c, len(batch)) == 56
+    assert sort_bytes_per_key(c, len(batch)) == 48
     c.stats_select([])
     check_image(c, S, orc)
+
+
+def test_counts_with_the_previous_bit_length(cp, orc):
+    """From the second large batch on, validation counts the buckets with the
+    previous batch's bit length: the counts are used when the batch has no
+    more bits than that and its buckets still fit (48 bytes per key), and the
+    batch is recounted otherwise (56); a skewed batch still falls back to the
+    LSD passes.  Every batch is checked
+    against the oracle."""
+    seed = synth.SEED_BASE + 1400
+    base = synth.uniform_keys(100_000, seed, bits=40)
+    c = cp.CPMA(base)
+    S = orc.build_set(base)
+    steps = [
+        (synth.uniform_keys(1_000_000, seed + 1, bits=40), 56),   # no earlier bit length
+        (synth.uniform_keys(1_000_000, seed + 2, bits=40), 48),   # same bits
+        (synth.uniform_keys(1_000_000, seed + 3, bits=39), 48),   # fewer bits: counts hold
+        # three bits fewer: the old split leaves 32 buckets of ~25000 keys,
+        # more than a block's LDS holds, so the batch is recounted
+        (synth.uniform_keys(800_000, seed + 4, bits=36), 56),
+        (synth.uniform_keys(1_000_000, seed + 5, bits=38), 56),   # more bits: recounted
+        (shuffled(synth.zipf_keys(1_000_000, seed + 6, bits=34), seed + 7), lsd(5)),
+        (synth.uniform_keys(1_000_000, seed + 8, bits=40), 56),   # more bits than the skewed batch
+        (np.sort(synth.unique_uniform_keys(1_000_000, seed + 9, bits=40)), 24),  # sorted: no sort
+    ]
+    for step, (batch, per_key) in enumerate(steps):
+        print(f"[batch sort] sequence step {step}: k={len(batch)}", flush=True)
+        S, added = orc.insert(S, batch)
+        c.stats_select(["sort"])
+        assert c.insert_batch(batch) == added, step
+        assert sort_bytes_per_key(c, len(batch)) == per_key, step
+        c.stats_select([])
+        check_image(c, S, orc)
