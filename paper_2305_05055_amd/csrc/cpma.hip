@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -267,8 +268,11 @@ hipEvent_t get_event(cpma* s) {
     s->evpool.pop_back();
     return e;
   }
+  // timing only: results always come back through stream synchronisation,
+  // so the record needs no system-scope fence (whose cache writeback and
+  // invalidation would idle the GPU between the timed kernels)
   hipEvent_t e;
-  HIPCHK(hipEventCreate(&e));
+  HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   return e;
 }
 
@@ -347,12 +351,29 @@ void msd_buffers(cpma* s, uint64_t k, const MsdPlan& p) {
 }
 
 // Bucket starts from the per-tile counts in s->cnt, and the largest bucket
-// into dinfo->max_bucket.
-void msd_offsets(cpma* s, const MsdPlan& p, hipStream_t st) {
+// into dinfo->max_bucket; with publish, the BatchInfo also goes to s->hinfo
+// (see wait_published).
+void msd_offsets(cpma* s, const MsdPlan& p, hipStream_t st, bool publish = false) {
   scan<uint32_t>(s, s->koff.as<uint32_t>(), p.nc(), st, LoadFn<uint32_t>{s->cnt.as<uint32_t>()});
+  if (publish) __atomic_store_n(&s->hinfo->ready, 0u, __ATOMIC_RELEASE);
   hipLaunchKernelGGL(k_msd_max, dim3(1), dim3(kMsdThreads), 0, st, (const uint32_t*)s->koff.as<uint32_t>(), p.nt,
-                     p.nd, s->dinfo);
+                     p.nd, s->dinfo, publish ? s->hinfo : nullptr);
   HIPCHK(hipGetLastError());
+}
+
+// Waits until a kernel has published the BatchInfo to s->hinfo (its ready
+// field), polling host memory instead of synchronising the stream, whose
+// later work may already be queued.  Bounded: after a second the stream is
+// synchronised, which reports a device error if there was one.
+void wait_published(cpma* s, hipStream_t st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t it = 1;; it++) {
+    if (__atomic_load_n(&s->hinfo->ready, __ATOMIC_ACQUIRE)) return;
+    if ((it & 4095u) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) break;
+    __builtin_ia32_pause();
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  if (!__atomic_load_n(&s->hinfo->ready, __ATOMIC_ACQUIRE)) throw Fail{CPMA_ERR_DEVICE};
 }
 
 // Split, bucket sorts and packing, once the bucket starts are known and no
@@ -428,7 +449,7 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
     hipLaunchKernelGGL(k_validate_msd, dim3(guess.nt), dim3(kMsdThreads), 0, st, src, (uint32_t)k, guess.r, guess.nd,
                        s->dinfo, s->cnt.as<uint32_t>());
     HIPCHK(hipGetLastError());
-    msd_offsets(s, guess, st);
+    msd_offsets(s, guess, st, true);
   } else if (msd_size) {
     hipLaunchKernelGGL(k_validate, dim3(grid_for(k, 256, 4096)), dim3(256), 0, st, src, k, s->dinfo);
   } else {
@@ -436,8 +457,12 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
                        s->cnt.as<uint32_t>());
   }
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(s->hinfo, s->dinfo, sizeof(BatchInfo), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  if (fused) {
+    wait_published(s, st);
+  } else {
+    HIPCHK(hipMemcpyAsync(s->hinfo, s->dinfo, sizeof(BatchInfo), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   if (s->hinfo->has_reserved) throw Fail{CPMA_ERR_RESERVED_KEY};
 
   const uint64_t* sorted = src;

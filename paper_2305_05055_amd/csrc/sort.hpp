@@ -19,7 +19,7 @@ struct BatchInfo {
   unsigned int has_reserved;
   unsigned int unsorted;
   unsigned int max_bucket;  // largest MSD bucket of a split (large batches)
-  unsigned int pad;
+  unsigned int ready;       // set last when a kernel publishes the struct to host memory
 };
 
 __global__ void __launch_bounds__(256) k_validate(const uint64_t* __restrict__ keys, uint64_t k,
@@ -400,14 +400,33 @@ __global__ void __launch_bounds__(kMsdThreads) k_validate_msd(const uint64_t* __
 }
 
 // Largest bucket after the scan of k_msd_hist's counts (koff[d * ntiles] is
-// where bucket d starts, koff[nd * ntiles] the total).
+// where bucket d starts, koff[nd * ntiles] the total).  One block.  With hout
+// (host memory) it also publishes the whole BatchInfo there, the validation's
+// fields included, and then sets hout->ready, so the host can poll instead of
+// copying and synchronising.
 __global__ void __launch_bounds__(kMsdThreads) k_msd_max(const uint32_t* __restrict__ koff, uint32_t ntiles,
-                                                         uint32_t nd, BatchInfo* __restrict__ info) {
+                                                         uint32_t nd, BatchInfo* __restrict__ info,
+                                                         BatchInfo* hout) {
+  __shared__ uint32_t wm[kMsdThreads / kWave];
   uint32_t m = 0;
   for (uint32_t d = threadIdx.x; d < nd; d += kMsdThreads)
     m = max(m, koff[(uint64_t)(d + 1) * ntiles] - koff[(uint64_t)d * ntiles]);
   m = __shfl(dpp_incl_max(m), kWave - 1);
-  if (lane_id() == 0 && m) atomicMax(&info->max_bucket, m);
+  if (lane_id() == 0) wm[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < kMsdThreads / kWave; w++) m = max(m, wm[w]);
+    m = max(m, atomicMax(&info->max_bucket, m));
+    if (hout) {
+      hout->or_all = __hip_atomic_load(&info->or_all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      hout->has_reserved = __hip_atomic_load(&info->has_reserved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      hout->unsorted = __hip_atomic_load(&info->unsorted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      hout->max_bucket = m;
+      __threadfence_system();
+      __hip_atomic_store(&hout->ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
 }
 
 __global__ void __launch_bounds__(kMsdThreads) k_msd_scatter(const uint64_t* __restrict__ in,
