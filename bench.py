@@ -240,24 +240,30 @@ WHOLE_RUN_TRACES = {
 }
 
 
+# the kernels that open an update batch: validation alone, with the first LSD
+# digit's counts, or with the MSD split's bucket counts
+VALIDATION_KERNELS = ("k_validate", "k_validate_hist", "k_validate_msd")
+
+
 def trace_summary(kind, csv_path, args):
     """Markdown summary of a rocprofv3 --kernel-trace run.  steps: the kernels of
-    the timed headline steps (every update batch opens with one launch of
-    k_validate_hist; the timed batches are the 2K before the last PHASE_STEPS
-    steps' 2 * PHASE_STEPS); gate: every launch from the first range_map kernel
+    the timed headline steps (every update batch opens with its validation
+    kernel, after the fills that clear its counters and flags; the timed
+    batches are the 2K before the last PHASE_STEPS steps' 2 * PHASE_STEPS); gate: every launch from the first range_map kernel
     on (one warm-up and three timed passes of the cold range gate)."""
     rows = trace_rows(csv_path)
     shape = f"--steps {args.steps} --warmup {args.warmup}"
     if kind == "steps":
         cmd = ("rocprofv3 --kernel-trace --stats --output-format csv -d " + PROF_DIR + "/tr_steps -o run -- "
                f"python3 /root/repo/bench.py --only-steps --no-cpu-baseline {shape}")
-        starts = [i for i, r in enumerate(rows) if r[1] == "k_validate_hist"]
+        starts = [i for i, r in enumerate(rows) if r[1] in VALIDATION_KERNELS]
         nb = MERGES_PER_STEP * args.steps
         first, last = starts[-(nb + TAIL_MERGES)], starts[-TAIL_MERGES]
-        # each batch's validation follows one k_fill that clears its flags
-        if rows[first - 1][1].startswith("k_fill"):
+        # each batch's validation follows the fills that clear its counters
+        # and flags
+        while rows[first - 1][1].startswith("k_fill"):
             first -= 1
-        if rows[last - 1][1].startswith("k_fill"):
+        while rows[last - 1][1].startswith("k_fill"):
             last -= 1
         sel = rows[first:last]
         title = "insert + delete batch pairs of 1e7 uniform 40-bit keys on a 1e8-key CPMA"

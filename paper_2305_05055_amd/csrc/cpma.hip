@@ -380,14 +380,14 @@ void wait_published(cpma* s, hipStream_t st) {
 // bucket exceeds kBktCap.
 void msd_finish(cpma* s, const uint64_t* src, uint64_t k, const MsdPlan& p, hipStream_t st) {
   const uint32_t* koff = s->koff.as<uint32_t>();
-  hipLaunchKernelGGL(k_msd_scatter, dim3(p.nt), dim3(kMsdThreads), 0, st, src, s->kb0.as<uint64_t>(), (uint32_t)k,
+  hipLaunchKernelGGL(k_msd_scatter, dim3(p.nt), dim3(kMsdThreads), 0, st, src, s->kb0.as<uint32_t>(), (uint32_t)k,
                      p.r, p.nd, koff);
   HIPCHK(hipGetLastError());
   // the per-tile counts are consumed: their buffer takes the buckets' first
   // occurrence counts and those counts' scan (nc >= 32 nd)
   uint32_t* ucnt = s->cnt.as<uint32_t>();
   uint32_t* uoff = ucnt + p.nd + 1;
-  hipLaunchKernelGGL(k_bucket_sort, dim3(p.nd), dim3(kBktThreads), 0, st, (const uint64_t*)s->kb0.as<uint64_t>(),
+  hipLaunchKernelGGL(k_bucket_sort, dim3(p.nd), dim3(kBktThreads), 0, st, (const uint32_t*)s->kb0.as<uint32_t>(),
                      s->kb1.as<uint64_t>(), koff, p.nt, p.r, ucnt, s->dinfo);
   HIPCHK(hipGetLastError());
   scan<uint32_t>(s, uoff, p.nd, st, LoadFn<uint32_t>{ucnt});
@@ -481,14 +481,15 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
       s->msd_bits = bits;
       if (counted) {
         msd_finish(s, src, k, guess, st);
-        // split (read + write), bucket sort (read + write), packing (read +
-        // write); the counts came with the validation, repeats are removed
-        phase_end(s, pm, st, 48ull * k);
+        // split (read 8, write 4), bucket sort (read 4, write 8), packing
+        // (read + write 16); the counts came with the validation, repeats are
+        // removed
+        phase_end(s, pm, st, 40ull * k);
         return s->kdedup.as<uint64_t>();
       }
       if (msd_split_sort(s, src, k, bits, st)) {
-        // count (read), then as above
-        phase_end(s, pm, st, 56ull * k);
+        // count (read 8), then as above
+        phase_end(s, pm, st, 48ull * k);
         return s->kdedup.as<uint64_t>();
       }
     }

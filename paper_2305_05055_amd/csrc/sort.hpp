@@ -429,8 +429,10 @@ __global__ void __launch_bounds__(kMsdThreads) k_msd_max(const uint32_t* __restr
   }
 }
 
+// The bucket's low parts only go out: a key is its bucket number above its
+// low r bits, and the bucket sort restores it.
 __global__ void __launch_bounds__(kMsdThreads) k_msd_scatter(const uint64_t* __restrict__ in,
-                                                             uint64_t* __restrict__ out, uint32_t n, int r,
+                                                             uint32_t* __restrict__ out, uint32_t n, int r,
                                                              uint32_t nd, const uint32_t* __restrict__ koff) {
   __shared__ uint64_t tile[kMsdTile];
   __shared__ uint32_t h[kMsdMaxBuckets];   // counts, then the tile's bucket offsets
@@ -452,29 +454,38 @@ __global__ void __launch_bounds__(kMsdThreads) k_msd_scatter(const uint64_t* __r
   for (int j = 0; j < kMsdItems; j++)
     if (base + j * kMsdThreads + tid < n) rk[j] = atomicAdd(&h[msd_bucket(x[j], r, nd)], 1u);
   __syncthreads();
-  // exclusive scan of the 2048 counters, two per thread
-  static_assert(kMsdMaxBuckets == 2 * kMsdThreads, "two counters per thread");
-  const uint32_t c0 = h[2 * tid], c1 = h[2 * tid + 1];
-  const uint32_t incl = wave_incl_scan(c0 + c1);
+  // exclusive scan of the 2048 counters, kPer consecutive ones per thread
+  constexpr int kPer = kMsdMaxBuckets / kMsdThreads;
+  static_assert(kPer * kMsdThreads == kMsdMaxBuckets, "counters split evenly over the threads");
+  uint32_t c[kPer], sum = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; q++) {
+    c[q] = h[kPer * tid + q];
+    sum += c[q];
+  }
+  const uint32_t incl = wave_incl_scan(sum);
   if (lane == kWave - 1) wsum[wid] = incl;
   __syncthreads();
-  uint32_t wofs = 0;
+  uint32_t run = incl - sum;
 #pragma unroll
   for (int w = 0; w < kMsdThreads / kWave; w++)
-    if (w < wid) wofs += wsum[w];
-  const uint32_t ex = wofs + incl - (c0 + c1);
-  h[2 * tid] = ex;
-  h[2 * tid + 1] = ex + c0;
+    if (w < wid) run += wsum[w];
+#pragma unroll
+  for (int q = 0; q < kPer; q++) {
+    h[kPer * tid + q] = run;
+    run += c[q];
+  }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < kMsdItems; j++)
     if (base + j * kMsdThreads + tid < n) tile[h[msd_bucket(x[j], r, nd)] + rk[j]] = x[j];
   __syncthreads();
   const uint32_t m = min(kMsdTile, n - base);
+  const uint32_t lowmask = r >= 32 ? 0xffffffffu : ((1u << r) - 1u);
   for (uint32_t i = tid; i < m; i += kMsdThreads) {
     const uint64_t y = tile[i];
     const uint32_t d = msd_bucket(y, r, nd);
-    out[gb[d] + (i - h[d])] = y;
+    out[gb[d] + (i - h[d])] = (uint32_t)y & lowmask;
   }
 }
 
@@ -502,7 +513,7 @@ __device__ __forceinline__ void match_bit(uint32_t y, uint32_t& p0, uint32_t& p1
 // rounds).  The host launches this only when every bucket holds at most
 // kBktCap keys; a larger one is left unsorted and flagged.
 __global__ void __launch_bounds__(kBktThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
-k_bucket_sort(const uint64_t* __restrict__ in,
+k_bucket_sort(const uint32_t* __restrict__ in,
                                                              uint64_t* __restrict__ out,
                                                              const uint32_t* __restrict__ koff, uint32_t ntiles,
                                                              int r, uint32_t* __restrict__ ucnt,
@@ -520,12 +531,11 @@ k_bucket_sort(const uint64_t* __restrict__ in,
   }
   const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
   const uint32_t wb = (uint32_t)wid * (kBktRounds * kWave);
-  const uint32_t lowmask = r >= 32 ? 0xffffffffu : ((1u << r) - 1u);
   uint32_t x[kBktRounds];
 #pragma unroll
   for (int j = 0; j < kBktRounds; j++) {
     const uint32_t i = wb + (uint32_t)j * kWave + lane;
-    x[j] = i < n ? (uint32_t)in[beg + i] & lowmask : 0u;
+    x[j] = i < n ? in[beg + i] : 0u;
   }
   for (int sh = 0; sh < r; sh += 8) {
     const bool first = sh == 0;
