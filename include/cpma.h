@@ -508,7 +508,8 @@ uint64_t cpma_clock_ns(void);
  * enabled, every call records HIP events around its phases on the call's stream
  * and accumulates, per phase, the number of timed launches, their total device
  * time, and the algorithmic HBM bytes the phase had to move:
- *   CPMA_PHASE_SORT        radix passes + repeat removal of a batch
+ *   CPMA_PHASE_SORT        sort (MSD split + bucket sorts, or LSD passes) and
+ *                          repeat removal of a batch
  *   CPMA_PHASE_LOCATE      leaf location + touched-leaf segments
  *   CPMA_PHASE_MERGE       the main per-leaf merge kernel (one wave per leaf of
  *                          narrow key span; one lane per leaf above 1024-byte

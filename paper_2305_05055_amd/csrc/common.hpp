@@ -184,4 +184,15 @@ __global__ void k_fill(T* p, uint64_t n, T v) {
     p[i] = v;
 }
 
+// Two small regions cleared in one launch of one block (an update's counters
+// and its batch flags): one launch less on a queue that is often idle.
+__global__ void k_clear2(uint32_t* a, uint32_t na, uint32_t* b, uint32_t nb) {
+  for (uint32_t i = threadIdx.x; i < na + nb; i += blockDim.x) {
+    if (i < na)
+      a[i] = 0u;
+    else
+      b[i - na] = 0u;
+  }
+}
+
 }  // namespace cpma_dev

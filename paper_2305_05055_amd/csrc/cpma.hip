@@ -422,7 +422,8 @@ bool msd_split_sort(cpma* s, const uint64_t* src, uint64_t k, int bits, hipStrea
 // Returns the device pointer of the sorted repeat-free batch; its length is in
 // dctr->kprime (device).  Throws CPMA_ERR_RESERVED_KEY before any mutation.
 // ---------------------------------------------------------------------------
-const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem mem, hipStream_t st) {
+const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem mem, hipStream_t st,
+                              bool clear_counters = false) {
   if (k >= (1ull << 32)) throw Fail{CPMA_ERR_INVALID};
   const uint64_t* src = keys;
   if (mem == CPMA_MEM_HOST) {
@@ -430,8 +431,13 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
     HIPCHK(hipMemcpyAsync(s->kin.p, keys, k * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     src = s->kin.as<uint64_t>();
   }
-  hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(s->dinfo),
-                     (uint64_t)(sizeof(BatchInfo) / 4), 0u);
+  if (clear_counters)  // the update's counters too, in the same launch
+    hipLaunchKernelGGL(k_clear2, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(s->dctr),
+                       (uint32_t)(sizeof(Counters) / 4), reinterpret_cast<uint32_t*>(s->dinfo),
+                       (uint32_t)(sizeof(BatchInfo) / 4));
+  else
+    hipLaunchKernelGGL((k_fill<uint32_t>), dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(s->dinfo),
+                       (uint64_t)(sizeof(BatchInfo) / 4), 0u);
   // validation reads every key once; below the MSD split's size it also
   // counts the first radix digit per sort tile (used if the batch turns out
   // unsorted)
@@ -1820,8 +1826,7 @@ static cpma_status update(cpma* s, const uint64_t* keys, uint64_t k, cpma_mem me
         delta = apply_small(s, src, k, insert, st);
       }
     } else {
-      zero_counters(s, st);
-      const uint64_t* B = prepare_batch(s, keys, k, mem, st);
+      const uint64_t* B = prepare_batch(s, keys, k, mem, st, true);
       delta = apply_batch(s, B, k, insert, st, false, wants_rebuild(s, k));
     }
     resolve_phases(s);
