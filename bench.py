@@ -243,6 +243,8 @@ WHOLE_RUN_TRACES = {
 # the kernels that open an update batch: validation alone, with the first LSD
 # digit's counts, or with the MSD split's bucket counts
 VALIDATION_KERNELS = ("k_validate", "k_validate_hist", "k_validate_msd")
+# the fills before it
+CLEAR_KERNELS = ("k_fill", "k_clear2")
 
 
 def trace_summary(kind, csv_path, args):
@@ -261,9 +263,9 @@ def trace_summary(kind, csv_path, args):
         first, last = starts[-(nb + TAIL_MERGES)], starts[-TAIL_MERGES]
         # each batch's validation follows the fills that clear its counters
         # and flags
-        while rows[first - 1][1].startswith("k_fill"):
+        while rows[first - 1][1].startswith(CLEAR_KERNELS):
             first -= 1
-        while rows[last - 1][1].startswith("k_fill"):
+        while rows[last - 1][1].startswith(CLEAR_KERNELS):
             last -= 1
         sel = rows[first:last]
         title = "insert + delete batch pairs of 1e7 uniform 40-bit keys on a 1e8-key CPMA"
