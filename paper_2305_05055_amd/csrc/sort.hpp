@@ -332,46 +332,59 @@ __global__ void __launch_bounds__(kMsdThreads) k_msd_hist(const uint64_t* __rest
 
 // Validation and k_msd_hist's counts in one read, for a bucket shift taken
 // from an earlier batch (the host discards the counts if this batch has more
-// bits).  One block per split tile, item i = base + 1024 j + tid; the right
-// neighbour of lane 63 is lane 0 of the next wave (or of wave 0 in the next
-// round), exchanged through LDS, and only the tile's last item reads the next
-// tile's first key.
-__global__ void __launch_bounds__(kMsdThreads) k_validate_msd(const uint64_t* __restrict__ keys, uint32_t n,
-                                                              int r, uint32_t nd, BatchInfo* __restrict__ info,
-                                                              uint32_t* __restrict__ counts) {
+// bits).  One block per split tile, item i = base + 1024 j + tid.  A key's
+// right neighbour is the next lane's (DPP); lane 63's is lane 0 of the next
+// wave (or of wave 0 in the next round), so lane 63 parks its keys in LDS and
+// compares them after the barrier, when the keys' registers are free; only
+// the tile's last item reads the next tile's first key.
+__global__ void __launch_bounds__(kMsdThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_validate_msd(const uint64_t* __restrict__ keys, uint32_t n, int r, uint32_t nd, BatchInfo* __restrict__ info,
+               uint32_t* __restrict__ counts) {
   constexpr int kW = kMsdThreads / kWave;
   __shared__ uint32_t h[kMsdMaxBuckets];
   __shared__ uint64_t first[kMsdItems][kW];
+  __shared__ uint64_t last[kMsdItems][kW];
   __shared__ uint64_t red[kW];
   __shared__ uint32_t fl[kW];
   const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
   for (uint32_t d = tid; d < kMsdMaxBuckets; d += kMsdThreads) h[d] = 0;
   const uint32_t base = blockIdx.x * kMsdTile;
-  uint64_t x[kMsdItems];
-#pragma unroll
-  for (int j = 0; j < kMsdItems; j++) {
-    const uint32_t i = base + j * kMsdThreads + tid;
-    x[j] = i < n ? keys[i] : 0;
-  }
-  const uint64_t after = base + kMsdTile < n ? keys[base + kMsdTile] : 0;  // the next tile's first key
-  if (lane == 0) {
-#pragma unroll
-    for (int j = 0; j < kMsdItems; j++) first[j][wid] = x[j];
-  }
-  __syncthreads();
+  __syncthreads();  // counters cleared
   uint64_t orv = 0;
   uint32_t res = 0, uns = 0;
+  // two halves of kMsdItems / 2 loads in flight, so two blocks fit a CU
+  constexpr int kHalf = kMsdItems / 2;
 #pragma unroll
-  for (int j = 0; j < kMsdItems; j++) {
-    const uint32_t i = base + j * kMsdThreads + tid;
-    uint64_t nx = dpp_next64(x[j]);
-    if (lane == kWave - 1)
-      nx = wid + 1 < kW ? first[j][wid + 1] : (j + 1 < kMsdItems ? first[j + 1][0] : after);
-    if (i < n) {
-      orv |= x[j];
-      res |= (x[j] == kNoKey);
-      if (i + 1 < n && nx < x[j]) uns = 1;
-      atomicAdd(&h[msd_bucket(x[j], r, nd)], 1u);
+  for (int hf = 0; hf < 2; hf++) {
+    uint64_t x[kHalf];
+#pragma unroll
+    for (int q = 0; q < kHalf; q++) {
+      const uint32_t i = base + (hf * kHalf + q) * kMsdThreads + tid;
+      x[q] = i < n ? keys[i] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kHalf; q++) {
+      const int j = hf * kHalf + q;
+      const uint32_t i = base + j * kMsdThreads + tid;
+      const uint64_t nx = dpp_next64(x[q]);
+      if (lane == 0) first[j][wid] = x[q];
+      if (lane == kWave - 1) last[j][wid] = x[q];
+      if (i < n) {
+        orv |= x[q];
+        res |= (x[q] == kNoKey);
+        if (lane != kWave - 1 && i + 1 < n && nx < x[q]) uns = 1;
+        atomicAdd(&h[msd_bucket(x[q], r, nd)], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  if (lane == kWave - 1) {
+    const uint64_t after = base + kMsdTile < n ? keys[base + kMsdTile] : 0;  // the next tile's first key
+#pragma unroll
+    for (int j = 0; j < kMsdItems; j++) {
+      const uint32_t i = base + j * kMsdThreads + tid;
+      const uint64_t nx = wid + 1 < kW ? first[j][wid + 1] : (j + 1 < kMsdItems ? first[j + 1][0] : after);
+      if (i + 1 < n && nx < last[j][wid]) uns = 1;
     }
   }
   orv = wave_or(orv);
