@@ -187,11 +187,17 @@ struct BwdWriter {
   }
 };
 
-constexpr uint32_t kLaneHeavy = 4096;  // inserts with longer slices take the wave path
+// Insert slices longer than this take the one-wave heavy merge.  One lane
+// walking a slice key by key is latency-bound (about 2 us per key), so a
+// single long slice would set the batch's latency: at 2 and 4 KiB leaves a
+// slice of 300 / 4000 keys in one leaf took 0.9 / 3.1 ms here and 0.07 /
+// 0.43 ms on the heavy merge.  Uniform batches give these leaves slices of
+// ~50-110 keys, which stay on the lane.
+constexpr uint32_t kLaneHeavy = 256;
 
-// The main merge for leaves larger than the wave merge takes: every segment.
-// (Long insert slices of smaller leaves go to the heavy merge instead: one lane
-// walking a slice key by key is latency-bound, about 2 us per key.)
+// The main merge for leaves larger than the wave merge takes: every segment
+// except the long insert slices above.  (Long insert slices of smaller leaves
+// go to the heavy merge too.)
 __global__ void __launch_bounds__(256) k_merge_lane(MergeArgs a) {
   const uint64_t T = a.ctr->T;
   const uint64_t lanes = (uint64_t)gridDim.x * blockDim.x;
