@@ -388,7 +388,7 @@ void msd_finish(cpma* s, const uint64_t* src, uint64_t k, const MsdPlan& p, hipS
   uint32_t* ucnt = s->cnt.as<uint32_t>();
   uint32_t* uoff = ucnt + p.nd + 1;
   hipLaunchKernelGGL(k_bucket_sort, dim3(p.nd), dim3(kBktThreads), 0, st, (const uint32_t*)s->kb0.as<uint32_t>(),
-                     s->kb1.as<uint64_t>(), koff, p.nt, p.r, ucnt, s->dinfo);
+                     s->kb1.as<uint64_t>(), koff, p.nt, p.r, ucnt, &s->dctr->error);
   HIPCHK(hipGetLastError());
   scan<uint32_t>(s, uoff, p.nd, st, LoadFn<uint32_t>{ucnt});
   hipLaunchKernelGGL(k_bucket_compact, dim3(p.nd), dim3(256), 0, st, (const uint64_t*)s->kb1.as<uint64_t>(), koff,
@@ -450,13 +450,17 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
   const bool msd_size = k >= kMsdMinKeys && k <= kMsdMaxKeys;
   MsdPlan guess;
   const bool fused = msd_size && s->msd_bits > 0 && msd_plan(k, s->msd_bits, &guess);
+  // the validation counts the first LSD digit when the split is out of reach
+  // (batch size, or the last large batch's bit length); hist0 says whether
+  // those counts are still in s->cnt
+  bool hist0 = !msd_size || (s->msd_bits > 0 && !fused);
   if (fused) {
     msd_buffers(s, k, guess);
     hipLaunchKernelGGL(k_validate_msd, dim3(guess.nt), dim3(kMsdThreads), 0, st, src, (uint32_t)k, guess.r, guess.nd,
                        s->dinfo, s->cnt.as<uint32_t>());
     HIPCHK(hipGetLastError());
     msd_offsets(s, guess, st, true);
-  } else if (msd_size) {
+  } else if (!hist0) {
     hipLaunchKernelGGL(k_validate, dim3(grid_for(k, 256, 4096)), dim3(256), 0, st, src, k, s->dinfo);
   } else {
     hipLaunchKernelGGL(k_validate_hist, dim3(nblk), dim3(kSortThreads), 0, st, src, (uint32_t)k, s->dinfo,
@@ -493,16 +497,20 @@ const uint64_t* prepare_batch(cpma* s, const uint64_t* keys, uint64_t k, cpma_me
         phase_end(s, pm, st, 40ull * k);
         return s->kdedup.as<uint64_t>();
       }
-      if (msd_split_sort(s, src, k, bits, st)) {
-        // count (read 8), then as above
-        phase_end(s, pm, st, 48ull * k);
-        return s->kdedup.as<uint64_t>();
+      MsdPlan own;
+      if (msd_plan(k, bits, &own)) {
+        hist0 = false;  // the recount overwrites them
+        if (msd_split_sort(s, src, k, bits, st)) {
+          // count (read 8), then as above
+          phase_end(s, pm, st, 48ull * k);
+          return s->kdedup.as<uint64_t>();
+        }
       }
     }
     const uint64_t* in = src;
     for (int p = 0; p < passes; p++) {
       uint64_t* out = (p & 1) ? s->kb1.as<uint64_t>() : s->kb0.as<uint64_t>();
-      if (p > 0 || msd_size)  // else the first pass's counts came with the validation
+      if (p > 0 || !hist0)  // else the first pass's counts came with the validation
         hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, st, in, (uint32_t)k, 8 * p,
                            s->cnt.as<uint32_t>());
       HIPCHK(hipGetLastError());

@@ -524,13 +524,14 @@ __device__ __forceinline__ void match_bit(uint32_t y, uint32_t& p0, uint32_t& p1
 // reads its digit's counter, then the group's lowest lane adds the group;
 // LDS executes one wave's operations in order, so no wait is needed between
 // rounds).  The host launches this only when every bucket holds at most
-// kBktCap keys; a larger one is left unsorted and flagged.
+// kBktCap keys; a larger one is left unsorted and raises *err (the update's
+// device-error counter, which the host checks before it reports success).
 __global__ void __launch_bounds__(kBktThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_bucket_sort(const uint32_t* __restrict__ in,
                                                              uint64_t* __restrict__ out,
                                                              const uint32_t* __restrict__ koff, uint32_t ntiles,
                                                              int r, uint32_t* __restrict__ ucnt,
-                                                             BatchInfo* __restrict__ info) {
+                                                             unsigned int* __restrict__ err) {
   __shared__ uint32_t buf[kBktCap];
   __shared__ uint32_t cnt[kBktWaves][256];  // the first pass uses row 0 for the whole block
   __shared__ uint32_t wsum[256 / kWave];
@@ -539,7 +540,10 @@ k_bucket_sort(const uint32_t* __restrict__ in,
   const uint32_t beg = koff[(uint64_t)bkt * ntiles];
   const uint32_t n = koff[(uint64_t)(bkt + 1) * ntiles] - beg;
   if (n > kBktCap) {
-    if (threadIdx.x == 0) atomicOr(&info->unsorted, 2u);
+    if (threadIdx.x == 0) {
+      ucnt[bkt] = 0u;
+      atomicOr(err, 1u);
+    }
     return;
   }
   const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;

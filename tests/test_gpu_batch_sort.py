@@ -134,6 +134,12 @@ def test_counts_with_the_previous_bit_length(cp, orc):
         # recounted with no low part; the next byte batch uses its counts
         (synth.uniform_keys(600_000, seed + 10, bits=8), 48),
         (synth.uniform_keys(600_000, seed + 11, bits=8), 40),
+        # 44-bit keys leave a 36-bit low part: LSD passes, first after counts
+        # for the byte keys' bit length, then with the validation counting
+        # the first digit
+        (synth.uniform_keys(1_000_000, seed + 12, bits=44), lsd(6)),
+        (synth.uniform_keys(1_000_000, seed + 13, bits=44), lsd(6)),
+        (synth.uniform_keys(1_000_000, seed + 14, bits=40), 48),  # the split again
     ]
     for step, (batch, per_key) in enumerate(steps):
         print(f"[batch sort] sequence step {step}: k={len(batch)}", flush=True)
